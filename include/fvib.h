@@ -1,0 +1,278 @@
+/*
+ * fvib -- one time step of an incompressible finite-volume solver with
+ * immersed-boundary fluid-structure coupling, and its discrete adjoint,
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The method is the one of Fan, Liu, Wang & Wang, "Diff-FlowFSI: A
+ * GPU-Optimized Differentiable CFD Platform for High-Fidelity Turbulence
+ * and FSI Simulations" (arXiv 2505.23940):
+ *   - staggered finite volumes on a rectangular, uniform or stretched grid
+ *     (Sec. 2.2.1), periodic / Dirichlet / Neumann boundaries (Sec. 2.4,
+ *     Table 1);
+ *   - forward-Euler predictor with central or upwind convection and central
+ *     diffusion (Eq. 4), direct-forcing IBM (Eq. 5);
+ *   - modified pressure Poisson equation (Eq. 9) and correction (Eq. 10);
+ *   - 4-point-kernel transfers between markers and the grid (Eqs. 18-22);
+ *   - rigid spring-damper body integrated with RK4 (Eq. 12);
+ *   - one weakly coupled step = Alg. 1 with N = 1;
+ *   - reverse-mode gradients (Sec. 2.3.1), here as a hand-written discrete
+ *     adjoint of every sub-step with the Poisson adjoint taken through the
+ *     implicit function theorem (Eq. 24).
+ *
+ * Conventions common to every call
+ * --------------------------------
+ * Layout.  Velocity component c (0 = u, 1 = v, 2 = w) lives on the faces
+ * normal to axis c; the face with index i along axis c is the low face of
+ * cell i.  Arrays are dense and C-contiguous in (z, y, x) order, x fastest.
+ * Along its own axis a component has n[c] faces on a periodic axis and
+ * n[c] + 1 faces otherwise; along the other axes it has n[a] entries.
+ * Pressure is cell-centred, shape (n[2], n[1], n[0]).  2D grids use
+ * dim = 2, n[2] = 1 and two components.  fvib_field_layout() returns the
+ * exact shapes.
+ *
+ * Precision.  FVIB_PREC_FP64: velocities, forcing fields and all
+ * arithmetic are double.  FVIB_PREC_FP32_MIXED: velocities and forcing
+ * fields are float and the stencils run in float, while the Poisson
+ * residual, its iterative-refinement correction, the pressure and every
+ * global reduction are double.  Pressure and body state are always double.
+ *
+ * Memory.  Pointers in fvib_fields / fvib_adjoint / fvib_step_info are
+ * device pointers owned by the caller; the library never frees them.  The
+ * library owns the handle and its workspace.  Host pointers in the
+ * descriptors are read during the call only.
+ *
+ * Streams.  All device work is enqueued on the HIP stream given at
+ * creation.  fvib_step / fvib_step_adjoint synchronise that stream only to
+ * poll the convergence of the Poisson solve (every check_every
+ * iterations); results are ready when the stream is.
+ *
+ * Errors.  Every call returns FVIB_OK (0) or a negative status.  Invalid
+ * arguments are reported before any work is enqueued.  Device-side
+ * conditions (no convergence, non-finite residual) are reported in the
+ * returned status and in info->status, and the message is available from
+ * fvib_last_error().  A handle must not be used from two threads at once.
+ */
+#ifndef FVIB_H
+#define FVIB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fvib_grid fvib_grid;   /* opaque handle owned by the library */
+
+enum {
+  FVIB_OK = 0,
+  FVIB_EINVAL = -1,      /* invalid argument or descriptor               */
+  FVIB_ENOMEM = -2,      /* device or host allocation failed             */
+  FVIB_EHIP = -3,        /* a HIP runtime call failed                    */
+  FVIB_ENOCONV = -4,     /* Poisson solve did not reach poisson_tol      */
+  FVIB_ENONFINITE = -5,  /* NaN / Inf met in a global reduction          */
+  FVIB_ESTATE = -6       /* call out of order (e.g. no body set)         */
+};
+
+/* Boundary kinds (Table 1 of the paper).  The velocity vector of each
+ * boundary is given in fvib_grid_desc.bc_vel. */
+enum {
+  FVIB_BC_PERIODIC = 0,           /* must be paired on both sides of an axis   */
+  FVIB_BC_NOSLIP = 1,             /* Dirichlet wall, wall velocity bc_vel      */
+  FVIB_BC_FREESLIP = 2,           /* zero normal velocity, zero shear          */
+  FVIB_BC_INFLOW = 3,             /* Dirichlet velocity bc_vel                 */
+  FVIB_BC_OUTFLOW_CONVECTIVE = 4, /* du/dt + U_conv du/dn = 0 on normal faces  */
+  FVIB_BC_OUTFLOW_NEUMANN = 5     /* du/dn = 0                                 */
+};
+
+enum { FVIB_CONV_CENTRAL2 = 0, FVIB_CONV_UPWIND1 = 1 };
+enum { FVIB_PREC_FP64 = 0, FVIB_PREC_FP32_MIXED = 1 };
+enum { FVIB_BODY_STATIC = 0, FVIB_BODY_RIGID_SPRING = 1 };
+enum { FVIB_DTYPE_F32 = 0, FVIB_DTYPE_F64 = 1 };
+
+/* Grid and solver description (Sec. 2.4 of the paper). */
+typedef struct {
+  int32_t dim;              /* 2 or 3                                          */
+  int32_t n[3];             /* cells per axis; n[2] = 1 when dim = 2           */
+  const double *faces[3];   /* host: n[a] + 1 increasing face coordinates;
+                               periodic axes must be uniform                   */
+  int32_t bc[3][2];         /* boundary kind per axis and side (0 low, 1 high) */
+  double bc_vel[3][2][3];   /* velocity vector of each boundary                */
+  double nu;                /* kinematic viscosity, > 0                        */
+  double rho;               /* density, > 0                                    */
+  double dt;                /* time step, > 0                                  */
+  double u_conv;            /* convective outflow speed                        */
+  int32_t convection;       /* FVIB_CONV_*                                     */
+  int32_t precision;        /* FVIB_PREC_*                                     */
+  double poisson_tol;       /* stop when max over cells of |div u^{n+1}|,
+                               evaluated in double before any rounding to the
+                               storage type, is <= poisson_tol (units 1/time) */
+  int32_t poisson_maxit;    /* max CG iterations per solve (per refinement
+                               sweep in mixed mode)                            */
+  int32_t ir_maxit;         /* max refinement sweeps (mixed mode)              */
+  double inner_rtol;        /* residual reduction of each float inner solve    */
+  int32_t check_every;      /* iterations between convergence polls, >= 1     */
+} fvib_grid_desc;
+
+/* Immersed rigid body: a closed polygon of Lagrangian markers (2D only). */
+typedef struct {
+  int32_t kind;             /* FVIB_BODY_STATIC or FVIB_BODY_RIGID_SPRING      */
+  int32_t n_markers;        /* M >= 3                                          */
+  const double *X0;         /* host, M x 2 marker positions at zero
+                               displacement, counter-clockwise                 */
+  const double *ds;         /* host, M arc-length elements                     */
+  int32_t free_dof[3];      /* 1 where the translational DOF is free           */
+  double m;                 /* body mass (Eq. 12), > 0 for a spring body       */
+} fvib_body_desc;
+
+/* Per-step fields (device pointers).  body = [d_x, d_y, d_z, v_x, v_y, v_z]
+ * (displacement and velocity, double).  kc = [k_x, k_y, k_z, c_x, c_y, c_z]
+ * (double) are the spring stiffness and damping of Eq. 12; fb is an
+ * external body force per face (e.g. a driving pressure gradient), may be
+ * NULL for zero. */
+typedef struct {
+  void *u[3];               /* velocity components (dtype per precision)       */
+  double *p;                /* pressure; on input the initial guess            */
+  const void *fb[3];        /* body-force components or NULL                   */
+  double *body;             /* body state (6 doubles), may be NULL w/o body    */
+  const double *kc;         /* spring constants (6 doubles), may be NULL       */
+} fvib_fields;
+
+/* Adjoint fields (device pointers), same layouts as fvib_fields. */
+typedef struct {
+  void *u[3];               /* adjoint velocity                                */
+  void *fb[3];              /* adjoint body force (accumulated), may be NULL   */
+  double *body;             /* adjoint body state (6 doubles)                  */
+  double *kc;               /* adjoint spring constants (accumulated, 6)       */
+} fvib_adjoint;
+
+/* Step diagnostics, written on the stream into device (or host-mapped)
+ * memory. 64 bytes. */
+typedef struct {
+  int32_t status;           /* FVIB_OK or a negative status                    */
+  int32_t cg_iters;         /* total CG iterations of the step                 */
+  int32_t ir_iters;         /* refinement sweeps (mixed mode), else 0          */
+  int32_t flags;            /* reserved                                        */
+  double res;               /* final max |div| estimate of the Poisson solve   */
+  double div_max;           /* max |D u^{n+1}| in double before storage        */
+  double force[3];          /* fluid force on the body F^n (Eq. 20, summed)    */
+  double reserved;
+} fvib_step_info;
+
+/* Create a grid handle.  Validates the descriptor (paired periodic sides,
+ * uniform periodic axes, increasing faces, positive nu / rho / dt), uploads
+ * the per-axis metrics and allocates the workspace.  hip_stream is a
+ * hipStream_t (NULL = default stream).  On success *out receives the
+ * handle; on failure *out is NULL. */
+int fvib_create_grid(const fvib_grid_desc *desc, void *hip_stream, fvib_grid **out);
+
+/* Destroy a handle and release its workspace (synchronises its stream). */
+int fvib_destroy_grid(fvib_grid *g);
+
+/* Shape and element strides (z, y, x order) of component comp (0..2) or of
+ * the pressure (comp = 3) / a cell field, and its dtype (FVIB_DTYPE_*). */
+int fvib_field_layout(const fvib_grid *g, int comp, int64_t shape[3],
+                      int64_t strides[3], int *dtype);
+
+/* Attach an immersed body (Sec. 2.1, Eqs. 18-22); NULL removes it.  2D
+ * grids with equal uniform spacing h in x and y only.  The body must stay
+ * at least four cells away from the domain boundary.  Point classes are
+ * rebuilt inside fvib_step from the displacement in the body state. */
+int fvib_ib_set_body(fvib_grid *g, const fvib_body_desc *body);
+
+/* One weakly coupled time step (Alg. 1 with N = 1): classification and
+ * target velocities, predictor with direct forcing (Eqs. 4-5), boundary
+ * faces, modified PPE (Eq. 9) solved by conjugate gradients (double, or
+ * float inner solves inside double iterative refinement), correction
+ * (Eq. 10), loads on the body (Eq. 20) and RK4 body update (Eq. 12).
+ * out may alias in (in-place step).  info may be NULL. */
+int fvib_step(fvib_grid *g, const fvib_fields *in, fvib_fields *out,
+              fvib_step_info *info);
+
+/* Discrete adjoint of fvib_step at the state fwd_in (the masks of the step
+ * are frozen).  Given the adjoints of the step outputs -- bar_out->u
+ * (u^{n+1}), bar_out->body (body state^{n+1}) and dF (3 doubles, device:
+ * the direct derivative of the loss with respect to the force F^n reported
+ * by the step, may be NULL) -- it writes bar_in->u (u^n) and
+ * bar_in->body (body state^n) and adds into bar_in->fb and bar_in->kc.
+ * bar_in may not alias bar_out.  The pressure of fwd_in is not used. */
+int fvib_step_adjoint(fvib_grid *g, const fvib_fields *fwd_in,
+                      const fvib_adjoint *bar_out, const double *dF,
+                      fvib_adjoint *bar_in, fvib_step_info *info);
+
+/* Mean wall shear J = (nu/2) [ <u>_lo / (yc_0 - y_0) + <u>_hi / (y_N - yc_{N-1}) ]
+ * of the streamwise velocity at the two wall-adjacent rows (walls normal
+ * to y, at rest).  Writes J (1 double, device) and, if ubar is not NULL,
+ * adds dJ/du into ubar[0] (dtype of the velocity). */
+int fvib_loss_wall_shear(fvib_grid *g, const void *u0, double *J, void *ubar0);
+
+/* Root-mean-square lift coefficient of a force history:
+ * J = sqrt(mean_n C_L^2), C_L = 2 F_y / (rho U^2 D).  Fh: nsteps rows of
+ * `stride` doubles with F at offset `offset` (device).  Writes J (device)
+ * and, if dFh is not NULL, dJ/dF into the same row layout of dFh. */
+int fvib_loss_rms_lift(fvib_grid *g, const double *Fh, int nsteps, int stride,
+                       int offset, double u_ref, double diameter, double *J,
+                       double *dFh);
+
+/* Message of the last error on this handle ("" if none). */
+const char *fvib_last_error(const fvib_grid *g);
+
+/* ---------------------------------------------------------------------
+ * Sub-step entry points for parity tests.  Same layouts as above; every
+ * pointer is a device pointer.
+ * ------------------------------------------------------------------- */
+
+/* Eq. 4 right-hand side R = -div(u (x) u) + nu lap u + fb on the faces the
+ * momentum equation advances (other faces receive 0). */
+int fvib_test_momentum(fvib_grid *g, const void *const u[3], const void *const fb[3],
+                       void *R[3]);
+
+/* Volume-integrated PPE right-hand side b of Eq. 9 (double, mean not
+ * removed) from a predicted field ustar (no forcing mask). */
+int fvib_test_ppe_rhs(fvib_grid *g, const void *const ustar[3], double *b);
+
+/* Solve A p = b - mean(b) with the step's solver (double or mixed);
+ * p is the initial guess on input.  iters may be NULL. */
+int fvib_test_poisson(fvib_grid *g, const double *b, double *p, int32_t *iters);
+
+/* Matrix-free A p of the volume-integrated PPE operator (double). */
+int fvib_test_apply_A(fvib_grid *g, const double *p, double *Ap);
+
+/* Point classes of the current body at displacement body[0..2]: writes
+ * one byte per face (0 fluid, 1 solid, 2 immersed-boundary point) into
+ * cls[c] (full face arrays). */
+int fvib_test_ib_classify(fvib_grid *g, const double *body, uint8_t *cls[3]);
+
+/* ---------------------------------------------------------------------
+ * Kernel timing for measurement.  While enabled, every launch of the
+ * classes below is bracketed by HIP events recorded on the handle's stream
+ * (the stream the kernels run on); totals accumulate until re-enabled.
+ * ------------------------------------------------------------------- */
+enum {
+  FVIB_K_PREDICTOR = 0,   /* Eqs. 4-5 predictor with direct forcing        */
+  FVIB_K_BOUNDARY = 1,    /* boundary-normal faces and outflow correction  */
+  FVIB_K_PPE_RHS = 2,     /* Eq. 9 right-hand side                         */
+  FVIB_K_RESIDUAL = 3,    /* double residual / refinement sweep            */
+  FVIB_K_CG_DIR = 4,      /* CG search direction + p.Ap                    */
+  FVIB_K_CG_UPDATE = 5,   /* CG iterate / residual update + r.r            */
+  FVIB_K_IR_CORRECT = 6,  /* refinement correction                         */
+  FVIB_K_PROJECT = 7,     /* Eq. 10 correction + divergence check          */
+  FVIB_K_IB = 8,          /* point classes, targets, loads, RK4            */
+  FVIB_K_ADJOINT = 9,     /* adjoint stencils                              */
+  FVIB_K_NCLASSES = 16
+};
+
+/* Start (enable != 0, totals cleared) or stop recording. */
+int fvib_timing_enable(fvib_grid *g, int enable);
+
+/* Total device time (ms) and launch count of one kernel class since the
+ * last enable; synchronises the stream. */
+int fvib_timing_read(fvib_grid *g, int kclass, double *total_ms, int64_t *launches);
+
+/* Build version string. */
+const char *fvib_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FVIB_H */

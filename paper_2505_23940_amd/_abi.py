@@ -1,0 +1,115 @@
+"""ctypes mirror of include/fvib.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libfvib.so")
+
+FVIB_OK, FVIB_EINVAL, FVIB_ENOMEM, FVIB_EHIP, FVIB_ENOCONV, FVIB_ENONFINITE, FVIB_ESTATE = \
+    0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOCONV",
+                -5: "ENONFINITE", -6: "ESTATE"}
+
+BC = {"periodic": 0, "noslip": 1, "freeslip": 2, "inflow": 3, "outflow_conv": 4,
+      "outflow_neumann": 5}
+CONV = {"central": 0, "upwind": 1}
+PREC = {"fp64": 0, "fp32": 1}
+BODY = {"static": 0, "spring": 1}
+DTYPE_F32, DTYPE_F64 = 0, 1
+
+EXPORTS = (
+    "fvib_create_grid", "fvib_destroy_grid", "fvib_field_layout", "fvib_ib_set_body",
+    "fvib_step", "fvib_step_adjoint", "fvib_loss_wall_shear", "fvib_loss_rms_lift",
+    "fvib_last_error", "fvib_test_momentum", "fvib_test_ppe_rhs", "fvib_test_poisson",
+    "fvib_test_apply_A", "fvib_test_ib_classify", "fvib_timing_enable", "fvib_timing_read",
+    "fvib_version",
+)
+K_CLASSES = {"predictor": 0, "boundary": 1, "ppe_rhs": 2, "residual": 3, "cg_dir": 4,
+             "cg_update": 5, "ir_correct": 6, "project": 7, "ib": 8, "adjoint": 9}
+
+
+class GridDesc(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("n", C.c_int32 * 3),
+        ("faces", C.c_void_p * 3),
+        ("bc", (C.c_int32 * 2) * 3),
+        ("bc_vel", ((C.c_double * 3) * 2) * 3),
+        ("nu", C.c_double), ("rho", C.c_double), ("dt", C.c_double), ("u_conv", C.c_double),
+        ("convection", C.c_int32), ("precision", C.c_int32),
+        ("poisson_tol", C.c_double),
+        ("poisson_maxit", C.c_int32), ("ir_maxit", C.c_int32),
+        ("inner_rtol", C.c_double),
+        ("check_every", C.c_int32),
+    ]
+
+
+class BodyDesc(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32), ("n_markers", C.c_int32),
+        ("X0", C.c_void_p), ("ds", C.c_void_p),
+        ("free_dof", C.c_int32 * 3), ("m", C.c_double),
+    ]
+
+
+class Fields(C.Structure):
+    _fields_ = [
+        ("u", C.c_void_p * 3), ("p", C.c_void_p), ("fb", C.c_void_p * 3),
+        ("body", C.c_void_p), ("kc", C.c_void_p),
+    ]
+
+
+class Adjoint(C.Structure):
+    _fields_ = [
+        ("u", C.c_void_p * 3), ("fb", C.c_void_p * 3), ("body", C.c_void_p), ("kc", C.c_void_p),
+    ]
+
+
+class StepInfo(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("cg_iters", C.c_int32), ("ir_iters", C.c_int32),
+        ("flags", C.c_int32), ("res", C.c_double), ("div_max", C.c_double),
+        ("force", C.c_double * 3), ("reserved", C.c_double),
+    ]
+
+
+assert C.sizeof(StepInfo) == 64
+
+_LIB = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load libfvib.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"libfvib.so not built at {path}; run paper_2505_23940_amd.build")
+    lib = C.CDLL(path)
+    vp, i32, i64p = C.c_void_p, C.c_int, C.POINTER(C.c_int64)
+    lib.fvib_create_grid.argtypes = [C.POINTER(GridDesc), vp, C.POINTER(vp)]
+    lib.fvib_destroy_grid.argtypes = [vp]
+    lib.fvib_field_layout.argtypes = [vp, i32, i64p, i64p, C.POINTER(C.c_int)]
+    lib.fvib_ib_set_body.argtypes = [vp, C.POINTER(BodyDesc)]
+    lib.fvib_step.argtypes = [vp, C.POINTER(Fields), C.POINTER(Fields), vp]
+    lib.fvib_step_adjoint.argtypes = [vp, C.POINTER(Fields), C.POINTER(Adjoint), vp,
+                                      C.POINTER(Adjoint), vp]
+    lib.fvib_loss_wall_shear.argtypes = [vp, vp, vp, vp]
+    lib.fvib_loss_rms_lift.argtypes = [vp, vp, i32, i32, i32, C.c_double, C.c_double, vp, vp]
+    lib.fvib_last_error.argtypes = [vp]
+    lib.fvib_last_error.restype = C.c_char_p
+    lib.fvib_test_momentum.argtypes = [vp, vp * 3, vp * 3, vp * 3]
+    lib.fvib_test_ppe_rhs.argtypes = [vp, vp * 3, vp]
+    lib.fvib_test_poisson.argtypes = [vp, vp, vp, C.POINTER(C.c_int32)]
+    lib.fvib_test_apply_A.argtypes = [vp, vp, vp]
+    lib.fvib_test_ib_classify.argtypes = [vp, vp, vp * 3]
+    lib.fvib_timing_enable.argtypes = [vp, i32]
+    lib.fvib_timing_read.argtypes = [vp, i32, C.POINTER(C.c_double), i64p]
+    lib.fvib_version.restype = C.c_char_p
+    for name in EXPORTS:
+        getattr(lib, name).restype = getattr(lib, name).restype or C.c_int
+    lib.fvib_last_error.restype = C.c_char_p
+    lib.fvib_version.restype = C.c_char_p
+    _LIB = lib
+    return lib

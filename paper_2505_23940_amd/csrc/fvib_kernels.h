@@ -1,0 +1,73 @@
+// Host-side launchers of the fvib kernels (one declaration per entry).
+#pragma once
+
+#include "fvib_internal.h"
+
+namespace fvib {
+
+// Immersed-boundary geometry resident on the device (2D).
+struct IbGeo {
+  int M;                       // markers
+  const double* X0;            // M x 2 reference positions
+  const double* ds;            // M arc-length elements
+  double xmin0, ymin0;         // lower corner of the reference polygon box
+  double h;                    // uniform grid spacing
+  int margin;                  // cells between the polygon box and the window
+  int W[2][2];                 // window widths per component (x, y)
+  int ext[2][2];               // array extents per component (x, y)
+  const double* fx[2];         // face-point x coordinates per component
+  const double* fy[2];         // face-point y coordinates per component
+  int* origin;                 // 4 ints: window origin per component
+  uint8_t* cls[2];             // window point classes
+  int kind;                    // FVIB_BODY_*
+  int free_dof[3];
+  double m, rho, dt;
+};
+
+// k_momentum.hip
+template <typename T>
+int launch_predictor(const Geo<T>& G, const T* const u[3], const T* const fb[3], T* out[3],
+                     const IbView<T>& ib, int mode, hipStream_t s);
+template <typename T>
+int launch_boundary(const Geo<T>& G, const Planes& PL, const T* const un[3], T* us[3],
+                    RedBuf red, SolverScalars* sc, hipStream_t s);
+
+// k_poisson.hip
+template <typename T>
+int launch_ppe_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
+                   const IbView<T>& ib, double* b, RedBuf red, SolverScalars* sc,
+                   hipStream_t s);
+int launch_residual(const PGeo<double>& P, int mode, const double* b, const double* x,
+                    double* r64, float* r32, float* d32, RedBuf red, SolverScalars* sc,
+                    double tol, double inner_rtol, hipStream_t s);
+// ev (nullable): three events recorded before the direction kernel, between
+// the two kernels and after the update kernel.
+template <typename V>
+int launch_cg_iter(const PGeo<V>& P, int mode, const V* r, const V* pold, V* pnew, V* x, V* rw,
+                   RedBuf red, SolverScalars* sc, double tol, int maxit, hipStream_t s,
+                   hipEvent_t* ev);
+int launch_ir_correct(int64_t n, double* p, const float* d, const SolverScalars* sc,
+                      hipStream_t s);
+template <typename T>
+int launch_project(const Geo<T>& G, const PGeo<double>& P, const T* const us[3], const double* p,
+                   T* out[3], RedBuf red, SolverScalars* sc, hipStream_t s);
+int launch_apply_A(const PGeo<double>& P, const double* x, double* y, hipStream_t s);
+
+// k_ib.hip
+template <typename T>
+int launch_ib_classify(const IbGeo& B, const double* body, T* us0, T* us1, SolverScalars* sc,
+                       hipStream_t s);
+template <typename T>
+int launch_loads_body(const IbGeo& B, const IbView<T>& ib, const double* body_in,
+                      double* body_out, const double* kc, SolverScalars* sc, hipStream_t s);
+int launch_copy_info(const SolverScalars* sc, fvib_step_info* info, int cg_iters, int ir_iters,
+                     hipStream_t s);
+
+// k_loss.hip
+template <typename T>
+int launch_wall_shear(int nx, int ny, int nz, const T* u, T* ubar, double wlo, double whi,
+                      double* J, hipStream_t s);
+int launch_rms_lift(const double* Fh, int S, int stride, int off, double g, double* J,
+                    double* dFh, hipStream_t s);
+
+}  // namespace fvib

@@ -1,0 +1,237 @@
+// Immersed-boundary kernels (2D): point classes, target velocities, loads
+// on the body and the rigid-body update (paper Sec. 2.1, Eqs. 12, 18-22).
+//
+// Point classes (Sec. 2.1, Fig. 2) are evaluated per velocity component on
+// that component's own face points inside a fixed-size window that follows
+// the body: solid = inside the closed marker polygon (crossing number,
+// half-open rule y_a <= y < y_b, double precision, no contraction of the
+// multiply-add so the decision is reproducible); immersed-boundary point =
+// not solid with a solid axis neighbour.  Both are forced (Eq. 5).
+//
+// Target velocity on IB points: the marker velocity interpolated with the
+// normalised 4-point-kernel weights w_k = delta_h(x - X_k) dV_k
+// (Eqs. 18-19, Shepard form); on solid points the body velocity (Eq. 23).
+//
+// Loads (Eq. 20): q_k = -sum_x f(x) delta_h(x - X_k) h^2 over forced faces,
+// F = rho sum_k q_k dV_k with dV_k = ds_k h; then classic RK4 of
+// m w'' + c w' + k w = F with F held over the step (Eq. 12).
+#include "fvib_kernels.h"
+
+namespace fvib {
+
+__device__ __forceinline__ double phi4(double s) {
+  s = fabs(s);
+  if (s <= 1.0) return (3.0 - 2.0 * s + sqrt(1.0 + 4.0 * s - 4.0 * s * s)) / 8.0;
+  if (s <= 2.0) return (5.0 - 2.0 * s - sqrt(-7.0 + 12.0 * s - 4.0 * s * s)) / 8.0;
+  return 0.0;
+}
+
+__device__ __forceinline__ double d_h(double r, double h) { return phi4(r / h) / h; }
+
+__device__ __forceinline__ void window_origin(const IbGeo& B, const double* body, int c,
+                                              int* ox, int* oy, bool* clamped) {
+  const double dx = body[0], dy = body[1];
+  int x0 = (int)floor((B.xmin0 + dx - B.fx[c][0]) / B.h) - B.margin;
+  int y0 = (int)floor((B.ymin0 + dy - B.fy[c][0]) / B.h) - B.margin;
+  const int xmax = B.ext[c][0] - B.W[c][0];
+  const int ymax = B.ext[c][1] - B.W[c][1];
+  bool cl = false;
+  if (x0 < 0) { x0 = 0; cl = true; }
+  if (y0 < 0) { y0 = 0; cl = true; }
+  if (x0 > xmax) { x0 = xmax; cl = true; }
+  if (y0 > ymax) { y0 = ymax; cl = true; }
+  *ox = x0;
+  *oy = y0;
+  *clamped = *clamped || cl;
+}
+
+__device__ bool inside_polygon(const IbGeo& B, double dxb, double dyb, double px, double py) {
+#pragma clang fp contract(off)
+  bool inside = false;
+  const int M = B.M;
+  for (int k = 0; k < M; ++k) {
+    const int kn = (k + 1 == M) ? 0 : k + 1;
+    const double ax = B.X0[2 * k] + dxb, ay = B.X0[2 * k + 1] + dyb;
+    const double bx = B.X0[2 * kn] + dxb, by = B.X0[2 * kn + 1] + dyb;
+    if ((ay <= py && py < by) || (by <= py && py < ay)) {
+      double t = (py - ay) * (bx - ax);
+      t = t / (by - ay);
+      const double xint = ax + t;
+      if (px < xint) inside = !inside;
+    }
+  }
+  return inside;
+}
+
+// pass 1: solid flags inside the window, and the window origins
+__global__ void __launch_bounds__(kBlock)
+k_ib_solid(IbGeo B, const double* __restrict__ body, SolverScalars* sc) {
+  int org[4];
+  bool clamped = false;
+  window_origin(B, body, 0, &org[0], &org[1], &clamped);
+  window_origin(B, body, 1, &org[2], &org[3], &clamped);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int q = 0; q < 4; ++q) B.origin[q] = org[q];
+    if (clamped) sc->clamp = 1;
+  }
+  const int n0 = B.W[0][0] * B.W[0][1];
+  const int n1 = B.W[1][0] * B.W[1][1];
+  for (int t = blockIdx.x * kBlock + threadIdx.x; t < n0 + n1; t += gridDim.x * kBlock) {
+    const int c = (t < n0) ? 0 : 1;
+    const int l = (c == 0) ? t : t - n0;
+    const int li = l % B.W[c][0], lj = l / B.W[c][0];
+    const int i = org[2 * c] + li, j = org[2 * c + 1] + lj;
+    const bool in = inside_polygon(B, body[0], body[1], B.fx[c][i], B.fy[c][j]);
+    B.cls[c][l] = in ? 1 : 0;
+  }
+}
+
+// pass 2: immersed-boundary points and target velocities
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_ib_targets(IbGeo B, const double* __restrict__ body, T* __restrict__ us0,
+             T* __restrict__ us1) {
+  T* us[2] = {us0, us1};
+  const int n0 = B.W[0][0] * B.W[0][1];
+  const int n1 = B.W[1][0] * B.W[1][1];
+  const double dxb = body[0], dyb = body[1];
+  for (int t = blockIdx.x * kBlock + threadIdx.x; t < n0 + n1; t += gridDim.x * kBlock) {
+    const int c = (t < n0) ? 0 : 1;
+    const int l = (c == 0) ? t : t - n0;
+    const int Wx = B.W[c][0], Wy = B.W[c][1];
+    const int li = l % Wx, lj = l / Wx;
+    const uint8_t* cl = B.cls[c];
+    const double Uc = body[3 + c];
+    if (cl[l] == 1) {
+      us[c][l] = (T)Uc;
+      continue;
+    }
+    const bool nb = (li > 0 && cl[l - 1] == 1) || (li + 1 < Wx && cl[l + 1] == 1) ||
+                    (lj > 0 && cl[l - Wx] == 1) || (lj + 1 < Wy && cl[l + Wx] == 1);
+    if (!nb) continue;
+    B.cls[c][l] = 2;
+    const int i = B.origin[2 * c] + li, j = B.origin[2 * c + 1] + lj;
+    const double px = B.fx[c][i], py = B.fy[c][j];
+    double num = 0.0, den = 0.0;
+    for (int k = 0; k < B.M; ++k) {
+      const double Xx = B.X0[2 * k] + dxb, Xy = B.X0[2 * k + 1] + dyb;
+      const double w = d_h(px - Xx, B.h) * d_h(py - Xy, B.h) * (B.ds[k] * B.h);
+      num += w * Uc;
+      den += w;
+    }
+    us[c][l] = (T)((den > 0.0) ? num / den : Uc);
+  }
+}
+
+// Loads on the body and RK4 update; one block.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_loads_body(IbGeo B, IbView<T> ib, const double* __restrict__ body_in,
+             double* __restrict__ body_out, const double* __restrict__ kc, SolverScalars* sc) {
+  const double dxb = body_in[0], dyb = body_in[1];
+  const double h = B.h;
+  double q[2] = {0.0, 0.0};
+  for (int k = threadIdx.x; k < B.M; k += kBlock) {
+    const double Xx = B.X0[2 * k] + dxb, Xy = B.X0[2 * k + 1] + dyb;
+    const double dV = B.ds[k] * h;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int i0 = (int)floor((Xx - B.fx[c][0]) / h) - 1;
+      const int j0 = (int)floor((Xy - B.fy[c][0]) / h) - 1;
+      const int ox = ib.origin[2 * c], oy = ib.origin[2 * c + 1];
+      double acc = 0.0;
+      for (int dj = 0; dj < 4; ++dj) {
+        const int lj = j0 + dj - oy;
+        if (lj < 0 || lj >= B.W[c][1]) continue;
+        const double wy = d_h(B.fy[c][j0 + dj] - Xy, h);
+        for (int di = 0; di < 4; ++di) {
+          const int li = i0 + di - ox;
+          if (li < 0 || li >= B.W[c][0]) continue;
+          const int l = lj * B.W[c][0] + li;
+          if (!ib.cls[c][l]) continue;
+          acc += (double)ib.f[c][l] * d_h(B.fx[c][i0 + di] - Xx, h) * wy;
+        }
+      }
+      q[c] += acc * (h * h) * dV;
+    }
+  }
+  block_sum<2>(q);
+  if (threadIdx.x != 0) return;
+  double F[3] = {-B.rho * q[0], -B.rho * q[1], 0.0};
+  for (int a = 0; a < 3; ++a) sc->force[a] = F[a];
+  double st[6];
+  for (int a = 0; a < 6; ++a) st[a] = body_in[a];
+  if (B.kind == FVIB_BODY_RIGID_SPRING) {
+    const double m = B.m, dt = B.dt;
+    for (int a = 0; a < 3; ++a) {
+      if (!B.free_dof[a]) continue;
+      const double kk = kc ? kc[a] : 0.0, cc = kc ? kc[3 + a] : 0.0;
+      const double d = st[a], v = st[3 + a], Fa = F[a];
+      const double k1d = v, k1v = (Fa - cc * v - kk * d) / m;
+      const double d2 = d + 0.5 * dt * k1d, v2 = v + 0.5 * dt * k1v;
+      const double k2d = v2, k2v = (Fa - cc * v2 - kk * d2) / m;
+      const double d3 = d + 0.5 * dt * k2d, v3 = v + 0.5 * dt * k2v;
+      const double k3d = v3, k3v = (Fa - cc * v3 - kk * d3) / m;
+      const double d4 = d + dt * k3d, v4 = v + dt * k3v;
+      const double k4d = v4, k4v = (Fa - cc * v4 - kk * d4) / m;
+      st[a] = d + (dt / 6.0) * (k1d + 2.0 * k2d + 2.0 * k3d + k4d);
+      st[3 + a] = v + (dt / 6.0) * (k1v + 2.0 * k2v + 2.0 * k3v + k4v);
+    }
+  }
+  for (int a = 0; a < 6; ++a) body_out[a] = st[a];
+}
+
+__global__ void k_copy_info(const SolverScalars* sc, fvib_step_info* info, int cg_iters,
+                            int ir_iters) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int st = sc->status;
+  if (st == FVIB_OK && sc->clamp) st = FVIB_EINVAL;
+  info->status = st;
+  info->cg_iters = cg_iters;
+  info->ir_iters = ir_iters;
+  info->flags = sc->clamp;
+  info->res = sc->crit;
+  info->div_max = sc->div_max;
+  for (int a = 0; a < 3; ++a) info->force[a] = sc->force[a];
+  info->reserved = 0.0;
+}
+
+// ------------------------------------------------------------ launchers
+template <typename T>
+int launch_ib_classify(const IbGeo& B, const double* body, T* us0, T* us1, SolverScalars* sc,
+                       hipStream_t s) {
+  const int n = B.W[0][0] * B.W[0][1] + B.W[1][0] * B.W[1][1];
+  const int nb = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_ib_solid, dim3(nb), dim3(kBlock), 0, s, B, body, sc);
+  FVIB_HIP(hipGetLastError());
+  hipLaunchKernelGGL((k_ib_targets<T>), dim3(nb), dim3(kBlock), 0, s, B, body, us0, us1);
+  FVIB_HIP(hipGetLastError());
+  return FVIB_OK;
+}
+
+template <typename T>
+int launch_loads_body(const IbGeo& B, const IbView<T>& ib, const double* body_in,
+                      double* body_out, const double* kc, SolverScalars* sc, hipStream_t s) {
+  hipLaunchKernelGGL((k_loads_body<T>), dim3(1), dim3(kBlock), 0, s, B, ib, body_in, body_out,
+                     kc, sc);
+  FVIB_HIP(hipGetLastError());
+  return FVIB_OK;
+}
+
+int launch_copy_info(const SolverScalars* sc, fvib_step_info* info, int cg_iters, int ir_iters,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_info, dim3(1), dim3(64), 0, s, sc, info, cg_iters, ir_iters);
+  FVIB_HIP(hipGetLastError());
+  return FVIB_OK;
+}
+
+template int launch_ib_classify<float>(const IbGeo&, const double*, float*, float*,
+                                       SolverScalars*, hipStream_t);
+template int launch_ib_classify<double>(const IbGeo&, const double*, double*, double*,
+                                        SolverScalars*, hipStream_t);
+template int launch_loads_body<float>(const IbGeo&, const IbView<float>&, const double*, double*,
+                                      const double*, SolverScalars*, hipStream_t);
+template int launch_loads_body<double>(const IbGeo&, const IbView<double>&, const double*,
+                                       double*, const double*, SolverScalars*, hipStream_t);
+
+}  // namespace fvib

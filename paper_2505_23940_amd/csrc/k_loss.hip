@@ -1,0 +1,72 @@
+// Scalar losses used to seed the adjoint: mean wall shear stress of a
+// wall-bounded flow and the root-mean-square lift coefficient of a force
+// history.  Each writes J and, optionally, its gradient.
+#include "fvib_kernels.h"
+
+namespace fvib {
+
+// J = (nu / 2) [ <u>_lo / (yc_0 - y_0) + <u>_hi / (y_N - yc_{N-1}) ], the
+// x-z means taken over the streamwise faces of the two wall-adjacent rows.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_wall_shear(int nx, int ny, int nz, const T* __restrict__ u, T* __restrict__ ubar, double wlo,
+             double whi, double* J) {
+  const int64_t plane = (int64_t)nx * nz;
+  double s[2] = {0.0, 0.0};
+  for (int64_t r = threadIdx.x; r < plane; r += kBlock) {
+    const int i = (int)(r % nx), k = (int)(r / nx);
+    const int64_t lo = ((int64_t)k * ny + 0) * nx + i;
+    const int64_t hi = ((int64_t)k * ny + (ny - 1)) * nx + i;
+    s[0] += (double)u[lo];
+    s[1] += (double)u[hi];
+    if (ubar) {
+      ubar[lo] = (T)((double)ubar[lo] + wlo / (double)plane);
+      ubar[hi] = (T)((double)ubar[hi] + whi / (double)plane);
+    }
+  }
+  block_sum<2>(s);
+  if (threadIdx.x == 0) *J = wlo * s[0] / (double)plane + whi * s[1] / (double)plane;
+}
+
+// J = sqrt(mean_n C_L^2), C_L = 2 F_y / (rho U^2 D); dJ/dF_y(n) = C_L(n) g / (S J)
+// with g = 2 / (rho U^2 D).
+__global__ void __launch_bounds__(kBlock)
+k_rms_lift(const double* __restrict__ Fh, int S, int stride, int off, double g, double* J,
+           double* dFh) {
+  double s[1] = {0.0};
+  for (int n = threadIdx.x; n < S; n += kBlock) {
+    const double cl = g * Fh[(int64_t)n * stride + off];
+    s[0] += cl * cl;
+  }
+  block_sum<1>(s);
+  const double j = sqrt(s[0] / (double)S);
+  if (threadIdx.x == 0) *J = j;
+  if (!dFh) return;
+  for (int n = threadIdx.x; n < S; n += kBlock) {
+    const double cl = g * Fh[(int64_t)n * stride + off];
+    dFh[(int64_t)n * stride + off] = (j > 0.0) ? cl * g / ((double)S * j) : 0.0;
+  }
+}
+
+template <typename T>
+int launch_wall_shear(int nx, int ny, int nz, const T* u, T* ubar, double wlo, double whi,
+                      double* J, hipStream_t s) {
+  hipLaunchKernelGGL((k_wall_shear<T>), dim3(1), dim3(kBlock), 0, s, nx, ny, nz, u, ubar, wlo,
+                     whi, J);
+  FVIB_HIP(hipGetLastError());
+  return FVIB_OK;
+}
+
+int launch_rms_lift(const double* Fh, int S, int stride, int off, double g, double* J,
+                    double* dFh, hipStream_t s) {
+  hipLaunchKernelGGL(k_rms_lift, dim3(1), dim3(kBlock), 0, s, Fh, S, stride, off, g, J, dFh);
+  FVIB_HIP(hipGetLastError());
+  return FVIB_OK;
+}
+
+template int launch_wall_shear<float>(int, int, int, const float*, float*, double, double,
+                                      double*, hipStream_t);
+template int launch_wall_shear<double>(int, int, int, const double*, double*, double, double,
+                                       double*, hipStream_t);
+
+}  // namespace fvib

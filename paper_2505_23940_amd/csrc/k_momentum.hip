@@ -1,0 +1,336 @@
+// Predictor of the projection method with direct forcing (paper Eqs. 4-5)
+// and the boundary-normal faces.
+//
+// R = -div(u (x) u) + nu lap(u) + f_b is evaluated on every face that the
+// momentum equation advances.  Convection is in divergence form: along its
+// own axis a component is carried to the cell centre as the mean of its two
+// faces; across the other axes it is interpolated linearly between cell
+// centres to the edge and multiplied by the transverse component
+// interpolated along the own axis (central), or the transported value is
+// taken from the upwind side (first-order upwind).  Diffusion is the
+// central second-order finite-volume Laplacian.
+//
+// One thread owns one cell and computes the low face of that cell for every
+// component, so each velocity array is read once per sweep with the
+// stencil neighbours served from L1/L2.
+#include "fvib_internal.h"
+
+namespace fvib {
+
+template <int C, int DIM, typename T>
+__device__ __forceinline__ T momentum_rhs(const Geo<T>& G, const T* const* u, const T* fbC,
+                                          int i, int j, int k) {
+  const int I[3] = {i, j, k};
+  const T* q = u[C];
+  const T q0 = ld<C, DIM>(G, q, i, j, k);
+  const int ic = I[C];
+  T conv = T(0);
+  T visc = T(0);
+  // convection along the own axis: fluxes at the two adjacent cell centres
+  {
+    int Im[3] = {i, j, k}, Ip[3] = {i, j, k};
+    Im[C] -= 1;
+    Ip[C] += 1;
+    const T qm = ld<C, DIM>(G, q, Im[0], Im[1], Im[2]);
+    const T qp = ld<C, DIM>(G, q, Ip[0], Ip[1], Ip[2]);
+    const T Qlo = T(0.5) * (qm + q0);
+    const T Qhi = T(0.5) * (q0 + qp);
+    T Flo, Fhi;
+    if (G.upwind) {
+      Flo = Qlo * (Qlo > T(0) ? qm : (Qlo < T(0) ? q0 : T(0)));
+      Fhi = Qhi * (Qhi > T(0) ? q0 : (Qhi < T(0) ? qp : T(0)));
+    } else {
+      Flo = Qlo * Qlo;
+      Fhi = Qhi * Qhi;
+    }
+    conv = (Fhi - Flo) / G.dc[C][ic];
+  }
+  // convection across the other axes: edge fluxes at a-faces ia and ia + 1
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    if (a == C) continue;
+    const int ia = I[a];
+    int Am[3] = {i, j, k}, Ap[3] = {i, j, k};
+    Am[a] -= 1;
+    Ap[a] += 1;
+    const T cm = ld<C, DIM>(G, q, Am[0], Am[1], Am[2]);
+    const T cp = ld<C, DIM>(G, q, Ap[0], Ap[1], Ap[2]);
+    // component a at (a-face ia, own cells ic-1, ic) and at a-face ia + 1
+    int B00[3] = {i, j, k};
+    B00[C] -= 1;
+    int B10[3] = {B00[0], B00[1], B00[2]};
+    B10[a] += 1;
+    const T* qa = u[a];
+    T a00, a01, a10, a11;
+    if (a == 0) {
+      a00 = ld<0, DIM>(G, qa, B00[0], B00[1], B00[2]);
+      a01 = ld<0, DIM>(G, qa, i, j, k);
+      a10 = ld<0, DIM>(G, qa, B10[0], B10[1], B10[2]);
+      a11 = ld<0, DIM>(G, qa, Ap[0], Ap[1], Ap[2]);
+    } else if (a == 1) {
+      a00 = ld<1, DIM>(G, qa, B00[0], B00[1], B00[2]);
+      a01 = ld<1, DIM>(G, qa, i, j, k);
+      a10 = ld<1, DIM>(G, qa, B10[0], B10[1], B10[2]);
+      a11 = ld<1, DIM>(G, qa, Ap[0], Ap[1], Ap[2]);
+    } else {
+      a00 = ld<2, DIM>(G, qa, B00[0], B00[1], B00[2]);
+      a01 = ld<2, DIM>(G, qa, i, j, k);
+      a10 = ld<2, DIM>(G, qa, B10[0], B10[1], B10[2]);
+      a11 = ld<2, DIM>(G, qa, Ap[0], Ap[1], Ap[2]);
+    }
+    const T wc = G.wi[C][ic];
+    const T V0 = (T(1) - wc) * a00 + wc * a01;
+    const T V1 = (T(1) - wc) * a10 + wc * a11;
+    T F0, F1;
+    if (G.upwind) {
+      F0 = V0 * (V0 > T(0) ? cm : (V0 < T(0) ? q0 : T(0)));
+      F1 = V1 * (V1 > T(0) ? q0 : (V1 < T(0) ? cp : T(0)));
+    } else {
+      const T w0 = G.wi[a][ia], w1 = G.wi[a][ia + 1];
+      const T U0 = (T(1) - w0) * cm + w0 * q0;
+      const T U1 = (T(1) - w1) * q0 + w1 * cp;
+      F0 = U0 * V0;
+      F1 = U1 * V1;
+    }
+    conv += (F1 - F0) / G.dx[a][ia];
+  }
+  // diffusion, summed over the axes in order
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    int Am[3] = {i, j, k}, Ap[3] = {i, j, k};
+    Am[a] -= 1;
+    Ap[a] += 1;
+    const T cm = ld<C, DIM>(G, q, Am[0], Am[1], Am[2]);
+    const T cp = ld<C, DIM>(G, q, Ap[0], Ap[1], Ap[2]);
+    const int ia = I[a];
+    if (a == C) {
+      visc += ((cp - q0) / G.dxe[C][ia + 1] - (q0 - cm) / G.dxe[C][ia]) / G.dc[C][ia];
+    } else {
+      visc += ((cp - q0) / G.dc[a][ia + 1] - (q0 - cm) / G.dc[a][ia]) / G.dx[a][ia];
+    }
+  }
+  const T fb = fbC ? fbC[fidx(G.ext[C], i, j, k)] : T(0);
+  return -conv + G.nu * visc + fb;
+}
+
+// Is face (i, j, k) of component C advanced by the momentum equation?
+template <int C, typename T>
+__device__ __forceinline__ bool evolved(const Geo<T>& G, int i, int j, int k) {
+  const int I[3] = {i, j, k};
+  return G.per[C] || (I[C] >= 1 && I[C] <= G.n[C] - 1);
+}
+
+// Forcing class of face (i, j) of component C < 2: 0 fluid, else forced.
+template <int C, typename T>
+__device__ __forceinline__ int forced(const IbView<T>& ib, int i, int j, int* lidx) {
+  if (!ib.active) return 0;
+  const int li = i - ib.origin[2 * C + 0];
+  const int lj = j - ib.origin[2 * C + 1];
+  if (li < 0 || lj < 0 || li >= ib.W[C][0] || lj >= ib.W[C][1]) return 0;
+  *lidx = lj * ib.W[C][0] + li;
+  return ib.cls[C][*lidx];
+}
+
+// Predictor (MODE 0) or right-hand side (MODE 1) of component C at face
+// (i, j, k):  u* = u + dt (R + f),  f = eps [ -R + (u_s - u) / dt ], i.e.
+// u* = u + dt R off the body and u* = u_s on forced faces.
+template <int C, int DIM, int MODE, typename T>
+__device__ __forceinline__ void predict_face(const Geo<T>& G, const T* const* u, const T* fb,
+                                             T* out, const IbView<T>& ib, int i, int j, int k) {
+  if (C >= DIM || !evolved<C>(G, i, j, k)) return;
+  const T R = momentum_rhs<C, DIM, T>(G, u, fb, i, j, k);
+  const int64_t id = fidx(G.ext[C], i, j, k);
+  if (MODE == 1) {
+    out[id] = R;
+    return;
+  }
+  const T un = u[C][id];
+  if constexpr (C < 2) {
+    int li = 0;
+    if (forced<C>(ib, i, j, &li)) {
+      // Eq. 5 substituted into Eq. 4: the forced face takes the target
+      // exactly, so u* - u_c stays free of rounding on forced faces.
+      const T us = ib.us[C][li];
+      ib.f[C][li] = -R + (us - un) / G.dt;
+      out[id] = us;
+      return;
+    }
+  }
+  out[id] = un + G.dt * R;
+}
+
+// MODE 0: predictor (writes u*, and the forcing on forced faces).
+// MODE 1: right-hand side only (writes R on advanced faces).
+template <typename T, int DIM, int MODE>
+__global__ void __launch_bounds__(kBlock)
+k_predictor(Geo<T> G, Tiling tl, const T* __restrict__ u0, const T* __restrict__ u1,
+            const T* __restrict__ u2, const T* __restrict__ fb0, const T* __restrict__ fb1,
+            const T* __restrict__ fb2, T* __restrict__ o0, T* __restrict__ o1,
+            T* __restrict__ o2, IbView<T> ib) {
+  const T* u[3] = {u0, u1, u2};
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  for (int t = b; t < tl.ntiles; t += gridDim.x) {
+    const int tx = t % tl.ntx;
+    const int ty = (t / tl.ntx) % tl.nty;
+    const int k = t / (tl.ntx * tl.nty);
+    const int i = tx * kTileX + (threadIdx.x & (kTileX - 1));
+    const int j = ty * kTileY + (threadIdx.x / kTileX);
+    if (i >= G.n[0] || j >= G.n[1]) continue;
+    predict_face<0, DIM, MODE, T>(G, u, fb0, o0, ib, i, j, k);
+    predict_face<1, DIM, MODE, T>(G, u, fb1, o1, ib, i, j, k);
+    predict_face<2, DIM, MODE, T>(G, u, fb2, o2, ib, i, j, k);
+  }
+}
+
+// ------------------------------------------------------ boundary faces
+// Faces normal to a bounded axis: walls / inflow hold bc_vel, a convective
+// outflow advects u_b with U_conv, a zero-gradient outflow copies the
+// advanced neighbour.  The outward flux of every boundary face is summed
+// (double) for the outflow correction.
+template <typename T>
+__device__ __forceinline__ double face_area(const Geo<T>& G, int c, int i, int j, int k) {
+  const int I[3] = {i, j, k};
+  double A = 1.0;
+  for (int a = 0; a < G.dim; ++a)
+    if (a != c) A *= (double)G.dx[a][I[a]];
+  return A;
+}
+
+template <typename T>
+__device__ __forceinline__ void plane_face(const Geo<T>& G, const Plane& P, int64_t r,
+                                           int& i, int& j, int& k) {
+  // enumerate the plane with the other two axes in (x, y, z) order
+  int I[3];
+  const int c = P.c;
+  const int b = (P.side == 0) ? 0 : G.n[c];
+  int64_t rem = r;
+  for (int a = 0; a < 3; ++a) {
+    if (a == c) { I[a] = b; continue; }
+    const int na = G.n[a];
+    I[a] = (int)(rem % na);
+    rem /= na;
+  }
+  i = I[0]; j = I[1]; k = I[2];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_boundary_faces(Geo<T> G, Planes PL, const T* __restrict__ un0, const T* __restrict__ un1,
+                 const T* __restrict__ un2, T* us0, T* us1, T* us2, RedBuf red,
+                 SolverScalars* sc) {
+  const T* un[3] = {un0, un1, un2};
+  T* us[3] = {us0, us1, us2};
+  int64_t total = 0;
+  for (int q = 0; q < PL.np; ++q) total += PL.p[q].count;
+  double flux = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < total;
+       r += (int64_t)gridDim.x * kBlock) {
+    int q = 0;
+    while (q + 1 < PL.np && r >= PL.p[q + 1].start) ++q;
+    const Plane& P = PL.p[q];
+    int i, j, k;
+    plane_face(G, P, r - P.start, i, j, k);
+    const int c = P.c;
+    const int64_t id = fidx(G.ext[c], i, j, k);
+    int In[3] = {i, j, k};
+    In[c] += (P.side == 0) ? 1 : -1;
+    const int64_t inner = fidx(G.ext[c], In[0], In[1], In[2]);
+    T val;
+    if (P.kind == FVIB_BC_OUTFLOW_CONVECTIVE) {
+      const T ub = un[c][id];
+      val = ub - G.dt * T(PL.u_conv) * (ub - un[c][inner]) / T(P.h);
+    } else if (P.kind == FVIB_BC_OUTFLOW_NEUMANN) {
+      val = us[c][inner];
+    } else {
+      val = T(P.value);
+    }
+    us[c][id] = val;
+    const double sign = (P.side == 0) ? -1.0 : 1.0;
+    flux += sign * (double)val * face_area(G, c, i, j, k);
+  }
+  if (!PL.any_outflow) return;
+  double v[1] = {flux}, tot[1];
+  if (grid_reduce<1, 1>(v, red.partial, red.ticket, tot)) {
+    if (threadIdx.x == 0) sc->meanb = tot[0] / PL.area_out;   // correction value
+  }
+}
+
+// Uniform correction of the outflow faces: u_b -= sign * net / area_out.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_outflow_correct(Geo<T> G, Planes PL, T* us0, T* us1, T* us2, const SolverScalars* sc) {
+  T* us[3] = {us0, us1, us2};
+  const double corr = sc->meanb;
+  int64_t total = 0;
+  for (int q = 0; q < PL.np; ++q) total += PL.p[q].count;
+  for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < total;
+       r += (int64_t)gridDim.x * kBlock) {
+    int q = 0;
+    while (q + 1 < PL.np && r >= PL.p[q + 1].start) ++q;
+    const Plane& P = PL.p[q];
+    if (P.kind != FVIB_BC_OUTFLOW_CONVECTIVE && P.kind != FVIB_BC_OUTFLOW_NEUMANN) continue;
+    int i, j, k;
+    plane_face(G, P, r - P.start, i, j, k);
+    const int64_t id = fidx(G.ext[P.c], i, j, k);
+    const double sign = (P.side == 0) ? -1.0 : 1.0;
+    us[P.c][id] = (T)((double)us[P.c][id] - sign * corr);
+  }
+}
+
+// ------------------------------------------------------------ launchers
+template <typename T>
+int launch_predictor(const Geo<T>& G, const T* const u[3], const T* const fb[3], T* out[3],
+                     const IbView<T>& ib, int mode, hipStream_t s) {
+  const Tiling tl = make_tiling(G.n[0], G.n[1], G.n[2], 4 * kMaxRedBlocks);
+  dim3 grid(tl.nblocks), block(kBlock);
+  if (G.dim == 2) {
+    if (mode == 0)
+      hipLaunchKernelGGL((k_predictor<T, 2, 0>), grid, block, 0, s, G, tl, u[0], u[1], u[2],
+                         fb[0], fb[1], fb[2], out[0], out[1], out[2], ib);
+    else
+      hipLaunchKernelGGL((k_predictor<T, 2, 1>), grid, block, 0, s, G, tl, u[0], u[1], u[2],
+                         fb[0], fb[1], fb[2], out[0], out[1], out[2], ib);
+  } else {
+    if (mode == 0)
+      hipLaunchKernelGGL((k_predictor<T, 3, 0>), grid, block, 0, s, G, tl, u[0], u[1], u[2],
+                         fb[0], fb[1], fb[2], out[0], out[1], out[2], ib);
+    else
+      hipLaunchKernelGGL((k_predictor<T, 3, 1>), grid, block, 0, s, G, tl, u[0], u[1], u[2],
+                         fb[0], fb[1], fb[2], out[0], out[1], out[2], ib);
+  }
+  FVIB_HIP(hipGetLastError());
+  return FVIB_OK;
+}
+
+template <typename T>
+int launch_boundary(const Geo<T>& G, const Planes& PL, const T* const un[3], T* us[3],
+                    RedBuf red, SolverScalars* sc, hipStream_t s) {
+  if (PL.np == 0) return FVIB_OK;
+  int64_t total = 0;
+  for (int q = 0; q < PL.np; ++q) total += PL.p[q].count;
+  int nb = (int)((total + kBlock - 1) / kBlock);
+  if (nb > kMaxRedBlocks) nb = kMaxRedBlocks;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL((k_boundary_faces<T>), dim3(nb), dim3(kBlock), 0, s, G, PL, un[0], un[1],
+                     un[2], us[0], us[1], us[2], red, sc);
+  FVIB_HIP(hipGetLastError());
+  if (PL.any_outflow) {
+    hipLaunchKernelGGL((k_outflow_correct<T>), dim3(nb), dim3(kBlock), 0, s, G, PL, us[0], us[1],
+                       us[2], (const SolverScalars*)sc);
+    FVIB_HIP(hipGetLastError());
+  }
+  return FVIB_OK;
+}
+
+template int launch_predictor<float>(const Geo<float>&, const float* const[3],
+                                     const float* const[3], float* [3], const IbView<float>&,
+                                     int, hipStream_t);
+template int launch_predictor<double>(const Geo<double>&, const double* const[3],
+                                      const double* const[3], double* [3],
+                                      const IbView<double>&, int, hipStream_t);
+template int launch_boundary<float>(const Geo<float>&, const Planes&, const float* const[3],
+                                    float* [3], RedBuf, SolverScalars*, hipStream_t);
+template int launch_boundary<double>(const Geo<double>&, const Planes&, const double* const[3],
+                                     double* [3], RedBuf, SolverScalars*, hipStream_t);
+
+}  // namespace fvib

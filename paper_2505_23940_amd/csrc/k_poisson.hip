@@ -1,0 +1,457 @@
+// Modified pressure Poisson equation (paper Eq. 9), its solution by
+// conjugate gradients (the paper's pressure solver), iterative refinement
+// with a float inner solve and a double residual, and the velocity
+// correction (Eq. 10).
+//
+// The PPE is solved in its volume-integrated symmetric form
+//   (A p)_c = sum_{interior faces f of c} (A_f / dc_f) (p_c - p_nb)
+//   b_c     = -(rho / dt) sum_{faces f of c} (+-) A_f u~_f,
+//   u~ = (1 - eps) u* + eps u_c,
+// with homogeneous Neumann conditions on bounded axes; A is symmetric
+// positive semi-definite with the constants as null space, so b has its
+// mean removed and every iterate is kept at zero mean.
+//
+// Convergence is measured by what the correction leaves behind: for the
+// residual r = b - A p the divergence of the corrected field is
+// -(dt / rho) r_c / V_c, and the solve stops when its maximum over the
+// cells falls below the requested tolerance.
+#include "fvib_internal.h"
+#include "fvib_kernels.h"
+
+namespace fvib {
+
+
+template <typename V, int DIM, typename Get>
+__device__ __forceinline__ V apply_A(const PGeo<V>& P, const Get& get, int i, int j, int k, V xc) {
+  const int I[3] = {i, j, k};
+  V acc = V(0);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    V area = V(1);
+#pragma unroll
+    for (int b = 0; b < DIM; ++b)
+      if (b != a) area *= P.dx[b][I[b]];
+    const int ia = I[a];
+    const int na = P.n[a];
+    if (P.per[a] || ia > 0) {
+      int J[3] = {i, j, k};
+      J[a] = (ia == 0) ? na - 1 : ia - 1;
+      acc += area * P.idc[a][ia] * (xc - get(J[0], J[1], J[2]));
+    }
+    if (P.per[a] || ia < na - 1) {
+      int J[3] = {i, j, k};
+      J[a] = (ia == na - 1) ? 0 : ia + 1;
+      acc += area * P.idc[a][ia + 1] * (xc - get(J[0], J[1], J[2]));
+    }
+  }
+  return acc;
+}
+
+template <typename V>
+__device__ __forceinline__ double cell_volume(const PGeo<V>& P, int i, int j, int k) {
+  double v = (double)P.dx[0][i] * (double)P.dx[1][j];
+  if (P.dim == 3) v *= (double)P.dx[2][k];
+  return v;
+}
+
+#define FVIB_TILE_LOOP(tl)                                                      \
+  for (int t_ = xcd_block(blockIdx.x, gridDim.x); t_ < (tl).ntiles; t_ += gridDim.x) { \
+    const int i = (t_ % (tl).ntx) * kTileX + (threadIdx.x & (kTileX - 1));   \
+    const int j = ((t_ / (tl).ntx) % (tl).nty) * kTileY + (threadIdx.x / kTileX); \
+    const int k = t_ / ((tl).ntx * (tl).nty);                                 \
+    if (i >= nx_ || j >= ny_) continue;                                       \
+    const int64_t c_ = ((int64_t)k * ny_ + j) * nx_ + i;
+
+#define FVIB_TILE_END }
+
+// ----------------------------------------------------------------- RHS
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_ppe_rhs(Geo<T> G, PGeo<double> P, Tiling tl, const T* __restrict__ s0,
+          const T* __restrict__ s1, const T* __restrict__ s2, IbView<T> ib,
+          double* __restrict__ b, RedBuf red, SolverScalars* sc) {
+  const int nx_ = G.n[0], ny_ = G.n[1];
+  const T* us[3] = {s0, s1, s2};
+  const double scale = -1.0 / P.dt_over_rho;
+  double sum = 0.0;
+  FVIB_TILE_LOOP(tl)
+    const int I[3] = {i, j, k};
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      double A = 1.0;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a)
+        if (a != c) A *= P.dx[a][I[a]];
+      int H[3] = {i, j, k};
+      H[c] += 1;
+      if (G.per[c] && H[c] == G.n[c]) H[c] = 0;
+      double lo = (double)us[c][fidx(G.ext[c], i, j, k)];
+      double hi = (double)us[c][fidx(G.ext[c], H[0], H[1], H[2])];
+      if (ib.active && c < 2) {
+        const double Uc = ib.body[3 + c];
+        const int* o = ib.origin;
+        const int W0 = ib.W[c][0], W1 = ib.W[c][1];
+        int li = i - o[2 * c], ljj = j - o[2 * c + 1];
+        if (li >= 0 && ljj >= 0 && li < W0 && ljj < W1 && ib.cls[c][ljj * W0 + li]) lo = Uc;
+        li = H[0] - o[2 * c];
+        ljj = H[1] - o[2 * c + 1];
+        if (li >= 0 && ljj >= 0 && li < W0 && ljj < W1 && ib.cls[c][ljj * W0 + li]) hi = Uc;
+      }
+      acc += hi * A - lo * A;
+    }
+    const double bc = scale * acc;
+    b[c_] = bc;
+    sum += bc;
+  FVIB_TILE_END
+  double v[1] = {sum}, tot[1];
+  if (grid_reduce<1, 1>(v, red.partial, red.ticket, tot)) {
+    if (threadIdx.x == 0) sc->meanb = tot[0] * P.inv_ncell;
+  }
+}
+
+// ------------------------------------------------------------ residual
+// r = b - mean(b) - A x in double.  MODE 0 (double CG): writes r (double)
+// and starts the solve.  MODE 1 (refinement): writes r as float for the
+// inner solve, clears the inner iterate and decides whether refinement is
+// finished.  Also records sum(x) to keep the iterate at zero mean.
+template <int DIM, int MODE>
+__global__ void __launch_bounds__(kBlock)
+k_residual(PGeo<double> P, Tiling tl, const double* __restrict__ b,
+           const double* __restrict__ x, double* __restrict__ r64, float* __restrict__ r32,
+           float* __restrict__ d32, RedBuf red, SolverScalars* sc, double tol,
+           double inner_rtol) {
+  const int nx_ = P.n[0], ny_ = P.n[1];
+  const double mb = sc->meanb;
+  double rr = 0.0, sx = 0.0, mx = 0.0;
+  auto get = [&](int a, int b_, int c) { return x[((int64_t)c * ny_ + b_) * nx_ + a]; };
+  FVIB_TILE_LOOP(tl)
+    const double xc = x[c_];
+    const double r = b[c_] - mb - apply_A<double, DIM>(P, get, i, j, k, xc);
+    if (MODE == 0) {
+      r64[c_] = r;
+    } else {
+      r32[c_] = (float)r;
+      d32[c_] = 0.0f;
+    }
+    rr += r * r;
+    sx += xc;
+    mx = fmax(mx, fabs(r) / cell_volume(P, i, j, k));
+  FVIB_TILE_END
+  double v[3] = {rr, sx, mx}, tot[3];
+  if (grid_reduce<3, 2>(v, red.partial, red.ticket, tot)) {
+    if (threadIdx.x == 0) {
+      const double crit = tot[2] * P.dt_over_rho;
+      sc->rr = tot[0];
+      sc->rr0 = tot[0];
+      sc->beta = 0.0;
+      sc->iters = 0;
+      sc->crit = crit;
+      sc->sumx = tot[1];
+      sc->tol_rr = inner_rtol * inner_rtol * tot[0];
+      const bool bad = !(tot[0] == tot[0]) || !(crit == crit);
+      if (bad) sc->status = FVIB_ENONFINITE;
+      const bool conv = bad || crit <= tol || tot[0] == 0.0;
+      sc->done = conv ? 1 : 0;
+      if (MODE == 1) sc->outer_done = conv ? 1 : 0;
+    }
+  }
+}
+
+// ------------------------------------------------------ CG direction
+// p_new = r + beta p_old (beta = 0 on the first iteration), then p.Ap and
+// sum(p).  p_new is formed on the fly at the stencil neighbours, so p_old
+// and r are each read once.
+template <typename V, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_cg_dir(PGeo<V> P, Tiling tl, const V* __restrict__ r, const V* __restrict__ pold,
+         V* __restrict__ pnew, RedBuf red, SolverScalars* sc) {
+  if (sc->done) return;
+  const int nx_ = P.n[0], ny_ = P.n[1];
+  const V beta = (V)sc->beta;
+  const bool first = (sc->iters == 0);
+  double pq = 0.0, sp = 0.0;
+  auto get = [&](int a, int b_, int c) {
+    const int64_t id = ((int64_t)c * ny_ + b_) * nx_ + a;
+    return first ? r[id] : r[id] + beta * pold[id];
+  };
+  FVIB_TILE_LOOP(tl)
+    const V pc = first ? r[c_] : r[c_] + beta * pold[c_];
+    const V q = apply_A<V, DIM>(P, get, i, j, k, pc);
+    pnew[c_] = pc;
+    pq += (double)pc * (double)q;
+    sp += (double)pc;
+  FVIB_TILE_END
+  double v[2] = {pq, sp}, tot[2];
+  if (grid_reduce<2, 2>(v, red.partial, red.ticket, tot)) {
+    if (threadIdx.x == 0) {
+      sc->pq = tot[0];
+      sc->alpha = (tot[0] > 0.0) ? sc->rr / tot[0] : 0.0;
+      sc->sump = tot[1];      // sum(p), used to keep x at zero mean
+      if (!(tot[0] == tot[0])) {
+        sc->status = FVIB_ENONFINITE;
+        sc->done = 1;
+        sc->outer_done = 1;
+      } else if (!(tot[0] > 0.0)) {
+        sc->done = 1;         // exact solution reached (p = 0)
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------- CG update
+// x += alpha (p - mean p), r -= alpha A p; r.r and max |r / V| decide the
+// next beta and convergence.  MODE 0: stop on the divergence criterion
+// (double solve).  MODE 1: stop on r.r <= inner_rtol^2 r0.r0 (inner solve).
+template <typename V, int DIM, int MODE>
+__global__ void __launch_bounds__(kBlock)
+k_cg_update(PGeo<V> P, Tiling tl, const V* __restrict__ p, V* __restrict__ x,
+            V* __restrict__ r, RedBuf red, SolverScalars* sc, double tol, int maxit) {
+  if (sc->done) return;
+  const int nx_ = P.n[0], ny_ = P.n[1];
+  const V alpha = (V)sc->alpha;
+  const V shift = (V)(sc->alpha * sc->sump * P.inv_ncell);
+  double rr = 0.0, mx = 0.0;
+  auto get = [&](int a, int b_, int c) { return p[((int64_t)c * ny_ + b_) * nx_ + a]; };
+  FVIB_TILE_LOOP(tl)
+    const V pc = p[c_];
+    const V q = apply_A<V, DIM>(P, get, i, j, k, pc);
+    x[c_] = x[c_] + (alpha * pc - shift);
+    const V rn = r[c_] - alpha * q;
+    r[c_] = rn;
+    rr += (double)rn * (double)rn;
+    if (MODE == 0) mx = fmax(mx, fabs((double)rn) / cell_volume(P, i, j, k));
+  FVIB_TILE_END
+  double v[2] = {rr, mx}, tot[2];
+  if (grid_reduce<2, 1>(v, red.partial, red.ticket, tot)) {
+    if (threadIdx.x == 0) {
+      const double rrn = tot[0];
+      sc->beta = (sc->rr > 0.0) ? rrn / sc->rr : 0.0;
+      sc->rr = rrn;
+      sc->iters += 1;
+      bool conv;
+      if (MODE == 0) {
+        sc->crit = tot[1] * P.dt_over_rho;
+        conv = sc->crit <= tol;
+      } else {
+        conv = rrn <= sc->tol_rr;
+      }
+      if (!(rrn == rrn)) {
+        sc->status = FVIB_ENONFINITE;
+        sc->outer_done = 1;
+        conv = true;
+      }
+      if (!conv && sc->iters >= maxit) {
+        if (MODE == 0) sc->status = FVIB_ENOCONV;
+        conv = true;
+      }
+      sc->done = conv ? 1 : 0;
+    }
+  }
+}
+
+// ------------------------------------------------ refinement correction
+// p64 += d32 - mean(p64): the residual kernel recorded sum(p64) and the
+// inner iterate is kept at zero mean by its own updates.
+__global__ void __launch_bounds__(kBlock)
+k_ir_correct(int64_t n, double* __restrict__ p, const float* __restrict__ d,
+             const SolverScalars* sc, double inv_n) {
+  const double shift = sc->sumx * inv_n;
+  for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < n;
+       c += (int64_t)gridDim.x * kBlock)
+    p[c] = (p[c] + (double)d[c]) - shift;
+}
+
+// --------------------------------------------------------- projection
+// u^{n+1} = u* - (dt/rho) (p_c - p_{c-1}) / dc on every face that is not a
+// boundary face of a bounded axis (those keep u*).  Each thread owns the
+// low faces of its cell and, on the last cell of a bounded axis, the high
+// boundary face.  The divergence of the corrected field is evaluated in
+// double before rounding to the storage type and its maximum recorded.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_project(Geo<T> G, PGeo<double> P, Tiling tl, const T* __restrict__ s0,
+          const T* __restrict__ s1, const T* __restrict__ s2, const double* __restrict__ p,
+          T* __restrict__ o0, T* __restrict__ o1, T* __restrict__ o2, RedBuf red,
+          SolverScalars* sc) {
+  const int nx_ = G.n[0], ny_ = G.n[1];
+  const T* us[3] = {s0, s1, s2};
+  T* out[3] = {o0, o1, o2};
+  const double f = P.dt_over_rho;
+  double mx = 0.0;
+  FVIB_TILE_LOOP(tl)
+    const int I[3] = {i, j, k};
+    const double pc = p[c_];
+    double div = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const int ic = I[c];
+      const int nc = G.n[c];
+      double A = 1.0;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a)
+        if (a != c) A *= P.dx[a][I[a]];
+      // low face
+      const int64_t lo_id = fidx(G.ext[c], i, j, k);
+      double ulo = (double)us[c][lo_id];
+      if (G.per[c] || ic > 0) {
+        int J[3] = {i, j, k};
+        J[c] = (ic == 0) ? nc - 1 : ic - 1;
+        const double pn = p[((int64_t)J[2] * ny_ + J[1]) * nx_ + J[0]];
+        ulo = ulo - f * (pc - pn) * P.idc[c][ic];
+      }
+      out[c][lo_id] = (T)ulo;
+      // high face
+      int H[3] = {i, j, k};
+      H[c] = ic + 1;
+      double uhi;
+      if (G.per[c] || ic + 1 < nc) {
+        if (H[c] == nc) H[c] = 0;
+        const int64_t hi_id = fidx(G.ext[c], H[0], H[1], H[2]);
+        const double pn = p[((int64_t)H[2] * ny_ + H[1]) * nx_ + H[0]];
+        uhi = (double)us[c][hi_id] - f * (pn - pc) * P.idc[c][ic + 1];
+      } else {
+        const int64_t hi_id = fidx(G.ext[c], H[0], H[1], H[2]);
+        uhi = (double)us[c][hi_id];
+        out[c][hi_id] = (T)uhi;     // boundary face of a bounded axis
+      }
+      div += (uhi - ulo) * A;
+    }
+    mx = fmax(mx, fabs(div) / cell_volume(P, i, j, k));
+  FVIB_TILE_END
+  double v[1] = {mx}, tot[1];
+  if (grid_reduce<1, 0>(v, red.partial, red.ticket, tot)) {
+    if (threadIdx.x == 0) sc->div_max = tot[0];
+  }
+}
+
+// ---------------------------------------------------------- apply A
+__global__ void __launch_bounds__(kBlock)
+k_apply_A(PGeo<double> P, Tiling tl, const double* __restrict__ x, double* __restrict__ y) {
+  const int nx_ = P.n[0], ny_ = P.n[1];
+  auto get = [&](int a, int b_, int c) { return x[((int64_t)c * ny_ + b_) * nx_ + a]; };
+  FVIB_TILE_LOOP(tl)
+    if (P.dim == 3)
+      y[c_] = apply_A<double, 3>(P, get, i, j, k, x[c_]);
+    else
+      y[c_] = apply_A<double, 2>(P, get, i, j, k, x[c_]);
+  FVIB_TILE_END
+}
+
+// ============================================================ launchers
+static inline Tiling red_tiling(const int n[3]) { return make_tiling(n[0], n[1], n[2]); }
+
+template <typename T>
+int launch_ppe_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
+                   const IbView<T>& ib, double* b, RedBuf red, SolverScalars* sc,
+                   hipStream_t s) {
+  const Tiling tl = red_tiling(G.n);
+  if (G.dim == 2)
+    hipLaunchKernelGGL((k_ppe_rhs<T, 2>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, us[0],
+                       us[1], us[2], ib, b, red, sc);
+  else
+    hipLaunchKernelGGL((k_ppe_rhs<T, 3>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, us[0],
+                       us[1], us[2], ib, b, red, sc);
+  FVIB_HIP(hipGetLastError());
+  return FVIB_OK;
+}
+
+int launch_residual(const PGeo<double>& P, int mode, const double* b, const double* x,
+                    double* r64, float* r32, float* d32, RedBuf red, SolverScalars* sc,
+                    double tol, double inner_rtol, hipStream_t s) {
+  const Tiling tl = red_tiling(P.n);
+  dim3 g(tl.nblocks), bl(kBlock);
+  if (P.dim == 2) {
+    if (mode == 0)
+      hipLaunchKernelGGL((k_residual<2, 0>), g, bl, 0, s, P, tl, b, x, r64, r32, d32, red, sc, tol, inner_rtol);
+    else
+      hipLaunchKernelGGL((k_residual<2, 1>), g, bl, 0, s, P, tl, b, x, r64, r32, d32, red, sc, tol, inner_rtol);
+  } else {
+    if (mode == 0)
+      hipLaunchKernelGGL((k_residual<3, 0>), g, bl, 0, s, P, tl, b, x, r64, r32, d32, red, sc, tol, inner_rtol);
+    else
+      hipLaunchKernelGGL((k_residual<3, 1>), g, bl, 0, s, P, tl, b, x, r64, r32, d32, red, sc, tol, inner_rtol);
+  }
+  FVIB_HIP(hipGetLastError());
+  return FVIB_OK;
+}
+
+template <typename V>
+int launch_cg_iter(const PGeo<V>& P, int mode, const V* r, const V* pold, V* pnew, V* x, V* rw,
+                   RedBuf red, SolverScalars* sc, double tol, int maxit, hipStream_t s,
+                   hipEvent_t* ev) {
+  const Tiling tl = red_tiling(P.n);
+  dim3 g(tl.nblocks), bl(kBlock);
+  if (ev) FVIB_HIP(hipEventRecord(ev[0], s));
+  if (P.dim == 2)
+    hipLaunchKernelGGL((k_cg_dir<V, 2>), g, bl, 0, s, P, tl, r, pold, pnew, red, sc);
+  else
+    hipLaunchKernelGGL((k_cg_dir<V, 3>), g, bl, 0, s, P, tl, r, pold, pnew, red, sc);
+  FVIB_HIP(hipGetLastError());
+  if (ev) FVIB_HIP(hipEventRecord(ev[1], s));
+  if (P.dim == 2) {
+    if (mode == 0)
+      hipLaunchKernelGGL((k_cg_update<V, 2, 0>), g, bl, 0, s, P, tl, (const V*)pnew, x, rw, red, sc, tol, maxit);
+    else
+      hipLaunchKernelGGL((k_cg_update<V, 2, 1>), g, bl, 0, s, P, tl, (const V*)pnew, x, rw, red, sc, tol, maxit);
+  } else {
+    if (mode == 0)
+      hipLaunchKernelGGL((k_cg_update<V, 3, 0>), g, bl, 0, s, P, tl, (const V*)pnew, x, rw, red, sc, tol, maxit);
+    else
+      hipLaunchKernelGGL((k_cg_update<V, 3, 1>), g, bl, 0, s, P, tl, (const V*)pnew, x, rw, red, sc, tol, maxit);
+  }
+  FVIB_HIP(hipGetLastError());
+  if (ev) FVIB_HIP(hipEventRecord(ev[2], s));
+  return FVIB_OK;
+}
+
+int launch_ir_correct(int64_t n, double* p, const float* d, const SolverScalars* sc,
+                      hipStream_t s) {
+  int nb = (int)((n + kBlock - 1) / kBlock);
+  if (nb > 4 * kMaxRedBlocks) nb = 4 * kMaxRedBlocks;
+  hipLaunchKernelGGL(k_ir_correct, dim3(nb), dim3(kBlock), 0, s, n, p, d, sc, 1.0 / (double)n);
+  FVIB_HIP(hipGetLastError());
+  return FVIB_OK;
+}
+
+template <typename T>
+int launch_project(const Geo<T>& G, const PGeo<double>& P, const T* const us[3], const double* p,
+                   T* out[3], RedBuf red, SolverScalars* sc, hipStream_t s) {
+  const Tiling tl = red_tiling(G.n);
+  if (G.dim == 2)
+    hipLaunchKernelGGL((k_project<T, 2>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, us[0],
+                       us[1], us[2], p, out[0], out[1], out[2], red, sc);
+  else
+    hipLaunchKernelGGL((k_project<T, 3>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, us[0],
+                       us[1], us[2], p, out[0], out[1], out[2], red, sc);
+  FVIB_HIP(hipGetLastError());
+  return FVIB_OK;
+}
+
+int launch_apply_A(const PGeo<double>& P, const double* x, double* y, hipStream_t s) {
+  const Tiling tl = red_tiling(P.n);
+  hipLaunchKernelGGL(k_apply_A, dim3(tl.nblocks), dim3(kBlock), 0, s, P, tl, x, y);
+  FVIB_HIP(hipGetLastError());
+  return FVIB_OK;
+}
+
+template int launch_ppe_rhs<float>(const Geo<float>&, const PGeo<double>&, const float* const[3],
+                                   const IbView<float>&, double*, RedBuf, SolverScalars*,
+                                   hipStream_t);
+template int launch_ppe_rhs<double>(const Geo<double>&, const PGeo<double>&,
+                                    const double* const[3], const IbView<double>&, double*,
+                                    RedBuf, SolverScalars*, hipStream_t);
+template int launch_cg_iter<float>(const PGeo<float>&, int, const float*, const float*, float*,
+                                   float*, float*, RedBuf, SolverScalars*, double, int,
+                                   hipStream_t, hipEvent_t*);
+template int launch_cg_iter<double>(const PGeo<double>&, int, const double*, const double*,
+                                    double*, double*, double*, RedBuf, SolverScalars*, double,
+                                    int, hipStream_t, hipEvent_t*);
+template int launch_project<float>(const Geo<float>&, const PGeo<double>&, const float* const[3],
+                                   const double*, float* [3], RedBuf, SolverScalars*,
+                                   hipStream_t);
+template int launch_project<double>(const Geo<double>&, const PGeo<double>&,
+                                    const double* const[3], const double*, double* [3], RedBuf,
+                                    SolverScalars*, hipStream_t);
+
+}  // namespace fvib
