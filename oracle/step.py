@@ -52,7 +52,7 @@ def init_state(g: Grid, u0, body0=None):
     p = torch.zeros(g.cell_shape(), dtype=F64)
     if body0 is None:
         body0 = np.zeros(6)
-    return {"u": u, "p": p, "body": torch.as_tensor(np.asarray(body0), dtype=F64)}
+    return {"u": u, "p": p, "body": _as64(body0)}
 
 
 def body_geometry(g: Grid, bstate: torch.Tensor):

@@ -106,7 +106,10 @@ struct Grid {
   SolverScalars* sc = nullptr;
   SolverScalars* sch = nullptr;   // pinned host mirror
   fvib_step_info* info_dev = nullptr;
+  double* mu = nullptr;           // adjoint pressure (kept as the next warm start)
+  double* body_tmp = nullptr;     // scratch body state (adjoint recomputation)
   int last_iters = 0;
+  int last_iters_adj = 0;
   // immersed body
   bool has_body = false;
   IbGeo ib;
@@ -161,6 +164,8 @@ static void release(Grid* g) {
   f(g->ticket);
   f(g->sc);
   f(g->info_dev);
+  f(g->mu);
+  f(g->body_tmp);
   if (g->sch) (void)hipHostFree(g->sch);
   f(g->ib_mem);
   f(g->origin);
@@ -390,11 +395,22 @@ static int read_scalars(Grid* g) {
 
 // Solve A p = b - mean(b) in place on p (initial guess on input); meanb
 // must already be in the device scalars.
-static int poisson_solve(Grid* g, const double* b, double* p, int* cg_total, int* ir_total) {
+static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* last,
+                         int* cg_total, int* ir_total) {
   int rc;
   *cg_total = 0;
   *ir_total = 0;
-  const double tol = g->d.poisson_tol;
+  const int saved = g->last_iters;
+  g->last_iters = *last;
+  struct Restore {
+    Grid* g;
+    int* last;
+    int saved;
+    ~Restore() {
+      *last = g->last_iters;
+      g->last_iters = saved;
+    }
+  } restore{g, last, saved};
   if (g->prec == FVIB_PREC_FP64) {
     rc = timed(g, FVIB_K_RESIDUAL, [&] {
       return launch_residual(g->P64, 0, b, p, g->r64, nullptr, nullptr, g->red(), g->sc, tol,
@@ -506,7 +522,9 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
     FVIB_HIP(hipMemcpyAsync(out->p, in->p, g->ncell * sizeof(double), hipMemcpyDeviceToDevice,
                             g->stream));
   int cg = 0, ir = 0;
-  if ((rc = poisson_solve(g, g->b, out->p, &cg, &ir))) return rc;
+  int last = g->last_iters;
+  if ((rc = poisson_solve(g, g->b, out->p, g->d.poisson_tol, &last, &cg, &ir))) return rc;
+  g->last_iters = last;
   if ((rc = timed(g, FVIB_K_PROJECT, [&] {
          return launch_project<T>(G, g->P64, (const T* const*)us, out->p, uo, g->red(), g->sc,
                                   g->stream);
@@ -530,6 +548,90 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
   if (st == FVIB_ENONFINITE) return fail(g, st, "non-finite value in a global reduction");
   g->err.clear();
   return st;
+}
+
+// Discrete adjoint of one step (see k_adjoint.hip for the derivation).
+template <typename T>
+static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint* bo,
+                             const double* dF, fvib_adjoint* bi, fvib_step_info* info) {
+  int rc;
+  if ((rc = reset_scalars(g))) return rc;
+  const Geo<T>& G = geo_of<T>(g);
+  const int d = g->dim;
+  const T* u[3] = {(const T*)in->u[0], (const T*)in->u[1], d == 3 ? (const T*)in->u[2] : nullptr};
+  const T* fb[3] = {(const T*)in->fb[0], (const T*)in->fb[1], d == 3 ? (const T*)in->fb[2] : nullptr};
+  T* usb[3] = {(T*)g->ustar[0], (T*)g->ustar[1], (T*)g->ustar[2]};
+  const T* ub1[3] = {(const T*)bo->u[0], (const T*)bo->u[1], d == 3 ? (const T*)bo->u[2] : nullptr};
+  T* ub0[3] = {(T*)bi->u[0], (T*)bi->u[1], d == 3 ? (T*)bi->u[2] : nullptr};
+  T* fbb[3] = {(T*)bi->fb[0], (T*)bi->fb[1], d == 3 ? (T*)bi->fb[2] : nullptr};
+  const IbView<T> ib = ib_view<T>(g, in->body);
+  if (g->has_body) {
+    // recompute the forward forcing and force of this step (frozen classes)
+    rc = timed(g, FVIB_K_IB, [&] {
+      return launch_ib_classify<T>(g->ib, in->body, (T*)g->us[0], (T*)g->us[1], g->sc,
+                                   g->stream);
+    });
+    if (rc) return rc;
+    if ((rc = timed(g, FVIB_K_PREDICTOR,
+                    [&] { return launch_predictor<T>(G, u, fb, usb, ib, 0, g->stream); })))
+      return rc;
+    rc = timed(g, FVIB_K_IB, [&] {
+      int r = launch_loads_body<T>(g->ib, ib, in->body, g->body_tmp, in->kc, g->sc, g->stream);
+      if (r) return r;
+      return launch_adj_body_loads<T>(g->ib, ib, in->body, bo->body, dF, in->kc, bi->body,
+                                      bi->kc, g->sc, g->stream);
+    });
+    if (rc) return rc;
+  } else if (bi->body) {
+    if (bo->body)
+      FVIB_HIP(hipMemcpyAsync(bi->body, bo->body, 6 * sizeof(double), hipMemcpyDeviceToDevice,
+                              g->stream));
+    else
+      FVIB_HIP(hipMemsetAsync(bi->body, 0, 6 * sizeof(double), g->stream));
+  }
+  // projection^T: A mu = G^T ubar^{n+1}
+  if ((rc = timed(g, FVIB_K_ADJOINT,
+                  [&] { return launch_adj_rhs<T>(G, g->P64, ub1, g->b, g->red(), g->sc, g->stream); })))
+    return rc;
+  if ((rc = read_scalars(g))) return rc;
+  const double ymax = g->sch->crit;
+  int cg = 0, ir = 0;
+  if (ymax > 0.0) {
+    const double tol = 1e-11 * ymax * g->d.dt / g->d.rho;
+    if ((rc = poisson_solve(g, g->b, g->mu, tol, &g->last_iters_adj, &cg, &ir))) return rc;
+  } else {
+    FVIB_HIP(hipMemsetAsync(g->mu, 0, g->ncell * sizeof(double), g->stream));
+  }
+  if ((rc = timed(g, FVIB_K_ADJOINT,
+                  [&] { return launch_adj_ustar<T>(G, g->P64, ub1, g->mu, ib, usb, g->stream); })))
+    return rc;
+  if (g->has_body && bi->body) {
+    rc = timed(g, FVIB_K_IB, [&] {
+      return launch_adj_ubody<T>(G, g->P64, g->ib, ub1, g->mu, ib, bi->body, g->stream);
+    });
+    if (rc) return rc;
+  }
+  if ((rc = timed(g, FVIB_K_ADJOINT, [&] {
+         return launch_adj_outflow<T>(G, g->planes, 0, usb, ub0, g->red(), g->sc, g->stream);
+       })))
+    return rc;
+  if ((rc = timed(g, FVIB_K_ADJOINT, [&] {
+         return launch_adj_momentum<T>(G, u, (const T* const*)usb, ib, ub0, fbb, g->stream);
+       })))
+    return rc;
+  if ((rc = timed(g, FVIB_K_ADJOINT, [&] {
+         return launch_adj_outflow<T>(G, g->planes, 1, usb, ub0, g->red(), g->sc, g->stream);
+       })))
+    return rc;
+  fvib_step_info* dst = info ? info : g->info_dev;
+  if ((rc = launch_copy_info(g->sc, dst, cg, ir, g->stream))) return rc;
+  if ((rc = read_scalars(g))) return rc;
+  if (g->timer.on) g->timer.resolve();
+  const int st = g->sch->status;
+  if (st == FVIB_ENOCONV) return fail(g, st, "adjoint Poisson solve did not converge");
+  if (st == FVIB_ENONFINITE) return fail(g, st, "non-finite value in the adjoint");
+  g->err.clear();
+  return FVIB_OK;
 }
 
 }  // namespace fvib
@@ -616,10 +718,13 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
   ok &= dmalloc(&g->ticket, 64 * sizeof(unsigned int)) == FVIB_OK;
   ok &= dmalloc(&g->sc, sizeof(SolverScalars)) == FVIB_OK;
   ok &= dmalloc(&g->info_dev, sizeof(fvib_step_info)) == FVIB_OK;
+  ok &= dmalloc(&g->mu, g->ncell * sizeof(double)) == FVIB_OK;
+  ok &= dmalloc(&g->body_tmp, 8 * sizeof(double)) == FVIB_OK;
   if (!ok) return bail(FVIB_ENOMEM, "device allocation of the workspace failed");
   if (hipHostMalloc((void**)&g->sch, sizeof(SolverScalars), hipHostMallocDefault) != hipSuccess)
     return bail(FVIB_ENOMEM, "pinned host allocation failed");
-  if (hipMemset(g->ticket, 0, 64 * sizeof(unsigned int)) != hipSuccess ||
+  if (hipMemset(g->mu, 0, g->ncell * sizeof(double)) != hipSuccess ||
+      hipMemset(g->ticket, 0, 64 * sizeof(unsigned int)) != hipSuccess ||
       hipMemset(g->sc, 0, sizeof(SolverScalars)) != hipSuccess)
     return bail(FVIB_EHIP, "workspace initialisation failed");
   for (int c = 0; c < g->dim; ++c)
@@ -778,6 +883,22 @@ int fvib_step(fvib_grid* h, const fvib_fields* in, fvib_fields* out, fvib_step_i
   return step_impl<float>(g, in, out, info);
 }
 
+int fvib_step_adjoint(fvib_grid* h, const fvib_fields* fwd_in, const fvib_adjoint* bar_out,
+                      const double* dF, fvib_adjoint* bar_in, fvib_step_info* info) {
+  if (!h) return FVIB_EINVAL;
+  Grid* g = &h->g;
+  if (!fwd_in || !bar_out || !bar_in) return fail(g, FVIB_EINVAL, "NULL argument");
+  for (int c = 0; c < g->dim; ++c) {
+    if (!fwd_in->u[c] || !bar_out->u[c] || !bar_in->u[c])
+      return fail(g, FVIB_EINVAL, "velocity or adjoint pointer is NULL");
+    if (bar_in->u[c] == bar_out->u[c]) return fail(g, FVIB_EINVAL, "bar_in may not alias bar_out");
+  }
+  if (g->has_body && (!fwd_in->body || !bar_in->body))
+    return fail(g, FVIB_EINVAL, "body state and its adjoint are required with a body");
+  if (g->prec == FVIB_PREC_FP64) return step_adjoint_impl<double>(g, fwd_in, bar_out, dF, bar_in, info);
+  return step_adjoint_impl<float>(g, fwd_in, bar_out, dF, bar_in, info);
+}
+
 const char* fvib_last_error(const fvib_grid* h) {
   if (!h) return g_create_error.c_str();
   return h->g.err.c_str();
@@ -849,7 +970,9 @@ int fvib_test_poisson(fvib_grid* h, const double* b, double* p, int32_t* iters) 
   const double mean = s / (double)g->ncell;
   FVIB_HIP(hipMemcpyAsync(&g->sc->meanb, &mean, sizeof(double), hipMemcpyHostToDevice, g->stream));
   int cg = 0, ir = 0;
-  if ((rc = poisson_solve(g, b, p, &cg, &ir))) return rc;
+  int last = g->last_iters;
+  if ((rc = poisson_solve(g, b, p, g->d.poisson_tol, &last, &cg, &ir))) return rc;
+  g->last_iters = last;
   if ((rc = read_scalars(g))) return rc;
   if (iters) *iters = cg;
   if (g->sch->status) return fail(g, g->sch->status, "Poisson solve failed");

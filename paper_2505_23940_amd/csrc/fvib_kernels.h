@@ -63,6 +63,27 @@ int launch_loads_body(const IbGeo& B, const IbView<T>& ib, const double* body_in
 int launch_copy_info(const SolverScalars* sc, fvib_step_info* info, int cg_iters, int ir_iters,
                      hipStream_t s);
 
+// k_adjoint.hip
+template <typename T>
+int launch_adj_body_loads(const IbGeo& B, const IbView<T>& ib, const double* st,
+                          const double* stbar_out, const double* dF, const double* kc,
+                          double* stbar_in, double* kcbar, SolverScalars* sc, hipStream_t s);
+template <typename T>
+int launch_adj_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const ub[3], double* y,
+                   RedBuf red, SolverScalars* sc, hipStream_t s);
+template <typename T>
+int launch_adj_ustar(const Geo<T>& G, const PGeo<double>& P, const T* const ub1[3],
+                     const double* mu, const IbView<T>& ib, T* usb[3], hipStream_t s);
+template <typename T>
+int launch_adj_ubody(const Geo<T>& G, const PGeo<double>& P, const IbGeo& B, const T* const ub1[3],
+                     const double* mu, const IbView<T>& ib, double* stbar, hipStream_t s);
+template <typename T>
+int launch_adj_outflow(const Geo<T>& G, const Planes& PL, int mode, T* usb[3], T* ubar[3],
+                       RedBuf red, SolverScalars* sc, hipStream_t s);
+template <typename T>
+int launch_adj_momentum(const Geo<T>& G, const T* const u[3], const T* const usb[3],
+                        const IbView<T>& ib, T* ubar[3], T* fbbar[3], hipStream_t s);
+
 // k_loss.hip
 template <typename T>
 int launch_wall_shear(int nx, int ny, int nz, const T* u, T* ubar, double wlo, double whi,

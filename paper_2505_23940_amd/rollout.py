@@ -1,0 +1,139 @@
+"""Differentiable rollouts over libfvib (reverse mode through the discrete
+adjoint of each step).
+
+The forward pass repeats ``fvib_step`` (the paper's main loop, Alg. 2, with
+one weakly coupled step per iteration) and keeps a checkpoint every
+``ckpt_every`` steps.  The backward pass walks the segments in reverse:
+it restores the segment's checkpoint, recomputes the states inside the
+segment with the same (deterministic) forward step, then applies
+``fvib_step_adjoint`` step by step.  Memory is O(S / K + K) states; K = 1
+keeps every state and recomputes nothing.  Gradients flow to the initial
+velocity, the body-force field, the spring constants (k, c) and the
+initial body state; the loss may read the final velocity, the final body
+state and the per-step force history.
+"""
+from __future__ import annotations
+
+from typing import List, Optional
+
+import torch
+
+from . import Grid, INFO_DOUBLES
+
+
+class _Rollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, grid: Grid, nsteps: int, ckpt_every: int, nd: int, *tensors):
+        u0 = list(tensors[:nd])
+        fb = list(tensors[nd:2 * nd])
+        kc, body0 = tensors[2 * nd], tensors[2 * nd + 1]
+        dev = grid.device
+        u = [x.detach().clone() for x in u0]
+        p = grid.zeros_p()
+        body = body0.detach().clone()
+        fbd = [x.detach() for x in fb]
+        kcd = kc.detach()
+        info = torch.zeros((nsteps, INFO_DOUBLES), dtype=torch.float64, device=dev)
+        ckpts = {}
+        for n in range(nsteps):
+            if n % ckpt_every == 0:
+                ckpts[n] = ([x.clone() for x in u], p.clone(), body.clone())
+            grid.step(u, p, fbd, body, kcd, info=info[n])
+        ctx.grid = grid
+        ctx.nsteps = nsteps
+        ctx.k = ckpt_every
+        ctx.nd = nd
+        ctx.ckpts = ckpts
+        ctx.save_for_backward(*fbd, kcd)
+        Fh = info[:, 4:7].clone()
+        ctx.mark_non_differentiable(p)
+        return (*u, body, Fh, p)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        grid: Grid = ctx.grid
+        nd, S, K = ctx.nd, ctx.nsteps, ctx.k
+        saved = ctx.saved_tensors
+        fb = list(saved[:nd])
+        kc = saved[nd]
+        gu = grads[:nd]
+        gbody, gF = grads[nd], grads[nd + 1]
+        ubar = [(g.contiguous().clone() if g is not None else torch.zeros(grid.layouts[c][0], dtype=grid.dtype, device=grid.device))
+                for c, g in enumerate(gu)]
+        ubar_tmp = grid.zeros_u()
+        bbar = gbody.contiguous().clone() if gbody is not None else torch.zeros(6, dtype=torch.float64, device=grid.device)
+        bbar_tmp = torch.zeros(6, dtype=torch.float64, device=grid.device)
+        gF = gF.contiguous() if gF is not None else torch.zeros((S, 3), dtype=torch.float64, device=grid.device)
+        fbbar = grid.zeros_u()
+        kcbar = torch.zeros(6, dtype=torch.float64, device=grid.device)
+        starts = list(range(0, S, K))
+        for s0 in reversed(starts):
+            s1 = min(s0 + K, S)
+            cu, cp, cb = ctx.ckpts[s0]
+            u = [x.clone() for x in cu]
+            p = cp.clone()
+            body = cb.clone()
+            states = []
+            for n in range(s0, s1):
+                states.append(([x.clone() for x in u], body.clone()))
+                if n + 1 < s1:
+                    grid.step(u, p, fb, body, kc)
+            for n in reversed(range(s0, s1)):
+                un, bn = states[n - s0]
+                dF = gF[n].contiguous()
+                grid.step_adjoint(un, fb, bn, kc, ubar, bbar, dF, ubar_tmp, bbar_tmp,
+                                  fbbar=fbbar, kcbar=kcbar)
+                ubar, ubar_tmp = ubar_tmp, ubar
+                bbar, bbar_tmp = bbar_tmp, bbar
+        return (None, None, None, None, *ubar, *fbbar, kcbar, bbar)
+
+
+def rollout(grid: Grid, u0: List[torch.Tensor], fb: Optional[List[torch.Tensor]], kc: torch.Tensor,
+            body0: torch.Tensor, nsteps: int, ckpt_every: int = 1):
+    """Differentiable rollout; returns (u_final list, body_final, F history (S, 3), p_final)."""
+    if fb is None:
+        fb = grid.zeros_u()
+    nd = grid.dim
+    outs = _Rollout.apply(grid, int(nsteps), int(max(1, ckpt_every)), nd, *u0, *fb, kc, body0)
+    return list(outs[:nd]), outs[nd], outs[nd + 1], outs[nd + 2]
+
+
+class _WallShear(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, grid: Grid, u0: torch.Tensor):
+        ctx.grid = grid
+        ctx.shape = u0.shape
+        return grid.loss_wall_shear(u0.detach().contiguous())[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        grid = ctx.grid
+        ubar = torch.zeros(ctx.shape, dtype=grid.dtype, device=grid.device)
+        dummy = torch.zeros(ctx.shape, dtype=grid.dtype, device=grid.device)
+        grid.loss_wall_shear(dummy, ubar)
+        return None, ubar * g.to(ubar.dtype)
+
+
+def wall_shear(grid: Grid, u0: torch.Tensor) -> torch.Tensor:
+    """Mean wall shear stress of the streamwise velocity (two walls normal to y)."""
+    return _WallShear.apply(grid, u0)
+
+
+class _RmsLift(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, grid: Grid, Fh: torch.Tensor, u_ref: float, diameter: float):
+        Fc = Fh.detach().contiguous()
+        dF = torch.zeros_like(Fc)
+        J = grid.loss_rms_lift(Fc.view(-1), 3, 1, u_ref, diameter, dF.view(-1))
+        ctx.save_for_backward(dF)
+        return J[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        (dF,) = ctx.saved_tensors
+        return None, dF * g, None, None
+
+
+def rms_lift(grid: Grid, Fh: torch.Tensor, u_ref: float = 1.0, diameter: float = 1.0) -> torch.Tensor:
+    """sqrt(mean C_L^2) of a force history (S, 3), C_L = 2 F_y / (rho U^2 D)."""
+    return _RmsLift.apply(grid, Fh, u_ref, diameter)
