@@ -1,14 +1,18 @@
 #!/usr/bin/env python3
-"""Throughput of the FV + IBM time step on one MI355X.
+"""Throughput of the FV + IBM time step and its discrete adjoint on one MI355X.
 
 Default workload: the 3D turbulent channel at Re_tau = 180 on a
-192 x 128 x 160 tanh-stretched grid, float32 stencils with float64
-residual / refinement (the configuration the headline metric and the HBM
-roofline target are quoted on).  One timed step = forward step
-(predictor, boundary faces, PPE, CG / refinement, projection) and, once
-available, its discrete adjoint with recomputation.
+192 x 128 x 160 tanh-stretched grid (x periodic, y walls, z periodic),
+laminar profile plus 10% seeded noise, driven by a uniform body force;
+float32 stencils with float64 residual / refinement.  One timed step is the
+whole hot path: the forward step (predictor with forcing, boundary faces,
+PPE right-hand side, refinement with the inner solve, projection) and its
+discrete adjoint, run as a differentiable rollout (checkpoint every
+--ckpt steps, recomputation inside segments) whose loss is the mean wall
+shear stress after the last step; the gradient is taken with respect to
+the body-force field.
 
-Prints ONE JSON line.  `value` = Mcell-updates/s of the whole job.
+Prints ONE JSON line; `value` = Mcell-updates/s of forward + adjoint.
 """
 from __future__ import annotations
 
@@ -20,36 +24,43 @@ import time
 
 import numpy as np
 
-HBM_PEAK_GBS = 8000.0           # MI355X HBM3E peak
+HBM_PEAK_GBS = 8000.0                     # MI355X HBM3E
+MFMA_PEAK_TFS = {"fp32": 157.3, "fp64": 78.6}   # dense matrix-core peaks
 
-# algorithmic bytes per cell per launch (d = velocity components, s = bytes
-# of the velocity type, v = bytes of the solve vectors)
-def kernel_bytes(d: int, s: int, v: int, mixed: bool) -> dict:
+
+def kernel_cost(d: int, s: int, mixed: bool, n: tuple):
+    """Algorithmic cost per launch per cell: ("bytes", B) or ("flops", F).
+
+    d = velocity components, s = bytes per velocity value."""
+    v = 4 if mixed else 8          # inner-solve vector type
     return {
-        "predictor": 3 * d * s,                 # read u, f_b; write u*
-        "ppe_rhs": d * s + 8,                   # read u*; write b (double)
-        "residual": 8 + 8 + (4 + 4 if mixed else 8),  # read b, p; write r (+ clear inner iterate)
-        "cg_dir": 3 * v,                        # read r, p_old; write p_new
-        "cg_update": 5 * v,                     # read p, x, r; write x, r
-        "ir_correct": 8 + 4 + 8,                # read p, d; write p
-        "project": 2 * d * s + 8,               # read u*, p; write u
-        "boundary": 0,
-        "ib": 0,
-        "adjoint": 0,
+        "predictor": ("bytes", 3 * d * s),                 # read u, f_b; write u*
+        "ppe_rhs": ("bytes", d * s + 8),                   # read u*; write b
+        "residual": ("bytes", 8 + 8 + v),                  # read b, p; write r
+        "cg_dir": ("bytes", 3 * v),                        # read r, p_old; write p_new
+        "cg_update": ("bytes", 5 * v),                     # read p, x, r; write x, r
+        "ir_correct": ("bytes", 8 + v + 8),                # read p, d; write p
+        "project": ("bytes", 2 * d * s + 8),               # read u*, p; write u
+        "adj_momentum": ("bytes", d * (2 * d + 3) * s),    # per component: read u, ustar_bar; write ubar; rw fbbar
+        "fdm_x": ("flops", 2 * n[0]),                      # dense contraction along x
+        "fdm_y": ("flops", 2 * n[1]),
+        "fdm_z": ("flops", 2 * n[2]),
     }
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="channel")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--solver", default="fdm", choices=["fdm", "cg"])
+    ap.add_argument("--ckpt", type=int, default=1, help="checkpoint interval of the rollout")
     ap.add_argument("--tol", type=float, default=1e-8, help="max |div u| target of the PPE solve")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle sample timed on the host (0 = skip)")
-    ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the forward-only and fp64 runs")
     return ap.parse_args()
 
 
@@ -60,40 +71,56 @@ def make_workload(name):
     return W.by_name(name, "full")
 
 
-def run_gpu(w, precision, steps, warmup, tol):
+def setup(w, precision, tol, solver):
     import torch
     import fvib_workloads as W
     import paper_2505_23940_amd as F
-    g = F.Grid.from_workload(w, precision=precision, poisson_tol=tol, check_every=64)
+    g = F.Grid.from_workload(w, precision=precision, poisson_tol=tol, check_every=64,
+                             solver=solver)
     u0, fb = W.initial_fields(w)
-    u = g.to_u(u0)
+    ut = g.to_u(u0)
     fbt = g.to_u(fb)
+    body = torch.tensor(W.body_state0(w), dtype=torch.float64, device=g.device)
+    kcv = (list(w.body.k) + list(w.body.c)) if w.body is not None else [0.0] * 6
+    kc = torch.tensor(kcv, dtype=torch.float64, device=g.device)
+    return g, ut, fbt, body, kc
+
+
+def fwd_adj_pass(g, w, ut, fbt, body, kc, steps, ckpt):
+    """Differentiable rollout of `steps` steps, loss, backward."""
+    from paper_2505_23940_amd.rollout import rms_lift, rollout, wall_shear
+    fb = [x.detach().clone().requires_grad_(True) for x in fbt]
+    kcr = kc.detach().clone().requires_grad_(True)
+    uS, bS, Fh, _ = rollout(g, [x.clone() for x in ut], fb, kcr, body.clone(), steps,
+                            ckpt_every=ckpt)
+    J = wall_shear(g, uS[0]) if w.body is None else rms_lift(g, Fh)
+    J.backward()
+    return J
+
+
+def fwd_pass(g, ut, fbt, body, kc, steps):
+    import torch
+    u = [x.clone() for x in ut]
     p = g.zeros_p()
-    body = kc = None
-    if w.body is not None:
-        body = torch.tensor(W.body_state0(w), dtype=torch.float64, device=g.device)
-        kc = torch.tensor(list(w.body.k) + list(w.body.c), dtype=torch.float64, device=g.device)
-    for i in range(warmup):
-        g.step(u, p, fbt, body, kc)
-        print(f"[bench] warmup {precision} step {i}: {g.last_info()}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    g.timing_enable(True)
+    b = body.clone()
     infos = []
+    for _ in range(steps):
+        g.step(u, p, fbt, b, kc)
+        infos.append(g.last_info())
+    return infos
+
+
+def timed(fn):
+    import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        g.step(u, p, fbt, body, kc)
-        infos.append(g.last_info())
+    out = fn()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    print(f"[bench] timed {steps} {precision} steps in {t1 - t0:.3f} s", file=sys.stderr, flush=True)
-    timing = g.timing_read()
-    g.timing_enable(False)
-    return t1 - t0, infos, timing, g
+    return time.perf_counter() - t0, out
 
 
 def cpu_baseline(w, budget_s):
-    """The oracle as it stands, forward steps on the host cores."""
+    """The oracle as it stands: forward steps on the host cores."""
     import torch
     import fvib_workloads as W
     from oracle import Grid, init_state, make_params, step
@@ -114,10 +141,47 @@ def cpu_baseline(w, budget_s):
             if time.perf_counter() - t0 > budget_s:
                 break
         dt = time.perf_counter() - t0
-    return {"value": w.ncells * n / dt / 1e6, "unit": "Mcell-updates/s",
+    return {"value": round(w.ncells * n / dt / 1e6, 3), "unit": "Mcell-updates/s",
             "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"{n} forward steps of the same workload (float64, exact Poisson solve), "
-                      f"{dt:.1f} s"}
+            "sample": f"{n} forward steps (float64, exact Poisson solve by per-axis "
+                      f"eigen-decomposition) of the same workload in {dt:.1f} s; the oracle's "
+                      f"own autograd adjoint is not timed"}
+
+
+def roofline(timing, w, precision, mixed):
+    ncell = w.ncells
+    s = 4 if mixed else 8
+    cost = kernel_cost(w.dim, s, mixed, w.n)
+    table = {}
+    for name, (ms, nl) in timing.items():
+        if nl == 0:
+            continue
+        avg_us = ms / nl * 1e3
+        row = {"launches": nl, "total_ms": round(ms, 3), "avg_us": round(avg_us, 2)}
+        if name in cost:
+            kind, per_cell = cost[name]
+            amount = per_cell * ncell
+            if kind == "bytes":
+                row["GB_s"] = round(amount / (avg_us * 1e-6) / 1e9, 1)
+            else:
+                row["TFLOP_s"] = round(amount / (avg_us * 1e-6) / 1e12, 2)
+        table[name] = row
+    dom = max((k for k in table if k in cost), key=lambda k: table[k]["total_ms"])
+    kind, per_cell = cost[dom]
+    amount = per_cell * ncell
+    avg_s = table[dom]["avg_us"] * 1e-6
+    if kind == "bytes":
+        ach = amount / avg_s / 1e9
+        rl = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+              "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+              "bytes_per_launch": amount, "traffic": None}
+    else:
+        ach = amount / avg_s / 1e12
+        pk = MFMA_PEAK_TFS["fp32" if mixed else "fp64"]
+        rl = {"bound": "mfma", "kernel": dom, "achieved": round(ach, 2), "peak": pk,
+              "unit": "TFLOP/s", "frac": round(ach / pk, 4), "flops_per_launch": amount,
+              "traffic": None}
+    return rl, table
 
 
 def main():
@@ -126,59 +190,59 @@ def main():
         print(f"bench.py: this build runs on one GPU only (asked for {a.gpus}); "
               "multi-GPU sharding is described in DESIGN.md and not built.", file=sys.stderr)
         sys.exit(2)
-    import torch
     w = make_workload(a.workload)
     mixed = a.precision == "fp32"
-    elapsed, infos, timing, g = run_gpu(w, a.precision, a.steps, a.warmup, a.tol)
     ncell = w.ncells
-    mcells = ncell * a.steps / elapsed / 1e6
-    s = 4 if mixed else 8
-    kb = kernel_bytes(w.dim, s, 4 if mixed else 8, mixed)
-    per_kernel = {}
-    for name, (ms, n) in timing.items():
-        if n == 0:
-            continue
-        bpl = kb.get(name, 0) * ncell
-        avg_us = ms / n * 1e3
-        per_kernel[name] = {"launches": n, "total_ms": round(ms, 3), "avg_us": round(avg_us, 2),
-                            "GB_s": round(bpl / (avg_us * 1e-6) / 1e9, 1) if bpl else None}
-    dom = max(per_kernel.items(), key=lambda kv: kv[1]["total_ms"])[0]
-    dom_bytes = kb.get(dom, 0) * ncell
-    dom_avg_s = per_kernel[dom]["avg_us"] * 1e-6
-    achieved = dom_bytes / dom_avg_s / 1e9 if dom_bytes else 0.0
-    cg = [i["cg_iters"] for i in infos]
-    ir = [i["ir_iters"] for i in infos]
+    g, ut, fbt, body, kc = setup(w, a.precision, a.tol, a.solver)
+    # warm-up: untimed forward + adjoint of `warmup` steps
+    if a.warmup > 0:
+        fwd_adj_pass(g, w, ut, fbt, body, kc, a.warmup, a.ckpt)
+        print(f"[bench] warmup done ({a.warmup} steps)", file=sys.stderr, flush=True)
+    g.timing_enable(True)
+    el, J = timed(lambda: fwd_adj_pass(g, w, ut, fbt, body, kc, a.steps, a.ckpt))
+    timing = g.timing_read()
+    g.timing_enable(False)
+    print(f"[bench] fwd+adj {a.steps} steps in {el:.3f} s (J = {float(J):.6g})", file=sys.stderr,
+          flush=True)
+    rl, table = roofline(timing, w, a.precision, mixed)
+    value = ncell * a.steps / el / 1e6
     out = {
         "metric": "Mcell-updates/s, fwd and fwd+adjoint step (FP32 vs FP64); % HBM roofline",
-        "value": round(mcells, 3),
+        "value": round(value, 3),
         "unit": "Mcell-updates/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(elapsed / a.steps * 1e3, 3),
+        "ms_per_step": round(el / a.steps * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": "channel Re_tau=180, 192x128x160 tanh-stretched, laminar + 10% "
-                               "seeded noise, uniform driving force" if a.workload == "channel"
-                               else a.workload,
-                   "cells": ncell, "precision": "fp32 stencils + fp64 residual/refinement"
-                   if mixed else "fp64", "step": "forward", "poisson_tol": a.tol,
-                   "cg_iters_per_step": float(np.mean(cg)), "ir_sweeps_per_step": float(np.mean(ir)),
-                   "div_max": max(i["div_max"] for i in infos)},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "bytes_per_launch": dom_bytes, "traffic": None},
-        "kernels": per_kernel,
+        "config": {"workload": ("channel Re_tau=180, 192x128x160 tanh-stretched, laminar + 10% "
+                                "seeded noise, uniform driving force" if a.workload == "channel"
+                                else a.workload),
+                   "cells": ncell, "step": "forward + discrete adjoint (checkpointed rollout)",
+                   "precision": ("fp32 stencils + fp64 residual/refinement" if mixed else "fp64"),
+                   "poisson": a.solver, "poisson_tol": a.tol, "ckpt_every": a.ckpt},
+        "roofline": rl,
+        "kernels": table,
     }
-    if not a.no_fp64_compare and mixed:
-        e64, inf64, _, _ = run_gpu(w, "fp64", max(2, a.steps // 2), 1, a.tol)
-        v64 = ncell * max(2, a.steps // 2) / e64 / 1e6
-        out["fp64_value"] = round(v64, 3)
-        out["fp32_over_fp64"] = round(mcells / v64, 3)
-        out["fp64_cg_iters_per_step"] = float(np.mean([i["cg_iters"] for i in inf64]))
+    if not a.no_extra:
+        gi = g
+        el_f, infos = timed(lambda: fwd_pass(gi, ut, fbt, body, kc, a.steps))
+        out["fwd_value"] = round(ncell * a.steps / el_f / 1e6, 3)
+        out["fwd_ir_sweeps_per_step"] = float(np.mean([i["ir_iters"] for i in infos]))
+        out["fwd_div_max"] = max(i["div_max"] for i in infos)
+        print(f"[bench] fwd {a.steps} steps in {el_f:.3f} s", file=sys.stderr, flush=True)
+        if mixed:
+            g64, u64, f64, b64, k64 = setup(w, "fp64", a.tol, a.solver)
+            n64 = max(2, a.steps // 2)
+            fwd_adj_pass(g64, w, u64, f64, b64, k64, 1, a.ckpt)
+            el64, _ = timed(lambda: fwd_adj_pass(g64, w, u64, f64, b64, k64, n64, a.ckpt))
+            out["fp64_value"] = round(ncell * n64 / el64 / 1e6, 3)
+            out["fp32_over_fp64"] = round(value / out["fp64_value"], 3)
+            print(f"[bench] fp64 fwd+adj {n64} steps in {el64:.3f} s", file=sys.stderr, flush=True)
     if a.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -87,6 +87,12 @@ enum {
 enum { FVIB_CONV_CENTRAL2 = 0, FVIB_CONV_UPWIND1 = 1 };
 enum { FVIB_PREC_FP64 = 0, FVIB_PREC_FP32_MIXED = 1 };
 enum { FVIB_BODY_STATIC = 0, FVIB_BODY_RIGID_SPRING = 1 };
+/* Pressure solver.  CG: conjugate gradients (the paper's solver; double
+ * CG, or float CG inside double iterative refinement).  FDM: exact fast
+ * diagonalisation of the separable operator (per-axis eigenbases applied as
+ * dense contractions on the matrix cores) inside the same double-residual
+ * refinement; both stop on the same double-precision divergence test. */
+enum { FVIB_SOLVER_CG = 0, FVIB_SOLVER_FDM = 1 };
 enum { FVIB_DTYPE_F32 = 0, FVIB_DTYPE_F64 = 1 };
 
 /* Grid and solver description (Sec. 2.4 of the paper). */
@@ -111,6 +117,7 @@ typedef struct {
   int32_t ir_maxit;         /* max refinement sweeps (mixed mode)              */
   double inner_rtol;        /* residual reduction of each float inner solve    */
   int32_t check_every;      /* iterations between convergence polls, >= 1     */
+  int32_t solver;           /* FVIB_SOLVER_*: inner solve of the refinement   */
 } fvib_grid_desc;
 
 /* Immersed rigid body: a closed polygon of Lagrangian markers (2D only). */
@@ -189,7 +196,8 @@ int fvib_step(fvib_grid *g, const fvib_fields *in, fvib_fields *out,
               fvib_step_info *info);
 
 /* Discrete adjoint of fvib_step at the state fwd_in (the masks of the step
- * are frozen).  Given the adjoints of the step outputs -- bar_out->u
+ * are frozen).  Its Poisson solve stops at a max-norm residual of 1e-10
+ * (double) or 1e-7 (mixed) relative to its right-hand side.  Given the adjoints of the step outputs -- bar_out->u
  * (u^{n+1}), bar_out->body (body state^{n+1}) and dF (3 doubles, device:
  * the direct derivative of the loss with respect to the force F^n reported
  * by the step, may be NULL) -- it writes bar_in->u (u^n) and
@@ -258,6 +266,10 @@ enum {
   FVIB_K_PROJECT = 7,     /* Eq. 10 correction + divergence check          */
   FVIB_K_IB = 8,          /* point classes, targets, loads, RK4            */
   FVIB_K_ADJOINT = 9,     /* adjoint stencils                              */
+  FVIB_K_FDM_X = 10,      /* fast-diagonalisation contraction along x      */
+  FVIB_K_FDM_Y = 11,      /* ... along y                                   */
+  FVIB_K_FDM_Z = 12,      /* ... along z                                   */
+  FVIB_K_ADJ_MOMENTUM = 13, /* transposed momentum stencil (all components) */
   FVIB_K_NCLASSES = 16
 };
 

@@ -17,7 +17,7 @@ import numpy as np
 import torch
 
 from . import _abi
-from ._abi import BC, BODY, CONV, PREC, STATUS_NAMES
+from ._abi import BC, BODY, CONV, PREC, SOLVER, STATUS_NAMES
 
 __all__ = ["Grid", "FvibError", "fvib_create_grid", "fvib_destroy_grid", "fvib_field_layout",
            "fvib_ib_set_body", "fvib_step", "fvib_step_adjoint", "fvib_loss_wall_shear",
@@ -125,7 +125,7 @@ class Grid:
                  dt: float = 1e-3, u_conv: float = 1.0, convection: str = "central",
                  precision: str = "fp64", poisson_tol: float = 1e-10,
                  poisson_maxit: int = 100000, ir_maxit: int = 30, inner_rtol: float = 1e-4,
-                 check_every: int = 64, device: str = "cuda:0"):
+                 check_every: int = 64, solver: str = "fdm", device: str = "cuda:0"):
         self.device = torch.device(device)
         self.dim = int(dim)
         self.n = tuple(int(x) for x in n)
@@ -156,6 +156,8 @@ class Grid:
         d.ir_maxit = ir_maxit
         d.inner_rtol = inner_rtol
         d.check_every = check_every
+        d.solver = SOLVER[solver]
+        self.solver = solver
         self.desc = d
         self.nu, self.rho, self.dt = nu, rho, dt
         with torch.cuda.device(self.device):

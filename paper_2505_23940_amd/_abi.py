@@ -17,6 +17,7 @@ BC = {"periodic": 0, "noslip": 1, "freeslip": 2, "inflow": 3, "outflow_conv": 4,
 CONV = {"central": 0, "upwind": 1}
 PREC = {"fp64": 0, "fp32": 1}
 BODY = {"static": 0, "spring": 1}
+SOLVER = {"cg": 0, "fdm": 1}
 DTYPE_F32, DTYPE_F64 = 0, 1
 
 EXPORTS = (
@@ -27,7 +28,8 @@ EXPORTS = (
     "fvib_version",
 )
 K_CLASSES = {"predictor": 0, "boundary": 1, "ppe_rhs": 2, "residual": 3, "cg_dir": 4,
-             "cg_update": 5, "ir_correct": 6, "project": 7, "ib": 8, "adjoint": 9}
+             "cg_update": 5, "ir_correct": 6, "project": 7, "ib": 8, "adjoint": 9,
+             "fdm_x": 10, "fdm_y": 11, "fdm_z": 12, "adj_momentum": 13}
 
 
 class GridDesc(C.Structure):
@@ -42,6 +44,7 @@ class GridDesc(C.Structure):
         ("poisson_maxit", C.c_int32), ("ir_maxit", C.c_int32),
         ("inner_rtol", C.c_double),
         ("check_every", C.c_int32),
+        ("solver", C.c_int32),
     ]
 
 

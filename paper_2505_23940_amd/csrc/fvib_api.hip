@@ -107,6 +107,11 @@ struct Grid {
   SolverScalars* sch = nullptr;   // pinned host mirror
   fvib_step_info* info_dev = nullptr;
   double* mu = nullptr;           // adjoint pressure (kept as the next warm start)
+  double* d64 = nullptr;          // double inner correction (fast diagonalisation)
+  double* fdm_d = nullptr;        // eigenbases (double) and eigenvalues
+  float* fdm_f = nullptr;         // eigenbases (float)
+  FdmPlan<double> F64;
+  FdmPlan<float> F32;
   double* body_tmp = nullptr;     // scratch body state (adjoint recomputation)
   int last_iters = 0;
   int last_iters_adj = 0;
@@ -120,6 +125,7 @@ struct Grid {
   void* fw[2] = {nullptr, nullptr};
   std::string err;
   Timer timer;
+  std::vector<double> crit_log;   // residual criterion per refinement sweep of the last solve
 
   size_t esize() const { return prec == FVIB_PREC_FP64 ? sizeof(double) : sizeof(float); }
   RedBuf red() const { return RedBuf{partial, ticket}; }
@@ -166,6 +172,9 @@ static void release(Grid* g) {
   f(g->info_dev);
   f(g->mu);
   f(g->body_tmp);
+  f(g->d64);
+  f(g->fdm_d);
+  f(g->fdm_f);
   if (g->sch) (void)hipHostFree(g->sch);
   f(g->ib_mem);
   f(g->origin);
@@ -261,8 +270,14 @@ static int validate(const fvib_grid_desc* d, std::string& msg) {
   if (d->precision != FVIB_PREC_FP64 && d->precision != FVIB_PREC_FP32_MIXED) { msg = "unknown precision"; return FVIB_EINVAL; }
   if (!(d->poisson_tol > 0)) { msg = "poisson_tol must be positive"; return FVIB_EINVAL; }
   if (d->poisson_maxit < 1 || d->check_every < 1) { msg = "poisson_maxit and check_every must be >= 1"; return FVIB_EINVAL; }
-  if (d->precision == FVIB_PREC_FP32_MIXED && (d->ir_maxit < 1 || !(d->inner_rtol > 0 && d->inner_rtol < 1))) {
-    msg = "mixed precision needs ir_maxit >= 1 and 0 < inner_rtol < 1";
+  if (d->solver != FVIB_SOLVER_CG && d->solver != FVIB_SOLVER_FDM) { msg = "unknown solver"; return FVIB_EINVAL; }
+  if ((d->precision == FVIB_PREC_FP32_MIXED || d->solver == FVIB_SOLVER_FDM) && d->ir_maxit < 1) {
+    msg = "refinement needs ir_maxit >= 1";
+    return FVIB_EINVAL;
+  }
+  if (d->precision == FVIB_PREC_FP32_MIXED && d->solver == FVIB_SOLVER_CG &&
+      !(d->inner_rtol > 0 && d->inner_rtol < 1)) {
+    msg = "float inner CG needs 0 < inner_rtol < 1";
     return FVIB_EINVAL;
   }
   return FVIB_OK;
@@ -411,6 +426,54 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
       g->last_iters = saved;
     }
   } restore{g, last, saved};
+  g->crit_log.clear();
+  if (g->d.solver == FVIB_SOLVER_FDM) {
+    const bool d64 = g->prec == FVIB_PREC_FP64;
+    int sweeps = 0;
+    for (; sweeps < g->d.ir_maxit + 1; ++sweeps) {
+      rc = timed(g, FVIB_K_RESIDUAL, [&] {
+        return launch_residual(g->P64, d64 ? 3 : 2, b, p, g->r64, g->r32, nullptr, g->red(), g->sc,
+                               tol, 0.5, g->stream);
+      });
+      if (rc) return rc;
+      if ((rc = read_scalars(g))) return rc;
+      g->crit_log.push_back(g->sch->crit);
+      if (g->sch->outer_done) break;
+      if (sweeps == g->d.ir_maxit) {
+        int stc = FVIB_ENOCONV;
+        FVIB_HIP(hipMemcpyAsync(&g->sc->status, &stc, sizeof(int), hipMemcpyHostToDevice, g->stream));
+        FVIB_HIP(hipStreamSynchronize(g->stream));
+        break;
+      }
+      // d = A^+ r by fast diagonalisation (forward axes, then inverse axes)
+      for (int pass = 0; pass < 2 * g->dim; ++pass) {
+        const bool fwd = pass < g->dim;
+        const int a = fwd ? pass : 2 * g->dim - 1 - pass;
+        const bool last = pass == 2 * g->dim - 1;
+        rc = timed(g, FVIB_K_FDM_X + a, [&] {
+          if (d64) {
+            const double* in = (pass == 0) ? g->r64 : ((pass % 2) ? g->pA64 : g->pB64);
+            double* out = last ? g->d64 : ((pass % 2) ? g->pB64 : g->pA64);
+            return launch_fdm_axis<double>(g->F64, a, fwd, in, out, g->stream);
+          }
+          const float* in = (pass == 0) ? g->r32 : ((pass % 2) ? g->pA32 : g->pB32);
+          float* out = last ? g->d32 : ((pass % 2) ? g->pB32 : g->pA32);
+          return launch_fdm_axis<float>(g->F32, a, fwd, in, out, g->stream);
+        });
+        if (rc) return rc;
+      }
+      rc = timed(g, FVIB_K_IR_CORRECT, [&] {
+        return d64 ? launch_add_correction<double>(g->ncell, p, g->d64, g->stream)
+                   : launch_add_correction<float>(g->ncell, p, g->d32, g->stream);
+      });
+      if (rc) return rc;
+    }
+    if ((rc = timed(g, FVIB_K_IR_CORRECT, [&] { return launch_gauge(g->ncell, p, g->sc, g->stream); })))
+      return rc;
+    *cg_total = 0;
+    *ir_total = sweeps;
+    return FVIB_OK;
+  }
   if (g->prec == FVIB_PREC_FP64) {
     rc = timed(g, FVIB_K_RESIDUAL, [&] {
       return launch_residual(g->P64, 0, b, p, g->r64, nullptr, nullptr, g->red(), g->sc, tol,
@@ -433,6 +496,7 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
     });
     if (rc) return rc;
     if ((rc = read_scalars(g))) return rc;
+    g->crit_log.push_back(g->sch->crit);
     if (g->sch->outer_done) break;
     if (sweeps == g->d.ir_maxit) {
       // refinement budget exhausted: report it on the device scalars
@@ -456,6 +520,24 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
   *cg_total = total;
   *ir_total = sweeps;
   return FVIB_OK;
+}
+
+static std::string describe_solve(const Grid* g, double tol) {
+  char buf[96];
+  std::string m = " (target ";
+  snprintf(buf, sizeof(buf), "%.3e", tol);
+  m += buf;
+  m += "; criterion per sweep:";
+  const size_t n = g->crit_log.size();
+  for (size_t i = 0; i < n; ++i) {
+    if (n > 12 && i == 6) {
+      m += " ...";
+      i = n - 6;
+    }
+    snprintf(buf, sizeof(buf), " %.3e", g->crit_log[i]);
+    m += buf;
+  }
+  return m + ")";
 }
 
 template <typename T>
@@ -544,7 +626,8 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
   if (st == FVIB_OK && g->sch->clamp) {
     return fail(g, FVIB_EINVAL, "immersed body left the region allowed by its window");
   }
-  if (st == FVIB_ENOCONV) return fail(g, st, "Poisson solve did not reach poisson_tol");
+  if (st == FVIB_ENOCONV)
+    return fail(g, st, "Poisson solve did not reach poisson_tol" + describe_solve(g, g->d.poisson_tol));
   if (st == FVIB_ENONFINITE) return fail(g, st, "non-finite value in a global reduction");
   g->err.clear();
   return st;
@@ -596,8 +679,13 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
   if ((rc = read_scalars(g))) return rc;
   const double ymax = g->sch->crit;
   int cg = 0, ir = 0;
+  double adj_tol = 0.0;
   if (ymax > 0.0) {
-    const double tol = 1e-11 * ymax * g->d.dt / g->d.rho;
+    // relative max-norm target of the adjoint solve: well inside the gradient
+    // tolerances and above the double rounding floor of the residual
+    const double rtol = (g->prec == FVIB_PREC_FP64) ? 1e-10 : 1e-7;
+    const double tol = rtol * ymax * g->d.dt / g->d.rho;
+    adj_tol = tol;
     if ((rc = poisson_solve(g, g->b, g->mu, tol, &g->last_iters_adj, &cg, &ir))) return rc;
   } else {
     FVIB_HIP(hipMemsetAsync(g->mu, 0, g->ncell * sizeof(double), g->stream));
@@ -615,7 +703,7 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
          return launch_adj_outflow<T>(G, g->planes, 0, usb, ub0, g->red(), g->sc, g->stream);
        })))
     return rc;
-  if ((rc = timed(g, FVIB_K_ADJOINT, [&] {
+  if ((rc = timed(g, FVIB_K_ADJ_MOMENTUM, [&] {
          return launch_adj_momentum<T>(G, u, (const T* const*)usb, ib, ub0, fbb, g->stream);
        })))
     return rc;
@@ -628,7 +716,11 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
   if ((rc = read_scalars(g))) return rc;
   if (g->timer.on) g->timer.resolve();
   const int st = g->sch->status;
-  if (st == FVIB_ENOCONV) return fail(g, st, "adjoint Poisson solve did not converge");
+  if (st == FVIB_ENOCONV) {
+    char buf[64];
+    snprintf(buf, sizeof(buf), "; rhs max |y/V| %.3e", ymax);
+    return fail(g, st, "adjoint Poisson solve did not converge" + describe_solve(g, adj_tol) + buf);
+  }
   if (st == FVIB_ENONFINITE) return fail(g, st, "non-finite value in the adjoint");
   g->err.clear();
   return FVIB_OK;
@@ -721,6 +813,57 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
   ok &= dmalloc(&g->mu, g->ncell * sizeof(double)) == FVIB_OK;
   ok &= dmalloc(&g->body_tmp, 8 * sizeof(double)) == FVIB_OK;
   if (!ok) return bail(FVIB_ENOMEM, "device allocation of the workspace failed");
+  if (g->d.solver == FVIB_SOLVER_FDM) {
+    if (g->prec == FVIB_PREC_FP64 && dmalloc(&g->d64, g->ncell * sizeof(double)))
+      return bail(FVIB_ENOMEM, "device allocation of the workspace failed");
+    if (g->prec == FVIB_PREC_FP64 && !g->r64) {
+      if (dmalloc(&g->r64, g->ncell * sizeof(double)) || dmalloc(&g->pA64, g->ncell * sizeof(double)) ||
+          dmalloc(&g->pB64, g->ncell * sizeof(double)))
+        return bail(FVIB_ENOMEM, "device allocation of the workspace failed");
+    }
+    std::vector<double> hd;   // per axis: phi, phiT, lam
+    size_t off[3][3];
+    for (int a = 0; a < g->dim; ++a) {
+      std::vector<double> phi, lam;
+      axis_eigen(g->faces[a], g->per[a] != 0, phi, lam);
+      const int N = g->n[a];
+      std::vector<double> phiT((size_t)N * N);
+      for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) phiT[(size_t)j * N + i] = phi[(size_t)i * N + j];
+      off[a][0] = hd.size();
+      hd.insert(hd.end(), phi.begin(), phi.end());
+      off[a][1] = hd.size();
+      hd.insert(hd.end(), phiT.begin(), phiT.end());
+      off[a][2] = hd.size();
+      hd.insert(hd.end(), lam.begin(), lam.end());
+    }
+    std::vector<float> hf(hd.begin(), hd.end());
+    if (dmalloc(&g->fdm_d, hd.size() * sizeof(double)) || dmalloc(&g->fdm_f, hf.size() * sizeof(float)))
+      return bail(FVIB_ENOMEM, "device allocation of the eigenbases failed");
+    if (hipMemcpy(g->fdm_d, hd.data(), hd.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g->fdm_f, hf.data(), hf.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(FVIB_EHIP, "upload of the eigenbases failed");
+    memset(&g->F64, 0, sizeof(g->F64));
+    memset(&g->F32, 0, sizeof(g->F32));
+    g->F64.dim = g->F32.dim = g->dim;
+    FdmDiv dv;
+    memset(&dv, 0, sizeof(dv));
+    dv.dim = g->dim;
+    dv.axis = g->dim - 1;
+    for (int a = 0; a < 3; ++a) {
+      g->F64.n[a] = g->F32.n[a] = g->n[a];
+      dv.n[a] = g->n[a];
+      if (a < g->dim) {
+        g->F64.phi[a] = g->fdm_d + off[a][0];
+        g->F64.phiT[a] = g->fdm_d + off[a][1];
+        g->F32.phi[a] = g->fdm_f + off[a][0];
+        g->F32.phiT[a] = g->fdm_f + off[a][1];
+        dv.lam[a] = g->fdm_d + off[a][2];
+      }
+    }
+    g->F64.div = dv;
+    g->F32.div = dv;
+  }
   if (hipHostMalloc((void**)&g->sch, sizeof(SolverScalars), hipHostMallocDefault) != hipSuccess)
     return bail(FVIB_ENOMEM, "pinned host allocation failed");
   if (hipMemset(g->mu, 0, g->ncell * sizeof(double)) != hipSuccess ||

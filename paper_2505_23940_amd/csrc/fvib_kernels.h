@@ -1,6 +1,8 @@
 // Host-side launchers of the fvib kernels (one declaration per entry).
 #pragma once
 
+#include <vector>
+
 #include "fvib_internal.h"
 
 namespace fvib {
@@ -22,6 +24,22 @@ struct IbGeo {
   int kind;                    // FVIB_BODY_*
   int free_dof[3];
   double m, rho, dt;
+};
+
+// Fast-diagonalisation plan: per-axis eigenbases on the device.
+struct FdmDiv {
+  int dim, axis;               // axis = last forward axis (dim - 1)
+  int n[3];
+  const double* lam[3];        // per-axis eigenvalues (ascending, lam[0] = 0)
+};
+
+template <typename V>
+struct FdmPlan {
+  int dim;
+  int n[3];
+  const V* phi[3];             // n x n row-major, column m = mode m
+  const V* phiT[3];            // transpose
+  FdmDiv div;
 };
 
 // k_momentum.hip
@@ -83,6 +101,15 @@ int launch_adj_outflow(const Geo<T>& G, const Planes& PL, int mode, T* usb[3], T
 template <typename T>
 int launch_adj_momentum(const Geo<T>& G, const T* const u[3], const T* const usb[3],
                         const IbView<T>& ib, T* ubar[3], T* fbbar[3], hipStream_t s);
+
+// k_fdm.hip
+template <typename V>
+int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, hipStream_t s);
+template <typename V>
+int launch_add_correction(int64_t n, double* p, const V* d, hipStream_t s);
+int launch_gauge(int64_t n, double* p, const SolverScalars* sc, hipStream_t s);
+void axis_eigen(const std::vector<double>& f, bool periodic, std::vector<double>& phi,
+                std::vector<double>& lam);
 
 // k_loss.hip
 template <typename T>

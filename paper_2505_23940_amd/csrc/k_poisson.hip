@@ -112,9 +112,11 @@ k_ppe_rhs(Geo<T> G, PGeo<double> P, Tiling tl, const T* __restrict__ s0,
 
 // ------------------------------------------------------------ residual
 // r = b - mean(b) - A x in double.  MODE 0 (double CG): writes r (double)
-// and starts the solve.  MODE 1 (refinement): writes r as float for the
-// inner solve, clears the inner iterate and decides whether refinement is
-// finished.  Also records sum(x) to keep the iterate at zero mean.
+// and starts the solve.  Refinement sweeps decide whether refinement is
+// finished and hand r to the inner solve: MODE 1 float CG (r as float, the
+// inner iterate cleared), MODE 2 float fast diagonalisation (r as float),
+// MODE 3 double fast diagonalisation (r as double).  Also records sum(x)
+// for the pressure gauge.
 template <int DIM, int MODE>
 __global__ void __launch_bounds__(kBlock)
 k_residual(PGeo<double> P, Tiling tl, const double* __restrict__ b,
@@ -128,11 +130,11 @@ k_residual(PGeo<double> P, Tiling tl, const double* __restrict__ b,
   FVIB_TILE_LOOP(tl)
     const double xc = x[c_];
     const double r = b[c_] - mb - apply_A<double, DIM>(P, get, i, j, k, xc);
-    if (MODE == 0) {
+    if (MODE == 0 || MODE == 3) {
       r64[c_] = r;
     } else {
       r32[c_] = (float)r;
-      d32[c_] = 0.0f;
+      if (MODE == 1) d32[c_] = 0.0f;
     }
     rr += r * r;
     sx += xc;
@@ -153,7 +155,7 @@ k_residual(PGeo<double> P, Tiling tl, const double* __restrict__ b,
       if (bad) sc->status = FVIB_ENONFINITE;
       const bool conv = bad || crit <= tol || tot[0] == 0.0;
       sc->done = conv ? 1 : 0;
-      if (MODE == 1) sc->outer_done = conv ? 1 : 0;
+      if (MODE != 0) sc->outer_done = conv ? 1 : 0;
     }
   }
 }
@@ -361,17 +363,25 @@ int launch_residual(const PGeo<double>& P, int mode, const double* b, const doub
                     double tol, double inner_rtol, hipStream_t s) {
   const Tiling tl = red_tiling(P.n);
   dim3 g(tl.nblocks), bl(kBlock);
+#define FVIB_RES(D, M)                                                                        \
+  hipLaunchKernelGGL((k_residual<D, M>), g, bl, 0, s, P, tl, b, x, r64, r32, d32, red, sc, tol, \
+                     inner_rtol)
   if (P.dim == 2) {
-    if (mode == 0)
-      hipLaunchKernelGGL((k_residual<2, 0>), g, bl, 0, s, P, tl, b, x, r64, r32, d32, red, sc, tol, inner_rtol);
-    else
-      hipLaunchKernelGGL((k_residual<2, 1>), g, bl, 0, s, P, tl, b, x, r64, r32, d32, red, sc, tol, inner_rtol);
+    switch (mode) {
+      case 0: FVIB_RES(2, 0); break;
+      case 1: FVIB_RES(2, 1); break;
+      case 2: FVIB_RES(2, 2); break;
+      default: FVIB_RES(2, 3); break;
+    }
   } else {
-    if (mode == 0)
-      hipLaunchKernelGGL((k_residual<3, 0>), g, bl, 0, s, P, tl, b, x, r64, r32, d32, red, sc, tol, inner_rtol);
-    else
-      hipLaunchKernelGGL((k_residual<3, 1>), g, bl, 0, s, P, tl, b, x, r64, r32, d32, red, sc, tol, inner_rtol);
+    switch (mode) {
+      case 0: FVIB_RES(3, 0); break;
+      case 1: FVIB_RES(3, 1); break;
+      case 2: FVIB_RES(3, 2); break;
+      default: FVIB_RES(3, 3); break;
+    }
   }
+#undef FVIB_RES
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }

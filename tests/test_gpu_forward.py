@@ -86,20 +86,23 @@ def test_ppe_rhs_and_operator_parity(case):
 
 @pytest.mark.parametrize("case", list(_cases().keys()))
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_poisson_solution_parity(case, precision):
-    """CG (double) and refinement around float CG reach the exact solution
-    of the same discrete system."""
+@pytest.mark.parametrize("solver", ["cg", "fdm"])
+def test_poisson_solution_parity(case, precision, solver):
+    """CG (double, or float inside double refinement) and the fast
+    diagonalisation inside double refinement reach the exact solution of the
+    same discrete system."""
     need_gpu()
     from oracle import Grid as OGrid
-    from oracle.poisson import solver
+    from oracle.poisson import solver as exact
     w = _cases()[case]
-    g = make_grid(w, precision=precision, poisson_tol=1e-12, inner_rtol=1e-3)
+    g = make_grid(w, precision=precision, poisson_tol=1e-12, inner_rtol=1e-3, solver=solver)
     og = OGrid(w)
     b = torch.tensor(W.random_cells(w, 5))
     p, iters = g.test_poisson(b.to(g.device))
-    pe = solver(og).solve(b - b.mean())
+    pe = exact(og).solve(b - b.mean())
     err = float((gauge(p.cpu()) - pe).abs().max())
-    assert iters > 0
+    if solver == "cg":
+        assert iters > 0
     assert err <= 1e-9 * float(pe.abs().max()), (err, iters)
 
 
@@ -122,11 +125,12 @@ def test_ib_classification_bit_exact(name):
 
 
 # ------------------------------------------------------------ whole step
-def test_tgv2d_fp64_100_steps():
+@pytest.mark.parametrize("solver", ["cg", "fdm"])
+def test_tgv2d_fp64_100_steps(solver):
     """2D Taylor-Green vortex, 64 x 64, dt 1e-3, 100 steps, float64."""
     need_gpu()
     w = W.tgv2d()
-    gr = gpu_rollout(w, w.steps, "fp64", tol=1e-13)
+    gr = gpu_rollout(w, w.steps, "fp64", tol=1e-13, solver=solver)
     orc = oracle_rollout(w, w.steps)
     assert rel_l2(gr["u"], orc["u"]) <= 1e-10
     assert rel_l2([gauge(gr["p"])], [orc["p"]]) <= 1e-10
@@ -134,10 +138,11 @@ def test_tgv2d_fp64_100_steps():
 
 
 @pytest.mark.parametrize("name", ["tgv3d", "channel", "cylinder", "viv"])
-def test_small_workloads_fp64(name):
+@pytest.mark.parametrize("solver", ["cg", "fdm"])
+def test_small_workloads_fp64(name, solver):
     need_gpu()
     w = W.by_name(name, "small")
-    gr = gpu_rollout(w, w.steps, "fp64", tol=1e-12)
+    gr = gpu_rollout(w, w.steps, "fp64", tol=1e-12, solver=solver)
     orc = oracle_rollout(w, w.steps)
     assert rel_l2(gr["u"], orc["u"]) <= 1e-10, name
     assert rel_l2([gauge(gr["p"])], [orc["p"]]) <= 1e-9, name
@@ -147,10 +152,11 @@ def test_small_workloads_fp64(name):
 
 
 @pytest.mark.parametrize("name", ["tgv3d", "channel", "cylinder", "viv"])
-def test_small_workloads_fp32_mixed(name):
+@pytest.mark.parametrize("solver", ["cg", "fdm"])
+def test_small_workloads_fp32_mixed(name, solver):
     need_gpu()
     w = W.by_name(name, "small")
-    gr = gpu_rollout(w, w.steps, "fp32", tol=1e-8)
+    gr = gpu_rollout(w, w.steps, "fp32", tol=1e-8, solver=solver)
     orc = oracle_rollout(w, w.steps)
     assert rel_l2(gr["u"], orc["u"]) <= 1e-5, name
     assert max(i["div_max"] for i in gr["infos"]) <= 1e-8
