@@ -106,7 +106,7 @@ struct Grid {
   SolverScalars* sc = nullptr;
   SolverScalars* sch = nullptr;   // pinned host mirror
   fvib_step_info* info_dev = nullptr;
-  double* mu = nullptr;           // adjoint pressure (kept as the next warm start)
+  double* mu = nullptr;           // adjoint pressure
   double* d64 = nullptr;          // double inner correction (fast diagonalisation)
   double* fdm_d = nullptr;        // eigenbases (double) and eigenvalues
   float* fdm_f = nullptr;         // eigenbases (float)
@@ -686,6 +686,11 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
     const double rtol = (g->prec == FVIB_PREC_FP64) ? 1e-10 : 1e-7;
     const double tol = rtol * ymax * g->d.dt / g->d.rho;
     adj_tol = tol;
+    // Start from zero: the target is relative to this right-hand side, and a
+    // warm start from another step's solution would put the double rounding
+    // floor of the residual (~eps |A mu|) above it when the right-hand side
+    // is small (e.g. zero up to rounding).
+    FVIB_HIP(hipMemsetAsync(g->mu, 0, g->ncell * sizeof(double), g->stream));
     if ((rc = poisson_solve(g, g->b, g->mu, tol, &g->last_iters_adj, &cg, &ir))) return rc;
   } else {
     FVIB_HIP(hipMemsetAsync(g->mu, 0, g->ncell * sizeof(double), g->stream));
