@@ -114,6 +114,19 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks) {
   return (b % kXcds) * per + b / kXcds;
 }
 
+// LDS halo planes (tile of kTileX x kTileY cells plus a one-cell halo) kept
+// in a three-slot ring for planes k-1, k, k+1 while a block marches in z.
+constexpr int kZChunk = 16;
+constexpr int kLX = kTileX + 2, kLY = kTileY + 2;
+
+template <typename T, int DIM>
+struct PlaneRing {
+  T v[DIM][3][kLY][kLX];
+};
+
+__device__ __forceinline__ int ring_slot(int k) { return ((k % 3) + 3) % 3; }
+
+
 // ------------------------------------------------------------- reductions
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

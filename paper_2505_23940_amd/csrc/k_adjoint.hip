@@ -465,191 +465,282 @@ __device__ __forceinline__ T ldu_c(const AdjCtx<T>& X, int c, int i, int j, int 
   return ldu<2, DIM>(X, i, j, k);
 }
 
-// Adjoint of the component-C input face J = (i, j, k): collects every use
-// of u_C(J) in R (convection and diffusion, with ghost preimages), plus the
-// direct predictor term, and the body-force adjoint of J itself.
+// Gather of every use of u_C(J) in R (convection and diffusion, ghost
+// preimages included).  RB(c, di, dj, dk) / U(c, di, dj, dk) return Rbar and
+// u^n of component c at an offset of at most one step per axis from J
+// (Rbar is zero outside the domain and on faces R does not advance).
+template <int C, int DIM, typename T, typename RBL, typename UL>
+__device__ __forceinline__ T adj_gather(const Geo<T>& G, const RBL& RB, const UL& U,
+                                        const int J[3]) {
+  const int jc = J[C];
+  const bool upw = G.upwind != 0;
+  T acc = T(0);
+  // ---- own-direction convection: J is the right face of cell jc-1 and the
+  // left face of cell jc
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const int m = jc - 1 + side;            // cell index along C
+    if (!G.per[C] && (m < 0 || m > G.n[C] - 1)) continue;
+    const int oL = side - 1, oR = side;     // offsets of faces m, m+1 from J
+    const T uL = U(C, C == 0 ? oL : 0, C == 1 ? oL : 0, C == 2 ? oL : 0);
+    const T uR = U(C, C == 0 ? oR : 0, C == 1 ? oR : 0, C == 2 ? oR : 0);
+    int mm = m;
+    if (G.per[C] && mm < 0) mm += G.n[C];
+    // Pbar(m) = Cbar(face m)/dc[m] - Cbar(face m+1)/dc[m+1], Cbar = -Rbar
+    const T Pb = -RB(C, C == 0 ? oL : 0, C == 1 ? oL : 0, C == 2 ? oL : 0) / G.dc[C][mm] +
+                 RB(C, C == 0 ? oR : 0, C == 1 ? oR : 0, C == 2 ? oR : 0) / G.dc[C][m + 1];
+    const T Q = T(0.5) * (uL + uR);
+    T d;
+    if (upw) {
+      const T up = Q > T(0) ? uL : (Q < T(0) ? uR : T(0));
+      d = T(0.5) * up + (side == 0 ? (Q < T(0) ? Q : T(0)) : (Q > T(0) ? Q : T(0)));
+    } else {
+      d = Q;
+    }
+    acc += d * Pb;
+  }
+  // ---- cross-direction convection through the edge fluxes
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    if (a == C) continue;
+    const int ja = J[a];
+    const int na = G.n[a];
+    const int nc = G.n[C];
+    const T wc = G.wi[C][jc];
+    const int ax = (a == 0), ay = (a == 1), az = (a == 2);
+    const int cx = (C == 0), cy = (C == 1), cz = (C == 2);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int jj;          // a-face index of the edge
+      T sg = T(1);     // ghost sign (1 for a real use)
+      bool lower;      // J (or its ghost) is the lower cell jj-1 of the edge
+      if (e == 0) { jj = ja; lower = false; }
+      else if (e == 1) { jj = ja + 1; lower = true; }
+      else if (e == 2) {                // ghost below the low boundary
+        if (G.per[a] || ja != 0) continue;
+        jj = 0; lower = true;
+        sg = G.dir[a][0] ? T(-1) : T(1);
+      } else {                          // ghost above the high boundary
+        if (G.per[a] || ja != na - 1) continue;
+        jj = na; lower = false;
+        sg = G.dir[a][1] ? T(-1) : T(1);
+      }
+      const int oa = jj - ja;           // 0 or 1
+      const T wa = G.wi[a][jj];
+      const T wJ = lower ? (T(1) - wa) : wa;
+      // U = u_C carried along a (cells jj-1, jj), V = u_a carried along C
+      const T cL = U(C, ax * (oa - 1), ay * (oa - 1), az * (oa - 1));
+      const T cR = U(C, ax * oa, ay * oa, az * oa);
+      const T Uv = (T(1) - wa) * cL + wa * cR;
+      const T aL = U(a, ax * oa - cx, ay * oa - cy, az * oa - cz);
+      const T aR = U(a, ax * oa, ay * oa, az * oa);
+      const T V = (T(1) - wc) * aL + wc * aR;
+      // flux adjoints of the C-equation (cells jj-1, jj along a) and of the
+      // a-equation (cells jc-1, jc along C)
+      T FbC = T(0);
+      {
+        int c0 = jj - 1, c1 = jj;
+        if (G.per[a]) {
+          if (c0 < 0) c0 += na;
+          if (c1 >= na) c1 -= na;
+        }
+        if (G.per[a] || jj - 1 >= 0)
+          FbC += -RB(C, ax * (oa - 1), ay * (oa - 1), az * (oa - 1)) / G.dx[a][c0];
+        if (G.per[a] || jj <= na - 1) FbC -= -RB(C, ax * oa, ay * oa, az * oa) / G.dx[a][c1];
+      }
+      T Fba = T(0);
+      {
+        int c0 = jc - 1, c1 = jc;
+        if (G.per[C]) {
+          if (c0 < 0) c0 += nc;
+          if (c1 >= nc) c1 -= nc;
+        }
+        if (G.per[C] || jc - 1 >= 0)
+          Fba += -RB(a, ax * oa - cx, ay * oa - cy, az * oa - cz) / G.dx[C][c0];
+        if (G.per[C] || jc <= nc - 1) Fba -= -RB(a, ax * oa, ay * oa, az * oa) / G.dx[C][c1];
+      }
+      T contrib;
+      if (!upw) {
+        contrib = wJ * V * (FbC + Fba);
+      } else {
+        // C-equation: F_C = V * (V > 0 ? u_C(jj-1) : V < 0 ? u_C(jj) : 0)
+        const bool sel = lower ? (V > T(0)) : (V < T(0));
+        const T partC = sel ? V * FbC : T(0);
+        // a-equation: F_a = U * (U > 0 ? u_a(jc-1) : U < 0 ? u_a(jc) : 0)
+        const T upa = Uv > T(0) ? aL : (Uv < T(0) ? aR : T(0));
+        contrib = partC + wJ * upa * Fba;
+      }
+      acc += sg * contrib;
+    }
+  }
+  // ---- diffusion (transpose), with ghost preimages
+  const T nu = G.nu;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const int ja = J[a];
+    const int na = (a == C) ? G.ext[C][C] : G.n[a];
+    const int ax = (a == 0), ay = (a == 1), az = (a == 2);
+#pragma unroll
+    for (int o = -1; o <= 1; ++o) {
+      int ia = ja + o;
+      if (G.per[a]) {
+        if (ia < 0) ia += na;
+        if (ia >= na) ia -= na;
+      } else if (ia < 0 || ia >= na) {
+        continue;
+      }
+      const T rb = RB(C, ax * o, ay * o, az * o);
+      if (rb == T(0)) continue;
+      T hp, hm, H;
+      if (a == C) {
+        hp = G.dxe[C][ia + 1];
+        hm = G.dxe[C][ia];
+        H = G.dc[C][ia];
+      } else {
+        hp = G.dc[a][ia + 1];
+        hm = G.dc[a][ia];
+        H = G.dx[a][ia];
+      }
+      T coef;
+      if (o == -1) coef = T(1) / (hp * H);           // J = I + e_a
+      else if (o == 1) coef = T(1) / (hm * H);       // J = I - e_a
+      else coef = -(T(1) / hp + T(1) / hm) / H;
+      acc += nu * rb * coef;
+      // I = J at a bounded tangential boundary reads a ghost made from J
+      if (o == 0 && a != C && !G.per[a]) {
+        if (ia == 0) acc += nu * rb * (G.dir[a][0] ? T(-1) : T(1)) / (hm * H);
+        if (ia == na - 1) acc += nu * rb * (G.dir[a][1] ? T(-1) : T(1)) / (hp * H);
+      }
+    }
+  }
+  return acc;
+}
+
+// Direct predictor term of an advanced face J and its body-force adjoint:
+// ubar += (1 - eps) ustar_bar - eps fbar / dt,  fbbar += Rbar(J).
+template <int C, int DIM, typename T>
+__device__ __forceinline__ T adj_direct(const AdjCtx<T>& X, const int J[3], int64_t id, T rJ,
+                                        T* __restrict__ fbbar) {
+  const Geo<T>& G = X.G;
+  const bool evolvedJ = G.per[C] || (J[C] >= 1 && J[C] <= G.n[C] - 1);
+  if (!evolvedJ) return T(0);
+  T direct = X.usb[C][id];
+  if constexpr (C < 2) {
+    int li = 0;
+    if (forced_cls<C>(X.ib, J[0], J[1], &li)) direct = -X.ib.f[C][li] / G.dt;
+  }
+  if (fbbar) fbbar[id] += rJ;
+  return direct;
+}
+
+// Cell-based transposed momentum stencil with LDS halo planes of u^n and
+// Rbar (same tiling and z-march as the predictor).  Each thread writes the
+// low face of its cell for every component; faces on the high boundary of
+// a bounded own axis are left to k_adj_momentum_plane.
+template <typename T, int DIM>
+struct AdjRings {
+  T u[DIM][3][kLY][kLX];
+  T r[DIM][3][kLY][kLX];
+};
+
+template <int DIM, typename T>
+__device__ __forceinline__ void adj_fill(const AdjCtx<T>& X, AdjRings<T, DIM>& S, int slot,
+                                         int i0, int j0, int kk) {
+  const Geo<T>& G = X.G;
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    for (int s = threadIdx.x; s < kLX * kLY; s += kBlock) {
+      const int sy = s / kLX, sx = s - sy * kLX;
+      const int gi = min(i0 - 1 + sx, G.n[0]), gj = min(j0 - 1 + sy, G.n[1]);
+      S.u[c][slot][sy][sx] = ldu_c<DIM>(X, c, gi, gj, kk);
+      S.r[c][slot][sy][sx] = rbar_c<DIM>(X, c, gi, gj, kk);
+    }
+  }
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_adj_momentum_lds(AdjCtx<T> X, int ntx, int nty, int nzc, T* __restrict__ ub0,
+                   T* __restrict__ ub1, T* __restrict__ ub2, T* __restrict__ fb0,
+                   T* __restrict__ fb1, T* __restrict__ fb2) {
+  __shared__ AdjRings<T, DIM> S;
+  const Geo<T>& G = X.G;
+  T* ubar[3] = {ub0, ub1, ub2};
+  T* fbb[3] = {fb0, fb1, fb2};
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  if (b >= ntx * nty * nzc) return;
+  const int tx = b % ntx, ty = (b / ntx) % nty, zc = b / (ntx * nty);
+  const int i0 = tx * kTileX, j0 = ty * kTileY;
+  const int lx = threadIdx.x & (kTileX - 1), ly = threadIdx.x / kTileX;
+  const int i = i0 + lx, j = j0 + ly;
+  const int k0 = (DIM == 3) ? zc * kZChunk : 0;
+  const int k1 = (DIM == 3) ? min(k0 + kZChunk, G.n[2]) : 1;
+  const bool inside = i < G.n[0] && j < G.n[1];
+  if (DIM == 3) {
+    adj_fill<DIM>(X, S, ring_slot(k0 - 1), i0, j0, k0 - 1);
+    adj_fill<DIM>(X, S, ring_slot(k0), i0, j0, k0);
+    adj_fill<DIM>(X, S, ring_slot(k0 + 1), i0, j0, k0 + 1);
+  } else {
+    adj_fill<DIM>(X, S, 0, i0, j0, 0);
+  }
+  for (int k = k0; k < k1; ++k) {
+    __syncthreads();
+    const int sc = (DIM == 3) ? ring_slot(k) : 0;
+    const int sm = (DIM == 3) ? ring_slot(k - 1) : 0;
+    const int sp = (DIM == 3) ? ring_slot(k + 1) : 0;
+    if (inside) {
+      auto Ul = [&](int c, int di, int dj, int dk) -> T {
+        const int sl = dk < 0 ? sm : (dk > 0 ? sp : sc);
+        return S.u[c][sl][ly + 1 + dj][lx + 1 + di];
+      };
+      auto Rl = [&](int c, int di, int dj, int dk) -> T {
+        const int sl = dk < 0 ? sm : (dk > 0 ? sp : sc);
+        return S.r[c][sl][ly + 1 + dj][lx + 1 + di];
+      };
+      const int J[3] = {i, j, k};
+#define FVIB_ADJ_COMP(CC)                                                           \
+      if (CC < DIM) {                                                               \
+        const int64_t id = fidx(G.ext[CC], i, j, k);                                \
+        T acc = adj_gather<CC, DIM, T>(G, Rl, Ul, J);                               \
+        acc += adj_direct<CC, DIM, T>(X, J, id, Rl(CC, 0, 0, 0), fbb[CC]);          \
+        ubar[CC][id] = acc;                                                         \
+      }
+      FVIB_ADJ_COMP(0)
+      FVIB_ADJ_COMP(1)
+      FVIB_ADJ_COMP(2)
+#undef FVIB_ADJ_COMP
+    }
+    if (DIM == 3 && k + 1 < k1) {
+      __syncthreads();
+      adj_fill<DIM>(X, S, sm, i0, j0, k + 2);
+    }
+  }
+}
+
+// Faces on the high boundary of a bounded own axis (face index n[C]).
 template <int C, int DIM, typename T>
 __global__ void __launch_bounds__(kBlock)
-k_adj_momentum(AdjCtx<T> X, T* __restrict__ ubar, T* __restrict__ fbbar) {
+k_adj_momentum_plane(AdjCtx<T> X, T* __restrict__ ubar) {
   const Geo<T>& G = X.G;
-  const int e0 = G.ext[C][0], e1 = G.ext[C][1], e2 = G.ext[C][2];
-  const int64_t n = (int64_t)e0 * e1 * e2;
-  const bool upw = G.upwind != 0;
-  for (int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x; id < n;
-       id += (int64_t)gridDim.x * kBlock) {
-    const int J[3] = {(int)(id % e0), (int)((id / e0) % e1), (int)(id / ((int64_t)e0 * e1))};
-    const int jc = J[C];
-    T acc = T(0);
-    // ---- direct term and body-force adjoint of J itself
-    const T rJ = rbar<C, DIM>(X, J[0], J[1], J[2]);
-    const bool evolvedJ = G.per[C] || (jc >= 1 && jc <= G.n[C] - 1);
-    if (evolvedJ) {
-      T direct = X.usb[C][id];
-      if constexpr (C < 2) {
-        int li = 0;
-        if (forced_cls<C>(X.ib, J[0], J[1], &li)) direct = -X.ib.f[C][li] / G.dt;
-      }
-      acc += direct;
-      if (fbbar) fbbar[id] += rJ;
+  int64_t count = 1;
+  for (int a = 0; a < 3; ++a)
+    if (a != C) count *= G.n[a];
+  for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < count;
+       r += (int64_t)gridDim.x * kBlock) {
+    int J[3];
+    int64_t rem = r;
+    for (int a = 0; a < 3; ++a) {
+      if (a == C) { J[a] = G.n[C]; continue; }
+      J[a] = (int)(rem % G.n[a]);
+      rem /= G.n[a];
     }
-    // ---- own-direction convection: J is the right face of cell jc-1 and
-    // the left face of cell jc
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const int m = jc - 1 + side;            // cell index along C
-      if (!G.per[C] && (m < 0 || m > G.n[C] - 1)) continue;
-      int L[3] = {J[0], J[1], J[2]}, R[3] = {J[0], J[1], J[2]};
-      L[C] = m;
-      R[C] = m + 1;
-      const T uL = ld<C, DIM>(G, X.u[C], L[0], L[1], L[2]);
-      const T uR = ld<C, DIM>(G, X.u[C], R[0], R[1], R[2]);
-      // Pbar(m) = Cbar(face m)/dc[m] - Cbar(face m+1)/dc[m+1], Cbar = -Rbar
-      int mm = m;
-      if (G.per[C] && mm < 0) mm += G.n[C];
-      const int mp = m + 1;
-      const T Pb = -rbar<C, DIM>(X, L[0], L[1], L[2]) / G.dc[C][mm] +
-                   rbar<C, DIM>(X, R[0], R[1], R[2]) / G.dc[C][mp];
-      const T Q = T(0.5) * (uL + uR);
-      T d;
-      if (upw) {
-        const T up = Q > T(0) ? uL : (Q < T(0) ? uR : T(0));
-        // side 0: J is the right face of m; side 1: J is the left face
-        d = T(0.5) * up + (side == 0 ? (Q < T(0) ? Q : T(0)) : (Q > T(0) ? Q : T(0)));
-      } else {
-        d = Q;
-      }
-      acc += d * Pb;
-    }
-    // ---- cross-direction convection through the edge fluxes
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-      if (a == C) continue;
-      const int ja = J[a];
-      const int na = G.n[a];
-      const T wc = G.wi[C][jc];
-      // candidate edges: (a-face jj, role of J in the factor u_C carried along
-      // a): weight of J and ghost sign
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int jj;         // a-face index of the edge
-        T wJ;           // weight of J in U = (1-w) u_C(jj-1) + w u_C(jj)
-        T sg = T(1);    // ghost sign (1 for real use)
-        bool lower;     // J (or its ghost) is the lower cell jj-1
-        if (e == 0) { jj = ja; lower = false; }
-        else if (e == 1) { jj = ja + 1; lower = true; }
-        else if (e == 2) {                // ghost below the low boundary
-          if (G.per[a] || ja != 0) continue;
-          jj = 0; lower = true;
-          sg = G.dir[a][0] ? T(-1) : T(1);
-        } else {                          // ghost above the high boundary
-          if (G.per[a] || ja != na - 1) continue;
-          jj = na; lower = false;
-          sg = G.dir[a][1] ? T(-1) : T(1);
-        }
-        int jw = jj;
-        if (G.per[a] && jw == na) jw = 0;           // periodic wrap of the a-face
-        const T wa = G.wi[a][jj];
-        wJ = lower ? (T(1) - wa) : wa;
-        // U and V at the edge (C-face jc, a-face jj)
-        int B0[3] = {J[0], J[1], J[2]}, B1[3] = {J[0], J[1], J[2]};
-        B0[a] = jj - 1;
-        B1[a] = jj;
-        const T cL = ld<C, DIM>(G, X.u[C], B0[0], B0[1], B0[2]);
-        const T cR = ld<C, DIM>(G, X.u[C], B1[0], B1[1], B1[2]);
-        const T U = (T(1) - wa) * cL + wa * cR;
-        int A0[3] = {J[0], J[1], J[2]}, A1[3] = {J[0], J[1], J[2]};
-        A0[a] = jw;
-        A1[a] = jw;
-        A0[C] = jc - 1;
-        A1[C] = jc;
-        const T aL = ldu_c<DIM>(X, a, A0[0], A0[1], A0[2]);
-        const T aR = ldu_c<DIM>(X, a, A1[0], A1[1], A1[2]);
-        const T V = (T(1) - wc) * aL + wc * aR;
-        // flux adjoints of the C-equation (cells jj-1, jj along a) and of
-        // the a-equation (cells jc-1, jc along C)
-        int F0[3] = {J[0], J[1], J[2]}, F1[3] = {J[0], J[1], J[2]};
-        F0[a] = jj - 1;
-        F1[a] = jj;
-        T FbC = T(0);
-        {
-          int c0 = jj - 1, c1 = jj;
-          if (G.per[a]) {
-            if (c0 < 0) c0 += na;
-            if (c1 >= na) c1 -= na;
-          }
-          if (G.per[a] || jj - 1 >= 0) FbC += -rbar<C, DIM>(X, F0[0], F0[1], F0[2]) / G.dx[a][c0];
-          if (G.per[a] || jj <= na - 1) FbC -= -rbar<C, DIM>(X, F1[0], F1[1], F1[2]) / G.dx[a][c1];
-        }
-        T Fba = T(0);
-        {
-          const int nc = G.n[C];
-          int c0 = jc - 1, c1 = jc;
-          if (G.per[C]) {
-            if (c0 < 0) c0 += nc;
-            if (c1 >= nc) c1 -= nc;
-          }
-          if (G.per[C] || jc - 1 >= 0) Fba += -rbar_c<DIM>(X, a, A0[0], A0[1], A0[2]) / G.dx[C][c0];
-          if (G.per[C] || jc <= nc - 1) Fba -= -rbar_c<DIM>(X, a, A1[0], A1[1], A1[2]) / G.dx[C][c1];
-        }
-        T contrib;
-        if (!upw) {
-          contrib = wJ * V * (FbC + Fba);
-        } else {
-          // C-equation: F_C = V * (V > 0 ? u_C(jj-1) : V < 0 ? u_C(jj) : 0)
-          const bool sel = lower ? (V > T(0)) : (V < T(0));
-          const T partC = sel ? V * FbC : T(0);
-          // a-equation: F_a = U * (U > 0 ? u_a(jc-1) : U < 0 ? u_a(jc) : 0)
-          const T upa = U > T(0) ? aL : (U < T(0) ? aR : T(0));
-          contrib = partC + wJ * upa * Fba;
-        }
-        acc += sg * contrib;
-      }
-    }
-    // ---- diffusion (transpose), with ghost preimages
-    const T nu = G.nu;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-      const int ja = J[a];
-      const int na = (a == C) ? G.ext[C][C] : G.n[a];
-      // output faces I = J - e_a (J is its + neighbour), J (centre), J + e_a
-#pragma unroll
-      for (int o = -1; o <= 1; ++o) {
-        int I[3] = {J[0], J[1], J[2]};
-        I[a] = ja + o;
-        int ia = I[a];
-        if (G.per[a]) {
-          if (ia < 0) ia += na;
-          if (ia >= na) ia -= na;
-        } else if (ia < 0 || ia >= na) {
-          continue;
-        }
-        I[a] = ia;
-        const T rb = rbar<C, DIM>(X, I[0], I[1], I[2]);
-        if (rb == T(0)) continue;
-        T hp, hm, H;
-        if (a == C) {
-          hp = G.dxe[C][ia + 1];
-          hm = G.dxe[C][ia];
-          H = G.dc[C][ia];
-        } else {
-          hp = G.dc[a][ia + 1];
-          hm = G.dc[a][ia];
-          H = G.dx[a][ia];
-        }
-        T coef;
-        if (o == -1) coef = T(1) / (hp * H);           // J = I + e_a
-        else if (o == 1) coef = T(1) / (hm * H);       // J = I - e_a
-        else coef = -(T(1) / hp + T(1) / hm) / H;
-        acc += nu * rb * coef;
-        // ghost preimages: I at a bounded tangential boundary reads a ghost
-        // made from J (= I)
-        if (o == 0 && a != C && !G.per[a]) {
-          if (ia == 0) acc += nu * rb * (G.dir[a][0] ? T(-1) : T(1)) / (hm * H);
-          if (ia == na - 1) acc += nu * rb * (G.dir[a][1] ? T(-1) : T(1)) / (hp * H);
-        }
-      }
-    }
-    ubar[id] = acc;
+    auto Ug = [&](int c, int di, int dj, int dk) -> T {
+      return ldu_c<DIM>(X, c, J[0] + di, J[1] + dj, J[2] + dk);
+    };
+    auto Rg = [&](int c, int di, int dj, int dk) -> T {
+      return rbar_c<DIM>(X, c, J[0] + di, J[1] + dj, J[2] + dk);
+    };
+    ubar[fidx(G.ext[C], J[0], J[1], J[2])] = adj_gather<C, DIM, T>(G, Rg, Ug, J);
   }
 }
 
@@ -743,16 +834,31 @@ int launch_adj_momentum(const Geo<T>& G, const T* const u[3], const T* const usb
     X.usb[c] = usb[c];
   }
   X.ib = ib;
+  const int ntx = (G.n[0] + kTileX - 1) / kTileX;
+  const int nty = (G.n[1] + kTileY - 1) / kTileY;
+  const int nzc = (G.dim == 3) ? (G.n[2] + kZChunk - 1) / kZChunk : 1;
+  int nb = ntx * nty * nzc;
+  nb = (nb + kXcds - 1) / kXcds * kXcds;
+  if (G.dim == 2)
+    hipLaunchKernelGGL((k_adj_momentum_lds<T, 2>), dim3(nb), dim3(kBlock), 0, s, X, ntx, nty, nzc,
+                       ubar[0], ubar[1], ubar[2], fbbar[0], fbbar[1], fbbar[2]);
+  else
+    hipLaunchKernelGGL((k_adj_momentum_lds<T, 3>), dim3(nb), dim3(kBlock), 0, s, X, ntx, nty, nzc,
+                       ubar[0], ubar[1], ubar[2], fbbar[0], fbbar[1], fbbar[2]);
+  FVIB_HIP(hipGetLastError());
   for (int c = 0; c < G.dim; ++c) {
-    const int64_t n = (int64_t)G.ext[c][0] * G.ext[c][1] * G.ext[c][2];
-    const dim3 gr(nblk(n)), bl(kBlock);
+    if (G.per[c]) continue;
+    int64_t count = 1;
+    for (int a = 0; a < 3; ++a)
+      if (a != c) count *= G.n[a];
+    const dim3 gr(nblk(count)), bl(kBlock);
     if (G.dim == 2) {
-      if (c == 0) hipLaunchKernelGGL((k_adj_momentum<0, 2, T>), gr, bl, 0, s, X, ubar[0], fbbar[0]);
-      else hipLaunchKernelGGL((k_adj_momentum<1, 2, T>), gr, bl, 0, s, X, ubar[1], fbbar[1]);
+      if (c == 0) hipLaunchKernelGGL((k_adj_momentum_plane<0, 2, T>), gr, bl, 0, s, X, ubar[0]);
+      else hipLaunchKernelGGL((k_adj_momentum_plane<1, 2, T>), gr, bl, 0, s, X, ubar[1]);
     } else {
-      if (c == 0) hipLaunchKernelGGL((k_adj_momentum<0, 3, T>), gr, bl, 0, s, X, ubar[0], fbbar[0]);
-      else if (c == 1) hipLaunchKernelGGL((k_adj_momentum<1, 3, T>), gr, bl, 0, s, X, ubar[1], fbbar[1]);
-      else hipLaunchKernelGGL((k_adj_momentum<2, 3, T>), gr, bl, 0, s, X, ubar[2], fbbar[2]);
+      if (c == 0) hipLaunchKernelGGL((k_adj_momentum_plane<0, 3, T>), gr, bl, 0, s, X, ubar[0]);
+      else if (c == 1) hipLaunchKernelGGL((k_adj_momentum_plane<1, 3, T>), gr, bl, 0, s, X, ubar[1]);
+      else hipLaunchKernelGGL((k_adj_momentum_plane<2, 3, T>), gr, bl, 0, s, X, ubar[2]);
     }
     FVIB_HIP(hipGetLastError());
   }

@@ -17,22 +17,21 @@
 
 namespace fvib {
 
-template <int C, int DIM, typename T>
-__device__ __forceinline__ T momentum_rhs(const Geo<T>& G, const T* const* u, const T* fbC,
-                                          int i, int j, int k) {
+// R of component C at face (i, j, k).  `L(c, di, dj, dk)` returns component
+// c at the offset (di, dj, dk) from (i, j, k), boundary rules applied (each
+// offset is -1, 0 or +1 per axis).
+template <int C, int DIM, typename T, typename Load>
+__device__ __forceinline__ T momentum_rhs(const Geo<T>& G, const Load& L, const T* fbC, int i,
+                                          int j, int k) {
   const int I[3] = {i, j, k};
-  const T* q = u[C];
-  const T q0 = ld<C, DIM>(G, q, i, j, k);
+  const T q0 = L(C, 0, 0, 0);
   const int ic = I[C];
   T conv = T(0);
   T visc = T(0);
   // convection along the own axis: fluxes at the two adjacent cell centres
   {
-    int Im[3] = {i, j, k}, Ip[3] = {i, j, k};
-    Im[C] -= 1;
-    Ip[C] += 1;
-    const T qm = ld<C, DIM>(G, q, Im[0], Im[1], Im[2]);
-    const T qp = ld<C, DIM>(G, q, Ip[0], Ip[1], Ip[2]);
+    const T qm = L(C, C == 0 ? -1 : 0, C == 1 ? -1 : 0, C == 2 ? -1 : 0);
+    const T qp = L(C, C == 0 ? 1 : 0, C == 1 ? 1 : 0, C == 2 ? 1 : 0);
     const T Qlo = T(0.5) * (qm + q0);
     const T Qhi = T(0.5) * (q0 + qp);
     T Flo, Fhi;
@@ -50,34 +49,15 @@ __device__ __forceinline__ T momentum_rhs(const Geo<T>& G, const T* const* u, co
   for (int a = 0; a < DIM; ++a) {
     if (a == C) continue;
     const int ia = I[a];
-    int Am[3] = {i, j, k}, Ap[3] = {i, j, k};
-    Am[a] -= 1;
-    Ap[a] += 1;
-    const T cm = ld<C, DIM>(G, q, Am[0], Am[1], Am[2]);
-    const T cp = ld<C, DIM>(G, q, Ap[0], Ap[1], Ap[2]);
+    const int ex = (a == 0), ey = (a == 1), ez = (a == 2);
+    const int cx = (C == 0), cy = (C == 1), cz = (C == 2);
+    const T cm = L(C, -ex, -ey, -ez);
+    const T cp = L(C, ex, ey, ez);
     // component a at (a-face ia, own cells ic-1, ic) and at a-face ia + 1
-    int B00[3] = {i, j, k};
-    B00[C] -= 1;
-    int B10[3] = {B00[0], B00[1], B00[2]};
-    B10[a] += 1;
-    const T* qa = u[a];
-    T a00, a01, a10, a11;
-    if (a == 0) {
-      a00 = ld<0, DIM>(G, qa, B00[0], B00[1], B00[2]);
-      a01 = ld<0, DIM>(G, qa, i, j, k);
-      a10 = ld<0, DIM>(G, qa, B10[0], B10[1], B10[2]);
-      a11 = ld<0, DIM>(G, qa, Ap[0], Ap[1], Ap[2]);
-    } else if (a == 1) {
-      a00 = ld<1, DIM>(G, qa, B00[0], B00[1], B00[2]);
-      a01 = ld<1, DIM>(G, qa, i, j, k);
-      a10 = ld<1, DIM>(G, qa, B10[0], B10[1], B10[2]);
-      a11 = ld<1, DIM>(G, qa, Ap[0], Ap[1], Ap[2]);
-    } else {
-      a00 = ld<2, DIM>(G, qa, B00[0], B00[1], B00[2]);
-      a01 = ld<2, DIM>(G, qa, i, j, k);
-      a10 = ld<2, DIM>(G, qa, B10[0], B10[1], B10[2]);
-      a11 = ld<2, DIM>(G, qa, Ap[0], Ap[1], Ap[2]);
-    }
+    const T a00 = L(a, -cx, -cy, -cz);
+    const T a01 = L(a, 0, 0, 0);
+    const T a10 = L(a, ex - cx, ey - cy, ez - cz);
+    const T a11 = L(a, ex, ey, ez);
     const T wc = G.wi[C][ic];
     const T V0 = (T(1) - wc) * a00 + wc * a01;
     const T V1 = (T(1) - wc) * a10 + wc * a11;
@@ -97,11 +77,9 @@ __device__ __forceinline__ T momentum_rhs(const Geo<T>& G, const T* const* u, co
   // diffusion, summed over the axes in order
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
-    int Am[3] = {i, j, k}, Ap[3] = {i, j, k};
-    Am[a] -= 1;
-    Ap[a] += 1;
-    const T cm = ld<C, DIM>(G, q, Am[0], Am[1], Am[2]);
-    const T cp = ld<C, DIM>(G, q, Ap[0], Ap[1], Ap[2]);
+    const int ex = (a == 0), ey = (a == 1), ez = (a == 2);
+    const T cm = L(C, -ex, -ey, -ez);
+    const T cp = L(C, ex, ey, ez);
     const int ia = I[a];
     if (a == C) {
       visc += ((cp - q0) / G.dxe[C][ia + 1] - (q0 - cm) / G.dxe[C][ia]) / G.dc[C][ia];
@@ -134,17 +112,17 @@ __device__ __forceinline__ int forced(const IbView<T>& ib, int i, int j, int* li
 // Predictor (MODE 0) or right-hand side (MODE 1) of component C at face
 // (i, j, k):  u* = u + dt (R + f),  f = eps [ -R + (u_s - u) / dt ], i.e.
 // u* = u + dt R off the body and u* = u_s on forced faces.
-template <int C, int DIM, int MODE, typename T>
-__device__ __forceinline__ void predict_face(const Geo<T>& G, const T* const* u, const T* fb,
-                                             T* out, const IbView<T>& ib, int i, int j, int k) {
+template <int C, int DIM, int MODE, typename T, typename Load>
+__device__ __forceinline__ void predict_face(const Geo<T>& G, const Load& L, const T* fb, T* out,
+                                             const IbView<T>& ib, int i, int j, int k) {
   if (C >= DIM || !evolved<C>(G, i, j, k)) return;
-  const T R = momentum_rhs<C, DIM, T>(G, u, fb, i, j, k);
+  const T R = momentum_rhs<C, DIM, T>(G, L, fb, i, j, k);
   const int64_t id = fidx(G.ext[C], i, j, k);
   if (MODE == 1) {
     out[id] = R;
     return;
   }
-  const T un = u[C][id];
+  const T un = L(C, 0, 0, 0);
   if constexpr (C < 2) {
     int li = 0;
     if (forced<C>(ib, i, j, &li)) {
@@ -159,26 +137,76 @@ __device__ __forceinline__ void predict_face(const Geo<T>& G, const T* const* u,
   out[id] = un + G.dt * R;
 }
 
+// LDS halo tiles: a block owns a 64 x 4 tile of cells in x-y and marches
+// through a chunk of z-planes, keeping planes k-1, k, k+1 of every
+// component (with a one-cell halo, boundary rules applied when the halo is
+// filled) in a three-slot ring.  Each value is loaded once per plane
+// instead of once per use.
+template <int DIM, typename T>
+__device__ __forceinline__ void fill_plane(const Geo<T>& G, const T* const* u,
+                                           PlaneRing<T, DIM>& R, int slot, int i0, int j0,
+                                           int kk) {
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    for (int s = threadIdx.x; s < kLX * kLY; s += kBlock) {
+      const int sy = s / kLX, sx = s - sy * kLX;
+      // halo slots past a ragged tile edge are clamped to one step outside
+      // the domain (their values are never used), so every load stays in
+      // bounds however small the axis
+      const int gi = min(i0 - 1 + sx, G.n[0]), gj = min(j0 - 1 + sy, G.n[1]);
+      T val;
+      if (c == 0) val = ld<0, DIM>(G, u[0], gi, gj, kk);
+      else if (c == 1) val = ld<1, DIM>(G, u[1], gi, gj, kk);
+      else val = ld<2, DIM>(G, u[2], gi, gj, kk);
+      R.v[c][slot][sy][sx] = val;
+    }
+  }
+}
+
 // MODE 0: predictor (writes u*, and the forcing on forced faces).
 // MODE 1: right-hand side only (writes R on advanced faces).
 template <typename T, int DIM, int MODE>
 __global__ void __launch_bounds__(kBlock)
-k_predictor(Geo<T> G, Tiling tl, const T* __restrict__ u0, const T* __restrict__ u1,
-            const T* __restrict__ u2, const T* __restrict__ fb0, const T* __restrict__ fb1,
-            const T* __restrict__ fb2, T* __restrict__ o0, T* __restrict__ o1,
-            T* __restrict__ o2, IbView<T> ib) {
+k_predictor(Geo<T> G, int ntx, int nty, int nzc, const T* __restrict__ u0,
+            const T* __restrict__ u1, const T* __restrict__ u2, const T* __restrict__ fb0,
+            const T* __restrict__ fb1, const T* __restrict__ fb2, T* __restrict__ o0,
+            T* __restrict__ o1, T* __restrict__ o2, IbView<T> ib) {
+  __shared__ PlaneRing<T, DIM> R;
   const T* u[3] = {u0, u1, u2};
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  for (int t = b; t < tl.ntiles; t += gridDim.x) {
-    const int tx = t % tl.ntx;
-    const int ty = (t / tl.ntx) % tl.nty;
-    const int k = t / (tl.ntx * tl.nty);
-    const int i = tx * kTileX + (threadIdx.x & (kTileX - 1));
-    const int j = ty * kTileY + (threadIdx.x / kTileX);
-    if (i >= G.n[0] || j >= G.n[1]) continue;
-    predict_face<0, DIM, MODE, T>(G, u, fb0, o0, ib, i, j, k);
-    predict_face<1, DIM, MODE, T>(G, u, fb1, o1, ib, i, j, k);
-    predict_face<2, DIM, MODE, T>(G, u, fb2, o2, ib, i, j, k);
+  if (b >= ntx * nty * nzc) return;
+  const int tx = b % ntx, ty = (b / ntx) % nty, zc = b / (ntx * nty);
+  const int i0 = tx * kTileX, j0 = ty * kTileY;
+  const int lx = threadIdx.x & (kTileX - 1), ly = threadIdx.x / kTileX;
+  const int i = i0 + lx, j = j0 + ly;
+  const int k0 = (DIM == 3) ? zc * kZChunk : 0;
+  const int k1 = (DIM == 3) ? min(k0 + kZChunk, G.n[2]) : 1;
+  const bool inside = i < G.n[0] && j < G.n[1];
+  if (DIM == 3) {
+    fill_plane<DIM>(G, u, R, ring_slot(k0 - 1), i0, j0, k0 - 1);
+    fill_plane<DIM>(G, u, R, ring_slot(k0), i0, j0, k0);
+    fill_plane<DIM>(G, u, R, ring_slot(k0 + 1), i0, j0, k0 + 1);
+  } else {
+    fill_plane<DIM>(G, u, R, 0, i0, j0, 0);
+  }
+  for (int k = k0; k < k1; ++k) {
+    __syncthreads();
+    const int sc = (DIM == 3) ? ring_slot(k) : 0;
+    const int sm = (DIM == 3) ? ring_slot(k - 1) : 0;
+    const int sp = (DIM == 3) ? ring_slot(k + 1) : 0;
+    if (inside) {
+      auto L = [&](int c, int di, int dj, int dk) -> T {
+        const int sl = dk < 0 ? sm : (dk > 0 ? sp : sc);
+        return R.v[c][sl][ly + 1 + dj][lx + 1 + di];
+      };
+      predict_face<0, DIM, MODE, T>(G, L, fb0, o0, ib, i, j, k);
+      predict_face<1, DIM, MODE, T>(G, L, fb1, o1, ib, i, j, k);
+      predict_face<2, DIM, MODE, T>(G, L, fb2, o2, ib, i, j, k);
+    }
+    if (DIM == 3 && k + 1 < k1) {
+      __syncthreads();
+      fill_plane<DIM>(G, u, R, sm, i0, j0, k + 2);   // slot of plane k-1 takes k+2
+    }
   }
 }
 
@@ -281,23 +309,21 @@ k_outflow_correct(Geo<T> G, Planes PL, T* us0, T* us1, T* us2, const SolverScala
 template <typename T>
 int launch_predictor(const Geo<T>& G, const T* const u[3], const T* const fb[3], T* out[3],
                      const IbView<T>& ib, int mode, hipStream_t s) {
-  const Tiling tl = make_tiling(G.n[0], G.n[1], G.n[2], 4 * kMaxRedBlocks);
-  dim3 grid(tl.nblocks), block(kBlock);
+  const int ntx = (G.n[0] + kTileX - 1) / kTileX;
+  const int nty = (G.n[1] + kTileY - 1) / kTileY;
+  const int nzc = (G.dim == 3) ? (G.n[2] + kZChunk - 1) / kZChunk : 1;
+  int nb = ntx * nty * nzc;
+  nb = (nb + kXcds - 1) / kXcds * kXcds;
+  dim3 grid(nb), block(kBlock);
+#define FVIB_PRED(D, M)                                                                        \
+  hipLaunchKernelGGL((k_predictor<T, D, M>), grid, block, 0, s, G, ntx, nty, nzc, u[0], u[1], \
+                     u[2], fb[0], fb[1], fb[2], out[0], out[1], out[2], ib)
   if (G.dim == 2) {
-    if (mode == 0)
-      hipLaunchKernelGGL((k_predictor<T, 2, 0>), grid, block, 0, s, G, tl, u[0], u[1], u[2],
-                         fb[0], fb[1], fb[2], out[0], out[1], out[2], ib);
-    else
-      hipLaunchKernelGGL((k_predictor<T, 2, 1>), grid, block, 0, s, G, tl, u[0], u[1], u[2],
-                         fb[0], fb[1], fb[2], out[0], out[1], out[2], ib);
+    if (mode == 0) FVIB_PRED(2, 0); else FVIB_PRED(2, 1);
   } else {
-    if (mode == 0)
-      hipLaunchKernelGGL((k_predictor<T, 3, 0>), grid, block, 0, s, G, tl, u[0], u[1], u[2],
-                         fb[0], fb[1], fb[2], out[0], out[1], out[2], ib);
-    else
-      hipLaunchKernelGGL((k_predictor<T, 3, 1>), grid, block, 0, s, G, tl, u[0], u[1], u[2],
-                         fb[0], fb[1], fb[2], out[0], out[1], out[2], ib);
+    if (mode == 0) FVIB_PRED(3, 0); else FVIB_PRED(3, 1);
   }
+#undef FVIB_PRED
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
