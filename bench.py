@@ -41,7 +41,7 @@ def kernel_cost(d: int, s: int, mixed: bool, n: tuple):
         "cg_update": ("bytes", 5 * v),                     # read p, x, r; write x, r
         "ir_correct": ("bytes", 8 + v + 8),                # read p, d; write p
         "project": ("bytes", 2 * d * s + 8),               # read u*, p; write u
-        "adj_momentum": ("bytes", d * (2 * d + 3) * s),    # per component: read u, ustar_bar; write ubar; rw fbbar
+        "adj_momentum": ("bytes", 5 * d * s),              # read u, ustar_bar; write ubar; rw fbbar
         "fdm_x": ("flops", 2 * n[0]),                      # dense contraction along x
         "fdm_y": ("flops", 2 * n[1]),
         "fdm_z": ("flops", 2 * n[2]),
@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle sample timed on the host (0 = skip)")
     ap.add_argument("--no-extra", action="store_true", help="skip the forward-only and fp64 runs")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -243,6 +245,14 @@ def main():
             out["fp64_value"] = round(ncell * n64 / el64 / 1e6, 3)
             out["fp32_over_fp64"] = round(value / out["fp64_value"], 3)
             print(f"[bench] fp64 fwd+adj {n64} steps in {el64:.3f} s", file=sys.stderr, flush=True)
+    if a.copy_probe:
+        import torch
+        src = torch.ones(64 << 20, dtype=torch.float32, device=g.device)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
     if a.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
     print(json.dumps(out), flush=True)

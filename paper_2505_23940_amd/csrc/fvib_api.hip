@@ -86,6 +86,8 @@ struct Grid {
   // metrics
   double* md = nullptr;
   float* mf = nullptr;
+  size_t stn_off = 0;     // first stencil coefficient in md / mf
+  size_t pst_off = 0;     // first pressure-operator coefficient in md / mf
   Geo<double> G64;
   Geo<float> G32;
   PGeo<double> P64;
@@ -102,7 +104,6 @@ struct Grid {
   float* pA32 = nullptr;
   float* pB32 = nullptr;
   double* partial = nullptr;
-  unsigned int* ticket = nullptr;
   SolverScalars* sc = nullptr;
   SolverScalars* sch = nullptr;   // pinned host mirror
   fvib_step_info* info_dev = nullptr;
@@ -128,7 +129,7 @@ struct Grid {
   std::vector<double> crit_log;   // residual criterion per refinement sweep of the last solve
 
   size_t esize() const { return prec == FVIB_PREC_FP64 ? sizeof(double) : sizeof(float); }
-  RedBuf red() const { return RedBuf{partial, ticket}; }
+  RedBuf red() const { return RedBuf{partial}; }
 };
 
 // Run `launch` bracketed by timing events of class cls when timing is on.
@@ -167,7 +168,6 @@ static void release(Grid* g) {
   f(g->pA32);
   f(g->pB32);
   f(g->partial);
-  f(g->ticket);
   f(g->sc);
   f(g->info_dev);
   f(g->mu);
@@ -235,6 +235,47 @@ static void axis_metrics(const std::vector<double>& f, bool periodic, std::vecto
   out.insert(out.end(), dc.begin(), dc.end());
   out.insert(out.end(), wi.begin(), wi.end());
   out.insert(out.end(), idc.begin(), idc.end());
+}
+
+// Stencil coefficients of one axis (layout of Met4 in fvib_internal.h),
+// built from the metrics of axis_metrics: (n + 2) cell entries for index
+// -1 .. n, then (n + 3) face entries for index -1 .. n + 1.
+static void stencil_coeffs(const std::vector<double>& ax, int N, bool periodic,
+                           std::vector<double>& out) {
+  const double* dx = ax.data();
+  const double* dxe = dx + N;
+  const double* dc = dxe + N + 2;
+  const double* wi = dc + N + 1;
+  for (int i = -1; i <= N; ++i) {
+    int q = i;
+    if (periodic) q = (i + N) % N;
+    else q = i < 0 ? 0 : (i > N - 1 ? N - 1 : i);
+    out.push_back(1.0 / dx[q]);
+    out.push_back(1.0 / (dc[q + 1] * dx[q]));
+    out.push_back(1.0 / (dc[q] * dx[q]));
+    out.push_back(0.0);
+  }
+  for (int f = -1; f <= N + 1; ++f) {
+    int q = f;
+    if (periodic) q = (f + N) % N;
+    else q = f < 0 ? 0 : (f > N ? N : f);
+    out.push_back(1.0 / dc[q]);
+    out.push_back(1.0 / (dxe[q + 1] * dc[q]));
+    out.push_back(1.0 / (dxe[q] * dc[q]));
+    out.push_back(wi[q]);
+  }
+}
+
+// Pressure-operator coefficients of one axis: kf(n + 1), the face
+// coefficient 1/dc with zeros on the faces of a bounded boundary (no flux
+// crosses them), then iv(n) = 1/dx.
+static void pressure_coeffs(const std::vector<double>& ax, int N, bool periodic,
+                            std::vector<double>& out) {
+  const double* dx = ax.data();
+  const double* dc = dx + N + N + 2;
+  for (int f = 0; f <= N; ++f)
+    out.push_back((!periodic && (f == 0 || f == N)) ? 0.0 : 1.0 / dc[f]);
+  for (int i = 0; i < N; ++i) out.push_back(1.0 / dx[i]);
 }
 
 static int validate(const fvib_grid_desc* d, std::string& msg) {
@@ -305,6 +346,13 @@ static void fill_geo(Grid* g, Geo<T>& G, const T* m) {
     G.wi[a] = m + off + 3 * N + 3;
     off += 5 * (size_t)N + 5;
   }
+  size_t so = g->stn_off;
+  for (int a = 0; a < 3; ++a) {
+    const int N = g->n[a];
+    G.mc[a] = reinterpret_cast<const Met4<T>*>(m + so) + 1;
+    G.mf[a] = reinterpret_cast<const Met4<T>*>(m + so) + (N + 2) + 1;
+    so += 4 * (size_t)(2 * N + 5);
+  }
   G.nu = (T)g->d.nu;
   G.dt = (T)g->d.dt;
   G.rho = (T)g->d.rho;
@@ -323,6 +371,13 @@ static void fill_pgeo(Grid* g, PGeo<V>& P, const V* m) {
     P.dx[a] = m + off;
     P.idc[a] = m + off + 4 * N + 4;
     off += 5 * (size_t)N + 5;
+  }
+  size_t po = g->pst_off;
+  for (int a = 0; a < 3; ++a) {
+    const int N = g->n[a];
+    P.kf[a] = m + po;
+    P.iv[a] = m + po + N + 1;
+    po += 2 * (size_t)N + 1;
   }
   P.dt_over_rho = g->d.dt / g->d.rho;
   P.inv_ncell = 1.0 / (double)g->ncell;
@@ -428,48 +483,65 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
   } restore{g, last, saved};
   g->crit_log.clear();
   if (g->d.solver == FVIB_SOLVER_FDM) {
+    // Refinement sweeps are launched ahead of the host's convergence check
+    // (as many as the previous solve of this kind needed); once the
+    // residual kernel marks the refinement finished, the sweeps still in
+    // the queue return at once.  The host synchronises once per batch.
     const bool d64 = g->prec == FVIB_PREC_FP64;
-    int sweeps = 0;
-    for (; sweeps < g->d.ir_maxit + 1; ++sweeps) {
-      rc = timed(g, FVIB_K_RESIDUAL, [&] {
-        return launch_residual(g->P64, d64 ? 3 : 2, b, p, g->r64, g->r32, nullptr, g->red(), g->sc,
-                               tol, 0.5, g->stream);
+    const int* stop = &g->sc->outer_done;
+    auto residual = [&](int first) {
+      return timed(g, FVIB_K_RESIDUAL, [&] {
+        return launch_residual(g->P64, d64 ? 3 : 2, b, p, g->r64, g->r32, nullptr, g->red(),
+                               g->sc, tol, 0.5, g->stream, first);
       });
-      if (rc) return rc;
+    };
+    auto sweep = [&]() -> int {
+      // d = A^+ r by fast diagonalisation (forward axes, then inverse axes)
+      for (int pass = 0; pass < 2 * g->dim; ++pass) {
+        const bool fwd = pass < g->dim;
+        const int a = fwd ? pass : 2 * g->dim - 1 - pass;
+        const bool lastp = pass == 2 * g->dim - 1;
+        int r2 = timed(g, FVIB_K_FDM_X + a, [&] {
+          if (d64) {
+            const double* in = (pass == 0) ? g->r64 : ((pass % 2) ? g->pA64 : g->pB64);
+            double* out = lastp ? g->d64 : ((pass % 2) ? g->pB64 : g->pA64);
+            return launch_fdm_axis<double>(g->F64, a, fwd, in, out, stop, g->stream);
+          }
+          const float* in = (pass == 0) ? g->r32 : ((pass % 2) ? g->pA32 : g->pB32);
+          float* out = lastp ? g->d32 : ((pass % 2) ? g->pB32 : g->pA32);
+          return launch_fdm_axis<float>(g->F32, a, fwd, in, out, stop, g->stream);
+        });
+        if (r2) return r2;
+      }
+      int r2 = timed(g, FVIB_K_IR_CORRECT, [&] {
+        return d64 ? launch_add_correction<double>(g->ncell, p, g->d64, stop, g->stream)
+                   : launch_add_correction<float>(g->ncell, p, g->d32, stop, g->stream);
+      });
+      if (r2) return r2;
+      return residual(0);
+    };
+    if ((rc = residual(1))) return rc;
+    int launched = 0;
+    int batch = std::max(1, std::min(g->last_iters, g->d.ir_maxit));
+    for (;;) {
+      for (int q = 0; q < batch && launched < g->d.ir_maxit; ++q, ++launched)
+        if ((rc = sweep())) return rc;
       if ((rc = read_scalars(g))) return rc;
       g->crit_log.push_back(g->sch->crit);
       if (g->sch->outer_done) break;
-      if (sweeps == g->d.ir_maxit) {
+      if (launched >= g->d.ir_maxit) {
+        // refinement budget exhausted: report it on the device scalars
         int stc = FVIB_ENOCONV;
         FVIB_HIP(hipMemcpyAsync(&g->sc->status, &stc, sizeof(int), hipMemcpyHostToDevice, g->stream));
         FVIB_HIP(hipStreamSynchronize(g->stream));
         break;
       }
-      // d = A^+ r by fast diagonalisation (forward axes, then inverse axes)
-      for (int pass = 0; pass < 2 * g->dim; ++pass) {
-        const bool fwd = pass < g->dim;
-        const int a = fwd ? pass : 2 * g->dim - 1 - pass;
-        const bool last = pass == 2 * g->dim - 1;
-        rc = timed(g, FVIB_K_FDM_X + a, [&] {
-          if (d64) {
-            const double* in = (pass == 0) ? g->r64 : ((pass % 2) ? g->pA64 : g->pB64);
-            double* out = last ? g->d64 : ((pass % 2) ? g->pB64 : g->pA64);
-            return launch_fdm_axis<double>(g->F64, a, fwd, in, out, g->stream);
-          }
-          const float* in = (pass == 0) ? g->r32 : ((pass % 2) ? g->pA32 : g->pB32);
-          float* out = last ? g->d32 : ((pass % 2) ? g->pB32 : g->pA32);
-          return launch_fdm_axis<float>(g->F32, a, fwd, in, out, g->stream);
-        });
-        if (rc) return rc;
-      }
-      rc = timed(g, FVIB_K_IR_CORRECT, [&] {
-        return d64 ? launch_add_correction<double>(g->ncell, p, g->d64, g->stream)
-                   : launch_add_correction<float>(g->ncell, p, g->d32, g->stream);
-      });
-      if (rc) return rc;
+      batch = 1;
     }
     if ((rc = timed(g, FVIB_K_IR_CORRECT, [&] { return launch_gauge(g->ncell, p, g->sc, g->stream); })))
       return rc;
+    const int sweeps = g->sch->outer_done ? g->sch->sweeps : launched;
+    g->last_iters = sweeps;
     *cg_total = 0;
     *ir_total = sweeps;
     return FVIB_OK;
@@ -774,12 +846,19 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
     g->nface[c] = (int64_t)g->ext[c][0] * g->ext[c][1] * g->ext[c][2];
   }
   // metrics
-  std::vector<double> m;
+  std::vector<double> m, stn, pst;
   for (int a = 0; a < 3; ++a) {
     std::vector<double> ax;
     axis_metrics(g->faces[a], g->per[a] != 0, ax);
     m.insert(m.end(), ax.begin(), ax.end());
+    stencil_coeffs(ax, g->n[a], g->per[a] != 0, stn);
+    pressure_coeffs(ax, g->n[a], g->per[a] != 0, pst);
   }
+  m.resize((m.size() + 3) / 4 * 4, 0.0);     // Met4 entries start aligned
+  g->stn_off = m.size();
+  m.insert(m.end(), stn.begin(), stn.end());
+  g->pst_off = m.size();
+  m.insert(m.end(), pst.begin(), pst.end());
   std::vector<float> mf(m.begin(), m.end());
   auto bail = [&](int code, const char* what) {
     release(g);
@@ -812,7 +891,6 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
     ok &= dmalloc(&g->pB32, g->ncell * sizeof(float)) == FVIB_OK;
   }
   ok &= dmalloc(&g->partial, 4 * kMaxRedBlocks * sizeof(double)) == FVIB_OK;
-  ok &= dmalloc(&g->ticket, 64 * sizeof(unsigned int)) == FVIB_OK;
   ok &= dmalloc(&g->sc, sizeof(SolverScalars)) == FVIB_OK;
   ok &= dmalloc(&g->info_dev, sizeof(fvib_step_info)) == FVIB_OK;
   ok &= dmalloc(&g->mu, g->ncell * sizeof(double)) == FVIB_OK;
@@ -835,12 +913,16 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
       std::vector<double> phiT((size_t)N * N);
       for (int i = 0; i < N; ++i)
         for (int j = 0; j < N; ++j) phiT[(size_t)j * N + i] = phi[(size_t)i * N + j];
+      // every block starts on a 4-element boundary (vector loads of rows)
       off[a][0] = hd.size();
       hd.insert(hd.end(), phi.begin(), phi.end());
+      hd.resize((hd.size() + 3) / 4 * 4, 0.0);
       off[a][1] = hd.size();
       hd.insert(hd.end(), phiT.begin(), phiT.end());
+      hd.resize((hd.size() + 3) / 4 * 4, 0.0);
       off[a][2] = hd.size();
       hd.insert(hd.end(), lam.begin(), lam.end());
+      hd.resize((hd.size() + 3) / 4 * 4, 0.0);
     }
     std::vector<float> hf(hd.begin(), hd.end());
     if (dmalloc(&g->fdm_d, hd.size() * sizeof(double)) || dmalloc(&g->fdm_f, hf.size() * sizeof(float)))
@@ -872,7 +954,6 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
   if (hipHostMalloc((void**)&g->sch, sizeof(SolverScalars), hipHostMallocDefault) != hipSuccess)
     return bail(FVIB_ENOMEM, "pinned host allocation failed");
   if (hipMemset(g->mu, 0, g->ncell * sizeof(double)) != hipSuccess ||
-      hipMemset(g->ticket, 0, 64 * sizeof(unsigned int)) != hipSuccess ||
       hipMemset(g->sc, 0, sizeof(SolverScalars)) != hipSuccess)
     return bail(FVIB_EHIP, "workspace initialisation failed");
   for (int c = 0; c < g->dim; ++c)
@@ -1175,9 +1256,9 @@ int fvib_loss_wall_shear(fvib_grid* h, const void* u0, double* J, void* ubar0) {
   const int nx = g->ext[0][0], nz = g->ext[0][2];
   int rc;
   if (g->prec == FVIB_PREC_FP64)
-    rc = launch_wall_shear<double>(nx, N, nz, (const double*)u0, (double*)ubar0, wlo, whi, J, g->stream);
+    rc = launch_wall_shear<double>(nx, N, nz, (const double*)u0, (double*)ubar0, wlo, whi, J, g->partial, g->stream);
   else
-    rc = launch_wall_shear<float>(nx, N, nz, (const float*)u0, (float*)ubar0, wlo, whi, J, g->stream);
+    rc = launch_wall_shear<float>(nx, N, nz, (const float*)u0, (float*)ubar0, wlo, whi, J, g->partial, g->stream);
   return rc;
 }
 

@@ -24,6 +24,18 @@ constexpr int kXcds = 8;             // MI355X: 8 XCDs, round-robin dispatch
 //   dx[i]  cell width (n), dxe[e] widths with one mirrored/periodic ghost on
 //   each side (n + 2, dxe[i + 1] = dx[i]), dc[f] centre spacing at face f
 //   (n + 1), wi[f] interpolation weight of the upper cell at face f (n + 1).
+// Stencil coefficients of one index along an axis, four per entry so one
+// vector load fetches them.  Cell entries (index -1 .. n):
+//   x = 1/dx, y = 1/(dc[i+1] dx[i]), z = 1/(dc[i] dx[i]), w = 0;
+// face entries (index -1 .. n+1):
+//   x = 1/dc, y = 1/(dxe[f+1] dc[f]), z = 1/(dxe[f] dc[f]), w = wi[f].
+// Entries past the ends wrap on periodic axes and repeat the end entry on
+// bounded ones (there they only ever multiply a zero adjoint).
+template <typename T>
+struct alignas(4 * sizeof(T)) Met4 {
+  T x, y, z, w;
+};
+
 template <typename T>
 struct Geo {
   int dim;
@@ -33,6 +45,8 @@ struct Geo {
   int dir[3][2];       // 1: Dirichlet ghost rule on boundary (a, side)
   T gv[3][3][2];       // ghost value g of comp c behind boundary (a, side)
   const T *dx[3], *dxe[3], *dc[3], *wi[3];
+  const Met4<T>* mc[3];  // cell coefficients, mc[a][i] valid for i in [-1, n]
+  const Met4<T>* mf[3];  // face coefficients, mf[a][f] valid for f in [-1, n+1]
   T nu, dt, rho;
   int upwind;
 };
@@ -87,6 +101,36 @@ __device__ __forceinline__ T ld(const Geo<T>& G, const T* __restrict__ q, int i,
   return neg ? off - v : v;
 }
 
+// Branch-free variant of ld for halo fills: the index of each axis is
+// wrapped (periodic) or clamped (bounded) with selects, and the ghost rule
+// of the last axis found outside is applied.  *outside reports whether any
+// bounded axis was left (the index then names the boundary-adjacent face).
+template <int C, int DIM, typename T>
+__device__ __forceinline__ T ld_halo(const Geo<T>& G, const T* __restrict__ q, int i, int j,
+                                     int k, bool* outside) {
+  int I[3] = {i, j, k};
+  T off = T(0);
+  bool neg = false, out = false;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const int e = G.ext[C][a];
+    const bool lo = I[a] < 0, hi = I[a] >= e;
+    const bool per = G.per[a] != 0;
+    const int wrapped = lo ? I[a] + e : (hi ? I[a] - e : I[a]);
+    const int clamped = lo ? 0 : (hi ? e - 1 : I[a]);
+    I[a] = per ? wrapped : clamped;
+    const bool ghost = !per && (lo || hi);
+    const bool dir = lo ? (G.dir[a][0] != 0) : (G.dir[a][1] != 0);
+    const T g2 = T(2) * (lo ? G.gv[C][a][0] : G.gv[C][a][1]);
+    neg = (ghost && dir) ? true : (ghost ? false : neg);
+    off = (ghost && dir) ? g2 : off;
+    out = out || ghost;
+  }
+  *outside = out;
+  const T v = q[fidx(G.ext[C], I[0], I[1], I[2])];
+  return neg ? off - v : v;
+}
+
 // --------------------------------------------------------- tile iteration
 // Logical tiles of kTileX x kTileY cells in one z-plane.  Blocks are
 // dispatched round-robin over the XCDs; remapping the block id makes every
@@ -125,6 +169,50 @@ struct PlaneRing {
 };
 
 __device__ __forceinline__ int ring_slot(int k) { return ((k % 3) + 3) % 3; }
+
+// Stencil coefficients of a block's tile in LDS: entries -1 .. 64 of the
+// tile along x, -1 .. 4 along y and -1 .. kZChunk along z (relative to the
+// tile origin), loaded once per block since they do not change along the
+// z-march.  Indices past the grid are clamped (those entries are never
+// used for a real face).
+constexpr int kMX = (kLX > kZChunk + 2) ? kLX : kZChunk + 2;
+
+template <typename T>
+struct TileMet {
+  Met4<T> c[3][kMX];
+  Met4<T> f[3][kMX];
+};
+
+template <int DIM, typename T>
+__device__ __forceinline__ void load_tile_met(const Geo<T>& G, TileMet<T>& M, int i0, int j0,
+                                              int k0) {
+  const int base[3] = {i0 - 1, j0 - 1, k0 - 1};
+  for (int e = threadIdx.x; e < DIM * kMX; e += kBlock) {
+    const int a = e / kMX, x = e - a * kMX;
+    const int n = G.n[a];
+    const int gi = base[a] + x;
+    M.c[a][x] = G.mc[a][min(gi, n)];        // cell entries exist for -1 .. n
+    M.f[a][x] = G.mf[a][min(gi, n + 1)];    // face entries for -1 .. n + 1
+  }
+}
+
+// Coefficient access relative to a face J: mc(a, off) / mf(a, off) are the
+// cell / face entries at index J[a] + off (off in -1 .. 1) along axis a.
+template <typename T>
+struct MetLds {
+  const TileMet<T>* M;
+  int o[3];           // LDS index of J along each axis
+  __device__ __forceinline__ Met4<T> mc(int a, int off) const { return M->c[a][o[a] + off]; }
+  __device__ __forceinline__ Met4<T> mf(int a, int off) const { return M->f[a][o[a] + off]; }
+};
+
+template <typename T>
+struct MetGlobal {
+  const Geo<T>* G;
+  int J[3];
+  __device__ __forceinline__ Met4<T> mc(int a, int off) const { return G->mc[a][J[a] + off]; }
+  __device__ __forceinline__ Met4<T> mf(int a, int off) const { return G->mf[a][J[a] + off]; }
+};
 
 
 // ------------------------------------------------------------- reductions
@@ -174,52 +262,61 @@ __device__ __forceinline__ double block_max(double v) {
   return m;
 }
 
-// Deterministic grid reduction: every block stores its partials, the last
-// block to arrive (atomic ticket) combines them in block order.  Returns
-// true in the last block, whose threads then all hold the totals in tot.
-// Kinds: first NS values are sums, the remaining NV - NS are maxima.
+// Deterministic two-pass grid reduction.  Every block of the producing
+// kernel reduces its values in a fixed order and stores one partial per
+// value; a one-block kernel launched right after it on the same stream
+// combines the partials in block order and hands the totals to an
+// epilogue.  The kernel boundary makes the partials visible, so no block
+// needs a device-wide fence (on a multi-XCD part such a fence writes back
+// and invalidates the XCD's L2 and costs every block that follows it).
+// Kinds: the first NS values are sums, the remaining NV - NS are maxima.
 template <int NV, int NS>
-__device__ __forceinline__ bool grid_reduce(double (&v)[NV], double* partial,
-                                            unsigned int* ticket, double (&tot)[NV]) {
-  __shared__ bool last;
+__device__ __forceinline__ void block_partials(double (&v)[NV], double* partial) {
   double s[NS > 0 ? NS : 1];
-#pragma unroll
-  for (int q = 0; q < NS; ++q) s[q] = v[q];
   if constexpr (NS > 0) {
-    double tmp[NS];
 #pragma unroll
-    for (int q = 0; q < NS; ++q) tmp[q] = s[q];
-    block_sum<NS>(tmp);
-#pragma unroll
-    for (int q = 0; q < NS; ++q) s[q] = tmp[q];
+    for (int q = 0; q < NS; ++q) s[q] = v[q];
+    block_sum<NS>(s);
   }
   double mx[NV - NS > 0 ? NV - NS : 1];
 #pragma unroll
   for (int q = NS; q < NV; ++q) mx[q - NS] = block_max(v[q]);
-  const int nb = gridDim.x;
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < NS; ++q) partial[q * kMaxRedBlocks + blockIdx.x] = s[q];
 #pragma unroll
     for (int q = NS; q < NV; ++q) partial[q * kMaxRedBlocks + blockIdx.x] = mx[q - NS];
-    __threadfence();
-    const unsigned int t = atomicAdd(ticket, 1u);
-    last = (t == (unsigned int)(nb - 1));
   }
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
+}
+
+struct SolverScalars;
+
+// Second pass: FIN::skip(sc) lets an epilogue stand down with its producer
+// (a finished CG solve launches no work); FIN::apply(tot, sc) runs on
+// thread 0 with the totals.
+template <int NV, int NS, typename FIN>
+__global__ void __launch_bounds__(kBlock)
+k_reduce_finish(const double* __restrict__ partial, int nb, SolverScalars* sc, FIN fin) {
+  if (fin.skip(sc)) return;
+  // all loads issued before the (fixed-order) combination
+  constexpr int kPer = kMaxRedBlocks / kBlock;
+  double x[NV][kPer];
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int b = threadIdx.x + u * kBlock;
+      x[q][u] = (b < nb) ? partial[q * kMaxRedBlocks + b] : ((q < NS) ? 0.0 : -1.0);
+    }
   double acc[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
     double a = (q < NS) ? 0.0 : -1.0;
-    const volatile double* pq = partial + q * kMaxRedBlocks;
-    for (int b = threadIdx.x; b < nb; b += kBlock) {
-      const double x = pq[b];
-      a = (q < NS) ? a + x : fmax(a, x);
-    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) a = (q < NS) ? a + x[q][u] : fmax(a, x[q][u]);
     acc[q] = a;
   }
+  double tot[NV];
   if constexpr (NS > 0) {
     double tmp[NS];
 #pragma unroll
@@ -230,8 +327,15 @@ __device__ __forceinline__ bool grid_reduce(double (&v)[NV], double* partial,
   }
 #pragma unroll
   for (int q = NS; q < NV; ++q) tot[q] = block_max(acc[q]);
-  if (threadIdx.x == 0) *ticket = 0u;   // ready for the next launch
-  return true;
+  if (threadIdx.x == 0) fin.apply(tot, sc);
+}
+
+template <int NV, int NS, typename FIN>
+inline hipError_t launch_finish(const double* partial, int nb, SolverScalars* sc, const FIN& fin,
+                                hipStream_t s) {
+  hipLaunchKernelGGL((k_reduce_finish<NV, NS, FIN>), dim3(1), dim3(kBlock), 0, s, partial, nb, sc,
+                     fin);
+  return hipGetLastError();
 }
 
 // Pressure-operator metrics in the vector type V of the solve.
@@ -242,6 +346,8 @@ struct PGeo {
   int per[3];
   const V* dx[3];    // cell widths
   const V* idc[3];   // 1 / centre spacing at faces 0..n
+  const V* kf[3];    // idc with zeros on the faces of a bounded boundary
+  const V* iv[3];    // 1 / cell width
   double dt_over_rho;
   double inv_ncell;
 };
@@ -282,12 +388,12 @@ struct SolverScalars {
   int iters;        // iterations of the current CG solve
   int status;       // FVIB_OK or a negative status
   int clamp;        // body window clamped (body left the allowed region)
-  int pad[3];
+  int sweeps;       // refinement corrections applied in the current solve
+  int pad[2];
 };
 
 struct RedBuf {
   double* partial;          // 4 * kMaxRedBlocks doubles
-  unsigned int* ticket;     // one counter per reduction site
 };
 
 // ------------------------------------------------------------ host glue

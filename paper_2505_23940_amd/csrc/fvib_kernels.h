@@ -55,9 +55,11 @@ template <typename T>
 int launch_ppe_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
                    const IbView<T>& ib, double* b, RedBuf red, SolverScalars* sc,
                    hipStream_t s);
+// first = 0: a refinement sweep launched ahead of the host's check; it
+// does nothing once the device scalars say the refinement is finished.
 int launch_residual(const PGeo<double>& P, int mode, const double* b, const double* x,
                     double* r64, float* r32, float* d32, RedBuf red, SolverScalars* sc,
-                    double tol, double inner_rtol, hipStream_t s);
+                    double tol, double inner_rtol, hipStream_t s, int first = 1);
 // ev (nullable): three events recorded before the direction kernel, between
 // the two kernels and after the update kernel.
 template <typename V>
@@ -104,9 +106,10 @@ int launch_adj_momentum(const Geo<T>& G, const T* const u[3], const T* const usb
 
 // k_fdm.hip
 template <typename V>
-int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, hipStream_t s);
+int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, const int* stop,
+                    hipStream_t s);
 template <typename V>
-int launch_add_correction(int64_t n, double* p, const V* d, hipStream_t s);
+int launch_add_correction(int64_t n, double* p, const V* d, const int* stop, hipStream_t s);
 int launch_gauge(int64_t n, double* p, const SolverScalars* sc, hipStream_t s);
 void axis_eigen(const std::vector<double>& f, bool periodic, std::vector<double>& phi,
                 std::vector<double>& lam);
@@ -114,7 +117,7 @@ void axis_eigen(const std::vector<double>& f, bool periodic, std::vector<double>
 // k_loss.hip
 template <typename T>
 int launch_wall_shear(int nx, int ny, int nz, const T* u, T* ubar, double wlo, double whi,
-                      double* J, hipStream_t s);
+                      double* J, double* partial, hipStream_t s);
 int launch_rms_lift(const double* Fh, int S, int stride, int off, double g, double* J,
                     double* dFh, hipStream_t s);
 

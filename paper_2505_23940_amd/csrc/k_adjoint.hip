@@ -226,32 +226,43 @@ k_adj_rhs(Geo<T> G, PGeo<double> P, Tiling tl, const T* __restrict__ b0,
     const int k = t_ / (tl.ntx * tl.nty);
     if (i >= nx_ || j >= ny_) continue;
     const int I[3] = {i, j, k};
+    double lo[DIM], hi[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const int ic = I[c], nc = G.n[c];
+      int H[3] = {i, j, k};
+      H[c] = (G.per[c] && ic + 1 == nc) ? 0 : ic + 1;
+      lo[c] = (double)ub[c][fidx(G.ext[c], i, j, k)];
+      hi[c] = (double)ub[c][fidx(G.ext[c], H[0], H[1], H[2])];
+    }
     double acc = 0.0;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
       const int ic = I[c], nc = G.n[c];
-      if (G.per[c] || ic > 0)
-        acc += (double)ub[c][fidx(G.ext[c], i, j, k)] * P.idc[c][ic];
-      if (G.per[c] || ic + 1 < nc) {
-        int H[3] = {i, j, k};
-        H[c] = (ic + 1 == nc) ? 0 : ic + 1;
-        acc -= (double)ub[c][fidx(G.ext[c], H[0], H[1], H[2])] * P.idc[c][ic + 1];
-      }
+      // boundary faces of a bounded axis carry no flux (selected, not
+      // multiplied, so whatever the adjoint holds there cannot leak in)
+      const double tl_ = lo[c] * P.idc[c][ic], th_ = hi[c] * P.idc[c][ic + 1];
+      acc += (G.per[c] || ic > 0) ? tl_ : 0.0;
+      acc -= (G.per[c] || ic + 1 < nc) ? th_ : 0.0;
     }
     y[((int64_t)k * ny_ + j) * nx_ + i] = acc;
     sum += acc;
-    double v = (double)P.dx[0][i] * (double)P.dx[1][j];
-    if (DIM == 3) v *= (double)P.dx[2][k];
-    mx = fmax(mx, fabs(acc) / v);
+    double iv = (double)P.iv[0][i] * (double)P.iv[1][j];
+    if (DIM == 3) iv *= (double)P.iv[2][k];
+    mx = fmax(mx, fabs(acc) * iv);
   }
-  double v[2] = {sum, mx}, tot[2];
-  if (grid_reduce<2, 1>(v, red.partial, red.ticket, tot)) {
-    if (threadIdx.x == 0) {
-      sc->meanb = tot[0] * P.inv_ncell;
-      sc->crit = tot[1];
-    }
-  }
+  double v[2] = {sum, mx};
+  block_partials<2, 1>(v, red.partial);
 }
+
+struct FinAdjRhs {          // mean of G^T ubar and max |y / V|
+  double inv_ncell;
+  __device__ bool skip(const SolverScalars*) const { return false; }
+  __device__ void apply(const double* t, SolverScalars* sc) const {
+    sc->meanb = t[0] * inv_ncell;
+    sc->crit = t[1];
+  }
+};
 
 template <int C, typename T>
 __device__ __forceinline__ int forced_cls(const IbView<T>& ib, int i, int j, int* lidx) {
@@ -358,11 +369,15 @@ k_adj_outflow_sum(Geo<T> G, Planes PL, const T* __restrict__ u0, const T* __rest
     const double sign = (Pn.side == 0) ? -1.0 : 1.0;
     acc += sign * (double)us[Pn.c][fidx(G.ext[Pn.c], I[0], I[1], I[2])];
   }
-  double v[1] = {acc}, tot[1];
-  if (grid_reduce<1, 1>(v, red.partial, red.ticket, tot)) {
-    if (threadIdx.x == 0) sc->meanb = -tot[0] / PL.area_out;
-  }
+  double v[1] = {acc};
+  block_partials<1, 1>(v, red.partial);
 }
+
+struct FinAdjOutflow {      // K = -(1/A_out) sum_out s_b ustar_bar_b
+  double area_out;
+  __device__ bool skip(const SolverScalars*) const { return false; }
+  __device__ void apply(const double* t, SolverScalars* sc) const { sc->meanb = -t[0] / area_out; }
+};
 
 // mode 0: outflow correction + zero-gradient hand-off (before the momentum
 // adjoint); mode 1: convective outflow into ubar^n (after it).
@@ -421,8 +436,10 @@ struct AdjCtx {
   IbView<T> ib;       // point classes; ib.f holds fbar on forced faces
 };
 
-// Rbar of component C at face (i, j, k); indices may lie one step outside
-// the array (periodic wrap, else zero).
+// Rbar / dt of component C at face (i, j, k), i.e. ustar_bar, or -fbar / dt
+// on a forced face; indices may lie one step outside the array (periodic
+// wrap, else zero).  The momentum adjoint gathers with this scaled Rbar and
+// multiplies the sum by dt once.
 template <int C, int DIM, typename T>
 __device__ __forceinline__ T rbar(const AdjCtx<T>& X, int i, int j, int k) {
   int I[3] = {i, j, k};
@@ -440,9 +457,9 @@ __device__ __forceinline__ T rbar(const AdjCtx<T>& X, int i, int j, int k) {
   if (!X.G.per[C] && (I[C] < 1 || I[C] > X.G.n[C] - 1)) return T(0);
   if constexpr (C < 2) {
     int li;
-    if (forced_cls<C>(X.ib, I[0], I[1], &li)) return -X.ib.f[C][li];
+    if (forced_cls<C>(X.ib, I[0], I[1], &li)) return -X.ib.f[C][li] / X.G.dt;
   }
-  return X.G.dt * X.usb[C][fidx(X.G.ext[C], I[0], I[1], I[2])];
+  return X.usb[C][fidx(X.G.ext[C], I[0], I[1], I[2])];
 }
 
 template <int A_, int DIM, typename T>
@@ -468,170 +485,98 @@ __device__ __forceinline__ T ldu_c(const AdjCtx<T>& X, int c, int i, int j, int 
 // Gather of every use of u_C(J) in R (convection and diffusion, ghost
 // preimages included).  RB(c, di, dj, dk) / U(c, di, dj, dk) return Rbar and
 // u^n of component c at an offset of at most one step per axis from J
-// (Rbar is zero outside the domain and on faces R does not advance).
-template <int C, int DIM, typename T, typename RBL, typename UL>
-__device__ __forceinline__ T adj_gather(const Geo<T>& G, const RBL& RB, const UL& U,
+// (Rbar is zero outside the domain and on faces R does not advance, so the
+// terms of stencils that do not exist vanish without a branch; the padded
+// coefficient tables keep every index in range).
+template <int C, int DIM, bool UPW, typename T, typename RBL, typename UL, typename ML>
+__device__ __forceinline__ T adj_gather(const Geo<T>& G, const RBL& RB, const UL& U, const ML& M,
                                         const int J[3]) {
-  const int jc = J[C];
-  const bool upw = G.upwind != 0;
-  T acc = T(0);
-  // ---- own-direction convection: J is the right face of cell jc-1 and the
-  // left face of cell jc
-#pragma unroll
-  for (int side = 0; side < 2; ++side) {
-    const int m = jc - 1 + side;            // cell index along C
-    if (!G.per[C] && (m < 0 || m > G.n[C] - 1)) continue;
-    const int oL = side - 1, oR = side;     // offsets of faces m, m+1 from J
-    const T uL = U(C, C == 0 ? oL : 0, C == 1 ? oL : 0, C == 2 ? oL : 0);
-    const T uR = U(C, C == 0 ? oR : 0, C == 1 ? oR : 0, C == 2 ? oR : 0);
-    int mm = m;
-    if (G.per[C] && mm < 0) mm += G.n[C];
-    // Pbar(m) = Cbar(face m)/dc[m] - Cbar(face m+1)/dc[m+1], Cbar = -Rbar
-    const T Pb = -RB(C, C == 0 ? oL : 0, C == 1 ? oL : 0, C == 2 ? oL : 0) / G.dc[C][mm] +
-                 RB(C, C == 0 ? oR : 0, C == 1 ? oR : 0, C == 2 ? oR : 0) / G.dc[C][m + 1];
-    const T Q = T(0.5) * (uL + uR);
-    T d;
-    if (upw) {
-      const T up = Q > T(0) ? uL : (Q < T(0) ? uR : T(0));
-      d = T(0.5) * up + (side == 0 ? (Q < T(0) ? Q : T(0)) : (Q > T(0) ? Q : T(0)));
+  constexpr int cx = (C == 0), cy = (C == 1), cz = (C == 2);
+  const T u0 = U(C, 0, 0, 0), r0 = RB(C, 0, 0, 0);
+  const T nu = G.nu;
+  const Met4<T> fcm = M.mf(C, -1), fc0 = M.mf(C, 0), fcp = M.mf(C, 1);
+  T acc;
+  // ---- own axis: convective fluxes at the centres of cells jc-1 and jc,
+  // F = Q^2 (central) or Q u_upwind, Q the mean of the two faces; Fbar of a
+  // cell is the difference of the scaled Rbar of its two faces
+  {
+    const T um = U(C, -cx, -cy, -cz), up = U(C, cx, cy, cz);
+    const T rm = RB(C, -cx, -cy, -cz), rp = RB(C, cx, cy, cz);
+    const T Pb0 = r0 * fc0.x - rm * fcm.x;
+    const T Pb1 = rp * fcp.x - r0 * fc0.x;
+    const T Q0 = T(0.5) * (um + u0), Q1 = T(0.5) * (u0 + up);
+    if constexpr (!UPW) {
+      acc = Q0 * Pb0 + Q1 * Pb1;
     } else {
-      d = Q;
+      // J is the upper face of cell jc-1 and the lower face of cell jc
+      const T w0 = Q0 > T(0) ? um : (Q0 < T(0) ? u0 : T(0));
+      const T w1 = Q1 > T(0) ? u0 : (Q1 < T(0) ? up : T(0));
+      const T d0 = T(0.5) * w0 + (Q0 < T(0) ? Q0 : T(0));
+      const T d1 = T(0.5) * w1 + (Q1 > T(0) ? Q1 : T(0));
+      acc = d0 * Pb0 + d1 * Pb1;
     }
-    acc += d * Pb;
+    // own-axis diffusion
+    acc += nu * (rm * fcm.y + rp * fcp.z - r0 * (fc0.y + fc0.z));
   }
-  // ---- cross-direction convection through the edge fluxes
+  // ---- cross axes: the edge at a-face ja (e = 0, J the upper cell) and at
+  // a-face ja + 1 (e = 1, J the lower cell).  The edge carries F_C = U V for
+  // the C-equation (U: u_C along a, V: u_a along C) and F_a for the
+  // a-equation.  Behind a bounded a-boundary the ghost of J sits on the
+  // other side of the same edge, so the ghost preimage is the same edge
+  // term with the ghost's weight and sign (the a-equation has no flux
+  // there: its boundary face is not advanced).
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     if (a == C) continue;
-    const int ja = J[a];
-    const int na = G.n[a];
-    const int nc = G.n[C];
-    const T wc = G.wi[C][jc];
     const int ax = (a == 0), ay = (a == 1), az = (a == 2);
-    const int cx = (C == 0), cy = (C == 1), cz = (C == 2);
+    const int ja = J[a];
+    const Met4<T> cam = M.mc(a, -1), ca0 = M.mc(a, 0), cap = M.mc(a, 1);
+    const T ixc_lo = M.mc(C, -1).x, ixc_hi = M.mc(C, 0).x;
+    const T wc = fc0.w;
+    const bool gb = !G.per[a];
+    const T sg_lo = (gb && ja == 0) ? (G.dir[a][0] ? T(-1) : T(1)) : T(0);
+    const T sg_hi = (gb && ja == G.n[a] - 1) ? (G.dir[a][1] ? T(-1) : T(1)) : T(0);
+    const T rca = RB(C, -ax, -ay, -az), rcb = RB(C, ax, ay, az);
+    const T uca = U(C, -ax, -ay, -az), ucb = U(C, ax, ay, az);
+    T cross = T(0);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      int jj;          // a-face index of the edge
-      T sg = T(1);     // ghost sign (1 for a real use)
-      bool lower;      // J (or its ghost) is the lower cell jj-1 of the edge
-      if (e == 0) { jj = ja; lower = false; }
-      else if (e == 1) { jj = ja + 1; lower = true; }
-      else if (e == 2) {                // ghost below the low boundary
-        if (G.per[a] || ja != 0) continue;
-        jj = 0; lower = true;
-        sg = G.dir[a][0] ? T(-1) : T(1);
-      } else {                          // ghost above the high boundary
-        if (G.per[a] || ja != na - 1) continue;
-        jj = na; lower = false;
-        sg = G.dir[a][1] ? T(-1) : T(1);
-      }
-      const int oa = jj - ja;           // 0 or 1
-      const T wa = G.wi[a][jj];
-      const T wJ = lower ? (T(1) - wa) : wa;
-      // U = u_C carried along a (cells jj-1, jj), V = u_a carried along C
-      const T cL = U(C, ax * (oa - 1), ay * (oa - 1), az * (oa - 1));
-      const T cR = U(C, ax * oa, ay * oa, az * oa);
-      const T Uv = (T(1) - wa) * cL + wa * cR;
-      const T aL = U(a, ax * oa - cx, ay * oa - cy, az * oa - cz);
-      const T aR = U(a, ax * oa, ay * oa, az * oa);
+    for (int e = 0; e < 2; ++e) {
+      const T wa = M.mf(a, e).w;
+      // u_C below / above the edge along a, Rbar_C likewise
+      const T cL = e ? u0 : uca, cR = e ? ucb : u0;
+      const T rL = e ? r0 : rca, rR = e ? rcb : r0;
+      const T FbC = rR * (e ? cap.x : ca0.x) - rL * (e ? ca0.x : cam.x);
+      // u_a and Rbar_a on the edge's a-face, C-cells jc-1 and jc
+      const T aL = U(a, ax * e - cx, ay * e - cy, az * e - cz);
+      const T aR = U(a, ax * e, ay * e, az * e);
+      const T Fba = RB(a, ax * e, ay * e, az * e) * ixc_hi -
+                    RB(a, ax * e - cx, ay * e - cy, az * e - cz) * ixc_lo;
       const T V = (T(1) - wc) * aL + wc * aR;
-      // flux adjoints of the C-equation (cells jj-1, jj along a) and of the
-      // a-equation (cells jc-1, jc along C)
-      T FbC = T(0);
-      {
-        int c0 = jj - 1, c1 = jj;
-        if (G.per[a]) {
-          if (c0 < 0) c0 += na;
-          if (c1 >= na) c1 -= na;
-        }
-        if (G.per[a] || jj - 1 >= 0)
-          FbC += -RB(C, ax * (oa - 1), ay * (oa - 1), az * (oa - 1)) / G.dx[a][c0];
-        if (G.per[a] || jj <= na - 1) FbC -= -RB(C, ax * oa, ay * oa, az * oa) / G.dx[a][c1];
-      }
-      T Fba = T(0);
-      {
-        int c0 = jc - 1, c1 = jc;
-        if (G.per[C]) {
-          if (c0 < 0) c0 += nc;
-          if (c1 >= nc) c1 -= nc;
-        }
-        if (G.per[C] || jc - 1 >= 0)
-          Fba += -RB(a, ax * oa - cx, ay * oa - cy, az * oa - cz) / G.dx[C][c0];
-        if (G.per[C] || jc <= nc - 1) Fba -= -RB(a, ax * oa, ay * oa, az * oa) / G.dx[C][c1];
-      }
-      T contrib;
-      if (!upw) {
-        contrib = wJ * V * (FbC + Fba);
+      const T wJ = e ? (T(1) - wa) : wa;      // weight of J in U
+      const T wG = e ? wa : (T(1) - wa);      // weight of J's ghost in U
+      const T sg = e ? sg_hi : sg_lo;
+      if constexpr (!UPW) {
+        cross += V * (wJ * (FbC + Fba) + sg * wG * FbC);
       } else {
-        // C-equation: F_C = V * (V > 0 ? u_C(jj-1) : V < 0 ? u_C(jj) : 0)
-        const bool sel = lower ? (V > T(0)) : (V < T(0));
-        const T partC = sel ? V * FbC : T(0);
-        // a-equation: F_a = U * (U > 0 ? u_a(jc-1) : U < 0 ? u_a(jc) : 0)
+        // F_C = V u_C(upwind of V), F_a = U u_a(upwind of U)
+        const bool selJ = e ? (V > T(0)) : (V < T(0));
+        const bool selG = e ? (V < T(0)) : (V > T(0));
+        const T Uv = (T(1) - wa) * cL + wa * cR;
         const T upa = Uv > T(0) ? aL : (Uv < T(0) ? aR : T(0));
-        contrib = partC + wJ * upa * Fba;
-      }
-      acc += sg * contrib;
-    }
-  }
-  // ---- diffusion (transpose), with ghost preimages
-  const T nu = G.nu;
-#pragma unroll
-  for (int a = 0; a < DIM; ++a) {
-    const int ja = J[a];
-    const int na = (a == C) ? G.ext[C][C] : G.n[a];
-    const int ax = (a == 0), ay = (a == 1), az = (a == 2);
-#pragma unroll
-    for (int o = -1; o <= 1; ++o) {
-      int ia = ja + o;
-      if (G.per[a]) {
-        if (ia < 0) ia += na;
-        if (ia >= na) ia -= na;
-      } else if (ia < 0 || ia >= na) {
-        continue;
-      }
-      const T rb = RB(C, ax * o, ay * o, az * o);
-      if (rb == T(0)) continue;
-      T hp, hm, H;
-      if (a == C) {
-        hp = G.dxe[C][ia + 1];
-        hm = G.dxe[C][ia];
-        H = G.dc[C][ia];
-      } else {
-        hp = G.dc[a][ia + 1];
-        hm = G.dc[a][ia];
-        H = G.dx[a][ia];
-      }
-      T coef;
-      if (o == -1) coef = T(1) / (hp * H);           // J = I + e_a
-      else if (o == 1) coef = T(1) / (hm * H);       // J = I - e_a
-      else coef = -(T(1) / hp + T(1) / hm) / H;
-      acc += nu * rb * coef;
-      // I = J at a bounded tangential boundary reads a ghost made from J
-      if (o == 0 && a != C && !G.per[a]) {
-        if (ia == 0) acc += nu * rb * (G.dir[a][0] ? T(-1) : T(1)) / (hm * H);
-        if (ia == na - 1) acc += nu * rb * (G.dir[a][1] ? T(-1) : T(1)) / (hp * H);
+        cross += (selJ ? V * FbC : T(0)) + wJ * upa * Fba + sg * (selG ? V * FbC : T(0));
       }
     }
+    acc += cross;
+    // cross diffusion, the ghost of J behind a bounded boundary included
+    acc += nu * (rca * cam.y + rcb * cap.z - r0 * (ca0.y + ca0.z) +
+                   r0 * (sg_lo * ca0.z + sg_hi * ca0.y));
   }
   return acc;
 }
 
-// Direct predictor term of an advanced face J and its body-force adjoint:
-// ubar += (1 - eps) ustar_bar - eps fbar / dt,  fbbar += Rbar(J).
-template <int C, int DIM, typename T>
-__device__ __forceinline__ T adj_direct(const AdjCtx<T>& X, const int J[3], int64_t id, T rJ,
-                                        T* __restrict__ fbbar) {
-  const Geo<T>& G = X.G;
-  const bool evolvedJ = G.per[C] || (J[C] >= 1 && J[C] <= G.n[C] - 1);
-  if (!evolvedJ) return T(0);
-  T direct = X.usb[C][id];
-  if constexpr (C < 2) {
-    int li = 0;
-    if (forced_cls<C>(X.ib, J[0], J[1], &li)) direct = -X.ib.f[C][li] / G.dt;
-  }
-  if (fbbar) fbbar[id] += rJ;
-  return direct;
-}
+// The direct predictor term of an advanced face J, (1 - eps) ustar_bar -
+// eps fbar / dt, is the scaled Rbar of J itself (zero on faces that are not
+// advanced); the body-force adjoint takes fbbar += Rbar(J) = dt * that.
 
 // Cell-based transposed momentum stencil with LDS halo planes of u^n and
 // Rbar (same tiling and z-march as the predictor).  Each thread writes the
@@ -643,27 +588,92 @@ struct AdjRings {
   T r[DIM][3][kLY][kLX];
 };
 
+// Scaled Rbar for a halo slot: the same values as rbar, with the index arithmetic
+// done by selects (zero outside a bounded axis and on faces R does not
+// advance).
+template <int C, int DIM, typename T>
+__device__ __forceinline__ T rb_halo(const AdjCtx<T>& X, int i, int j, int k) {
+  const Geo<T>& G = X.G;
+  int I[3] = {i, j, k};
+  bool out = false;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const int e = G.ext[C][a];
+    const bool lo = I[a] < 0, hi = I[a] >= e;
+    const bool per = G.per[a] != 0;
+    I[a] = per ? (lo ? I[a] + e : (hi ? I[a] - e : I[a])) : (lo ? 0 : (hi ? e - 1 : I[a]));
+    out = out || (!per && (lo || hi));
+  }
+  const bool evolved = G.per[C] || (I[C] >= 1 && I[C] <= G.n[C] - 1);
+  T v = X.usb[C][fidx(G.ext[C], I[0], I[1], I[2])];
+  if constexpr (C < 2) {
+    if (X.ib.active) {
+      int li = 0;
+      if (forced_cls<C>(X.ib, I[0], I[1], &li)) v = -X.ib.f[C][li] / G.dt;
+    }
+  }
+  return (out || !evolved) ? T(0) : v;
+}
+
+// Halo slots of one plane in registers (two per thread at most), so the
+// loads of plane k + 3 can be in flight while plane k + 1 is computed.
+template <typename T, int DIM>
+struct AdjRegs {
+  T u[2][DIM], r[2][DIM];
+};
+
 template <int DIM, typename T>
-__device__ __forceinline__ void adj_fill(const AdjCtx<T>& X, AdjRings<T, DIM>& S, int slot,
-                                         int i0, int j0, int kk) {
+__device__ __forceinline__ void adj_load(const AdjCtx<T>& X, AdjRegs<T, DIM>& P, int i0, int j0,
+                                         int kk) {
   const Geo<T>& G = X.G;
 #pragma unroll
-  for (int c = 0; c < DIM; ++c) {
-    for (int s = threadIdx.x; s < kLX * kLY; s += kBlock) {
-      const int sy = s / kLX, sx = s - sy * kLX;
-      const int gi = min(i0 - 1 + sx, G.n[0]), gj = min(j0 - 1 + sy, G.n[1]);
-      S.u[c][slot][sy][sx] = ldu_c<DIM>(X, c, gi, gj, kk);
-      S.r[c][slot][sy][sx] = rbar_c<DIM>(X, c, gi, gj, kk);
+  for (int h = 0; h < 2; ++h) {
+    const int s = threadIdx.x + h * kBlock;
+    if (s >= kLX * kLY) break;
+    const int sy = s / kLX, sx = s - sy * kLX;
+    const int gi = min(i0 - 1 + sx, G.n[0]), gj = min(j0 - 1 + sy, G.n[1]);
+    bool out;
+    P.u[h][0] = ld_halo<0, DIM>(G, X.u[0], gi, gj, kk, &out);
+    P.r[h][0] = rb_halo<0, DIM>(X, gi, gj, kk);
+    P.u[h][1] = ld_halo<1, DIM>(G, X.u[1], gi, gj, kk, &out);
+    P.r[h][1] = rb_halo<1, DIM>(X, gi, gj, kk);
+    if constexpr (DIM == 3) {
+      P.u[h][2] = ld_halo<2, DIM>(G, X.u[2], gi, gj, kk, &out);
+      P.r[h][2] = rb_halo<2, DIM>(X, gi, gj, kk);
     }
   }
 }
 
-template <typename T, int DIM>
+template <int DIM, typename T>
+__device__ __forceinline__ void adj_store(AdjRings<T, DIM>& S, int slot, const AdjRegs<T, DIM>& P) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int s = threadIdx.x + h * kBlock;
+    if (s >= kLX * kLY) break;
+    const int sy = s / kLX, sx = s - sy * kLX;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      S.u[c][slot][sy][sx] = P.u[h][c];
+      S.r[c][slot][sy][sx] = P.r[h][c];
+    }
+  }
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ void adj_fill(const AdjCtx<T>& X, AdjRings<T, DIM>& S, int slot,
+                                         int i0, int j0, int kk) {
+  AdjRegs<T, DIM> P;
+  adj_load<DIM>(X, P, i0, j0, kk);
+  adj_store<DIM>(S, slot, P);
+}
+
+template <typename T, int DIM, bool UPW>
 __global__ void __launch_bounds__(kBlock)
 k_adj_momentum_lds(AdjCtx<T> X, int ntx, int nty, int nzc, T* __restrict__ ub0,
                    T* __restrict__ ub1, T* __restrict__ ub2, T* __restrict__ fb0,
                    T* __restrict__ fb1, T* __restrict__ fb2) {
   __shared__ AdjRings<T, DIM> S;
+  __shared__ TileMet<T> TM;
   const Geo<T>& G = X.G;
   T* ubar[3] = {ub0, ub1, ub2};
   T* fbb[3] = {fb0, fb1, fb2};
@@ -671,15 +681,20 @@ k_adj_momentum_lds(AdjCtx<T> X, int ntx, int nty, int nzc, T* __restrict__ ub0,
   if (b >= ntx * nty * nzc) return;
   const int tx = b % ntx, ty = (b / ntx) % nty, zc = b / (ntx * nty);
   const int i0 = tx * kTileX, j0 = ty * kTileY;
-  const int lx = threadIdx.x & (kTileX - 1), ly = threadIdx.x / kTileX;
+  // one wavefront per tile row: ly (and so j) is uniform across the wave
+  const int lx = threadIdx.x & (kTileX - 1);
+  const int ly = __builtin_amdgcn_readfirstlane(threadIdx.x / kTileX);
   const int i = i0 + lx, j = j0 + ly;
   const int k0 = (DIM == 3) ? zc * kZChunk : 0;
   const int k1 = (DIM == 3) ? min(k0 + kZChunk, G.n[2]) : 1;
   const bool inside = i < G.n[0] && j < G.n[1];
+  load_tile_met<DIM>(G, TM, i0, j0, k0);
+  AdjRegs<T, DIM> nxt;
   if (DIM == 3) {
     adj_fill<DIM>(X, S, ring_slot(k0 - 1), i0, j0, k0 - 1);
     adj_fill<DIM>(X, S, ring_slot(k0), i0, j0, k0);
     adj_fill<DIM>(X, S, ring_slot(k0 + 1), i0, j0, k0 + 1);
+    if (k0 + 1 < k1) adj_load<DIM>(X, nxt, i0, j0, k0 + 2);
   } else {
     adj_fill<DIM>(X, S, 0, i0, j0, 0);
   }
@@ -698,12 +713,21 @@ k_adj_momentum_lds(AdjCtx<T> X, int ntx, int nty, int nzc, T* __restrict__ ub0,
         return S.r[c][sl][ly + 1 + dj][lx + 1 + di];
       };
       const int J[3] = {i, j, k};
+      const MetLds<T> M{&TM, {lx + 1, ly + 1, k - k0 + 1}};
+      // body-force adjoint of the three faces first: its loads overlap the
+      // gathers
+      int64_t id[3];
+      T fbo[3] = {T(0), T(0), T(0)};
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        id[c] = fidx(G.ext[c], i, j, k);
+        if (fbb[c]) fbo[c] = fbb[c][id[c]];
+      }
 #define FVIB_ADJ_COMP(CC)                                                           \
       if (CC < DIM) {                                                               \
-        const int64_t id = fidx(G.ext[CC], i, j, k);                                \
-        T acc = adj_gather<CC, DIM, T>(G, Rl, Ul, J);                               \
-        acc += adj_direct<CC, DIM, T>(X, J, id, Rl(CC, 0, 0, 0), fbb[CC]);          \
-        ubar[CC][id] = acc;                                                         \
+        const T rJ = Rl(CC, 0, 0, 0);                                               \
+        ubar[CC][id[CC]] = G.dt * adj_gather<CC, DIM, UPW, T>(G, Rl, Ul, M, J) + rJ; \
+        if (fbb[CC]) fbb[CC][id[CC]] = fbo[CC] + G.dt * rJ;                         \
       }
       FVIB_ADJ_COMP(0)
       FVIB_ADJ_COMP(1)
@@ -712,13 +736,14 @@ k_adj_momentum_lds(AdjCtx<T> X, int ntx, int nty, int nzc, T* __restrict__ ub0,
     }
     if (DIM == 3 && k + 1 < k1) {
       __syncthreads();
-      adj_fill<DIM>(X, S, sm, i0, j0, k + 2);
+      adj_store<DIM>(S, sm, nxt);                     // slot of plane k-1 takes k+2
+      if (k + 2 < k1) adj_load<DIM>(X, nxt, i0, j0, k + 3);
     }
   }
 }
 
 // Faces on the high boundary of a bounded own axis (face index n[C]).
-template <int C, int DIM, typename T>
+template <int C, int DIM, bool UPW, typename T>
 __global__ void __launch_bounds__(kBlock)
 k_adj_momentum_plane(AdjCtx<T> X, T* __restrict__ ubar) {
   const Geo<T>& G = X.G;
@@ -740,7 +765,8 @@ k_adj_momentum_plane(AdjCtx<T> X, T* __restrict__ ubar) {
     auto Rg = [&](int c, int di, int dj, int dk) -> T {
       return rbar_c<DIM>(X, c, J[0] + di, J[1] + dj, J[2] + dk);
     };
-    ubar[fidx(G.ext[C], J[0], J[1], J[2])] = adj_gather<C, DIM, T>(G, Rg, Ug, J);
+    const MetGlobal<T> M{&G, {J[0], J[1], J[2]}};
+    ubar[fidx(G.ext[C], J[0], J[1], J[2])] = G.dt * adj_gather<C, DIM, UPW, T>(G, Rg, Ug, M, J);
   }
 }
 
@@ -770,6 +796,7 @@ int launch_adj_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const ub[3],
     hipLaunchKernelGGL((k_adj_rhs<T, 3>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, ub[0],
                        ub[1], ub[2], y, red, sc);
   FVIB_HIP(hipGetLastError());
+  FVIB_HIP((launch_finish<2, 1>(red.partial, tl.nblocks, sc, FinAdjRhs{P.inv_ncell}, s)));
   return FVIB_OK;
 }
 
@@ -817,12 +844,16 @@ int launch_adj_outflow(const Geo<T>& G, const Planes& PL, int mode, T* usb[3], T
     hipLaunchKernelGGL((k_adj_outflow_sum<T>), dim3(nb), dim3(kBlock), 0, s, G, PL, usb[0], usb[1],
                        usb[2], red, sc);
     FVIB_HIP(hipGetLastError());
+    FVIB_HIP((launch_finish<1, 1>(red.partial, nb, sc, FinAdjOutflow{PL.area_out}, s)));
   }
   hipLaunchKernelGGL((k_adj_outflow_apply<T>), dim3(nb), dim3(kBlock), 0, s, G, PL, mode, usb[0],
                      usb[1], usb[2], ubar[0], ubar[1], ubar[2], (const SolverScalars*)sc);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
+
+template <bool UPW, typename T>
+static int launch_adj_momentum_t(const AdjCtx<T>& X, T* ubar[3], T* fbbar[3], hipStream_t s);
 
 template <typename T>
 int launch_adj_momentum(const Geo<T>& G, const T* const u[3], const T* const usb[3],
@@ -834,17 +865,24 @@ int launch_adj_momentum(const Geo<T>& G, const T* const u[3], const T* const usb
     X.usb[c] = usb[c];
   }
   X.ib = ib;
+  if (G.upwind) return launch_adj_momentum_t<true>(X, ubar, fbbar, s);
+  return launch_adj_momentum_t<false>(X, ubar, fbbar, s);
+}
+
+template <bool UPW, typename T>
+static int launch_adj_momentum_t(const AdjCtx<T>& X, T* ubar[3], T* fbbar[3], hipStream_t s) {
+  const Geo<T>& G = X.G;
   const int ntx = (G.n[0] + kTileX - 1) / kTileX;
   const int nty = (G.n[1] + kTileY - 1) / kTileY;
   const int nzc = (G.dim == 3) ? (G.n[2] + kZChunk - 1) / kZChunk : 1;
   int nb = ntx * nty * nzc;
   nb = (nb + kXcds - 1) / kXcds * kXcds;
   if (G.dim == 2)
-    hipLaunchKernelGGL((k_adj_momentum_lds<T, 2>), dim3(nb), dim3(kBlock), 0, s, X, ntx, nty, nzc,
-                       ubar[0], ubar[1], ubar[2], fbbar[0], fbbar[1], fbbar[2]);
+    hipLaunchKernelGGL((k_adj_momentum_lds<T, 2, UPW>), dim3(nb), dim3(kBlock), 0, s, X, ntx, nty,
+                       nzc, ubar[0], ubar[1], ubar[2], fbbar[0], fbbar[1], fbbar[2]);
   else
-    hipLaunchKernelGGL((k_adj_momentum_lds<T, 3>), dim3(nb), dim3(kBlock), 0, s, X, ntx, nty, nzc,
-                       ubar[0], ubar[1], ubar[2], fbbar[0], fbbar[1], fbbar[2]);
+    hipLaunchKernelGGL((k_adj_momentum_lds<T, 3, UPW>), dim3(nb), dim3(kBlock), 0, s, X, ntx, nty,
+                       nzc, ubar[0], ubar[1], ubar[2], fbbar[0], fbbar[1], fbbar[2]);
   FVIB_HIP(hipGetLastError());
   for (int c = 0; c < G.dim; ++c) {
     if (G.per[c]) continue;
@@ -853,12 +891,12 @@ int launch_adj_momentum(const Geo<T>& G, const T* const u[3], const T* const usb
       if (a != c) count *= G.n[a];
     const dim3 gr(nblk(count)), bl(kBlock);
     if (G.dim == 2) {
-      if (c == 0) hipLaunchKernelGGL((k_adj_momentum_plane<0, 2, T>), gr, bl, 0, s, X, ubar[0]);
-      else hipLaunchKernelGGL((k_adj_momentum_plane<1, 2, T>), gr, bl, 0, s, X, ubar[1]);
+      if (c == 0) hipLaunchKernelGGL((k_adj_momentum_plane<0, 2, UPW, T>), gr, bl, 0, s, X, ubar[0]);
+      else hipLaunchKernelGGL((k_adj_momentum_plane<1, 2, UPW, T>), gr, bl, 0, s, X, ubar[1]);
     } else {
-      if (c == 0) hipLaunchKernelGGL((k_adj_momentum_plane<0, 3, T>), gr, bl, 0, s, X, ubar[0]);
-      else if (c == 1) hipLaunchKernelGGL((k_adj_momentum_plane<1, 3, T>), gr, bl, 0, s, X, ubar[1]);
-      else hipLaunchKernelGGL((k_adj_momentum_plane<2, 3, T>), gr, bl, 0, s, X, ubar[2]);
+      if (c == 0) hipLaunchKernelGGL((k_adj_momentum_plane<0, 3, UPW, T>), gr, bl, 0, s, X, ubar[0]);
+      else if (c == 1) hipLaunchKernelGGL((k_adj_momentum_plane<1, 3, UPW, T>), gr, bl, 0, s, X, ubar[1]);
+      else hipLaunchKernelGGL((k_adj_momentum_plane<2, 3, UPW, T>), gr, bl, 0, s, X, ubar[2]);
     }
     FVIB_HIP(hipGetLastError());
   }

@@ -63,7 +63,8 @@ constexpr int BKc = 16;  // contraction chunk
 template <typename V, bool XFAST, bool DIV>
 __global__ void __launch_bounds__(kBlock)
 k_axis_gemm(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A, int K,
-            int inner, int64_t ncols, FdmDiv dv) {
+            int inner, int64_t ncols, FdmDiv dv, const int* stop) {
+  if (stop && *stop) return;
   __shared__ V As[BKc][BM + 1];
   __shared__ V Bs[BKc][BN + 1];
   typedef typename Mfma<V>::acc_t acc_t;
@@ -174,10 +175,184 @@ k_axis_gemm(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A,
   }
 }
 
+// Register-blocked variant for axes of at most 256 cells with K % 4 == 0
+// (every axis of the production grids).  A block owns 16 NT grid lines and
+// produces all K modes for them, so X is read from HBM once; wave w owns
+// the 16-row tiles w, w + 4, ... of the operator.  Both operands go straight
+// from L1/L2 into registers: within a batch of 16 contraction indices, lane
+// group q holds indices 4q .. 4q + 3 (contiguous in a row of A, and in a
+// line of X when the axis is the fast one) and MFMA step s contracts index
+// 4q + s, so each operand needs one vector load per batch.  The next batch
+// is loaded while the current one is multiplied.
+template <typename V>
+struct Quad {
+  V v[4];
+};
+
+template <typename V, bool CONTIG>
+__device__ __forceinline__ Quad<V> ld_quad(const V* p, int64_t stride) {
+  Quad<V> r;
+  if constexpr (CONTIG) {
+    if constexpr (sizeof(V) == 4) {
+      const float4 t = *reinterpret_cast<const float4*>(p);
+      r.v[0] = t.x; r.v[1] = t.y; r.v[2] = t.z; r.v[3] = t.w;
+    } else {
+      const double2 t0 = *reinterpret_cast<const double2*>(p);
+      const double2 t1 = *reinterpret_cast<const double2*>(p + 2);
+      r.v[0] = t0.x; r.v[1] = t0.y; r.v[2] = t1.x; r.v[3] = t1.y;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) r.v[j] = p[j * stride];
+  }
+  return r;
+}
+
+template <typename V, bool XFAST, bool DIV, int MT, int NT>
+__global__ void __launch_bounds__(kBlock)
+k_axis_mfma(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A, int K,
+            int inner, int64_t ncols, FdmDiv dv, const int* stop) {
+  if (stop && *stop) return;
+  typedef typename Mfma<V>::acc_t acc_t;
+  // quads per batch: 2 (32 contraction indices) in float, 1 in double
+  constexpr int QB = sizeof(V) == 4 ? 2 : 1;
+  constexpr int KB = 16 * QB;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int q = lane >> 4, r = lane & 15;
+  const int ntr = (K + 15) >> 4;
+  const int64_t n0 = (int64_t)blockIdx.x * (16 * NT);
+  const V* ap[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    int m = 16 * (w + 4 * mt) + r;
+    if (m >= K) m = K - 1;                  // rows past K are computed, never stored
+    ap[mt] = A + (int64_t)m * K + 4 * q;
+  }
+  const V* xp[NT];
+  int64_t base[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    int64_t n = n0 + 16 * t + r;
+    if (n >= ncols) n = ncols - 1;          // lines past ncols likewise
+    if (XFAST) {
+      base[t] = n * (int64_t)K;
+      xp[t] = X + base[t] + 4 * q;
+    } else {
+      const int64_t o = n / inner, i = n - o * inner;
+      base[t] = o * (int64_t)K * inner + i;
+      xp[t] = X + base[t] + (int64_t)(4 * q) * inner;
+    }
+  }
+  acc_t acc[MT][NT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[mt][t] = acc_t{0, 0, 0, 0};
+  Quad<V> a_c[QB][MT], b_c[QB][NT], a_n[QB][MT], b_n[QB][NT];
+  auto load = [&](int kb, Quad<V> (*a)[MT], Quad<V> (*b)[NT]) {
+#pragma unroll
+    for (int j = 0; j < QB; ++j) {
+      // K % 4 == 0: a quad is all inside or all past K; past K the load is
+      // redirected to the quad at k = 0 of the same line and zeroed
+      const int k = kb + 16 * j;
+      const bool ok = k + 4 * q < K;
+      const int ka = ok ? k : -4 * q;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        a[j][mt] = ld_quad<V, true>(ap[mt] + ka, 1);
+        if (!ok) a[j][mt] = Quad<V>{{V(0), V(0), V(0), V(0)}};
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        b[j][t] = ld_quad<V, XFAST>(xp[t] + (XFAST ? ka : (int64_t)ka * inner), inner);
+        if (!ok) b[j][t] = Quad<V>{{V(0), V(0), V(0), V(0)}};
+      }
+    }
+  };
+  load(0, a_c, b_c);
+  for (int kb = 0; kb < K; kb += KB) {
+    if (kb + KB < K) load(kb + KB, a_n, b_n);
+#pragma unroll
+    for (int j = 0; j < QB; ++j)
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          if (w + 4 * mt >= ntr) continue;  // wave-uniform: no such row tile
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            acc[mt][t] = Mfma<V>::op(a_c[j][mt].v[s], b_c[j][t].v[s], acc[mt][t]);
+        }
+#pragma unroll
+    for (int j = 0; j < QB; ++j) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) a_c[j][mt] = a_n[j][mt];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) b_c[j][t] = b_n[j][t];
+    }
+  }
+  // epilogue: lane holds D[Mfma<V>::row(lane, v)][col r] of each tile
+  double lrest[NT];
+  if (DIV) {
+    // eigenvalue sum of the faster axes' modes of each line (decoded from i)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int64_t n = n0 + 16 * t + r;
+      int64_t rem = XFAST ? 0 : (n % inner);
+      double ls = 0.0;
+      int allz = 1;
+      for (int b = 0; b < dv.axis; ++b) {
+        const int mb = (int)(rem % dv.n[b]);
+        rem /= dv.n[b];
+        ls += dv.lam[b][mb];
+        allz &= (mb == 0);
+      }
+      lrest[t] = allz ? -1.0 : ls;          // -1 marks the lines of the zero mode
+    }
+  }
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    if (w + 4 * mt >= ntr) continue;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int64_t n = n0 + 16 * t + r;
+      if (n >= ncols) continue;
+      const int mrow0 = 16 * (w + 4 * mt);
+      if constexpr (XFAST && !DIV && sizeof(V) == 4) {
+        // float layout: this lane's four values are rows 4q .. 4q + 3 of
+        // one line, contiguous along the fast axis (K % 4 == 0)
+        const int m = mrow0 + 4 * q;
+        if (m < K) {
+          const acc_t& c = acc[mt][t];
+          *reinterpret_cast<float4*>(Y + base[t] + m) = make_float4(c[0], c[1], c[2], c[3]);
+        }
+        continue;
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = mrow0 + Mfma<V>::row(lane, v);
+        if (m >= K) continue;
+        V val = acc[mt][t][v];
+        if (DIV) {
+          const bool zero = (lrest[t] < 0.0) && m == 0;
+          const double ls = (lrest[t] < 0.0 ? 0.0 : lrest[t]) + dv.lam[dv.axis][m];
+          val = zero ? V(0) : (V)((double)val / ls);
+        }
+        if (XFAST)
+          Y[base[t] + m] = val;
+        else
+          Y[base[t] + (int64_t)m * inner] = val;
+      }
+    }
+  }
+}
+
 // p += d (refinement correction, double accumulator)
 template <typename V>
 __global__ void __launch_bounds__(kBlock)
-k_add_correction(int64_t n, double* __restrict__ p, const V* __restrict__ d) {
+k_add_correction(int64_t n, double* __restrict__ p, const V* __restrict__ d, const int* stop) {
+  if (stop && *stop) return;
   for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < n;
        c += (int64_t)gridDim.x * kBlock)
     p[c] += (double)d[c];
@@ -194,7 +369,8 @@ k_gauge(int64_t n, double* __restrict__ p, const SolverScalars* sc, double inv_n
 
 // ------------------------------------------------------------- launchers
 template <typename V>
-int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, hipStream_t s) {
+int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, const int* stop,
+                    hipStream_t s) {
   const int K = F.n[a];
   int inner = 1;
   for (int b = 0; b < a; ++b) inner *= F.n[b];
@@ -202,27 +378,51 @@ int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, h
   for (int b = a + 1; b < 3; ++b) outer *= F.n[b];
   const int64_t ncols = outer * inner;
   const V* Am = fwd ? F.phiT[a] : F.phi[a];
-  dim3 grid((K + BM - 1) / BM, (unsigned)((ncols + BN - 1) / BN));
   const bool div = fwd && a == F.dim - 1;
+  if (K % 4 == 0 && K <= 256) {
+    constexpr int NT = 2;
+    const dim3 g((unsigned)((ncols + 16 * NT - 1) / (16 * NT)));
+    const int mt = (K + 63) / 64;
+#define FVIB_AX(XF, DV, MT)                                                                     \
+    hipLaunchKernelGGL((k_axis_mfma<V, XF, DV, MT, NT>), g, dim3(kBlock), 0, s, in, out, Am, K, \
+                       inner, ncols, F.div, stop)
+#define FVIB_AXM(XF, DV)                                                                        \
+    switch (mt) {                                                                               \
+      case 1: FVIB_AX(XF, DV, 1); break;                                                        \
+      case 2: FVIB_AX(XF, DV, 2); break;                                                        \
+      case 3: FVIB_AX(XF, DV, 3); break;                                                        \
+      default: FVIB_AX(XF, DV, 4); break;                                                       \
+    }
+    if (inner == 1) {
+      if (div) { FVIB_AXM(true, true) } else { FVIB_AXM(true, false) }
+    } else {
+      if (div) { FVIB_AXM(false, true) } else { FVIB_AXM(false, false) }
+    }
+#undef FVIB_AXM
+#undef FVIB_AX
+    FVIB_HIP(hipGetLastError());
+    return FVIB_OK;
+  }
+  dim3 grid((K + BM - 1) / BM, (unsigned)((ncols + BN - 1) / BN));
   if (inner == 1) {
     if (div)
-      hipLaunchKernelGGL((k_axis_gemm<V, true, true>), grid, dim3(kBlock), 0, s, in, out, Am, K, inner, ncols, F.div);
+      hipLaunchKernelGGL((k_axis_gemm<V, true, true>), grid, dim3(kBlock), 0, s, in, out, Am, K, inner, ncols, F.div, stop);
     else
-      hipLaunchKernelGGL((k_axis_gemm<V, true, false>), grid, dim3(kBlock), 0, s, in, out, Am, K, inner, ncols, F.div);
+      hipLaunchKernelGGL((k_axis_gemm<V, true, false>), grid, dim3(kBlock), 0, s, in, out, Am, K, inner, ncols, F.div, stop);
   } else {
     if (div)
-      hipLaunchKernelGGL((k_axis_gemm<V, false, true>), grid, dim3(kBlock), 0, s, in, out, Am, K, inner, ncols, F.div);
+      hipLaunchKernelGGL((k_axis_gemm<V, false, true>), grid, dim3(kBlock), 0, s, in, out, Am, K, inner, ncols, F.div, stop);
     else
-      hipLaunchKernelGGL((k_axis_gemm<V, false, false>), grid, dim3(kBlock), 0, s, in, out, Am, K, inner, ncols, F.div);
+      hipLaunchKernelGGL((k_axis_gemm<V, false, false>), grid, dim3(kBlock), 0, s, in, out, Am, K, inner, ncols, F.div, stop);
   }
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
 
 template <typename V>
-int launch_add_correction(int64_t n, double* p, const V* d, hipStream_t s) {
+int launch_add_correction(int64_t n, double* p, const V* d, const int* stop, hipStream_t s) {
   int nb = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 8 * kMaxRedBlocks);
-  hipLaunchKernelGGL((k_add_correction<V>), dim3(nb), dim3(kBlock), 0, s, n, p, d);
+  hipLaunchKernelGGL((k_add_correction<V>), dim3(nb), dim3(kBlock), 0, s, n, p, d, stop);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
@@ -234,10 +434,13 @@ int launch_gauge(int64_t n, double* p, const SolverScalars* sc, hipStream_t s) {
   return FVIB_OK;
 }
 
-template int launch_fdm_axis<float>(const FdmPlan<float>&, int, bool, const float*, float*, hipStream_t);
-template int launch_fdm_axis<double>(const FdmPlan<double>&, int, bool, const double*, double*, hipStream_t);
-template int launch_add_correction<float>(int64_t, double*, const float*, hipStream_t);
-template int launch_add_correction<double>(int64_t, double*, const double*, hipStream_t);
+template int launch_fdm_axis<float>(const FdmPlan<float>&, int, bool, const float*, float*,
+                                    const int*, hipStream_t);
+template int launch_fdm_axis<double>(const FdmPlan<double>&, int, bool, const double*, double*,
+                                     const int*, hipStream_t);
+template int launch_add_correction<float>(int64_t, double*, const float*, const int*, hipStream_t);
+template int launch_add_correction<double>(int64_t, double*, const double*, const int*,
+                                           hipStream_t);
 
 // ============================================================ host setup
 // Symmetric eigen-decomposition by cyclic Jacobi rotations (stretched axes).

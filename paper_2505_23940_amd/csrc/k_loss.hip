@@ -1,6 +1,8 @@
 // Scalar losses used to seed the adjoint: mean wall shear stress of a
 // wall-bounded flow and the root-mean-square lift coefficient of a force
 // history.  Each writes J and, optionally, its gradient.
+#include <algorithm>
+
 #include "fvib_kernels.h"
 
 namespace fvib {
@@ -10,10 +12,11 @@ namespace fvib {
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_wall_shear(int nx, int ny, int nz, const T* __restrict__ u, T* __restrict__ ubar, double wlo,
-             double whi, double* J) {
+             double whi, double* partial) {
   const int64_t plane = (int64_t)nx * nz;
   double s[2] = {0.0, 0.0};
-  for (int64_t r = threadIdx.x; r < plane; r += kBlock) {
+  for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < plane;
+       r += (int64_t)gridDim.x * kBlock) {
     const int i = (int)(r % nx), k = (int)(r / nx);
     const int64_t lo = ((int64_t)k * ny + 0) * nx + i;
     const int64_t hi = ((int64_t)k * ny + (ny - 1)) * nx + i;
@@ -24,9 +27,17 @@ k_wall_shear(int nx, int ny, int nz, const T* __restrict__ u, T* __restrict__ ub
       ubar[hi] = (T)((double)ubar[hi] + whi / (double)plane);
     }
   }
-  block_sum<2>(s);
-  if (threadIdx.x == 0) *J = wlo * s[0] / (double)plane + whi * s[1] / (double)plane;
+  block_partials<2, 2>(s, partial);
 }
+
+struct FinWallShear {
+  double wlo, whi, plane;
+  double* J;
+  __device__ bool skip(const SolverScalars*) const { return false; }
+  __device__ void apply(const double* t, SolverScalars*) const {
+    *J = wlo * t[0] / plane + whi * t[1] / plane;
+  }
+};
 
 // J = sqrt(mean_n C_L^2), C_L = 2 F_y / (rho U^2 D); dJ/dF_y(n) = C_L(n) g / (S J)
 // with g = 2 / (rho U^2 D).
@@ -50,10 +61,14 @@ k_rms_lift(const double* __restrict__ Fh, int S, int stride, int off, double g, 
 
 template <typename T>
 int launch_wall_shear(int nx, int ny, int nz, const T* u, T* ubar, double wlo, double whi,
-                      double* J, hipStream_t s) {
-  hipLaunchKernelGGL((k_wall_shear<T>), dim3(1), dim3(kBlock), 0, s, nx, ny, nz, u, ubar, wlo,
-                     whi, J);
+                      double* J, double* partial, hipStream_t s) {
+  const int64_t plane = (int64_t)nx * nz;
+  int nb = (int)std::min<int64_t>((plane + kBlock - 1) / kBlock, kMaxRedBlocks);
+  hipLaunchKernelGGL((k_wall_shear<T>), dim3(nb), dim3(kBlock), 0, s, nx, ny, nz, u, ubar, wlo,
+                     whi, partial);
   FVIB_HIP(hipGetLastError());
+  FVIB_HIP((launch_finish<2, 2>(partial, nb, nullptr,
+                                FinWallShear{wlo, whi, (double)plane, J}, s)));
   return FVIB_OK;
 }
 
@@ -65,8 +80,8 @@ int launch_rms_lift(const double* Fh, int S, int stride, int off, double g, doub
 }
 
 template int launch_wall_shear<float>(int, int, int, const float*, float*, double, double,
-                                      double*, hipStream_t);
+                                      double*, double*, hipStream_t);
 template int launch_wall_shear<double>(int, int, int, const double*, double*, double, double,
-                                       double*, hipStream_t);
+                                       double*, double*, hipStream_t);
 
 }  // namespace fvib

@@ -20,15 +20,13 @@ namespace fvib {
 // R of component C at face (i, j, k).  `L(c, di, dj, dk)` returns component
 // c at the offset (di, dj, dk) from (i, j, k), boundary rules applied (each
 // offset is -1, 0 or +1 per axis).
-template <int C, int DIM, typename T, typename Load>
-__device__ __forceinline__ T momentum_rhs(const Geo<T>& G, const Load& L, const T* fbC, int i,
-                                          int j, int k) {
-  const int I[3] = {i, j, k};
+template <int C, int DIM, typename T, typename Load, typename ML>
+__device__ __forceinline__ T momentum_rhs(const Geo<T>& G, const Load& L, const ML& M, T fb) {
   const T q0 = L(C, 0, 0, 0);
-  const int ic = I[C];
-  T conv = T(0);
-  T visc = T(0);
-  // convection along the own axis: fluxes at the two adjacent cell centres
+  const Met4<T> fc = M.mf(C, 0);
+  T conv, visc;
+  // along the own axis: convective fluxes at the two adjacent cell centres
+  // and the own-axis diffusion
   {
     const T qm = L(C, C == 0 ? -1 : 0, C == 1 ? -1 : 0, C == 2 ? -1 : 0);
     const T qp = L(C, C == 0 ? 1 : 0, C == 1 ? 1 : 0, C == 2 ? 1 : 0);
@@ -42,15 +40,17 @@ __device__ __forceinline__ T momentum_rhs(const Geo<T>& G, const Load& L, const 
       Flo = Qlo * Qlo;
       Fhi = Qhi * Qhi;
     }
-    conv = (Fhi - Flo) / G.dc[C][ic];
+    conv = (Fhi - Flo) * fc.x;
+    visc = (qp - q0) * fc.y - (q0 - qm) * fc.z;
   }
-  // convection across the other axes: edge fluxes at a-faces ia and ia + 1
+  // across the other axes: edge fluxes at a-faces ia and ia + 1, and the
+  // cross diffusion
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     if (a == C) continue;
-    const int ia = I[a];
     const int ex = (a == 0), ey = (a == 1), ez = (a == 2);
     const int cx = (C == 0), cy = (C == 1), cz = (C == 2);
+    const Met4<T> ca = M.mc(a, 0);
     const T cm = L(C, -ex, -ey, -ez);
     const T cp = L(C, ex, ey, ez);
     // component a at (a-face ia, own cells ic-1, ic) and at a-face ia + 1
@@ -58,7 +58,7 @@ __device__ __forceinline__ T momentum_rhs(const Geo<T>& G, const Load& L, const 
     const T a01 = L(a, 0, 0, 0);
     const T a10 = L(a, ex - cx, ey - cy, ez - cz);
     const T a11 = L(a, ex, ey, ez);
-    const T wc = G.wi[C][ic];
+    const T wc = fc.w;
     const T V0 = (T(1) - wc) * a00 + wc * a01;
     const T V1 = (T(1) - wc) * a10 + wc * a11;
     T F0, F1;
@@ -66,28 +66,15 @@ __device__ __forceinline__ T momentum_rhs(const Geo<T>& G, const Load& L, const 
       F0 = V0 * (V0 > T(0) ? cm : (V0 < T(0) ? q0 : T(0)));
       F1 = V1 * (V1 > T(0) ? q0 : (V1 < T(0) ? cp : T(0)));
     } else {
-      const T w0 = G.wi[a][ia], w1 = G.wi[a][ia + 1];
+      const T w0 = M.mf(a, 0).w, w1 = M.mf(a, 1).w;
       const T U0 = (T(1) - w0) * cm + w0 * q0;
       const T U1 = (T(1) - w1) * q0 + w1 * cp;
       F0 = U0 * V0;
       F1 = U1 * V1;
     }
-    conv += (F1 - F0) / G.dx[a][ia];
+    conv += (F1 - F0) * ca.x;
+    visc += (cp - q0) * ca.y - (q0 - cm) * ca.z;
   }
-  // diffusion, summed over the axes in order
-#pragma unroll
-  for (int a = 0; a < DIM; ++a) {
-    const int ex = (a == 0), ey = (a == 1), ez = (a == 2);
-    const T cm = L(C, -ex, -ey, -ez);
-    const T cp = L(C, ex, ey, ez);
-    const int ia = I[a];
-    if (a == C) {
-      visc += ((cp - q0) / G.dxe[C][ia + 1] - (q0 - cm) / G.dxe[C][ia]) / G.dc[C][ia];
-    } else {
-      visc += ((cp - q0) / G.dc[a][ia + 1] - (q0 - cm) / G.dc[a][ia]) / G.dx[a][ia];
-    }
-  }
-  const T fb = fbC ? fbC[fidx(G.ext[C], i, j, k)] : T(0);
   return -conv + G.nu * visc + fb;
 }
 
@@ -112,11 +99,11 @@ __device__ __forceinline__ int forced(const IbView<T>& ib, int i, int j, int* li
 // Predictor (MODE 0) or right-hand side (MODE 1) of component C at face
 // (i, j, k):  u* = u + dt (R + f),  f = eps [ -R + (u_s - u) / dt ], i.e.
 // u* = u + dt R off the body and u* = u_s on forced faces.
-template <int C, int DIM, int MODE, typename T, typename Load>
-__device__ __forceinline__ void predict_face(const Geo<T>& G, const Load& L, const T* fb, T* out,
-                                             const IbView<T>& ib, int i, int j, int k) {
+template <int C, int DIM, int MODE, typename T, typename Load, typename ML>
+__device__ __forceinline__ void predict_face(const Geo<T>& G, const Load& L, const ML& M, T fbv,
+                                             T* out, const IbView<T>& ib, int i, int j, int k) {
   if (C >= DIM || !evolved<C>(G, i, j, k)) return;
-  const T R = momentum_rhs<C, DIM, T>(G, L, fb, i, j, k);
+  const T R = momentum_rhs<C, DIM, T>(G, L, M, fbv);
   const int64_t id = fidx(G.ext[C], i, j, k);
   if (MODE == 1) {
     out[id] = R;
@@ -141,26 +128,55 @@ __device__ __forceinline__ void predict_face(const Geo<T>& G, const Load& L, con
 // through a chunk of z-planes, keeping planes k-1, k, k+1 of every
 // component (with a one-cell halo, boundary rules applied when the halo is
 // filled) in a three-slot ring.  Each value is loaded once per plane
-// instead of once per use.
+// instead of once per use.  The tile's stencil coefficients sit in LDS
+// as well.  A plane is brought in two halves: load_plane issues the global loads of
+// this thread's (at most two) halo slots into registers, store_plane puts
+// them into a ring slot.  The z-march loads plane k + 3 while plane k + 1
+// is computed, so the load latency hides behind the stencil arithmetic.
+template <typename T, int DIM>
+struct PlaneRegs {
+  T v[2][DIM];
+};
+
+template <int DIM, typename T>
+__device__ __forceinline__ void load_plane(const Geo<T>& G, const T* const* u, PlaneRegs<T, DIM>& P,
+                                           int i0, int j0, int kk) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int s = threadIdx.x + h * kBlock;
+    if (s >= kLX * kLY) break;
+    const int sy = s / kLX, sx = s - sy * kLX;
+    // halo slots past a ragged tile edge are clamped to one step outside
+    // the domain (their values are never used), so every load stays in
+    // bounds however small the axis
+    const int gi = min(i0 - 1 + sx, G.n[0]), gj = min(j0 - 1 + sy, G.n[1]);
+    bool out;
+    P.v[h][0] = ld_halo<0, DIM>(G, u[0], gi, gj, kk, &out);
+    P.v[h][1] = ld_halo<1, DIM>(G, u[1], gi, gj, kk, &out);
+    if constexpr (DIM == 3) P.v[h][2] = ld_halo<2, DIM>(G, u[2], gi, gj, kk, &out);
+  }
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ void store_plane(PlaneRing<T, DIM>& R, int slot,
+                                            const PlaneRegs<T, DIM>& P) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int s = threadIdx.x + h * kBlock;
+    if (s >= kLX * kLY) break;
+    const int sy = s / kLX, sx = s - sy * kLX;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) R.v[c][slot][sy][sx] = P.v[h][c];
+  }
+}
+
 template <int DIM, typename T>
 __device__ __forceinline__ void fill_plane(const Geo<T>& G, const T* const* u,
                                            PlaneRing<T, DIM>& R, int slot, int i0, int j0,
                                            int kk) {
-#pragma unroll
-  for (int c = 0; c < DIM; ++c) {
-    for (int s = threadIdx.x; s < kLX * kLY; s += kBlock) {
-      const int sy = s / kLX, sx = s - sy * kLX;
-      // halo slots past a ragged tile edge are clamped to one step outside
-      // the domain (their values are never used), so every load stays in
-      // bounds however small the axis
-      const int gi = min(i0 - 1 + sx, G.n[0]), gj = min(j0 - 1 + sy, G.n[1]);
-      T val;
-      if (c == 0) val = ld<0, DIM>(G, u[0], gi, gj, kk);
-      else if (c == 1) val = ld<1, DIM>(G, u[1], gi, gj, kk);
-      else val = ld<2, DIM>(G, u[2], gi, gj, kk);
-      R.v[c][slot][sy][sx] = val;
-    }
-  }
+  PlaneRegs<T, DIM> P;
+  load_plane<DIM>(G, u, P, i0, j0, kk);
+  store_plane<DIM>(R, slot, P);
 }
 
 // MODE 0: predictor (writes u*, and the forcing on forced faces).
@@ -172,20 +188,27 @@ k_predictor(Geo<T> G, int ntx, int nty, int nzc, const T* __restrict__ u0,
             const T* __restrict__ fb1, const T* __restrict__ fb2, T* __restrict__ o0,
             T* __restrict__ o1, T* __restrict__ o2, IbView<T> ib) {
   __shared__ PlaneRing<T, DIM> R;
+  __shared__ TileMet<T> TM;
   const T* u[3] = {u0, u1, u2};
+  const T* fbp[3] = {fb0, fb1, fb2};
   const int b = xcd_block(blockIdx.x, gridDim.x);
   if (b >= ntx * nty * nzc) return;
   const int tx = b % ntx, ty = (b / ntx) % nty, zc = b / (ntx * nty);
   const int i0 = tx * kTileX, j0 = ty * kTileY;
-  const int lx = threadIdx.x & (kTileX - 1), ly = threadIdx.x / kTileX;
+  // one wavefront per tile row: ly (and so j) is uniform across the wave
+  const int lx = threadIdx.x & (kTileX - 1);
+  const int ly = __builtin_amdgcn_readfirstlane(threadIdx.x / kTileX);
   const int i = i0 + lx, j = j0 + ly;
   const int k0 = (DIM == 3) ? zc * kZChunk : 0;
   const int k1 = (DIM == 3) ? min(k0 + kZChunk, G.n[2]) : 1;
   const bool inside = i < G.n[0] && j < G.n[1];
+  load_tile_met<DIM>(G, TM, i0, j0, k0);
+  PlaneRegs<T, DIM> nxt;
   if (DIM == 3) {
     fill_plane<DIM>(G, u, R, ring_slot(k0 - 1), i0, j0, k0 - 1);
     fill_plane<DIM>(G, u, R, ring_slot(k0), i0, j0, k0);
     fill_plane<DIM>(G, u, R, ring_slot(k0 + 1), i0, j0, k0 + 1);
+    if (k0 + 1 < k1) load_plane<DIM>(G, u, nxt, i0, j0, k0 + 2);
   } else {
     fill_plane<DIM>(G, u, R, 0, i0, j0, 0);
   }
@@ -199,13 +222,20 @@ k_predictor(Geo<T> G, int ntx, int nty, int nzc, const T* __restrict__ u0,
         const int sl = dk < 0 ? sm : (dk > 0 ? sp : sc);
         return R.v[c][sl][ly + 1 + dj][lx + 1 + di];
       };
-      predict_face<0, DIM, MODE, T>(G, L, fb0, o0, ib, i, j, k);
-      predict_face<1, DIM, MODE, T>(G, L, fb1, o1, ib, i, j, k);
-      predict_face<2, DIM, MODE, T>(G, L, fb2, o2, ib, i, j, k);
+      // body force of the three faces first: its loads overlap the stencil
+      T fbv[3] = {T(0), T(0), T(0)};
+#pragma unroll
+      for (int c = 0; c < DIM; ++c)
+        if (fbp[c]) fbv[c] = fbp[c][fidx(G.ext[c], i, j, k)];
+      const MetLds<T> M{&TM, {lx + 1, ly + 1, k - k0 + 1}};
+      predict_face<0, DIM, MODE, T>(G, L, M, fbv[0], o0, ib, i, j, k);
+      predict_face<1, DIM, MODE, T>(G, L, M, fbv[1], o1, ib, i, j, k);
+      predict_face<2, DIM, MODE, T>(G, L, M, fbv[2], o2, ib, i, j, k);
     }
     if (DIM == 3 && k + 1 < k1) {
       __syncthreads();
-      fill_plane<DIM>(G, u, R, sm, i0, j0, k + 2);   // slot of plane k-1 takes k+2
+      store_plane<DIM>(R, sm, nxt);                   // slot of plane k-1 takes k+2
+      if (k + 2 < k1) load_plane<DIM>(G, u, nxt, i0, j0, k + 3);
     }
   }
 }
@@ -277,11 +307,15 @@ k_boundary_faces(Geo<T> G, Planes PL, const T* __restrict__ un0, const T* __rest
     flux += sign * (double)val * face_area(G, c, i, j, k);
   }
   if (!PL.any_outflow) return;
-  double v[1] = {flux}, tot[1];
-  if (grid_reduce<1, 1>(v, red.partial, red.ticket, tot)) {
-    if (threadIdx.x == 0) sc->meanb = tot[0] / PL.area_out;   // correction value
-  }
+  double v[1] = {flux};
+  block_partials<1, 1>(v, red.partial);
 }
+
+struct FinOutflow {         // net boundary flux per unit outflow area
+  double area_out;
+  __device__ bool skip(const SolverScalars*) const { return false; }
+  __device__ void apply(const double* t, SolverScalars* sc) const { sc->meanb = t[0] / area_out; }
+};
 
 // Uniform correction of the outflow faces: u_b -= sign * net / area_out.
 template <typename T>
@@ -341,6 +375,7 @@ int launch_boundary(const Geo<T>& G, const Planes& PL, const T* const un[3], T* 
                      un[2], us[0], us[1], us[2], red, sc);
   FVIB_HIP(hipGetLastError());
   if (PL.any_outflow) {
+    FVIB_HIP((launch_finish<1, 1>(red.partial, nb, sc, FinOutflow{PL.area_out}, s)));
     hipLaunchKernelGGL((k_outflow_correct<T>), dim3(nb), dim3(kBlock), 0, s, G, PL, us[0], us[1],
                        us[2], (const SolverScalars*)sc);
     FVIB_HIP(hipGetLastError());

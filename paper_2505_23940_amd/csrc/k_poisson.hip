@@ -21,36 +21,51 @@
 namespace fvib {
 
 
+// Neighbour cell of index ia along an axis of na cells: wrapped on a
+// periodic axis, clamped on a bounded one (where the face between them is a
+// boundary face whose coefficient kf is zero).  Every index is valid, so
+// all loads of a stencil can be issued before any arithmetic.
+__device__ __forceinline__ int nb_lo(int ia, int na, int per) {
+  return ia > 0 ? ia - 1 : (per ? na - 1 : 0);
+}
+__device__ __forceinline__ int nb_hi(int ia, int na, int per) {
+  return ia < na - 1 ? ia + 1 : (per ? 0 : na - 1);
+}
+
 template <typename V, int DIM, typename Get>
 __device__ __forceinline__ V apply_A(const PGeo<V>& P, const Get& get, int i, int j, int k, V xc) {
   const int I[3] = {i, j, k};
+  V lo[DIM], hi[DIM], d[DIM], klo[DIM], khi[DIM];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const int ia = I[a];
+    int J[3] = {i, j, k};
+    J[a] = nb_lo(ia, P.n[a], P.per[a]);
+    lo[a] = get(J[0], J[1], J[2]);
+    J[a] = nb_hi(ia, P.n[a], P.per[a]);
+    hi[a] = get(J[0], J[1], J[2]);
+    d[a] = P.dx[a][ia];
+    klo[a] = P.kf[a][ia];
+    khi[a] = P.kf[a][ia + 1];
+  }
   V acc = V(0);
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     V area = V(1);
 #pragma unroll
     for (int b = 0; b < DIM; ++b)
-      if (b != a) area *= P.dx[b][I[b]];
-    const int ia = I[a];
-    const int na = P.n[a];
-    if (P.per[a] || ia > 0) {
-      int J[3] = {i, j, k};
-      J[a] = (ia == 0) ? na - 1 : ia - 1;
-      acc += area * P.idc[a][ia] * (xc - get(J[0], J[1], J[2]));
-    }
-    if (P.per[a] || ia < na - 1) {
-      int J[3] = {i, j, k};
-      J[a] = (ia == na - 1) ? 0 : ia + 1;
-      acc += area * P.idc[a][ia + 1] * (xc - get(J[0], J[1], J[2]));
-    }
+      if (b != a) area *= d[b];
+    acc += area * klo[a] * (xc - lo[a]);
+    acc += area * khi[a] * (xc - hi[a]);
   }
   return acc;
 }
 
+// 1 / cell volume
 template <typename V>
-__device__ __forceinline__ double cell_volume(const PGeo<V>& P, int i, int j, int k) {
-  double v = (double)P.dx[0][i] * (double)P.dx[1][j];
-  if (P.dim == 3) v *= (double)P.dx[2][k];
+__device__ __forceinline__ double inv_volume(const PGeo<V>& P, int i, int j, int k) {
+  double v = (double)P.iv[0][i] * (double)P.iv[1][j];
+  if (P.dim == 3) v *= (double)P.iv[2][k];
   return v;
 }
 
@@ -64,6 +79,87 @@ __device__ __forceinline__ double cell_volume(const PGeo<V>& P, int i, int j, in
 
 #define FVIB_TILE_END }
 
+// ------------------------------------------------ reduction epilogues
+struct FinMeanB {           // mean of the PPE right-hand side
+  double inv_ncell;
+  __device__ bool skip(const SolverScalars*) const { return false; }
+  __device__ void apply(const double* t, SolverScalars* sc) const { sc->meanb = t[0] * inv_ncell; }
+};
+
+template <int MODE>
+struct FinResidual {        // start of a solve / refinement sweep
+  double tol, inner_rtol, dt_over_rho;
+  int first;                // first residual of the solve (never skipped)
+  __device__ bool skip(const SolverScalars* sc) const { return !first && sc->outer_done; }
+  __device__ void apply(const double* t, SolverScalars* sc) const {
+    sc->sweeps = first ? 0 : sc->sweeps + 1;
+    const double crit = t[2] * dt_over_rho;
+    sc->rr = t[0];
+    sc->rr0 = t[0];
+    sc->beta = 0.0;
+    sc->iters = 0;
+    sc->crit = crit;
+    sc->sumx = t[1];
+    sc->tol_rr = inner_rtol * inner_rtol * t[0];
+    const bool bad = !(t[0] == t[0]) || !(crit == crit);
+    if (bad) sc->status = FVIB_ENONFINITE;
+    const bool conv = bad || crit <= tol || t[0] == 0.0;
+    sc->done = conv ? 1 : 0;
+    if (MODE != 0) sc->outer_done = conv ? 1 : 0;
+  }
+};
+
+struct FinCgDir {
+  __device__ bool skip(const SolverScalars* sc) const { return sc->done != 0; }
+  __device__ void apply(const double* t, SolverScalars* sc) const {
+    sc->pq = t[0];
+    sc->alpha = (t[0] > 0.0) ? sc->rr / t[0] : 0.0;
+    sc->sump = t[1];          // sum(p), used to keep x at zero mean
+    if (!(t[0] == t[0])) {
+      sc->status = FVIB_ENONFINITE;
+      sc->done = 1;
+      sc->outer_done = 1;
+    } else if (!(t[0] > 0.0)) {
+      sc->done = 1;           // exact solution reached (p = 0)
+    }
+  }
+};
+
+template <int MODE>
+struct FinCgUpdate {
+  double tol, dt_over_rho;
+  int maxit;
+  __device__ bool skip(const SolverScalars* sc) const { return sc->done != 0; }
+  __device__ void apply(const double* t, SolverScalars* sc) const {
+    const double rrn = t[0];
+    sc->beta = (sc->rr > 0.0) ? rrn / sc->rr : 0.0;
+    sc->rr = rrn;
+    sc->iters += 1;
+    bool conv;
+    if (MODE == 0) {
+      sc->crit = t[1] * dt_over_rho;
+      conv = sc->crit <= tol;
+    } else {
+      conv = rrn <= sc->tol_rr;
+    }
+    if (!(rrn == rrn)) {
+      sc->status = FVIB_ENONFINITE;
+      sc->outer_done = 1;
+      conv = true;
+    }
+    if (!conv && sc->iters >= maxit) {
+      if (MODE == 0) sc->status = FVIB_ENOCONV;
+      conv = true;
+    }
+    sc->done = conv ? 1 : 0;
+  }
+};
+
+struct FinDivMax {
+  __device__ bool skip(const SolverScalars*) const { return false; }
+  __device__ void apply(const double* t, SolverScalars* sc) const { sc->div_max = t[0]; }
+};
+
 // ----------------------------------------------------------------- RHS
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kBlock)
@@ -76,38 +172,47 @@ k_ppe_rhs(Geo<T> G, PGeo<double> P, Tiling tl, const T* __restrict__ s0,
   double sum = 0.0;
   FVIB_TILE_LOOP(tl)
     const int I[3] = {i, j, k};
+    double lo[DIM], hi[DIM], d[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      int H[3] = {i, j, k};
+      H[c] += 1;
+      if (G.per[c] && H[c] == G.n[c]) H[c] = 0;
+      lo[c] = (double)us[c][fidx(G.ext[c], i, j, k)];
+      hi[c] = (double)us[c][fidx(G.ext[c], H[0], H[1], H[2])];
+      d[c] = P.dx[c][I[c]];
+    }
+    if (ib.active) {
+      // u~ = u_c on the forced faces
+#pragma unroll
+      for (int c = 0; c < (DIM < 2 ? DIM : 2); ++c) {
+        const double Uc = ib.body[3 + c];
+        const int* o = ib.origin;
+        const int W0 = ib.W[c][0], W1 = ib.W[c][1];
+        int li = i - o[2 * c], ljj = j - o[2 * c + 1];
+        if (li >= 0 && ljj >= 0 && li < W0 && ljj < W1 && ib.cls[c][ljj * W0 + li]) lo[c] = Uc;
+        int H[2] = {i + (c == 0), j + (c == 1)};
+        if (G.per[c] && H[c] == G.n[c]) H[c] = 0;
+        li = H[0] - o[2 * c];
+        ljj = H[1] - o[2 * c + 1];
+        if (li >= 0 && ljj >= 0 && li < W0 && ljj < W1 && ib.cls[c][ljj * W0 + li]) hi[c] = Uc;
+      }
+    }
     double acc = 0.0;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
       double A = 1.0;
 #pragma unroll
       for (int a = 0; a < DIM; ++a)
-        if (a != c) A *= P.dx[a][I[a]];
-      int H[3] = {i, j, k};
-      H[c] += 1;
-      if (G.per[c] && H[c] == G.n[c]) H[c] = 0;
-      double lo = (double)us[c][fidx(G.ext[c], i, j, k)];
-      double hi = (double)us[c][fidx(G.ext[c], H[0], H[1], H[2])];
-      if (ib.active && c < 2) {
-        const double Uc = ib.body[3 + c];
-        const int* o = ib.origin;
-        const int W0 = ib.W[c][0], W1 = ib.W[c][1];
-        int li = i - o[2 * c], ljj = j - o[2 * c + 1];
-        if (li >= 0 && ljj >= 0 && li < W0 && ljj < W1 && ib.cls[c][ljj * W0 + li]) lo = Uc;
-        li = H[0] - o[2 * c];
-        ljj = H[1] - o[2 * c + 1];
-        if (li >= 0 && ljj >= 0 && li < W0 && ljj < W1 && ib.cls[c][ljj * W0 + li]) hi = Uc;
-      }
-      acc += hi * A - lo * A;
+        if (a != c) A *= d[a];
+      acc += hi[c] * A - lo[c] * A;
     }
     const double bc = scale * acc;
     b[c_] = bc;
     sum += bc;
   FVIB_TILE_END
-  double v[1] = {sum}, tot[1];
-  if (grid_reduce<1, 1>(v, red.partial, red.ticket, tot)) {
-    if (threadIdx.x == 0) sc->meanb = tot[0] * P.inv_ncell;
-  }
+  double v[1] = {sum};
+  block_partials<1, 1>(v, red.partial);
 }
 
 // ------------------------------------------------------------ residual
@@ -121,14 +226,15 @@ template <int DIM, int MODE>
 __global__ void __launch_bounds__(kBlock)
 k_residual(PGeo<double> P, Tiling tl, const double* __restrict__ b,
            const double* __restrict__ x, double* __restrict__ r64, float* __restrict__ r32,
-           float* __restrict__ d32, RedBuf red, SolverScalars* sc, double tol,
-           double inner_rtol) {
+           float* __restrict__ d32, RedBuf red, SolverScalars* sc, int first) {
+  if (!first && sc->outer_done) return;
   const int nx_ = P.n[0], ny_ = P.n[1];
   const double mb = sc->meanb;
   double rr = 0.0, sx = 0.0, mx = 0.0;
   auto get = [&](int a, int b_, int c) { return x[((int64_t)c * ny_ + b_) * nx_ + a]; };
   FVIB_TILE_LOOP(tl)
     const double xc = x[c_];
+    const double ivol = inv_volume(P, i, j, k);
     const double r = b[c_] - mb - apply_A<double, DIM>(P, get, i, j, k, xc);
     if (MODE == 0 || MODE == 3) {
       r64[c_] = r;
@@ -138,26 +244,10 @@ k_residual(PGeo<double> P, Tiling tl, const double* __restrict__ b,
     }
     rr += r * r;
     sx += xc;
-    mx = fmax(mx, fabs(r) / cell_volume(P, i, j, k));
+    mx = fmax(mx, fabs(r) * ivol);
   FVIB_TILE_END
-  double v[3] = {rr, sx, mx}, tot[3];
-  if (grid_reduce<3, 2>(v, red.partial, red.ticket, tot)) {
-    if (threadIdx.x == 0) {
-      const double crit = tot[2] * P.dt_over_rho;
-      sc->rr = tot[0];
-      sc->rr0 = tot[0];
-      sc->beta = 0.0;
-      sc->iters = 0;
-      sc->crit = crit;
-      sc->sumx = tot[1];
-      sc->tol_rr = inner_rtol * inner_rtol * tot[0];
-      const bool bad = !(tot[0] == tot[0]) || !(crit == crit);
-      if (bad) sc->status = FVIB_ENONFINITE;
-      const bool conv = bad || crit <= tol || tot[0] == 0.0;
-      sc->done = conv ? 1 : 0;
-      if (MODE != 0) sc->outer_done = conv ? 1 : 0;
-    }
-  }
+  double v[3] = {rr, sx, mx};
+  block_partials<3, 2>(v, red.partial);
 }
 
 // ------------------------------------------------------ CG direction
@@ -184,21 +274,8 @@ k_cg_dir(PGeo<V> P, Tiling tl, const V* __restrict__ r, const V* __restrict__ po
     pq += (double)pc * (double)q;
     sp += (double)pc;
   FVIB_TILE_END
-  double v[2] = {pq, sp}, tot[2];
-  if (grid_reduce<2, 2>(v, red.partial, red.ticket, tot)) {
-    if (threadIdx.x == 0) {
-      sc->pq = tot[0];
-      sc->alpha = (tot[0] > 0.0) ? sc->rr / tot[0] : 0.0;
-      sc->sump = tot[1];      // sum(p), used to keep x at zero mean
-      if (!(tot[0] == tot[0])) {
-        sc->status = FVIB_ENONFINITE;
-        sc->done = 1;
-        sc->outer_done = 1;
-      } else if (!(tot[0] > 0.0)) {
-        sc->done = 1;         // exact solution reached (p = 0)
-      }
-    }
-  }
+  double v[2] = {pq, sp};
+  block_partials<2, 2>(v, red.partial);
 }
 
 // --------------------------------------------------------- CG update
@@ -217,39 +294,17 @@ k_cg_update(PGeo<V> P, Tiling tl, const V* __restrict__ p, V* __restrict__ x,
   auto get = [&](int a, int b_, int c) { return p[((int64_t)c * ny_ + b_) * nx_ + a]; };
   FVIB_TILE_LOOP(tl)
     const V pc = p[c_];
+    const double ivol = (MODE == 0) ? inv_volume(P, i, j, k) : 0.0;
+    const V xo = x[c_], ro = r[c_];
     const V q = apply_A<V, DIM>(P, get, i, j, k, pc);
-    x[c_] = x[c_] + (alpha * pc - shift);
-    const V rn = r[c_] - alpha * q;
+    x[c_] = xo + (alpha * pc - shift);
+    const V rn = ro - alpha * q;
     r[c_] = rn;
     rr += (double)rn * (double)rn;
-    if (MODE == 0) mx = fmax(mx, fabs((double)rn) / cell_volume(P, i, j, k));
+    if (MODE == 0) mx = fmax(mx, fabs((double)rn) * ivol);
   FVIB_TILE_END
-  double v[2] = {rr, mx}, tot[2];
-  if (grid_reduce<2, 1>(v, red.partial, red.ticket, tot)) {
-    if (threadIdx.x == 0) {
-      const double rrn = tot[0];
-      sc->beta = (sc->rr > 0.0) ? rrn / sc->rr : 0.0;
-      sc->rr = rrn;
-      sc->iters += 1;
-      bool conv;
-      if (MODE == 0) {
-        sc->crit = tot[1] * P.dt_over_rho;
-        conv = sc->crit <= tol;
-      } else {
-        conv = rrn <= sc->tol_rr;
-      }
-      if (!(rrn == rrn)) {
-        sc->status = FVIB_ENONFINITE;
-        sc->outer_done = 1;
-        conv = true;
-      }
-      if (!conv && sc->iters >= maxit) {
-        if (MODE == 0) sc->status = FVIB_ENOCONV;
-        conv = true;
-      }
-      sc->done = conv ? 1 : 0;
-    }
-  }
+  double v[2] = {rr, mx};
+  block_partials<2, 1>(v, red.partial);
 }
 
 // ------------------------------------------------ refinement correction
@@ -266,7 +321,7 @@ k_ir_correct(int64_t n, double* __restrict__ p, const float* __restrict__ d,
 
 // --------------------------------------------------------- projection
 // u^{n+1} = u* - (dt/rho) (p_c - p_{c-1}) / dc on every face that is not a
-// boundary face of a bounded axis (those keep u*).  Each thread owns the
+// boundary face of a bounded axis (those keep u*: their coefficient is 0).  Each thread owns the
 // low faces of its cell and, on the last cell of a bounded axis, the high
 // boundary face.  The divergence of the corrected field is evaluated in
 // double before rounding to the storage type and its maximum recorded.
@@ -284,47 +339,46 @@ k_project(Geo<T> G, PGeo<double> P, Tiling tl, const T* __restrict__ s0,
   FVIB_TILE_LOOP(tl)
     const int I[3] = {i, j, k};
     const double pc = p[c_];
+    const double ivol = inv_volume(P, i, j, k);
+    int64_t lo_id[DIM], hi_id[DIM];
+    double ulo[DIM], uhi[DIM], plo[DIM], phi[DIM], d[DIM], klo[DIM], khi[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const int ic = I[c], nc = G.n[c];
+      int H[3] = {i, j, k};
+      H[c] = (G.per[c] && ic + 1 == nc) ? 0 : ic + 1;
+      lo_id[c] = fidx(G.ext[c], i, j, k);
+      hi_id[c] = fidx(G.ext[c], H[0], H[1], H[2]);
+      ulo[c] = (double)us[c][lo_id[c]];
+      uhi[c] = (double)us[c][hi_id[c]];
+      int J[3] = {i, j, k};
+      J[c] = nb_lo(ic, nc, G.per[c]);
+      plo[c] = p[((int64_t)J[2] * ny_ + J[1]) * nx_ + J[0]];
+      J[c] = nb_hi(ic, nc, G.per[c]);
+      phi[c] = p[((int64_t)J[2] * ny_ + J[1]) * nx_ + J[0]];
+      d[c] = P.dx[c][ic];
+      klo[c] = P.kf[c][ic];
+      khi[c] = P.kf[c][ic + 1];
+    }
     double div = 0.0;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
-      const int ic = I[c];
-      const int nc = G.n[c];
+      const int ic = I[c], nc = G.n[c];
       double A = 1.0;
 #pragma unroll
       for (int a = 0; a < DIM; ++a)
-        if (a != c) A *= P.dx[a][I[a]];
-      // low face
-      const int64_t lo_id = fidx(G.ext[c], i, j, k);
-      double ulo = (double)us[c][lo_id];
-      if (G.per[c] || ic > 0) {
-        int J[3] = {i, j, k};
-        J[c] = (ic == 0) ? nc - 1 : ic - 1;
-        const double pn = p[((int64_t)J[2] * ny_ + J[1]) * nx_ + J[0]];
-        ulo = ulo - f * (pc - pn) * P.idc[c][ic];
-      }
-      out[c][lo_id] = (T)ulo;
-      // high face
-      int H[3] = {i, j, k};
-      H[c] = ic + 1;
-      double uhi;
-      if (G.per[c] || ic + 1 < nc) {
-        if (H[c] == nc) H[c] = 0;
-        const int64_t hi_id = fidx(G.ext[c], H[0], H[1], H[2]);
-        const double pn = p[((int64_t)H[2] * ny_ + H[1]) * nx_ + H[0]];
-        uhi = (double)us[c][hi_id] - f * (pn - pc) * P.idc[c][ic + 1];
-      } else {
-        const int64_t hi_id = fidx(G.ext[c], H[0], H[1], H[2]);
-        uhi = (double)us[c][hi_id];
-        out[c][hi_id] = (T)uhi;     // boundary face of a bounded axis
-      }
-      div += (uhi - ulo) * A;
+        if (a != c) A *= d[a];
+      // faces of a bounded boundary have kf = 0 and keep u*
+      const double lo = ulo[c] - f * (pc - plo[c]) * klo[c];
+      const double hi = uhi[c] - f * (phi[c] - pc) * khi[c];
+      out[c][lo_id[c]] = (T)lo;
+      if (!G.per[c] && ic + 1 == nc) out[c][hi_id[c]] = (T)hi;
+      div += (hi - lo) * A;
     }
-    mx = fmax(mx, fabs(div) / cell_volume(P, i, j, k));
+    mx = fmax(mx, fabs(div) * ivol);
   FVIB_TILE_END
-  double v[1] = {mx}, tot[1];
-  if (grid_reduce<1, 0>(v, red.partial, red.ticket, tot)) {
-    if (threadIdx.x == 0) sc->div_max = tot[0];
-  }
+  double v[1] = {mx};
+  block_partials<1, 0>(v, red.partial);
 }
 
 // ---------------------------------------------------------- apply A
@@ -355,17 +409,21 @@ int launch_ppe_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
     hipLaunchKernelGGL((k_ppe_rhs<T, 3>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, us[0],
                        us[1], us[2], ib, b, red, sc);
   FVIB_HIP(hipGetLastError());
+  FVIB_HIP((launch_finish<1, 1>(red.partial, tl.nblocks, sc, FinMeanB{P.inv_ncell}, s)));
   return FVIB_OK;
 }
 
 int launch_residual(const PGeo<double>& P, int mode, const double* b, const double* x,
                     double* r64, float* r32, float* d32, RedBuf red, SolverScalars* sc,
-                    double tol, double inner_rtol, hipStream_t s) {
+                    double tol, double inner_rtol, hipStream_t s, int first) {
   const Tiling tl = red_tiling(P.n);
   dim3 g(tl.nblocks), bl(kBlock);
 #define FVIB_RES(D, M)                                                                        \
-  hipLaunchKernelGGL((k_residual<D, M>), g, bl, 0, s, P, tl, b, x, r64, r32, d32, red, sc, tol, \
-                     inner_rtol)
+  hipLaunchKernelGGL((k_residual<D, M>), g, bl, 0, s, P, tl, b, x, r64, r32, d32, red, sc,      \
+                     first);                                                                    \
+  FVIB_HIP(hipGetLastError());                                                                  \
+  FVIB_HIP((launch_finish<3, 2>(red.partial, tl.nblocks, sc,                                    \
+                                FinResidual<M>{tol, inner_rtol, P.dt_over_rho, first}, s)))
   if (P.dim == 2) {
     switch (mode) {
       case 0: FVIB_RES(2, 0); break;
@@ -398,6 +456,7 @@ int launch_cg_iter(const PGeo<V>& P, int mode, const V* r, const V* pold, V* pne
   else
     hipLaunchKernelGGL((k_cg_dir<V, 3>), g, bl, 0, s, P, tl, r, pold, pnew, red, sc);
   FVIB_HIP(hipGetLastError());
+  FVIB_HIP((launch_finish<2, 2>(red.partial, tl.nblocks, sc, FinCgDir{}, s)));
   if (ev) FVIB_HIP(hipEventRecord(ev[1], s));
   if (P.dim == 2) {
     if (mode == 0)
@@ -411,6 +470,12 @@ int launch_cg_iter(const PGeo<V>& P, int mode, const V* r, const V* pold, V* pne
       hipLaunchKernelGGL((k_cg_update<V, 3, 1>), g, bl, 0, s, P, tl, (const V*)pnew, x, rw, red, sc, tol, maxit);
   }
   FVIB_HIP(hipGetLastError());
+  if (mode == 0)
+    FVIB_HIP((launch_finish<2, 1>(red.partial, tl.nblocks, sc,
+                                  FinCgUpdate<0>{tol, P.dt_over_rho, maxit}, s)));
+  else
+    FVIB_HIP((launch_finish<2, 1>(red.partial, tl.nblocks, sc,
+                                  FinCgUpdate<1>{tol, P.dt_over_rho, maxit}, s)));
   if (ev) FVIB_HIP(hipEventRecord(ev[2], s));
   return FVIB_OK;
 }
@@ -435,6 +500,7 @@ int launch_project(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
     hipLaunchKernelGGL((k_project<T, 3>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, us[0],
                        us[1], us[2], p, out[0], out[1], out[2], red, sc);
   FVIB_HIP(hipGetLastError());
+  FVIB_HIP((launch_finish<1, 0>(red.partial, tl.nblocks, sc, FinDivMax{}, s)));
   return FVIB_OK;
 }
 

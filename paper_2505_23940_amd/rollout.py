@@ -37,8 +37,15 @@ class _Rollout(torch.autograd.Function):
         ckpts = {}
         for n in range(nsteps):
             if n % ckpt_every == 0:
-                ckpts[n] = ([x.clone() for x in u], p.clone(), body.clone())
-            grid.step(u, p, fbd, body, kcd, info=info[n])
+                # the state entering a segment is kept as is; the step writes
+                # its result into fresh tensors (p is copied by the step)
+                ckpts[n] = (u, p, body)
+                u2 = [torch.empty_like(x) for x in u]
+                p2, b2 = torch.empty_like(p), torch.empty_like(body)
+                grid.step(u, p, fbd, body, kcd, u_out=u2, p_out=p2, body_out=b2, info=info[n])
+                u, p, body = u2, p2, b2
+            else:
+                grid.step(u, p, fbd, body, kcd, info=info[n])
         ctx.grid = grid
         ctx.nsteps = nsteps
         ctx.k = ckpt_every
@@ -70,14 +77,18 @@ class _Rollout(torch.autograd.Function):
         for s0 in reversed(starts):
             s1 = min(s0 + K, S)
             cu, cp, cb = ctx.ckpts[s0]
-            u = [x.clone() for x in cu]
-            p = cp.clone()
-            body = cb.clone()
-            states = []
-            for n in range(s0, s1):
-                states.append(([x.clone() for x in u], body.clone()))
-                if n + 1 < s1:
-                    grid.step(u, p, fb, body, kc)
+            # states n = s0 .. s1-1 of the segment: the checkpoint, then the
+            # recomputed ones, each step writing into fresh velocity tensors
+            states = [(cu, cb)]
+            if s1 - s0 > 1:
+                p = cp.clone()
+                u, body = cu, cb
+                for n in range(s0, s1 - 1):
+                    u2 = [torch.empty_like(x) for x in u]
+                    b2 = torch.empty_like(body)
+                    grid.step(u, p, fb, body, kc, u_out=u2, p_out=p, body_out=b2)
+                    u, body = u2, b2
+                    states.append((u, body))
             for n in reversed(range(s0, s1)):
                 un, bn = states[n - s0]
                 dF = gF[n].contiguous()
