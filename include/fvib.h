@@ -276,6 +276,11 @@ enum {
 /* Start (enable != 0, totals cleared) or stop recording. */
 int fvib_timing_enable(fvib_grid *g, int enable);
 
+/* Restrict recording to the classes whose bit (1u << class) is set in
+ * class_mask (default: all).  Fewer events keep the host's launch rate
+ * close to that of an untimed run. */
+int fvib_timing_select(fvib_grid *g, uint32_t class_mask);
+
 /* Total device time (ms) and launch count of one kernel class since the
  * last enable; synchronises the stream. */
 int fvib_timing_read(fvib_grid *g, int kclass, double *total_ms, int64_t *launches);

@@ -297,7 +297,15 @@ class Grid:
         return J
 
     # --------------------------------------------------------- timing
-    def timing_enable(self, on: bool = True) -> None:
+    def timing_enable(self, on: bool = True, classes=None) -> None:
+        """Start (totals cleared) or stop event timing; `classes` (names of
+        _abi.K_CLASSES) restricts it to those kernel classes."""
+        mask = 0xFFFFFFFF
+        if classes is not None:
+            mask = 0
+            for name in classes:
+                mask |= 1 << _abi.K_CLASSES[name]
+        _check(lib().fvib_timing_select(self.h, mask), self.h)
         _check(lib().fvib_timing_enable(self.h, 1 if on else 0), self.h)
 
     def timing_read(self) -> dict:

@@ -25,6 +25,7 @@ int hip_fail(hipError_t e, const char* what, const char* file, int line) {
 // HIP-event timing of kernel classes on the handle's stream.
 struct Timer {
   bool on = false;
+  uint32_t mask = 0xffffffffu;   // classes recorded while on
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   struct Pending {
@@ -187,7 +188,7 @@ static void release(Grid* g) {
 
 template <typename F>
 static int timed(Grid* g, int cls, F&& launch) {
-  if (!g->timer.on) return launch();
+  if (!g->timer.on || !((g->timer.mask >> cls) & 1u)) return launch();
   hipEvent_t a = g->timer.next(), b = g->timer.next();
   if (!a || !b) return launch();
   FVIB_HIP(hipEventRecord(a, g->stream));
@@ -429,7 +430,8 @@ static int cg_run(Grid* g, const PGeo<V>& P, int mode, V* r, V* pa, V* pb, V* x,
     for (int q = 0; q < chunk; ++q) {
       hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
       bool use_ev = false;
-      if (g->timer.on) {
+      if (g->timer.on && (((g->timer.mask >> FVIB_K_CG_DIR) & 1u) ||
+                          ((g->timer.mask >> FVIB_K_CG_UPDATE) & 1u))) {
         ev[0] = g->timer.next();
         ev[1] = g->timer.next();
         ev[2] = g->timer.next();
@@ -745,28 +747,22 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
       FVIB_HIP(hipMemsetAsync(bi->body, 0, 6 * sizeof(double), g->stream));
   }
   // projection^T: A mu = G^T ubar^{n+1}
-  if ((rc = timed(g, FVIB_K_ADJOINT,
-                  [&] { return launch_adj_rhs<T>(G, g->P64, ub1, g->b, g->red(), g->sc, g->stream); })))
+  // relative max-norm target of the adjoint solve, set on the device from
+  // the right-hand side (no host round trip): well inside the gradient
+  // tolerances and above the double rounding floor of the residual.  A zero
+  // right-hand side gives a zero target and a zero residual at once.
+  const double rtol = (g->prec == FVIB_PREC_FP64) ? 1e-10 : 1e-7;
+  if ((rc = timed(g, FVIB_K_ADJOINT, [&] {
+         return launch_adj_rhs<T>(G, g->P64, ub1, g->b, g->red(), g->sc, rtol, g->stream);
+       })))
     return rc;
-  if ((rc = read_scalars(g))) return rc;
-  const double ymax = g->sch->crit;
   int cg = 0, ir = 0;
-  double adj_tol = 0.0;
-  if (ymax > 0.0) {
-    // relative max-norm target of the adjoint solve: well inside the gradient
-    // tolerances and above the double rounding floor of the residual
-    const double rtol = (g->prec == FVIB_PREC_FP64) ? 1e-10 : 1e-7;
-    const double tol = rtol * ymax * g->d.dt / g->d.rho;
-    adj_tol = tol;
-    // Start from zero: the target is relative to this right-hand side, and a
-    // warm start from another step's solution would put the double rounding
-    // floor of the residual (~eps |A mu|) above it when the right-hand side
-    // is small (e.g. zero up to rounding).
-    FVIB_HIP(hipMemsetAsync(g->mu, 0, g->ncell * sizeof(double), g->stream));
-    if ((rc = poisson_solve(g, g->b, g->mu, tol, &g->last_iters_adj, &cg, &ir))) return rc;
-  } else {
-    FVIB_HIP(hipMemsetAsync(g->mu, 0, g->ncell * sizeof(double), g->stream));
-  }
+  // Start from zero: the target is relative to this right-hand side, and a
+  // warm start from another step's solution would put the double rounding
+  // floor of the residual (~eps |A mu|) above it when the right-hand side
+  // is small (e.g. zero up to rounding).
+  FVIB_HIP(hipMemsetAsync(g->mu, 0, g->ncell * sizeof(double), g->stream));
+  if ((rc = poisson_solve(g, g->b, g->mu, -1.0, &g->last_iters_adj, &cg, &ir))) return rc;
   if ((rc = timed(g, FVIB_K_ADJOINT,
                   [&] { return launch_adj_ustar<T>(G, g->P64, ub1, g->mu, ib, usb, g->stream); })))
     return rc;
@@ -795,8 +791,9 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
   const int st = g->sch->status;
   if (st == FVIB_ENOCONV) {
     char buf[64];
-    snprintf(buf, sizeof(buf), "; rhs max |y/V| %.3e", ymax);
-    return fail(g, st, "adjoint Poisson solve did not converge" + describe_solve(g, adj_tol) + buf);
+    snprintf(buf, sizeof(buf), "; rhs max |y/V| %.3e", g->sch->ymax);
+    return fail(g, st, "adjoint Poisson solve did not converge" +
+                           describe_solve(g, g->sch->tol_dev) + buf);
   }
   if (st == FVIB_ENONFINITE) return fail(g, st, "non-finite value in the adjoint");
   g->err.clear();
@@ -1279,6 +1276,12 @@ int fvib_timing_enable(fvib_grid* h, int enable) {
   g->timer.resolve();
   g->timer.clear();
   g->timer.on = enable != 0;
+  return FVIB_OK;
+}
+
+int fvib_timing_select(fvib_grid* h, uint32_t class_mask) {
+  if (!h) return FVIB_EINVAL;
+  h->g.timer.mask = class_mask;
   return FVIB_OK;
 }
 

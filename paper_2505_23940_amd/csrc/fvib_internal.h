@@ -153,6 +153,31 @@ inline Tiling make_tiling(int nx, int ny, int nz, int max_blocks = kMaxRedBlocks
   return t;
 }
 
+// Column march: a unit is one tile of an x-y plane and a chunk of z-planes;
+// each thread owns one (i, j) column of its unit and walks up the chunk,
+// so values of plane k + 1 are reused as plane k and k - 1 (each value
+// crosses HBM once per chunk) and the next plane is prefetched.
+struct ColTiling {
+  int ntx, nty, nzc, zchunk;
+  int nunits;
+  int nblocks;      // multiple of kXcds, at most kMaxRedBlocks
+};
+
+inline ColTiling make_col_tiling(int nx, int ny, int nz) {
+  ColTiling t;
+  t.ntx = (nx + kTileX - 1) / kTileX;
+  t.nty = (ny + kTileY - 1) / kTileY;
+  const int per_plane = t.ntx * t.nty;
+  int nzc = (nz + 15) / 16;
+  if (per_plane * nzc > kMaxRedBlocks) nzc = kMaxRedBlocks / per_plane > 0 ? kMaxRedBlocks / per_plane : 1;
+  t.zchunk = (nz + nzc - 1) / nzc;
+  t.nzc = (nz + t.zchunk - 1) / t.zchunk;
+  t.nunits = per_plane * t.nzc;
+  int nb = t.nunits < kMaxRedBlocks ? t.nunits : kMaxRedBlocks;
+  t.nblocks = (nb + kXcds - 1) / kXcds * kXcds;
+  return t;
+}
+
 __device__ __forceinline__ int xcd_block(int b, int nblocks) {
   const int per = nblocks / kXcds;       // nblocks is a multiple of kXcds
   return (b % kXcds) * per + b / kXcds;
@@ -383,6 +408,8 @@ struct SolverScalars {
   double div_max;   // max |D u^{n+1}| of the projection
   double force[3];
   double loss;
+  double ymax;      // adjoint right-hand side: max |y / V|
+  double tol_dev;   // stopping target set on the device (tol < 0 on the host)
   int done;         // current CG solve finished
   int outer_done;   // refinement finished
   int iters;        // iterations of the current CG solve

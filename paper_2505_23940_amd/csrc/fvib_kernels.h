@@ -89,8 +89,10 @@ int launch_adj_body_loads(const IbGeo& B, const IbView<T>& ib, const double* st,
                           const double* stbar_out, const double* dF, const double* kc,
                           double* stbar_in, double* kcbar, SolverScalars* sc, hipStream_t s);
 template <typename T>
+// rtol: relative target of the adjoint solve, set on the device as
+// rtol * max |y / V| * dt / rho (used by a solve called with tol < 0).
 int launch_adj_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const ub[3], double* y,
-                   RedBuf red, SolverScalars* sc, hipStream_t s);
+                   RedBuf red, SolverScalars* sc, double rtol, hipStream_t s);
 template <typename T>
 int launch_adj_ustar(const Geo<T>& G, const PGeo<double>& P, const T* const ub1[3],
                      const double* mu, const IbView<T>& ib, T* usb[3], hipStream_t s);

@@ -255,12 +255,14 @@ k_adj_rhs(Geo<T> G, PGeo<double> P, Tiling tl, const T* __restrict__ b0,
   block_partials<2, 1>(v, red.partial);
 }
 
-struct FinAdjRhs {          // mean of G^T ubar and max |y / V|
-  double inv_ncell;
+struct FinAdjRhs {          // mean of G^T ubar, max |y / V| and the solve target
+  double inv_ncell, rtol, dt_over_rho;
   __device__ bool skip(const SolverScalars*) const { return false; }
   __device__ void apply(const double* t, SolverScalars* sc) const {
     sc->meanb = t[0] * inv_ncell;
     sc->crit = t[1];
+    sc->ymax = t[1];
+    sc->tol_dev = rtol * t[1] * dt_over_rho;
   }
 };
 
@@ -787,7 +789,7 @@ int launch_adj_body_loads(const IbGeo& B, const IbView<T>& ib, const double* st,
 
 template <typename T>
 int launch_adj_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const ub[3], double* y,
-                   RedBuf red, SolverScalars* sc, hipStream_t s) {
+                   RedBuf red, SolverScalars* sc, double rtol, hipStream_t s) {
   const Tiling tl = make_tiling(G.n[0], G.n[1], G.n[2]);
   if (G.dim == 2)
     hipLaunchKernelGGL((k_adj_rhs<T, 2>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, ub[0],
@@ -796,7 +798,8 @@ int launch_adj_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const ub[3],
     hipLaunchKernelGGL((k_adj_rhs<T, 3>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, ub[0],
                        ub[1], ub[2], y, red, sc);
   FVIB_HIP(hipGetLastError());
-  FVIB_HIP((launch_finish<2, 1>(red.partial, tl.nblocks, sc, FinAdjRhs{P.inv_ncell}, s)));
+  FVIB_HIP((launch_finish<2, 1>(red.partial, tl.nblocks, sc,
+                                FinAdjRhs{P.inv_ncell, rtol, P.dt_over_rho}, s)));
   return FVIB_OK;
 }
 
@@ -908,7 +911,7 @@ static int launch_adj_momentum_t(const AdjCtx<T>& X, T* ubar[3], T* fbbar[3], hi
                                         const double*, const double*, const double*, double*,   \
                                         double*, SolverScalars*, hipStream_t);                  \
   template int launch_adj_rhs<T>(const Geo<T>&, const PGeo<double>&, const T* const[3],         \
-                                 double*, RedBuf, SolverScalars*, hipStream_t);                 \
+                                 double*, RedBuf, SolverScalars*, double, hipStream_t);         \
   template int launch_adj_ustar<T>(const Geo<T>&, const PGeo<double>&, const T* const[3],       \
                                    const double*, const IbView<T>&, T* [3], hipStream_t);       \
   template int launch_adj_ubody<T>(const Geo<T>&, const PGeo<double>&, const IbGeo&,            \

@@ -208,7 +208,7 @@ __device__ __forceinline__ Quad<V> ld_quad(const V* p, int64_t stride) {
   return r;
 }
 
-template <typename V, bool XFAST, bool DIV, int MT, int NT>
+template <typename V, bool XFAST, bool DIV, bool TAIL, int MT, int NT>
 __global__ void __launch_bounds__(kBlock)
 k_axis_mfma(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A, int K,
             int inner, int64_t ncols, FdmDiv dv, const int* stop) {
@@ -222,11 +222,13 @@ k_axis_mfma(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A,
   const int q = lane >> 4, r = lane & 15;
   const int ntr = (K + 15) >> 4;
   const int64_t n0 = (int64_t)blockIdx.x * (16 * NT);
+  // every wave runs MT row tiles; tiles past K read row K - 1 and are
+  // never stored
   const V* ap[MT];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     int m = 16 * (w + 4 * mt) + r;
-    if (m >= K) m = K - 1;                  // rows past K are computed, never stored
+    if (m >= K) m = K - 1;
     ap[mt] = A + (int64_t)m * K + 4 * q;
   }
   const V* xp[NT];
@@ -249,49 +251,52 @@ k_axis_mfma(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A,
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[mt][t] = acc_t{0, 0, 0, 0};
-  Quad<V> a_c[QB][MT], b_c[QB][NT], a_n[QB][MT], b_n[QB][NT];
   auto load = [&](int kb, Quad<V> (*a)[MT], Quad<V> (*b)[NT]) {
 #pragma unroll
     for (int j = 0; j < QB; ++j) {
-      // K % 4 == 0: a quad is all inside or all past K; past K the load is
-      // redirected to the quad at k = 0 of the same line and zeroed
+      // K % 4 == 0: a quad is all inside or all past K.  With TAIL, a quad
+      // past K is read at k = 0 of its line and its operator part zeroed
+      // (the product is then zero whatever the line holds there).
       const int k = kb + 16 * j;
-      const bool ok = k + 4 * q < K;
+      const bool ok = !TAIL || k + 4 * q < K;
       const int ka = ok ? k : -4 * q;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         a[j][mt] = ld_quad<V, true>(ap[mt] + ka, 1);
-        if (!ok) a[j][mt] = Quad<V>{{V(0), V(0), V(0), V(0)}};
+        if (TAIL) {
+          const V z = ok ? V(1) : V(0);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) a[j][mt].v[e] *= z;
+        }
       }
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
+      for (int t = 0; t < NT; ++t)
         b[j][t] = ld_quad<V, XFAST>(xp[t] + (XFAST ? ka : (int64_t)ka * inner), inner);
-        if (!ok) b[j][t] = Quad<V>{{V(0), V(0), V(0), V(0)}};
-      }
     }
   };
-  load(0, a_c, b_c);
-  for (int kb = 0; kb < K; kb += KB) {
-    if (kb + KB < K) load(kb + KB, a_n, b_n);
+  auto compute = [&](const Quad<V> (*a)[MT], const Quad<V> (*b)[NT]) {
 #pragma unroll
     for (int j = 0; j < QB; ++j)
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          if (w + 4 * mt >= ntr) continue;  // wave-uniform: no such row tile
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
           for (int t = 0; t < NT; ++t)
-            acc[mt][t] = Mfma<V>::op(a_c[j][mt].v[s], b_c[j][t].v[s], acc[mt][t]);
-        }
-#pragma unroll
-    for (int j = 0; j < QB; ++j) {
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) a_c[j][mt] = a_n[j][mt];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) b_c[j][t] = b_n[j][t];
-    }
+            acc[mt][t] = Mfma<V>::op(a[j][mt].v[s], b[j][t].v[s], acc[mt][t]);
+  };
+  // two register buffers in ping-pong: batch kb + KB is in flight while
+  // batch kb is multiplied
+  Quad<V> a0[QB][MT], b0[QB][NT], a1[QB][MT], b1[QB][NT];
+  load(0, a0, b0);
+  int kb = 0;
+  for (; kb + KB < K; kb += 2 * KB) {
+    load(kb + KB, a1, b1);
+    compute(a0, b0);
+    if (kb + 2 * KB < K) load(kb + 2 * KB, a0, b0);
+    compute(a1, b1);
   }
+  if (kb < K) compute(a0, b0);
   // epilogue: lane holds D[Mfma<V>::row(lane, v)][col r] of each tile
   double lrest[NT];
   if (DIV) {
@@ -348,6 +353,193 @@ k_axis_mfma(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A,
   }
 }
 
+// LDS-staged variant (K % 32 == 0, K <= 256, and for a strided axis
+// blocks of lines that never straddle two outer indices): per chunk of KC
+// contraction indices the block loads the operator rows (K x KC) and its
+// 16 NT lines (16 NT x KC) with 16-byte coalesced loads into LDS, both
+// stored contraction-contiguous, and each wave reads its MFMA operands back
+// as 16-byte LDS reads (same quad assignment as above).  The next chunk is
+// loaded into registers while the current one is multiplied.  NT is chosen
+// per axis so that the blocks spread evenly over the CUs.
+template <typename V>
+struct LdsGemm {
+  static constexpr int KC = sizeof(V) == 4 ? 32 : 16;   // 128 bytes of a row
+  static constexpr int VW = 16 / sizeof(V);            // elements per 16 B
+  static constexpr int PAD = VW;                       // row padding
+  static constexpr int LD = KC + PAD;                  // LDS row stride
+  static constexpr int RV = KC / VW;                   // 16-byte vectors per row chunk (8)
+};
+
+template <typename V, bool XFAST, bool DIV, int MT, int NT>
+__global__ void __launch_bounds__(kBlock)
+k_axis_lds(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A, int K, int inner,
+           int64_t ncols, FdmDiv dv, const int* stop) {
+  if (stop && *stop) return;
+  typedef LdsGemm<V> L;
+  typedef typename Mfma<V>::acc_t acc_t;
+  constexpr int NC = 16 * NT;
+  constexpr int RV = L::RV;
+  typedef __attribute__((ext_vector_type(L::VW))) V vec_t;
+  __shared__ __attribute__((aligned(16))) V As[256 * L::LD];
+  __shared__ __attribute__((aligned(16))) V Xs[NC * L::LD];
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int q = lane >> 4, r = lane & 15;
+  const int ntr = K >> 4;
+  const int64_t n0 = (int64_t)blockIdx.x * NC;
+  // strided axis: the block's lines are consecutive inner indices of one
+  // outer index
+  const int64_t o0 = XFAST ? 0 : n0 / inner;
+  const int64_t i0 = XFAST ? 0 : n0 - o0 * inner;
+  const V* xbase = XFAST ? X : X + o0 * (int64_t)K * inner + i0;
+  // per-thread global chunk loads: operator rows (K * RV vectors, a whole
+  // number K / 32 per thread since K % 32 == 0) and lines (NC * RV vectors)
+  constexpr int AV = 256 * RV / kBlock;                 // at most 8 per thread
+  constexpr int XV = (NC * RV + kBlock - 1) / kBlock;
+  const int av = K * RV / kBlock;                       // wave-uniform
+  vec_t ra[AV], rx[XV];
+  auto gload = [&](int kc) {
+#pragma unroll
+    for (int u = 0; u < AV; ++u) {
+      if (u < av) {
+        const int e = t + u * kBlock;
+        const int m = e / RV, f = e - m * RV;
+        ra[u] = *reinterpret_cast<const vec_t*>(A + (int64_t)m * K + kc + f * L::VW);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < XV; ++u) {
+      const int e = t + u * kBlock;
+      if ((NC * RV) % kBlock == 0 || e < NC * RV) {
+        if (XFAST) {
+          const int col = e / RV, f = e - col * RV;
+          int64_t n = n0 + col;
+          if (n >= ncols) n = ncols - 1;
+          rx[u] = *reinterpret_cast<const vec_t*>(X + n * (int64_t)K + kc + f * L::VW);
+        } else {
+          constexpr int CV = NC / L::VW;                  // vectors per index row
+          const int k = e / CV, c = e - k * CV;
+          rx[u] = *reinterpret_cast<const vec_t*>(xbase + (int64_t)(kc + k) * inner + c * L::VW);
+        }
+      }
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int u = 0; u < AV; ++u) {
+      if (u < av) {
+        const int e = t + u * kBlock;
+        const int m = e / RV, f = e - m * RV;
+        *reinterpret_cast<vec_t*>(As + m * L::LD + f * L::VW) = ra[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < XV; ++u) {
+      const int e = t + u * kBlock;
+      if ((NC * RV) % kBlock == 0 || e < NC * RV) {
+        if (XFAST) {
+          const int col = e / RV, f = e - col * RV;
+          *reinterpret_cast<vec_t*>(Xs + col * L::LD + f * L::VW) = rx[u];
+        } else {
+          constexpr int CV = NC / L::VW;
+          const int k = e / CV, c = e - k * CV;
+#pragma unroll
+          for (int j = 0; j < L::VW; ++j) Xs[(c * L::VW + j) * L::LD + k] = rx[u][j];
+        }
+      }
+    }
+  };
+  acc_t acc[MT][NT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) acc[mt][tt] = acc_t{0, 0, 0, 0};
+  gload(0);
+  for (int kc = 0; kc < K; kc += L::KC) {
+    __syncthreads();                 // previous chunk fully consumed
+    sstore();
+    __syncthreads();
+    if (kc + L::KC < K) gload(kc + L::KC);
+#pragma unroll
+    for (int g = 0; g < L::KC / 16; ++g) {
+      const int kq = 16 * g + 4 * q;   // this lane group's quad in the chunk
+      Quad<V> xa[NT];
+#pragma unroll
+      for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) xa[tt].v[e] = Xs[(16 * tt + r) * L::LD + kq + e];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int tile = w + 4 * mt;
+        if (tile >= ntr) continue;     // wave-uniform
+        Quad<V> aa;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) aa.v[e] = As[(16 * tile + r) * L::LD + kq + e];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int tt = 0; tt < NT; ++tt)
+            acc[mt][tt] = Mfma<V>::op(aa.v[s], xa[tt].v[s], acc[mt][tt]);
+      }
+    }
+  }
+  // epilogue (as in k_axis_mfma)
+  double lrest[NT];
+  if (DIV) {
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      const int64_t n = n0 + 16 * tt + r;
+      int64_t rem = XFAST ? 0 : (n % inner);
+      double ls = 0.0;
+      int allz = 1;
+      for (int b = 0; b < dv.axis; ++b) {
+        const int mb = (int)(rem % dv.n[b]);
+        rem /= dv.n[b];
+        ls += dv.lam[b][mb];
+        allz &= (mb == 0);
+      }
+      lrest[tt] = allz ? -1.0 : ls;
+    }
+  }
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int tile = w + 4 * mt;
+    if (tile >= ntr) continue;
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      const int64_t n = n0 + 16 * tt + r;
+      if (n >= ncols) continue;
+      int64_t base;
+      if (XFAST) {
+        base = n * (int64_t)K;
+      } else {
+        const int64_t o = n / inner, i = n - o * inner;
+        base = o * (int64_t)K * inner + i;
+      }
+      if constexpr (XFAST && !DIV && sizeof(V) == 4) {
+        const acc_t& c = acc[mt][tt];
+        *reinterpret_cast<float4*>(Y + base + 16 * tile + 4 * q) = make_float4(c[0], c[1], c[2], c[3]);
+        continue;
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = 16 * tile + Mfma<V>::row(lane, v);
+        V val = acc[mt][tt][v];
+        if (DIV) {
+          const bool zero = (lrest[tt] < 0.0) && m == 0;
+          const double ls = (lrest[tt] < 0.0 ? 0.0 : lrest[tt]) + dv.lam[dv.axis][m];
+          val = zero ? V(0) : (V)((double)val / ls);
+        }
+        if (XFAST)
+          Y[base + m] = val;
+        else
+          Y[base + (int64_t)m * inner] = val;
+      }
+    }
+  }
+}
+
 // p += d (refinement correction, double accumulator)
 template <typename V>
 __global__ void __launch_bounds__(kBlock)
@@ -368,6 +560,31 @@ k_gauge(int64_t n, double* __restrict__ p, const SolverScalars* sc, double inv_n
 }
 
 // ------------------------------------------------------------- launchers
+// Lines per block of k_axis_lds (in units of 16).  A strided axis takes 2
+// (its lines are transposed into LDS; wider blocks measured slower on
+// gfx950), else 1, and needs blocks that stay inside one outer index.  The
+// contiguous axis takes the count whose blocks fill the CUs most evenly by
+// a simple model (a block costs its tiles plus a fixed start-up of about
+// 1.5 tiles; blocks run in rounds of one per CU).  0: no count fits.
+static int lds_line_tiles(int64_t ncols, int inner) {
+  constexpr int kCUs = 256;
+  if (inner != 1) return inner % 32 == 0 ? 2 : (inner % 16 == 0 ? 1 : 0);
+  int best = 0;
+  double best_cost = 1e300;
+  for (int nt = 1; nt <= 6; ++nt) {
+    const int nc = 16 * nt;
+    if (inner != 1 && inner % nc != 0) continue;
+    const int64_t blocks = (ncols + nc - 1) / nc;
+    const int64_t rounds = (blocks + kCUs - 1) / kCUs;
+    const double cost = (double)rounds * (nt + 1.5);
+    if (cost < best_cost - 1e-9) {
+      best_cost = cost;
+      best = nt;
+    }
+  }
+  return best;
+}
+
 template <typename V>
 int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, const int* stop,
                     hipStream_t s) {
@@ -379,13 +596,52 @@ int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, c
   const int64_t ncols = outer * inner;
   const V* Am = fwd ? F.phiT[a] : F.phi[a];
   const bool div = fwd && a == F.dim - 1;
+  const int nt = (K % 32 == 0 && K <= 256) ? lds_line_tiles(ncols, inner) : 0;
+  if (nt > 0) {
+    const dim3 g((unsigned)((ncols + 16 * nt - 1) / (16 * nt)));
+    const int mt = (K / 16 + 3) / 4;
+#define FVIB_AL(XF, DV, MT, NT)                                                                 \
+    hipLaunchKernelGGL((k_axis_lds<V, XF, DV, MT, NT>), g, dim3(kBlock), 0, s, in, out, Am, K,  \
+                       inner, ncols, F.div, stop)
+#define FVIB_ALN(XF, DV, MT)                                                                    \
+    switch (nt) {                                                                               \
+      case 1: FVIB_AL(XF, DV, MT, 1); break;                                                    \
+      case 2: FVIB_AL(XF, DV, MT, 2); break;                                                    \
+      case 3: FVIB_AL(XF, DV, MT, 3); break;                                                    \
+      case 4: FVIB_AL(XF, DV, MT, 4); break;                                                    \
+      case 5: FVIB_AL(XF, DV, MT, 5); break;                                                    \
+      default: FVIB_AL(XF, DV, MT, 6); break;                                                   \
+    }
+#define FVIB_ALM(XF, DV)                                                                        \
+    switch (mt) {                                                                               \
+      case 1: FVIB_ALN(XF, DV, 1) break;                                                        \
+      case 2: FVIB_ALN(XF, DV, 2) break;                                                        \
+      case 3: FVIB_ALN(XF, DV, 3) break;                                                        \
+      default: FVIB_ALN(XF, DV, 4) break;                                                       \
+    }
+    if (inner == 1) {
+      if (div) { FVIB_ALM(true, true) } else { FVIB_ALM(true, false) }
+    } else {
+      if (div) { FVIB_ALM(false, true) } else { FVIB_ALM(false, false) }
+    }
+#undef FVIB_ALM
+#undef FVIB_ALN
+#undef FVIB_AL
+    FVIB_HIP(hipGetLastError());
+    return FVIB_OK;
+  }
   if (K % 4 == 0 && K <= 256) {
     constexpr int NT = 2;
     const dim3 g((unsigned)((ncols + 16 * NT - 1) / (16 * NT)));
     const int mt = (K + 63) / 64;
+    const bool tail = K % (sizeof(V) == 4 ? 32 : 16) != 0;
 #define FVIB_AX(XF, DV, MT)                                                                     \
-    hipLaunchKernelGGL((k_axis_mfma<V, XF, DV, MT, NT>), g, dim3(kBlock), 0, s, in, out, Am, K, \
-                       inner, ncols, F.div, stop)
+    if (tail)                                                                                   \
+      hipLaunchKernelGGL((k_axis_mfma<V, XF, DV, true, MT, NT>), g, dim3(kBlock), 0, s, in, out, \
+                         Am, K, inner, ncols, F.div, stop);                                     \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_axis_mfma<V, XF, DV, false, MT, NT>), g, dim3(kBlock), 0, s, in,    \
+                         out, Am, K, inner, ncols, F.div, stop)
 #define FVIB_AXM(XF, DV)                                                                        \
     switch (mt) {                                                                               \
       case 1: FVIB_AX(XF, DV, 1); break;                                                        \

@@ -94,6 +94,7 @@ struct FinResidual {        // start of a solve / refinement sweep
   __device__ void apply(const double* t, SolverScalars* sc) const {
     sc->sweeps = first ? 0 : sc->sweeps + 1;
     const double crit = t[2] * dt_over_rho;
+    const double tol = this->tol < 0.0 ? sc->tol_dev : this->tol;
     sc->rr = t[0];
     sc->rr0 = t[0];
     sc->beta = 0.0;
@@ -138,7 +139,7 @@ struct FinCgUpdate {
     bool conv;
     if (MODE == 0) {
       sc->crit = t[1] * dt_over_rho;
-      conv = sc->crit <= tol;
+      conv = sc->crit <= (tol < 0.0 ? sc->tol_dev : tol);
     } else {
       conv = rrn <= sc->tol_rr;
     }
@@ -224,28 +225,91 @@ k_ppe_rhs(Geo<T> G, PGeo<double> P, Tiling tl, const T* __restrict__ s0,
 // for the pressure gauge.
 template <int DIM, int MODE>
 __global__ void __launch_bounds__(kBlock)
-k_residual(PGeo<double> P, Tiling tl, const double* __restrict__ b,
+k_residual(PGeo<double> P, ColTiling ct, const double* __restrict__ b,
            const double* __restrict__ x, double* __restrict__ r64, float* __restrict__ r32,
            float* __restrict__ d32, RedBuf red, SolverScalars* sc, int first) {
   if (!first && sc->outer_done) return;
-  const int nx_ = P.n[0], ny_ = P.n[1];
+  const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+  const int64_t sxy = (int64_t)nx * ny;
   const double mb = sc->meanb;
   double rr = 0.0, sx = 0.0, mx = 0.0;
-  auto get = [&](int a, int b_, int c) { return x[((int64_t)c * ny_ + b_) * nx_ + a]; };
-  FVIB_TILE_LOOP(tl)
-    const double xc = x[c_];
-    const double ivol = inv_volume(P, i, j, k);
-    const double r = b[c_] - mb - apply_A<double, DIM>(P, get, i, j, k, xc);
-    if (MODE == 0 || MODE == 3) {
-      r64[c_] = r;
-    } else {
-      r32[c_] = (float)r;
-      if (MODE == 1) d32[c_] = 0.0f;
+  const int lx = threadIdx.x & (kTileX - 1), ly = threadIdx.x / kTileX;
+  for (int u = xcd_block(blockIdx.x, gridDim.x); u < ct.nunits; u += gridDim.x) {
+    const int tx = u % ct.ntx, ty = (u / ct.ntx) % ct.nty, zc = u / (ct.ntx * ct.nty);
+    const int i = tx * kTileX + lx, j = ty * kTileY + ly;
+    if (i >= nx || j >= ny) continue;
+    const int k0 = zc * ct.zchunk, k1 = min(k0 + ct.zchunk, nz);
+    // column constants: x-y neighbours (wrapped / clamped, the boundary
+    // faces carry kf = 0) and coefficients
+    const int64_t cC = (int64_t)j * nx + i;
+    const int64_t cW = (int64_t)j * nx + nb_lo(i, nx, P.per[0]);
+    const int64_t cE = (int64_t)j * nx + nb_hi(i, nx, P.per[0]);
+    const int64_t cS = (int64_t)nb_lo(j, ny, P.per[1]) * nx + i;
+    const int64_t cN = (int64_t)nb_hi(j, ny, P.per[1]) * nx + i;
+    const double dxi = P.dx[0][i], dyj = P.dx[1][j];
+    const double kxl = P.kf[0][i], kxh = P.kf[0][i + 1];
+    const double kyl = P.kf[1][j], kyh = P.kf[1][j + 1];
+    const double ivxy = (double)P.iv[0][i] * (double)P.iv[1][j];
+    auto emit = [&](int k, double xc, double r, double iv) {
+      const int64_t c = (int64_t)k * sxy + cC;
+      if (MODE == 0 || MODE == 3) {
+        r64[c] = r;
+      } else {
+        r32[c] = (float)r;
+        if (MODE == 1) d32[c] = 0.0f;
+      }
+      rr += r * r;
+      sx += xc;
+      mx = fmax(mx, fabs(r) * iv);
+    };
+    if (DIM == 2) {
+      // same term order as apply_A
+      const double xc = x[cC];
+      double acc = 0.0;
+      acc += dyj * kxl * (xc - x[cW]);
+      acc += dyj * kxh * (xc - x[cE]);
+      acc += dxi * kyl * (xc - x[cS]);
+      acc += dxi * kyh * (xc - x[cN]);
+      emit(0, xc, b[cC] - mb - acc, ivxy);
+      continue;
     }
-    rr += r * r;
-    sx += xc;
-    mx = fmax(mx, fabs(r) * ivol);
-  FVIB_TILE_END
+    const int pz = P.per[2];
+    auto at = [&](int64_t off, int k) { return x[(int64_t)k * sxy + off]; };
+    double xm = at(cC, nb_lo(k0, nz, pz)), xc = at(cC, k0), xp = at(cC, nb_hi(k0, nz, pz));
+    double w = at(cW, k0), e = at(cE, k0), so = at(cS, k0), no = at(cN, k0);
+    double bb = b[(int64_t)k0 * sxy + cC];
+    for (int k = k0; k < k1; ++k) {
+      // plane k + 1 is fetched while plane k is evaluated
+      double xp2 = 0.0, w2 = 0.0, e2 = 0.0, so2 = 0.0, no2 = 0.0, bb2 = 0.0;
+      if (k + 1 < k1) {
+        xp2 = at(cC, nb_hi(k + 1, nz, pz));
+        w2 = at(cW, k + 1);
+        e2 = at(cE, k + 1);
+        so2 = at(cS, k + 1);
+        no2 = at(cN, k + 1);
+        bb2 = b[(int64_t)(k + 1) * sxy + cC];
+      }
+      const double dzk = P.dx[2][k], kzl = P.kf[2][k], kzh = P.kf[2][k + 1];
+      // same term order as apply_A
+      double acc = 0.0;
+      const double ax = dyj * dzk, ay = dxi * dzk, az = dxi * dyj;
+      acc += ax * kxl * (xc - w);
+      acc += ax * kxh * (xc - e);
+      acc += ay * kyl * (xc - so);
+      acc += ay * kyh * (xc - no);
+      acc += az * kzl * (xc - xm);
+      acc += az * kzh * (xc - xp);
+      emit(k, xc, bb - mb - acc, ivxy * (double)P.iv[2][k]);
+      xm = xc;
+      xc = xp;
+      xp = xp2;
+      w = w2;
+      e = e2;
+      so = so2;
+      no = no2;
+      bb = bb2;
+    }
+  }
   double v[3] = {rr, sx, mx};
   block_partials<3, 2>(v, red.partial);
 }
@@ -416,13 +480,13 @@ int launch_ppe_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
 int launch_residual(const PGeo<double>& P, int mode, const double* b, const double* x,
                     double* r64, float* r32, float* d32, RedBuf red, SolverScalars* sc,
                     double tol, double inner_rtol, hipStream_t s, int first) {
-  const Tiling tl = red_tiling(P.n);
-  dim3 g(tl.nblocks), bl(kBlock);
+  const ColTiling ct = make_col_tiling(P.n[0], P.n[1], P.n[2]);
+  dim3 g(ct.nblocks), bl(kBlock);
 #define FVIB_RES(D, M)                                                                        \
-  hipLaunchKernelGGL((k_residual<D, M>), g, bl, 0, s, P, tl, b, x, r64, r32, d32, red, sc,      \
+  hipLaunchKernelGGL((k_residual<D, M>), g, bl, 0, s, P, ct, b, x, r64, r32, d32, red, sc,      \
                      first);                                                                    \
   FVIB_HIP(hipGetLastError());                                                                  \
-  FVIB_HIP((launch_finish<3, 2>(red.partial, tl.nblocks, sc,                                    \
+  FVIB_HIP((launch_finish<3, 2>(red.partial, ct.nblocks, sc,                                    \
                                 FinResidual<M>{tol, inner_rtol, P.dt_over_rho, first}, s)))
   if (P.dim == 2) {
     switch (mode) {

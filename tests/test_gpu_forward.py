@@ -106,6 +106,26 @@ def test_poisson_solution_parity(case, precision, solver):
     assert err <= 1e-9 * float(pe.abs().max()), (err, iters)
 
 
+@pytest.mark.parametrize("dims", [(192, 128, 160), (64, 32, 96), (96, 256, 32)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_poisson_parity_channel_shapes(dims, precision):
+    """Fast-diagonalisation solve at the channel's production shape (and
+    shapes whose axes take the other operator-tile counts), against the
+    oracle's exact solve."""
+    need_gpu()
+    from oracle import Grid as OGrid
+    from oracle.poisson import solver as exact
+    nx, ny, nz = dims
+    w = W.channel(nx=nx, ny=ny, nz=nz)
+    g = make_grid(w, precision=precision, poisson_tol=1e-12, inner_rtol=1e-3, solver="fdm")
+    og = OGrid(w)
+    b = torch.tensor(W.random_cells(w, 11))
+    p, _ = g.test_poisson(b.to(g.device))
+    pe = exact(og).solve(b - b.mean())
+    err = float((gauge(p.cpu()) - pe).abs().max())
+    assert err <= 1e-9 * float(pe.abs().max()), (dims, precision, err)
+
+
 @pytest.mark.parametrize("name", ["cylinder", "viv"])
 def test_ib_classification_bit_exact(name):
     need_gpu()
