@@ -45,6 +45,8 @@ def kernel_cost(d: int, s: int, mixed: bool, n: tuple):
         "fdm_x": ("flops", 2 * n[0]),                      # dense contraction along x
         "fdm_y": ("flops", 2 * n[1]),
         "fdm_z": ("flops", 2 * n[2]),
+        # last axis forward + division + inverse in one launch
+        "fdm_last": ("flops", 4 * n[2 if d == 3 else 1]),
     }
 
 

@@ -270,6 +270,7 @@ enum {
   FVIB_K_FDM_Y = 11,      /* ... along y                                   */
   FVIB_K_FDM_Z = 12,      /* ... along z                                   */
   FVIB_K_ADJ_MOMENTUM = 13, /* transposed momentum stencil (all components) */
+  FVIB_K_FDM_LAST = 14,   /* last axis: forward, division and inverse in one */
   FVIB_K_NCLASSES = 16
 };
 
@@ -284,6 +285,15 @@ int fvib_timing_select(fvib_grid *g, uint32_t class_mask);
 /* Total device time (ms) and launch count of one kernel class since the
  * last enable; synchronises the stream. */
 int fvib_timing_read(fvib_grid *g, int kclass, double *total_ms, int64_t *launches);
+
+/* Deferred status (on != 0): fvib_step and fvib_step_adjoint return as soon
+ * as the step's work is enqueued instead of waiting for it, so the host can
+ * enqueue the next step while this one runs.  A Poisson solve that exhausts
+ * its refinement budget is still reported at once (the solve polls its
+ * convergence); every other device-side condition (body window left,
+ * non-finite reduction) is reported only in info->status, which the caller
+ * reads after synchronising the stream.  Off by default. */
+int fvib_defer_status(fvib_grid *g, int on);
 
 /* Build version string. */
 const char *fvib_version(void);

@@ -265,7 +265,8 @@ class Grid:
 
     # --------------------------------------------------------- adjoint
     def step_adjoint(self, u, fb, body, kc, ubar_out, bodybar_out, dF, ubar_in, bodybar_in,
-                     fbbar=None, kcbar=None, check: bool = True) -> int:
+                     fbbar=None, kcbar=None, check: bool = True,
+                     info: Optional[torch.Tensor] = None) -> int:
         fin = self._fields(u, None, fb, body, kc)
         fin.p = 0
         bo = _abi.Adjoint()
@@ -277,7 +278,8 @@ class Grid:
         bo.body = _ptr(bodybar_out)
         bi.body = _ptr(bodybar_in)
         bi.kc = _ptr(kcbar)
-        rc = fvib_step_adjoint(self.h, fin, bo, _ptr(dF), bi, _ptr(self._info))
+        rc = fvib_step_adjoint(self.h, fin, bo, _ptr(dF), bi,
+                               _ptr(info if info is not None else self._info))
         if check:
             _check(rc, self.h)
         return rc
@@ -295,6 +297,21 @@ class Grid:
         _check(fvib_loss_rms_lift(self.h, _ptr(Fh), nsteps, stride, offset, u_ref, diameter,
                                   _ptr(J), _ptr(dFh)), self.h)
         return J
+
+    # --------------------------------------------------------- deferred status
+    def defer_status(self, on: bool = True) -> None:
+        """Steps return once enqueued; their status is only in the info
+        records (see check_infos)."""
+        _check(lib().fvib_defer_status(self.h, 1 if on else 0), self.h)
+
+    def check_infos(self, infos: torch.Tensor, what: str = "step") -> None:
+        """Raise if any fvib_step_info record (rows of a float64 tensor)
+        holds a non-zero status (synchronises with the device)."""
+        st = infos.reshape(-1, INFO_DOUBLES).view(torch.int32)[:, 0].cpu()
+        bad = torch.nonzero(st).flatten()
+        if bad.numel():
+            n = int(bad[0])
+            raise RuntimeError(f"libfvib {what} {n}: status {int(st[n])}")
 
     # --------------------------------------------------------- timing
     def timing_enable(self, on: bool = True, classes=None) -> None:

@@ -117,6 +117,7 @@ struct Grid {
   double* body_tmp = nullptr;     // scratch body state (adjoint recomputation)
   int last_iters = 0;
   int last_iters_adj = 0;
+  bool defer = false;        // steps return once enqueued (fvib_defer_status)
   // immersed body
   bool has_body = false;
   IbGeo ib;
@@ -467,8 +468,11 @@ static int read_scalars(Grid* g) {
 
 // Solve A p = b - mean(b) in place on p (initial guess on input); meanb
 // must already be in the device scalars.
+// gauge: remove the mean of the fast-diagonalisation result (the pressure
+// returned by a step); the adjoint pressure enters only through differences
+// and skips it.
 static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* last,
-                         int* cg_total, int* ir_total) {
+                         int* cg_total, int* ir_total, bool gauge = true) {
   int rc;
   *cg_total = 0;
   *ir_total = 0;
@@ -498,22 +502,38 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
       });
     };
     auto sweep = [&]() -> int {
-      // d = A^+ r by fast diagonalisation (forward axes, then inverse axes)
-      for (int pass = 0; pass < 2 * g->dim; ++pass) {
+      // d = A^+ r by fast diagonalisation: forward axes, then inverse axes,
+      // through two scratch buffers; the last forward axis may carry the
+      // first inverse one in the same launch
+      const int np = 2 * g->dim;
+      int pass = 0, buf = 0;
+      while (pass < np) {
         const bool fwd = pass < g->dim;
-        const int a = fwd ? pass : 2 * g->dim - 1 - pass;
-        const bool lastp = pass == 2 * g->dim - 1;
-        int r2 = timed(g, FVIB_K_FDM_X + a, [&] {
+        const int a = fwd ? pass : np - 1 - pass;
+        const bool can_fuse = fwd && pass == g->dim - 1;
+        const bool will_fuse = can_fuse && (d64 ? fdm_fuses_last_axis<double>(g->F64)
+                                                : fdm_fuses_last_axis<float>(g->F32));
+        bool fused = false;
+        int r2 = timed(g, will_fuse ? FVIB_K_FDM_LAST : FVIB_K_FDM_X + a, [&] {
+          // the last pass writes d (with dim >= 2 a fused launch never ends
+          // the sweep)
+          const bool ends = pass == np - 1;
           if (d64) {
-            const double* in = (pass == 0) ? g->r64 : ((pass % 2) ? g->pA64 : g->pB64);
-            double* out = lastp ? g->d64 : ((pass % 2) ? g->pB64 : g->pA64);
-            return launch_fdm_axis<double>(g->F64, a, fwd, in, out, stop, g->stream);
+            const double* in = (pass == 0) ? g->r64 : (buf ? g->pB64 : g->pA64);
+            double* outp = (buf ? g->pA64 : g->pB64);
+            if (ends) outp = g->d64;
+            return launch_fdm_axis<double>(g->F64, a, fwd, in, outp, stop, g->stream,
+                                           can_fuse ? &fused : nullptr);
           }
-          const float* in = (pass == 0) ? g->r32 : ((pass % 2) ? g->pA32 : g->pB32);
-          float* out = lastp ? g->d32 : ((pass % 2) ? g->pB32 : g->pA32);
-          return launch_fdm_axis<float>(g->F32, a, fwd, in, out, stop, g->stream);
+          const float* in = (pass == 0) ? g->r32 : (buf ? g->pB32 : g->pA32);
+          float* outp = (buf ? g->pA32 : g->pB32);
+          if (ends) outp = g->d32;
+          return launch_fdm_axis<float>(g->F32, a, fwd, in, outp, stop, g->stream,
+                                        can_fuse ? &fused : nullptr);
         });
         if (r2) return r2;
+        pass += fused ? 2 : 1;
+        buf ^= 1;
       }
       int r2 = timed(g, FVIB_K_IR_CORRECT, [&] {
         return d64 ? launch_add_correction<double>(g->ncell, p, g->d64, stop, g->stream)
@@ -536,11 +556,13 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
         int stc = FVIB_ENOCONV;
         FVIB_HIP(hipMemcpyAsync(&g->sc->status, &stc, sizeof(int), hipMemcpyHostToDevice, g->stream));
         FVIB_HIP(hipStreamSynchronize(g->stream));
+        g->sch->status = FVIB_ENOCONV;
         break;
       }
       batch = 1;
     }
-    if ((rc = timed(g, FVIB_K_IR_CORRECT, [&] { return launch_gauge(g->ncell, p, g->sc, g->stream); })))
+    if (gauge &&
+        (rc = timed(g, FVIB_K_IR_CORRECT, [&] { return launch_gauge(g->ncell, p, g->sc, g->stream); })))
       return rc;
     const int sweeps = g->sch->outer_done ? g->sch->sweeps : launched;
     g->last_iters = sweeps;
@@ -681,6 +703,9 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
   int last = g->last_iters;
   if ((rc = poisson_solve(g, g->b, out->p, g->d.poisson_tol, &last, &cg, &ir))) return rc;
   g->last_iters = last;
+  if (g->defer && g->sch->status == FVIB_ENOCONV)
+    return fail(g, FVIB_ENOCONV,
+                "Poisson solve did not reach poisson_tol" + describe_solve(g, g->d.poisson_tol));
   if ((rc = timed(g, FVIB_K_PROJECT, [&] {
          return launch_project<T>(G, g->P64, (const T* const*)us, out->p, uo, g->red(), g->sc,
                                   g->stream);
@@ -694,6 +719,10 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
   }
   fvib_step_info* dst = info ? info : g->info_dev;
   if ((rc = launch_copy_info(g->sc, dst, cg, ir, g->stream))) return rc;
+  if (g->defer) {                // status only in the info record
+    g->err.clear();
+    return FVIB_OK;
+  }
   if ((rc = read_scalars(g))) return rc;
   if (g->timer.on) g->timer.resolve();
   int st = g->sch->status;
@@ -762,13 +791,16 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
   // floor of the residual (~eps |A mu|) above it when the right-hand side
   // is small (e.g. zero up to rounding).
   FVIB_HIP(hipMemsetAsync(g->mu, 0, g->ncell * sizeof(double), g->stream));
-  if ((rc = poisson_solve(g, g->b, g->mu, -1.0, &g->last_iters_adj, &cg, &ir))) return rc;
+  if ((rc = poisson_solve(g, g->b, g->mu, -1.0, &g->last_iters_adj, &cg, &ir, false))) return rc;
+  if (g->defer && g->sch->status == FVIB_ENOCONV)
+    return fail(g, FVIB_ENOCONV, "adjoint Poisson solve did not converge" +
+                                     describe_solve(g, g->sch->tol_dev));
   if ((rc = timed(g, FVIB_K_ADJOINT,
-                  [&] { return launch_adj_ustar<T>(G, g->P64, ub1, g->mu, ib, usb, g->stream); })))
+                  [&] { return launch_adj_ustar<T>(G, g->P64, ub1, g->mu, ib, usb, g->sc, g->stream); })))
     return rc;
   if (g->has_body && bi->body) {
     rc = timed(g, FVIB_K_IB, [&] {
-      return launch_adj_ubody<T>(G, g->P64, g->ib, ub1, g->mu, ib, bi->body, g->stream);
+      return launch_adj_ubody<T>(G, g->P64, g->ib, ub1, g->mu, ib, bi->body, g->sc, g->stream);
     });
     if (rc) return rc;
   }
@@ -786,6 +818,10 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
     return rc;
   fvib_step_info* dst = info ? info : g->info_dev;
   if ((rc = launch_copy_info(g->sc, dst, cg, ir, g->stream))) return rc;
+  if (g->defer) {                // status only in the info record
+    g->err.clear();
+    return FVIB_OK;
+  }
   if ((rc = read_scalars(g))) return rc;
   if (g->timer.on) g->timer.resolve();
   const int st = g->sch->status;
@@ -1276,6 +1312,12 @@ int fvib_timing_enable(fvib_grid* h, int enable) {
   g->timer.resolve();
   g->timer.clear();
   g->timer.on = enable != 0;
+  return FVIB_OK;
+}
+
+int fvib_defer_status(fvib_grid* h, int on) {
+  if (!h) return FVIB_EINVAL;
+  h->g.defer = on != 0;
   return FVIB_OK;
 }
 

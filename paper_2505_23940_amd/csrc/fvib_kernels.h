@@ -94,11 +94,15 @@ template <typename T>
 int launch_adj_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const ub[3], double* y,
                    RedBuf red, SolverScalars* sc, double rtol, hipStream_t s);
 template <typename T>
+// mu is used at zero mean: sc->sumx is its sum (measured by the solve's
+// last residual sweep)
 int launch_adj_ustar(const Geo<T>& G, const PGeo<double>& P, const T* const ub1[3],
-                     const double* mu, const IbView<T>& ib, T* usb[3], hipStream_t s);
+                     const double* mu, const IbView<T>& ib, T* usb[3], const SolverScalars* sc,
+                     hipStream_t s);
 template <typename T>
 int launch_adj_ubody(const Geo<T>& G, const PGeo<double>& P, const IbGeo& B, const T* const ub1[3],
-                     const double* mu, const IbView<T>& ib, double* stbar, hipStream_t s);
+                     const double* mu, const IbView<T>& ib, double* stbar,
+                     const SolverScalars* sc, hipStream_t s);
 template <typename T>
 int launch_adj_outflow(const Geo<T>& G, const Planes& PL, int mode, T* usb[3], T* ubar[3],
                        RedBuf red, SolverScalars* sc, hipStream_t s);
@@ -107,9 +111,15 @@ int launch_adj_momentum(const Geo<T>& G, const T* const u[3], const T* const usb
                         const IbView<T>& ib, T* ubar[3], T* fbbar[3], hipStream_t s);
 
 // k_fdm.hip
+// Whether launch_fdm_axis fuses the last forward and first inverse axis.
+template <typename V>
+bool fdm_fuses_last_axis(const FdmPlan<V>& F);
+// fused (nullable): on the last forward axis, ask for the first inverse
+// contraction of the same axis to run in the same launch; *fused tells
+// whether it did (out then holds the inverse-transformed values).
 template <typename V>
 int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, const int* stop,
-                    hipStream_t s);
+                    hipStream_t s, bool* fused = nullptr);
 template <typename V>
 int launch_add_correction(int64_t n, double* p, const V* d, const int* stop, hipStream_t s);
 int launch_gauge(int64_t n, double* p, const SolverScalars* sc, hipStream_t s);

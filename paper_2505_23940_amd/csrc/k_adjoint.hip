@@ -276,10 +276,11 @@ __device__ __forceinline__ int forced_cls(const IbView<T>& ib, int i, int j, int
   return ib.cls[C][*lidx];
 }
 
-// (S^T mu)_f = A_f (mu_{f-1} - mu_f) with the cells that exist.
+// (S^T mu)_f = A_f (mu_{f-1} - mu_f) with the cells that exist, mu taken at
+// zero mean (mu - shift).
 template <int C, typename T>
 __device__ __forceinline__ double st_mu(const Geo<T>& G, const PGeo<double>& P,
-                                        const double* mu, int i, int j, int k) {
+                                        const double* mu, int i, int j, int k, double shift) {
   const int I[3] = {i, j, k};
   const int ic = I[C], nc = G.n[C];
   double A = 1.0;
@@ -290,32 +291,85 @@ __device__ __forceinline__ double st_mu(const Geo<T>& G, const PGeo<double>& P,
   int L[3] = {i, j, k};
   if (G.per[C] || ic > 0) {
     L[C] = (ic == 0) ? nc - 1 : ic - 1;
-    lo = mu[((int64_t)L[2] * ny + L[1]) * nx + L[0]];
+    lo = mu[((int64_t)L[2] * ny + L[1]) * nx + L[0]] - shift;
   }
   if (G.per[C] || ic < nc) {
     int H[3] = {i, j, k};
     H[C] = (ic == nc) ? 0 : ic;
-    hi = mu[((int64_t)H[2] * ny + H[1]) * nx + H[0]];
+    hi = mu[((int64_t)H[2] * ny + H[1]) * nx + H[0]] - shift;
   }
   return A * (lo - hi);
 }
 
-// ustar_bar = ubar^{n+1} + (1 - eps) S^T mu on every face of component C.
-template <int C, typename T>
+// ustar_bar = ubar^{n+1} + (1 - eps) S^T mu on every face, all components
+// in one launch.  Each thread walks a z-column of a tile chunk and owns the
+// low faces of its cells (and the high face of the last cell of a bounded
+// axis); mu is taken at zero mean (its mean is the solve's last measured
+// sum / n, so the solve itself needs no gauge pass).
+template <typename T, int DIM>
 __global__ void __launch_bounds__(kBlock)
-k_adj_ustar(Geo<T> G, PGeo<double> P, const T* __restrict__ ubar1, const double* __restrict__ mu,
-            IbView<T> ib, T* __restrict__ usb) {
-  const int e0 = G.ext[C][0], e1 = G.ext[C][1], e2 = G.ext[C][2];
-  const int64_t n = (int64_t)e0 * e1 * e2;
-  for (int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x; id < n;
-       id += (int64_t)gridDim.x * kBlock) {
-    const int i = (int)(id % e0);
-    const int j = (int)((id / e0) % e1);
-    const int k = (int)(id / ((int64_t)e0 * e1));
-    double v = (double)ubar1[id];
-    int li;
-    if (!forced_cls<C>(ib, i, j, &li)) v += st_mu<C>(G, P, mu, i, j, k);
-    usb[id] = (T)v;
+k_adj_ustar(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__ b0,
+            const T* __restrict__ b1, const T* __restrict__ b2, const double* __restrict__ mu,
+            IbView<T> ib, T* __restrict__ s0, T* __restrict__ s1, T* __restrict__ s2,
+            const SolverScalars* sc) {
+  const T* ub[3] = {b0, b1, b2};
+  T* us[3] = {s0, s1, s2};
+  const double shift = sc->sumx * P.inv_ncell;
+  const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
+  const int64_t sxy = (int64_t)nx * ny;
+  const int lx = threadIdx.x & (kTileX - 1), ly = threadIdx.x / kTileX;
+  for (int u = xcd_block(blockIdx.x, gridDim.x); u < ct.nunits; u += gridDim.x) {
+    const int tx = u % ct.ntx, ty = (u / ct.ntx) % ct.nty, zc = u / (ct.ntx * ct.nty);
+    const int i = tx * kTileX + lx, j = ty * kTileY + ly;
+    if (i >= nx || j >= ny) continue;
+    const int k0 = zc * ct.zchunk, k1 = min(k0 + ct.zchunk, nz);
+    const int64_t cC = (int64_t)j * nx + i;
+    const int64_t cW = (int64_t)j * nx + (i > 0 ? i - 1 : nx - 1);
+    const int64_t cS = (int64_t)(j > 0 ? j - 1 : ny - 1) * nx + i;
+    const bool hasW = G.per[0] || i > 0, hasS = G.per[1] || j > 0;
+    const double dxi = P.dx[0][i], dyj = P.dx[1][j];
+    double mzm = 0.0;
+    bool hasZ = false;
+    if (DIM == 3) {
+      hasZ = G.per[2] || k0 > 0;
+      if (hasZ) mzm = mu[(int64_t)(k0 > 0 ? k0 - 1 : nz - 1) * sxy + cC] - shift;
+    }
+    for (int k = k0; k < k1; ++k) {
+      const int64_t c = (int64_t)k * sxy + cC;
+      const double mc = mu[c] - shift;
+      const double mw = hasW ? mu[(int64_t)k * sxy + cW] - shift : 0.0;
+      const double ms = hasS ? mu[(int64_t)k * sxy + cS] - shift : 0.0;
+      const double dzk = (DIM == 3) ? (double)P.dx[2][k] : 1.0;
+      const int I[3] = {i, j, k};
+      const double lo[3] = {mw, ms, hasZ ? mzm : 0.0};
+      const double area[3] = {dyj * dzk, dxi * dzk, dxi * dyj};
+#pragma unroll
+      for (int C = 0; C < DIM; ++C) {
+        // low face of the cell
+        const int64_t id = fidx(G.ext[C], i, j, k);
+        double v = (double)ub[C][id];
+        int li = 0;
+        bool forced = false;
+        if (C == 0) forced = forced_cls<0>(ib, i, j, &li);
+        else if (C == 1) forced = forced_cls<1>(ib, i, j, &li);
+        if (!forced) v += area[C] * (lo[C] - mc);
+        us[C][id] = (T)v;
+        // high face of the last cell of a bounded axis
+        if (!G.per[C] && I[C] == G.n[C] - 1) {
+          int H[3] = {i, j, k};
+          H[C] += 1;
+          const int64_t ih = fidx(G.ext[C], H[0], H[1], H[2]);
+          double vh = (double)ub[C][ih];
+          bool fh = false;
+          if (C == 0) fh = forced_cls<0>(ib, H[0], H[1], &li);
+          else if (C == 1) fh = forced_cls<1>(ib, H[0], H[1], &li);
+          if (!fh) vh += area[C] * mc;
+          us[C][ih] = (T)vh;
+        }
+      }
+      mzm = mc;
+      hasZ = true;
+    }
   }
 }
 
@@ -325,15 +379,17 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_adj_ubody(Geo<T> G, PGeo<double> P, IbGeo B, const T* __restrict__ ub0,
             const T* __restrict__ ub1, const double* __restrict__ mu, IbView<T> ib,
-            double* __restrict__ stbar) {
+            double* __restrict__ stbar, const SolverScalars* sc) {
   const T* ub[2] = {ub0, ub1};
+  const double shift = sc->sumx * P.inv_ncell;
   double s[2] = {0.0, 0.0};
   for (int c = 0; c < 2; ++c) {
     const int W0 = B.W[c][0], W1 = B.W[c][1];
     for (int l = threadIdx.x; l < W0 * W1; l += kBlock) {
       if (!B.cls[c][l]) continue;
       const int i = B.origin[2 * c] + l % W0, j = B.origin[2 * c + 1] + l / W0;
-      const double sm = (c == 0) ? st_mu<0>(G, P, mu, i, j, 0) : st_mu<1>(G, P, mu, i, j, 0);
+      const double sm = (c == 0) ? st_mu<0>(G, P, mu, i, j, 0, shift)
+                                 : st_mu<1>(G, P, mu, i, j, 0, shift);
       s[c] += (double)ub[c][fidx(G.ext[c], i, j, 0)] + sm + (double)ib.f[c][l] / (double)G.dt;
     }
   }
@@ -811,25 +867,25 @@ static inline int nblk(int64_t n) {
 
 template <typename T>
 int launch_adj_ustar(const Geo<T>& G, const PGeo<double>& P, const T* const ub1[3],
-                     const double* mu, const IbView<T>& ib, T* usb[3], hipStream_t s) {
-  for (int c = 0; c < G.dim; ++c) {
-    const int64_t n = (int64_t)G.ext[c][0] * G.ext[c][1] * G.ext[c][2];
-    if (c == 0)
-      hipLaunchKernelGGL((k_adj_ustar<0, T>), dim3(nblk(n)), dim3(kBlock), 0, s, G, P, ub1[0], mu, ib, usb[0]);
-    else if (c == 1)
-      hipLaunchKernelGGL((k_adj_ustar<1, T>), dim3(nblk(n)), dim3(kBlock), 0, s, G, P, ub1[1], mu, ib, usb[1]);
-    else
-      hipLaunchKernelGGL((k_adj_ustar<2, T>), dim3(nblk(n)), dim3(kBlock), 0, s, G, P, ub1[2], mu, ib, usb[2]);
-    FVIB_HIP(hipGetLastError());
-  }
+                     const double* mu, const IbView<T>& ib, T* usb[3], const SolverScalars* sc,
+                     hipStream_t s) {
+  const ColTiling ct = make_col_tiling(G.n[0], G.n[1], G.n[2]);
+  if (G.dim == 2)
+    hipLaunchKernelGGL((k_adj_ustar<T, 2>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct, ub1[0],
+                       ub1[1], ub1[2], mu, ib, usb[0], usb[1], usb[2], sc);
+  else
+    hipLaunchKernelGGL((k_adj_ustar<T, 3>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct, ub1[0],
+                       ub1[1], ub1[2], mu, ib, usb[0], usb[1], usb[2], sc);
+  FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
 
 template <typename T>
 int launch_adj_ubody(const Geo<T>& G, const PGeo<double>& P, const IbGeo& B, const T* const ub1[3],
-                     const double* mu, const IbView<T>& ib, double* stbar, hipStream_t s) {
+                     const double* mu, const IbView<T>& ib, double* stbar,
+                     const SolverScalars* sc, hipStream_t s) {
   hipLaunchKernelGGL((k_adj_ubody<T>), dim3(1), dim3(kBlock), 0, s, G, P, B, ub1[0], ub1[1], mu, ib,
-                     stbar);
+                     stbar, sc);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
@@ -913,10 +969,11 @@ static int launch_adj_momentum_t(const AdjCtx<T>& X, T* ubar[3], T* fbbar[3], hi
   template int launch_adj_rhs<T>(const Geo<T>&, const PGeo<double>&, const T* const[3],         \
                                  double*, RedBuf, SolverScalars*, double, hipStream_t);         \
   template int launch_adj_ustar<T>(const Geo<T>&, const PGeo<double>&, const T* const[3],       \
-                                   const double*, const IbView<T>&, T* [3], hipStream_t);       \
+                                   const double*, const IbView<T>&, T* [3],                     \
+                                   const SolverScalars*, hipStream_t);                          \
   template int launch_adj_ubody<T>(const Geo<T>&, const PGeo<double>&, const IbGeo&,            \
                                    const T* const[3], const double*, const IbView<T>&,          \
-                                   double*, hipStream_t);                                       \
+                                   double*, const SolverScalars*, hipStream_t);                 \
   template int launch_adj_outflow<T>(const Geo<T>&, const Planes&, int, T* [3], T* [3],         \
                                      RedBuf, SolverScalars*, hipStream_t);                      \
   template int launch_adj_momentum<T>(const Geo<T>&, const T* const[3], const T* const[3],      \

@@ -370,18 +370,24 @@ struct LdsGemm {
   static constexpr int RV = KC / VW;                   // 16-byte vectors per row chunk (8)
 };
 
-template <typename V, bool XFAST, bool DIV, int MT, int NT>
+// FUSE (with DIV): the divided modes stay in LDS and the same block applies
+// the inverse operator A2 of this axis at once, so the last forward and the
+// first inverse contraction of a sweep share one pass over memory.
+template <typename V, bool XFAST, bool DIV, bool FUSE, int MT, int NT>
 __global__ void __launch_bounds__(kBlock)
-k_axis_lds(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A, int K, int inner,
-           int64_t ncols, FdmDiv dv, const int* stop) {
+k_axis_lds(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A,
+           const V* __restrict__ A2, int K, int inner, int64_t ncols, FdmDiv dv,
+           const int* stop) {
   if (stop && *stop) return;
   typedef LdsGemm<V> L;
   typedef typename Mfma<V>::acc_t acc_t;
   constexpr int NC = 16 * NT;
   constexpr int RV = L::RV;
   typedef __attribute__((ext_vector_type(L::VW))) V vec_t;
+  constexpr int LDY = 256 + L::VW;                      // stride of the fused modes
   __shared__ __attribute__((aligned(16))) V As[256 * L::LD];
   __shared__ __attribute__((aligned(16))) V Xs[NC * L::LD];
+  __shared__ __attribute__((aligned(16))) V Ys[FUSE ? NC * LDY : 1];
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -399,15 +405,16 @@ k_axis_lds(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A, 
   constexpr int XV = (NC * RV + kBlock - 1) / kBlock;
   const int av = K * RV / kBlock;                       // wave-uniform
   vec_t ra[AV], rx[XV];
-  auto gload = [&](int kc) {
+  auto gload = [&](const V* Aop, int kc, bool with_x) {
 #pragma unroll
     for (int u = 0; u < AV; ++u) {
       if (u < av) {
         const int e = t + u * kBlock;
         const int m = e / RV, f = e - m * RV;
-        ra[u] = *reinterpret_cast<const vec_t*>(A + (int64_t)m * K + kc + f * L::VW);
+        ra[u] = *reinterpret_cast<const vec_t*>(Aop + (int64_t)m * K + kc + f * L::VW);
       }
     }
+    if (!with_x) return;
 #pragma unroll
     for (int u = 0; u < XV; ++u) {
       const int e = t + u * kBlock;
@@ -425,7 +432,7 @@ k_axis_lds(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A, 
       }
     }
   };
-  auto sstore = [&]() {
+  auto sstore = [&](bool with_x) {
 #pragma unroll
     for (int u = 0; u < AV; ++u) {
       if (u < av) {
@@ -434,6 +441,7 @@ k_axis_lds(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A, 
         *reinterpret_cast<vec_t*>(As + m * L::LD + f * L::VW) = ra[u];
       }
     }
+    if (!with_x) return;
 #pragma unroll
     for (int u = 0; u < XV; ++u) {
       const int e = t + u * kBlock;
@@ -451,42 +459,50 @@ k_axis_lds(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A, 
     }
   };
   acc_t acc[MT][NT];
+  // one contraction over K: B operand from the staged lines (phase 1) or
+  // from the modes kept in LDS (phase 2 of FUSE)
+  auto gemm = [&](const V* Aop, bool from_ys) {
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int tt = 0; tt < NT; ++tt) acc[mt][tt] = acc_t{0, 0, 0, 0};
-  gload(0);
-  for (int kc = 0; kc < K; kc += L::KC) {
-    __syncthreads();                 // previous chunk fully consumed
-    sstore();
-    __syncthreads();
-    if (kc + L::KC < K) gload(kc + L::KC);
+      for (int tt = 0; tt < NT; ++tt) acc[mt][tt] = acc_t{0, 0, 0, 0};
+    gload(Aop, 0, !from_ys);
+    for (int kc = 0; kc < K; kc += L::KC) {
+      __syncthreads();                 // previous chunk fully consumed
+      sstore(!from_ys);
+      __syncthreads();
+      if (kc + L::KC < K) gload(Aop, kc + L::KC, !from_ys);
 #pragma unroll
-    for (int g = 0; g < L::KC / 16; ++g) {
-      const int kq = 16 * g + 4 * q;   // this lane group's quad in the chunk
-      Quad<V> xa[NT];
+      for (int g = 0; g < L::KC / 16; ++g) {
+        const int kq = 16 * g + 4 * q;   // this lane group's quad in the chunk
+        Quad<V> xa[NT];
 #pragma unroll
-      for (int tt = 0; tt < NT; ++tt)
+        for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) xa[tt].v[e] = Xs[(16 * tt + r) * L::LD + kq + e];
+          for (int e = 0; e < 4; ++e)
+            xa[tt].v[e] = from_ys ? Ys[(16 * tt + r) * LDY + kc + kq + e]
+                                  : Xs[(16 * tt + r) * L::LD + kq + e];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const int tile = w + 4 * mt;
-        if (tile >= ntr) continue;     // wave-uniform
-        Quad<V> aa;
+        for (int mt = 0; mt < MT; ++mt) {
+          const int tile = w + 4 * mt;
+          if (tile >= ntr) continue;     // wave-uniform
+          Quad<V> aa;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) aa.v[e] = As[(16 * tile + r) * L::LD + kq + e];
+          for (int e = 0; e < 4; ++e) aa.v[e] = As[(16 * tile + r) * L::LD + kq + e];
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+          for (int s = 0; s < 4; ++s)
 #pragma unroll
-          for (int tt = 0; tt < NT; ++tt)
-            acc[mt][tt] = Mfma<V>::op(aa.v[s], xa[tt].v[s], acc[mt][tt]);
+            for (int tt = 0; tt < NT; ++tt)
+              acc[mt][tt] = Mfma<V>::op(aa.v[s], xa[tt].v[s], acc[mt][tt]);
+        }
       }
     }
-  }
-  // epilogue (as in k_axis_mfma)
+  };
+  gemm(A, false);
+  // division by the eigenvalue sum (last forward axis)
   double lrest[NT];
   if (DIV) {
+    // eigenvalue sum of the faster axes' modes of each line (decoded from i)
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt) {
       const int64_t n = n0 + 16 * tt + r;
@@ -499,9 +515,33 @@ k_axis_lds(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A, 
         ls += dv.lam[b][mb];
         allz &= (mb == 0);
       }
-      lrest[tt] = allz ? -1.0 : ls;
+      lrest[tt] = allz ? -1.0 : ls;      // -1 marks the lines of the zero mode
     }
   }
+  auto divide = [&](int tt, int m, V val) -> V {
+    const bool zero = (lrest[tt] < 0.0) && m == 0;
+    const double ls = (lrest[tt] < 0.0 ? 0.0 : lrest[tt]) + dv.lam[dv.axis][m];
+    return zero ? V(0) : (V)((double)val / ls);
+  };
+  if constexpr (FUSE) {
+    // divided modes into LDS (every row < K of every line), then the inverse
+    // operator of the same axis; the barriers at the top of each chunk of
+    // the second contraction order these writes before their reads
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int tile = w + 4 * mt;
+      if (tile >= ntr) continue;
+#pragma unroll
+      for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = 16 * tile + Mfma<V>::row(lane, v);
+          Ys[(16 * tt + r) * LDY + m] = divide(tt, m, acc[mt][tt][v]);
+        }
+    }
+    gemm(A2, true);
+  }
+  constexpr bool DIVOUT = DIV && !FUSE;
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     const int tile = w + 4 * mt;
@@ -517,7 +557,7 @@ k_axis_lds(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A, 
         const int64_t o = n / inner, i = n - o * inner;
         base = o * (int64_t)K * inner + i;
       }
-      if constexpr (XFAST && !DIV && sizeof(V) == 4) {
+      if constexpr (XFAST && !DIVOUT && sizeof(V) == 4) {
         const acc_t& c = acc[mt][tt];
         *reinterpret_cast<float4*>(Y + base + 16 * tile + 4 * q) = make_float4(c[0], c[1], c[2], c[3]);
         continue;
@@ -526,11 +566,7 @@ k_axis_lds(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A, 
       for (int v = 0; v < 4; ++v) {
         const int m = 16 * tile + Mfma<V>::row(lane, v);
         V val = acc[mt][tt][v];
-        if (DIV) {
-          const bool zero = (lrest[tt] < 0.0) && m == 0;
-          const double ls = (lrest[tt] < 0.0 ? 0.0 : lrest[tt]) + dv.lam[dv.axis][m];
-          val = zero ? V(0) : (V)((double)val / ls);
-        }
+        if (DIVOUT) val = divide(tt, m, val);
         if (XFAST)
           Y[base + m] = val;
         else
@@ -586,8 +622,21 @@ static int lds_line_tiles(int64_t ncols, int inner) {
 }
 
 template <typename V>
+bool fdm_fuses_last_axis(const FdmPlan<V>& F) {
+  const int a = F.dim - 1;
+  const int K = F.n[a];
+  int inner = 1;
+  for (int b = 0; b < a; ++b) inner *= F.n[b];
+  int64_t outer = 1;
+  for (int b = a + 1; b < 3; ++b) outer *= F.n[b];
+  const int nt = (K % 32 == 0 && K <= 256) ? lds_line_tiles(outer * inner, inner) : 0;
+  return nt > 0 && inner != 1 && nt <= 2;
+}
+
+template <typename V>
 int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, const int* stop,
-                    hipStream_t s) {
+                    hipStream_t s, bool* fused) {
+  if (fused) *fused = false;
   const int K = F.n[a];
   int inner = 1;
   for (int b = 0; b < a; ++b) inner *= F.n[b];
@@ -597,12 +646,33 @@ int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, c
   const V* Am = fwd ? F.phiT[a] : F.phi[a];
   const bool div = fwd && a == F.dim - 1;
   const int nt = (K % 32 == 0 && K <= 256) ? lds_line_tiles(ncols, inner) : 0;
+  if (nt > 0 && div && fused && inner != 1 && nt <= 2) {
+    // last forward axis, division and first inverse axis in one launch
+    const dim3 g((unsigned)((ncols + 16 * nt - 1) / (16 * nt)));
+    const int mt = (K / 16 + 3) / 4;
+#define FVIB_AF(MT, NT)                                                                         \
+    hipLaunchKernelGGL((k_axis_lds<V, false, true, true, MT, NT>), g, dim3(kBlock), 0, s, in,   \
+                       out, Am, F.phi[a], K, inner, ncols, F.div, stop)
+#define FVIB_AFN(MT)                                                                            \
+    if (nt == 1) FVIB_AF(MT, 1); else FVIB_AF(MT, 2);
+    switch (mt) {
+      case 1: FVIB_AFN(1) break;
+      case 2: FVIB_AFN(2) break;
+      case 3: FVIB_AFN(3) break;
+      default: FVIB_AFN(4) break;
+    }
+#undef FVIB_AFN
+#undef FVIB_AF
+    FVIB_HIP(hipGetLastError());
+    *fused = true;
+    return FVIB_OK;
+  }
   if (nt > 0) {
     const dim3 g((unsigned)((ncols + 16 * nt - 1) / (16 * nt)));
     const int mt = (K / 16 + 3) / 4;
 #define FVIB_AL(XF, DV, MT, NT)                                                                 \
-    hipLaunchKernelGGL((k_axis_lds<V, XF, DV, MT, NT>), g, dim3(kBlock), 0, s, in, out, Am, K,  \
-                       inner, ncols, F.div, stop)
+    hipLaunchKernelGGL((k_axis_lds<V, XF, DV, false, MT, NT>), g, dim3(kBlock), 0, s, in, out,  \
+                       Am, Am, K, inner, ncols, F.div, stop)
 #define FVIB_ALN(XF, DV, MT)                                                                    \
     switch (nt) {                                                                               \
       case 1: FVIB_AL(XF, DV, MT, 1); break;                                                    \
@@ -690,10 +760,12 @@ int launch_gauge(int64_t n, double* p, const SolverScalars* sc, hipStream_t s) {
   return FVIB_OK;
 }
 
+template bool fdm_fuses_last_axis<float>(const FdmPlan<float>&);
+template bool fdm_fuses_last_axis<double>(const FdmPlan<double>&);
 template int launch_fdm_axis<float>(const FdmPlan<float>&, int, bool, const float*, float*,
-                                    const int*, hipStream_t);
+                                    const int*, hipStream_t, bool*);
 template int launch_fdm_axis<double>(const FdmPlan<double>&, int, bool, const double*, double*,
-                                     const int*, hipStream_t);
+                                     const int*, hipStream_t, bool*);
 template int launch_add_correction<float>(int64_t, double*, const float*, const int*, hipStream_t);
 template int launch_add_correction<double>(int64_t, double*, const double*, const int*,
                                            hipStream_t);

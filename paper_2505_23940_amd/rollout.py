@@ -21,6 +21,21 @@ import torch
 from . import Grid, INFO_DOUBLES
 
 
+def _forward_steps(grid, nsteps, ckpt_every, u, p, body, fbd, kcd, info, ckpts):
+    for n in range(nsteps):
+        if n % ckpt_every == 0:
+            # the state entering a segment is kept as is; the step writes
+            # its result into fresh tensors (p is copied by the step)
+            ckpts[n] = (u, p, body)
+            u2 = [torch.empty_like(x) for x in u]
+            p2, b2 = torch.empty_like(p), torch.empty_like(body)
+            grid.step(u, p, fbd, body, kcd, u_out=u2, p_out=p2, body_out=b2, info=info[n])
+            u, p, body = u2, p2, b2
+        else:
+            grid.step(u, p, fbd, body, kcd, info=info[n])
+    ckpts["final"] = (u, p, body)
+
+
 class _Rollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, grid: Grid, nsteps: int, ckpt_every: int, nd: int, *tensors):
@@ -35,17 +50,14 @@ class _Rollout(torch.autograd.Function):
         kcd = kc.detach()
         info = torch.zeros((nsteps, INFO_DOUBLES), dtype=torch.float64, device=dev)
         ckpts = {}
-        for n in range(nsteps):
-            if n % ckpt_every == 0:
-                # the state entering a segment is kept as is; the step writes
-                # its result into fresh tensors (p is copied by the step)
-                ckpts[n] = (u, p, body)
-                u2 = [torch.empty_like(x) for x in u]
-                p2, b2 = torch.empty_like(p), torch.empty_like(body)
-                grid.step(u, p, fbd, body, kcd, u_out=u2, p_out=p2, body_out=b2, info=info[n])
-                u, p, body = u2, p2, b2
-            else:
-                grid.step(u, p, fbd, body, kcd, info=info[n])
+        # steps are enqueued back to back; their statuses are checked once
+        grid.defer_status(True)
+        try:
+            _forward_steps(grid, nsteps, ckpt_every, u, p, body, fbd, kcd, info, ckpts)
+        finally:
+            grid.defer_status(False)
+        u, p, body = ckpts.pop("final")
+        grid.check_infos(info, "forward step")
         ctx.grid = grid
         ctx.nsteps = nsteps
         ctx.k = ckpt_every
@@ -74,28 +86,39 @@ class _Rollout(torch.autograd.Function):
         fbbar = grid.zeros_u()
         kcbar = torch.zeros(6, dtype=torch.float64, device=grid.device)
         starts = list(range(0, S, K))
-        for s0 in reversed(starts):
-            s1 = min(s0 + K, S)
-            cu, cp, cb = ctx.ckpts[s0]
-            # states n = s0 .. s1-1 of the segment: the checkpoint, then the
-            # recomputed ones, each step writing into fresh velocity tensors
-            states = [(cu, cb)]
-            if s1 - s0 > 1:
-                p = cp.clone()
-                u, body = cu, cb
-                for n in range(s0, s1 - 1):
-                    u2 = [torch.empty_like(x) for x in u]
-                    b2 = torch.empty_like(body)
-                    grid.step(u, p, fb, body, kc, u_out=u2, p_out=p, body_out=b2)
-                    u, body = u2, b2
-                    states.append((u, body))
-            for n in reversed(range(s0, s1)):
-                un, bn = states[n - s0]
-                dF = gF[n].contiguous()
-                grid.step_adjoint(un, fb, bn, kc, ubar, bbar, dF, ubar_tmp, bbar_tmp,
-                                  fbbar=fbbar, kcbar=kcbar)
-                ubar, ubar_tmp = ubar_tmp, ubar
-                bbar, bbar_tmp = bbar_tmp, bbar
+        # recomputed and adjoint steps are enqueued back to back; their
+        # statuses are checked once at the end
+        infos_f = torch.zeros((S, INFO_DOUBLES), dtype=torch.float64, device=grid.device)
+        infos_a = torch.zeros((S, INFO_DOUBLES), dtype=torch.float64, device=grid.device)
+        grid.defer_status(True)
+        try:
+            for s0 in reversed(starts):
+                s1 = min(s0 + K, S)
+                cu, cp, cb = ctx.ckpts[s0]
+                # states n = s0 .. s1-1 of the segment: the checkpoint, then the
+                # recomputed ones, each step writing into fresh velocity tensors
+                states = [(cu, cb)]
+                if s1 - s0 > 1:
+                    p = cp.clone()
+                    u, body = cu, cb
+                    for n in range(s0, s1 - 1):
+                        u2 = [torch.empty_like(x) for x in u]
+                        b2 = torch.empty_like(body)
+                        grid.step(u, p, fb, body, kc, u_out=u2, p_out=p, body_out=b2,
+                                  info=infos_f[n])
+                        u, body = u2, b2
+                        states.append((u, body))
+                for n in reversed(range(s0, s1)):
+                    un, bn = states[n - s0]
+                    dF = gF[n].contiguous()
+                    grid.step_adjoint(un, fb, bn, kc, ubar, bbar, dF, ubar_tmp, bbar_tmp,
+                                      fbbar=fbbar, kcbar=kcbar, info=infos_a[n])
+                    ubar, ubar_tmp = ubar_tmp, ubar
+                    bbar, bbar_tmp = bbar_tmp, bbar
+        finally:
+            grid.defer_status(False)
+        grid.check_infos(infos_f, "recomputed step")
+        grid.check_infos(infos_a, "adjoint step")
         return (None, None, None, None, *ubar, *fbbar, kcbar, bbar)
 
 
