@@ -47,6 +47,7 @@ def kernel_cost(d: int, s: int, mixed: bool, n: tuple):
         "fdm_z": ("flops", 2 * n[2]),
         # last axis forward + division + inverse in one launch
         "fdm_last": ("flops", 4 * n[2 if d == 3 else 1]),
+        "fft": ("bytes", 2 * v),                           # read and write one vector
     }
 
 

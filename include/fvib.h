@@ -271,6 +271,7 @@ enum {
   FVIB_K_FDM_Z = 12,      /* ... along z                                   */
   FVIB_K_ADJ_MOMENTUM = 13, /* transposed momentum stencil (all components) */
   FVIB_K_FDM_LAST = 14,   /* last axis: forward, division and inverse in one */
+  FVIB_K_FFT = 15,        /* real FFT along a uniform periodic axis          */
   FVIB_K_NCLASSES = 16
 };
 

@@ -513,8 +513,10 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
         const bool can_fuse = fwd && pass == g->dim - 1;
         const bool will_fuse = can_fuse && (d64 ? fdm_fuses_last_axis<double>(g->F64)
                                                 : fdm_fuses_last_axis<float>(g->F32));
+        const bool by_fft = d64 ? fft_usable<double>(g->F64, a) : fft_usable<float>(g->F32, a);
         bool fused = false;
-        int r2 = timed(g, will_fuse ? FVIB_K_FDM_LAST : FVIB_K_FDM_X + a, [&] {
+        const int cls = by_fft ? FVIB_K_FFT : (will_fuse ? FVIB_K_FDM_LAST : FVIB_K_FDM_X + a);
+        int r2 = timed(g, cls, [&] {
           // the last pass writes d (with dim >= 2 a fused launch never ends
           // the sweep)
           const bool ends = pass == np - 1;
@@ -937,8 +939,9 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
           dmalloc(&g->pB64, g->ncell * sizeof(double)))
         return bail(FVIB_ENOMEM, "device allocation of the workspace failed");
     }
-    std::vector<double> hd;   // per axis: phi, phiT, lam
-    size_t off[3][3];
+    std::vector<double> hd;   // per axis: phi, phiT, lam, FFT twiddles
+    size_t off[3][4];
+    FftAxis fax[3];
     for (int a = 0; a < g->dim; ++a) {
       std::vector<double> phi, lam;
       axis_eigen(g->faces[a], g->per[a] != 0, phi, lam);
@@ -956,6 +959,20 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
       off[a][2] = hd.size();
       hd.insert(hd.end(), lam.begin(), lam.end());
       hd.resize((hd.size() + 3) / 4 * 4, 0.0);
+      // uniform periodic axis: real FFT in place of the contraction with its
+      // Fourier basis; twiddles exp(-2 pi i k / N) as (re, im)
+      const std::vector<double>& fa = g->faces[a];
+      fax[a] = fft_plan(N, (fa[N] - fa[0]) / N);
+      if (!g->per[a]) fax[a].on = 0;
+      off[a][3] = hd.size();
+      if (fax[a].on) {
+        for (int k = 0; k < N; ++k) {
+          const double th = -2.0 * 3.14159265358979323846 * k / N;
+          hd.push_back(cos(th));
+          hd.push_back(sin(th));
+        }
+        hd.resize((hd.size() + 3) / 4 * 4, 0.0);
+      }
     }
     std::vector<float> hf(hd.begin(), hd.end());
     if (dmalloc(&g->fdm_d, hd.size() * sizeof(double)) || dmalloc(&g->fdm_f, hf.size() * sizeof(float)))
@@ -979,6 +996,11 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
         g->F32.phi[a] = g->fdm_f + off[a][0];
         g->F32.phiT[a] = g->fdm_f + off[a][1];
         dv.lam[a] = g->fdm_d + off[a][2];
+        g->F64.fft[a] = g->F32.fft[a] = fax[a];
+        if (fax[a].on) {
+          g->F64.tw[a] = g->fdm_d + off[a][3];
+          g->F32.tw[a] = g->fdm_f + off[a][3];
+        }
       }
     }
     g->F64.div = dv;

@@ -33,6 +33,18 @@ struct FdmDiv {
   const double* lam[3];        // per-axis eigenvalues (ascending, lam[0] = 0)
 };
 
+// Uniform periodic axes whose length factors into 2, 3, 5 use a real FFT
+// in place of the dense contraction with their (real Fourier) basis.
+constexpr int kFftMaxN = 256;
+constexpr int kFftMaxStages = 8;
+
+struct FftAxis {
+  int on;                      // axis transformed by FFT
+  int nst;                     // number of radix stages
+  int radix[kFftMaxStages];    // radices (2, 3, 4, 5) in stage order
+  double a, b;                 // basis scales sqrt(2/N)/sqrt(h), 1/sqrt(N h)
+};
+
 template <typename V>
 struct FdmPlan {
   int dim;
@@ -40,7 +52,20 @@ struct FdmPlan {
   const V* phi[3];             // n x n row-major, column m = mode m
   const V* phiT[3];            // transpose
   FdmDiv div;
+  FftAxis fft[3];
+  const V* tw[3];              // exp(-2 pi i k / N), k < N, as (re, im) pairs
 };
+
+// Radix plan of an FFT of length n (0 stages if n does not factor into
+// 2, 3, 5 or exceeds kFftMaxN).
+FftAxis fft_plan(int n, double h);
+
+// k_fft.hip: mode 0 forward, 1 inverse, 2 forward + division + inverse.
+template <typename V>
+int launch_fft_axis(const FdmPlan<V>& F, int a, int mode, const V* in, V* out, const int* stop,
+                    hipStream_t s);
+template <typename V>
+bool fft_usable(const FdmPlan<V>& F, int a);
 
 // k_momentum.hip
 template <typename T>

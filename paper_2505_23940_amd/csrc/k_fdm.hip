@@ -624,6 +624,7 @@ static int lds_line_tiles(int64_t ncols, int inner) {
 template <typename V>
 bool fdm_fuses_last_axis(const FdmPlan<V>& F) {
   const int a = F.dim - 1;
+  if (fft_usable(F, a)) return true;
   const int K = F.n[a];
   int inner = 1;
   for (int b = 0; b < a; ++b) inner *= F.n[b];
@@ -637,6 +638,15 @@ template <typename V>
 int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, const int* stop,
                     hipStream_t s, bool* fused) {
   if (fused) *fused = false;
+  if (fft_usable(F, a)) {
+    const bool last = fwd && a == F.dim - 1;
+    if (!last) return launch_fft_axis<V>(F, a, fwd ? 0 : 1, in, out, stop, s);
+    if (fused) {
+      *fused = true;
+      return launch_fft_axis<V>(F, a, 2, in, out, stop, s);
+    }
+    // a division without the fused inverse falls through to the contraction
+  }
   const int K = F.n[a];
   int inner = 1;
   for (int b = 0; b < a; ++b) inner *= F.n[b];
