@@ -36,12 +36,9 @@ struct FdmDiv {
 // Uniform periodic axes whose length factors into 2, 3, 5 use a real FFT
 // in place of the dense contraction with their (real Fourier) basis.
 constexpr int kFftMaxN = 256;
-constexpr int kFftMaxStages = 8;
 
 struct FftAxis {
   int on;                      // axis transformed by FFT
-  int nst;                     // number of radix stages
-  int radix[kFftMaxStages];    // radices (2, 3, 4, 5) in stage order
   double a, b;                 // basis scales sqrt(2/N)/sqrt(h), 1/sqrt(N h)
 };
 
@@ -56,8 +53,8 @@ struct FdmPlan {
   const V* tw[3];              // exp(-2 pi i k / N), k < N, as (re, im) pairs
 };
 
-// Radix plan of an FFT of length n (0 stages if n does not factor into
-// 2, 3, 5 or exceeds kFftMaxN).
+// FFT description of a uniform periodic axis of length n and spacing h
+// (on = 0 if no FFT kernel exists for n).
 FftAxis fft_plan(int n, double h);
 
 // k_fft.hip: mode 0 forward, 1 inverse, 2 forward + division + inverse.

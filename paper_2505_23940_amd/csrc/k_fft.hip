@@ -25,7 +25,55 @@ struct FftCfg {
   static constexpr int P = LPB / 2;                      // complex lines
 };
 
-// R-point DFT (sign -) on (re, im) arrays, R = 2, 3, 4, 5.
+// sin and cos of 2 pi j / R (compile time): reduction to the nearest
+// quarter turn, then Taylor series on |r| <= pi / 4.
+constexpr void cx_sincos(int j, int R, double& s, double& c) {
+  constexpr double kPi = 3.14159265358979323846;
+  const int q8 = 4 * j;                    // angle in quarter turns = 4 j / R
+  int quad = (2 * q8 + R) / (2 * R);       // nearest quarter turn
+  const double r = 2.0 * kPi * ((double)(q8 - quad * R) / (4.0 * R));
+  double sr = 0.0, cr = 0.0, term = r;
+  for (int n = 1; n < 30; n += 2) {        // sin r = r - r^3/3! + ...
+    sr += term;
+    term *= -r * r / ((n + 1) * (n + 2));
+  }
+  term = 1.0;
+  for (int n = 0; n < 30; n += 2) {        // cos r = 1 - r^2/2! + ...
+    cr += term;
+    term *= -r * r / ((n + 1) * (n + 2));
+  }
+  quad &= 3;
+  s = quad == 0 ? sr : quad == 1 ? cr : quad == 2 ? -sr : -cr;
+  c = quad == 0 ? cr : quad == 1 ? -sr : quad == 2 ? -cr : sr;
+}
+
+// Roots exp(-2 pi i j / R), j < R.
+template <int R>
+struct Roots {
+  double c[R], s[R];
+  constexpr Roots() : c(), s() {
+    for (int j = 0; j < R; ++j) {
+      double sn = 0.0, cs = 0.0;
+      cx_sincos(j, R, sn, cs);
+      c[j] = cs;
+      s[j] = -sn;
+    }
+  }
+};
+
+// Split of a composite radix R = A B (A the first factor of 4, 2, 3, 5).
+constexpr int dft_split(int R) {
+  if (R % 4 == 0 && R != 4) return 4;
+  if (R % 2 == 0 && R != 2 && R != 4) return 2;
+  if (R % 3 == 0 && R != 3) return 3;
+  if (R % 5 == 0 && R != 5) return 5;
+  return R;
+}
+
+// R-point DFT (sign -) in registers on (re, im) arrays.  R = 2, 3, 4, 5
+// directly; a composite R = A B by one Cooley-Tukey split: A-point DFTs
+// over n1 of x[B n1 + n2], twiddles exp(-2 pi i n2 k1 / R), B-point DFTs
+// over n2 into X[k1 + A k2].
 template <int R, typename V>
 __device__ __forceinline__ void dft_small(V (&xr)[R], V (&xi)[R]) {
   if constexpr (R == 2) {
@@ -42,23 +90,15 @@ __device__ __forceinline__ void dft_small(V (&xr)[R], V (&xi)[R]) {
     // X1 = d0 - i d1, X3 = d0 + i d1
     xr[1] = d0r + d1i; xi[1] = d0i - d1r;
     xr[3] = d0r - d1i; xi[3] = d0i + d1r;
-  } else {
-    // R = 3 or 5: direct sum with the R-th roots of unity exp(-2 pi i q / R)
-    constexpr double c3[3] = {1.0, -0.5, -0.5};
-    constexpr double s3[3] = {0.0, -0.86602540378443865, 0.86602540378443865};
-    constexpr double c5[5] = {1.0, 0.30901699437494742, -0.80901699437494742,
-                              -0.80901699437494742, 0.30901699437494742};
-    constexpr double s5[5] = {0.0, -0.95105651629515357, -0.58778525229247313,
-                              0.58778525229247313, 0.95105651629515357};
+  } else if constexpr (R == 3 || R == 5) {
+    constexpr Roots<R> W{};
     V yr[R], yi[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      V sr = V(0), si = V(0);
+      V sr = xr[0], si = xi[0];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int q = (r * k) % R;
-        const V c = (V)(R == 3 ? c3[q % 3] : c5[q % 5]);
-        const V sn = (V)(R == 3 ? s3[q % 3] : s5[q % 5]);
+      for (int r = 1; r < R; ++r) {
+        const V c = (V)W.c[(r * k) % R], sn = (V)W.s[(r * k) % R];
         sr += xr[r] * c - xi[r] * sn;
         si += xr[r] * sn + xi[r] * c;
       }
@@ -70,17 +110,65 @@ __device__ __forceinline__ void dft_small(V (&xr)[R], V (&xi)[R]) {
       xr[k] = yr[k];
       xi[k] = yi[k];
     }
+  } else {
+    constexpr int A = dft_split(R), B = R / A;
+    static_assert(A > 1 && B > 1 && A * B == R, "radix without a kernel");
+    constexpr Roots<R> W{};
+    V yr[B][A], yi[B][A];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) {
+      V tr[A], ti[A];
+#pragma unroll
+      for (int n1 = 0; n1 < A; ++n1) {
+        tr[n1] = xr[B * n1 + n2];
+        ti[n1] = xi[B * n1 + n2];
+      }
+      dft_small<A, V>(tr, ti);
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1) {
+        const int e = (n2 * k1) % R;
+        if (e == 0) {
+          yr[n2][k1] = tr[k1];
+          yi[n2][k1] = ti[k1];
+        } else {
+          const V c = (V)W.c[e], sn = (V)W.s[e];
+          yr[n2][k1] = tr[k1] * c - ti[k1] * sn;
+          yi[n2][k1] = tr[k1] * sn + ti[k1] * c;
+        }
+      }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      V tr[B], ti[B];
+#pragma unroll
+      for (int n2 = 0; n2 < B; ++n2) {
+        tr[n2] = yr[n2][k1];
+        ti[n2] = yi[n2][k1];
+      }
+      dft_small<B, V>(tr, ti);
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) {
+        xr[k1 + A * k2] = tr[k2];
+        xi[k1 + A * k2] = ti[k2];
+      }
+    }
   }
 }
 
-// Radix plan (compile time, same rule as fft_plan): radix-4 stages, one
-// radix-2 stage for an odd power of two, then radix-3 and radix-5 stages.
+// Radix plan (compile time): each stage takes the largest radix of
+// 16, 12, 10, 8, 6, 5, 4, 3, 2 that divides what is left of n, so the
+// common lengths need two passes through LDS.
 constexpr int fft_radix_at(int n, int st) {
-  int m = n, k = 0;
-  while (m % 4 == 0) { if (k == st) return 4; ++k; m /= 4; }
-  if (m % 2 == 0) { if (k == st) return 2; ++k; m /= 2; }
-  while (m % 3 == 0) { if (k == st) return 3; ++k; m /= 3; }
-  while (m % 5 == 0) { if (k == st) return 5; ++k; m /= 5; }
+  constexpr int kR[9] = {16, 12, 10, 8, 6, 5, 4, 3, 2};
+  int m = n;
+  for (int k = 0; m > 1; ++k) {
+    int r = 0;
+    for (int q = 0; q < 9 && r == 0; ++q)
+      if (m % kR[q] == 0) r = kR[q];
+    if (r == 0) return 0;
+    if (k == st) return r;
+    m /= r;
+  }
   return 0;
 }
 constexpr int fft_nstages(int n) {
@@ -94,90 +182,80 @@ struct alignas(2 * sizeof(V)) Cx {
   V r, i;
 };
 
+// LDS index of complex entry k of packed line pair p: line-contiguous for a
+// contiguous axis, line-interleaved (index-major) for a strided axis, so that
+// in both cases a block's global lines land in LDS as one dense image.
+template <int N, int P, bool IL>
+__device__ __forceinline__ int zidx(int p, int k) {
+  return IL ? k * P + p : p * N + k;
+}
+
 // One Stockham stage of radix R over P complex lines of length N (current
-// sub-transform length NS): src -> dst.
-template <int R, int N, int NS, int P, typename V>
+// sub-transform length NS): src -> dst.  Consecutive threads take
+// consecutive entries of the layout.
+template <int R, int N, int NS, int P, bool IL, typename V>
 __device__ __forceinline__ void fft_stage(const Cx<V>* src, Cx<V>* dst, const Cx<V>* tw) {
   constexpr int NR = N / R;
   constexpr int TWS = N / (NS * R);
-  for (int e = threadIdx.x; e < P * NR; e += kBlock) {
-    const int p = e / NR, j = e - p * NR;
-    const int k = j % NS;
-    const Cx<V>* s0 = src + p * N;
-    Cx<V>* d0 = dst + p * N;
-    V xr[R], xi[R];
+  constexpr int NE = P * NR;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const Cx<V> v = s0[j + r * NR];
-      xr[r] = v.r;
-      xi[r] = v.i;
+  for (int e0 = 0; e0 < NE; e0 += kBlock) {
+    const int e = e0 + (int)threadIdx.x;
+    if (NE % kBlock == 0 || e < NE) {
+      int p, j;
+      if (IL) { p = e % P; j = e / P; } else { p = e / NR; j = e - p * NR; }
+      const int k = j % NS;
+      V xr[R], xi[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const Cx<V> v = src[zidx<N, P, IL>(p, j + r * NR)];
+        xr[r] = v.r;
+        xi[r] = v.i;
+      }
+      // r k TWS <= (R - 1)(NS - 1) N / (NS R) < N: no wrap; the first
+      // stage (NS = 1) has none
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const Cx<V> w = tw[r * k * TWS];
+          const V vr = xr[r] * w.r - xi[r] * w.i;
+          xi[r] = xr[r] * w.i + xi[r] * w.r;
+          xr[r] = vr;
+        }
+      }
+      dft_small<R, V>(xr, xi);
+      const int idx = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[zidx<N, P, IL>(p, idx + r * NS)] = Cx<V>{xr[r], xi[r]};
     }
-#pragma unroll
-    for (int r = 1; r < R; ++r) {
-      const Cx<V> w = tw[(r * k * TWS) % N];
-      const V vr = xr[r] * w.r - xi[r] * w.i;
-      xi[r] = xr[r] * w.i + xi[r] * w.r;
-      xr[r] = vr;
-    }
-    dft_small<R, V>(xr, xi);
-    const int idx = (j / NS) * NS * R + k;
-#pragma unroll
-    for (int r = 0; r < R; ++r) d0[idx + r * NS] = Cx<V>{xr[r], xi[r]};
   }
 }
 
 // Stockham FFT of P complex lines of length N in src (dst is scratch);
 // returns the buffer that holds the result.
-template <typename V, int N, int P, int ST = 0, int NS = 1>
+template <typename V, int N, int P, bool IL, int ST = 0, int NS = 1>
 __device__ __forceinline__ Cx<V>* fft_lines(Cx<V>* src, Cx<V>* dst, const Cx<V>* tw) {
   if constexpr (ST == fft_nstages(N)) {
     return src;
   } else {
     constexpr int R = fft_radix_at(N, ST);
-    fft_stage<R, N, NS, P, V>(src, dst, tw);
+    fft_stage<R, N, NS, P, IL, V>(src, dst, tw);
     __syncthreads();
-    return fft_lines<V, N, P, ST + 1, NS * R>(dst, src, tw);
+    return fft_lines<V, N, P, IL, ST + 1, NS * R>(dst, src, tw);
   }
 }
 
-// Real coefficient c of line part (0: x1, 1: x2) from the packed spectrum Z
-// (interleaved, length N) of its pair.
-template <typename V>
-__device__ __forceinline__ V spec_coeff(const V* Z, int N, int c, int part, double a, double b) {
-  if (c == 0) return (V)(b * (double)Z[part]);
-  if ((N & 1) == 0 && c == N - 1) return (V)(b * (double)Z[2 * (N / 2) + part]);
-  const int m = (c + 1) / 2;
-  const V zmr = Z[2 * m], zmi = Z[2 * m + 1];
-  const V znr = Z[2 * (N - m)], zni = Z[2 * (N - m) + 1];
-  V v;
-  if (c & 1) {     // cosine coefficient: a Re X_m
-    v = part == 0 ? (zmr + znr) : (zmi + zni);
-  } else {         // sine coefficient: -a Im X_m
-    v = part == 0 ? (zni - zmi) : (zmr - znr);
-  }
-  return (V)(0.5 * a * (double)v);
-}
-
-// conj of the packed Hermitian spectrum Y1 + i Y2 at index m, from the real
-// coefficients y1, y2 (each N long, stride 1).
-template <typename V>
-__device__ __forceinline__ void herm_pack_conj(const V* y1, const V* y2, int N, int m, double a,
-                                               double b, V* zr, V* zi) {
-  double y1r, y1i, y2r, y2i;
-  if (m == 0) {
-    y1r = b * y1[0]; y1i = 0.0; y2r = b * y2[0]; y2i = 0.0;
-  } else if ((N & 1) == 0 && m == N / 2) {
-    y1r = b * y1[N - 1]; y1i = 0.0; y2r = b * y2[N - 1]; y2i = 0.0;
-  } else {
-    const int mm = (2 * m < N) ? m : N - m;
-    const double sg = (2 * m < N) ? -1.0 : 1.0;    // Y_{N-m} = conj(Y_m)
-    y1r = 0.5 * a * y1[2 * mm - 1]; y1i = sg * 0.5 * a * y1[2 * mm];
-    y2r = 0.5 * a * y2[2 * mm - 1]; y2i = sg * 0.5 * a * y2[2 * mm];
-  }
-  // Z = Y1 + i Y2, stored conjugated for the forward transform
-  *zr = (V)(y1r - y2i);
-  *zi = (V)(-(y1i + y2r));
-}
+// Relations used below (a = sqrt(2 / N) / sqrt(h), b = 1 / sqrt(N h), the
+// normalisation of the orthonormal real Fourier basis on a uniform axis of
+// spacing h; Z = FFT(x1 + i x2) of a line pair; X1_m = (Z_m + conj Z_{N-m}) / 2,
+// X2_m = (Z_m - conj Z_{N-m}) / (2 i)):
+//   coefficient 0           b Re X_0
+//   coefficient 2m - 1      a Re X_m          (cosine of wavenumber m)
+//   coefficient 2m          -a Im X_m         (sine of wavenumber m)
+//   coefficient N - 1       b Re X_{N/2}      (N even, alternating sign)
+// and back: Y_0 = b y_0, Y_{N/2} = b y_{N-1}, Y_m = (a / 2)(y_{2m-1} - i y_{2m})
+// for 0 < m < N / 2, Y_{N-m} = conj Y_m; x = IDFT(Y1 + i Y2) =
+// conj FFT(conj(Y1 + i Y2)) splits into the two real lines.
 
 // MODE 0: forward (lines -> basis coefficients), 1: inverse, 2: forward,
 // division by the eigenvalue sum, inverse.  N is the axis length.
@@ -186,20 +264,50 @@ __global__ void __launch_bounds__(kBlock)
 k_fft_axis(const V* __restrict__ X, V* __restrict__ Y, int inner, int64_t ncols, FftAxis ax,
            const V* __restrict__ twg, FdmDiv dv, const int* stop) {
   if (stop && *stop) return;
+  constexpr bool IL = !XFAST;
   typedef FftCfg<V> C;
   constexpr int LPB = C::LPB, P = C::P;
-  __shared__ Cx<V> bufA[P * N];
-  __shared__ Cx<V> bufB[P * N];
+  constexpr int VW = 16 / (int)sizeof(V);            // 16-byte global vectors
+  typedef __attribute__((ext_vector_type(VW))) V vec_t;
+  __shared__ __attribute__((aligned(16))) Cx<V> bufA[P * N];
+  __shared__ __attribute__((aligned(16))) Cx<V> bufB[P * N];
   __shared__ Cx<V> tw[N];
   __shared__ double lam_s[MODE == 2 ? N : 1];
   __shared__ double lrest_s[MODE == 2 ? LPB : 1];
-  V* rowsB = reinterpret_cast<V*>(bufB);        // LPB real rows of N
   const int t = threadIdx.x;
   const int64_t n0 = (int64_t)blockIdx.x * LPB;
   const int64_t o0 = XFAST ? 0 : n0 / inner;
   const int64_t i0 = XFAST ? 0 : n0 - o0 * inner;
   const int64_t base = XFAST ? n0 * (int64_t)N : o0 * (int64_t)N * inner + i0;
   const int nl = (int)((ncols - n0) < LPB ? (ncols - n0) : LPB);   // lines of this block
+  // Global vectors of the block.  Contiguous axis: slot (p, kv) holds
+  // entries VW kv .. VW kv + VW - 1 of lines 2p and 2p + 1 (lines past the
+  // end read as zero and are not written); strided axis (every block full):
+  // slot e holds lines VW c .. VW c + VW - 1 at index k, e = k LPB / VW + c.
+  constexpr int NV = XFAST ? P * N / VW : LPB * N / VW;
+  constexpr int PT = (NV + kBlock - 1) / kBlock;
+  constexpr int LV = XFAST ? 2 : 1;
+  constexpr int KV = N / VW;
+  auto gaddr = [&](int e, int h) -> int64_t {
+    if (XFAST) {
+      const int p = e / KV, kv = e - p * KV;
+      return base + (int64_t)(2 * p + h) * N + kv * VW;
+    }
+    const int k = e / (LPB / VW), c = e - k * (LPB / VW);
+    return base + (int64_t)k * inner + c * VW;
+  };
+  auto gvalid = [&](int e, int h) -> bool { return !XFAST || 2 * (e / KV) + h < nl; };
+  vec_t rv[PT][LV];
+#pragma unroll
+  for (int u = 0; u < PT; ++u) {
+    const int e = t + u * kBlock;
+#pragma unroll
+    for (int h = 0; h < LV; ++h) {
+      rv[u][h] = vec_t{};
+      if ((NV % kBlock == 0 || e < NV) && gvalid(e, h))
+        rv[u][h] = *reinterpret_cast<const vec_t*>(X + gaddr(e, h));
+    }
+  }
   for (int e = t; e < N; e += kBlock) tw[e] = Cx<V>{twg[2 * e], twg[2 * e + 1]};
   if (MODE == 2) {
     for (int e = t; e < N; e += kBlock) lam_s[e] = dv.lam[dv.axis][e];
@@ -217,67 +325,161 @@ k_fft_axis(const V* __restrict__ X, V* __restrict__ Y, int inner, int64_t ncols,
       lrest_s[t] = allz ? -1.0 : ls;
     }
   }
-  // element (line l, index k) of this block in global memory
-  auto gidx = [&](int l, int k) -> int64_t {
-    return XFAST ? base + (int64_t)l * N + k : base + (int64_t)k * inner + l;
-  };
-  auto split = [&](int e, int& l, int& k) {
-    if (XFAST) { l = e / N; k = e - l * N; } else { k = e / LPB; l = e - k * LPB; }
-  };
-  // load: lines as packed complex pairs (MODE 0, 2) or as real rows (MODE 1)
-  V* packA = reinterpret_cast<V*>(bufA);
-  for (int e = t; e < LPB * N; e += kBlock) {
-    int l, k;
-    split(e, l, k);
-    const V v = l < nl ? X[gidx(l, k)] : V(0);
-    if (MODE == 1) rowsB[l * N + k] = v;
-    else packA[2 * ((l >> 1) * N + k) + (l & 1)] = v;
+  V* fA = reinterpret_cast<V*>(bufA);
+  V* fB = reinterpret_cast<V*>(bufB);
+  // real row entry (l, c) in LDS, same layout rule as zidx
+  auto ridx = [&](int l, int c) -> int { return IL ? c * LPB + l : l * N + c; };
+  // LDS image of the block: real rows in bufB (MODE 1) or packed pairs in bufA
+#pragma unroll
+  for (int u = 0; u < PT; ++u) {
+    const int e = t + u * kBlock;
+    if (NV % kBlock == 0 || e < NV) {
+      if (IL) {
+        *reinterpret_cast<vec_t*>((MODE == 1 ? fB : fA) + e * VW) = rv[u][0];
+      } else {
+        const int p = e / KV, kv = e - p * KV;
+        if (MODE == 1) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            *reinterpret_cast<vec_t*>(fB + (2 * p + h) * N + kv * VW) = rv[u][h];
+        } else {
+          // interleave the pair: (x1_k, x2_k) for k = VW kv ...
+          vec_t lo, hi;
+#pragma unroll
+          for (int j = 0; j < VW / 2; ++j) {
+            lo[2 * j] = rv[u][0][j];
+            lo[2 * j + 1] = rv[u][1][j];
+            hi[2 * j] = rv[u][0][j + VW / 2];
+            hi[2 * j + 1] = rv[u][1][j + VW / 2];
+          }
+          V* d = fA + 2 * (p * N + kv * VW);
+          *reinterpret_cast<vec_t*>(d) = lo;
+          *reinterpret_cast<vec_t*>(d + VW) = hi;
+        }
+      }
+    }
   }
   __syncthreads();
-  const double a = ax.a, b = ax.b;
-  if (MODE != 1) {
-    Cx<V>* res = fft_lines<V, N, P>(bufA, bufB, tw);
-    // basis coefficients of every line as real rows in the other buffer
-    V* rows = reinterpret_cast<V*>(res == bufA ? bufB : bufA);
-    const V* Z = reinterpret_cast<const V*>(res);
-    for (int e = t; e < LPB * N; e += kBlock) {
-      const int l = e / N, c = e - l * N;
-      V v = spec_coeff<V>(Z + 2 * (l >> 1) * N, N, c, l & 1, a, b);
-      if (MODE == 2) {
-        const double lr = lrest_s[l];
-        v = (lr < 0.0 && c == 0) ? V(0) : (V)((double)v / ((lr < 0.0 ? 0.0 : lr) + lam_s[c]));
+  const V ha = (V)(0.5 * ax.a), hb = (V)ax.b;
+  // work items (p, m), m = 0 .. N / 2: the wavenumber-m pair of lines
+  // 2p, 2p + 1 (N is even for every supported length)
+  constexpr int H = N / 2;
+  constexpr int NI = P * (H + 1);
+  auto item = [&](int e, int& p, int& m) {
+    if (IL) { p = e % P; m = e / P; } else { p = e / (H + 1); m = e - p * (H + 1); }
+  };
+  Cx<V>* spec = bufA;              // conj packed spectrum for the inverse
+  if (MODE == 0) {
+    const Cx<V>* Z = fft_lines<V, N, P, IL>(bufA, bufB, tw);
+    V* rows = reinterpret_cast<V*>(Z == bufA ? bufB : bufA);
+    for (int e = t; e < NI; e += kBlock) {
+      int p, m;
+      item(e, p, m);
+      if (m == 0 || m == H) {
+        const int c = m == 0 ? 0 : N - 1;
+        const Cx<V> z = Z[zidx<N, P, IL>(p, m)];
+        rows[ridx(2 * p, c)] = hb * z.r;
+        rows[ridx(2 * p + 1, c)] = hb * z.i;
+      } else {
+        const Cx<V> zm = Z[zidx<N, P, IL>(p, m)], zn = Z[zidx<N, P, IL>(p, N - m)];
+        rows[ridx(2 * p, 2 * m - 1)] = ha * (zm.r + zn.r);
+        rows[ridx(2 * p + 1, 2 * m - 1)] = ha * (zm.i + zn.i);
+        rows[ridx(2 * p, 2 * m)] = ha * (zn.i - zm.i);
+        rows[ridx(2 * p + 1, 2 * m)] = ha * (zm.r - zn.r);
       }
-      rows[l * N + c] = v;
     }
     __syncthreads();
-    if (MODE == 0) {
-      for (int e = t; e < LPB * N; e += kBlock) {
-        int l, k;
-        split(e, l, k);
-        if (l < nl) Y[gidx(l, k)] = rows[l * N + k];
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+      const int e = t + u * kBlock;
+      if (NV % kBlock == 0 || e < NV) {
+#pragma unroll
+        for (int h = 0; h < LV; ++h) {
+          const int off = IL ? e * VW : (2 * (e / KV) + h) * N + (e % KV) * VW;
+          if (gvalid(e, h))
+            *reinterpret_cast<vec_t*>(Y + gaddr(e, h)) = *reinterpret_cast<const vec_t*>(rows + off);
+        }
       }
-      return;
     }
-    if (rows != rowsB) {
-      for (int e = t; e < LPB * N; e += kBlock) rowsB[e] = rows[e];
-      __syncthreads();
-    }
+    return;
   }
-  // inverse: real rows in bufB -> conj of the packed spectra in bufA
-  for (int e = t; e < P * N; e += kBlock) {
-    const int p = e / N, m = e - p * N;
-    V zr, zi;
-    herm_pack_conj<V>(rowsB + (2 * p) * N, rowsB + (2 * p + 1) * N, N, m, a, b, &zr, &zi);
-    bufA[p * N + m] = Cx<V>{zr, zi};
+  // packed conj spectrum entries m and N - m of pair p from the basis
+  // coefficients: (c1, s1) cosine and sine of wavenumber m of line 2p,
+  // (c2, s2) of line 2p + 1
+  auto put_pair = [&](int p, int m, V c1, V s1, V c2, V s2) {
+    const V y1r = ha * c1, y2r = ha * c2, y1s = ha * s1, y2s = ha * s2;
+    spec[zidx<N, P, IL>(p, m)] = Cx<V>{y1r + y2s, y1s - y2r};
+    spec[zidx<N, P, IL>(p, N - m)] = Cx<V>{y1r - y2s, -(y1s + y2r)};
+  };
+  if (MODE == 2) {
+    const Cx<V>* Z = fft_lines<V, N, P, IL>(bufA, bufB, tw);
+    spec = Z == bufA ? bufB : bufA;
+    // spectrum -> basis coefficients -> division -> packed conj spectrum
+    auto divd = [&](V v, int l, int c) -> V {
+      const double lr = lrest_s[l];
+      if (lr < 0.0 && c == 0) return V(0);
+      return v / (V)((lr < 0.0 ? 0.0 : lr) + lam_s[c]);
+    };
+    for (int e = t; e < NI; e += kBlock) {
+      int p, m;
+      item(e, p, m);
+      if (m == 0 || m == H) {
+        const int c = m == 0 ? 0 : N - 1;
+        const Cx<V> z = Z[zidx<N, P, IL>(p, m)];
+        const V y1 = divd(hb * z.r, 2 * p, c), y2 = divd(hb * z.i, 2 * p + 1, c);
+        spec[zidx<N, P, IL>(p, m)] = Cx<V>{hb * y1, -(hb * y2)};
+      } else {
+        const Cx<V> zm = Z[zidx<N, P, IL>(p, m)], zn = Z[zidx<N, P, IL>(p, N - m)];
+        const int c1 = 2 * m - 1, c2 = 2 * m;
+        put_pair(p, m, divd(ha * (zm.r + zn.r), 2 * p, c1), divd(ha * (zn.i - zm.i), 2 * p, c2),
+                 divd(ha * (zm.i + zn.i), 2 * p + 1, c1), divd(ha * (zm.r - zn.r), 2 * p + 1, c2));
+      }
+    }
+  } else {
+    // MODE 1: real rows in bufB -> packed conj spectrum in bufA
+    for (int e = t; e < NI; e += kBlock) {
+      int p, m;
+      item(e, p, m);
+      if (m == 0 || m == H) {
+        const int c = m == 0 ? 0 : N - 1;
+        spec[zidx<N, P, IL>(p, m)] =
+            Cx<V>{hb * fB[ridx(2 * p, c)], -(hb * fB[ridx(2 * p + 1, c)])};
+      } else {
+        put_pair(p, m, fB[ridx(2 * p, 2 * m - 1)], fB[ridx(2 * p, 2 * m)],
+                 fB[ridx(2 * p + 1, 2 * m - 1)], fB[ridx(2 * p + 1, 2 * m)]);
+      }
+    }
   }
   __syncthreads();
-  Cx<V>* res = fft_lines<V, N, P>(bufA, bufB, tw);
+  Cx<V>* res = fft_lines<V, N, P, IL>(spec, spec == bufA ? bufB : bufA, tw);
   // x1 = Re conj(FFT) = Re FFT, x2 = Im conj(FFT) = -Im FFT
-  for (int e = t; e < LPB * N; e += kBlock) {
-    int l, k;
-    split(e, l, k);
-    const Cx<V> z = res[(l >> 1) * N + k];
-    if (l < nl) Y[gidx(l, k)] = (l & 1) ? -z.i : z.r;
+  const V* fr = reinterpret_cast<const V*>(res);
+#pragma unroll
+  for (int u = 0; u < PT; ++u) {
+    const int e = t + u * kBlock;
+    if (NV % kBlock == 0 || e < NV) {
+      if (IL) {
+        vec_t v = *reinterpret_cast<const vec_t*>(fr + e * VW);
+#pragma unroll
+        for (int j = 1; j < VW; j += 2) v[j] = -v[j];
+        *reinterpret_cast<vec_t*>(Y + gaddr(e, 0)) = v;
+      } else {
+        const int p = e / KV, kv = e - p * KV;
+        const V* s = fr + 2 * (p * N + kv * VW);
+        const vec_t lo = *reinterpret_cast<const vec_t*>(s);
+        const vec_t hi = *reinterpret_cast<const vec_t*>(s + VW);
+        vec_t x1, x2;
+#pragma unroll
+        for (int j = 0; j < VW / 2; ++j) {
+          x1[j] = lo[2 * j];
+          x2[j] = -lo[2 * j + 1];
+          x1[j + VW / 2] = hi[2 * j];
+          x2[j + VW / 2] = -hi[2 * j + 1];
+        }
+        if (gvalid(e, 0)) *reinterpret_cast<vec_t*>(Y + gaddr(e, 0)) = x1;
+        if (gvalid(e, 1)) *reinterpret_cast<vec_t*>(Y + gaddr(e, 1)) = x2;
+      }
+    }
   }
 }
 
@@ -293,25 +495,9 @@ static bool fft_size_supported(int n) {
 
 FftAxis fft_plan(int n, double h) {
   FftAxis ax;
-  ax.on = 0;
-  ax.nst = 0;
-  for (int i = 0; i < kFftMaxStages; ++i) ax.radix[i] = 0;
   ax.a = sqrt(2.0 / n) / sqrt(h);
   ax.b = 1.0 / sqrt(n * h);
-  if (n < 2 || n > kFftMaxN) return ax;
-  int m = n;
-  for (int r : {4, 2, 3, 5}) {
-    while (m % r == 0 && !(r == 2 && m % 4 == 0)) {
-      if (ax.nst == kFftMaxStages) return ax;
-      ax.radix[ax.nst++] = r;
-      m /= r;
-    }
-  }
-  if (m != 1) {
-    ax.nst = 0;
-    return ax;
-  }
-  ax.on = 1;
+  ax.on = fft_size_supported(n) ? 1 : 0;
   return ax;
 }
 
@@ -319,6 +505,8 @@ template <typename V>
 int launch_fft_axis(const FdmPlan<V>& F, int a, int mode, const V* in, V* out, const int* stop,
                     hipStream_t s) {
   const int N = F.n[a];
+  // the kernel moves 16-byte vectors
+  if (((uintptr_t)in | (uintptr_t)out) % 16 != 0) return FVIB_EINVAL;
   int inner = 1;
   for (int q = 0; q < a; ++q) inner *= F.n[q];
   int64_t outer = 1;
