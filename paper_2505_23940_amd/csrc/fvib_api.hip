@@ -504,9 +504,11 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
     auto sweep = [&]() -> int {
       // d = A^+ r by fast diagonalisation: forward axes, then inverse axes,
       // through two scratch buffers; the last forward axis may carry the
-      // first inverse one in the same launch
+      // first inverse one in the same launch, and the last inverse axis may
+      // add d to p itself (else a correction pass follows)
       const int np = 2 * g->dim;
       int pass = 0, buf = 0;
+      bool corrected = false;
       while (pass < np) {
         const bool fwd = pass < g->dim;
         const int a = fwd ? pass : np - 1 - pass;
@@ -520,28 +522,31 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
           // the last pass writes d (with dim >= 2 a fused launch never ends
           // the sweep)
           const bool ends = pass == np - 1;
+          double* acc = ends ? p : nullptr;
           if (d64) {
             const double* in = (pass == 0) ? g->r64 : (buf ? g->pB64 : g->pA64);
             double* outp = (buf ? g->pA64 : g->pB64);
             if (ends) outp = g->d64;
             return launch_fdm_axis<double>(g->F64, a, fwd, in, outp, stop, g->stream,
-                                           can_fuse ? &fused : nullptr);
+                                           can_fuse ? &fused : nullptr, acc, &corrected);
           }
           const float* in = (pass == 0) ? g->r32 : (buf ? g->pB32 : g->pA32);
           float* outp = (buf ? g->pA32 : g->pB32);
           if (ends) outp = g->d32;
           return launch_fdm_axis<float>(g->F32, a, fwd, in, outp, stop, g->stream,
-                                        can_fuse ? &fused : nullptr);
+                                        can_fuse ? &fused : nullptr, acc, &corrected);
         });
         if (r2) return r2;
         pass += fused ? 2 : 1;
         buf ^= 1;
       }
-      int r2 = timed(g, FVIB_K_IR_CORRECT, [&] {
-        return d64 ? launch_add_correction<double>(g->ncell, p, g->d64, stop, g->stream)
-                   : launch_add_correction<float>(g->ncell, p, g->d32, stop, g->stream);
-      });
-      if (r2) return r2;
+      if (!corrected) {
+        int r2 = timed(g, FVIB_K_IR_CORRECT, [&] {
+          return d64 ? launch_add_correction<double>(g->ncell, p, g->d64, stop, g->stream)
+                     : launch_add_correction<float>(g->ncell, p, g->d32, stop, g->stream);
+        });
+        if (r2) return r2;
+      }
       return residual(0);
     };
     if ((rc = residual(1))) return rc;

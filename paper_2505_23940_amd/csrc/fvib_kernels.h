@@ -58,9 +58,11 @@ struct FdmPlan {
 FftAxis fft_plan(int n, double h);
 
 // k_fft.hip: mode 0 forward, 1 inverse, 2 forward + division + inverse.
+// acc (nullable, contiguous axis, mode 1): add the result to acc instead
+// of storing it in out.
 template <typename V>
 int launch_fft_axis(const FdmPlan<V>& F, int a, int mode, const V* in, V* out, const int* stop,
-                    hipStream_t s);
+                    hipStream_t s, double* acc = nullptr);
 template <typename V>
 bool fft_usable(const FdmPlan<V>& F, int a);
 
@@ -139,9 +141,12 @@ bool fdm_fuses_last_axis(const FdmPlan<V>& F);
 // fused (nullable): on the last forward axis, ask for the first inverse
 // contraction of the same axis to run in the same launch; *fused tells
 // whether it did (out then holds the inverse-transformed values).
+// acc (nullable): on an inverse axis, ask for the result to be added to the
+// double array acc instead of stored in out; *accd tells whether it was.
 template <typename V>
 int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, const int* stop,
-                    hipStream_t s, bool* fused = nullptr);
+                    hipStream_t s, bool* fused = nullptr, double* acc = nullptr,
+                    bool* accd = nullptr);
 template <typename V>
 int launch_add_correction(int64_t n, double* p, const V* d, const int* stop, hipStream_t s);
 int launch_gauge(int64_t n, double* p, const SolverScalars* sc, hipStream_t s);

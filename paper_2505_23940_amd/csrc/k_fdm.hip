@@ -636,10 +636,15 @@ bool fdm_fuses_last_axis(const FdmPlan<V>& F) {
 
 template <typename V>
 int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, const int* stop,
-                    hipStream_t s, bool* fused) {
+                    hipStream_t s, bool* fused, double* acc, bool* accd) {
   if (fused) *fused = false;
+  if (accd) *accd = false;
   if (fft_usable(F, a)) {
     const bool last = fwd && a == F.dim - 1;
+    if (!fwd && acc && accd && a == 0) {
+      *accd = true;
+      return launch_fft_axis<V>(F, a, 1, in, out, stop, s, acc);
+    }
     if (!last) return launch_fft_axis<V>(F, a, fwd ? 0 : 1, in, out, stop, s);
     if (fused) {
       *fused = true;
@@ -773,9 +778,9 @@ int launch_gauge(int64_t n, double* p, const SolverScalars* sc, hipStream_t s) {
 template bool fdm_fuses_last_axis<float>(const FdmPlan<float>&);
 template bool fdm_fuses_last_axis<double>(const FdmPlan<double>&);
 template int launch_fdm_axis<float>(const FdmPlan<float>&, int, bool, const float*, float*,
-                                    const int*, hipStream_t, bool*);
+                                    const int*, hipStream_t, bool*, double*, bool*);
 template int launch_fdm_axis<double>(const FdmPlan<double>&, int, bool, const double*, double*,
-                                     const int*, hipStream_t, bool*);
+                                     const int*, hipStream_t, bool*, double*, bool*);
 template int launch_add_correction<float>(int64_t, double*, const float*, const int*, hipStream_t);
 template int launch_add_correction<double>(int64_t, double*, const double*, const int*,
                                            hipStream_t);

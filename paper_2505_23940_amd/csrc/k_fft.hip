@@ -258,11 +258,15 @@ __device__ __forceinline__ Cx<V>* fft_lines(Cx<V>* src, Cx<V>* dst, const Cx<V>*
 // conj FFT(conj(Y1 + i Y2)) splits into the two real lines.
 
 // MODE 0: forward (lines -> basis coefficients), 1: inverse, 2: forward,
-// division by the eigenvalue sum, inverse.  N is the axis length.
-template <typename V, int N, bool XFAST, int MODE>
+// division by the eigenvalue sum, inverse.  N is the axis length.  ACC
+// (contiguous axis, MODE 1): the result is added to the double array pacc
+// instead of being stored in Y (the refinement correction p += d of the
+// last pass of a sweep).
+template <typename V, int N, bool XFAST, int MODE, bool ACC>
 __global__ void __launch_bounds__(kBlock)
 k_fft_axis(const V* __restrict__ X, V* __restrict__ Y, int inner, int64_t ncols, FftAxis ax,
-           const V* __restrict__ twg, FdmDiv dv, const int* stop) {
+           const V* __restrict__ twg, FdmDiv dv, const int* stop, double* __restrict__ pacc) {
+  static_assert(!ACC || (XFAST && MODE == 1), "accumulation is for the contiguous inverse");
   if (stop && *stop) return;
   constexpr bool IL = !XFAST;
   typedef FftCfg<V> C;
@@ -306,6 +310,22 @@ k_fft_axis(const V* __restrict__ X, V* __restrict__ Y, int inner, int64_t ncols,
       rv[u][h] = vec_t{};
       if ((NV % kBlock == 0 || e < NV) && gvalid(e, h))
         rv[u][h] = *reinterpret_cast<const vec_t*>(X + gaddr(e, h));
+    }
+  }
+  // ACC: the accumulator entries of this thread's output slots, fetched
+  // with the input
+  typedef __attribute__((ext_vector_type(VW))) double dvec_t;
+  dvec_t pv[ACC ? PT : 1][ACC ? LV : 1];
+  if constexpr (ACC) {
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+      const int e = t + u * kBlock;
+#pragma unroll
+      for (int h = 0; h < LV; ++h) {
+        pv[u][h] = dvec_t{};
+        if ((NV % kBlock == 0 || e < NV) && gvalid(e, h))
+          pv[u][h] = *reinterpret_cast<const dvec_t*>(pacc + gaddr(e, h));
+      }
     }
   }
   for (int e = t; e < N; e += kBlock) tw[e] = Cx<V>{twg[2 * e], twg[2 * e + 1]};
@@ -476,8 +496,19 @@ k_fft_axis(const V* __restrict__ X, V* __restrict__ Y, int inner, int64_t ncols,
           x1[j + VW / 2] = hi[2 * j];
           x2[j + VW / 2] = -hi[2 * j + 1];
         }
-        if (gvalid(e, 0)) *reinterpret_cast<vec_t*>(Y + gaddr(e, 0)) = x1;
-        if (gvalid(e, 1)) *reinterpret_cast<vec_t*>(Y + gaddr(e, 1)) = x2;
+        if constexpr (ACC) {
+          dvec_t q1 = pv[u][0], q2 = pv[u][LV - 1];
+#pragma unroll
+          for (int j = 0; j < VW; ++j) {
+            q1[j] += (double)x1[j];
+            q2[j] += (double)x2[j];
+          }
+          if (gvalid(e, 0)) *reinterpret_cast<dvec_t*>(pacc + gaddr(e, 0)) = q1;
+          if (gvalid(e, 1)) *reinterpret_cast<dvec_t*>(pacc + gaddr(e, 1)) = q2;
+        } else {
+          if (gvalid(e, 0)) *reinterpret_cast<vec_t*>(Y + gaddr(e, 0)) = x1;
+          if (gvalid(e, 1)) *reinterpret_cast<vec_t*>(Y + gaddr(e, 1)) = x2;
+        }
       }
     }
   }
@@ -503,36 +534,40 @@ FftAxis fft_plan(int n, double h) {
 
 template <typename V>
 int launch_fft_axis(const FdmPlan<V>& F, int a, int mode, const V* in, V* out, const int* stop,
-                    hipStream_t s) {
+                    hipStream_t s, double* acc) {
   const int N = F.n[a];
-  // the kernel moves 16-byte vectors
-  if (((uintptr_t)in | (uintptr_t)out) % 16 != 0) return FVIB_EINVAL;
+  // the kernel moves 16-byte vectors (32-byte ones of the accumulator)
+  if (((uintptr_t)in | (uintptr_t)out) % 16 != 0 || (uintptr_t)acc % 32 != 0) return FVIB_EINVAL;
   int inner = 1;
   for (int q = 0; q < a; ++q) inner *= F.n[q];
   int64_t outer = 1;
   for (int q = a + 1; q < 3; ++q) outer *= F.n[q];
   const int64_t ncols = outer * inner;
+  if (acc && !(inner == 1 && mode == 1)) return FVIB_EINVAL;
+  if (inner == 1 && mode == 2) return FVIB_EINVAL;
   constexpr int LPB = FftCfg<V>::LPB;
   const dim3 g((unsigned)((ncols + LPB - 1) / LPB));
   bool done = false;
-#define FVIB_FFT(NN, XF, M)                                                                     \
-  hipLaunchKernelGGL((k_fft_axis<V, NN, XF, M>), g, dim3(kBlock), 0, s, in, out, inner, ncols,  \
-                     F.fft[a], F.tw[a], F.div, stop)
+#define FVIB_FFT(NN, XF, M, AC)                                                                 \
+  hipLaunchKernelGGL((k_fft_axis<V, NN, XF, M, AC>), g, dim3(kBlock), 0, s, in, out, inner,     \
+                     ncols, F.fft[a], F.tw[a], F.div, stop, acc)
 #define FVIB_FFT_N(NN)                                                                          \
   if (!done && N == NN) {                                                                       \
     done = true;                                                                                \
     if (inner == 1) {                                                                           \
-      if (mode == 0) FVIB_FFT(NN, true, 0); else FVIB_FFT(NN, true, 1);                         \
+      if (mode == 0) FVIB_FFT(NN, true, 0, false);                                              \
+      else if (acc) FVIB_FFT(NN, true, 1, true);                                                \
+      else FVIB_FFT(NN, true, 1, false);                                                        \
     } else {                                                                                    \
-      if (mode == 0) FVIB_FFT(NN, false, 0);                                                    \
-      else if (mode == 1) FVIB_FFT(NN, false, 1);                                               \
-      else FVIB_FFT(NN, false, 2);                                                              \
+      if (mode == 0) FVIB_FFT(NN, false, 0, false);                                             \
+      else if (mode == 1) FVIB_FFT(NN, false, 1, false);                                        \
+      else FVIB_FFT(NN, false, 2, false);                                                       \
     }                                                                                           \
   }
   FVIB_FFT_SIZES(FVIB_FFT_N)
 #undef FVIB_FFT_N
 #undef FVIB_FFT
-  if (!done || (inner == 1 && mode == 2)) return FVIB_EINVAL;
+  if (!done) return FVIB_EINVAL;
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
@@ -547,9 +582,9 @@ bool fft_usable(const FdmPlan<V>& F, int a) {
 }
 
 template int launch_fft_axis<float>(const FdmPlan<float>&, int, int, const float*, float*,
-                                    const int*, hipStream_t);
+                                    const int*, hipStream_t, double*);
 template int launch_fft_axis<double>(const FdmPlan<double>&, int, int, const double*, double*,
-                                     const int*, hipStream_t);
+                                     const int*, hipStream_t, double*);
 template bool fft_usable<float>(const FdmPlan<float>&, int);
 template bool fft_usable<double>(const FdmPlan<double>&, int);
 
