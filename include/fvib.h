@@ -150,6 +150,10 @@ typedef struct {
   void *fb[3];              /* adjoint body force (accumulated), may be NULL   */
   double *body;             /* adjoint body state (6 doubles)                  */
   double *kc;               /* adjoint spring constants (accumulated, 6)       */
+  double *mu;               /* adjoint pressure (cells, like p), may be NULL:  */
+                            /* in bar_in, the initial guess of the step's      */
+                            /* adjoint Poisson solve on input and its solution */
+                            /* on output; NULL starts from zero in workspace   */
 } fvib_adjoint;
 
 /* Step diagnostics, written on the stream into device (or host-mapped)
@@ -202,7 +206,11 @@ int fvib_step(fvib_grid *g, const fvib_fields *in, fvib_fields *out,
  * the direct derivative of the loss with respect to the force F^n reported
  * by the step, may be NULL) -- it writes bar_in->u (u^n) and
  * bar_in->body (body state^n) and adds into bar_in->fb and bar_in->kc.
- * bar_in may not alias bar_out.  The pressure of fwd_in is not used. */
+ * bar_in may not alias bar_out.  The pressure of fwd_in is not used.
+ * bar_in->mu (optional) warm-starts the adjoint solve, e.g. with the
+ * previous adjoint step's solution along a rollout; a warm start that
+ * does not converge within the sweeps its first check allows is dropped
+ * and the solve restarts from zero, so the stopping test is the same. */
 int fvib_step_adjoint(fvib_grid *g, const fvib_fields *fwd_in,
                       const fvib_adjoint *bar_out, const double *dF,
                       fvib_adjoint *bar_in, fvib_step_info *info);

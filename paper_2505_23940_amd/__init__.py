@@ -266,7 +266,14 @@ class Grid:
     # --------------------------------------------------------- adjoint
     def step_adjoint(self, u, fb, body, kc, ubar_out, bodybar_out, dF, ubar_in, bodybar_in,
                      fbbar=None, kcbar=None, check: bool = True,
-                     info: Optional[torch.Tensor] = None) -> int:
+                     info: Optional[torch.Tensor] = None,
+                     mu: Optional[torch.Tensor] = None) -> int:
+        """Adjoint of one step (fvib_step_adjoint).  mu (optional, float64,
+        pressure layout) warm-starts the adjoint Poisson solve and receives
+        its solution."""
+        if mu is not None and (tuple(mu.shape) != tuple(self.pshape) or mu.dtype != torch.float64
+                               or not mu.is_contiguous() or mu.device != self.device):
+            raise ValueError(f"mu must be a contiguous float64 tensor of shape {self.pshape}")
         fin = self._fields(u, None, fb, body, kc)
         fin.p = 0
         bo = _abi.Adjoint()
@@ -278,6 +285,7 @@ class Grid:
         bo.body = _ptr(bodybar_out)
         bi.body = _ptr(bodybar_in)
         bi.kc = _ptr(kcbar)
+        bi.mu = _ptr(mu)
         rc = fvib_step_adjoint(self.h, fin, bo, _ptr(dF), bi,
                                _ptr(info if info is not None else self._info))
         if check:

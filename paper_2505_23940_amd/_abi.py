@@ -69,6 +69,7 @@ class Fields(C.Structure):
 class Adjoint(C.Structure):
     _fields_ = [
         ("u", C.c_void_p * 3), ("fb", C.c_void_p * 3), ("body", C.c_void_p), ("kc", C.c_void_p),
+        ("mu", C.c_void_p),
     ]
 
 

@@ -471,8 +471,12 @@ static int read_scalars(Grid* g) {
 // gauge: remove the mean of the fast-diagonalisation result (the pressure
 // returned by a step); the adjoint pressure enters only through differences
 // and skips it.
+// warm: p holds a guess that may be discarded (fast diagonalisation only):
+// if a host check finds the refinement stalled (the criterion fell by less
+// than a factor 10 since the previous check) before it converged, p
+// restarts from zero.
 static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* last,
-                         int* cg_total, int* ir_total, bool gauge = true) {
+                         int* cg_total, int* ir_total, bool gauge = true, bool warm = false) {
   int rc;
   *cg_total = 0;
   *ir_total = 0;
@@ -552,12 +556,24 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
     if ((rc = residual(1))) return rc;
     int launched = 0;
     int batch = std::max(1, std::min(g->last_iters, g->d.ir_maxit));
+    double prev_crit = HUGE_VAL;
     for (;;) {
       for (int q = 0; q < batch && launched < g->d.ir_maxit; ++q, ++launched)
         if ((rc = sweep())) return rc;
       if ((rc = read_scalars(g))) return rc;
       g->crit_log.push_back(g->sch->crit);
       if (g->sch->outer_done) break;
+      if (warm && !(g->sch->crit < 0.1 * prev_crit)) {
+        // the guess has stalled the refinement: restart from zero with the
+        // full budget
+        warm = false;
+        launched = 0;
+        FVIB_HIP(hipMemsetAsync(p, 0, g->ncell * sizeof(double), g->stream));
+        if ((rc = residual(1))) return rc;
+        batch = 2;
+        continue;
+      }
+      prev_crit = g->sch->crit;
       if (launched >= g->d.ir_maxit) {
         // refinement budget exhausted: report it on the device scalars
         int stc = FVIB_ENOCONV;
@@ -793,21 +809,26 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
        })))
     return rc;
   int cg = 0, ir = 0;
-  // Start from zero: the target is relative to this right-hand side, and a
-  // warm start from another step's solution would put the double rounding
-  // floor of the residual (~eps |A mu|) above it when the right-hand side
-  // is small (e.g. zero up to rounding).
-  FVIB_HIP(hipMemsetAsync(g->mu, 0, g->ncell * sizeof(double), g->stream));
-  if ((rc = poisson_solve(g, g->b, g->mu, -1.0, &g->last_iters_adj, &cg, &ir, false))) return rc;
+  // A caller's guess (the previous adjoint step's solution) usually leaves
+  // one sweep to do.  The target is relative to this right-hand side, so a
+  // guess much larger than this step's solution can hold the double
+  // rounding floor of the residual (~eps |A mu|) above it; such a guess is
+  // dropped at the first check (see poisson_solve).  Without a guess the
+  // solve starts from zero in the workspace.
+  const bool warm = bi->mu != nullptr && g->d.solver == FVIB_SOLVER_FDM;
+  double* mu = bi->mu ? bi->mu : g->mu;
+  if (!warm) FVIB_HIP(hipMemsetAsync(mu, 0, g->ncell * sizeof(double), g->stream));
+  if ((rc = poisson_solve(g, g->b, mu, -1.0, &g->last_iters_adj, &cg, &ir, false, warm)))
+    return rc;
   if (g->defer && g->sch->status == FVIB_ENOCONV)
     return fail(g, FVIB_ENOCONV, "adjoint Poisson solve did not converge" +
                                      describe_solve(g, g->sch->tol_dev));
   if ((rc = timed(g, FVIB_K_ADJOINT,
-                  [&] { return launch_adj_ustar<T>(G, g->P64, ub1, g->mu, ib, usb, g->sc, g->stream); })))
+                  [&] { return launch_adj_ustar<T>(G, g->P64, ub1, mu, ib, usb, g->sc, g->stream); })))
     return rc;
   if (g->has_body && bi->body) {
     rc = timed(g, FVIB_K_IB, [&] {
-      return launch_adj_ubody<T>(G, g->P64, g->ib, ub1, g->mu, ib, bi->body, g->sc, g->stream);
+      return launch_adj_ubody<T>(G, g->P64, g->ib, ub1, mu, ib, bi->body, g->sc, g->stream);
     });
     if (rc) return rc;
   }

@@ -85,6 +85,8 @@ class _Rollout(torch.autograd.Function):
         gF = gF.contiguous() if gF is not None else torch.zeros((S, 3), dtype=torch.float64, device=grid.device)
         fbbar = grid.zeros_u()
         kcbar = torch.zeros(6, dtype=torch.float64, device=grid.device)
+        # adjoint pressure, carried from step to step as the next solve's guess
+        mu = grid.zeros_p()
         starts = list(range(0, S, K))
         # recomputed and adjoint steps are enqueued back to back; their
         # statuses are checked once at the end
@@ -112,7 +114,7 @@ class _Rollout(torch.autograd.Function):
                     un, bn = states[n - s0]
                     dF = gF[n].contiguous()
                     grid.step_adjoint(un, fb, bn, kc, ubar, bbar, dF, ubar_tmp, bbar_tmp,
-                                      fbbar=fbbar, kcbar=kcbar, info=infos_a[n])
+                                      fbbar=fbbar, kcbar=kcbar, info=infos_a[n], mu=mu)
                     ubar, ubar_tmp = ubar_tmp, ubar
                     bbar, bbar_tmp = bbar_tmp, bbar
         finally:

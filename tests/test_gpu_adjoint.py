@@ -196,3 +196,49 @@ def test_checkpoint_interval_invariance():
     for x, y in zip(a[1], b[1]):
         assert np.abs(x - y).max() <= 1e-13 * max(np.abs(y).max(), 1e-30)
     assert np.abs(a[2] - b[2]).max() <= 1e-13 * np.abs(b[2]).max()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_adjoint_mu_warm_start(precision):
+    """The adjoint solve's optional guess changes nothing beyond the solve
+    tolerance: an exact guess, a poor guess (the solve restarts from zero
+    if the guess stalls it) and, with a zero right-hand side, a large guess
+    that must be dropped."""
+    need_gpu()
+    w = _rollout_case("channel")
+    u, fb, body, kc, ubar, bbar, dF = _inputs(w, 17, False)
+    g = make_grid(w, precision=precision, poisson_tol=1e-12)
+    dev = g.device
+    ut, fbt = g.to_u(u), g.to_u(fb)
+    bt = torch.tensor(body, dtype=F64, device=dev)
+    kct = torch.tensor(kc, dtype=F64, device=dev)
+    dFt = torch.tensor(dF, dtype=F64, device=dev)
+    bb1 = torch.tensor(bbar, dtype=F64, device=dev)
+
+    def run(ub1, mu):
+        ub0, fbb = g.zeros_u(), g.zeros_u()
+        bb0 = torch.zeros(6, dtype=F64, device=dev)
+        kcb = torch.zeros(6, dtype=F64, device=dev)
+        g.step_adjoint(ut, fbt, bt, kct, ub1, bb1, dFt, ub0, bb0, fbbar=fbb, kcbar=kcb, mu=mu)
+        torch.cuda.synchronize()
+        return [x.double().cpu().numpy() for x in ub0 + fbb]
+
+    ub1 = g.to_u(ubar)
+    ref = run(ub1, None)
+    tol = 1e-9 if precision == "fp64" else 2e-4
+    mu = g.zeros_p()
+    for guess in ("zero", "exact", "poor"):
+        if guess == "poor":
+            gen = torch.Generator(device="cpu").manual_seed(3)
+            mu.copy_(torch.randn(tuple(g.pshape), generator=gen, dtype=F64) * float(mu.abs().max()))
+        out = run(ub1, mu)
+        for a, b in zip(out, ref):
+            _close(a, b, tol, guess)
+    # zero right-hand side: outputs vanish whatever the guess
+    z = [torch.zeros_like(x) for x in ub1]
+    bb1.zero_()
+    dFt.zero_()
+    mu.copy_(torch.randn(tuple(g.pshape), generator=torch.Generator().manual_seed(4), dtype=F64))
+    out = run(z, mu)
+    for a in out[:w.dim]:
+        assert np.abs(a).max() == 0.0
