@@ -280,10 +280,13 @@ enum {
   FVIB_K_ADJ_MOMENTUM = 13, /* transposed momentum stencil (all components) */
   FVIB_K_FDM_LAST = 14,   /* last axis: forward, division and inverse in one */
   FVIB_K_FFT = 15,        /* real FFT along a uniform periodic axis          */
-  FVIB_K_NCLASSES = 16
+  FVIB_K_FFT_ACC = 16,    /* last inverse FFT of a sweep, adding into p      */
+  FVIB_K_NCLASSES = 17
 };
 
-/* Start (enable != 0, totals cleared) or stop recording. */
+/* Start (enable != 0, totals cleared) or stop recording.  A recorded
+ * launch is timed from the start of its first kernel to the end of its
+ * last (kernel execution only). */
 int fvib_timing_enable(fvib_grid *g, int enable);
 
 /* Restrict recording to the classes whose bit (1u << class) is set in
@@ -291,9 +294,20 @@ int fvib_timing_enable(fvib_grid *g, int enable);
  * close to that of an untimed run. */
 int fvib_timing_select(fvib_grid *g, uint32_t class_mask);
 
+/* Record one launch in `every` (>= 1, default 1) of each class.  Each
+ * recorded launch carries timestamp events in its dispatch, which idles
+ * the device for a few microseconds around it; sampling keeps a timed run
+ * close to an untimed one. */
+int fvib_timing_sample(fvib_grid *g, int every);
+
 /* Total device time (ms) and launch count of one kernel class since the
- * last enable; synchronises the stream. */
+ * last enable; synchronises the stream.  Launches of refinement sweeps
+ * that the device skipped (queued ahead of the convergence check and found
+ * the solve converged) are not included. */
 int fvib_timing_read(fvib_grid *g, int kclass, double *total_ms, int64_t *launches);
+
+/* The same for the skipped launches alone (each returns at once). */
+int fvib_timing_read_skipped(fvib_grid *g, int kclass, double *total_ms, int64_t *launches);
 
 /* Deferred status (on != 0): fvib_step and fvib_step_adjoint return as soon
  * as the step's work is enqueued instead of waiting for it, so the host can

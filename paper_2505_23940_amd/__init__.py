@@ -322,24 +322,29 @@ class Grid:
             raise RuntimeError(f"libfvib {what} {n}: status {int(st[n])}")
 
     # --------------------------------------------------------- timing
-    def timing_enable(self, on: bool = True, classes=None) -> None:
+    def timing_enable(self, on: bool = True, classes=None, every: int = 1) -> None:
         """Start (totals cleared) or stop event timing; `classes` (names of
-        _abi.K_CLASSES) restricts it to those kernel classes."""
+        _abi.K_CLASSES) restricts it to those kernel classes, `every` times
+        one launch in `every` of each class."""
         mask = 0xFFFFFFFF
         if classes is not None:
             mask = 0
             for name in classes:
                 mask |= 1 << _abi.K_CLASSES[name]
         _check(lib().fvib_timing_select(self.h, mask), self.h)
+        _check(lib().fvib_timing_sample(self.h, int(every)), self.h)
         _check(lib().fvib_timing_enable(self.h, 1 if on else 0), self.h)
 
-    def timing_read(self) -> dict:
-        """{kernel class: (total_ms, launches)} since the last enable."""
+    def timing_read(self, skipped: bool = False) -> dict:
+        """{kernel class: (total_ms, launches)} since the last enable; with
+        skipped, the launches of refinement sweeps that the device skipped
+        (excluded from the default figures)."""
+        fn = lib().fvib_timing_read_skipped if skipped else lib().fvib_timing_read
         out = {}
         for name, k in _abi.K_CLASSES.items():
             ms = C.c_double()
             n = C.c_int64()
-            _check(lib().fvib_timing_read(self.h, k, C.byref(ms), C.byref(n)), self.h)
+            _check(fn(self.h, k, C.byref(ms), C.byref(n)), self.h)
             out[name] = (ms.value, n.value)
         return out
 

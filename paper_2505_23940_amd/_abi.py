@@ -27,12 +27,14 @@ EXPORTS = (
     "fvib_test_apply_A", "fvib_test_ib_classify", "fvib_timing_enable", "fvib_timing_select",
     "fvib_defer_status",
     "fvib_timing_read",
+    "fvib_timing_read_skipped",
+    "fvib_timing_sample",
     "fvib_version",
 )
 K_CLASSES = {"predictor": 0, "boundary": 1, "ppe_rhs": 2, "residual": 3, "cg_dir": 4,
              "cg_update": 5, "ir_correct": 6, "project": 7, "ib": 8, "adjoint": 9,
              "fdm_x": 10, "fdm_y": 11, "fdm_z": 12, "adj_momentum": 13, "fdm_last": 14,
-             "fft": 15}
+             "fft": 15, "fft_acc": 16}
 
 
 class GridDesc(C.Structure):
@@ -115,6 +117,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.fvib_timing_select.argtypes = [vp, C.c_uint32]
     lib.fvib_defer_status.argtypes = [vp, i32]
     lib.fvib_timing_read.argtypes = [vp, i32, C.POINTER(C.c_double), i64p]
+    lib.fvib_timing_read_skipped.argtypes = [vp, i32, C.POINTER(C.c_double), i64p]
+    lib.fvib_timing_sample.argtypes = [vp, i32]
     lib.fvib_version.restype = C.c_char_p
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype or C.c_int

@@ -12,6 +12,7 @@
 
 namespace fvib {
 
+thread_local LaunchTiming* t_launch_timing = nullptr;
 static thread_local std::string g_create_error;
 
 int hip_fail(hipError_t e, const char* what, const char* file, int line) {
@@ -26,15 +27,39 @@ int hip_fail(hipError_t e, const char* what, const char* file, int line) {
 struct Timer {
   bool on = false;
   uint32_t mask = 0xffffffffu;   // classes recorded while on
+  int every = 1;                 // record one launch in `every` of each class
+  int64_t seen[FVIB_K_NCLASSES] = {0};
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   struct Pending {
     int cls;
     hipEvent_t a, b;
+    int tag;                     // refinement sweep number (0: not a sweep)
+    bool noop;                   // skipped on the device (after convergence)
   };
   std::vector<Pending> pending;
   double total[FVIB_K_NCLASSES] = {0};
   int64_t count[FVIB_K_NCLASSES] = {0};
+  double total_noop[FVIB_K_NCLASSES] = {0};
+  int64_t count_noop[FVIB_K_NCLASSES] = {0};
+  // Speculative refinement sweeps: launches are tagged with their sweep
+  // number; when the solve ends, those past the sweeps that ran are
+  // counted apart (their kernels returned at once).
+  int tag = 0;
+  size_t solve_begin = 0;
+  void begin_solve() {
+    solve_begin = pending.size();
+    tag = 0;
+  }
+  void restart_solve() {          // every sweep so far ran
+    for (size_t i = solve_begin; i < pending.size(); ++i) pending[i].tag = 0;
+    tag = 0;
+  }
+  void end_solve(int sweeps_run) {
+    for (size_t i = solve_begin; i < pending.size(); ++i)
+      if (pending[i].tag > sweeps_run) pending[i].noop = true;
+    tag = 0;
+  }
 
   hipEvent_t next() {
     if (used == pool.size()) {
@@ -47,26 +72,28 @@ struct Timer {
   // record the start of a launch of class cls; returns the event pair slot
   void mark(hipStream_t s, int cls, hipEvent_t a, hipEvent_t b) {
     (void)s;
-    pending.push_back({cls, a, b});
+    pending.push_back({cls, a, b, tag, false});
   }
   // all recorded events must be complete (stream synchronised)
   void resolve() {
     for (const Pending& p : pending) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-        total[p.cls] += ms;
-        count[p.cls] += 1;
+        (p.noop ? total_noop : total)[p.cls] += ms;
+        (p.noop ? count_noop : count)[p.cls] += 1;
       }
     }
     pending.clear();
+    solve_begin = 0;
     used = 0;
   }
   void clear() {
     pending.clear();
+    solve_begin = 0;
     used = 0;
     for (int i = 0; i < FVIB_K_NCLASSES; ++i) {
-      total[i] = 0;
-      count[i] = 0;
+      total[i] = total_noop[i] = 0;
+      count[i] = count_noop[i] = 0;
     }
   }
   ~Timer() {
@@ -190,12 +217,14 @@ static void release(Grid* g) {
 template <typename F>
 static int timed(Grid* g, int cls, F&& launch) {
   if (!g->timer.on || !((g->timer.mask >> cls) & 1u)) return launch();
+  if (g->timer.every > 1 && (g->timer.seen[cls]++ % g->timer.every) != 0) return launch();
   hipEvent_t a = g->timer.next(), b = g->timer.next();
   if (!a || !b) return launch();
-  FVIB_HIP(hipEventRecord(a, g->stream));
+  LaunchTiming lt{a, b, true};
+  t_launch_timing = &lt;
   int rc = launch();
-  FVIB_HIP(hipEventRecord(b, g->stream));
-  g->timer.mark(g->stream, cls, a, b);
+  t_launch_timing = nullptr;
+  if (!lt.first) g->timer.mark(g->stream, cls, a, b);   // at least one kernel ran
   return rc;
 }
 
@@ -499,6 +528,7 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
     // the queue return at once.  The host synchronises once per batch.
     const bool d64 = g->prec == FVIB_PREC_FP64;
     const int* stop = &g->sc->outer_done;
+    int launched = 0;              // sweeps launched since the last restart
     auto residual = [&](int first) {
       return timed(g, FVIB_K_RESIDUAL, [&] {
         return launch_residual(g->P64, d64 ? 3 : 2, b, p, g->r64, g->r32, nullptr, g->red(),
@@ -506,6 +536,7 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
       });
     };
     auto sweep = [&]() -> int {
+      g->timer.tag = launched + 1;
       // d = A^+ r by fast diagonalisation: forward axes, then inverse axes,
       // through two scratch buffers; the last forward axis may carry the
       // first inverse one in the same launch, and the last inverse axis may
@@ -521,7 +552,9 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
                                                 : fdm_fuses_last_axis<float>(g->F32));
         const bool by_fft = d64 ? fft_usable<double>(g->F64, a) : fft_usable<float>(g->F32, a);
         bool fused = false;
-        const int cls = by_fft ? FVIB_K_FFT : (will_fuse ? FVIB_K_FDM_LAST : FVIB_K_FDM_X + a);
+        // the last pass adds d into p when it is a contiguous FFT (a = 0)
+        const int cls = by_fft ? (pass == np - 1 ? FVIB_K_FFT_ACC : FVIB_K_FFT)
+                               : (will_fuse ? FVIB_K_FDM_LAST : FVIB_K_FDM_X + a);
         int r2 = timed(g, cls, [&] {
           // the last pass writes d (with dim >= 2 a fused launch never ends
           // the sweep)
@@ -553,8 +586,9 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
       }
       return residual(0);
     };
+    g->timer.begin_solve();
     if ((rc = residual(1))) return rc;
-    int launched = 0;
+    launched = 0;
     int batch = std::max(1, std::min(g->last_iters, g->d.ir_maxit));
     double prev_crit = HUGE_VAL;
     for (;;) {
@@ -568,6 +602,7 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
         // full budget
         warm = false;
         launched = 0;
+        g->timer.restart_solve();
         FVIB_HIP(hipMemsetAsync(p, 0, g->ncell * sizeof(double), g->stream));
         if ((rc = residual(1))) return rc;
         batch = 2;
@@ -584,10 +619,11 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
       }
       batch = 1;
     }
+    const int sweeps = g->sch->outer_done ? g->sch->sweeps : launched;
+    g->timer.end_solve(sweeps);
     if (gauge &&
         (rc = timed(g, FVIB_K_IR_CORRECT, [&] { return launch_gauge(g->ncell, p, g->sc, g->stream); })))
       return rc;
-    const int sweeps = g->sch->outer_done ? g->sch->sweeps : launched;
     g->last_iters = sweeps;
     *cg_total = 0;
     *ir_total = sweeps;
@@ -1382,6 +1418,23 @@ int fvib_timing_read(fvib_grid* h, int kclass, double* total_ms, int64_t* launch
   g->timer.resolve();
   if (total_ms) *total_ms = g->timer.total[kclass];
   if (launches) *launches = g->timer.count[kclass];
+  return FVIB_OK;
+}
+
+int fvib_timing_sample(fvib_grid* h, int every) {
+  if (!h || every < 1) return FVIB_EINVAL;
+  h->g.timer.every = every;
+  for (int i = 0; i < FVIB_K_NCLASSES; ++i) h->g.timer.seen[i] = 0;
+  return FVIB_OK;
+}
+
+int fvib_timing_read_skipped(fvib_grid* h, int kclass, double* total_ms, int64_t* launches) {
+  if (!h || kclass < 0 || kclass >= FVIB_K_NCLASSES) return FVIB_EINVAL;
+  Grid* g = &h->g;
+  FVIB_HIP(hipStreamSynchronize(g->stream));
+  g->timer.resolve();
+  if (total_ms) *total_ms = g->timer.total_noop[kclass];
+  if (launches) *launches = g->timer.count_noop[kclass];
   return FVIB_OK;
 }
 

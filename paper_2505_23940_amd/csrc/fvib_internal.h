@@ -6,12 +6,37 @@
 // 64-wide wavefronts, 256-thread blocks, eight XCDs with private L2.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "fvib.h"
 
 namespace fvib {
+
+// Kernel timing without marker packets: while a timed section is open on
+// this thread, launches carry the section's events in their own dispatch
+// (the first launch records the start, every launch the end), so the
+// measured interval is kernel execution only and the stream gets no extra
+// packets between kernels.
+struct LaunchTiming {
+  hipEvent_t start, stop;
+  bool first;                    // no launch has recorded start yet
+};
+extern thread_local LaunchTiming* t_launch_timing;
+
+template <typename F, typename... Args>
+inline void launch_kernel(F kernel, const dim3& grid, const dim3& block, uint32_t shmem,
+                          hipStream_t s, Args... args) {
+  LaunchTiming* lt = t_launch_timing;
+  if (!lt) {
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+    return;
+  }
+  hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, lt->first ? lt->start : nullptr, lt->stop,
+                        0u, args...);
+  lt->first = false;
+}
 
 constexpr int kBlock = 256;          // threads per block (4 wavefronts)
 constexpr int kTileX = 64;           // one wavefront spans 64 consecutive x
@@ -358,7 +383,7 @@ k_reduce_finish(const double* __restrict__ partial, int nb, SolverScalars* sc, F
 template <int NV, int NS, typename FIN>
 inline hipError_t launch_finish(const double* partial, int nb, SolverScalars* sc, const FIN& fin,
                                 hipStream_t s) {
-  hipLaunchKernelGGL((k_reduce_finish<NV, NS, FIN>), dim3(1), dim3(kBlock), 0, s, partial, nb, sc,
+  launch_kernel((k_reduce_finish<NV, NS, FIN>), dim3(1), dim3(kBlock), 0, s, partial, nb, sc,
                      fin);
   return hipGetLastError();
 }

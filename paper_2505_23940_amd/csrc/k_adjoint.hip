@@ -833,11 +833,11 @@ template <typename T>
 int launch_adj_body_loads(const IbGeo& B, const IbView<T>& ib, const double* st,
                           const double* stbar_out, const double* dF, const double* kc,
                           double* stbar_in, double* kcbar, SolverScalars* sc, hipStream_t s) {
-  hipLaunchKernelGGL((k_adj_body_loads<T>), dim3(1), dim3(kBlock), 0, s, B, ib, st, stbar_out, dF,
+  launch_kernel((k_adj_body_loads<T>), dim3(1), dim3(kBlock), 0, s, B, ib, st, stbar_out, dF,
                      kc, stbar_in, kcbar, sc);
   FVIB_HIP(hipGetLastError());
   const int n = B.W[0][0] * B.W[0][1] + B.W[1][0] * B.W[1][1];
-  hipLaunchKernelGGL((k_adj_fbar<T>), dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, B, st,
+  launch_kernel((k_adj_fbar<T>), dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, B, st,
                      (const SolverScalars*)sc, (T*)ib.f[0], (T*)ib.f[1]);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
@@ -848,10 +848,10 @@ int launch_adj_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const ub[3],
                    RedBuf red, SolverScalars* sc, double rtol, hipStream_t s) {
   const Tiling tl = make_tiling(G.n[0], G.n[1], G.n[2]);
   if (G.dim == 2)
-    hipLaunchKernelGGL((k_adj_rhs<T, 2>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, ub[0],
+    launch_kernel((k_adj_rhs<T, 2>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, ub[0],
                        ub[1], ub[2], y, red, sc);
   else
-    hipLaunchKernelGGL((k_adj_rhs<T, 3>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, ub[0],
+    launch_kernel((k_adj_rhs<T, 3>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, ub[0],
                        ub[1], ub[2], y, red, sc);
   FVIB_HIP(hipGetLastError());
   FVIB_HIP((launch_finish<2, 1>(red.partial, tl.nblocks, sc,
@@ -871,10 +871,10 @@ int launch_adj_ustar(const Geo<T>& G, const PGeo<double>& P, const T* const ub1[
                      hipStream_t s) {
   const ColTiling ct = make_col_tiling(G.n[0], G.n[1], G.n[2]);
   if (G.dim == 2)
-    hipLaunchKernelGGL((k_adj_ustar<T, 2>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct, ub1[0],
+    launch_kernel((k_adj_ustar<T, 2>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct, ub1[0],
                        ub1[1], ub1[2], mu, ib, usb[0], usb[1], usb[2], sc);
   else
-    hipLaunchKernelGGL((k_adj_ustar<T, 3>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct, ub1[0],
+    launch_kernel((k_adj_ustar<T, 3>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct, ub1[0],
                        ub1[1], ub1[2], mu, ib, usb[0], usb[1], usb[2], sc);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
@@ -884,7 +884,7 @@ template <typename T>
 int launch_adj_ubody(const Geo<T>& G, const PGeo<double>& P, const IbGeo& B, const T* const ub1[3],
                      const double* mu, const IbView<T>& ib, double* stbar,
                      const SolverScalars* sc, hipStream_t s) {
-  hipLaunchKernelGGL((k_adj_ubody<T>), dim3(1), dim3(kBlock), 0, s, G, P, B, ub1[0], ub1[1], mu, ib,
+  launch_kernel((k_adj_ubody<T>), dim3(1), dim3(kBlock), 0, s, G, P, B, ub1[0], ub1[1], mu, ib,
                      stbar, sc);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
@@ -900,12 +900,12 @@ int launch_adj_outflow(const Geo<T>& G, const Planes& PL, int mode, T* usb[3], T
   if (nb > kMaxRedBlocks) nb = kMaxRedBlocks;
   if (nb < 1) nb = 1;
   if (mode == 0) {
-    hipLaunchKernelGGL((k_adj_outflow_sum<T>), dim3(nb), dim3(kBlock), 0, s, G, PL, usb[0], usb[1],
+    launch_kernel((k_adj_outflow_sum<T>), dim3(nb), dim3(kBlock), 0, s, G, PL, usb[0], usb[1],
                        usb[2], red, sc);
     FVIB_HIP(hipGetLastError());
     FVIB_HIP((launch_finish<1, 1>(red.partial, nb, sc, FinAdjOutflow{PL.area_out}, s)));
   }
-  hipLaunchKernelGGL((k_adj_outflow_apply<T>), dim3(nb), dim3(kBlock), 0, s, G, PL, mode, usb[0],
+  launch_kernel((k_adj_outflow_apply<T>), dim3(nb), dim3(kBlock), 0, s, G, PL, mode, usb[0],
                      usb[1], usb[2], ubar[0], ubar[1], ubar[2], (const SolverScalars*)sc);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
@@ -937,10 +937,10 @@ static int launch_adj_momentum_t(const AdjCtx<T>& X, T* ubar[3], T* fbbar[3], hi
   int nb = ntx * nty * nzc;
   nb = (nb + kXcds - 1) / kXcds * kXcds;
   if (G.dim == 2)
-    hipLaunchKernelGGL((k_adj_momentum_lds<T, 2, UPW>), dim3(nb), dim3(kBlock), 0, s, X, ntx, nty,
+    launch_kernel((k_adj_momentum_lds<T, 2, UPW>), dim3(nb), dim3(kBlock), 0, s, X, ntx, nty,
                        nzc, ubar[0], ubar[1], ubar[2], fbbar[0], fbbar[1], fbbar[2]);
   else
-    hipLaunchKernelGGL((k_adj_momentum_lds<T, 3, UPW>), dim3(nb), dim3(kBlock), 0, s, X, ntx, nty,
+    launch_kernel((k_adj_momentum_lds<T, 3, UPW>), dim3(nb), dim3(kBlock), 0, s, X, ntx, nty,
                        nzc, ubar[0], ubar[1], ubar[2], fbbar[0], fbbar[1], fbbar[2]);
   FVIB_HIP(hipGetLastError());
   for (int c = 0; c < G.dim; ++c) {
@@ -950,12 +950,12 @@ static int launch_adj_momentum_t(const AdjCtx<T>& X, T* ubar[3], T* fbbar[3], hi
       if (a != c) count *= G.n[a];
     const dim3 gr(nblk(count)), bl(kBlock);
     if (G.dim == 2) {
-      if (c == 0) hipLaunchKernelGGL((k_adj_momentum_plane<0, 2, UPW, T>), gr, bl, 0, s, X, ubar[0]);
-      else hipLaunchKernelGGL((k_adj_momentum_plane<1, 2, UPW, T>), gr, bl, 0, s, X, ubar[1]);
+      if (c == 0) launch_kernel((k_adj_momentum_plane<0, 2, UPW, T>), gr, bl, 0, s, X, ubar[0]);
+      else launch_kernel((k_adj_momentum_plane<1, 2, UPW, T>), gr, bl, 0, s, X, ubar[1]);
     } else {
-      if (c == 0) hipLaunchKernelGGL((k_adj_momentum_plane<0, 3, UPW, T>), gr, bl, 0, s, X, ubar[0]);
-      else if (c == 1) hipLaunchKernelGGL((k_adj_momentum_plane<1, 3, UPW, T>), gr, bl, 0, s, X, ubar[1]);
-      else hipLaunchKernelGGL((k_adj_momentum_plane<2, 3, UPW, T>), gr, bl, 0, s, X, ubar[2]);
+      if (c == 0) launch_kernel((k_adj_momentum_plane<0, 3, UPW, T>), gr, bl, 0, s, X, ubar[0]);
+      else if (c == 1) launch_kernel((k_adj_momentum_plane<1, 3, UPW, T>), gr, bl, 0, s, X, ubar[1]);
+      else launch_kernel((k_adj_momentum_plane<2, 3, UPW, T>), gr, bl, 0, s, X, ubar[2]);
     }
     FVIB_HIP(hipGetLastError());
   }

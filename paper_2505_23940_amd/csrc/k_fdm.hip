@@ -166,10 +166,11 @@ k_axis_gemm(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A,
           const bool zero = (mm[0] == 0 && mm[1] == 0 && mm[2] == 0);
           val = zero ? V(0) : (V)((double)val / ls);
         }
+        // non-temporal: see the note on k_fft_axis' stores
         if (XFAST)
-          Y[base + m] = val;
+          __builtin_nontemporal_store(val, Y + base + m);
         else
-          Y[base + (int64_t)m * inner] = val;
+          __builtin_nontemporal_store(val, Y + base + (int64_t)m * inner);
       }
     }
   }
@@ -559,7 +560,9 @@ k_axis_lds(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A,
       }
       if constexpr (XFAST && !DIVOUT && sizeof(V) == 4) {
         const acc_t& c = acc[mt][tt];
-        *reinterpret_cast<float4*>(Y + base + 16 * tile + 4 * q) = make_float4(c[0], c[1], c[2], c[3]);
+        typedef __attribute__((ext_vector_type(4))) float f4_t;
+        __builtin_nontemporal_store(f4_t{c[0], c[1], c[2], c[3]},
+                                    reinterpret_cast<f4_t*>(Y + base + 16 * tile + 4 * q));
         continue;
       }
 #pragma unroll
@@ -567,10 +570,11 @@ k_axis_lds(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A,
         const int m = 16 * tile + Mfma<V>::row(lane, v);
         V val = acc[mt][tt][v];
         if (DIVOUT) val = divide(tt, m, val);
+        // non-temporal: see the note on k_fft_axis' stores
         if (XFAST)
-          Y[base + m] = val;
+          __builtin_nontemporal_store(val, Y + base + m);
         else
-          Y[base + (int64_t)m * inner] = val;
+          __builtin_nontemporal_store(val, Y + base + (int64_t)m * inner);
       }
     }
   }
@@ -666,7 +670,7 @@ int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, c
     const dim3 g((unsigned)((ncols + 16 * nt - 1) / (16 * nt)));
     const int mt = (K / 16 + 3) / 4;
 #define FVIB_AF(MT, NT)                                                                         \
-    hipLaunchKernelGGL((k_axis_lds<V, false, true, true, MT, NT>), g, dim3(kBlock), 0, s, in,   \
+    launch_kernel((k_axis_lds<V, false, true, true, MT, NT>), g, dim3(kBlock), 0, s, in,   \
                        out, Am, F.phi[a], K, inner, ncols, F.div, stop)
 #define FVIB_AFN(MT)                                                                            \
     if (nt == 1) FVIB_AF(MT, 1); else FVIB_AF(MT, 2);
@@ -686,7 +690,7 @@ int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, c
     const dim3 g((unsigned)((ncols + 16 * nt - 1) / (16 * nt)));
     const int mt = (K / 16 + 3) / 4;
 #define FVIB_AL(XF, DV, MT, NT)                                                                 \
-    hipLaunchKernelGGL((k_axis_lds<V, XF, DV, false, MT, NT>), g, dim3(kBlock), 0, s, in, out,  \
+    launch_kernel((k_axis_lds<V, XF, DV, false, MT, NT>), g, dim3(kBlock), 0, s, in, out,  \
                        Am, Am, K, inner, ncols, F.div, stop)
 #define FVIB_ALN(XF, DV, MT)                                                                    \
     switch (nt) {                                                                               \
@@ -722,10 +726,10 @@ int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, c
     const bool tail = K % (sizeof(V) == 4 ? 32 : 16) != 0;
 #define FVIB_AX(XF, DV, MT)                                                                     \
     if (tail)                                                                                   \
-      hipLaunchKernelGGL((k_axis_mfma<V, XF, DV, true, MT, NT>), g, dim3(kBlock), 0, s, in, out, \
+      launch_kernel((k_axis_mfma<V, XF, DV, true, MT, NT>), g, dim3(kBlock), 0, s, in, out, \
                          Am, K, inner, ncols, F.div, stop);                                     \
     else                                                                                        \
-      hipLaunchKernelGGL((k_axis_mfma<V, XF, DV, false, MT, NT>), g, dim3(kBlock), 0, s, in,    \
+      launch_kernel((k_axis_mfma<V, XF, DV, false, MT, NT>), g, dim3(kBlock), 0, s, in,    \
                          out, Am, K, inner, ncols, F.div, stop)
 #define FVIB_AXM(XF, DV)                                                                        \
     switch (mt) {                                                                               \
@@ -747,14 +751,14 @@ int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, c
   dim3 grid((K + BM - 1) / BM, (unsigned)((ncols + BN - 1) / BN));
   if (inner == 1) {
     if (div)
-      hipLaunchKernelGGL((k_axis_gemm<V, true, true>), grid, dim3(kBlock), 0, s, in, out, Am, K, inner, ncols, F.div, stop);
+      launch_kernel((k_axis_gemm<V, true, true>), grid, dim3(kBlock), 0, s, in, out, Am, K, inner, ncols, F.div, stop);
     else
-      hipLaunchKernelGGL((k_axis_gemm<V, true, false>), grid, dim3(kBlock), 0, s, in, out, Am, K, inner, ncols, F.div, stop);
+      launch_kernel((k_axis_gemm<V, true, false>), grid, dim3(kBlock), 0, s, in, out, Am, K, inner, ncols, F.div, stop);
   } else {
     if (div)
-      hipLaunchKernelGGL((k_axis_gemm<V, false, true>), grid, dim3(kBlock), 0, s, in, out, Am, K, inner, ncols, F.div, stop);
+      launch_kernel((k_axis_gemm<V, false, true>), grid, dim3(kBlock), 0, s, in, out, Am, K, inner, ncols, F.div, stop);
     else
-      hipLaunchKernelGGL((k_axis_gemm<V, false, false>), grid, dim3(kBlock), 0, s, in, out, Am, K, inner, ncols, F.div, stop);
+      launch_kernel((k_axis_gemm<V, false, false>), grid, dim3(kBlock), 0, s, in, out, Am, K, inner, ncols, F.div, stop);
   }
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
@@ -763,14 +767,14 @@ int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, c
 template <typename V>
 int launch_add_correction(int64_t n, double* p, const V* d, const int* stop, hipStream_t s) {
   int nb = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 8 * kMaxRedBlocks);
-  hipLaunchKernelGGL((k_add_correction<V>), dim3(nb), dim3(kBlock), 0, s, n, p, d, stop);
+  launch_kernel((k_add_correction<V>), dim3(nb), dim3(kBlock), 0, s, n, p, d, stop);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
 
 int launch_gauge(int64_t n, double* p, const SolverScalars* sc, hipStream_t s) {
   int nb = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 8 * kMaxRedBlocks);
-  hipLaunchKernelGGL(k_gauge, dim3(nb), dim3(kBlock), 0, s, n, p, sc, 1.0 / (double)n);
+  launch_kernel(k_gauge, dim3(nb), dim3(kBlock), 0, s, n, p, sc, 1.0 / (double)n);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }

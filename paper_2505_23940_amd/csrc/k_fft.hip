@@ -10,7 +10,10 @@
 // packed Hermitian spectrum Y1 + i Y2 and uses IDFT(Z) = conj(FFT(conj Z)).
 // With the division by the eigenvalue sum (last axis), the forward
 // transform, the division and the inverse run in one launch.  The work is
-// memory bound: every line crosses HBM once per launch.
+// memory bound: every line crosses HBM once per launch.  Outputs are
+// stored non-temporally: a pass writes about as much as the L2s hold, and
+// lines left dirty there would be written back at the kernel's end, idling
+// the next launch for several microseconds.
 #include <math.h>
 
 #include <vector>
@@ -417,7 +420,8 @@ k_fft_axis(const V* __restrict__ X, V* __restrict__ Y, int inner, int64_t ncols,
         for (int h = 0; h < LV; ++h) {
           const int off = IL ? e * VW : (2 * (e / KV) + h) * N + (e % KV) * VW;
           if (gvalid(e, h))
-            *reinterpret_cast<vec_t*>(Y + gaddr(e, h)) = *reinterpret_cast<const vec_t*>(rows + off);
+            __builtin_nontemporal_store(*reinterpret_cast<const vec_t*>(rows + off),
+                                        reinterpret_cast<vec_t*>(Y + gaddr(e, h)));
         }
       }
     }
@@ -482,7 +486,7 @@ k_fft_axis(const V* __restrict__ X, V* __restrict__ Y, int inner, int64_t ncols,
         vec_t v = *reinterpret_cast<const vec_t*>(fr + e * VW);
 #pragma unroll
         for (int j = 1; j < VW; j += 2) v[j] = -v[j];
-        *reinterpret_cast<vec_t*>(Y + gaddr(e, 0)) = v;
+        __builtin_nontemporal_store(v, reinterpret_cast<vec_t*>(Y + gaddr(e, 0)));
       } else {
         const int p = e / KV, kv = e - p * KV;
         const V* s = fr + 2 * (p * N + kv * VW);
@@ -506,8 +510,8 @@ k_fft_axis(const V* __restrict__ X, V* __restrict__ Y, int inner, int64_t ncols,
           if (gvalid(e, 0)) *reinterpret_cast<dvec_t*>(pacc + gaddr(e, 0)) = q1;
           if (gvalid(e, 1)) *reinterpret_cast<dvec_t*>(pacc + gaddr(e, 1)) = q2;
         } else {
-          if (gvalid(e, 0)) *reinterpret_cast<vec_t*>(Y + gaddr(e, 0)) = x1;
-          if (gvalid(e, 1)) *reinterpret_cast<vec_t*>(Y + gaddr(e, 1)) = x2;
+          if (gvalid(e, 0)) __builtin_nontemporal_store(x1, reinterpret_cast<vec_t*>(Y + gaddr(e, 0)));
+          if (gvalid(e, 1)) __builtin_nontemporal_store(x2, reinterpret_cast<vec_t*>(Y + gaddr(e, 1)));
         }
       }
     }
@@ -549,7 +553,7 @@ int launch_fft_axis(const FdmPlan<V>& F, int a, int mode, const V* in, V* out, c
   const dim3 g((unsigned)((ncols + LPB - 1) / LPB));
   bool done = false;
 #define FVIB_FFT(NN, XF, M, AC)                                                                 \
-  hipLaunchKernelGGL((k_fft_axis<V, NN, XF, M, AC>), g, dim3(kBlock), 0, s, in, out, inner,     \
+  launch_kernel((k_fft_axis<V, NN, XF, M, AC>), g, dim3(kBlock), 0, s, in, out, inner,     \
                      ncols, F.fft[a], F.tw[a], F.div, stop, acc)
 #define FVIB_FFT_N(NN)                                                                          \
   if (!done && N == NN) {                                                                       \

@@ -202,9 +202,9 @@ int launch_ib_classify(const IbGeo& B, const double* body, T* us0, T* us1, Solve
                        hipStream_t s) {
   const int n = B.W[0][0] * B.W[0][1] + B.W[1][0] * B.W[1][1];
   const int nb = (n + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_ib_solid, dim3(nb), dim3(kBlock), 0, s, B, body, sc);
+  launch_kernel(k_ib_solid, dim3(nb), dim3(kBlock), 0, s, B, body, sc);
   FVIB_HIP(hipGetLastError());
-  hipLaunchKernelGGL((k_ib_targets<T>), dim3(nb), dim3(kBlock), 0, s, B, body, us0, us1);
+  launch_kernel((k_ib_targets<T>), dim3(nb), dim3(kBlock), 0, s, B, body, us0, us1);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
@@ -212,7 +212,7 @@ int launch_ib_classify(const IbGeo& B, const double* body, T* us0, T* us1, Solve
 template <typename T>
 int launch_loads_body(const IbGeo& B, const IbView<T>& ib, const double* body_in,
                       double* body_out, const double* kc, SolverScalars* sc, hipStream_t s) {
-  hipLaunchKernelGGL((k_loads_body<T>), dim3(1), dim3(kBlock), 0, s, B, ib, body_in, body_out,
+  launch_kernel((k_loads_body<T>), dim3(1), dim3(kBlock), 0, s, B, ib, body_in, body_out,
                      kc, sc);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
@@ -220,7 +220,7 @@ int launch_loads_body(const IbGeo& B, const IbView<T>& ib, const double* body_in
 
 int launch_copy_info(const SolverScalars* sc, fvib_step_info* info, int cg_iters, int ir_iters,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_copy_info, dim3(1), dim3(64), 0, s, sc, info, cg_iters, ir_iters);
+  launch_kernel(k_copy_info, dim3(1), dim3(64), 0, s, sc, info, cg_iters, ir_iters);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }

@@ -64,7 +64,7 @@ int launch_wall_shear(int nx, int ny, int nz, const T* u, T* ubar, double wlo, d
                       double* J, double* partial, hipStream_t s) {
   const int64_t plane = (int64_t)nx * nz;
   int nb = (int)std::min<int64_t>((plane + kBlock - 1) / kBlock, kMaxRedBlocks);
-  hipLaunchKernelGGL((k_wall_shear<T>), dim3(nb), dim3(kBlock), 0, s, nx, ny, nz, u, ubar, wlo,
+  launch_kernel((k_wall_shear<T>), dim3(nb), dim3(kBlock), 0, s, nx, ny, nz, u, ubar, wlo,
                      whi, partial);
   FVIB_HIP(hipGetLastError());
   FVIB_HIP((launch_finish<2, 2>(partial, nb, nullptr,
@@ -74,7 +74,7 @@ int launch_wall_shear(int nx, int ny, int nz, const T* u, T* ubar, double wlo, d
 
 int launch_rms_lift(const double* Fh, int S, int stride, int off, double g, double* J,
                     double* dFh, hipStream_t s) {
-  hipLaunchKernelGGL(k_rms_lift, dim3(1), dim3(kBlock), 0, s, Fh, S, stride, off, g, J, dFh);
+  launch_kernel(k_rms_lift, dim3(1), dim3(kBlock), 0, s, Fh, S, stride, off, g, J, dFh);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }

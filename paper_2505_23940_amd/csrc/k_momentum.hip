@@ -350,7 +350,7 @@ int launch_predictor(const Geo<T>& G, const T* const u[3], const T* const fb[3],
   nb = (nb + kXcds - 1) / kXcds * kXcds;
   dim3 grid(nb), block(kBlock);
 #define FVIB_PRED(D, M)                                                                        \
-  hipLaunchKernelGGL((k_predictor<T, D, M>), grid, block, 0, s, G, ntx, nty, nzc, u[0], u[1], \
+  launch_kernel((k_predictor<T, D, M>), grid, block, 0, s, G, ntx, nty, nzc, u[0], u[1], \
                      u[2], fb[0], fb[1], fb[2], out[0], out[1], out[2], ib)
   if (G.dim == 2) {
     if (mode == 0) FVIB_PRED(2, 0); else FVIB_PRED(2, 1);
@@ -371,12 +371,12 @@ int launch_boundary(const Geo<T>& G, const Planes& PL, const T* const un[3], T* 
   int nb = (int)((total + kBlock - 1) / kBlock);
   if (nb > kMaxRedBlocks) nb = kMaxRedBlocks;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL((k_boundary_faces<T>), dim3(nb), dim3(kBlock), 0, s, G, PL, un[0], un[1],
+  launch_kernel((k_boundary_faces<T>), dim3(nb), dim3(kBlock), 0, s, G, PL, un[0], un[1],
                      un[2], us[0], us[1], us[2], red, sc);
   FVIB_HIP(hipGetLastError());
   if (PL.any_outflow) {
     FVIB_HIP((launch_finish<1, 1>(red.partial, nb, sc, FinOutflow{PL.area_out}, s)));
-    hipLaunchKernelGGL((k_outflow_correct<T>), dim3(nb), dim3(kBlock), 0, s, G, PL, us[0], us[1],
+    launch_kernel((k_outflow_correct<T>), dim3(nb), dim3(kBlock), 0, s, G, PL, us[0], us[1],
                        us[2], (const SolverScalars*)sc);
     FVIB_HIP(hipGetLastError());
   }

@@ -467,10 +467,10 @@ int launch_ppe_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
                    hipStream_t s) {
   const Tiling tl = red_tiling(G.n);
   if (G.dim == 2)
-    hipLaunchKernelGGL((k_ppe_rhs<T, 2>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, us[0],
+    launch_kernel((k_ppe_rhs<T, 2>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, us[0],
                        us[1], us[2], ib, b, red, sc);
   else
-    hipLaunchKernelGGL((k_ppe_rhs<T, 3>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, us[0],
+    launch_kernel((k_ppe_rhs<T, 3>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, us[0],
                        us[1], us[2], ib, b, red, sc);
   FVIB_HIP(hipGetLastError());
   FVIB_HIP((launch_finish<1, 1>(red.partial, tl.nblocks, sc, FinMeanB{P.inv_ncell}, s)));
@@ -483,7 +483,7 @@ int launch_residual(const PGeo<double>& P, int mode, const double* b, const doub
   const ColTiling ct = make_col_tiling(P.n[0], P.n[1], P.n[2]);
   dim3 g(ct.nblocks), bl(kBlock);
 #define FVIB_RES(D, M)                                                                        \
-  hipLaunchKernelGGL((k_residual<D, M>), g, bl, 0, s, P, ct, b, x, r64, r32, d32, red, sc,      \
+  launch_kernel((k_residual<D, M>), g, bl, 0, s, P, ct, b, x, r64, r32, d32, red, sc,      \
                      first);                                                                    \
   FVIB_HIP(hipGetLastError());                                                                  \
   FVIB_HIP((launch_finish<3, 2>(red.partial, ct.nblocks, sc,                                    \
@@ -516,22 +516,22 @@ int launch_cg_iter(const PGeo<V>& P, int mode, const V* r, const V* pold, V* pne
   dim3 g(tl.nblocks), bl(kBlock);
   if (ev) FVIB_HIP(hipEventRecord(ev[0], s));
   if (P.dim == 2)
-    hipLaunchKernelGGL((k_cg_dir<V, 2>), g, bl, 0, s, P, tl, r, pold, pnew, red, sc);
+    launch_kernel((k_cg_dir<V, 2>), g, bl, 0, s, P, tl, r, pold, pnew, red, sc);
   else
-    hipLaunchKernelGGL((k_cg_dir<V, 3>), g, bl, 0, s, P, tl, r, pold, pnew, red, sc);
+    launch_kernel((k_cg_dir<V, 3>), g, bl, 0, s, P, tl, r, pold, pnew, red, sc);
   FVIB_HIP(hipGetLastError());
   FVIB_HIP((launch_finish<2, 2>(red.partial, tl.nblocks, sc, FinCgDir{}, s)));
   if (ev) FVIB_HIP(hipEventRecord(ev[1], s));
   if (P.dim == 2) {
     if (mode == 0)
-      hipLaunchKernelGGL((k_cg_update<V, 2, 0>), g, bl, 0, s, P, tl, (const V*)pnew, x, rw, red, sc, tol, maxit);
+      launch_kernel((k_cg_update<V, 2, 0>), g, bl, 0, s, P, tl, (const V*)pnew, x, rw, red, sc, tol, maxit);
     else
-      hipLaunchKernelGGL((k_cg_update<V, 2, 1>), g, bl, 0, s, P, tl, (const V*)pnew, x, rw, red, sc, tol, maxit);
+      launch_kernel((k_cg_update<V, 2, 1>), g, bl, 0, s, P, tl, (const V*)pnew, x, rw, red, sc, tol, maxit);
   } else {
     if (mode == 0)
-      hipLaunchKernelGGL((k_cg_update<V, 3, 0>), g, bl, 0, s, P, tl, (const V*)pnew, x, rw, red, sc, tol, maxit);
+      launch_kernel((k_cg_update<V, 3, 0>), g, bl, 0, s, P, tl, (const V*)pnew, x, rw, red, sc, tol, maxit);
     else
-      hipLaunchKernelGGL((k_cg_update<V, 3, 1>), g, bl, 0, s, P, tl, (const V*)pnew, x, rw, red, sc, tol, maxit);
+      launch_kernel((k_cg_update<V, 3, 1>), g, bl, 0, s, P, tl, (const V*)pnew, x, rw, red, sc, tol, maxit);
   }
   FVIB_HIP(hipGetLastError());
   if (mode == 0)
@@ -548,7 +548,7 @@ int launch_ir_correct(int64_t n, double* p, const float* d, const SolverScalars*
                       hipStream_t s) {
   int nb = (int)((n + kBlock - 1) / kBlock);
   if (nb > 4 * kMaxRedBlocks) nb = 4 * kMaxRedBlocks;
-  hipLaunchKernelGGL(k_ir_correct, dim3(nb), dim3(kBlock), 0, s, n, p, d, sc, 1.0 / (double)n);
+  launch_kernel(k_ir_correct, dim3(nb), dim3(kBlock), 0, s, n, p, d, sc, 1.0 / (double)n);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
@@ -558,10 +558,10 @@ int launch_project(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
                    T* out[3], RedBuf red, SolverScalars* sc, hipStream_t s) {
   const Tiling tl = red_tiling(G.n);
   if (G.dim == 2)
-    hipLaunchKernelGGL((k_project<T, 2>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, us[0],
+    launch_kernel((k_project<T, 2>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, us[0],
                        us[1], us[2], p, out[0], out[1], out[2], red, sc);
   else
-    hipLaunchKernelGGL((k_project<T, 3>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, us[0],
+    launch_kernel((k_project<T, 3>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, us[0],
                        us[1], us[2], p, out[0], out[1], out[2], red, sc);
   FVIB_HIP(hipGetLastError());
   FVIB_HIP((launch_finish<1, 0>(red.partial, tl.nblocks, sc, FinDivMax{}, s)));
@@ -570,7 +570,7 @@ int launch_project(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
 
 int launch_apply_A(const PGeo<double>& P, const double* x, double* y, hipStream_t s) {
   const Tiling tl = red_tiling(P.n);
-  hipLaunchKernelGGL(k_apply_A, dim3(tl.nblocks), dim3(kBlock), 0, s, P, tl, x, y);
+  launch_kernel(k_apply_A, dim3(tl.nblocks), dim3(kBlock), 0, s, P, tl, x, y);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
