@@ -580,6 +580,108 @@ k_axis_lds(const V* __restrict__ X, V* __restrict__ Y, const V* __restrict__ A,
   }
 }
 
+// Strided axis, float, K = 16 k' <= 128 (no division): the operator stays
+// in registers.  Each wave owns row tiles w, w + 4 (MT of them) of the
+// K x K operator and loads its rows once from L2 (lane (r, q) holds
+// A[16 tile + r][16 g + 4 q + s] for every group g and s < 4, 16-byte loads);
+// the block's lines (NT tiles of 16, one outer index) are fetched from HBM
+// in one go, transposed into LDS line-major, and contracted with the same
+// quad order as k_axis_lds (lane group q takes k = 16 g + 4 q + s in the
+// s-th of four consecutive MFMAs).  One HBM latency per block instead of one
+// per contraction chunk, and no operator traffic through LDS.
+template <int K, int NT>
+__global__ void __launch_bounds__(kBlock)
+k_axis_reg(const float* __restrict__ X, float* __restrict__ Y, const float* __restrict__ A,
+           int inner, int64_t ncols, const int* stop) {
+  if (stop && *stop) return;
+  static_assert(K % 16 == 0 && K <= 128, "operator rows must fit the registers");
+  constexpr int NC = 16 * NT;                    // lines per block
+  constexpr int NTR = K / 16;                    // row tiles of the operator
+  constexpr int MT = (NTR + 3) / 4;              // row tiles per wave
+  constexpr int G = K / 16;                      // contraction groups
+  constexpr int LDK = K + 4;                     // LDS line stride (floats)
+  constexpr int CV = NC / 4;                     // float4 per index row of the tile
+  constexpr int XV = (K * CV + kBlock - 1) / kBlock;
+  typedef __attribute__((ext_vector_type(4))) float f4_t;
+  typedef typename Mfma<float>::acc_t acc_t;
+  __shared__ __attribute__((aligned(16))) float Xs[NC * LDK];
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int q = lane >> 4, r = lane & 15;
+  const int64_t n0 = (int64_t)blockIdx.x * NC;
+  const int64_t o0 = n0 / inner;
+  const int64_t i0 = n0 - o0 * inner;
+  const float* xb = X + o0 * (int64_t)K * inner + i0;
+  // the block's lines: index row k holds NC consecutive floats
+  f4_t rx[XV];
+#pragma unroll
+  for (int u = 0; u < XV; ++u) {
+    const int e = t + u * kBlock;
+    if ((K * CV) % kBlock == 0 || e < K * CV) {
+      const int k = e / CV, c = e - k * CV;
+      rx[u] = *reinterpret_cast<const f4_t*>(xb + (int64_t)k * inner + 4 * c);
+    }
+  }
+  // this wave's operator rows
+  f4_t ra[MT][G];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int tile = w + 4 * mt;
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      ra[mt][g] = tile < NTR ? *reinterpret_cast<const f4_t*>(A + (16 * tile + r) * K + 16 * g + 4 * q)
+                             : f4_t{0.f, 0.f, 0.f, 0.f};
+  }
+#pragma unroll
+  for (int u = 0; u < XV; ++u) {
+    const int e = t + u * kBlock;
+    if ((K * CV) % kBlock == 0 || e < K * CV) {
+      const int k = e / CV, c = e - k * CV;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Xs[(4 * c + j) * LDK + k] = rx[u][j];
+    }
+  }
+  __syncthreads();
+  acc_t acc[MT][NT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) acc[mt][tt] = acc_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    f4_t xa[NT];
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt)
+      xa[tt] = *reinterpret_cast<const f4_t*>(Xs + (16 * tt + r) * LDK + 16 * g + 4 * q);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      if (w + 4 * mt >= NTR) continue;           // wave-uniform
+#pragma unroll
+      for (int sidx = 0; sidx < 4; ++sidx)
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt)
+          acc[mt][tt] = Mfma<float>::op(ra[mt][g][sidx], xa[tt][sidx], acc[mt][tt]);
+    }
+  }
+  float* yb = Y + o0 * (int64_t)K * inner + i0;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int tile = w + 4 * mt;
+    if (tile >= NTR) continue;
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = 16 * tile + Mfma<float>::row(lane, v);
+        __builtin_nontemporal_store(acc[mt][tt][v], yb + (int64_t)m * inner + 16 * tt + r);
+      }
+  }
+}
+
+// Operator sizes with a k_axis_reg kernel.
+#define FVIB_REG_SIZES(X) X(32) X(64) X(96) X(128)
+
 // p += d (refinement correction, double accumulator)
 template <typename V>
 __global__ void __launch_bounds__(kBlock)
@@ -664,6 +766,25 @@ int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, c
   const int64_t ncols = outer * inner;
   const V* Am = fwd ? F.phiT[a] : F.phi[a];
   const bool div = fwd && a == F.dim - 1;
+  if constexpr (sizeof(V) == 4) {
+    // strided float axis without division: operator in registers
+    if (!div && inner != 1 && inner % 32 == 0) {
+      bool done = false;
+      const dim3 g((unsigned)(ncols / 32));
+#define FVIB_REG(KK)                                                                            \
+      if (!done && K == KK) {                                                                   \
+        done = true;                                                                            \
+        launch_kernel((k_axis_reg<KK, 2>), g, dim3(kBlock), 0, s, (const float*)in,             \
+                      (float*)out, (const float*)Am, inner, ncols, stop);                       \
+      }
+      FVIB_REG_SIZES(FVIB_REG)
+#undef FVIB_REG
+      if (done) {
+        FVIB_HIP(hipGetLastError());
+        return FVIB_OK;
+      }
+    }
+  }
   const int nt = (K % 32 == 0 && K <= 256) ? lds_line_tiles(ncols, inner) : 0;
   if (nt > 0 && div && fused && inner != 1 && nt <= 2) {
     // last forward axis, division and first inverse axis in one launch
