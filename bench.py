@@ -58,7 +58,7 @@ def kernel_cost(d: int, s: int, mixed: bool, n: tuple):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="channel")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])

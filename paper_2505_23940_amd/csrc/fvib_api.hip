@@ -504,8 +504,12 @@ static int read_scalars(Grid* g) {
 // if a host check finds the refinement stalled (the criterion fell by less
 // than a factor 10 since the previous check) before it converged, p
 // restarts from zero.
+// p_in: the initial guess when it is not already in p (nullptr: p); p
+// receives the solution either way.
 static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* last,
-                         int* cg_total, int* ir_total, bool gauge = true, bool warm = false) {
+                         int* cg_total, int* ir_total, bool gauge = true, bool warm = false,
+                         const double* p_in = nullptr) {
+  if (!p_in) p_in = p;
   int rc;
   *cg_total = 0;
   *ir_total = 0;
@@ -529,10 +533,12 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
     const bool d64 = g->prec == FVIB_PREC_FP64;
     const int* stop = &g->sc->outer_done;
     int launched = 0;              // sweeps launched since the last restart
+    // the first residual and the first correction read the guess in p_in;
+    // the correction writes p (carrying p_in over if the sweep is skipped)
     auto residual = [&](int first) {
       return timed(g, FVIB_K_RESIDUAL, [&] {
-        return launch_residual(g->P64, d64 ? 3 : 2, b, p, g->r64, g->r32, nullptr, g->red(),
-                               g->sc, tol, 0.5, g->stream, first);
+        return launch_residual(g->P64, d64 ? 3 : 2, b, first ? p_in : p, g->r64, g->r32,
+                               nullptr, g->red(), g->sc, tol, 0.5, g->stream, first);
       });
     };
     auto sweep = [&]() -> int {
@@ -544,6 +550,7 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
       const int np = 2 * g->dim;
       int pass = 0, buf = 0;
       bool corrected = false;
+      const double* src = launched == 0 ? p_in : p;    // iterate the correction adds to
       while (pass < np) {
         const bool fwd = pass < g->dim;
         const int a = fwd ? pass : np - 1 - pass;
@@ -565,13 +572,13 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
             double* outp = (buf ? g->pA64 : g->pB64);
             if (ends) outp = g->d64;
             return launch_fdm_axis<double>(g->F64, a, fwd, in, outp, stop, g->stream,
-                                           can_fuse ? &fused : nullptr, acc, &corrected);
+                                           can_fuse ? &fused : nullptr, acc, &corrected, src);
           }
           const float* in = (pass == 0) ? g->r32 : (buf ? g->pB32 : g->pA32);
           float* outp = (buf ? g->pA32 : g->pB32);
           if (ends) outp = g->d32;
           return launch_fdm_axis<float>(g->F32, a, fwd, in, outp, stop, g->stream,
-                                        can_fuse ? &fused : nullptr, acc, &corrected);
+                                        can_fuse ? &fused : nullptr, acc, &corrected, src);
         });
         if (r2) return r2;
         pass += fused ? 2 : 1;
@@ -579,8 +586,8 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
       }
       if (!corrected) {
         int r2 = timed(g, FVIB_K_IR_CORRECT, [&] {
-          return d64 ? launch_add_correction<double>(g->ncell, p, g->d64, stop, g->stream)
-                     : launch_add_correction<float>(g->ncell, p, g->d32, stop, g->stream);
+          return d64 ? launch_add_correction<double>(g->ncell, p, src, g->d64, stop, g->stream)
+                     : launch_add_correction<float>(g->ncell, p, src, g->d32, stop, g->stream);
         });
         if (r2) return r2;
       }
@@ -602,6 +609,7 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
         // full budget
         warm = false;
         launched = 0;
+        p_in = p;
         g->timer.restart_solve();
         FVIB_HIP(hipMemsetAsync(p, 0, g->ncell * sizeof(double), g->stream));
         if ((rc = residual(1))) return rc;
@@ -629,6 +637,9 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
     *ir_total = sweeps;
     return FVIB_OK;
   }
+  if (p_in != p)
+    FVIB_HIP(hipMemcpyAsync(p, p_in, g->ncell * sizeof(double), hipMemcpyDeviceToDevice,
+                            g->stream));
   if (g->prec == FVIB_PREC_FP64) {
     rc = timed(g, FVIB_K_RESIDUAL, [&] {
       return launch_residual(g->P64, 0, b, p, g->r64, nullptr, nullptr, g->red(), g->sc, tol,
@@ -755,12 +766,11 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
                                   g->stream);
        })))
     return rc;
-  if (out->p != in->p)
-    FVIB_HIP(hipMemcpyAsync(out->p, in->p, g->ncell * sizeof(double), hipMemcpyDeviceToDevice,
-                            g->stream));
   int cg = 0, ir = 0;
   int last = g->last_iters;
-  if ((rc = poisson_solve(g, g->b, out->p, g->d.poisson_tol, &last, &cg, &ir))) return rc;
+  if ((rc = poisson_solve(g, g->b, out->p, g->d.poisson_tol, &last, &cg, &ir, true, false,
+                          in->p)))
+    return rc;
   g->last_iters = last;
   if (g->defer && g->sch->status == FVIB_ENOCONV)
     return fail(g, FVIB_ENOCONV,
@@ -827,13 +837,10 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
                                       bi->kc, g->sc, g->stream);
     });
     if (rc) return rc;
-  } else if (bi->body) {
-    if (bo->body)
-      FVIB_HIP(hipMemcpyAsync(bi->body, bo->body, 6 * sizeof(double), hipMemcpyDeviceToDevice,
-                              g->stream));
-    else
-      FVIB_HIP(hipMemsetAsync(bi->body, 0, 6 * sizeof(double), g->stream));
   }
+  // without a body the adjoint body state passes through unchanged (copied
+  // at the end of the step, with the step record)
+  double* body_pass = (!g->has_body && bi->body) ? bi->body : nullptr;
   // projection^T: A mu = G^T ubar^{n+1}
   // relative max-norm target of the adjoint solve, set on the device from
   // the right-hand side (no host round trip): well inside the gradient
@@ -881,7 +888,7 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
        })))
     return rc;
   fvib_step_info* dst = info ? info : g->info_dev;
-  if ((rc = launch_copy_info(g->sc, dst, cg, ir, g->stream))) return rc;
+  if ((rc = launch_copy_info(g->sc, dst, cg, ir, g->stream, bo->body, body_pass))) return rc;
   if (g->defer) {                // status only in the info record
     g->err.clear();
     return FVIB_OK;

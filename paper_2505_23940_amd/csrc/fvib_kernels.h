@@ -58,11 +58,12 @@ struct FdmPlan {
 FftAxis fft_plan(int n, double h);
 
 // k_fft.hip: mode 0 forward, 1 inverse, 2 forward + division + inverse.
-// acc (nullable, contiguous axis, mode 1): add the result to acc instead
-// of storing it in out.
+// acc (nullable, contiguous axis, mode 1): store accin + result in acc
+// instead of the result in out (accin may equal acc; a skipped launch still
+// copies accin into acc when they differ).
 template <typename V>
 int launch_fft_axis(const FdmPlan<V>& F, int a, int mode, const V* in, V* out, const int* stop,
-                    hipStream_t s, double* acc = nullptr);
+                    hipStream_t s, double* acc = nullptr, const double* accin = nullptr);
 template <typename V>
 bool fft_usable(const FdmPlan<V>& F, int a);
 
@@ -105,7 +106,7 @@ template <typename T>
 int launch_loads_body(const IbGeo& B, const IbView<T>& ib, const double* body_in,
                       double* body_out, const double* kc, SolverScalars* sc, hipStream_t s);
 int launch_copy_info(const SolverScalars* sc, fvib_step_info* info, int cg_iters, int ir_iters,
-                     hipStream_t s);
+                     hipStream_t s, const double* body_src = nullptr, double* body_dst = nullptr);
 
 // k_adjoint.hip
 template <typename T>
@@ -141,14 +142,17 @@ bool fdm_fuses_last_axis(const FdmPlan<V>& F);
 // fused (nullable): on the last forward axis, ask for the first inverse
 // contraction of the same axis to run in the same launch; *fused tells
 // whether it did (out then holds the inverse-transformed values).
-// acc (nullable): on an inverse axis, ask for the result to be added to the
-// double array acc instead of stored in out; *accd tells whether it was.
+// acc (nullable): on an inverse axis, ask for accin + result to be stored
+// in the double array acc instead of the result in out (accin nullable:
+// acc itself); *accd tells whether it was.
 template <typename V>
 int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, const int* stop,
                     hipStream_t s, bool* fused = nullptr, double* acc = nullptr,
-                    bool* accd = nullptr);
+                    bool* accd = nullptr, const double* accin = nullptr);
+// p = pin + d (pin may equal p; with the stop flag set, p = pin)
 template <typename V>
-int launch_add_correction(int64_t n, double* p, const V* d, const int* stop, hipStream_t s);
+int launch_add_correction(int64_t n, double* p, const double* pin, const V* d, const int* stop,
+                          hipStream_t s);
 int launch_gauge(int64_t n, double* p, const SolverScalars* sc, hipStream_t s);
 void axis_eigen(const std::vector<double>& f, bool periodic, std::vector<double>& phi,
                 std::vector<double>& lam);

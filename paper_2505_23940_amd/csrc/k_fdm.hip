@@ -682,14 +682,17 @@ k_axis_reg(const float* __restrict__ X, float* __restrict__ Y, const float* __re
 // Operator sizes with a k_axis_reg kernel.
 #define FVIB_REG_SIZES(X) X(32) X(64) X(96) X(128)
 
-// p += d (refinement correction, double accumulator)
+// p = pin + d (refinement correction, double accumulator; pin == p in
+// place).  A skipped sweep still carries pin over into p.
 template <typename V>
 __global__ void __launch_bounds__(kBlock)
-k_add_correction(int64_t n, double* __restrict__ p, const V* __restrict__ d, const int* stop) {
-  if (stop && *stop) return;
+k_add_correction(int64_t n, double* p, const double* pin, const V* __restrict__ d,
+                 const int* stop) {
+  const bool skip = stop && *stop;
+  if (skip && pin == p) return;
   for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < n;
        c += (int64_t)gridDim.x * kBlock)
-    p[c] += (double)d[c];
+    p[c] = skip ? pin[c] : pin[c] + (double)d[c];
 }
 
 // p -= sum(p) / n with the sum measured by the last residual sweep
@@ -742,14 +745,14 @@ bool fdm_fuses_last_axis(const FdmPlan<V>& F) {
 
 template <typename V>
 int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, const int* stop,
-                    hipStream_t s, bool* fused, double* acc, bool* accd) {
+                    hipStream_t s, bool* fused, double* acc, bool* accd, const double* accin) {
   if (fused) *fused = false;
   if (accd) *accd = false;
   if (fft_usable(F, a)) {
     const bool last = fwd && a == F.dim - 1;
     if (!fwd && acc && accd && a == 0) {
       *accd = true;
-      return launch_fft_axis<V>(F, a, 1, in, out, stop, s, acc);
+      return launch_fft_axis<V>(F, a, 1, in, out, stop, s, acc, accin ? accin : acc);
     }
     if (!last) return launch_fft_axis<V>(F, a, fwd ? 0 : 1, in, out, stop, s);
     if (fused) {
@@ -886,9 +889,10 @@ int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, c
 }
 
 template <typename V>
-int launch_add_correction(int64_t n, double* p, const V* d, const int* stop, hipStream_t s) {
+int launch_add_correction(int64_t n, double* p, const double* pin, const V* d, const int* stop,
+                          hipStream_t s) {
   int nb = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 8 * kMaxRedBlocks);
-  launch_kernel((k_add_correction<V>), dim3(nb), dim3(kBlock), 0, s, n, p, d, stop);
+  launch_kernel((k_add_correction<V>), dim3(nb), dim3(kBlock), 0, s, n, p, pin, d, stop);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
@@ -903,12 +907,15 @@ int launch_gauge(int64_t n, double* p, const SolverScalars* sc, hipStream_t s) {
 template bool fdm_fuses_last_axis<float>(const FdmPlan<float>&);
 template bool fdm_fuses_last_axis<double>(const FdmPlan<double>&);
 template int launch_fdm_axis<float>(const FdmPlan<float>&, int, bool, const float*, float*,
-                                    const int*, hipStream_t, bool*, double*, bool*);
+                                    const int*, hipStream_t, bool*, double*, bool*,
+                                    const double*);
 template int launch_fdm_axis<double>(const FdmPlan<double>&, int, bool, const double*, double*,
-                                     const int*, hipStream_t, bool*, double*, bool*);
-template int launch_add_correction<float>(int64_t, double*, const float*, const int*, hipStream_t);
-template int launch_add_correction<double>(int64_t, double*, const double*, const int*,
-                                           hipStream_t);
+                                     const int*, hipStream_t, bool*, double*, bool*,
+                                     const double*);
+template int launch_add_correction<float>(int64_t, double*, const double*, const float*,
+                                          const int*, hipStream_t);
+template int launch_add_correction<double>(int64_t, double*, const double*, const double*,
+                                           const int*, hipStream_t);
 
 // ============================================================ host setup
 // Symmetric eigen-decomposition by cyclic Jacobi rotations (stretched axes).

@@ -262,15 +262,26 @@ __device__ __forceinline__ Cx<V>* fft_lines(Cx<V>* src, Cx<V>* dst, const Cx<V>*
 
 // MODE 0: forward (lines -> basis coefficients), 1: inverse, 2: forward,
 // division by the eigenvalue sum, inverse.  N is the axis length.  ACC
-// (contiguous axis, MODE 1): the result is added to the double array pacc
-// instead of being stored in Y (the refinement correction p += d of the
-// last pass of a sweep).
+// (contiguous axis, MODE 1): pacc = pin + result, in double, instead of
+// the result in Y (the refinement correction of the last pass of a sweep;
+// pin == pacc in place, else a skipped launch still copies pin).
 template <typename V, int N, bool XFAST, int MODE, bool ACC>
 __global__ void __launch_bounds__(kBlock)
 k_fft_axis(const V* __restrict__ X, V* __restrict__ Y, int inner, int64_t ncols, FftAxis ax,
-           const V* __restrict__ twg, FdmDiv dv, const int* stop, double* __restrict__ pacc) {
+           const V* __restrict__ twg, FdmDiv dv, const int* stop, double* pacc,
+           const double* pin) {
   static_assert(!ACC || (XFAST && MODE == 1), "accumulation is for the contiguous inverse");
-  if (stop && *stop) return;
+  if (stop && *stop) {
+    if constexpr (ACC) {
+      if (pin != pacc) {
+        const int64_t b0 = (int64_t)blockIdx.x * FftCfg<V>::LPB * N;
+        const int64_t left = ncols - (int64_t)blockIdx.x * FftCfg<V>::LPB;
+        const int64_t ne = (left < FftCfg<V>::LPB ? left : FftCfg<V>::LPB) * N;
+        for (int64_t e = threadIdx.x; e < ne; e += kBlock) pacc[b0 + e] = pin[b0 + e];
+      }
+    }
+    return;
+  }
   constexpr bool IL = !XFAST;
   typedef FftCfg<V> C;
   constexpr int LPB = C::LPB, P = C::P;
@@ -327,7 +338,7 @@ k_fft_axis(const V* __restrict__ X, V* __restrict__ Y, int inner, int64_t ncols,
       for (int h = 0; h < LV; ++h) {
         pv[u][h] = dvec_t{};
         if ((NV % kBlock == 0 || e < NV) && gvalid(e, h))
-          pv[u][h] = *reinterpret_cast<const dvec_t*>(pacc + gaddr(e, h));
+          pv[u][h] = *reinterpret_cast<const dvec_t*>(pin + gaddr(e, h));
       }
     }
   }
@@ -538,10 +549,12 @@ FftAxis fft_plan(int n, double h) {
 
 template <typename V>
 int launch_fft_axis(const FdmPlan<V>& F, int a, int mode, const V* in, V* out, const int* stop,
-                    hipStream_t s, double* acc) {
+                    hipStream_t s, double* acc, const double* accin) {
   const int N = F.n[a];
+  if (!accin) accin = acc;
   // the kernel moves 16-byte vectors (32-byte ones of the accumulator)
-  if (((uintptr_t)in | (uintptr_t)out) % 16 != 0 || (uintptr_t)acc % 32 != 0) return FVIB_EINVAL;
+  if (((uintptr_t)in | (uintptr_t)out) % 16 != 0 || ((uintptr_t)acc | (uintptr_t)accin) % 32 != 0)
+    return FVIB_EINVAL;
   int inner = 1;
   for (int q = 0; q < a; ++q) inner *= F.n[q];
   int64_t outer = 1;
@@ -553,8 +566,8 @@ int launch_fft_axis(const FdmPlan<V>& F, int a, int mode, const V* in, V* out, c
   const dim3 g((unsigned)((ncols + LPB - 1) / LPB));
   bool done = false;
 #define FVIB_FFT(NN, XF, M, AC)                                                                 \
-  launch_kernel((k_fft_axis<V, NN, XF, M, AC>), g, dim3(kBlock), 0, s, in, out, inner,     \
-                     ncols, F.fft[a], F.tw[a], F.div, stop, acc)
+  launch_kernel((k_fft_axis<V, NN, XF, M, AC>), g, dim3(kBlock), 0, s, in, out, inner,          \
+                ncols, F.fft[a], F.tw[a], F.div, stop, acc, accin)
 #define FVIB_FFT_N(NN)                                                                          \
   if (!done && N == NN) {                                                                       \
     done = true;                                                                                \
@@ -586,9 +599,9 @@ bool fft_usable(const FdmPlan<V>& F, int a) {
 }
 
 template int launch_fft_axis<float>(const FdmPlan<float>&, int, int, const float*, float*,
-                                    const int*, hipStream_t, double*);
+                                    const int*, hipStream_t, double*, const double*);
 template int launch_fft_axis<double>(const FdmPlan<double>&, int, int, const double*, double*,
-                                     const int*, hipStream_t, double*);
+                                     const int*, hipStream_t, double*, const double*);
 template bool fft_usable<float>(const FdmPlan<float>&, int);
 template bool fft_usable<double>(const FdmPlan<double>&, int);
 

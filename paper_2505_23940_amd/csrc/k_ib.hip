@@ -181,8 +181,11 @@ k_loads_body(IbGeo B, IbView<T> ib, const double* __restrict__ body_in,
   for (int a = 0; a < 6; ++a) body_out[a] = st[a];
 }
 
+// Also copies (or zeroes, src == nullptr) a 6-double body state when dst
+// is given (the adjoint body state of a step without a body).
 __global__ void k_copy_info(const SolverScalars* sc, fvib_step_info* info, int cg_iters,
-                            int ir_iters) {
+                            int ir_iters, const double* body_src, double* body_dst) {
+  if (body_dst && threadIdx.x < 6) body_dst[threadIdx.x] = body_src ? body_src[threadIdx.x] : 0.0;
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int st = sc->status;
   if (st == FVIB_OK && sc->clamp) st = FVIB_EINVAL;
@@ -219,8 +222,9 @@ int launch_loads_body(const IbGeo& B, const IbView<T>& ib, const double* body_in
 }
 
 int launch_copy_info(const SolverScalars* sc, fvib_step_info* info, int cg_iters, int ir_iters,
-                     hipStream_t s) {
-  launch_kernel(k_copy_info, dim3(1), dim3(64), 0, s, sc, info, cg_iters, ir_iters);
+                     hipStream_t s, const double* body_src, double* body_dst) {
+  launch_kernel(k_copy_info, dim3(1), dim3(64), 0, s, sc, info, cg_iters, ir_iters, body_src,
+                body_dst);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
