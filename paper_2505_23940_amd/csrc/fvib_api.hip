@@ -1008,8 +1008,10 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
           dmalloc(&g->pB64, g->ncell * sizeof(double)))
         return bail(FVIB_ENOMEM, "device allocation of the workspace failed");
     }
-    std::vector<double> hd;   // per axis: phi, phiT, lam, FFT twiddles
+    std::vector<double> hd;   // per axis: phi, phiT, lam, FFT twiddles, symmetric halves
     size_t off[3][4];
+    size_t soff[3][5];
+    bool symok[3] = {false, false, false};
     FftAxis fax[3];
     for (int a = 0; a < g->dim; ++a) {
       std::vector<double> phi, lam;
@@ -1041,6 +1043,47 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
           hd.push_back(sin(th));
         }
         hd.resize((hd.size() + 3) / 4 * 4, 0.0);
+      }
+      // Bounded axis with mirror-symmetric faces (not the last one, which
+      // carries the division): even / odd half bases for the float path,
+      // from the two half eigenproblems; lam of that path in [even | odd]
+      // order.
+      // (the split kernel takes strided axes whose faster extent is a
+      // multiple of 32; every float pass over this axis must use it, since
+      // the mode order differs from the dense basis)
+      int inner_a = 1;
+      for (int b2 = 0; b2 < a; ++b2) inner_a *= g->n[b2];
+      if (!g->per[a] && a > 0 && a != g->dim - 1 && inner_a % 32 == 0 &&
+          fdm_sym_size_supported(N)) {
+        const int H = N / 2;
+        const double L = fa[N] - fa[0];
+        bool ok = true;
+        for (int i = 0; i <= N && ok; ++i)
+          ok = fabs((fa[i] - fa[0]) - (fa[N] - fa[N - i])) <= 1e-12 * L;
+        if (ok) {
+          std::vector<double> ue, le, uo, lo;
+          axis_eigen_sym(fa, ue, le, uo, lo);
+          auto half = [&](const std::vector<double>& u, bool transposed) {
+            // forward [s][j] = u_j of mode s; inverse [j][s]
+            for (int r = 0; r < H; ++r)
+              for (int c = 0; c < H; ++c)
+                hd.push_back(transposed ? u[(size_t)r * H + c] : u[(size_t)c * H + r]);
+            hd.resize((hd.size() + 3) / 4 * 4, 0.0);
+          };
+          soff[a][0] = hd.size();
+          half(ue, false);
+          soff[a][1] = hd.size();
+          half(uo, false);
+          soff[a][2] = hd.size();
+          half(ue, true);
+          soff[a][3] = hd.size();
+          half(uo, true);
+          soff[a][4] = hd.size();
+          hd.insert(hd.end(), le.begin(), le.end());
+          hd.insert(hd.end(), lo.begin(), lo.end());
+          hd.resize((hd.size() + 3) / 4 * 4, 0.0);
+          symok[a] = true;
+        }
       }
     }
     std::vector<float> hf(hd.begin(), hd.end());
@@ -1074,6 +1117,15 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
     }
     g->F64.div = dv;
     g->F32.div = dv;
+    for (int a = 0; a < g->dim; ++a) {
+      if (!symok[a]) continue;
+      g->F32.sym[a].on = 1;
+      g->F32.sym[a].fe = g->fdm_f + soff[a][0];
+      g->F32.sym[a].fo = g->fdm_f + soff[a][1];
+      g->F32.sym[a].ie = g->fdm_f + soff[a][2];
+      g->F32.sym[a].io = g->fdm_f + soff[a][3];
+      g->F32.div.lam[a] = g->fdm_d + soff[a][4];
+    }
   }
   if (hipHostMalloc((void**)&g->sch, sizeof(SolverScalars), hipHostMallocDefault) != hipSuccess)
     return bail(FVIB_ENOMEM, "pinned host allocation failed");

@@ -42,6 +42,18 @@ struct FftAxis {
   double a, b;                 // basis scales sqrt(2/N)/sqrt(h), 1/sqrt(N h)
 };
 
+// Mirror-symmetric bounded axis split into even and odd halves (float
+// path): half-size operators, row-major H x H, and the mode order
+// [even modes | odd modes] of that axis in the transformed array.
+template <typename V>
+struct FdmSym {
+  int on;
+  const V* fe;                 // forward even: [s][j] = u_j of even mode s
+  const V* fo;                 // forward odd
+  const V* ie;                 // inverse even: [j][s] (transpose of fe)
+  const V* io;                 // inverse odd
+};
+
 template <typename V>
 struct FdmPlan {
   int dim;
@@ -51,7 +63,11 @@ struct FdmPlan {
   FdmDiv div;
   FftAxis fft[3];
   const V* tw[3];              // exp(-2 pi i k / N), k < N, as (re, im) pairs
+  FdmSym<V> sym[3];
 };
+
+// Whether an axis of length n has a symmetric-split kernel.
+bool fdm_sym_size_supported(int n);
 
 // FFT description of a uniform periodic axis of length n and spacing h
 // (on = 0 if no FFT kernel exists for n).
@@ -156,6 +172,9 @@ int launch_add_correction(int64_t n, double* p, const double* pin, const V* d, c
 int launch_gauge(int64_t n, double* p, const SolverScalars* sc, hipStream_t s);
 void axis_eigen(const std::vector<double>& f, bool periodic, std::vector<double>& phi,
                 std::vector<double>& lam);
+// Even and odd half eigenbases of a mirror-symmetric bounded axis (N even).
+void axis_eigen_sym(const std::vector<double>& f, std::vector<double>& ue, std::vector<double>& le,
+                    std::vector<double>& uo, std::vector<double>& lo);
 
 // k_loss.hip
 template <typename T>

@@ -679,6 +679,134 @@ k_axis_reg(const float* __restrict__ X, float* __restrict__ Y, const float* __re
   }
 }
 
+// Mirror-symmetric bounded axis (float, N = 2H): every eigenvector of a
+// 1D operator that commutes with the reflection j -> N - 1 - j is even or
+// odd, so the N x N contraction splits into two H x H ones.  Forward:
+// even modes from S_j = x_j + x_{N-1-j}, odd modes from D_j = x_j -
+// x_{N-1-j} (j < H), written as [even modes | odd modes]; inverse: E = Ie
+// c_even, O = Io c_odd and x_j = E_j + O_j, x_{N-1-j} = E_j - O_j.  Half
+// the matrix-core work of the dense form; same staging as k_axis_reg (each
+// wave holds even and odd row tiles w, w + 4, ... of its operators).
+template <int H, bool FWD>
+__global__ void __launch_bounds__(kBlock)
+k_axis_sym(const float* __restrict__ X, float* __restrict__ Y, const float* __restrict__ Ae,
+           const float* __restrict__ Ao, int inner, int64_t ncols, const int* stop) {
+  if (stop && *stop) return;
+  static_assert(H % 16 == 0 && H <= 128, "half operator rows must fit the registers");
+  constexpr int N = 2 * H;
+  constexpr int NT = 2, NC = 32;                 // lines per block
+  constexpr int TH = H / 16;                     // row tiles per half
+  constexpr int MT = (TH + 3) / 4;               // per wave and half
+  constexpr int G = H / 16;                      // contraction groups
+  constexpr int LDK = H + 4;
+  constexpr int CV = NC / 4;                     // float4 per index row
+  constexpr int XP = (H * CV + kBlock - 1) / kBlock;
+  typedef __attribute__((ext_vector_type(4))) float f4_t;
+  typedef typename Mfma<float>::acc_t acc_t;
+  __shared__ __attribute__((aligned(16))) float S0[NC * LDK];    // even operand, line-major
+  __shared__ __attribute__((aligned(16))) float S1[NC * LDK];    // odd operand
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int q = lane >> 4, r = lane & 15;
+  const int64_t n0 = (int64_t)blockIdx.x * NC;
+  const int64_t o0 = n0 / inner;
+  const int64_t i0 = n0 - o0 * inner;
+  const float* xb = X + o0 * (int64_t)N * inner + i0;
+  // index rows k and N-1-k (forward) or k and H+k (inverse) of the lines
+  f4_t ra[XP], rb[XP];
+#pragma unroll
+  for (int u = 0; u < XP; ++u) {
+    const int e = t + u * kBlock;
+    if ((H * CV) % kBlock == 0 || e < H * CV) {
+      const int k = e / CV, c = e - k * CV;
+      const int k2 = FWD ? N - 1 - k : H + k;
+      ra[u] = *reinterpret_cast<const f4_t*>(xb + (int64_t)k * inner + 4 * c);
+      rb[u] = *reinterpret_cast<const f4_t*>(xb + (int64_t)k2 * inner + 4 * c);
+    }
+  }
+  f4_t ae[MT][G], ao[MT][G];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int tile = w + 4 * mt;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int off = (16 * tile + r) * H + 16 * g + 4 * q;
+      ae[mt][g] = tile < TH ? *reinterpret_cast<const f4_t*>(Ae + off) : f4_t{0.f, 0.f, 0.f, 0.f};
+      ao[mt][g] = tile < TH ? *reinterpret_cast<const f4_t*>(Ao + off) : f4_t{0.f, 0.f, 0.f, 0.f};
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < XP; ++u) {
+    const int e = t + u * kBlock;
+    if ((H * CV) % kBlock == 0 || e < H * CV) {
+      const int k = e / CV, c = e - k * CV;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        S0[(4 * c + j) * LDK + k] = FWD ? ra[u][j] + rb[u][j] : ra[u][j];
+        S1[(4 * c + j) * LDK + k] = FWD ? ra[u][j] - rb[u][j] : rb[u][j];
+      }
+    }
+  }
+  __syncthreads();
+  acc_t ce[MT][NT], co[MT][NT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      ce[mt][tt] = acc_t{0.f, 0.f, 0.f, 0.f};
+      co[mt][tt] = acc_t{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    f4_t xe[NT], xo[NT];
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      xe[tt] = *reinterpret_cast<const f4_t*>(S0 + (16 * tt + r) * LDK + 16 * g + 4 * q);
+      xo[tt] = *reinterpret_cast<const f4_t*>(S1 + (16 * tt + r) * LDK + 16 * g + 4 * q);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      if (w + 4 * mt >= TH) continue;             // wave-uniform
+#pragma unroll
+      for (int sidx = 0; sidx < 4; ++sidx)
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt) {
+          ce[mt][tt] = Mfma<float>::op(ae[mt][g][sidx], xe[tt][sidx], ce[mt][tt]);
+          co[mt][tt] = Mfma<float>::op(ao[mt][g][sidx], xo[tt][sidx], co[mt][tt]);
+        }
+    }
+  }
+  float* yb = Y + o0 * (int64_t)N * inner + i0;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int tile = w + 4 * mt;
+    if (tile >= TH) continue;
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = 16 * tile + Mfma<float>::row(lane, v);
+        const float a = ce[mt][tt][v], b = co[mt][tt][v];
+        const int row0 = m, row1 = FWD ? H + m : N - 1 - m;
+        __builtin_nontemporal_store(FWD ? a : a + b, yb + (int64_t)row0 * inner + 16 * tt + r);
+        __builtin_nontemporal_store(FWD ? b : a - b, yb + (int64_t)row1 * inner + 16 * tt + r);
+      }
+  }
+}
+
+// Half sizes with a k_axis_sym kernel.
+#define FVIB_SYM_SIZES(X) X(16) X(32) X(48) X(64) X(96) X(128)
+
+bool fdm_sym_size_supported(int n) {
+  const int h = n / 2;
+  if (n % 2 != 0) return false;
+#define FVIB_SYM_IS(HH) if (h == HH) return true;
+  FVIB_SYM_SIZES(FVIB_SYM_IS)
+#undef FVIB_SYM_IS
+  return false;
+}
+
 // Operator sizes with a k_axis_reg kernel.
 #define FVIB_REG_SIZES(X) X(32) X(64) X(96) X(128)
 
@@ -770,6 +898,32 @@ int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, c
   const V* Am = fwd ? F.phiT[a] : F.phi[a];
   const bool div = fwd && a == F.dim - 1;
   if constexpr (sizeof(V) == 4) {
+    // mirror-symmetric strided float axis without division: two half-size
+    // contractions
+    if (F.sym[a].on && !div && inner != 1 && inner % 32 == 0) {
+      const int H = K / 2;
+      bool done = false;
+      const dim3 g((unsigned)(ncols / 32));
+      const float* A0 = fwd ? F.sym[a].fe : F.sym[a].ie;
+      const float* A1 = fwd ? F.sym[a].fo : F.sym[a].io;
+#define FVIB_SYM(HH)                                                                            \
+      if (!done && H == HH) {                                                                   \
+        done = true;                                                                            \
+        if (fwd)                                                                                \
+          launch_kernel((k_axis_sym<HH, true>), g, dim3(kBlock), 0, s, (const float*)in,        \
+                        (float*)out, A0, A1, inner, ncols, stop);                               \
+        else                                                                                    \
+          launch_kernel((k_axis_sym<HH, false>), g, dim3(kBlock), 0, s, (const float*)in,       \
+                        (float*)out, A0, A1, inner, ncols, stop);                               \
+      }
+      FVIB_SYM_SIZES(FVIB_SYM)
+#undef FVIB_SYM
+      if (done) {
+        FVIB_HIP(hipGetLastError());
+        return FVIB_OK;
+      }
+      return FVIB_EINVAL;      // the plan marks only axes with a kernel
+    }
     // strided float axis without division: operator in registers
     if (!div && inner != 1 && inner % 32 == 0) {
       bool done = false;
@@ -1033,6 +1187,58 @@ void axis_eigen(const std::vector<double>& f, bool periodic, std::vector<double>
     double sg = v[(size_t)0 * N + src] < 0 ? -1.0 : 1.0;
     for (int j = 0; j < N; ++j) phi[(size_t)j * N + m] = sg * v[(size_t)j * N + src] / sqrt(dx[j]);
     lam[m] = (m == 0) ? 0.0 : l[src];
+  }
+}
+
+// Mirror-symmetric bounded axis (faces symmetric about the middle, N even):
+// the Neumann operator T commutes with the reflection, so its generalised
+// eigenproblem T phi = lam W phi splits into an even and an odd half of size
+// H = N / 2 on the cells j < H: T restricted to them, with the coupling
+// across the middle folded in by x_H = +x_{H-1} (even) or -x_{H-1} (odd).
+// Solving the halves directly gives an exactly even / odd eigenbasis even
+// where the full problem has (numerically) degenerate pairs of wall modes.
+// ue, uo: H x H, column s = mode s, entries j < H, scaled so that the full
+// mirrored vector has unit W-norm; le, lo ascending (le[0] = 0).
+void axis_eigen_sym(const std::vector<double>& f, std::vector<double>& ue, std::vector<double>& le,
+                    std::vector<double>& uo, std::vector<double>& lo) {
+  const int N = (int)f.size() - 1;
+  const int H = N / 2;
+  std::vector<double> dx(N), xc(N);
+  for (int i = 0; i < N; ++i) {
+    dx[i] = f[i + 1] - f[i];
+    xc[i] = 0.5 * (f[i] + f[i + 1]);
+  }
+  for (int par = 0; par < 2; ++par) {
+    std::vector<double> C((size_t)H * H, 0.0);
+    for (int q = 1; q < H; ++q) {
+      const double coef = 1.0 / (xc[q] - xc[q - 1]);
+      const int i = q, j = q - 1;
+      C[(size_t)i * H + i] += coef;
+      C[(size_t)j * H + j] += coef;
+      C[(size_t)i * H + j] -= coef;
+      C[(size_t)j * H + i] -= coef;
+    }
+    // coupling of cells H-1 and H: diagonal coef, partner value +-x_{H-1}
+    const double cm = 1.0 / (xc[H] - xc[H - 1]);
+    C[(size_t)(H - 1) * H + (H - 1)] += par == 0 ? 0.0 : 2.0 * cm;
+    for (int i = 0; i < H; ++i)
+      for (int j = 0; j < H; ++j) C[(size_t)i * H + j] /= sqrt(dx[i] * dx[j]);
+    std::vector<double> l, v;
+    jacobi_eigen(H, C, l, v);
+    std::vector<int> ord(H);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::sort(ord.begin(), ord.end(), [&](int x, int y) { return l[x] < l[y]; });
+    std::vector<double>& u = par == 0 ? ue : uo;
+    std::vector<double>& lam = par == 0 ? le : lo;
+    u.assign((size_t)H * H, 0.0);
+    lam.assign(H, 0.0);
+    for (int m = 0; m < H; ++m) {
+      const int src = ord[m];
+      const double sg = v[(size_t)0 * H + src] < 0 ? -1.0 : 1.0;
+      for (int j = 0; j < H; ++j)
+        u[(size_t)j * H + m] = sg * v[(size_t)j * H + src] / sqrt(dx[j]) / sqrt(2.0);
+      lam[m] = (par == 0 && m == 0) ? 0.0 : l[src];
+    }
   }
 }
 
