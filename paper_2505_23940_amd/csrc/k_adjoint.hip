@@ -680,24 +680,117 @@ struct AdjRegs {
   T u[2][DIM], r[2][DIM];
 };
 
+// The x-y part of the halo rules of this thread's slots, which does not
+// change along the z-march: the in-plane offset of each slot per component
+// (wrapped on periodic axes, clamped on bounded ones), the ghost rule of u
+// (negated about 2 g behind a Dirichlet boundary) and whether the scaled
+// Rbar vanishes (outside a bounded axis, or an own-axis face that is not
+// advanced), plus the forced-face index of the 2D immersed boundary.  Each
+// plane then only adds its (uniform) z part.
+template <typename T, int DIM>
+struct AdjHalo {
+  int xy[2][DIM];
+  T goff[2][DIM];                // ghost offset 2 g of u (x-y), used when negated
+  uint32_t neg;                  // bit 3 h + c: u negated by an x-y ghost
+  uint32_t zr;                   // bit 3 h + c: Rbar zero by the x-y rules
+  int li[2][2];                  // forced index of components 0, 1 or -1
+};
+
 template <int DIM, typename T>
-__device__ __forceinline__ void adj_load(const AdjCtx<T>& X, AdjRegs<T, DIM>& P, int i0, int j0,
-                                         int kk) {
+__device__ __forceinline__ void adj_halo_init(const AdjCtx<T>& X, AdjHalo<T, DIM>& Hh, int i0,
+                                              int j0) {
   const Geo<T>& G = X.G;
+  Hh.neg = 0u;
+  Hh.zr = 0u;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int s = threadIdx.x + h * kBlock;
+    const int sy = s / kLX, sx = s - sy * kLX;
+    const int gi = min(i0 - 1 + sx, G.n[0]), gj = min(j0 - 1 + sy, G.n[1]);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      int I[2] = {gi, gj};
+      T off = T(0);
+      bool neg = false, out = false;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int e = G.ext[c][a];
+        const bool lo = I[a] < 0, hi = I[a] >= e;
+        const bool per = G.per[a] != 0;
+        const int wrapped = lo ? I[a] + e : (hi ? I[a] - e : I[a]);
+        const int clamped = lo ? 0 : (hi ? e - 1 : I[a]);
+        I[a] = per ? wrapped : clamped;
+        const bool ghost = !per && (lo || hi);
+        const bool dir = lo ? (G.dir[a][0] != 0) : (G.dir[a][1] != 0);
+        const T g2 = T(2) * (lo ? G.gv[c][a][0] : G.gv[c][a][1]);
+        neg = (ghost && dir) ? true : (ghost ? false : neg);
+        off = (ghost && dir) ? g2 : off;
+        out = out || ghost;
+      }
+      Hh.xy[h][c] = I[1] * G.ext[c][0] + I[0];
+      Hh.goff[h][c] = off;
+      // own-axis face not advanced (x or y component; z is per plane)
+      const bool notev = c < 2 && !G.per[c] && (I[c] < 1 || I[c] > G.n[c] - 1);
+      Hh.neg |= (neg ? 1u : 0u) << (3 * h + c);
+      Hh.zr |= ((out || notev) ? 1u : 0u) << (3 * h + c);
+      if (c < 2) {
+        int li = -1;
+        if (X.ib.active) {
+          int l = 0;
+          const int f = c == 0 ? forced_cls<0>(X.ib, I[0], I[1], &l) : forced_cls<1>(X.ib, I[0], I[1], &l);
+          li = f ? l : -1;
+        }
+        Hh.li[h][c] = li;
+      }
+    }
+  }
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ void adj_load(const AdjCtx<T>& X, const AdjHalo<T, DIM>& Hh,
+                                         AdjRegs<T, DIM>& P, int kk) {
+  const Geo<T>& G = X.G;
+  // z part of the rules for this plane (uniform across the block)
+  int64_t pbase[DIM];
+  bool gz = false, dz = false, zoff[DIM];
+  T g2z[DIM];
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    int kz = 0;
+    if constexpr (DIM == 3) {
+      const int e = G.ext[c][2];
+      const bool lo = kk < 0, hi = kk >= e;
+      const bool per = G.per[2] != 0;
+      kz = per ? (lo ? kk + e : (hi ? kk - e : kk)) : (lo ? 0 : (hi ? e - 1 : kk));
+      gz = !per && (lo || hi);
+      dz = lo ? (G.dir[2][0] != 0) : (G.dir[2][1] != 0);
+      g2z[c] = T(2) * (lo ? G.gv[c][2][0] : G.gv[c][2][1]);
+      zoff[c] = gz || (c == 2 && !G.per[2] && (kz < 1 || kz > G.n[2] - 1));
+    } else {
+      g2z[c] = T(0);
+      zoff[c] = false;
+    }
+    pbase[c] = (int64_t)kz * G.ext[c][0] * G.ext[c][1];
+  }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int s = threadIdx.x + h * kBlock;
     if (s >= kLX * kLY) break;
-    const int sy = s / kLX, sx = s - sy * kLX;
-    const int gi = min(i0 - 1 + sx, G.n[0]), gj = min(j0 - 1 + sy, G.n[1]);
-    bool out;
-    P.u[h][0] = ld_halo<0, DIM>(G, X.u[0], gi, gj, kk, &out);
-    P.r[h][0] = rb_halo<0, DIM>(X, gi, gj, kk);
-    P.u[h][1] = ld_halo<1, DIM>(G, X.u[1], gi, gj, kk, &out);
-    P.r[h][1] = rb_halo<1, DIM>(X, gi, gj, kk);
-    if constexpr (DIM == 3) {
-      P.u[h][2] = ld_halo<2, DIM>(G, X.u[2], gi, gj, kk, &out);
-      P.r[h][2] = rb_halo<2, DIM>(X, gi, gj, kk);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const int64_t id = pbase[c] + Hh.xy[h][c];
+      const T v = X.u[c][id];
+      const bool negxy = (Hh.neg >> (3 * h + c)) & 1u;
+      const bool neg = gz ? dz : negxy;
+      const T off = (gz && dz) ? g2z[c] : Hh.goff[h][c];
+      P.u[h][c] = neg ? off - v : v;
+      T rv = X.usb[c][id];
+      if (c < 2) {
+        const int li = Hh.li[h][c];
+        if (li >= 0) rv = -X.ib.f[c][li] / G.dt;
+      }
+      const bool zero = ((Hh.zr >> (3 * h + c)) & 1u) || zoff[c];
+      P.r[h][c] = zero ? T(0) : rv;
     }
   }
 }
@@ -718,15 +811,17 @@ __device__ __forceinline__ void adj_store(AdjRings<T, DIM>& S, int slot, const A
 }
 
 template <int DIM, typename T>
-__device__ __forceinline__ void adj_fill(const AdjCtx<T>& X, AdjRings<T, DIM>& S, int slot,
-                                         int i0, int j0, int kk) {
+__device__ __forceinline__ void adj_fill(const AdjCtx<T>& X, const AdjHalo<T, DIM>& Hh,
+                                         AdjRings<T, DIM>& S, int slot, int kk) {
   AdjRegs<T, DIM> P;
-  adj_load<DIM>(X, P, i0, j0, kk);
+  adj_load<DIM>(X, Hh, P, kk);
   adj_store<DIM>(S, slot, P);
 }
 
+// At most 128 registers (four waves per SIMD): a channel-sized grid then
+// runs in one round of blocks.
 template <typename T, int DIM, bool UPW>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, 4)
 k_adj_momentum_lds(AdjCtx<T> X, int ntx, int nty, int nzc, T* __restrict__ ub0,
                    T* __restrict__ ub1, T* __restrict__ ub2, T* __restrict__ fb0,
                    T* __restrict__ fb1, T* __restrict__ fb2) {
@@ -747,14 +842,16 @@ k_adj_momentum_lds(AdjCtx<T> X, int ntx, int nty, int nzc, T* __restrict__ ub0,
   const int k1 = (DIM == 3) ? min(k0 + kZChunk, G.n[2]) : 1;
   const bool inside = i < G.n[0] && j < G.n[1];
   load_tile_met<DIM>(G, TM, i0, j0, k0);
+  AdjHalo<T, DIM> Hh;
+  adj_halo_init<DIM>(X, Hh, i0, j0);
   AdjRegs<T, DIM> nxt;
   if (DIM == 3) {
-    adj_fill<DIM>(X, S, ring_slot(k0 - 1), i0, j0, k0 - 1);
-    adj_fill<DIM>(X, S, ring_slot(k0), i0, j0, k0);
-    adj_fill<DIM>(X, S, ring_slot(k0 + 1), i0, j0, k0 + 1);
-    if (k0 + 1 < k1) adj_load<DIM>(X, nxt, i0, j0, k0 + 2);
+    adj_fill<DIM>(X, Hh, S, ring_slot(k0 - 1), k0 - 1);
+    adj_fill<DIM>(X, Hh, S, ring_slot(k0), k0);
+    adj_fill<DIM>(X, Hh, S, ring_slot(k0 + 1), k0 + 1);
+    if (k0 + 1 < k1) adj_load<DIM>(X, Hh, nxt, k0 + 2);
   } else {
-    adj_fill<DIM>(X, S, 0, i0, j0, 0);
+    adj_fill<DIM>(X, Hh, S, 0, 0);
   }
   for (int k = k0; k < k1; ++k) {
     __syncthreads();
@@ -795,7 +892,7 @@ k_adj_momentum_lds(AdjCtx<T> X, int ntx, int nty, int nzc, T* __restrict__ ub0,
     if (DIM == 3 && k + 1 < k1) {
       __syncthreads();
       adj_store<DIM>(S, sm, nxt);                     // slot of plane k-1 takes k+2
-      if (k + 2 < k1) adj_load<DIM>(X, nxt, i0, j0, k + 3);
+      if (k + 2 < k1) adj_load<DIM>(X, Hh, nxt, k + 3);
     }
   }
 }
