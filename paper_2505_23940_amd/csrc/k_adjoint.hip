@@ -751,24 +751,24 @@ __device__ __forceinline__ void adj_load(const AdjCtx<T>& X, const AdjHalo<T, DI
                                          AdjRegs<T, DIM>& P, int kk) {
   const Geo<T>& G = X.G;
   // z part of the rules for this plane (uniform across the block)
+  // (per component: w has one more face than cells along a bounded z)
   int64_t pbase[DIM];
-  bool gz = false, dz = false, zoff[DIM];
+  bool gz[DIM], dz[DIM], zoff[DIM];
   T g2z[DIM];
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
     int kz = 0;
+    gz[c] = dz[c] = zoff[c] = false;
+    g2z[c] = T(0);
     if constexpr (DIM == 3) {
       const int e = G.ext[c][2];
       const bool lo = kk < 0, hi = kk >= e;
       const bool per = G.per[2] != 0;
       kz = per ? (lo ? kk + e : (hi ? kk - e : kk)) : (lo ? 0 : (hi ? e - 1 : kk));
-      gz = !per && (lo || hi);
-      dz = lo ? (G.dir[2][0] != 0) : (G.dir[2][1] != 0);
+      gz[c] = !per && (lo || hi);
+      dz[c] = lo ? (G.dir[2][0] != 0) : (G.dir[2][1] != 0);
       g2z[c] = T(2) * (lo ? G.gv[c][2][0] : G.gv[c][2][1]);
-      zoff[c] = gz || (c == 2 && !G.per[2] && (kz < 1 || kz > G.n[2] - 1));
-    } else {
-      g2z[c] = T(0);
-      zoff[c] = false;
+      zoff[c] = gz[c] || (c == 2 && !G.per[2] && (kz < 1 || kz > G.n[2] - 1));
     }
     pbase[c] = (int64_t)kz * G.ext[c][0] * G.ext[c][1];
   }
@@ -781,8 +781,8 @@ __device__ __forceinline__ void adj_load(const AdjCtx<T>& X, const AdjHalo<T, DI
       const int64_t id = pbase[c] + Hh.xy[h][c];
       const T v = X.u[c][id];
       const bool negxy = (Hh.neg >> (3 * h + c)) & 1u;
-      const bool neg = gz ? dz : negxy;
-      const T off = (gz && dz) ? g2z[c] : Hh.goff[h][c];
+      const bool neg = gz[c] ? dz[c] : negxy;
+      const T off = (gz[c] && dz[c]) ? g2z[c] : Hh.goff[h][c];
       P.u[h][c] = neg ? off - v : v;
       T rv = X.usb[c][id];
       if (c < 2) {

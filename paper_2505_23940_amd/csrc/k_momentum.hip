@@ -138,22 +138,89 @@ struct PlaneRegs {
   T v[2][DIM];
 };
 
+// The x-y part of the halo rules of this thread's slots (fixed along the
+// z-march): in-plane offset per component (wrapped / clamped) and the ghost
+// rule behind a bounded x or y boundary; each plane adds its uniform z part.
+// Halo slots past a ragged tile edge are clamped to one step outside the
+// domain (their values are never used), so every load stays in bounds
+// however small the axis.
+template <typename T, int DIM>
+struct PlaneHalo {
+  int xy[2][DIM];
+  T goff[2][DIM];                // ghost offset 2 g (x-y), used when negated
+  uint32_t neg;                  // bit 3 h + c: negated by an x-y ghost
+};
+
 template <int DIM, typename T>
-__device__ __forceinline__ void load_plane(const Geo<T>& G, const T* const* u, PlaneRegs<T, DIM>& P,
-                                           int i0, int j0, int kk) {
+__device__ __forceinline__ void plane_halo_init(const Geo<T>& G, PlaneHalo<T, DIM>& Hh, int i0,
+                                                int j0) {
+  Hh.neg = 0u;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int s = threadIdx.x + h * kBlock;
+    const int sy = s / kLX, sx = s - sy * kLX;
+    const int gi = min(i0 - 1 + sx, G.n[0]), gj = min(j0 - 1 + sy, G.n[1]);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      int I[2] = {gi, gj};
+      T off = T(0);
+      bool neg = false;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int e = G.ext[c][a];
+        const bool lo = I[a] < 0, hi = I[a] >= e;
+        const bool per = G.per[a] != 0;
+        const int wrapped = lo ? I[a] + e : (hi ? I[a] - e : I[a]);
+        const int clamped = lo ? 0 : (hi ? e - 1 : I[a]);
+        I[a] = per ? wrapped : clamped;
+        const bool ghost = !per && (lo || hi);
+        const bool dir = lo ? (G.dir[a][0] != 0) : (G.dir[a][1] != 0);
+        const T g2 = T(2) * (lo ? G.gv[c][a][0] : G.gv[c][a][1]);
+        neg = (ghost && dir) ? true : (ghost ? false : neg);
+        off = (ghost && dir) ? g2 : off;
+      }
+      Hh.xy[h][c] = I[1] * G.ext[c][0] + I[0];
+      Hh.goff[h][c] = off;
+      Hh.neg |= (neg ? 1u : 0u) << (3 * h + c);
+    }
+  }
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ void load_plane(const Geo<T>& G, const T* const* u,
+                                           const PlaneHalo<T, DIM>& Hh, PlaneRegs<T, DIM>& P,
+                                           int kk) {
+  // (per component: w has one more face than cells along a bounded z)
+  int64_t pbase[DIM];
+  bool gz[DIM], dz[DIM];
+  T g2z[DIM];
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    int kz = 0;
+    gz[c] = dz[c] = false;
+    g2z[c] = T(0);
+    if constexpr (DIM == 3) {
+      const int e = G.ext[c][2];
+      const bool lo = kk < 0, hi = kk >= e;
+      const bool per = G.per[2] != 0;
+      kz = per ? (lo ? kk + e : (hi ? kk - e : kk)) : (lo ? 0 : (hi ? e - 1 : kk));
+      gz[c] = !per && (lo || hi);
+      dz[c] = lo ? (G.dir[2][0] != 0) : (G.dir[2][1] != 0);
+      g2z[c] = T(2) * (lo ? G.gv[c][2][0] : G.gv[c][2][1]);
+    }
+    pbase[c] = (int64_t)kz * G.ext[c][0] * G.ext[c][1];
+  }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int s = threadIdx.x + h * kBlock;
     if (s >= kLX * kLY) break;
-    const int sy = s / kLX, sx = s - sy * kLX;
-    // halo slots past a ragged tile edge are clamped to one step outside
-    // the domain (their values are never used), so every load stays in
-    // bounds however small the axis
-    const int gi = min(i0 - 1 + sx, G.n[0]), gj = min(j0 - 1 + sy, G.n[1]);
-    bool out;
-    P.v[h][0] = ld_halo<0, DIM>(G, u[0], gi, gj, kk, &out);
-    P.v[h][1] = ld_halo<1, DIM>(G, u[1], gi, gj, kk, &out);
-    if constexpr (DIM == 3) P.v[h][2] = ld_halo<2, DIM>(G, u[2], gi, gj, kk, &out);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const T v = u[c][pbase[c] + Hh.xy[h][c]];
+      const bool neg = gz[c] ? dz[c] : (((Hh.neg >> (3 * h + c)) & 1u) != 0);
+      const T off = (gz[c] && dz[c]) ? g2z[c] : Hh.goff[h][c];
+      P.v[h][c] = neg ? off - v : v;
+    }
   }
 }
 
@@ -172,10 +239,10 @@ __device__ __forceinline__ void store_plane(PlaneRing<T, DIM>& R, int slot,
 
 template <int DIM, typename T>
 __device__ __forceinline__ void fill_plane(const Geo<T>& G, const T* const* u,
-                                           PlaneRing<T, DIM>& R, int slot, int i0, int j0,
-                                           int kk) {
+                                           const PlaneHalo<T, DIM>& Hh, PlaneRing<T, DIM>& R,
+                                           int slot, int kk) {
   PlaneRegs<T, DIM> P;
-  load_plane<DIM>(G, u, P, i0, j0, kk);
+  load_plane<DIM>(G, u, Hh, P, kk);
   store_plane<DIM>(R, slot, P);
 }
 
@@ -203,14 +270,16 @@ k_predictor(Geo<T> G, int ntx, int nty, int nzc, const T* __restrict__ u0,
   const int k1 = (DIM == 3) ? min(k0 + kZChunk, G.n[2]) : 1;
   const bool inside = i < G.n[0] && j < G.n[1];
   load_tile_met<DIM>(G, TM, i0, j0, k0);
+  PlaneHalo<T, DIM> Hh;
+  plane_halo_init<DIM>(G, Hh, i0, j0);
   PlaneRegs<T, DIM> nxt;
   if (DIM == 3) {
-    fill_plane<DIM>(G, u, R, ring_slot(k0 - 1), i0, j0, k0 - 1);
-    fill_plane<DIM>(G, u, R, ring_slot(k0), i0, j0, k0);
-    fill_plane<DIM>(G, u, R, ring_slot(k0 + 1), i0, j0, k0 + 1);
-    if (k0 + 1 < k1) load_plane<DIM>(G, u, nxt, i0, j0, k0 + 2);
+    fill_plane<DIM>(G, u, Hh, R, ring_slot(k0 - 1), k0 - 1);
+    fill_plane<DIM>(G, u, Hh, R, ring_slot(k0), k0);
+    fill_plane<DIM>(G, u, Hh, R, ring_slot(k0 + 1), k0 + 1);
+    if (k0 + 1 < k1) load_plane<DIM>(G, u, Hh, nxt, k0 + 2);
   } else {
-    fill_plane<DIM>(G, u, R, 0, i0, j0, 0);
+    fill_plane<DIM>(G, u, Hh, R, 0, 0);
   }
   for (int k = k0; k < k1; ++k) {
     __syncthreads();
@@ -235,7 +304,7 @@ k_predictor(Geo<T> G, int ntx, int nty, int nzc, const T* __restrict__ u0,
     if (DIM == 3 && k + 1 < k1) {
       __syncthreads();
       store_plane<DIM>(R, sm, nxt);                   // slot of plane k-1 takes k+2
-      if (k + 2 < k1) load_plane<DIM>(G, u, nxt, i0, j0, k + 3);
+      if (k + 2 < k1) load_plane<DIM>(G, u, Hh, nxt, k + 3);
     }
   }
 }
