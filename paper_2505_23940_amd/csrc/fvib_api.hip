@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -105,6 +106,7 @@ struct Timer {
 struct Grid {
   fvib_grid_desc d;
   hipStream_t stream = nullptr;
+  hipEvent_t check_ev = nullptr;   // convergence checks wait on it (spinning)
   int dim = 0, prec = 0;
   int n[3] = {1, 1, 1};
   int per[3] = {0, 0, 0};
@@ -185,6 +187,8 @@ static void release(Grid* g) {
   auto f = [](void* p) {
     if (p) (void)hipFree(p);
   };
+  if (g->check_ev) (void)hipEventDestroy(g->check_ev);
+  g->check_ev = nullptr;
   f(g->md);
   f(g->mf);
   for (int c = 0; c < 3; ++c) f(g->ustar[c]);
@@ -489,10 +493,31 @@ static int cg_run(Grid* g, const PGeo<V>& P, int mode, V* r, V* pa, V* pb, V* x,
   return FVIB_OK;
 }
 
-static int read_scalars(Grid* g) {
+// Device scalars to the host.  The host spins on an event instead of a
+// blocking stream synchronisation: it resumes as soon as the copy lands,
+// which shortens the device's idle time before the launches that follow
+// the check.
+static int enqueue_check(Grid* g) {
   FVIB_HIP(hipMemcpyAsync(g->sch, g->sc, sizeof(SolverScalars), hipMemcpyDeviceToHost, g->stream));
-  FVIB_HIP(hipStreamSynchronize(g->stream));
+  if (g->check_ev) FVIB_HIP(hipEventRecord(g->check_ev, g->stream));
   return FVIB_OK;
+}
+
+static int wait_check(Grid* g) {
+  if (!g->check_ev) {
+    FVIB_HIP(hipStreamSynchronize(g->stream));
+    return FVIB_OK;
+  }
+  hipError_t e;
+  while ((e = hipEventQuery(g->check_ev)) == hipErrorNotReady) {
+  }
+  FVIB_HIP(e);
+  return FVIB_OK;
+}
+
+static int read_scalars(Grid* g) {
+  int rc = enqueue_check(g);
+  return rc ? rc : wait_check(g);
 }
 
 // Solve A p = b - mean(b) in place on p (initial guess on input); meanb
@@ -506,9 +531,14 @@ static int read_scalars(Grid* g) {
 // restarts from zero.
 // p_in: the initial guess when it is not already in p (nullptr: p); p
 // receives the solution either way.
+// tail (fast diagonalisation, nullable): launches of work that depends on
+// the solution and may be repeated (pure functions of it); they are queued
+// behind each convergence check before the host waits for it, so the device
+// runs them meanwhile, and queued again if more sweeps follow.
 static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* last,
                          int* cg_total, int* ir_total, bool gauge = true, bool warm = false,
-                         const double* p_in = nullptr) {
+                         const double* p_in = nullptr,
+                         const std::function<int()>* tail = nullptr) {
   if (!p_in) p_in = p;
   int rc;
   *cg_total = 0;
@@ -601,7 +631,13 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
     for (;;) {
       for (int q = 0; q < batch && launched < g->d.ir_maxit; ++q, ++launched)
         if ((rc = sweep())) return rc;
-      if ((rc = read_scalars(g))) return rc;
+      g->timer.tag = 0;
+      if ((rc = enqueue_check(g))) return rc;
+      if (gauge &&
+          (rc = timed(g, FVIB_K_IR_CORRECT, [&] { return launch_gauge(g->ncell, p, g->sc, g->stream); })))
+        return rc;
+      if (tail && (rc = (*tail)())) return rc;
+      if ((rc = wait_check(g))) return rc;
       g->crit_log.push_back(g->sch->crit);
       if (g->sch->outer_done) break;
       if (warm && !(g->sch->crit < 0.1 * prev_crit)) {
@@ -629,9 +665,6 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
     }
     const int sweeps = g->sch->outer_done ? g->sch->sweeps : launched;
     g->timer.end_solve(sweeps);
-    if (gauge &&
-        (rc = timed(g, FVIB_K_IR_CORRECT, [&] { return launch_gauge(g->ncell, p, g->sc, g->stream); })))
-      return rc;
     g->last_iters = sweeps;
     *cg_total = 0;
     *ir_total = sweeps;
@@ -768,18 +801,22 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
     return rc;
   int cg = 0, ir = 0;
   int last = g->last_iters;
+  // the projection is queued behind each convergence check of the solve
+  const std::function<int()> project = [&]() {
+    return timed(g, FVIB_K_PROJECT, [&] {
+      return launch_project<T>(G, g->P64, (const T* const*)us, out->p, uo, g->red(), g->sc,
+                               g->stream);
+    });
+  };
+  const bool fdm = g->d.solver == FVIB_SOLVER_FDM;
   if ((rc = poisson_solve(g, g->b, out->p, g->d.poisson_tol, &last, &cg, &ir, true, false,
-                          in->p)))
+                          in->p, fdm ? &project : nullptr)))
     return rc;
   g->last_iters = last;
   if (g->defer && g->sch->status == FVIB_ENOCONV)
     return fail(g, FVIB_ENOCONV,
                 "Poisson solve did not reach poisson_tol" + describe_solve(g, g->d.poisson_tol));
-  if ((rc = timed(g, FVIB_K_PROJECT, [&] {
-         return launch_project<T>(G, g->P64, (const T* const*)us, out->p, uo, g->red(), g->sc,
-                                  g->stream);
-       })))
-    return rc;
+  if (!fdm && (rc = project())) return rc;
   if (g->has_body) {
     rc = timed(g, FVIB_K_IB, [&] {
       return launch_loads_body<T>(g->ib, ib, in->body, out->body, in->kc, g->sc, g->stream);
@@ -861,14 +898,19 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
   const bool warm = bi->mu != nullptr && g->d.solver == FVIB_SOLVER_FDM;
   double* mu = bi->mu ? bi->mu : g->mu;
   if (!warm) FVIB_HIP(hipMemsetAsync(mu, 0, g->ncell * sizeof(double), g->stream));
-  if ((rc = poisson_solve(g, g->b, mu, -1.0, &g->last_iters_adj, &cg, &ir, false, warm)))
+  // ustar_bar (a pure function of mu) is queued behind each convergence check
+  const std::function<int()> ustar = [&]() {
+    return timed(g, FVIB_K_ADJOINT,
+                 [&] { return launch_adj_ustar<T>(G, g->P64, ub1, mu, ib, usb, g->sc, g->stream); });
+  };
+  const bool fdm = g->d.solver == FVIB_SOLVER_FDM;
+  if ((rc = poisson_solve(g, g->b, mu, -1.0, &g->last_iters_adj, &cg, &ir, false, warm, nullptr,
+                          fdm ? &ustar : nullptr)))
     return rc;
   if (g->defer && g->sch->status == FVIB_ENOCONV)
     return fail(g, FVIB_ENOCONV, "adjoint Poisson solve did not converge" +
                                      describe_solve(g, g->sch->tol_dev));
-  if ((rc = timed(g, FVIB_K_ADJOINT,
-                  [&] { return launch_adj_ustar<T>(G, g->P64, ub1, mu, ib, usb, g->sc, g->stream); })))
-    return rc;
+  if (!fdm && (rc = ustar())) return rc;
   if (g->has_body && bi->body) {
     rc = timed(g, FVIB_K_IB, [&] {
       return launch_adj_ubody<T>(G, g->P64, g->ib, ub1, mu, ib, bi->body, g->sc, g->stream);
@@ -931,6 +973,8 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
   g->d = *desc;
   for (int a = 0; a < 3; ++a) g->d.faces[a] = nullptr;
   g->stream = (hipStream_t)hip_stream;
+  if (hipEventCreateWithFlags(&g->check_ev, hipEventDisableTiming) != hipSuccess)
+    g->check_ev = nullptr;
   g->dim = desc->dim;
   g->prec = desc->precision;
   g->ncell = 1;
