@@ -445,6 +445,86 @@ k_project(Geo<T> G, PGeo<double> P, Tiling tl, const T* __restrict__ s0,
   block_partials<1, 0>(v, red.partial);
 }
 
+// 3D projection as a column march: each thread owns an (x, y) column of a
+// unit and walks up its z-chunk keeping p at k - 1, k, k + 1 and the w
+// faces below and above the cell in registers (the next plane prefetched),
+// so p and u* cross HBM once per chunk; the x and y neighbours of a plane
+// are shared with the adjacent columns through the caches.  Same arithmetic
+// and term order as k_project.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_project_col(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__ s0,
+              const T* __restrict__ s1, const T* __restrict__ s2, const double* __restrict__ p,
+              T* __restrict__ o0, T* __restrict__ o1, T* __restrict__ o2, RedBuf red) {
+  const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
+  const int64_t sxy = (int64_t)nx * ny;
+  const double f = P.dt_over_rho;
+  double mx = 0.0;
+  const int lx = threadIdx.x & (kTileX - 1), ly = threadIdx.x / kTileX;
+  for (int u = xcd_block(blockIdx.x, gridDim.x); u < ct.nunits; u += gridDim.x) {
+    const int tx = u % ct.ntx, ty = (u / ct.ntx) % ct.nty, zc = u / (ct.ntx * ct.nty);
+    const int i = tx * kTileX + lx, j = ty * kTileY + ly;
+    if (i >= nx || j >= ny) continue;
+    const int k0 = zc * ct.zchunk, k1 = min(k0 + ct.zchunk, nz);
+    // column constants: face extents, neighbours and coefficients along x, y
+    const int ex0 = G.ext[0][0], ex1 = G.ext[0][1];       // u faces
+    const int ey0 = G.ext[1][0], ey1 = G.ext[1][1];       // v faces
+    const int ez0 = G.ext[2][0], ez1 = G.ext[2][1];       // w faces
+    const int iH = (G.per[0] && i + 1 == nx) ? 0 : i + 1;
+    const int jH = (G.per[1] && j + 1 == ny) ? 0 : j + 1;
+    const int64_t cC = (int64_t)j * nx + i;
+    const int64_t cW = (int64_t)j * nx + nb_lo(i, nx, P.per[0]);
+    const int64_t cE = (int64_t)j * nx + nb_hi(i, nx, P.per[0]);
+    const int64_t cS = (int64_t)nb_lo(j, ny, P.per[1]) * nx + i;
+    const int64_t cN = (int64_t)nb_hi(j, ny, P.per[1]) * nx + i;
+    const int64_t uL = (int64_t)j * ex0 + i, uH = (int64_t)j * ex0 + iH;
+    const int64_t vL = (int64_t)j * ey0 + i, vH = (int64_t)jH * ey0 + i;
+    const int64_t wL = (int64_t)j * ez0 + i;
+    const int64_t su = (int64_t)ex0 * ex1, sv = (int64_t)ey0 * ey1, sw = (int64_t)ez0 * ez1;
+    const double dx = P.dx[0][i], dy = P.dx[1][j];
+    const double kxl = P.kf[0][i], kxh = P.kf[0][i + 1];
+    const double kyl = P.kf[1][j], kyh = P.kf[1][j + 1];
+    const double ivxy = (double)P.iv[0][i] * (double)P.iv[1][j];
+    const bool xlast = !G.per[0] && i + 1 == nx, ylast = !G.per[1] && j + 1 == ny;
+    auto pz = [&](int k) { return p[(int64_t)k * sxy + cC]; };
+    double pm = pz(nb_lo(k0, nz, P.per[2])), pc = pz(k0);
+    double wlo = (double)s2[(int64_t)k0 * sw + wL];
+    for (int k = k0; k < k1; ++k) {
+      const int kn = nb_hi(k, nz, P.per[2]);
+      const int kH = (G.per[2] && k + 1 == nz) ? 0 : k + 1;
+      // plane loads (the z neighbours above come first)
+      const double pp = pz(kn);
+      const double whi = (double)s2[(int64_t)kH * sw + wL];
+      const int64_t pk = (int64_t)k * sxy;
+      const double pw = p[pk + cW], pe = p[pk + cE], ps = p[pk + cS], pn = p[pk + cN];
+      const double ulo = (double)s0[(int64_t)k * su + uL], uhi = (double)s0[(int64_t)k * su + uH];
+      const double vlo = (double)s1[(int64_t)k * sv + vL], vhi = (double)s1[(int64_t)k * sv + vH];
+      const double dz = P.dx[2][k], kzl = P.kf[2][k], kzh = P.kf[2][k + 1];
+      const double ivol = ivxy * (double)P.iv[2][k];
+      // faces of a bounded boundary have kf = 0 and keep u*
+      const double lx_ = ulo - f * (pc - pw) * kxl, hx = uhi - f * (pe - pc) * kxh;
+      const double ly_ = vlo - f * (pc - ps) * kyl, hy = vhi - f * (pn - pc) * kyh;
+      const double lz = wlo - f * (pc - pm) * kzl, hz = whi - f * (pp - pc) * kzh;
+      o0[(int64_t)k * su + uL] = (T)lx_;
+      if (xlast) o0[(int64_t)k * su + uH] = (T)hx;
+      o1[(int64_t)k * sv + vL] = (T)ly_;
+      if (ylast) o1[(int64_t)k * sv + vH] = (T)hy;
+      o2[(int64_t)k * sw + wL] = (T)lz;
+      if (!G.per[2] && k + 1 == nz) o2[(int64_t)kH * sw + wL] = (T)hz;
+      double div = 0.0;
+      div += (hx - lx_) * (dy * dz);
+      div += (hy - ly_) * (dx * dz);
+      div += (hz - lz) * (dx * dy);
+      mx = fmax(mx, fabs(div) * ivol);
+      pm = pc;
+      pc = pp;
+      wlo = whi;
+    }
+  }
+  double v[1] = {mx};
+  block_partials<1, 0>(v, red.partial);
+}
+
 // ---------------------------------------------------------- apply A
 __global__ void __launch_bounds__(kBlock)
 k_apply_A(PGeo<double> P, Tiling tl, const double* __restrict__ x, double* __restrict__ y) {
@@ -560,9 +640,14 @@ int launch_project(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
   if (G.dim == 2)
     launch_kernel((k_project<T, 2>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, us[0],
                        us[1], us[2], p, out[0], out[1], out[2], red, sc);
-  else
-    launch_kernel((k_project<T, 3>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, us[0],
-                       us[1], us[2], p, out[0], out[1], out[2], red, sc);
+  else {
+    const ColTiling ct = make_col_tiling(G.n[0], G.n[1], G.n[2]);
+    launch_kernel((k_project_col<T>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct, us[0],
+                  us[1], us[2], p, out[0], out[1], out[2], red);
+    FVIB_HIP(hipGetLastError());
+    FVIB_HIP((launch_finish<1, 0>(red.partial, ct.nblocks, sc, FinDivMax{}, s)));
+    return FVIB_OK;
+  }
   FVIB_HIP(hipGetLastError());
   FVIB_HIP((launch_finish<1, 0>(red.partial, tl.nblocks, sc, FinDivMax{}, s)));
   return FVIB_OK;
