@@ -157,6 +157,34 @@ def cpu_baseline(w, budget_s):
                       f"own autograd adjoint is not timed"}
 
 
+TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "hbm_traffic_channel_192x128x160_fp32.md")
+
+
+def measured_traffic(kernel_class):
+    """HBM bytes per launch of a kernel class from the committed counter
+    summary (FETCH_SIZE, WRITE_SIZE, calibrated); None if absent or if a
+    source file of the class changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        entry = json.loads(block).get(kernel_class)
+    except (OSError, IndexError, ValueError):
+        return None
+    if not entry:
+        return None
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2505_23940_amd", "csrc")
+    for name, digest in entry["sources"].items():
+        try:
+            cur = hashlib.sha256(open(os.path.join(csrc, name), "rb").read()).hexdigest()[:16]
+        except OSError:
+            return None
+        if cur != digest:
+            return None
+    return entry["traffic_bytes"]
+
+
 def dominant(table, w, mixed):
     """Kernel class with a cost model and the largest total time."""
     cost = kernel_cost(w.dim, 4 if mixed else 8, mixed, w.n)
@@ -237,6 +265,8 @@ def main():
     # launches of speculative refinement sweeps that found the solve
     # converged return at once; they are left out of the average above
     rl["skipped_launches"] = skipped[dom][1]
+    if a.workload == "channel" and mixed:
+        rl["traffic"] = measured_traffic(dom)
     rl["timed_launches"] = timing[dom][1]
     rl["sampled_every"] = TIMING_EVERY
     value = ncell * a.steps / el / 1e6
