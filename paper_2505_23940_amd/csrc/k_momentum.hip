@@ -20,7 +20,7 @@ namespace fvib {
 // R of component C at face (i, j, k).  `L(c, di, dj, dk)` returns component
 // c at the offset (di, dj, dk) from (i, j, k), boundary rules applied (each
 // offset is -1, 0 or +1 per axis).
-template <int C, int DIM, typename T, typename Load, typename ML>
+template <int C, int DIM, bool UPW, typename T, typename Load, typename ML>
 __device__ __forceinline__ T momentum_rhs(const Geo<T>& G, const Load& L, const ML& M, T fb) {
   const T q0 = L(C, 0, 0, 0);
   const Met4<T> fc = M.mf(C, 0);
@@ -33,7 +33,7 @@ __device__ __forceinline__ T momentum_rhs(const Geo<T>& G, const Load& L, const 
     const T Qlo = T(0.5) * (qm + q0);
     const T Qhi = T(0.5) * (q0 + qp);
     T Flo, Fhi;
-    if (G.upwind) {
+    if constexpr (UPW) {
       Flo = Qlo * (Qlo > T(0) ? qm : (Qlo < T(0) ? q0 : T(0)));
       Fhi = Qhi * (Qhi > T(0) ? q0 : (Qhi < T(0) ? qp : T(0)));
     } else {
@@ -62,7 +62,7 @@ __device__ __forceinline__ T momentum_rhs(const Geo<T>& G, const Load& L, const 
     const T V0 = (T(1) - wc) * a00 + wc * a01;
     const T V1 = (T(1) - wc) * a10 + wc * a11;
     T F0, F1;
-    if (G.upwind) {
+    if constexpr (UPW) {
       F0 = V0 * (V0 > T(0) ? cm : (V0 < T(0) ? q0 : T(0)));
       F1 = V1 * (V1 > T(0) ? q0 : (V1 < T(0) ? cp : T(0)));
     } else {
@@ -99,18 +99,20 @@ __device__ __forceinline__ int forced(const IbView<T>& ib, int i, int j, int* li
 // Predictor (MODE 0) or right-hand side (MODE 1) of component C at face
 // (i, j, k):  u* = u + dt (R + f),  f = eps [ -R + (u_s - u) / dt ], i.e.
 // u* = u + dt R off the body and u* = u_s on forced faces.
-template <int C, int DIM, int MODE, typename T, typename Load, typename ML>
+// UPW: upwind convection; IBA: an immersed body is active (else no face
+// is forced and the class lookups are compiled out).
+template <int C, int DIM, int MODE, bool UPW, bool IBA, typename T, typename Load, typename ML>
 __device__ __forceinline__ void predict_face(const Geo<T>& G, const Load& L, const ML& M, T fbv,
                                              T* out, const IbView<T>& ib, int i, int j, int k) {
   if (C >= DIM || !evolved<C>(G, i, j, k)) return;
-  const T R = momentum_rhs<C, DIM, T>(G, L, M, fbv);
+  const T R = momentum_rhs<C, DIM, UPW, T>(G, L, M, fbv);
   const int64_t id = fidx(G.ext[C], i, j, k);
   if (MODE == 1) {
     out[id] = R;
     return;
   }
   const T un = L(C, 0, 0, 0);
-  if constexpr (C < 2) {
+  if constexpr (C < 2 && IBA) {
     int li = 0;
     if (forced<C>(ib, i, j, &li)) {
       // Eq. 5 substituted into Eq. 4: the forced face takes the target
@@ -248,7 +250,7 @@ __device__ __forceinline__ void fill_plane(const Geo<T>& G, const T* const* u,
 
 // MODE 0: predictor (writes u*, and the forcing on forced faces).
 // MODE 1: right-hand side only (writes R on advanced faces).
-template <typename T, int DIM, int MODE>
+template <typename T, int DIM, int MODE, bool UPW, bool IBA>
 __global__ void __launch_bounds__(kBlock)
 k_predictor(Geo<T> G, int ntx, int nty, int nzc, const T* __restrict__ u0,
             const T* __restrict__ u1, const T* __restrict__ u2, const T* __restrict__ fb0,
@@ -272,6 +274,14 @@ k_predictor(Geo<T> G, int ntx, int nty, int nzc, const T* __restrict__ u0,
   load_tile_met<DIM>(G, TM, i0, j0, k0);
   PlaneHalo<T, DIM> Hh;
   plane_halo_init<DIM>(G, Hh, i0, j0);
+  // body force of this thread's faces, fetched one plane ahead
+  T fbn[3] = {T(0), T(0), T(0)};
+  auto load_fb = [&](int kk) {
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+      if (inside && fbp[c]) fbn[c] = fbp[c][fidx(G.ext[c], i, j, kk)];
+  };
+  load_fb(k0);
   PlaneRegs<T, DIM> nxt;
   if (DIM == 3) {
     fill_plane<DIM>(G, u, Hh, R, ring_slot(k0 - 1), k0 - 1);
@@ -286,20 +296,17 @@ k_predictor(Geo<T> G, int ntx, int nty, int nzc, const T* __restrict__ u0,
     const int sc = (DIM == 3) ? ring_slot(k) : 0;
     const int sm = (DIM == 3) ? ring_slot(k - 1) : 0;
     const int sp = (DIM == 3) ? ring_slot(k + 1) : 0;
+    T fbv[3] = {fbn[0], fbn[1], fbn[2]};
+    if (k + 1 < k1) load_fb(k + 1);
     if (inside) {
       auto L = [&](int c, int di, int dj, int dk) -> T {
         const int sl = dk < 0 ? sm : (dk > 0 ? sp : sc);
         return R.v[c][sl][ly + 1 + dj][lx + 1 + di];
       };
-      // body force of the three faces first: its loads overlap the stencil
-      T fbv[3] = {T(0), T(0), T(0)};
-#pragma unroll
-      for (int c = 0; c < DIM; ++c)
-        if (fbp[c]) fbv[c] = fbp[c][fidx(G.ext[c], i, j, k)];
       const MetLds<T> M{&TM, {lx + 1, ly + 1, k - k0 + 1}};
-      predict_face<0, DIM, MODE, T>(G, L, M, fbv[0], o0, ib, i, j, k);
-      predict_face<1, DIM, MODE, T>(G, L, M, fbv[1], o1, ib, i, j, k);
-      predict_face<2, DIM, MODE, T>(G, L, M, fbv[2], o2, ib, i, j, k);
+      predict_face<0, DIM, MODE, UPW, IBA, T>(G, L, M, fbv[0], o0, ib, i, j, k);
+      predict_face<1, DIM, MODE, UPW, IBA, T>(G, L, M, fbv[1], o1, ib, i, j, k);
+      predict_face<2, DIM, MODE, UPW, IBA, T>(G, L, M, fbv[2], o2, ib, i, j, k);
     }
     if (DIM == 3 && k + 1 < k1) {
       __syncthreads();
@@ -418,15 +425,24 @@ int launch_predictor(const Geo<T>& G, const T* const u[3], const T* const fb[3],
   int nb = ntx * nty * nzc;
   nb = (nb + kXcds - 1) / kXcds * kXcds;
   dim3 grid(nb), block(kBlock);
+#define FVIB_PRED4(D, M, U, I)                                                                 \
+  launch_kernel((k_predictor<T, D, M, U, I>), grid, block, 0, s, G, ntx, nty, nzc, u[0], u[1],  \
+                u[2], fb[0], fb[1], fb[2], out[0], out[1], out[2], ib)
 #define FVIB_PRED(D, M)                                                                        \
-  launch_kernel((k_predictor<T, D, M>), grid, block, 0, s, G, ntx, nty, nzc, u[0], u[1], \
-                     u[2], fb[0], fb[1], fb[2], out[0], out[1], out[2], ib)
+  do {                                                                                         \
+    if (G.upwind) {                                                                            \
+      if (ib.active) FVIB_PRED4(D, M, true, true); else FVIB_PRED4(D, M, true, false);        \
+    } else {                                                                                   \
+      if (ib.active) FVIB_PRED4(D, M, false, true); else FVIB_PRED4(D, M, false, false);      \
+    }                                                                                          \
+  } while (0)
   if (G.dim == 2) {
     if (mode == 0) FVIB_PRED(2, 0); else FVIB_PRED(2, 1);
   } else {
     if (mode == 0) FVIB_PRED(3, 0); else FVIB_PRED(3, 1);
   }
 #undef FVIB_PRED
+#undef FVIB_PRED4
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
