@@ -256,6 +256,16 @@ struct MetLds {
   __device__ __forceinline__ Met4<T> mf(int a, int off) const { return M->f[a][o[a] + off]; }
 };
 
+// As MetLds with the LDS index clamped to the tile's table (for a face one
+// step past the tile, whose out-of-table entries only multiply zero terms).
+template <typename T>
+struct MetLdsClamp {
+  const TileMet<T>* M;
+  int o[3];
+  __device__ __forceinline__ Met4<T> mc(int a, int off) const { return M->c[a][min(o[a] + off, kMX - 1)]; }
+  __device__ __forceinline__ Met4<T> mf(int a, int off) const { return M->f[a][min(o[a] + off, kMX - 1)]; }
+};
+
 template <typename T>
 struct MetGlobal {
   const Geo<T>* G;

@@ -638,8 +638,8 @@ __device__ __forceinline__ T adj_gather(const Geo<T>& G, const RBL& RB, const UL
 
 // Cell-based transposed momentum stencil with LDS halo planes of u^n and
 // Rbar (same tiling and z-march as the predictor).  Each thread writes the
-// low face of its cell for every component; faces on the high boundary of
-// a bounded own axis are left to k_adj_momentum_plane.
+// low face of its cell for every component, and the thread of the last cell
+// of a bounded axis also the high boundary face of that axis' component.
 template <typename T, int DIM>
 struct AdjRings {
   T u[DIM][3][kLY][kLX];
@@ -888,6 +888,34 @@ k_adj_momentum_lds(AdjCtx<T> X, int ntx, int nty, int nzc, T* __restrict__ ub0,
       FVIB_ADJ_COMP(1)
       FVIB_ADJ_COMP(2)
 #undef FVIB_ADJ_COMP
+      // The face on the high boundary of a bounded own axis (index n[C]) is
+      // gathered by the thread of the last cell.  Its stencil reaches one
+      // step past the tile only for values that multiply its own zero Rbar
+      // (a boundary face is not advanced) or the zero Rbar outside, so
+      // those indices are clamped into the tile.
+#define FVIB_ADJ_HI(CC, SX, SY, SZ)                                                     \
+      {                                                                                 \
+        auto Uh = [&](int c, int di, int dj, int dk) -> T {                             \
+          const int dd = dk + SZ;                                                       \
+          const int sl = dd < 0 ? sm : (dd > 0 ? sp : sc);                              \
+          return S.u[c][sl][min(ly + 1 + dj + SY, kLY - 1)][min(lx + 1 + di + SX, kLX - 1)]; \
+        };                                                                              \
+        auto Rh = [&](int c, int di, int dj, int dk) -> T {                             \
+          const int dd = dk + SZ;                                                       \
+          const int sl = dd < 0 ? sm : (dd > 0 ? sp : sc);                              \
+          return S.r[c][sl][min(ly + 1 + dj + SY, kLY - 1)][min(lx + 1 + di + SX, kLX - 1)]; \
+        };                                                                              \
+        const MetLdsClamp<T> Mh{&TM, {lx + 1 + SX, ly + 1 + SY, k - k0 + 1 + SZ}};      \
+        const int Jh[3] = {i + SX, j + SY, k + SZ};                                     \
+        ubar[CC][fidx(G.ext[CC], Jh[0], Jh[1], Jh[2])] =                                \
+            G.dt * adj_gather<CC, DIM, UPW, T>(G, Rh, Uh, Mh, Jh);                     \
+      }
+      if (!G.per[0] && i == G.n[0] - 1) FVIB_ADJ_HI(0, 1, 0, 0)
+      if (!G.per[1] && j == G.n[1] - 1) FVIB_ADJ_HI(1, 0, 1, 0)
+      if constexpr (DIM == 3) {
+        if (!G.per[2] && k == G.n[2] - 1) FVIB_ADJ_HI(2, 0, 0, 1)
+      }
+#undef FVIB_ADJ_HI
     }
     if (DIM == 3 && k + 1 < k1) {
       __syncthreads();
@@ -897,33 +925,6 @@ k_adj_momentum_lds(AdjCtx<T> X, int ntx, int nty, int nzc, T* __restrict__ ub0,
   }
 }
 
-// Faces on the high boundary of a bounded own axis (face index n[C]).
-template <int C, int DIM, bool UPW, typename T>
-__global__ void __launch_bounds__(kBlock)
-k_adj_momentum_plane(AdjCtx<T> X, T* __restrict__ ubar) {
-  const Geo<T>& G = X.G;
-  int64_t count = 1;
-  for (int a = 0; a < 3; ++a)
-    if (a != C) count *= G.n[a];
-  for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < count;
-       r += (int64_t)gridDim.x * kBlock) {
-    int J[3];
-    int64_t rem = r;
-    for (int a = 0; a < 3; ++a) {
-      if (a == C) { J[a] = G.n[C]; continue; }
-      J[a] = (int)(rem % G.n[a]);
-      rem /= G.n[a];
-    }
-    auto Ug = [&](int c, int di, int dj, int dk) -> T {
-      return ldu_c<DIM>(X, c, J[0] + di, J[1] + dj, J[2] + dk);
-    };
-    auto Rg = [&](int c, int di, int dj, int dk) -> T {
-      return rbar_c<DIM>(X, c, J[0] + di, J[1] + dj, J[2] + dk);
-    };
-    const MetGlobal<T> M{&G, {J[0], J[1], J[2]}};
-    ubar[fidx(G.ext[C], J[0], J[1], J[2])] = G.dt * adj_gather<C, DIM, UPW, T>(G, Rg, Ug, M, J);
-  }
-}
 
 // ============================================================== launchers
 template <typename T>
@@ -1040,22 +1041,6 @@ static int launch_adj_momentum_t(const AdjCtx<T>& X, T* ubar[3], T* fbbar[3], hi
     launch_kernel((k_adj_momentum_lds<T, 3, UPW>), dim3(nb), dim3(kBlock), 0, s, X, ntx, nty,
                        nzc, ubar[0], ubar[1], ubar[2], fbbar[0], fbbar[1], fbbar[2]);
   FVIB_HIP(hipGetLastError());
-  for (int c = 0; c < G.dim; ++c) {
-    if (G.per[c]) continue;
-    int64_t count = 1;
-    for (int a = 0; a < 3; ++a)
-      if (a != c) count *= G.n[a];
-    const dim3 gr(nblk(count)), bl(kBlock);
-    if (G.dim == 2) {
-      if (c == 0) launch_kernel((k_adj_momentum_plane<0, 2, UPW, T>), gr, bl, 0, s, X, ubar[0]);
-      else launch_kernel((k_adj_momentum_plane<1, 2, UPW, T>), gr, bl, 0, s, X, ubar[1]);
-    } else {
-      if (c == 0) launch_kernel((k_adj_momentum_plane<0, 3, UPW, T>), gr, bl, 0, s, X, ubar[0]);
-      else if (c == 1) launch_kernel((k_adj_momentum_plane<1, 3, UPW, T>), gr, bl, 0, s, X, ubar[1]);
-      else launch_kernel((k_adj_momentum_plane<2, 3, UPW, T>), gr, bl, 0, s, X, ubar[2]);
-    }
-    FVIB_HIP(hipGetLastError());
-  }
   return FVIB_OK;
 }
 
