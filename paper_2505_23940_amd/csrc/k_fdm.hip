@@ -703,8 +703,12 @@ k_axis_sym(const float* __restrict__ X, float* __restrict__ Y, const float* __re
   constexpr int XP = (H * CV + kBlock - 1) / kBlock;
   typedef __attribute__((ext_vector_type(4))) float f4_t;
   typedef typename Mfma<float>::acc_t acc_t;
-  __shared__ __attribute__((aligned(16))) float S0[NC * LDK];    // even operand, line-major
-  __shared__ __attribute__((aligned(16))) float S1[NC * LDK];    // odd operand
+  // even and odd operands (line-major), later the block's output rows
+  constexpr int LDY = NC + 4;                    // output row stride (floats)
+  constexpr int SMN = (2 * NC * LDK > N * LDY) ? 2 * NC * LDK : N * LDY;
+  __shared__ __attribute__((aligned(16))) float SM[SMN];
+  float* S0 = SM;
+  float* S1 = SM + NC * LDK;
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -777,7 +781,9 @@ k_axis_sym(const float* __restrict__ X, float* __restrict__ Y, const float* __re
         }
     }
   }
-  float* yb = Y + o0 * (int64_t)N * inner + i0;
+  // output rows through LDS, so each row of the block (NC lines, 128 bytes)
+  // leaves as whole 16-byte vectors
+  __syncthreads();                               // operands fully consumed
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     const int tile = w + 4 * mt;
@@ -789,9 +795,21 @@ k_axis_sym(const float* __restrict__ X, float* __restrict__ Y, const float* __re
         const int m = 16 * tile + Mfma<float>::row(lane, v);
         const float a = ce[mt][tt][v], b = co[mt][tt][v];
         const int row0 = m, row1 = FWD ? H + m : N - 1 - m;
-        __builtin_nontemporal_store(FWD ? a : a + b, yb + (int64_t)row0 * inner + 16 * tt + r);
-        __builtin_nontemporal_store(FWD ? b : a - b, yb + (int64_t)row1 * inner + 16 * tt + r);
+        SM[row0 * LDY + 16 * tt + r] = FWD ? a : a + b;
+        SM[row1 * LDY + 16 * tt + r] = FWD ? b : a - b;
       }
+  }
+  __syncthreads();
+  float* yb = Y + o0 * (int64_t)N * inner + i0;
+  constexpr int OV = N * CV;                     // float4 of the block's output
+#pragma unroll
+  for (int u = 0; u < (OV + kBlock - 1) / kBlock; ++u) {
+    const int e = t + u * kBlock;
+    if (OV % kBlock == 0 || e < OV) {
+      const int row = e / CV, c = e - row * CV;
+      __builtin_nontemporal_store(*reinterpret_cast<const f4_t*>(SM + row * LDY + 4 * c),
+                                  reinterpret_cast<f4_t*>(yb + (int64_t)row * inner + 4 * c));
+    }
   }
 }
 
