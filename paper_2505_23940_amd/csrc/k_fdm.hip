@@ -694,7 +694,7 @@ k_axis_sym(const float* __restrict__ X, float* __restrict__ Y, const float* __re
   if (stop && *stop) return;
   static_assert(H % 16 == 0 && H <= 128, "half operator rows must fit the registers");
   constexpr int N = 2 * H;
-  constexpr int NT = 2, NC = 32;                 // lines per block
+  constexpr int NT = 2, NC = 32;                 // lines per tile
   constexpr int TH = H / 16;                     // row tiles per half
   constexpr int MT = (TH + 3) / 4;               // per wave and half
   constexpr int G = H / 16;                      // contraction groups
@@ -703,7 +703,7 @@ k_axis_sym(const float* __restrict__ X, float* __restrict__ Y, const float* __re
   constexpr int XP = (H * CV + kBlock - 1) / kBlock;
   typedef __attribute__((ext_vector_type(4))) float f4_t;
   typedef typename Mfma<float>::acc_t acc_t;
-  // even and odd operands (line-major), later the block's output rows
+  // even and odd operands (line-major), later the tile's output rows
   constexpr int LDY = NC + 4;                    // output row stride (floats)
   constexpr int SMN = (2 * NC * LDK > N * LDY) ? 2 * NC * LDK : N * LDY;
   __shared__ __attribute__((aligned(16))) float SM[SMN];
@@ -713,22 +713,27 @@ k_axis_sym(const float* __restrict__ X, float* __restrict__ Y, const float* __re
   const int lane = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int q = lane >> 4, r = lane & 15;
-  const int64_t n0 = (int64_t)blockIdx.x * NC;
-  const int64_t o0 = n0 / inner;
-  const int64_t i0 = n0 - o0 * inner;
-  const float* xb = X + o0 * (int64_t)N * inner + i0;
-  // index rows k and N-1-k (forward) or k and H+k (inverse) of the lines
+  const int64_t ntiles = ncols / NC;
+  // index rows k and N-1-k (forward) or k and H+k (inverse) of a tile's lines
   f4_t ra[XP], rb[XP];
+  auto load_tile = [&](int64_t tile_id) {
+    const int64_t n0 = tile_id * NC;
+    const int64_t o0 = n0 / inner;
+    const float* xb = X + o0 * (int64_t)N * inner + (n0 - o0 * inner);
 #pragma unroll
-  for (int u = 0; u < XP; ++u) {
-    const int e = t + u * kBlock;
-    if ((H * CV) % kBlock == 0 || e < H * CV) {
-      const int k = e / CV, c = e - k * CV;
-      const int k2 = FWD ? N - 1 - k : H + k;
-      ra[u] = *reinterpret_cast<const f4_t*>(xb + (int64_t)k * inner + 4 * c);
-      rb[u] = *reinterpret_cast<const f4_t*>(xb + (int64_t)k2 * inner + 4 * c);
+    for (int u = 0; u < XP; ++u) {
+      const int e = t + u * kBlock;
+      if ((H * CV) % kBlock == 0 || e < H * CV) {
+        const int k = e / CV, c = e - k * CV;
+        const int k2 = FWD ? N - 1 - k : H + k;
+        ra[u] = *reinterpret_cast<const f4_t*>(xb + (int64_t)k * inner + 4 * c);
+        rb[u] = *reinterpret_cast<const f4_t*>(xb + (int64_t)k2 * inner + 4 * c);
+      }
     }
-  }
+  };
+  int64_t tile_id = blockIdx.x;
+  if (tile_id >= ntiles) return;
+  load_tile(tile_id);
   f4_t ae[MT][G], ao[MT][G];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
@@ -740,76 +745,84 @@ k_axis_sym(const float* __restrict__ X, float* __restrict__ Y, const float* __re
       ao[mt][g] = tile < TH ? *reinterpret_cast<const f4_t*>(Ao + off) : f4_t{0.f, 0.f, 0.f, 0.f};
     }
   }
+  // persistent loop over tiles: the next tile's lines are in flight while
+  // this one is contracted and stored
+  for (; tile_id < ntiles; tile_id += gridDim.x) {
 #pragma unroll
-  for (int u = 0; u < XP; ++u) {
-    const int e = t + u * kBlock;
-    if ((H * CV) % kBlock == 0 || e < H * CV) {
-      const int k = e / CV, c = e - k * CV;
+    for (int u = 0; u < XP; ++u) {
+      const int e = t + u * kBlock;
+      if ((H * CV) % kBlock == 0 || e < H * CV) {
+        const int k = e / CV, c = e - k * CV;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        S0[(4 * c + j) * LDK + k] = FWD ? ra[u][j] + rb[u][j] : ra[u][j];
-        S1[(4 * c + j) * LDK + k] = FWD ? ra[u][j] - rb[u][j] : rb[u][j];
+        for (int j = 0; j < 4; ++j) {
+          S0[(4 * c + j) * LDK + k] = FWD ? ra[u][j] + rb[u][j] : ra[u][j];
+          S1[(4 * c + j) * LDK + k] = FWD ? ra[u][j] - rb[u][j] : rb[u][j];
+        }
       }
     }
-  }
-  __syncthreads();
-  acc_t ce[MT][NT], co[MT][NT];
+    __syncthreads();
+    if (tile_id + gridDim.x < ntiles) load_tile(tile_id + gridDim.x);
+    acc_t ce[MT][NT], co[MT][NT];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int tt = 0; tt < NT; ++tt) {
-      ce[mt][tt] = acc_t{0.f, 0.f, 0.f, 0.f};
-      co[mt][tt] = acc_t{0.f, 0.f, 0.f, 0.f};
+      for (int tt = 0; tt < NT; ++tt) {
+        ce[mt][tt] = acc_t{0.f, 0.f, 0.f, 0.f};
+        co[mt][tt] = acc_t{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      f4_t xe[NT], xo[NT];
+#pragma unroll
+      for (int tt = 0; tt < NT; ++tt) {
+        xe[tt] = *reinterpret_cast<const f4_t*>(S0 + (16 * tt + r) * LDK + 16 * g + 4 * q);
+        xo[tt] = *reinterpret_cast<const f4_t*>(S1 + (16 * tt + r) * LDK + 16 * g + 4 * q);
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        if (w + 4 * mt >= TH) continue;           // wave-uniform
+#pragma unroll
+        for (int sidx = 0; sidx < 4; ++sidx)
+#pragma unroll
+          for (int tt = 0; tt < NT; ++tt) {
+            ce[mt][tt] = Mfma<float>::op(ae[mt][g][sidx], xe[tt][sidx], ce[mt][tt]);
+            co[mt][tt] = Mfma<float>::op(ao[mt][g][sidx], xo[tt][sidx], co[mt][tt]);
+          }
+      }
     }
-#pragma unroll
-  for (int g = 0; g < G; ++g) {
-    f4_t xe[NT], xo[NT];
-#pragma unroll
-    for (int tt = 0; tt < NT; ++tt) {
-      xe[tt] = *reinterpret_cast<const f4_t*>(S0 + (16 * tt + r) * LDK + 16 * g + 4 * q);
-      xo[tt] = *reinterpret_cast<const f4_t*>(S1 + (16 * tt + r) * LDK + 16 * g + 4 * q);
-    }
+    // output rows through LDS, so each row of the tile (NC lines, 128
+    // bytes) leaves as whole 16-byte vectors
+    __syncthreads();                             // operands fully consumed
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-      if (w + 4 * mt >= TH) continue;             // wave-uniform
+      const int tile = w + 4 * mt;
+      if (tile >= TH) continue;
 #pragma unroll
-      for (int sidx = 0; sidx < 4; ++sidx)
+      for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-        for (int tt = 0; tt < NT; ++tt) {
-          ce[mt][tt] = Mfma<float>::op(ae[mt][g][sidx], xe[tt][sidx], ce[mt][tt]);
-          co[mt][tt] = Mfma<float>::op(ao[mt][g][sidx], xo[tt][sidx], co[mt][tt]);
+        for (int v = 0; v < 4; ++v) {
+          const int m = 16 * tile + Mfma<float>::row(lane, v);
+          const float a = ce[mt][tt][v], b = co[mt][tt][v];
+          const int row0 = m, row1 = FWD ? H + m : N - 1 - m;
+          SM[row0 * LDY + 16 * tt + r] = FWD ? a : a + b;
+          SM[row1 * LDY + 16 * tt + r] = FWD ? b : a - b;
         }
     }
-  }
-  // output rows through LDS, so each row of the block (NC lines, 128 bytes)
-  // leaves as whole 16-byte vectors
-  __syncthreads();                               // operands fully consumed
+    __syncthreads();
+    const int64_t n0 = tile_id * NC;
+    const int64_t o0 = n0 / inner;
+    float* yb = Y + o0 * (int64_t)N * inner + (n0 - o0 * inner);
+    constexpr int OV = N * CV;                   // float4 of the tile's output
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
-    const int tile = w + 4 * mt;
-    if (tile >= TH) continue;
-#pragma unroll
-    for (int tt = 0; tt < NT; ++tt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int m = 16 * tile + Mfma<float>::row(lane, v);
-        const float a = ce[mt][tt][v], b = co[mt][tt][v];
-        const int row0 = m, row1 = FWD ? H + m : N - 1 - m;
-        SM[row0 * LDY + 16 * tt + r] = FWD ? a : a + b;
-        SM[row1 * LDY + 16 * tt + r] = FWD ? b : a - b;
+    for (int u = 0; u < (OV + kBlock - 1) / kBlock; ++u) {
+      const int e = t + u * kBlock;
+      if (OV % kBlock == 0 || e < OV) {
+        const int row = e / CV, c = e - row * CV;
+        __builtin_nontemporal_store(*reinterpret_cast<const f4_t*>(SM + row * LDY + 4 * c),
+                                    reinterpret_cast<f4_t*>(yb + (int64_t)row * inner + 4 * c));
       }
-  }
-  __syncthreads();
-  float* yb = Y + o0 * (int64_t)N * inner + i0;
-  constexpr int OV = N * CV;                     // float4 of the block's output
-#pragma unroll
-  for (int u = 0; u < (OV + kBlock - 1) / kBlock; ++u) {
-    const int e = t + u * kBlock;
-    if (OV % kBlock == 0 || e < OV) {
-      const int row = e / CV, c = e - row * CV;
-      __builtin_nontemporal_store(*reinterpret_cast<const f4_t*>(SM + row * LDY + 4 * c),
-                                  reinterpret_cast<f4_t*>(yb + (int64_t)row * inner + 4 * c));
     }
+    __syncthreads();                             // output staged out before the next operands
   }
 }
 
@@ -921,7 +934,8 @@ int launch_fdm_axis(const FdmPlan<V>& F, int a, bool fwd, const V* in, V* out, c
     if (F.sym[a].on && !div && inner != 1 && inner % 32 == 0) {
       const int H = K / 2;
       bool done = false;
-      const dim3 g((unsigned)(ncols / 32));
+      // persistent blocks, two tiles of 32 lines each on average
+      const dim3 g((unsigned)((ncols / 32 + 1) / 2));
       const float* A0 = fwd ? F.sym[a].fe : F.sym[a].ie;
       const float* A1 = fwd ? F.sym[a].fo : F.sym[a].io;
 #define FVIB_SYM(HH)                                                                            \
