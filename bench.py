@@ -108,15 +108,21 @@ def fwd_adj_pass(g, w, ut, fbt, body, kc, steps, ckpt):
 
 
 def fwd_pass(g, ut, fbt, body, kc, steps):
+    """Forward steps in place, enqueued back to back (one step record per
+    step, statuses checked after the last)."""
     import torch
+    from paper_2505_23940_amd import INFO_DOUBLES
     u = [x.clone() for x in ut]
     p = g.zeros_p()
     b = body.clone()
-    infos = []
-    for _ in range(steps):
-        g.step(u, p, fbt, b, kc)
-        infos.append(g.last_info())
-    return infos
+    info = torch.zeros((steps, INFO_DOUBLES), dtype=torch.float64, device=g.device)
+    g.defer_status(True)
+    try:
+        for n in range(steps):
+            g.step(u, p, fbt, b, kc, info=info[n])
+    finally:
+        g.defer_status(False)
+    return info
 
 
 def timed(fn):
@@ -294,7 +300,11 @@ def main():
     }
     if not a.no_extra:
         gi = g
-        el_f, infos = timed(lambda: fwd_pass(gi, ut, fbt, body, kc, a.steps))
+        el_f, info = timed(lambda: fwd_pass(gi, ut, fbt, body, kc, a.steps))
+        gi.check_infos(info, "forward step")
+        from paper_2505_23940_amd import parse_info
+        infos = parse_info(info)
+        infos = infos if isinstance(infos, list) else [infos]
         out["fwd_value"] = round(ncell * a.steps / el_f / 1e6, 3)
         out["fwd_ir_sweeps_per_step"] = float(np.mean([i["ir_iters"] for i in infos]))
         out["fwd_div_max"] = max(i["div_max"] for i in infos)

@@ -136,6 +136,7 @@ struct Grid {
   double* partial = nullptr;
   SolverScalars* sc = nullptr;
   SolverScalars* sch = nullptr;   // pinned host mirror
+  SolverScalars* sch_dev = nullptr;  // its device address
   fvib_step_info* info_dev = nullptr;
   double* mu = nullptr;           // adjoint pressure
   double* d64 = nullptr;          // double inner correction (fast diagonalisation)
@@ -497,8 +498,11 @@ static int cg_run(Grid* g, const PGeo<V>& P, int mode, V* r, V* pa, V* pb, V* x,
 // blocking stream synchronisation: it resumes as soon as the copy lands,
 // which shortens the device's idle time before the launches that follow
 // the check.
-static int enqueue_check(Grid* g) {
-  FVIB_HIP(hipMemcpyAsync(g->sch, g->sc, sizeof(SolverScalars), hipMemcpyDeviceToHost, g->stream));
+// mirrored: the last residual launched has written the mirror itself
+static int enqueue_check(Grid* g, bool mirrored = false) {
+  if (!mirrored)
+    FVIB_HIP(hipMemcpyAsync(g->sch, g->sc, sizeof(SolverScalars), hipMemcpyDeviceToHost,
+                            g->stream));
   if (g->check_ev) FVIB_HIP(hipEventRecord(g->check_ev, g->stream));
   return FVIB_OK;
 }
@@ -568,7 +572,8 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
     auto residual = [&](int first) {
       return timed(g, FVIB_K_RESIDUAL, [&] {
         return launch_residual(g->P64, d64 ? 3 : 2, b, first ? p_in : p, g->r64, g->r32,
-                               nullptr, g->red(), g->sc, tol, 0.5, g->stream, first);
+                               nullptr, g->red(), g->sc, tol, 0.5, g->stream, first,
+                               g->sch_dev);
       });
     };
     auto sweep = [&]() -> int {
@@ -632,7 +637,11 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
       for (int q = 0; q < batch && launched < g->d.ir_maxit; ++q, ++launched)
         if ((rc = sweep())) return rc;
       g->timer.tag = 0;
-      if ((rc = enqueue_check(g))) return rc;
+      // every sweep ends with a residual, whose epilogue (unless skipped
+      // after the refinement finished, leaving the scalars unchanged)
+      // copies the scalars into the host mirror: the check only records
+      // an event
+      if ((rc = enqueue_check(g, true))) return rc;
       if (gauge &&
           (rc = timed(g, FVIB_K_IR_CORRECT, [&] { return launch_gauge(g->ncell, p, g->sc, g->stream); })))
         return rc;
@@ -1173,6 +1182,8 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
   }
   if (hipHostMalloc((void**)&g->sch, sizeof(SolverScalars), hipHostMallocDefault) != hipSuccess)
     return bail(FVIB_ENOMEM, "pinned host allocation failed");
+  if (hipHostGetDevicePointer((void**)&g->sch_dev, g->sch, 0) != hipSuccess)
+    return bail(FVIB_EHIP, "no device address for the pinned solver scalars");
   if (hipMemset(g->mu, 0, g->ncell * sizeof(double)) != hipSuccess ||
       hipMemset(g->sc, 0, sizeof(SolverScalars)) != hipSuccess)
     return bail(FVIB_EHIP, "workspace initialisation failed");

@@ -98,9 +98,12 @@ int launch_ppe_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
                    hipStream_t s);
 // first = 0: a refinement sweep launched ahead of the host's check; it
 // does nothing once the device scalars say the refinement is finished.
+// mirror (nullable): device address of a pinned host SolverScalars that
+// receives a copy of the scalars whenever the launch is not skipped.
 int launch_residual(const PGeo<double>& P, int mode, const double* b, const double* x,
                     double* r64, float* r32, float* d32, RedBuf red, SolverScalars* sc,
-                    double tol, double inner_rtol, hipStream_t s, int first = 1);
+                    double tol, double inner_rtol, hipStream_t s, int first = 1,
+                    SolverScalars* mirror = nullptr);
 // ev (nullable): three events recorded before the direction kernel, between
 // the two kernels and after the update kernel.
 template <typename V>

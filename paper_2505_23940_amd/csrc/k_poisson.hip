@@ -90,6 +90,7 @@ template <int MODE>
 struct FinResidual {        // start of a solve / refinement sweep
   double tol, inner_rtol, dt_over_rho;
   int first;                // first residual of the solve (never skipped)
+  SolverScalars* mirror;    // nullable: device view of the host's pinned copy
   __device__ bool skip(const SolverScalars* sc) const { return !first && sc->outer_done; }
   __device__ void apply(const double* t, SolverScalars* sc) const {
     sc->sweeps = first ? 0 : sc->sweeps + 1;
@@ -107,6 +108,9 @@ struct FinResidual {        // start of a solve / refinement sweep
     const bool conv = bad || crit <= tol || t[0] == 0.0;
     sc->done = conv ? 1 : 0;
     if (MODE != 0) sc->outer_done = conv ? 1 : 0;
+    // the host's check reads the scalars once the stream has passed this
+    // kernel (completion makes the stores visible to it)
+    if (mirror) *mirror = *sc;
   }
 };
 
@@ -559,7 +563,8 @@ int launch_ppe_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
 
 int launch_residual(const PGeo<double>& P, int mode, const double* b, const double* x,
                     double* r64, float* r32, float* d32, RedBuf red, SolverScalars* sc,
-                    double tol, double inner_rtol, hipStream_t s, int first) {
+                    double tol, double inner_rtol, hipStream_t s, int first,
+                    SolverScalars* mirror) {
   const ColTiling ct = make_col_tiling(P.n[0], P.n[1], P.n[2]);
   dim3 g(ct.nblocks), bl(kBlock);
 #define FVIB_RES(D, M)                                                                        \
@@ -567,7 +572,7 @@ int launch_residual(const PGeo<double>& P, int mode, const double* b, const doub
                      first);                                                                    \
   FVIB_HIP(hipGetLastError());                                                                  \
   FVIB_HIP((launch_finish<3, 2>(red.partial, ct.nblocks, sc,                                    \
-                                FinResidual<M>{tol, inner_rtol, P.dt_over_rho, first}, s)))
+                                FinResidual<M>{tol, inner_rtol, P.dt_over_rho, first, mirror}, s)))
   if (P.dim == 2) {
     switch (mode) {
       case 0: FVIB_RES(2, 0); break;

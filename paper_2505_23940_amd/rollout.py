@@ -21,14 +21,30 @@ import torch
 from . import Grid, INFO_DOUBLES
 
 
+def _stack_like(x, n):
+    """n fresh tensors shaped like x, from one allocation (slices of it)."""
+    return torch.empty((n,) + tuple(x.shape), dtype=x.dtype, device=x.device)
+
+
 def _forward_steps(grid, nsteps, ckpt_every, u, p, body, fbd, kcd, info, ckpts):
+    # The state entering a segment is kept as is; the segment's first step
+    # writes its result into a fresh slot and the segment continues there in
+    # place.  The slots of all segments but the last come from one
+    # allocation per field (a device allocation per step stalls the
+    # stream); the last segment, whose state is returned, has its own.
+    nseg = (nsteps + ckpt_every - 1) // ckpt_every
+    if nseg > 1:
+        Us = [_stack_like(x, nseg - 1) for x in u]
+        Ps, Bs = _stack_like(p, nseg - 1), _stack_like(body, nseg - 1)
     for n in range(nsteps):
         if n % ckpt_every == 0:
-            # the state entering a segment is kept as is; the step writes
-            # its result into fresh tensors (p is copied by the step)
             ckpts[n] = (u, p, body)
-            u2 = [torch.empty_like(x) for x in u]
-            p2, b2 = torch.empty_like(p), torch.empty_like(body)
+            s = n // ckpt_every
+            if s < nseg - 1:
+                u2, p2, b2 = [X[s] for X in Us], Ps[s], Bs[s]
+            else:
+                u2 = [torch.empty_like(x) for x in u]
+                p2, b2 = torch.empty_like(p), torch.empty_like(body)
             grid.step(u, p, fbd, body, kcd, u_out=u2, p_out=p2, body_out=b2, info=info[n])
             u, p, body = u2, p2, b2
         else:
@@ -88,6 +104,11 @@ class _Rollout(torch.autograd.Function):
         # adjoint pressure, carried from step to step as the next solve's guess
         mu = grid.zeros_p()
         starts = list(range(0, S, K))
+        # states recomputed inside a segment, one allocation per field
+        if K > 1:
+            RU = [_stack_like(x, K - 1) for x in ubar]
+            RB = _stack_like(bbar, K - 1)
+            RP = grid.zeros_p()
         # recomputed and adjoint steps are enqueued back to back; their
         # statuses are checked once at the end
         infos_f = torch.zeros((S, INFO_DOUBLES), dtype=torch.float64, device=grid.device)
@@ -101,11 +122,13 @@ class _Rollout(torch.autograd.Function):
                 # recomputed ones, each step writing into fresh velocity tensors
                 states = [(cu, cb)]
                 if s1 - s0 > 1:
-                    p = cp.clone()
+                    p = RP
+                    p.copy_(cp)
                     u, body = cu, cb
                     for n in range(s0, s1 - 1):
-                        u2 = [torch.empty_like(x) for x in u]
-                        b2 = torch.empty_like(body)
+                        q = n - s0
+                        u2 = [X[q] for X in RU]
+                        b2 = RB[q]
                         grid.step(u, p, fb, body, kc, u_out=u2, p_out=p, body_out=b2,
                                   info=infos_f[n])
                         u, body = u2, b2
