@@ -315,7 +315,8 @@ class Grid:
     def check_infos(self, infos: torch.Tensor, what: str = "step") -> None:
         """Raise if any fvib_step_info record (rows of a float64 tensor)
         holds a non-zero status (synchronises with the device)."""
-        st = infos.reshape(-1, INFO_DOUBLES).view(torch.int32)[:, 0].cpu()
+        # the records are copied whole (contiguous), then read on the host
+        st = infos.reshape(-1, INFO_DOUBLES).cpu().view(torch.int32)[:, 0]
         bad = torch.nonzero(st).flatten()
         if bad.numel():
             n = int(bad[0])

@@ -111,8 +111,8 @@ class _Rollout(torch.autograd.Function):
             RP = grid.zeros_p()
         # recomputed and adjoint steps are enqueued back to back; their
         # statuses are checked once at the end
-        infos_f = torch.zeros((S, INFO_DOUBLES), dtype=torch.float64, device=grid.device)
-        infos_a = torch.zeros((S, INFO_DOUBLES), dtype=torch.float64, device=grid.device)
+        infos = torch.zeros((2, S, INFO_DOUBLES), dtype=torch.float64, device=grid.device)
+        infos_f, infos_a = infos[0], infos[1]
         grid.defer_status(True)
         try:
             for s0 in reversed(starts):
@@ -142,8 +142,9 @@ class _Rollout(torch.autograd.Function):
                     bbar, bbar_tmp = bbar_tmp, bbar
         finally:
             grid.defer_status(False)
-        grid.check_infos(infos_f, "recomputed step")
-        grid.check_infos(infos_a, "adjoint step")
+        host = infos.cpu()             # one read of both sets of records
+        grid.check_infos(host[0], "recomputed step")
+        grid.check_infos(host[1], "adjoint step")
         return (None, None, None, None, *ubar, *fbbar, kcbar, bbar)
 
 
