@@ -138,7 +138,7 @@ struct Grid {
   SolverScalars* sch = nullptr;   // pinned host mirror
   SolverScalars* sch_dev = nullptr;  // its device address
   fvib_step_info* info_dev = nullptr;
-  double* mu = nullptr;           // adjoint pressure
+  double* mu = nullptr;           // adjoint pressure; also the forward refinement iterate (3D)
   double* d64 = nullptr;          // double inner correction (fast diagonalisation)
   double* fdm_d = nullptr;        // eigenbases (double) and eigenvalues
   float* fdm_f = nullptr;         // eigenbases (float)
@@ -810,15 +810,21 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
     return rc;
   int cg = 0, ir = 0;
   int last = g->last_iters;
+  const bool fdm = g->d.solver == FVIB_SOLVER_FDM;
+  // In 3D with fast diagonalisation the refinement iterates in a workspace
+  // (the adjoint's, which keeps nothing between calls) and the projection,
+  // reading the iterate anyway, stores it minus its mean in out->p: no
+  // separate gauge pass.
+  const bool fold = fdm && g->dim == 3;
+  double* piter = fold ? g->mu : out->p;
   // the projection is queued behind each convergence check of the solve
   const std::function<int()> project = [&]() {
     return timed(g, FVIB_K_PROJECT, [&] {
-      return launch_project<T>(G, g->P64, (const T* const*)us, out->p, uo, g->red(), g->sc,
-                               g->stream);
+      return launch_project<T>(G, g->P64, (const T* const*)us, piter, uo, g->red(), g->sc,
+                               g->stream, fold ? out->p : nullptr);
     });
   };
-  const bool fdm = g->d.solver == FVIB_SOLVER_FDM;
-  if ((rc = poisson_solve(g, g->b, out->p, g->d.poisson_tol, &last, &cg, &ir, true, false,
+  if ((rc = poisson_solve(g, g->b, piter, g->d.poisson_tol, &last, &cg, &ir, !fold, false,
                           in->p, fdm ? &project : nullptr)))
     return rc;
   g->last_iters = last;

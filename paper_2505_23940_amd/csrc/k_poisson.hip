@@ -454,15 +454,20 @@ k_project(Geo<T> G, PGeo<double> P, Tiling tl, const T* __restrict__ s0,
 // faces below and above the cell in registers (the next plane prefetched),
 // so p and u* cross HBM once per chunk; the x and y neighbours of a plane
 // are shared with the adjacent columns through the caches.  Same arithmetic
-// and term order as k_project.
+// and term order as k_project.  pg (nullable, not p): receives p minus its
+// mean (the gradient does not see that constant).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_project_col(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__ s0,
               const T* __restrict__ s1, const T* __restrict__ s2, const double* __restrict__ p,
-              T* __restrict__ o0, T* __restrict__ o1, T* __restrict__ o2, RedBuf red) {
+              T* __restrict__ o0, T* __restrict__ o1, T* __restrict__ o2, RedBuf red,
+              double* __restrict__ pg, const SolverScalars* sc) {
   const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
   const int64_t sxy = (int64_t)nx * ny;
   const double f = P.dt_over_rho;
+  // gauge constant of the pressure copy (the mean of p, from the sum the
+  // last residual recorded)
+  const double mean = pg ? sc->sumx * P.inv_ncell : 0.0;
   double mx = 0.0;
   const int lx = threadIdx.x & (kTileX - 1), ly = threadIdx.x / kTileX;
   for (int u = xcd_block(blockIdx.x, gridDim.x); u < ct.nunits; u += gridDim.x) {
@@ -509,6 +514,7 @@ k_project_col(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__ s0,
       const double lx_ = ulo - f * (pc - pw) * kxl, hx = uhi - f * (pe - pc) * kxh;
       const double ly_ = vlo - f * (pc - ps) * kyl, hy = vhi - f * (pn - pc) * kyh;
       const double lz = wlo - f * (pc - pm) * kzl, hz = whi - f * (pp - pc) * kzh;
+      if (pg) pg[pk + cC] = pc - mean;
       o0[(int64_t)k * su + uL] = (T)lx_;
       if (xlast) o0[(int64_t)k * su + uH] = (T)hx;
       o1[(int64_t)k * sv + vL] = (T)ly_;
@@ -640,15 +646,16 @@ int launch_ir_correct(int64_t n, double* p, const float* d, const SolverScalars*
 
 template <typename T>
 int launch_project(const Geo<T>& G, const PGeo<double>& P, const T* const us[3], const double* p,
-                   T* out[3], RedBuf red, SolverScalars* sc, hipStream_t s) {
+                   T* out[3], RedBuf red, SolverScalars* sc, hipStream_t s, double* pg) {
   const Tiling tl = red_tiling(G.n);
+  if (pg && (G.dim != 3 || pg == p)) return FVIB_EINVAL;
   if (G.dim == 2)
     launch_kernel((k_project<T, 2>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, us[0],
                        us[1], us[2], p, out[0], out[1], out[2], red, sc);
   else {
     const ColTiling ct = make_col_tiling(G.n[0], G.n[1], G.n[2]);
     launch_kernel((k_project_col<T>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct, us[0],
-                  us[1], us[2], p, out[0], out[1], out[2], red);
+                  us[1], us[2], p, out[0], out[1], out[2], red, pg, sc);
     FVIB_HIP(hipGetLastError());
     FVIB_HIP((launch_finish<1, 0>(red.partial, ct.nblocks, sc, FinDivMax{}, s)));
     return FVIB_OK;
@@ -679,9 +686,9 @@ template int launch_cg_iter<double>(const PGeo<double>&, int, const double*, con
                                     int, hipStream_t, hipEvent_t*);
 template int launch_project<float>(const Geo<float>&, const PGeo<double>&, const float* const[3],
                                    const double*, float* [3], RedBuf, SolverScalars*,
-                                   hipStream_t);
+                                   hipStream_t, double*);
 template int launch_project<double>(const Geo<double>&, const PGeo<double>&,
                                     const double* const[3], const double*, double* [3], RedBuf,
-                                    SolverScalars*, hipStream_t);
+                                    SolverScalars*, hipStream_t, double*);
 
 }  // namespace fvib
