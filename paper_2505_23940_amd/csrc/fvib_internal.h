@@ -193,7 +193,9 @@ inline ColTiling make_col_tiling(int nx, int ny, int nz) {
   t.ntx = (nx + kTileX - 1) / kTileX;
   t.nty = (ny + kTileY - 1) / kTileY;
   const int per_plane = t.ntx * t.nty;
-  int nzc = (nz + 15) / 16;
+  // chunks of about ten planes: more columns in flight than longer chunks
+  // (a march is latency bound), less halo and set-up than shorter ones
+  int nzc = (nz + 9) / 10;
   if (per_plane * nzc > kMaxRedBlocks) nzc = kMaxRedBlocks / per_plane > 0 ? kMaxRedBlocks / per_plane : 1;
   t.zchunk = (nz + nzc - 1) / nzc;
   t.nzc = (nz + t.zchunk - 1) / t.zchunk;

@@ -255,6 +255,78 @@ k_adj_rhs(Geo<T> G, PGeo<double> P, Tiling tl, const T* __restrict__ b0,
   block_partials<2, 1>(v, red.partial);
 }
 
+// 3D column march of k_adj_rhs (same terms, same order): each thread walks
+// one (i, j) column of a chunk of z-planes, carrying the upper w face of
+// plane k over as the lower face of plane k + 1 and fetching the faces of
+// the next plane while it evaluates this one.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_adj_rhs_col(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__ b0,
+              const T* __restrict__ b1, const T* __restrict__ b2, double* __restrict__ y,
+              RedBuf red) {
+  const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
+  const int64_t sxy = (int64_t)nx * ny;
+  double sum = 0.0, mx = 0.0;
+  const int lx = threadIdx.x & (kTileX - 1), ly = threadIdx.x / kTileX;
+  for (int u = xcd_block(blockIdx.x, gridDim.x); u < ct.nunits; u += gridDim.x) {
+    const int tx = u % ct.ntx, ty = (u / ct.ntx) % ct.nty, zc = u / (ct.ntx * ct.nty);
+    const int i = tx * kTileX + lx, j = ty * kTileY + ly;
+    if (i >= nx || j >= ny) continue;
+    const int k0 = zc * ct.zchunk, k1 = min(k0 + ct.zchunk, nz);
+    const int ex0 = G.ext[0][0], ex1 = G.ext[0][1];
+    const int ey0 = G.ext[1][0], ey1 = G.ext[1][1];
+    const int ez0 = G.ext[2][0], ez1 = G.ext[2][1];
+    const int iH = (G.per[0] && i + 1 == nx) ? 0 : i + 1;
+    const int jH = (G.per[1] && j + 1 == ny) ? 0 : j + 1;
+    const int64_t uL = (int64_t)j * ex0 + i, uH = (int64_t)j * ex0 + iH;
+    const int64_t vL = (int64_t)j * ey0 + i, vH = (int64_t)jH * ey0 + i;
+    const int64_t wL = (int64_t)j * ez0 + i;
+    const int64_t su = (int64_t)ex0 * ex1, sv = (int64_t)ey0 * ey1, sw = (int64_t)ez0 * ez1;
+    // boundary faces of a bounded axis carry no flux (selected, not
+    // multiplied, so whatever the adjoint holds there cannot leak in)
+    const bool xl = G.per[0] || i > 0, xh = G.per[0] || i + 1 < nx;
+    const bool yl = G.per[1] || j > 0, yh = G.per[1] || j + 1 < ny;
+    const double cxl = P.idc[0][i], cxh = P.idc[0][i + 1];
+    const double cyl = P.idc[1][j], cyh = P.idc[1][j + 1];
+    const double ivxy = (double)P.iv[0][i] * (double)P.iv[1][j];
+    auto kup = [&](int k) { return (G.per[2] && k + 1 == nz) ? 0 : k + 1; };
+    double ulo = (double)b0[(int64_t)k0 * su + uL], uhi = (double)b0[(int64_t)k0 * su + uH];
+    double vlo = (double)b1[(int64_t)k0 * sv + vL], vhi = (double)b1[(int64_t)k0 * sv + vH];
+    double wlo = (double)b2[(int64_t)k0 * sw + wL], whi = (double)b2[(int64_t)kup(k0) * sw + wL];
+    for (int k = k0; k < k1; ++k) {
+      // faces of plane k + 1 (its lower w face is this plane's upper one)
+      double ulo2 = 0.0, uhi2 = 0.0, vlo2 = 0.0, vhi2 = 0.0, whi2 = 0.0;
+      if (k + 1 < k1) {
+        const int64_t kn = k + 1;
+        ulo2 = (double)b0[kn * su + uL];
+        uhi2 = (double)b0[kn * su + uH];
+        vlo2 = (double)b1[kn * sv + vL];
+        vhi2 = (double)b1[kn * sv + vH];
+        whi2 = (double)b2[(int64_t)kup(k + 1) * sw + wL];
+      }
+      const bool zl = G.per[2] || k > 0, zh = G.per[2] || k + 1 < nz;
+      double acc = 0.0;
+      acc += xl ? ulo * cxl : 0.0;
+      acc -= xh ? uhi * cxh : 0.0;
+      acc += yl ? vlo * cyl : 0.0;
+      acc -= yh ? vhi * cyh : 0.0;
+      acc += zl ? wlo * P.idc[2][k] : 0.0;
+      acc -= zh ? whi * P.idc[2][k + 1] : 0.0;
+      y[(int64_t)k * sxy + (int64_t)j * nx + i] = acc;
+      sum += acc;
+      mx = fmax(mx, fabs(acc) * (ivxy * (double)P.iv[2][k]));
+      ulo = ulo2;
+      uhi = uhi2;
+      vlo = vlo2;
+      vhi = vhi2;
+      wlo = whi;
+      whi = whi2;
+    }
+  }
+  double v[2] = {sum, mx};
+  block_partials<2, 1>(v, red.partial);
+}
+
 struct FinAdjRhs {          // mean of G^T ubar, max |y / V| and the solve target
   double inv_ncell, rtol, dt_over_rho;
   __device__ bool skip(const SolverScalars*) const { return false; }
@@ -944,13 +1016,18 @@ int launch_adj_body_loads(const IbGeo& B, const IbView<T>& ib, const double* st,
 template <typename T>
 int launch_adj_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const ub[3], double* y,
                    RedBuf red, SolverScalars* sc, double rtol, hipStream_t s) {
+  if (G.dim == 3) {
+    const ColTiling ct = make_col_tiling(G.n[0], G.n[1], G.n[2]);
+    launch_kernel((k_adj_rhs_col<T>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct, ub[0],
+                  ub[1], ub[2], y, red);
+    FVIB_HIP(hipGetLastError());
+    FVIB_HIP((launch_finish<2, 1>(red.partial, ct.nblocks, sc,
+                                  FinAdjRhs{P.inv_ncell, rtol, P.dt_over_rho}, s)));
+    return FVIB_OK;
+  }
   const Tiling tl = make_tiling(G.n[0], G.n[1], G.n[2]);
-  if (G.dim == 2)
-    launch_kernel((k_adj_rhs<T, 2>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, ub[0],
-                       ub[1], ub[2], y, red, sc);
-  else
-    launch_kernel((k_adj_rhs<T, 3>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, ub[0],
-                       ub[1], ub[2], y, red, sc);
+  launch_kernel((k_adj_rhs<T, 2>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, ub[0],
+                ub[1], ub[2], y, red, sc);
   FVIB_HIP(hipGetLastError());
   FVIB_HIP((launch_finish<2, 1>(red.partial, tl.nblocks, sc,
                                 FinAdjRhs{P.inv_ncell, rtol, P.dt_over_rho}, s)));
