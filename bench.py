@@ -31,11 +31,13 @@ TIMING_EVERY = 4
 MFMA_PEAK_TFS = {"fp32": 157.3, "fp64": 78.6}   # dense matrix-core peaks
 
 
-def kernel_cost(d: int, s: int, mixed: bool, n: tuple):
+def kernel_cost(d: int, s: int, mixed: bool, n: tuple, solver: str = "fdm"):
     """Algorithmic cost per launch per cell: ("bytes", B) or ("flops", F).
 
     d = velocity components, s = bytes per velocity value."""
     v = 4 if mixed else 8          # inner-solve vector type
+    # 3D fast diagonalisation: the projection also stores the gauged pressure
+    pg = 8 if (d == 3 and solver == "fdm") else 0
     return {
         "predictor": ("bytes", 3 * d * s),                 # read u, f_b; write u*
         "ppe_rhs": ("bytes", d * s + 8),                   # read u*; write b
@@ -43,7 +45,7 @@ def kernel_cost(d: int, s: int, mixed: bool, n: tuple):
         "cg_dir": ("bytes", 3 * v),                        # read r, p_old; write p_new
         "cg_update": ("bytes", 5 * v),                     # read p, x, r; write x, r
         "ir_correct": ("bytes", 8 + v + 8),                # read p, d; write p
-        "project": ("bytes", 2 * d * s + 8),               # read u*, p; write u
+        "project": ("bytes", 2 * d * s + 8 + pg),          # read u*, p; write u (and p)
         "adj_momentum": ("bytes", 5 * d * s),              # read u, ustar_bar; write ubar; rw fbbar
         "fdm_x": ("flops", 2 * n[0]),                      # dense contraction along x
         "fdm_y": ("flops", 2 * n[1]),
@@ -191,16 +193,16 @@ def measured_traffic(kernel_class):
     return entry["traffic_bytes"]
 
 
-def dominant(table, w, mixed):
+def dominant(table, w, mixed, solver):
     """Kernel class with a cost model and the largest total time."""
-    cost = kernel_cost(w.dim, 4 if mixed else 8, mixed, w.n)
+    cost = kernel_cost(w.dim, 4 if mixed else 8, mixed, w.n, solver)
     return max((k for k in table if k in cost), key=lambda k: table[k]["total_ms"])
 
 
-def roofline(timing, w, precision, mixed, dom=None):
+def roofline(timing, w, precision, mixed, solver, dom=None):
     ncell = w.ncells
     s = 4 if mixed else 8
-    cost = kernel_cost(w.dim, s, mixed, w.n)
+    cost = kernel_cost(w.dim, s, mixed, w.n, solver)
     table = {}
     for name, (ms, nl) in timing.items():
         if nl == 0:
@@ -250,12 +252,12 @@ def main():
     fwd_adj_pass(g, w, ut, fbt, body, kc, nw, a.ckpt)
     g.timing_enable(True)
     fwd_adj_pass(g, w, ut, fbt, body, kc, nw, a.ckpt)
-    _, table = roofline(g.timing_read(), w, a.precision, mixed)
+    _, table = roofline(g.timing_read(), w, a.precision, mixed, a.solver)
     for name, (ms, nl) in g.timing_read(skipped=True).items():
         if nl and name in table:
             table[name]["skipped"] = nl
     g.timing_enable(False)
-    dom = dominant(table, w, mixed)
+    dom = dominant(table, w, mixed, a.solver)
     print(f"[bench] warmup done ({nw} + {nw} steps); dominant kernel {dom}",
           file=sys.stderr, flush=True)
     # timed region: only a sample of the dominant class's launches carries
@@ -267,7 +269,7 @@ def main():
     g.timing_enable(False)
     print(f"[bench] fwd+adj {a.steps} steps in {el:.3f} s (J = {float(J.detach()):.6g})",
           file=sys.stderr, flush=True)
-    rl, _ = roofline(timing, w, a.precision, mixed, dom)
+    rl, _ = roofline(timing, w, a.precision, mixed, a.solver, dom)
     # launches of speculative refinement sweeps that found the solve
     # converged return at once; they are left out of the average above
     rl["skipped_launches"] = skipped[dom][1]

@@ -22,9 +22,12 @@
 
 namespace fvib {
 
-template <typename V>
+// Lines per block: 16 on the contiguous axis (two buffers of 8 complex
+// lines, about 25 KB of LDS, so six blocks fit a CU); the strided axis keeps
+// 32 float lines, whose interleaved rows then span 128 bytes.
+template <typename V, bool XFAST>
 struct FftCfg {
-  static constexpr int LPB = sizeof(V) == 4 ? 32 : 16;   // lines per block
+  static constexpr int LPB = (sizeof(V) == 4 && !XFAST) ? 32 : 16;
   static constexpr int P = LPB / 2;                      // complex lines
 };
 
@@ -274,16 +277,17 @@ k_fft_axis(const V* __restrict__ X, V* __restrict__ Y, int inner, int64_t ncols,
   if (stop && *stop) {
     if constexpr (ACC) {
       if (pin != pacc) {
-        const int64_t b0 = (int64_t)blockIdx.x * FftCfg<V>::LPB * N;
-        const int64_t left = ncols - (int64_t)blockIdx.x * FftCfg<V>::LPB;
-        const int64_t ne = (left < FftCfg<V>::LPB ? left : FftCfg<V>::LPB) * N;
+        constexpr int L = FftCfg<V, XFAST>::LPB;
+        const int64_t b0 = (int64_t)blockIdx.x * L * N;
+        const int64_t left = ncols - (int64_t)blockIdx.x * L;
+        const int64_t ne = (left < L ? left : L) * N;
         for (int64_t e = threadIdx.x; e < ne; e += kBlock) pacc[b0 + e] = pin[b0 + e];
       }
     }
     return;
   }
   constexpr bool IL = !XFAST;
-  typedef FftCfg<V> C;
+  typedef FftCfg<V, XFAST> C;
   constexpr int LPB = C::LPB, P = C::P;
   constexpr int VW = 16 / (int)sizeof(V);            // 16-byte global vectors
   typedef __attribute__((ext_vector_type(VW))) V vec_t;
@@ -562,12 +566,12 @@ int launch_fft_axis(const FdmPlan<V>& F, int a, int mode, const V* in, V* out, c
   const int64_t ncols = outer * inner;
   if (acc && !(inner == 1 && mode == 1)) return FVIB_EINVAL;
   if (inner == 1 && mode == 2) return FVIB_EINVAL;
-  constexpr int LPB = FftCfg<V>::LPB;
-  const dim3 g((unsigned)((ncols + LPB - 1) / LPB));
+  constexpr int LPBc = FftCfg<V, true>::LPB, LPBs = FftCfg<V, false>::LPB;
+  const dim3 gc((unsigned)((ncols + LPBc - 1) / LPBc)), gs((unsigned)((ncols + LPBs - 1) / LPBs));
   bool done = false;
 #define FVIB_FFT(NN, XF, M, AC)                                                                 \
-  launch_kernel((k_fft_axis<V, NN, XF, M, AC>), g, dim3(kBlock), 0, s, in, out, inner,          \
-                ncols, F.fft[a], F.tw[a], F.div, stop, acc, accin)
+  launch_kernel((k_fft_axis<V, NN, XF, M, AC>), XF ? gc : gs, dim3(kBlock), 0, s, in, out,      \
+                inner, ncols, F.fft[a], F.tw[a], F.div, stop, acc, accin)
 #define FVIB_FFT_N(NN)                                                                          \
   if (!done && N == NN) {                                                                       \
     done = true;                                                                                \
@@ -595,7 +599,7 @@ bool fft_usable(const FdmPlan<V>& F, int a) {
   if (!F.fft[a].on || !fft_size_supported(F.n[a])) return false;
   int inner = 1;
   for (int q = 0; q < a; ++q) inner *= F.n[q];
-  return inner == 1 || inner % FftCfg<V>::LPB == 0;
+  return inner == 1 || inner % FftCfg<V, false>::LPB == 0;
 }
 
 template int launch_fft_axis<float>(const FdmPlan<float>&, int, int, const float*, float*,

@@ -250,6 +250,13 @@ __device__ __forceinline__ void fill_plane(const Geo<T>& G, const T* const* u,
 
 // MODE 0: predictor (writes u*, and the forcing on forced faces).
 // MODE 1: right-hand side only (writes R on advanced faces).
+// z-chunk of the predictor's march: ten planes give 1536 blocks on the
+// channel grid, six to a CU at this kernel's occupancy, so all of them run
+// in one round (16-plane chunks left CUs idle); the tile metrics span more
+// planes than that.
+constexpr int kZChunkPred = 10;
+static_assert(kZChunkPred <= kZChunk, "tile metric tables cover kZChunk + 2 planes");
+
 template <typename T, int DIM, int MODE, bool UPW, bool IBA>
 __global__ void __launch_bounds__(kBlock)
 k_predictor(Geo<T> G, int ntx, int nty, int nzc, const T* __restrict__ u0,
@@ -268,8 +275,8 @@ k_predictor(Geo<T> G, int ntx, int nty, int nzc, const T* __restrict__ u0,
   const int lx = threadIdx.x & (kTileX - 1);
   const int ly = __builtin_amdgcn_readfirstlane(threadIdx.x / kTileX);
   const int i = i0 + lx, j = j0 + ly;
-  const int k0 = (DIM == 3) ? zc * kZChunk : 0;
-  const int k1 = (DIM == 3) ? min(k0 + kZChunk, G.n[2]) : 1;
+  const int k0 = (DIM == 3) ? zc * kZChunkPred : 0;
+  const int k1 = (DIM == 3) ? min(k0 + kZChunkPred, G.n[2]) : 1;
   const bool inside = i < G.n[0] && j < G.n[1];
   load_tile_met<DIM>(G, TM, i0, j0, k0);
   PlaneHalo<T, DIM> Hh;
@@ -421,7 +428,7 @@ int launch_predictor(const Geo<T>& G, const T* const u[3], const T* const fb[3],
                      const IbView<T>& ib, int mode, hipStream_t s) {
   const int ntx = (G.n[0] + kTileX - 1) / kTileX;
   const int nty = (G.n[1] + kTileY - 1) / kTileY;
-  const int nzc = (G.dim == 3) ? (G.n[2] + kZChunk - 1) / kZChunk : 1;
+  const int nzc = (G.dim == 3) ? (G.n[2] + kZChunkPred - 1) / kZChunkPred : 1;
   int nb = ntx * nty * nzc;
   nb = (nb + kXcds - 1) / kXcds * kXcds;
   dim3 grid(nb), block(kBlock);
