@@ -106,12 +106,14 @@ def test_poisson_solution_parity(case, precision, solver):
     assert err <= 1e-9 * float(pe.abs().max()), (err, iters)
 
 
-@pytest.mark.parametrize("dims", [(192, 128, 160), (64, 32, 96), (96, 256, 32)])
+@pytest.mark.parametrize("dims", [(192, 128, 160), (64, 32, 96), (96, 256, 32),
+                                  (48, 13, 10), (96, 5, 27)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_poisson_parity_channel_shapes(dims, precision):
     """Fast-diagonalisation solve at the channel's production shape (and
-    shapes whose axes take the other operator-tile counts), against the
-    oracle's exact solve."""
+    shapes whose axes take the other operator-tile counts; the last two
+    give the contiguous x FFT an odd line count that leaves its last block
+    partly filled, 130 and 135 lines), against the oracle's exact solve."""
     need_gpu()
     from oracle import Grid as OGrid
     from oracle.poisson import solver as exact
