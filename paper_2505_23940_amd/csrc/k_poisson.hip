@@ -514,13 +514,14 @@ k_project_col(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__ s0,
       const double lx_ = ulo - f * (pc - pw) * kxl, hx = uhi - f * (pe - pc) * kxh;
       const double ly_ = vlo - f * (pc - ps) * kyl, hy = vhi - f * (pn - pc) * kyh;
       const double lz = wlo - f * (pc - pm) * kzl, hz = whi - f * (pp - pc) * kzh;
-      if (pg) pg[pk + cC] = pc - mean;
-      o0[(int64_t)k * su + uL] = (T)lx_;
-      if (xlast) o0[(int64_t)k * su + uH] = (T)hx;
-      o1[(int64_t)k * sv + vL] = (T)ly_;
-      if (ylast) o1[(int64_t)k * sv + vH] = (T)hy;
-      o2[(int64_t)k * sw + wL] = (T)lz;
-      if (!G.per[2] && k + 1 == nz) o2[(int64_t)kH * sw + wL] = (T)hz;
+      // streaming stores: the next reader is the following step
+      if (pg) __builtin_nontemporal_store(pc - mean, &pg[pk + cC]);
+      __builtin_nontemporal_store((T)lx_, &o0[(int64_t)k * su + uL]);
+      if (xlast) __builtin_nontemporal_store((T)hx, &o0[(int64_t)k * su + uH]);
+      __builtin_nontemporal_store((T)ly_, &o1[(int64_t)k * sv + vL]);
+      if (ylast) __builtin_nontemporal_store((T)hy, &o1[(int64_t)k * sv + vH]);
+      __builtin_nontemporal_store((T)lz, &o2[(int64_t)k * sw + wL]);
+      if (!G.per[2] && k + 1 == nz) __builtin_nontemporal_store((T)hz, &o2[(int64_t)kH * sw + wL]);
       double div = 0.0;
       div += (hx - lx_) * (dy * dz);
       div += (hy - ly_) * (dx * dz);
