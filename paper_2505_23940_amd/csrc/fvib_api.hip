@@ -494,11 +494,12 @@ static int cg_run(Grid* g, const PGeo<V>& P, int mode, V* r, V* pa, V* pb, V* x,
   return FVIB_OK;
 }
 
-// Device scalars to the host.  The host spins on an event instead of a
-// blocking stream synchronisation: it resumes as soon as the copy lands,
-// which shortens the device's idle time before the launches that follow
-// the check.
-// mirrored: the last residual launched has written the mirror itself
+// Device scalars to the host: a copy into the pinned mirror (unless
+// mirrored: the last residual launched has written the mirror itself),
+// then an event.  The host spins on the event instead of a blocking stream
+// synchronisation: it resumes as soon as the scalars have landed, which
+// shortens the device's idle time before the launches that follow the
+// check.
 static int enqueue_check(Grid* g, bool mirrored = false) {
   if (!mirrored)
     FVIB_HIP(hipMemcpyAsync(g->sch, g->sc, sizeof(SolverScalars), hipMemcpyDeviceToHost,
