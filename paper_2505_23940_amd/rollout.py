@@ -21,9 +21,14 @@ import torch
 from . import Grid, INFO_DOUBLES
 
 
-def _stack_like(x, n):
-    """n fresh tensors shaped like x, from one allocation (slices of it)."""
-    return torch.empty((n,) + tuple(x.shape), dtype=x.dtype, device=x.device)
+def _slots_like(x, n):
+    """n fresh contiguous tensors shaped like x, carved from one allocation;
+    each starts on a 256-byte boundary, as a separate allocation would (the
+    library's vector loads need 16- and 32-byte alignment)."""
+    es = x.element_size()
+    per = -(-x.numel() * es // 256) * 256 // es
+    flat = torch.empty((n, per), dtype=x.dtype, device=x.device)
+    return [flat[s, :x.numel()].view(x.shape) for s in range(n)]
 
 
 def _forward_steps(grid, nsteps, ckpt_every, u, p, body, fbd, kcd, info, ckpts):
@@ -34,8 +39,8 @@ def _forward_steps(grid, nsteps, ckpt_every, u, p, body, fbd, kcd, info, ckpts):
     # stream); the last segment, whose state is returned, has its own.
     nseg = (nsteps + ckpt_every - 1) // ckpt_every
     if nseg > 1:
-        Us = [_stack_like(x, nseg - 1) for x in u]
-        Ps, Bs = _stack_like(p, nseg - 1), _stack_like(body, nseg - 1)
+        Us = [_slots_like(x, nseg - 1) for x in u]
+        Ps, Bs = _slots_like(p, nseg - 1), _slots_like(body, nseg - 1)
     for n in range(nsteps):
         if n % ckpt_every == 0:
             ckpts[n] = (u, p, body)
@@ -106,8 +111,8 @@ class _Rollout(torch.autograd.Function):
         starts = list(range(0, S, K))
         # states recomputed inside a segment, one allocation per field
         if K > 1:
-            RU = [_stack_like(x, K - 1) for x in ubar]
-            RB = _stack_like(bbar, K - 1)
+            RU = [_slots_like(x, K - 1) for x in ubar]
+            RB = _slots_like(bbar, K - 1)
             RP = grid.zeros_p()
         # recomputed and adjoint steps are enqueued back to back; their
         # statuses are checked once at the end
