@@ -818,11 +818,16 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
   // separate gauge pass.
   const bool fold = fdm && g->dim == 3;
   double* piter = fold ? g->mu : out->p;
+  fvib_step_info* dst = info ? info : g->info_dev;
+  // Without a body the scalars are final once the projection has run, so
+  // with fast diagonalisation its epilogue also writes the step record
+  // (sweeps as counted on the device).
+  const bool rec = fdm && !g->has_body;
   // the projection is queued behind each convergence check of the solve
   const std::function<int()> project = [&]() {
     return timed(g, FVIB_K_PROJECT, [&] {
       return launch_project<T>(G, g->P64, (const T* const*)us, piter, uo, g->red(), g->sc,
-                               g->stream, fold ? out->p : nullptr);
+                               g->stream, fold ? out->p : nullptr, rec ? dst : nullptr);
     });
   };
   if ((rc = poisson_solve(g, g->b, piter, g->d.poisson_tol, &last, &cg, &ir, !fold, false,
@@ -839,8 +844,10 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
     });
     if (rc) return rc;
   }
-  fvib_step_info* dst = info ? info : g->info_dev;
-  if ((rc = launch_copy_info(g->sc, dst, cg, ir, g->stream))) return rc;
+  // (a status the host set after the last projection still needs the copy)
+  if ((!rec || g->sch->status == FVIB_ENOCONV) &&
+      (rc = launch_copy_info(g->sc, dst, cg, ir, g->stream)))
+    return rc;
   if (g->defer) {                // status only in the info record
     g->err.clear();
     return FVIB_OK;

@@ -113,10 +113,12 @@ int launch_cg_iter(const PGeo<V>& P, int mode, const V* r, const V* pold, V* pne
 int launch_ir_correct(int64_t n, double* p, const float* d, const SolverScalars* sc,
                       hipStream_t s);
 // pg (nullable, 3D only, distinct from p): also store p minus its mean
-// (sc->sumx / ncell) there.
+// (sc->sumx / ncell) there.  info (nullable): also fill that step record
+// from the scalars (refinement sweeps as the iteration count).
 template <typename T>
 int launch_project(const Geo<T>& G, const PGeo<double>& P, const T* const us[3], const double* p,
-                   T* out[3], RedBuf red, SolverScalars* sc, hipStream_t s, double* pg = nullptr);
+                   T* out[3], RedBuf red, SolverScalars* sc, hipStream_t s, double* pg = nullptr,
+                   fvib_step_info* info = nullptr);
 int launch_apply_A(const PGeo<double>& P, const double* x, double* y, hipStream_t s);
 
 // k_ib.hip

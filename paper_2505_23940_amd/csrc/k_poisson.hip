@@ -161,8 +161,25 @@ struct FinCgUpdate {
 };
 
 struct FinDivMax {
+  // nullable: the step record, written here from the scalars (a solve by
+  // fast diagonalisation without a body, whose scalars are final once the
+  // projection has run)
+  fvib_step_info* info;
   __device__ bool skip(const SolverScalars*) const { return false; }
-  __device__ void apply(const double* t, SolverScalars* sc) const { sc->div_max = t[0]; }
+  __device__ void apply(const double* t, SolverScalars* sc) const {
+    sc->div_max = t[0];
+    if (!info) return;
+    int st = sc->status;
+    if (st == FVIB_OK && sc->clamp) st = FVIB_EINVAL;
+    info->status = st;
+    info->cg_iters = 0;
+    info->ir_iters = sc->sweeps;
+    info->flags = sc->clamp;
+    info->res = sc->crit;
+    info->div_max = t[0];
+    for (int a = 0; a < 3; ++a) info->force[a] = sc->force[a];
+    info->reserved = 0.0;
+  }
 };
 
 // ----------------------------------------------------------------- RHS
@@ -647,7 +664,8 @@ int launch_ir_correct(int64_t n, double* p, const float* d, const SolverScalars*
 
 template <typename T>
 int launch_project(const Geo<T>& G, const PGeo<double>& P, const T* const us[3], const double* p,
-                   T* out[3], RedBuf red, SolverScalars* sc, hipStream_t s, double* pg) {
+                   T* out[3], RedBuf red, SolverScalars* sc, hipStream_t s, double* pg,
+                   fvib_step_info* info) {
   const Tiling tl = red_tiling(G.n);
   if (pg && (G.dim != 3 || pg == p)) return FVIB_EINVAL;
   if (G.dim == 2)
@@ -658,11 +676,11 @@ int launch_project(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
     launch_kernel((k_project_col<T>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct, us[0],
                   us[1], us[2], p, out[0], out[1], out[2], red, pg, sc);
     FVIB_HIP(hipGetLastError());
-    FVIB_HIP((launch_finish<1, 0>(red.partial, ct.nblocks, sc, FinDivMax{}, s)));
+    FVIB_HIP((launch_finish<1, 0>(red.partial, ct.nblocks, sc, FinDivMax{info}, s)));
     return FVIB_OK;
   }
   FVIB_HIP(hipGetLastError());
-  FVIB_HIP((launch_finish<1, 0>(red.partial, tl.nblocks, sc, FinDivMax{}, s)));
+  FVIB_HIP((launch_finish<1, 0>(red.partial, tl.nblocks, sc, FinDivMax{info}, s)));
   return FVIB_OK;
 }
 
@@ -687,9 +705,9 @@ template int launch_cg_iter<double>(const PGeo<double>&, int, const double*, con
                                     int, hipStream_t, hipEvent_t*);
 template int launch_project<float>(const Geo<float>&, const PGeo<double>&, const float* const[3],
                                    const double*, float* [3], RedBuf, SolverScalars*,
-                                   hipStream_t, double*);
+                                   hipStream_t, double*, fvib_step_info*);
 template int launch_project<double>(const Geo<double>&, const PGeo<double>&,
                                     const double* const[3], const double*, double* [3], RedBuf,
-                                    SolverScalars*, hipStream_t, double*);
+                                    SolverScalars*, hipStream_t, double*, fvib_step_info*);
 
 }  // namespace fvib
