@@ -899,7 +899,7 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
     if (rc) return rc;
   }
   // without a body the adjoint body state passes through unchanged (copied
-  // with the step record)
+  // at the end of the step, with the step record)
   double* body_pass = (!g->has_body && bi->body) ? bi->body : nullptr;
   // projection^T: A mu = G^T ubar^{n+1}
   // relative max-norm target of the adjoint solve, set on the device from
@@ -921,18 +921,10 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
   const bool warm = bi->mu != nullptr && g->d.solver == FVIB_SOLVER_FDM;
   double* mu = bi->mu ? bi->mu : g->mu;
   if (!warm) FVIB_HIP(hipMemsetAsync(mu, 0, g->ncell * sizeof(double), g->stream));
-  fvib_step_info* dst = info ? info : g->info_dev;
-  // With fast diagonalisation, no body and no outflow planes the scalars
-  // are final once ustar_bar is formed, so its kernel also writes the step
-  // record and passes the body adjoint through.
-  const bool rec = g->d.solver == FVIB_SOLVER_FDM && !g->has_body && !g->planes.any_outflow;
   // ustar_bar (a pure function of mu) is queued behind each convergence check
   const std::function<int()> ustar = [&]() {
     return timed(g, FVIB_K_ADJOINT,
-                 [&] {
-                   return launch_adj_ustar<T>(G, g->P64, ub1, mu, ib, usb, g->sc, g->stream,
-                                              rec ? dst : nullptr, bo->body, body_pass);
-                 });
+                 [&] { return launch_adj_ustar<T>(G, g->P64, ub1, mu, ib, usb, g->sc, g->stream); });
   };
   const bool fdm = g->d.solver == FVIB_SOLVER_FDM;
   if ((rc = poisson_solve(g, g->b, mu, -1.0, &g->last_iters_adj, &cg, &ir, false, warm, nullptr,
@@ -960,10 +952,8 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
          return launch_adj_outflow<T>(G, g->planes, 1, usb, ub0, g->red(), g->sc, g->stream);
        })))
     return rc;
-  // (a status the host set after the last ustar_bar still needs the copy)
-  if ((!rec || g->sch->status == FVIB_ENOCONV) &&
-      (rc = launch_copy_info(g->sc, dst, cg, ir, g->stream, bo->body, body_pass)))
-    return rc;
+  fvib_step_info* dst = info ? info : g->info_dev;
+  if ((rc = launch_copy_info(g->sc, dst, cg, ir, g->stream, bo->body, body_pass))) return rc;
   if (g->defer) {                // status only in the info record
     g->err.clear();
     return FVIB_OK;

@@ -144,13 +144,9 @@ int launch_adj_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const ub[3],
 template <typename T>
 // mu is used at zero mean: sc->sumx is its sum (measured by the solve's
 // last residual sweep)
-// info (nullable): also write that step record from the scalars and set
-// body_dst (nullable) to body_src (zeros if null), in block 0 -- for a step
-// whose scalars are final at this point.
 int launch_adj_ustar(const Geo<T>& G, const PGeo<double>& P, const T* const ub1[3],
                      const double* mu, const IbView<T>& ib, T* usb[3], const SolverScalars* sc,
-                     hipStream_t s, fvib_step_info* info = nullptr,
-                     const double* body_src = nullptr, double* body_dst = nullptr);
+                     hipStream_t s);
 template <typename T>
 int launch_adj_ubody(const Geo<T>& G, const PGeo<double>& P, const IbGeo& B, const T* const ub1[3],
                      const double* mu, const IbView<T>& ib, double* stbar,

@@ -373,17 +373,6 @@ __device__ __forceinline__ double st_mu(const Geo<T>& G, const PGeo<double>& P,
   return A * (lo - hi);
 }
 
-// Step record of an adjoint step whose scalars are final once ustar_bar
-// has been formed (fast diagonalisation, no body, no outflow planes):
-// block 0 of k_adj_ustar writes it, and passes the body adjoint through
-// (body_dst = body_src, or zeros without a source), so no separate
-// record-copy launch follows the step.
-struct AdjRecord {
-  fvib_step_info* info;       // nullable: no record written here
-  const double* body_src;
-  double* body_dst;           // nullable
-};
-
 // ustar_bar = ubar^{n+1} + (1 - eps) S^T mu on every face, all components
 // in one launch.  Each thread walks a z-column of a tile chunk and owns the
 // low faces of its cells (and the high face of the last cell of a bounded
@@ -394,25 +383,9 @@ __global__ void __launch_bounds__(kBlock)
 k_adj_ustar(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__ b0,
             const T* __restrict__ b1, const T* __restrict__ b2, const double* __restrict__ mu,
             IbView<T> ib, T* __restrict__ s0, T* __restrict__ s1, T* __restrict__ s2,
-            const SolverScalars* sc, AdjRecord rec) {
+            const SolverScalars* sc) {
   const T* ub[3] = {b0, b1, b2};
   T* us[3] = {s0, s1, s2};
-  if (rec.info && blockIdx.x == 0) {
-    if (rec.body_dst && threadIdx.x < 6)
-      rec.body_dst[threadIdx.x] = rec.body_src ? rec.body_src[threadIdx.x] : 0.0;
-    if (threadIdx.x == 0) {
-      int st = sc->status;
-      if (st == FVIB_OK && sc->clamp) st = FVIB_EINVAL;
-      rec.info->status = st;
-      rec.info->cg_iters = 0;
-      rec.info->ir_iters = sc->sweeps;
-      rec.info->flags = sc->clamp;
-      rec.info->res = sc->crit;
-      rec.info->div_max = sc->div_max;
-      for (int a = 0; a < 3; ++a) rec.info->force[a] = sc->force[a];
-      rec.info->reserved = 0.0;
-    }
-  }
   const double shift = sc->sumx * P.inv_ncell;
   const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
   const int64_t sxy = (int64_t)nx * ny;
@@ -1070,16 +1043,14 @@ static inline int nblk(int64_t n) {
 template <typename T>
 int launch_adj_ustar(const Geo<T>& G, const PGeo<double>& P, const T* const ub1[3],
                      const double* mu, const IbView<T>& ib, T* usb[3], const SolverScalars* sc,
-                     hipStream_t s, fvib_step_info* info, const double* body_src,
-                     double* body_dst) {
+                     hipStream_t s) {
   const ColTiling ct = make_col_tiling(G.n[0], G.n[1], G.n[2]);
-  const AdjRecord rec{info, body_src, body_dst};
   if (G.dim == 2)
     launch_kernel((k_adj_ustar<T, 2>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct, ub1[0],
-                       ub1[1], ub1[2], mu, ib, usb[0], usb[1], usb[2], sc, rec);
+                       ub1[1], ub1[2], mu, ib, usb[0], usb[1], usb[2], sc);
   else
     launch_kernel((k_adj_ustar<T, 3>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct, ub1[0],
-                       ub1[1], ub1[2], mu, ib, usb[0], usb[1], usb[2], sc, rec);
+                       ub1[1], ub1[2], mu, ib, usb[0], usb[1], usb[2], sc);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
@@ -1158,8 +1129,7 @@ static int launch_adj_momentum_t(const AdjCtx<T>& X, T* ubar[3], T* fbbar[3], hi
                                  double*, RedBuf, SolverScalars*, double, hipStream_t);         \
   template int launch_adj_ustar<T>(const Geo<T>&, const PGeo<double>&, const T* const[3],       \
                                    const double*, const IbView<T>&, T* [3],                     \
-                                   const SolverScalars*, hipStream_t, fvib_step_info*,          \
-                                   const double*, double*);                                     \
+                                   const SolverScalars*, hipStream_t);                          \
   template int launch_adj_ubody<T>(const Geo<T>&, const PGeo<double>&, const IbGeo&,            \
                                    const T* const[3], const double*, const IbView<T>&,          \
                                    double*, const SolverScalars*, hipStream_t);                 \
