@@ -7,7 +7,7 @@
  * GPU-Optimized Differentiable CFD Platform for High-Fidelity Turbulence
  * and FSI Simulations" (arXiv 2505.23940):
  *   - staggered finite volumes on a rectangular, uniform or stretched grid
- *     (Sec. 2.2.1), periodic / Dirichlet / Neumann boundaries (Sec. 2.4,
+ *     (Sec. 2.3.1), periodic / Dirichlet / Neumann boundaries (Sec. 2.5,
  *     Table 1);
  *   - forward-Euler predictor with central or upwind convection and central
  *     diffusion (Eq. 4), direct-forcing IBM (Eq. 5);
@@ -15,7 +15,7 @@
  *   - 4-point-kernel transfers between markers and the grid (Eqs. 18-22);
  *   - rigid spring-damper body integrated with RK4 (Eq. 12);
  *   - one weakly coupled step = Alg. 1 with N = 1;
- *   - reverse-mode gradients (Sec. 2.3.1), here as a hand-written discrete
+ *   - reverse-mode gradients (Sec. 2.4.1), here as a hand-written discrete
  *     adjoint of every sub-step with the Poisson adjoint taken through the
  *     implicit function theorem (Eq. 24).
  *
@@ -95,7 +95,7 @@ enum { FVIB_BODY_STATIC = 0, FVIB_BODY_RIGID_SPRING = 1 };
 enum { FVIB_SOLVER_CG = 0, FVIB_SOLVER_FDM = 1 };
 enum { FVIB_DTYPE_F32 = 0, FVIB_DTYPE_F64 = 1 };
 
-/* Grid and solver description (Sec. 2.4 of the paper). */
+/* Grid and solver description (Sec. 2.5 of the paper). */
 typedef struct {
   int32_t dim;              /* 2 or 3                                          */
   int32_t n[3];             /* cells per axis; n[2] = 1 when dim = 2           */
@@ -184,7 +184,7 @@ int fvib_destroy_grid(fvib_grid *g);
 int fvib_field_layout(const fvib_grid *g, int comp, int64_t shape[3],
                       int64_t strides[3], int *dtype);
 
-/* Attach an immersed body (Sec. 2.1, Eqs. 18-22); NULL removes it.  2D
+/* Attach an immersed body (Sec. 2.2, Fig. 2; Sec. 2.3.3, Eqs. 18-22); NULL removes it.  2D
  * grids with equal uniform spacing h in x and y only.  The body must stay
  * at least four cells away from the domain boundary.  Point classes are
  * rebuilt inside fvib_step from the displacement in the body state. */

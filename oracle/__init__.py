@@ -5,7 +5,7 @@ the ``cpu_baseline`` leg of ``bench.py`` may import this package.  The GPU
 library never calls it and shares no code with it.
 
 It is a plain, slow, float64 implementation written from the paper
-(Fan, Liu, Wang & Wang, "Diff-FlowFSI", arXiv 2505.23940), Sec. 2.2:
+(Fan, Liu, Wang & Wang, "Diff-FlowFSI", arXiv 2505.23940), Sec. 2.3:
 
 * fluid  (``fluid.py``)  -- staggered finite volumes, central / upwind
   convection in divergence form, central diffusion, forward-Euler predictor
@@ -15,7 +15,7 @@ It is a plain, slow, float64 implementation written from the paper
   tensor-product eigen-decomposition (the plain definition the GPU reaches
   iteratively);
 * IBM   (``ibm.py``)    -- solid / immersed-boundary point classes
-  (Sec. 2.1, Fig. 2), solid-to-fluid interpolation (Eqs. 18-19) and
+  (Sec. 2.2, Fig. 2), solid-to-fluid interpolation (Eqs. 18-19) and
   fluid-to-solid spreading (Eq. 20) with the 4-point kernel (Eqs. 21-22);
 * body  (``body.py``)   -- rigid spring-damper oscillator with classic RK4
   (Eq. 12);

@@ -1,4 +1,4 @@
-"""Fluid sub-steps of the oracle (paper Sec. 2.2.1, Eqs. 4-10).
+"""Fluid sub-steps of the oracle (paper Sec. 2.3.1, Eqs. 4-10).
 
 Readings of the paper taken here (it only says "staggered FVM, second-order
 central or first-order upwind convection, central diffusion"):

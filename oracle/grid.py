@@ -1,4 +1,4 @@
-"""Staggered (MAC) grid metrics for the oracle -- Sec. 2.2.1 of the paper.
+"""Staggered (MAC) grid metrics for the oracle -- Sec. 2.3.1 of the paper.
 
 Pressure lives at cell centres and velocity component ``c`` on the faces
 normal to axis ``c`` (the west/south/bottom face of cell ``i`` carries

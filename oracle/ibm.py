@@ -1,8 +1,8 @@
-"""Immersed-boundary pieces of the oracle (paper Sec. 2.1 and Sec. 2.2.3).
+"""Immersed-boundary pieces of the oracle (paper Sec. 2.2 and Sec. 2.3.3).
 
 Readings taken here:
 
-* point classes (Sec. 2.1, Fig. 2) are evaluated per velocity component on
+* point classes (Sec. 2.2, Fig. 2) are evaluated per velocity component on
   that component's own face points.  A face point is *solid* if it lies
   inside the closed marker polygon (crossing-number test, half-open rule
   ``y_a <= y < y_b``, float64, evaluated as ``x < x_a + ((y - y_a)(x_b - x_a))

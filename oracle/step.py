@@ -2,7 +2,7 @@
 
 Order inside a step (Alg. 1, loop body):
 
-1. markers X_k = X0_k + d^n, point classes and forcing mask (Sec. 2.1);
+1. markers X_k = X0_k + d^n, point classes and forcing mask (Sec. 2.2);
 2. target / solid velocities from the body velocity (Eqs. 18-19, 23);
 3. predictor with direct forcing (Eqs. 4-5) and boundary faces;
 4. modified PPE (Eq. 9), exact solve, correction (Eq. 10);

@@ -1,7 +1,7 @@
 // Real FFT along a uniform periodic axis, in place of the dense contraction
 // with that axis' real Fourier eigenbasis (constant, cos / sin pairs of
 // increasing wavenumber, alternating sign for even N; the basis of the
-// periodic second-difference operator, Sec. 2.4's pressure operator on a
+// periodic second-difference operator, Sec. 2.5's pressure operator on a
 // uniform periodic axis).
 //
 // Two real lines are packed into one complex line z = x1 + i x2 and

@@ -1,7 +1,7 @@
 // Immersed-boundary kernels (2D): point classes, target velocities, loads
-// on the body and the rigid-body update (paper Sec. 2.1, Eqs. 12, 18-22).
+// on the body and the rigid-body update (paper Sec. 2.2, Eqs. 12, 18-22).
 //
-// Point classes (Sec. 2.1, Fig. 2) are evaluated per velocity component on
+// Point classes (Sec. 2.2, Fig. 2) are evaluated per velocity component on
 // that component's own face points inside a fixed-size window that follows
 // the body: solid = inside the closed marker polygon (crossing number,
 // half-open rule y_a <= y < y_b, double precision, no contraction of the
