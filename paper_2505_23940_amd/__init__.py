@@ -127,6 +127,8 @@ class Grid:
                  poisson_maxit: int = 100000, ir_maxit: int = 30, inner_rtol: float = 1e-4,
                  check_every: int = 64, solver: str = "fdm", device: str = "cuda:0"):
         self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         self.dim = int(dim)
         self.n = tuple(int(x) for x in n)
         self.precision = precision
@@ -209,14 +211,33 @@ class Grid:
         return out
 
     def _check_u(self, u, name="u"):
-        if len(u) != self.dim:
+        if u is None or len(u) != self.dim:
             raise ValueError(f"{name} needs {self.dim} components")
         for c in range(self.dim):
             t = u[c]
-            if tuple(t.shape) != tuple(self.layouts[c][0]) or t.dtype != self.dtype \
-                    or not t.is_contiguous() or t.device != self.device:
+            if not isinstance(t, torch.Tensor) or tuple(t.shape) != tuple(self.layouts[c][0]) \
+                    or t.dtype != self.dtype or not t.is_contiguous() or t.device != self.device:
                 raise ValueError(f"{name}[{c}] must be a contiguous {self.dtype} tensor of shape "
                                  f"{self.layouts[c][0]} on {self.device}")
+
+    def _check_t(self, t, name, shape=None, min_numel=None, required=True):
+        """A float64 tensor passed by pointer: contiguous, on the grid's
+        device, of the given shape or with at least min_numel elements.
+        Raises ValueError before anything is launched."""
+        if t is None:
+            if required:
+                raise ValueError(f"{name} is required")
+            return
+        ok = isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.is_contiguous() \
+            and t.device == self.device
+        if ok and shape is not None:
+            ok = tuple(t.shape) == tuple(shape)
+        if ok and min_numel is not None:
+            ok = t.numel() >= min_numel
+        if not ok:
+            what = f"shape {tuple(shape)}" if shape is not None else f">= {min_numel} elements"
+            raise ValueError(f"{name} must be a contiguous float64 tensor with {what} on "
+                             f"{self.device}")
 
     # ------------------------------------------------------------ body
     def set_body(self, kind: str, X0, ds, free_dof=(0, 0, 0), m: float = 1.0):
@@ -253,6 +274,13 @@ class Grid:
         u_out = u if u_out is None else u_out
         p_out = p if p_out is None else p_out
         body_out = body if body_out is None else body_out
+        self._check_u(u_out, "u_out")
+        self._check_t(p, "p", shape=self.pshape)
+        self._check_t(p_out, "p_out", shape=self.pshape)
+        self._check_t(body, "body", min_numel=6, required=self.has_body)
+        self._check_t(body_out, "body_out", min_numel=6, required=self.has_body)
+        self._check_t(kc, "kc", min_numel=6, required=False)
+        self._check_t(info, "info", min_numel=INFO_DOUBLES, required=False)
         fin = self._fields(u, p, fb, body, kc)
         fout = self._fields(u_out, p_out, fb, body_out, kc)
         rc = fvib_step(self.h, fin, fout, _ptr(info if info is not None else self._info))
@@ -271,9 +299,21 @@ class Grid:
         """Adjoint of one step (fvib_step_adjoint).  mu (optional, float64,
         pressure layout) warm-starts the adjoint Poisson solve and receives
         its solution."""
-        if mu is not None and (tuple(mu.shape) != tuple(self.pshape) or mu.dtype != torch.float64
-                               or not mu.is_contiguous() or mu.device != self.device):
-            raise ValueError(f"mu must be a contiguous float64 tensor of shape {self.pshape}")
+        self._check_u(u)
+        if fb is not None:
+            self._check_u(fb, "fb")
+        self._check_u(ubar_out, "ubar_out")
+        self._check_u(ubar_in, "ubar_in")
+        if fbbar is not None:
+            self._check_u(fbbar, "fbbar")
+        self._check_t(body, "body", min_numel=6, required=self.has_body)
+        self._check_t(kc, "kc", min_numel=6, required=False)
+        self._check_t(bodybar_out, "bodybar_out", min_numel=6, required=False)
+        self._check_t(bodybar_in, "bodybar_in", min_numel=6, required=self.has_body)
+        self._check_t(kcbar, "kcbar", min_numel=6, required=False)
+        self._check_t(dF, "dF", min_numel=3, required=False)
+        self._check_t(mu, "mu", shape=self.pshape, required=False)
+        self._check_t(info, "info", min_numel=INFO_DOUBLES, required=False)
         fin = self._fields(u, None, fb, body, kc)
         fin.p = 0
         bo = _abi.Adjoint()
