@@ -16,8 +16,10 @@ Workloads (all nondimensional, rho = 1, see the paper's validation cases):
 * ``channel``  -- 3D plane channel at Re_tau = 180 on a tanh-stretched
                   wall-normal grid, driven by a uniform body force
                   (Sec. 3.4.1 of the paper, Table 4).
-* ``viv``      -- 2D elastically mounted cylinder, 1-DOF transverse spring,
-                  m* = 2, U_r = 5, zeta = 0, Re = 150 (Sec. 3.2, Table 2).
+* ``viv``      -- 2D elastically mounted cylinder, 1-DOF transverse spring
+                  (or 2-DOF, equal springs in-line and cross-flow), m* = 2,
+                  U_r = 5, zeta = 0, Re = 150 (Sec. 3.2, Table 2); weak or
+                  strong coupling (Alg. 1 with N sub-iterations at most).
 
 Face arrays use the staggered (MAC) layout: component ``c`` lives on the
 faces normal to axis ``c``; arrays are C-contiguous in (z, y, x) order with
@@ -51,6 +53,8 @@ class Body:
     v0: tuple = (0.0, 0.0, 0.0)    # initial velocity
     diameter: float = 1.0
     u_ref: float = 1.0
+    coupling_iters: int = 1        # sub-iterations per step at most (1 = weak coupling)
+    coupling_tol: float = 1e-5     # coupling error that ends the sub-iterations
 
 
 @dataclass
@@ -166,7 +170,8 @@ def viv(nx: int = 1024, ny: int = 512, steps: int = 4000, dt: float = 4e-3,
         markers: int = 256, re: float = 150.0, mass_ratio: float = 2.0,
         u_r: float = 5.0, zeta: float = 0.0, d0: float = 0.1,
         precision: str = "fp32", lx: float = 32.0, ly: float = 16.0,
-        center=(8.0, 8.0)) -> Workload:
+        center=(8.0, 8.0), dof: int = 1, coupling_iters: int = 1,
+        coupling_tol: float = 1e-5) -> Workload:
     w = cylinder(nx=nx, ny=ny, steps=steps, dt=dt, markers=markers, re=re,
                  precision=precision, lx=lx, ly=ly, center=center)
     D = 1.0
@@ -175,9 +180,15 @@ def viv(nx: int = 1024, ny: int = 512, steps: int = 4000, dt: float = 4e-3,
     k = m * (2.0 * np.pi * fn) ** 2
     c = 2.0 * m * (2.0 * np.pi * fn) * zeta
     w.name = "viv"
-    w.body = Body("spring", w.body.X0, w.body.ds, free_dof=(0, 1, 0), m=m,
-                  k=(0.0, k, 0.0), c=(0.0, c, 0.0), d0=(0.0, d0, 0.0))
-    w.meta.update({"fn": fn, "mass_ratio": mass_ratio, "u_r": u_r})
+    if dof == 1:          # transverse (cross-flow) spring only
+        free, kk, cc = (0, 1, 0), (0.0, k, 0.0), (0.0, c, 0.0)
+    elif dof == 2:        # equal springs in-line and cross-flow (Sec. 3.2.2)
+        free, kk, cc = (1, 1, 0), (k, k, 0.0), (c, c, 0.0)
+    else:
+        raise ValueError(dof)
+    w.body = Body("spring", w.body.X0, w.body.ds, free_dof=free, m=m, k=kk, c=cc,
+                  d0=(0.0, d0, 0.0), coupling_iters=coupling_iters, coupling_tol=coupling_tol)
+    w.meta.update({"fn": fn, "mass_ratio": mass_ratio, "u_r": u_r, "dof": dof})
     return w
 
 
@@ -289,4 +300,8 @@ def by_name(name: str, size: str = "full") -> Workload:
         if size == "full":
             return viv()
         return viv(nx=256, ny=128, steps=20, markers=64, dt=4e-3)
+    if name == "viv2dof":       # 2-DOF, strongly coupled (Alg. 1, N <= 100, tol 1e-5)
+        if size == "full":
+            return viv(dof=2, coupling_iters=100)
+        return viv(nx=256, ny=128, steps=20, markers=64, dt=4e-3, dof=2, coupling_iters=100)
     raise KeyError(name)
