@@ -221,6 +221,21 @@ int fvib_step_adjoint(fvib_grid *g, const fvib_fields *fwd_in,
  * adds dJ/du into ubar[0] (dtype of the velocity). */
 int fvib_loss_wall_shear(fvib_grid *g, const void *u0, double *J, void *ubar0);
 
+/* Allocation-free variant of fvib_loss_wall_shear, for callers that
+ * cannot allocate device memory while they run (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, kernels and results (bit for bit) as fvib_loss_wall_shear;
+ * its block partial sums live in a static device array of the library
+ * (2 x 2048 doubles, 32 KiB per device, held until the process ends)
+ * instead of the handle's workspace, and the call allocates nothing.
+ * The launch is capped at 2048 blocks, so every wall plane fits; a launch
+ * that would need more slots than the array holds returns FVIB_EINVAL.
+ * The array is shared by every call on one device and keeps the last
+ * call's partial sums: calls that overlap on one device (different
+ * streams or threads) race.  FVIB_ESTATE if the array's address was not
+ * set up for the handle's device (done by fvib_create_grid). */
+int fvib_loss_wall_shear_noalloc(fvib_grid *g, const void *u0, double *J, void *ubar0);
+
 /* Root-mean-square lift coefficient of a force history:
  * J = sqrt(mean_n C_L^2), C_L = 2 F_y / (rho U^2 D).  Fh: nsteps rows of
  * `stride` doubles with F at offset `offset` (device).  Writes J (device)

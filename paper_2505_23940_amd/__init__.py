@@ -21,7 +21,7 @@ from ._abi import BC, BODY, CONV, PREC, SOLVER, STATUS_NAMES
 
 __all__ = ["Grid", "FvibError", "fvib_create_grid", "fvib_destroy_grid", "fvib_field_layout",
            "fvib_ib_set_body", "fvib_step", "fvib_step_adjoint", "fvib_loss_wall_shear",
-           "fvib_loss_rms_lift", "fvib_last_error", "fvib_version", "lib"]
+           "fvib_loss_wall_shear_noalloc", "fvib_loss_rms_lift", "fvib_last_error", "fvib_version", "lib"]
 
 
 class FvibError(RuntimeError):
@@ -84,6 +84,11 @@ def fvib_step_adjoint(h, fin: _abi.Fields, bar_out: _abi.Adjoint, dF_ptr: int,
 def fvib_loss_wall_shear(h, u0_ptr: int, J_ptr: int, ubar_ptr: int = 0) -> int:
     return lib().fvib_loss_wall_shear(h, C.c_void_p(u0_ptr), C.c_void_p(J_ptr),
                                       C.c_void_p(ubar_ptr))
+
+
+def fvib_loss_wall_shear_noalloc(h, u0_ptr: int, J_ptr: int, ubar_ptr: int = 0) -> int:
+    return lib().fvib_loss_wall_shear_noalloc(h, C.c_void_p(u0_ptr), C.c_void_p(J_ptr),
+                                              C.c_void_p(ubar_ptr))
 
 
 def fvib_loss_rms_lift(h, Fh_ptr: int, nsteps: int, stride: int, offset: int, u_ref: float,
@@ -220,6 +225,13 @@ class Grid:
                 raise ValueError(f"{name}[{c}] must be a contiguous {self.dtype} tensor of shape "
                                  f"{self.layouts[c][0]} on {self.device}")
 
+    def _check_comp(self, t, c, name):
+        """One velocity-like component c: contiguous, grid dtype and shape."""
+        if not isinstance(t, torch.Tensor) or tuple(t.shape) != tuple(self.layouts[c][0]) \
+                or t.dtype != self.dtype or not t.is_contiguous() or t.device != self.device:
+            raise ValueError(f"{name} must be a contiguous {self.dtype} tensor of shape "
+                             f"{self.layouts[c][0]} on {self.device}")
+
     def _check_t(self, t, name, shape=None, min_numel=None, required=True):
         """A float64 tensor passed by pointer: contiguous, on the grid's
         device, of the given shape or with at least min_numel elements.
@@ -334,9 +346,24 @@ class Grid:
 
     # --------------------------------------------------------- losses
     def loss_wall_shear(self, u0: torch.Tensor, ubar0: Optional[torch.Tensor] = None):
+        self._check_comp(u0, 0, "u0")
+        if ubar0 is not None:
+            self._check_comp(ubar0, 0, "ubar0")
         J = torch.zeros(1, dtype=torch.float64, device=self.device)
         _check(fvib_loss_wall_shear(self.h, _ptr(u0), _ptr(J), _ptr(ubar0)), self.h)
         return J
+
+    def loss_wall_shear_noalloc(self, u0: torch.Tensor, J: torch.Tensor,
+                                ubar0: Optional[torch.Tensor] = None) -> None:
+        """The allocation-free entry point: J (1 double on the device) and
+        ubar0 are the caller's; nothing is allocated by the call."""
+        self._check_comp(u0, 0, "u0")
+        if ubar0 is not None:
+            self._check_comp(ubar0, 0, "ubar0")
+        if not (isinstance(J, torch.Tensor) and J.dtype == torch.float64 and J.numel() >= 1
+                and J.device == self.device):
+            raise ValueError("J must be a float64 tensor of at least 1 element on the grid's device")
+        _check(fvib_loss_wall_shear_noalloc(self.h, _ptr(u0), _ptr(J), _ptr(ubar0)), self.h)
 
     def loss_rms_lift(self, Fh: torch.Tensor, stride: int, offset: int, u_ref: float = 1.0,
                       diameter: float = 1.0, dFh: Optional[torch.Tensor] = None):

@@ -22,7 +22,8 @@ DTYPE_F32, DTYPE_F64 = 0, 1
 
 EXPORTS = (
     "fvib_create_grid", "fvib_destroy_grid", "fvib_field_layout", "fvib_ib_set_body",
-    "fvib_step", "fvib_step_adjoint", "fvib_loss_wall_shear", "fvib_loss_rms_lift",
+    "fvib_step", "fvib_step_adjoint", "fvib_loss_wall_shear", "fvib_loss_wall_shear_noalloc",
+    "fvib_loss_rms_lift",
     "fvib_last_error", "fvib_test_momentum", "fvib_test_ppe_rhs", "fvib_test_poisson",
     "fvib_test_apply_A", "fvib_test_ib_classify", "fvib_timing_enable", "fvib_timing_select",
     "fvib_defer_status",
@@ -105,6 +106,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.fvib_step_adjoint.argtypes = [vp, C.POINTER(Fields), C.POINTER(Adjoint), vp,
                                       C.POINTER(Adjoint), vp]
     lib.fvib_loss_wall_shear.argtypes = [vp, vp, vp, vp]
+    lib.fvib_loss_wall_shear_noalloc.argtypes = [vp, vp, vp, vp]
     lib.fvib_loss_rms_lift.argtypes = [vp, vp, i32, i32, i32, C.c_double, C.c_double, vp, vp]
     lib.fvib_last_error.argtypes = [vp]
     lib.fvib_last_error.restype = C.c_char_p

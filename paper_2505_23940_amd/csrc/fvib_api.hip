@@ -106,6 +106,7 @@ struct Timer {
 struct Grid {
   fvib_grid_desc d;
   hipStream_t stream = nullptr;
+  int device = -1;                 // device current at creation (the stream's)
   hipEvent_t check_ev = nullptr;   // convergence checks wait on it (spinning)
   int dim = 0, prec = 0;
   int n[3] = {1, 1, 1};
@@ -1036,6 +1037,10 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
     delete h;
     return fail(nullptr, code, what);
   };
+  // the allocation-free loss finds its static scratch on this device
+  if (hipGetDevice(&g->device) != hipSuccess) return bail(FVIB_EHIP, "hipGetDevice failed");
+  if (noalloc_scratch_init(g->device) != FVIB_OK)
+    return bail(FVIB_EHIP, "address of the static scratch not found on this device");
   if (dmalloc(&g->md, m.size() * sizeof(double)) || dmalloc(&g->mf, mf.size() * sizeof(float)))
     return bail(FVIB_ENOMEM, "device allocation of metrics failed");
   if (hipMemcpy(g->md, m.data(), m.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
@@ -1488,23 +1493,50 @@ int fvib_test_ib_classify(fvib_grid* h, const double* body, uint8_t* cls[3]) {
   return FVIB_OK;
 }
 
-int fvib_loss_wall_shear(fvib_grid* h, const void* u0, double* J, void* ubar0) {
-  if (!h || !u0 || !J) return FVIB_EINVAL;
-  Grid* g = &h->g;
-  if (g->per[1] || g->d.bc[1][0] != FVIB_BC_NOSLIP || g->d.bc[1][1] != FVIB_BC_NOSLIP)
-    return fail(g, FVIB_EINVAL, "wall shear needs no-slip walls normal to y");
+static int wall_shear_run(Grid* g, const void* u0, double* J, void* ubar0, double* partial) {
   const std::vector<double>& y = g->faces[1];
   const int N = g->n[1];
   const double yc0 = 0.5 * (y[0] + y[1]), ycN = 0.5 * (y[N - 1] + y[N]);
   const double wlo = 0.5 * g->d.nu / (yc0 - y[0]);
   const double whi = 0.5 * g->d.nu / (y[N] - ycN);
   const int nx = g->ext[0][0], nz = g->ext[0][2];
-  int rc;
   if (g->prec == FVIB_PREC_FP64)
-    rc = launch_wall_shear<double>(nx, N, nz, (const double*)u0, (double*)ubar0, wlo, whi, J, g->partial, g->stream);
-  else
-    rc = launch_wall_shear<float>(nx, N, nz, (const float*)u0, (float*)ubar0, wlo, whi, J, g->partial, g->stream);
-  return rc;
+    return launch_wall_shear<double>(nx, N, nz, (const double*)u0, (double*)ubar0, wlo, whi, J,
+                                     partial, g->stream);
+  return launch_wall_shear<float>(nx, N, nz, (const float*)u0, (float*)ubar0, wlo, whi, J,
+                                  partial, g->stream);
+}
+
+static int wall_shear_check(Grid* g) {
+  if (g->per[1] || g->d.bc[1][0] != FVIB_BC_NOSLIP || g->d.bc[1][1] != FVIB_BC_NOSLIP)
+    return fail(g, FVIB_EINVAL, "wall shear needs no-slip walls normal to y");
+  return FVIB_OK;
+}
+
+int fvib_loss_wall_shear(fvib_grid* h, const void* u0, double* J, void* ubar0) {
+  if (!h || !u0 || !J) return FVIB_EINVAL;
+  Grid* g = &h->g;
+  int rc;
+  if ((rc = wall_shear_check(g))) return rc;
+  return wall_shear_run(g, u0, J, ubar0, g->partial);
+}
+
+int fvib_loss_wall_shear_noalloc(fvib_grid* h, const void* u0, double* J, void* ubar0) {
+  if (!h || !u0 || !J) return FVIB_EINVAL;
+  Grid* g = &h->g;
+  int rc;
+  if ((rc = wall_shear_check(g))) return rc;
+  int64_t cap = 0;
+  double* scr = noalloc_scratch(g->device, &cap);
+  if (!scr) return fail(g, FVIB_ESTATE, "static scratch address not set up on this device");
+  const int64_t need = wall_shear_slots(g->ext[0][0], g->ext[0][2]);
+  if (need > cap) {
+    char buf[160];
+    snprintf(buf, sizeof(buf), "wall plane needs %lld scratch slots, the static scratch holds %lld",
+             (long long)need, (long long)cap);
+    return fail(g, FVIB_EINVAL, buf);
+  }
+  return wall_shear_run(g, u0, J, ubar0, scr);
 }
 
 int fvib_loss_rms_lift(fvib_grid* h, const double* Fh, int nsteps, int stride, int offset,

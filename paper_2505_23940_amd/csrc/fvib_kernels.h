@@ -189,5 +189,13 @@ int launch_wall_shear(int nx, int ny, int nz, const T* u, T* ubar, double wlo, d
                       double* J, double* partial, hipStream_t s);
 int launch_rms_lift(const double* Fh, int S, int stride, int off, double g, double* J,
                     double* dFh, hipStream_t s);
+// Device address of the static scratch of the allocation-free wall-shear
+// loss on `device`: looked up once per device by noalloc_scratch_init (the
+// device must be current), then returned by noalloc_scratch (nullptr before
+// that); *slots receives its capacity in doubles.
+int noalloc_scratch_init(int device);
+double* noalloc_scratch(int device, int64_t* slots);
+// Partial-sum slots a wall-shear launch over an nx x nz wall plane uses.
+int64_t wall_shear_slots(int nx, int nz);
 
 }  // namespace fvib

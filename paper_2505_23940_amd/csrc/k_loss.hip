@@ -2,10 +2,41 @@
 // wall-bounded flow and the root-mean-square lift coefficient of a force
 // history.  Each writes J and, optionally, its gradient.
 #include <algorithm>
+#include <mutex>
 
 #include "fvib_kernels.h"
 
 namespace fvib {
+
+// Scratch of the allocation-free wall-shear loss: the block partial sums in
+// the layout of block_partials (2 sums x kMaxRedBlocks slots, 32 KiB).  Each
+// device holds its own copy until the process ends.  Host code never passes
+// the array's name to a kernel: it looks the device address up once per
+// device (noalloc_scratch_init) and passes that.
+constexpr int kNoAllocSlots = 2 * kMaxRedBlocks;
+static __device__ __align__(256) double scratch[kNoAllocSlots];
+
+constexpr int kMaxDevices = 64;
+static double* g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+int noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return FVIB_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return FVIB_OK;
+  double* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)", __FILE__, __LINE__);
+  g_scratch_ptr[device] = ptr;
+  return FVIB_OK;
+}
+
+double* noalloc_scratch(int device, int64_t* slots) {
+  if (slots) *slots = kNoAllocSlots;
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 // J = (nu / 2) [ <u>_lo / (yc_0 - y_0) + <u>_hi / (y_N - yc_{N-1}) ], the
 // x-z means taken over the streamwise faces of the two wall-adjacent rows.
@@ -59,11 +90,21 @@ k_rms_lift(const double* __restrict__ Fh, int S, int stride, int off, double g, 
   }
 }
 
+static int wall_shear_blocks(int nx, int nz) {
+  const int64_t plane = (int64_t)nx * nz;
+  return (int)std::min<int64_t>((plane + kBlock - 1) / kBlock, kMaxRedBlocks);
+}
+
+// block_partials<2, 2> writes slot q * kMaxRedBlocks + block for q = 0, 1
+int64_t wall_shear_slots(int nx, int nz) {
+  return (int64_t)kMaxRedBlocks + wall_shear_blocks(nx, nz);
+}
+
 template <typename T>
 int launch_wall_shear(int nx, int ny, int nz, const T* u, T* ubar, double wlo, double whi,
                       double* J, double* partial, hipStream_t s) {
   const int64_t plane = (int64_t)nx * nz;
-  int nb = (int)std::min<int64_t>((plane + kBlock - 1) / kBlock, kMaxRedBlocks);
+  const int nb = wall_shear_blocks(nx, nz);
   launch_kernel((k_wall_shear<T>), dim3(nb), dim3(kBlock), 0, s, nx, ny, nz, u, ubar, wlo,
                      whi, partial);
   FVIB_HIP(hipGetLastError());
