@@ -47,6 +47,8 @@ def kernel_cost(d: int, s: int, mixed: bool, n: tuple, solver: str = "fdm"):
         "ir_correct": ("bytes", 8 + v + 8),                # read p, d; write p
         "project": ("bytes", 2 * d * s + 8 + pg),          # read u*, p; write u (and p)
         "adj_momentum": ("bytes", 5 * d * s),              # read u, ustar_bar; write ubar; rw fbbar
+        "adj_rhs": ("bytes", d * s + 8),                   # read ubar; write G^T ubar
+        "adj_ustar": ("bytes", 2 * d * s + 8),             # read ubar, mu; write ustar_bar
         "fdm_x": ("flops", 2 * n[0]),                      # dense contraction along x
         "fdm_y": ("flops", 2 * n[1]),
         "fdm_z": ("flops", 2 * n[2]),
@@ -55,6 +57,28 @@ def kernel_cost(d: int, s: int, mixed: bool, n: tuple, solver: str = "fdm"):
         "fft": ("bytes", 2 * v),                           # read and write one vector
         "fft_acc": ("bytes", v + 16),                      # read d; read and write p
     }
+
+
+def other_workloads(precision, tol, solver, steps=20):
+    """Mcell-updates/s of the other four workloads at their full sizes, same
+    precision and solver: forward + adjoint (K = 1) and forward only, over
+    `steps` steps after a warm-up of the same length."""
+    import fvib_workloads as W
+    res = {}
+    for name in ("tgv2d", "tgv3d", "cylinder", "viv"):
+        w = W.by_name(name, "full")
+        g, ut, fbt, body, kc = setup(w, precision, tol, solver)
+        fwd_adj_pass(g, w, ut, fbt, body, kc, steps, 1)
+        el, _ = timed(lambda: fwd_adj_pass(g, w, ut, fbt, body, kc, steps, 1))
+        elf, info = timed(lambda: fwd_pass(g, ut, fbt, body, kc, steps))
+        g.check_infos(info, "forward step")
+        res[name] = {"cells": w.ncells, "steps": steps,
+                     "fwd_adj_value": round(w.ncells * steps / el / 1e6, 3),
+                     "fwd_value": round(w.ncells * steps / elf / 1e6, 3)}
+        print(f"[bench] {name}: fwd+adj {res[name]['fwd_adj_value']} Mcell/s, "
+              f"fwd {res[name]['fwd_value']} Mcell/s", file=sys.stderr, flush=True)
+        del g
+    return res
 
 
 def parse():
@@ -104,7 +128,16 @@ def fwd_adj_pass(g, w, ut, fbt, body, kc, steps, ckpt):
     kcr = kc.detach().clone().requires_grad_(True)
     uS, bS, Fh, _ = rollout(g, [x.clone() for x in ut], fb, kcr, body.clone(), steps,
                             ckpt_every=ckpt)
-    J = wall_shear(g, uS[0]) if w.body is None else rms_lift(g, Fh)
+    if w.body is not None:
+        J = rms_lift(g, Fh)
+    elif w.bc[1] == ["noslip", "noslip"]:
+        J = wall_shear(g, uS[0])
+    else:
+        # no loss of the paper's applies (periodic box): seed the adjoint
+        # with a unit adjoint of the final streamwise velocity
+        import torch
+        torch.autograd.backward(uS[0], grad_tensors=torch.ones_like(uS[0]))
+        return torch.zeros(())
     J.backward()
     return J
 
@@ -136,33 +169,61 @@ def timed(fn):
     return time.perf_counter() - t0, out
 
 
+def host_cpu():
+    """Model name and logical CPU count of the host (as lscpu / nproc show)."""
+    model = "?"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
 def cpu_baseline(w, budget_s):
-    """The oracle as it stands: forward steps on the host cores."""
+    """The oracle as it stands, forward + adjoint like `value`: a rollout
+    with autograd through every step (float64, exact Poisson solves), the
+    same loss, backward to the body-force field; 2 warm-up steps, then 5
+    timed steps, then 20 if the budget allows (the longer run is reported)."""
     import torch
     import fvib_workloads as W
-    from oracle import Grid, init_state, make_params, step
+    from oracle import Grid, init_state, make_params
+    from oracle.step import rms_lift, rollout, wall_shear
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     cores = max(1, min(cores, os.cpu_count() or 1))
     torch.set_num_threads(cores)
     og = Grid(w)
     u0, fb = W.initial_fields(w)
-    st = init_state(og, u0, W.body_state0(w))
-    pr = make_params(og, fb)
-    with torch.no_grad():
-        st, _ = step(og, st, pr)                 # warm-up (builds the eigenbases)
-        n = 0
+
+    def fwd_adj(n):
+        st = init_state(og, u0, W.body_state0(w))
+        pr = make_params(og, fb)
+        pr["fb"] = [x.clone().requires_grad_(True) for x in pr["fb"]]
+        st, Fh, _ = rollout(og, st, pr, n)
+        J = wall_shear(og, st["u"]) if w.body is None else rms_lift(og, Fh)
+        J.backward()
+
+    fwd_adj(2)                                    # warm-up (builds the eigenbases)
+    n = 5
+    t0 = time.perf_counter()
+    fwd_adj(n)
+    dt = time.perf_counter() - t0
+    if dt * 5.0 < budget_s:
+        n = 20
         t0 = time.perf_counter()
-        while True:
-            st, _ = step(og, st, pr)
-            n += 1
-            if time.perf_counter() - t0 > budget_s:
-                break
+        fwd_adj(n)
         dt = time.perf_counter() - t0
+    model, nproc = host_cpu()
     return {"value": round(w.ncells * n / dt / 1e6, 3), "unit": "Mcell-updates/s",
             "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"{n} forward steps (float64, exact Poisson solve by per-axis "
-                      f"eigen-decomposition) of the same workload in {dt:.1f} s; the oracle's "
-                      f"own autograd adjoint is not timed"}
+            "sample": f"{n}-step rollout of the same workload, forward + autograd adjoint "
+                      f"(float64, exact Poisson solve by per-axis eigen-decomposition, loss "
+                      f"and backward to the body force as in `value`) in {dt:.1f} s after a "
+                      f"2-step warm-up",
+            "host": {"nproc": nproc, "cpu": model}}
 
 
 TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
@@ -191,6 +252,24 @@ def measured_traffic(kernel_class):
         if cur != digest:
             return None
     return entry["traffic_bytes"]
+
+
+def step_bytes(table, w, mixed, solver, nsteps):
+    """Algorithmic HBM bytes of one step summed over the kernel classes of a
+    timed pass of `nsteps` steps (launch counts of that pass; matrix-core
+    contractions count their one read and one write of the vector)."""
+    s = 4 if mixed else 8
+    v = 4 if mixed else 8
+    cost = kernel_cost(w.dim, s, mixed, w.n, solver)
+    total, unmodeled = 0.0, []
+    for name, row in table.items():
+        if name not in cost:
+            unmodeled.append(name)
+            continue
+        kind, per_cell = cost[name]
+        per_cell = per_cell if kind == "bytes" else 2 * v
+        total += per_cell * w.ncells * row["launches"]
+    return total / nsteps, sorted(unmodeled)
 
 
 def dominant(table, w, mixed, solver):
@@ -250,15 +329,17 @@ def main():
     # class bracketed by HIP events -> per-class table and dominant kernel
     nw = max(1, a.warmup)
     fwd_adj_pass(g, w, ut, fbt, body, kc, nw, a.ckpt)
+    # the table pass has the timed run's length, so its launch counts per
+    # step (refinement sweeps included) are those of the timed run
     g.timing_enable(True)
-    fwd_adj_pass(g, w, ut, fbt, body, kc, nw, a.ckpt)
+    fwd_adj_pass(g, w, ut, fbt, body, kc, a.steps, a.ckpt)
     _, table = roofline(g.timing_read(), w, a.precision, mixed, a.solver)
     for name, (ms, nl) in g.timing_read(skipped=True).items():
         if nl and name in table:
             table[name]["skipped"] = nl
     g.timing_enable(False)
     dom = dominant(table, w, mixed, a.solver)
-    print(f"[bench] warmup done ({nw} + {nw} steps); dominant kernel {dom}",
+    print(f"[bench] warmup done ({nw} + {a.steps} steps); dominant kernel {dom}",
           file=sys.stderr, flush=True)
     # timed region: only a sample of the dominant class's launches carries
     # events, so the run stays close to an untimed one
@@ -300,7 +381,19 @@ def main():
         "roofline": rl,
         "kernels_table_pass": table,
     }
+    sb, unmod = step_bytes(table, w, mixed, a.solver, a.steps)
+    ach = sb / (el / a.steps) / 1e9
+    out["roofline_step"] = {"bound": "hbm", "model_bytes_per_step": round(sb),
+                            "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": round(ach / HBM_PEAK_GBS, 4),
+                            "launch_counts": f"kernel table pass ({a.steps} steps)",
+                            "classes_without_model": unmod}
     if not a.no_extra:
+        if a.ckpt != 20 and a.steps >= 20:
+            el20, _ = timed(lambda: fwd_adj_pass(g, w, ut, fbt, body, kc, a.steps, 20))
+            out["ckpt20_value"] = round(ncell * a.steps / el20 / 1e6, 3)
+            print(f"[bench] fwd+adj K=20 {a.steps} steps in {el20:.3f} s", file=sys.stderr,
+                  flush=True)
         gi = g
         el_f, info = timed(lambda: fwd_pass(gi, ut, fbt, body, kc, a.steps))
         gi.check_infos(info, "forward step")
@@ -319,6 +412,8 @@ def main():
             out["fp64_value"] = round(ncell * n64 / el64 / 1e6, 3)
             out["fp32_over_fp64"] = round(value / out["fp64_value"], 3)
             print(f"[bench] fp64 fwd+adj {n64} steps in {el64:.3f} s", file=sys.stderr, flush=True)
+    if not a.no_extra and a.workload == "channel":
+        out["other_workloads"] = other_workloads(a.precision, a.tol, a.solver)
     if a.copy_probe:
         import torch
         src = torch.ones(64 << 20, dtype=torch.float32, device=g.device)

@@ -162,11 +162,14 @@ typedef struct {
   int32_t status;           /* FVIB_OK or a negative status                    */
   int32_t cg_iters;         /* total CG iterations of the step                 */
   int32_t ir_iters;         /* refinement sweeps (mixed mode), else 0          */
-  int32_t flags;            /* reserved                                        */
+  int32_t flags;            /* bit 0: body window clamped; bits 8-23: coupling
+                               sub-iterations of a strongly coupled step (Alg. 1),
+                               0 for a weakly coupled one                       */
   double res;               /* final max |div| estimate of the Poisson solve   */
   double div_max;           /* max |D u^{n+1}| in double before storage        */
   double force[3];          /* fluid force on the body F^n (Eq. 20, summed)    */
-  double reserved;
+  double xi;                /* coupling error of the last sub-iteration
+                               (strongly coupled step), else 0                 */
 } fvib_step_info;
 
 /* Create a grid handle.  Validates the descriptor (paired periodic sides,
@@ -215,6 +218,38 @@ int fvib_step_adjoint(fvib_grid *g, const fvib_fields *fwd_in,
                       const fvib_adjoint *bar_out, const double *dF,
                       fvib_adjoint *bar_in, fvib_step_info *info);
 
+/* One strongly coupled time step (Alg. 1 with N = max_iters, Sec. 2.3.3):
+ * the structural iterate starts at the time level w^n = in->body; each
+ * coupling sub-iteration advances the fluid from u^n with the body placed
+ * and moving as the current iterate (point classes, target velocities,
+ * predictor with direct forcing, Eqs. 4-5, 18-23), takes its loads
+ * (Eq. 20) and advances the structure from w^n under them (Eq. 12, RK4)
+ * to the next iterate; the coupling error xi = |w_k - w_{k-1}|^2 /
+ * max(|w_{k-1}|^2, 1e-30) ends the sub-iterations once xi < tol, or after
+ * max_iters (1 <= max_iters <= 65535; max_iters = 1 is fvib_step).  The
+ * modified PPE (Eq. 9) and the correction (Eq. 10) do not feed the loads
+ * and run once, with the body at the last iterate the fluid saw.  out->body
+ * receives the last structural update; omega (device, 6 doubles, may be
+ * NULL, may not alias a body state) receives the iterate the fluid saw
+ * last, which fvib_step_strong_adjoint needs.  info->flags bits 8-23 hold
+ * the sub-iteration count, info->xi the last coupling error.  The host
+ * reads the coupling error after each sub-iteration (one stream
+ * synchronisation per sub-iteration).  Needs a body (FVIB_ESTATE). */
+int fvib_step_strong(fvib_grid *g, const fvib_fields *in, fvib_fields *out, int32_t max_iters,
+                     double tol, double *omega, fvib_step_info *info);
+
+/* Adjoint of fvib_step_strong by implicit differentiation of the coupling
+ * fixed point (Eq. 24, Sec. 2.4.1), at the iterate omega the forward step
+ * returned (point classes frozen at omega).  With Phi(w) the structural
+ * update from w^n under the loads of the fluid seen with the body at w,
+ * the fixed-point adjoint lam solves (I - dPhi/dw^T) lam = bar_out->body +
+ * dL/domega (6 x 6, on the device); u^n, f_b, w^n, k and c then receive the
+ * partial derivatives of L + lam . Phi at fixed omega.  Arguments and
+ * outputs as in fvib_step_adjoint. */
+int fvib_step_strong_adjoint(fvib_grid *g, const fvib_fields *fwd_in, const double *omega,
+                             const fvib_adjoint *bar_out, const double *dF,
+                             fvib_adjoint *bar_in, fvib_step_info *info);
+
 /* Mean wall shear J = (nu/2) [ <u>_lo / (yc_0 - y_0) + <u>_hi / (y_N - yc_{N-1}) ]
  * of the streamwise velocity at the two wall-adjacent rows (walls normal
  * to y, at rest).  Writes J (1 double, device) and, if ubar is not NULL,
@@ -247,6 +282,18 @@ int fvib_loss_rms_lift(fvib_grid *g, const double *Fh, int nsteps, int stride,
 /* Message of the last error on this handle ("" if none). */
 const char *fvib_last_error(const fvib_grid *g);
 
+/* Device-side failures are sticky (the error behaviour the paper's solver
+ * loop needs when a step of Alg. 2 fails): once a step or adjoint step has
+ * met one -- FVIB_ENOCONV, FVIB_ENONFINITE, or FVIB_EINVAL for a body that
+ * left its window -- that call and every later fvib_step /
+ * fvib_step_adjoint on the handle return it without enqueuing work.  With
+ * deferred status the step record's kernel also stores a failed status in
+ * a pinned word that the next step call reads, so a failure the host has
+ * not yet looked at stops the calls that follow it once the failed step
+ * has run.  fvib_clear_error synchronises the stream and resets the state
+ * (the fields of the failed step are not restored). */
+int fvib_clear_error(fvib_grid *g);
+
 /* ---------------------------------------------------------------------
  * Sub-step entry points for parity tests.  Same layouts as above; every
  * pointer is a device pointer.
@@ -268,6 +315,53 @@ int fvib_test_poisson(fvib_grid *g, const double *b, double *p, int32_t *iters);
 /* Matrix-free A p of the volume-integrated PPE operator (double). */
 int fvib_test_apply_A(fvib_grid *g, const double *p, double *Ap);
 
+/* Velocity correction of Eq. 10: u = ustar - (dt/rho) G p on the faces the
+ * correction acts on (boundary-normal faces of bounded axes keep ustar);
+ * *div_max (device, may be NULL) = max over cells of |D u| in double before
+ * rounding to the velocity type (Eq. 8).  u may not alias ustar. */
+int fvib_test_project(fvib_grid *g, const void *const ustar[3], const double *p, void *u[3],
+                      double *div_max);
+
+/* Adjoint of fvib_test_project with respect to the pressure (Sec. 2.4.1):
+ * pbar = -(dt/rho) G^T ubar (cells, double); the adjoint with respect to
+ * ustar is ubar itself. */
+int fvib_test_project_adjoint(fvib_grid *g, const void *const ubar[3], double *pbar);
+
+/* Target velocity of Eqs. 18-19 and 23 of the attached body at state body
+ * (6 doubles): u_s on every forced face (solid and immersed-boundary
+ * points) of component c written into the full face array us[c], 0 on the
+ * other faces. */
+int fvib_test_ib_target(fvib_grid *g, const double *body, void *us[3]);
+
+/* Adjoint of fvib_test_ib_target: adds into bodybar[3 + c] the sum of
+ * usbar[c] over the forced faces (the normalised interpolation returns the
+ * rigid velocity exactly, so the marker positions do not enter). */
+int fvib_test_ib_target_adjoint(fvib_grid *g, const double *body, const void *const usbar[3],
+                                double *bodybar);
+
+/* Loads of Eq. 20 summed as in Eq. 12: F (3 doubles) = rho sum_k q_k dV_k of
+ * the forcing field f (full face arrays; only the forced faces of the body
+ * at state body are read). */
+int fvib_test_ib_loads(fvib_grid *g, const double *body, const void *const f[3], double *F);
+
+/* Adjoint of fvib_test_ib_loads for a force adjoint Fbar (3 doubles):
+ * writes fbar (full face arrays, 0 off the forced faces) and adds the
+ * marker-position part into bodybar[0..1]. */
+int fvib_test_ib_loads_adjoint(fvib_grid *g, const double *body, const void *const f[3],
+                               const double *Fbar, void *fbar[3], double *bodybar);
+
+/* Rigid-body update of Eq. 12: one classic RK4 step of the body state under
+ * a force F (3 doubles) held over the step; kc = [k(3), c(3)] (NULL = 0);
+ * fixed degrees of freedom keep their values. */
+int fvib_test_body_rk4(fvib_grid *g, const double *body, const double *F, const double *kc,
+                       double *body_out);
+
+/* Adjoint of fvib_test_body_rk4: writes bodybar_in (6) and Fbar (3) and adds
+ * into kcbar (6, may be NULL). */
+int fvib_test_body_rk4_adjoint(fvib_grid *g, const double *body, const double *F,
+                               const double *kc, const double *bodybar_out, double *bodybar_in,
+                               double *Fbar, double *kcbar);
+
 /* Point classes of the current body at displacement body[0..2]: writes
  * one byte per face (0 fluid, 1 solid, 2 immersed-boundary point) into
  * cls[c] (full face arrays). */
@@ -288,7 +382,7 @@ enum {
   FVIB_K_IR_CORRECT = 6,  /* refinement correction                         */
   FVIB_K_PROJECT = 7,     /* Eq. 10 correction + divergence check          */
   FVIB_K_IB = 8,          /* point classes, targets, loads, RK4            */
-  FVIB_K_ADJOINT = 9,     /* adjoint stencils                              */
+  FVIB_K_ADJOINT = 9,     /* other adjoint stencils (boundary faces)       */
   FVIB_K_FDM_X = 10,      /* fast-diagonalisation contraction along x      */
   FVIB_K_FDM_Y = 11,      /* ... along y                                   */
   FVIB_K_FDM_Z = 12,      /* ... along z                                   */
@@ -296,7 +390,9 @@ enum {
   FVIB_K_FDM_LAST = 14,   /* last axis: forward, division and inverse in one */
   FVIB_K_FFT = 15,        /* real FFT along a uniform periodic axis          */
   FVIB_K_FFT_ACC = 16,    /* last inverse FFT of a sweep, adding into p      */
-  FVIB_K_NCLASSES = 17
+  FVIB_K_ADJ_RHS = 17,    /* adjoint Poisson right-hand side G^T ubar        */
+  FVIB_K_ADJ_USTAR = 18,  /* adjoint predicted velocity from the solution    */
+  FVIB_K_NCLASSES = 19
 };
 
 /* Start (enable != 0, totals cleared) or stop recording.  A recorded

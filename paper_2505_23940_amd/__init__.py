@@ -20,7 +20,8 @@ from . import _abi
 from ._abi import BC, BODY, CONV, PREC, SOLVER, STATUS_NAMES
 
 __all__ = ["Grid", "FvibError", "fvib_create_grid", "fvib_destroy_grid", "fvib_field_layout",
-           "fvib_ib_set_body", "fvib_step", "fvib_step_adjoint", "fvib_loss_wall_shear",
+           "fvib_ib_set_body", "fvib_step", "fvib_step_adjoint", "fvib_step_strong",
+           "fvib_step_strong_adjoint", "fvib_loss_wall_shear",
            "fvib_loss_wall_shear_noalloc", "fvib_loss_rms_lift", "fvib_last_error", "fvib_version", "lib"]
 
 
@@ -75,6 +76,19 @@ def fvib_step(h, fin: _abi.Fields, fout: _abi.Fields, info_ptr: int = 0) -> int:
     return lib().fvib_step(h, C.byref(fin), C.byref(fout), C.c_void_p(info_ptr))
 
 
+def fvib_step_strong(h, fin: _abi.Fields, fout: _abi.Fields, max_iters: int, tol: float,
+                     omega_ptr: int = 0, info_ptr: int = 0) -> int:
+    return lib().fvib_step_strong(h, C.byref(fin), C.byref(fout), int(max_iters), float(tol),
+                                  C.c_void_p(omega_ptr), C.c_void_p(info_ptr))
+
+
+def fvib_step_strong_adjoint(h, fin: _abi.Fields, omega_ptr: int, bar_out: _abi.Adjoint,
+                             dF_ptr: int, bar_in: _abi.Adjoint, info_ptr: int = 0) -> int:
+    return lib().fvib_step_strong_adjoint(h, C.byref(fin), C.c_void_p(omega_ptr),
+                                          C.byref(bar_out), C.c_void_p(dF_ptr), C.byref(bar_in),
+                                          C.c_void_p(info_ptr))
+
+
 def fvib_step_adjoint(h, fin: _abi.Fields, bar_out: _abi.Adjoint, dF_ptr: int,
                       bar_in: _abi.Adjoint, info_ptr: int = 0) -> int:
     return lib().fvib_step_adjoint(h, C.byref(fin), C.byref(bar_out), C.c_void_p(dF_ptr),
@@ -115,10 +129,13 @@ def parse_info(t: torch.Tensor) -> dict:
     ints = raw.view(torch.int32).view(-1, 2 * INFO_DOUBLES)
     out = []
     for r in range(raw.shape[0]):
+        fl = int(ints[r, 3])
         out.append({"status": int(ints[r, 0]), "cg_iters": int(ints[r, 1]),
-                    "ir_iters": int(ints[r, 2]), "flags": int(ints[r, 3]),
+                    "ir_iters": int(ints[r, 2]), "flags": fl, "clamp": fl & 1,
+                    "coupling_iters": (fl >> 8) & 0xFFFF,
                     "res": float(raw[r, 2]), "div_max": float(raw[r, 3]),
-                    "force": [float(raw[r, 4]), float(raw[r, 5]), float(raw[r, 6])]})
+                    "force": [float(raw[r, 4]), float(raw[r, 5]), float(raw[r, 6])],
+                    "xi": float(raw[r, 7])})
     return out[0] if len(out) == 1 else out
 
 
@@ -278,8 +295,12 @@ class Grid:
         return f
 
     def step(self, u, p, fb=None, body=None, kc=None, u_out=None, p_out=None, body_out=None,
-             info: Optional[torch.Tensor] = None, check: bool = True) -> int:
-        """One time step; in place unless *_out are given.  Returns the status."""
+             info: Optional[torch.Tensor] = None, check: bool = True, coupling=None,
+             omega: Optional[torch.Tensor] = None) -> int:
+        """One time step; in place unless *_out are given.  Returns the status.
+        coupling = (max_iters, tol) makes it the strongly coupled step
+        (fvib_step_strong); omega (6 doubles) then receives the iterate the
+        fluid saw last, which its adjoint needs."""
         self._check_u(u)
         if fb is not None:
             self._check_u(fb, "fb")
@@ -293,9 +314,15 @@ class Grid:
         self._check_t(body_out, "body_out", min_numel=6, required=self.has_body)
         self._check_t(kc, "kc", min_numel=6, required=False)
         self._check_t(info, "info", min_numel=INFO_DOUBLES, required=False)
+        self._check_t(omega, "omega", min_numel=6, required=False)
         fin = self._fields(u, p, fb, body, kc)
         fout = self._fields(u_out, p_out, fb, body_out, kc)
-        rc = fvib_step(self.h, fin, fout, _ptr(info if info is not None else self._info))
+        ip = _ptr(info if info is not None else self._info)
+        if coupling is None:
+            rc = fvib_step(self.h, fin, fout, ip)
+        else:
+            nmax, tol = coupling
+            rc = fvib_step_strong(self.h, fin, fout, nmax, tol, _ptr(omega), ip)
         if check:
             _check(rc, self.h)
         return rc
@@ -307,10 +334,12 @@ class Grid:
     def step_adjoint(self, u, fb, body, kc, ubar_out, bodybar_out, dF, ubar_in, bodybar_in,
                      fbbar=None, kcbar=None, check: bool = True,
                      info: Optional[torch.Tensor] = None,
-                     mu: Optional[torch.Tensor] = None) -> int:
+                     mu: Optional[torch.Tensor] = None,
+                     omega: Optional[torch.Tensor] = None) -> int:
         """Adjoint of one step (fvib_step_adjoint).  mu (optional, float64,
         pressure layout) warm-starts the adjoint Poisson solve and receives
-        its solution."""
+        its solution.  With omega (the iterate a strongly coupled step
+        returned) it is the adjoint of that step (fvib_step_strong_adjoint)."""
         self._check_u(u)
         if fb is not None:
             self._check_u(fb, "fb")
@@ -338,8 +367,12 @@ class Grid:
         bi.body = _ptr(bodybar_in)
         bi.kc = _ptr(kcbar)
         bi.mu = _ptr(mu)
-        rc = fvib_step_adjoint(self.h, fin, bo, _ptr(dF), bi,
-                               _ptr(info if info is not None else self._info))
+        ip = _ptr(info if info is not None else self._info)
+        if omega is None:
+            rc = fvib_step_adjoint(self.h, fin, bo, _ptr(dF), bi, ip)
+        else:
+            self._check_t(omega, "omega", min_numel=6)
+            rc = fvib_step_strong_adjoint(self.h, fin, _ptr(omega), bo, _ptr(dF), bi, ip)
         if check:
             _check(rc, self.h)
         return rc
@@ -443,6 +476,80 @@ class Grid:
         y = torch.empty_like(p)
         _check(lib().fvib_test_apply_A(self.h, _ptr(p), _ptr(y)), self.h)
         return y
+
+    def _arr3(self, ts):
+        vp = C.c_void_p * 3
+        return vp(*([_ptr(t) for t in ts] + [0] * (3 - len(ts))))
+
+    def test_project(self, ustar, p: torch.Tensor):
+        """Eq. 10 alone: returns (u, div_max)."""
+        self._check_u(ustar, "ustar")
+        self._check_t(p, "p", shape=self.pshape)
+        u = self.zeros_u()
+        dm = torch.zeros(1, dtype=torch.float64, device=self.device)
+        _check(lib().fvib_test_project(self.h, self._arr3(ustar), _ptr(p), self._arr3(u),
+                                       _ptr(dm)), self.h)
+        return u, float(dm[0])
+
+    def test_project_adjoint(self, ubar) -> torch.Tensor:
+        self._check_u(ubar, "ubar")
+        pbar = self.zeros_p()
+        _check(lib().fvib_test_project_adjoint(self.h, self._arr3(ubar), _ptr(pbar)), self.h)
+        return pbar
+
+    def test_ib_target(self, body: torch.Tensor) -> List[torch.Tensor]:
+        self._check_t(body, "body", min_numel=6)
+        us = self.zeros_u()
+        _check(lib().fvib_test_ib_target(self.h, _ptr(body), self._arr3(us)), self.h)
+        return us
+
+    def test_ib_target_adjoint(self, body: torch.Tensor, usbar, bodybar: torch.Tensor) -> None:
+        self._check_t(body, "body", min_numel=6)
+        self._check_u(usbar, "usbar")
+        self._check_t(bodybar, "bodybar", min_numel=6)
+        _check(lib().fvib_test_ib_target_adjoint(self.h, _ptr(body), self._arr3(usbar),
+                                                 _ptr(bodybar)), self.h)
+
+    def test_ib_loads(self, body: torch.Tensor, f) -> torch.Tensor:
+        self._check_t(body, "body", min_numel=6)
+        self._check_u(f, "f")
+        F = torch.zeros(3, dtype=torch.float64, device=self.device)
+        _check(lib().fvib_test_ib_loads(self.h, _ptr(body), self._arr3(f), _ptr(F)), self.h)
+        return F
+
+    def test_ib_loads_adjoint(self, body: torch.Tensor, f, Fbar: torch.Tensor,
+                              bodybar: torch.Tensor) -> List[torch.Tensor]:
+        self._check_t(body, "body", min_numel=6)
+        self._check_u(f, "f")
+        self._check_t(Fbar, "Fbar", min_numel=3)
+        self._check_t(bodybar, "bodybar", min_numel=6)
+        fbar = self.zeros_u()
+        _check(lib().fvib_test_ib_loads_adjoint(self.h, _ptr(body), self._arr3(f), _ptr(Fbar),
+                                                self._arr3(fbar), _ptr(bodybar)), self.h)
+        return fbar
+
+    def test_body_rk4(self, body: torch.Tensor, F: torch.Tensor, kc: torch.Tensor) -> torch.Tensor:
+        for t, n, m in ((body, "body", 6), (F, "F", 3), (kc, "kc", 6)):
+            self._check_t(t, n, min_numel=m)
+        out = torch.zeros(6, dtype=torch.float64, device=self.device)
+        _check(lib().fvib_test_body_rk4(self.h, _ptr(body), _ptr(F), _ptr(kc), _ptr(out)), self.h)
+        return out
+
+    def test_body_rk4_adjoint(self, body, F, kc, bodybar_out, kcbar):
+        """Returns (bodybar_in, Fbar); adds into kcbar."""
+        for t, n, m in ((body, "body", 6), (F, "F", 3), (kc, "kc", 6),
+                        (bodybar_out, "bodybar_out", 6), (kcbar, "kcbar", 6)):
+            self._check_t(t, n, min_numel=m)
+        bin_ = torch.zeros(6, dtype=torch.float64, device=self.device)
+        Fbar = torch.zeros(3, dtype=torch.float64, device=self.device)
+        _check(lib().fvib_test_body_rk4_adjoint(self.h, _ptr(body), _ptr(F), _ptr(kc),
+                                                _ptr(bodybar_out), _ptr(bin_), _ptr(Fbar),
+                                                _ptr(kcbar)), self.h)
+        return bin_, Fbar
+
+    def clear_error(self) -> None:
+        """Reset the handle after a device-side failure (fvib_clear_error)."""
+        _check(lib().fvib_clear_error(self.h), self.h)
 
     def test_ib_classify(self, body: torch.Tensor) -> List[torch.Tensor]:
         cls = [torch.zeros(self.layouts[c][0], dtype=torch.uint8, device=self.device) for c in range(2)]

@@ -22,10 +22,14 @@ DTYPE_F32, DTYPE_F64 = 0, 1
 
 EXPORTS = (
     "fvib_create_grid", "fvib_destroy_grid", "fvib_field_layout", "fvib_ib_set_body",
-    "fvib_step", "fvib_step_adjoint", "fvib_loss_wall_shear", "fvib_loss_wall_shear_noalloc",
+    "fvib_step", "fvib_step_adjoint", "fvib_step_strong", "fvib_step_strong_adjoint",
+    "fvib_loss_wall_shear", "fvib_loss_wall_shear_noalloc",
     "fvib_loss_rms_lift",
     "fvib_last_error", "fvib_test_momentum", "fvib_test_ppe_rhs", "fvib_test_poisson",
-    "fvib_test_apply_A", "fvib_test_ib_classify", "fvib_timing_enable", "fvib_timing_select",
+    "fvib_test_apply_A", "fvib_test_ib_classify", "fvib_test_project",
+    "fvib_test_project_adjoint", "fvib_test_ib_target", "fvib_test_ib_target_adjoint",
+    "fvib_test_ib_loads", "fvib_test_ib_loads_adjoint", "fvib_test_body_rk4",
+    "fvib_test_body_rk4_adjoint", "fvib_clear_error", "fvib_timing_enable", "fvib_timing_select",
     "fvib_defer_status",
     "fvib_timing_read",
     "fvib_timing_read_skipped",
@@ -35,7 +39,7 @@ EXPORTS = (
 K_CLASSES = {"predictor": 0, "boundary": 1, "ppe_rhs": 2, "residual": 3, "cg_dir": 4,
              "cg_update": 5, "ir_correct": 6, "project": 7, "ib": 8, "adjoint": 9,
              "fdm_x": 10, "fdm_y": 11, "fdm_z": 12, "adj_momentum": 13, "fdm_last": 14,
-             "fft": 15, "fft_acc": 16}
+             "fft": 15, "fft_acc": 16, "adj_rhs": 17, "adj_ustar": 18}
 
 
 class GridDesc(C.Structure):
@@ -80,7 +84,7 @@ class StepInfo(C.Structure):
     _fields_ = [
         ("status", C.c_int32), ("cg_iters", C.c_int32), ("ir_iters", C.c_int32),
         ("flags", C.c_int32), ("res", C.c_double), ("div_max", C.c_double),
-        ("force", C.c_double * 3), ("reserved", C.c_double),
+        ("force", C.c_double * 3), ("xi", C.c_double),
     ]
 
 
@@ -106,6 +110,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.fvib_step_adjoint.argtypes = [vp, C.POINTER(Fields), C.POINTER(Adjoint), vp,
                                       C.POINTER(Adjoint), vp]
     lib.fvib_loss_wall_shear.argtypes = [vp, vp, vp, vp]
+    lib.fvib_step_strong.argtypes = [vp, C.POINTER(Fields), C.POINTER(Fields), C.c_int32,
+                                     C.c_double, vp, vp]
+    lib.fvib_step_strong_adjoint.argtypes = [vp, C.POINTER(Fields), vp, C.POINTER(Adjoint), vp,
+                                             C.POINTER(Adjoint), vp]
     lib.fvib_loss_wall_shear_noalloc.argtypes = [vp, vp, vp, vp]
     lib.fvib_loss_rms_lift.argtypes = [vp, vp, i32, i32, i32, C.c_double, C.c_double, vp, vp]
     lib.fvib_last_error.argtypes = [vp]
@@ -115,6 +123,15 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.fvib_test_poisson.argtypes = [vp, vp, vp, C.POINTER(C.c_int32)]
     lib.fvib_test_apply_A.argtypes = [vp, vp, vp]
     lib.fvib_test_ib_classify.argtypes = [vp, vp, vp * 3]
+    lib.fvib_test_project.argtypes = [vp, vp * 3, vp, vp * 3, vp]
+    lib.fvib_test_project_adjoint.argtypes = [vp, vp * 3, vp]
+    lib.fvib_test_ib_target.argtypes = [vp, vp, vp * 3]
+    lib.fvib_test_ib_target_adjoint.argtypes = [vp, vp, vp * 3, vp]
+    lib.fvib_test_ib_loads.argtypes = [vp, vp, vp * 3, vp]
+    lib.fvib_test_ib_loads_adjoint.argtypes = [vp, vp, vp * 3, vp, vp * 3, vp]
+    lib.fvib_test_body_rk4.argtypes = [vp, vp, vp, vp, vp]
+    lib.fvib_test_body_rk4_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.fvib_clear_error.argtypes = [vp]
     lib.fvib_timing_enable.argtypes = [vp, i32]
     lib.fvib_timing_select.argtypes = [vp, C.c_uint32]
     lib.fvib_defer_status.argtypes = [vp, i32]

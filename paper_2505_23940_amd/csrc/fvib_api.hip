@@ -138,6 +138,10 @@ struct Grid {
   SolverScalars* sc = nullptr;
   SolverScalars* sch = nullptr;   // pinned host mirror
   SolverScalars* sch_dev = nullptr;  // its device address
+  int* sticky_h = nullptr;        // pinned: a step record's failed status lands here
+  int* sticky_d = nullptr;        // its device address
+  int sticky = 0;                 // failed status returned by later calls
+  std::string sticky_msg;
   fvib_step_info* info_dev = nullptr;
   double* mu = nullptr;           // adjoint pressure; also the forward refinement iterate (3D)
   double* d64 = nullptr;          // double inner correction (fast diagonalisation)
@@ -145,7 +149,7 @@ struct Grid {
   float* fdm_f = nullptr;         // eigenbases (float)
   FdmPlan<double> F64;
   FdmPlan<float> F32;
-  double* body_tmp = nullptr;     // scratch body state (adjoint recomputation)
+  double* body_tmp = nullptr;     // strong-coupling iterates, Jacobians and adjoints
   int last_iters = 0;
   int last_iters_adj = 0;
   bool defer = false;        // steps return once enqueued (fvib_defer_status)
@@ -211,6 +215,7 @@ static void release(Grid* g) {
   f(g->fdm_d);
   f(g->fdm_f);
   if (g->sch) (void)hipHostFree(g->sch);
+  if (g->sticky_h) (void)hipHostFree(g->sticky_h);
   f(g->ib_mem);
   f(g->origin);
   for (int c = 0; c < 2; ++c) {
@@ -780,8 +785,94 @@ static int reset_scalars(Grid* g) {
   return FVIB_OK;
 }
 
+// A device-side failure (no convergence, non-finite reduction, body window
+// left) is sticky: the call that meets it returns it, and so does every
+// later step call on the handle until fvib_clear_error.  With deferred
+// status the failure is seen by the host only through the step record; the
+// record kernels also store it in a pinned word the next call reads.
+static int device_fail(Grid* g, int code, const std::string& msg) {
+  g->sticky = code;
+  g->sticky_msg = msg;
+  return fail(g, code, msg);
+}
+
+static int sticky_check(Grid* g) {
+  if (!g->sticky && g->sticky_h) {
+    const int st = __atomic_load_n(g->sticky_h, __ATOMIC_ACQUIRE);
+    if (st != FVIB_OK) {
+      g->sticky = st;
+      g->sticky_msg = "an earlier step recorded a device-side failure (status " +
+                      std::to_string(st) + ")";
+    }
+  }
+  if (g->sticky)
+    return fail(g, g->sticky, g->sticky_msg + "; the handle keeps failing until fvib_clear_error");
+  return FVIB_OK;
+}
+
+// Strongly coupled step (Alg. 1 with N > 1): at most max_iters coupling
+// sub-iterations, stopping once the coupling error falls below tol.
+struct StrongOpt {
+  int max_iters;
+  double tol;
+  double* omega_out;   // nullable: the iterate the fluid saw last (device, 6)
+};
+
+// Workspace of the strongly coupled step and its adjoint (g->body_tmp):
+// two structural iterates, the sub-iteration Jacobians, the fluid's
+// body-velocity adjoint and the fixed-point adjoint.
+constexpr int kWsIterA = 0, kWsIterB = 8, kWsDF = 16, kWsRF = 40, kWsUbody = 64, kWsLam = 72;
+constexpr int kWsDoubles = 80;
+
+// Coupling sub-iterations of one step: the fluid part from u^n with the
+// body at the current iterate (point classes, target velocities, predictor
+// with direct forcing), its loads, and the structure from the time level
+// w^n under them; the coupling error goes to the host, which decides
+// whether another sub-iteration follows.  The Poisson solve and the
+// correction do not feed the loads, so they run once, after the last
+// sub-iteration.  Returns the iterate the fluid saw last (*om) and the
+// structural update from it (*wn).
 template <typename T>
-static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step_info* info) {
+static int strong_iterate(Grid* g, const fvib_fields* in, const StrongOpt* so, const T* const u[3],
+                          const T* const fb[3], T* const us[3], const double** om, double** wn,
+                          int* iters) {
+  int rc;
+  double* A = g->body_tmp + kWsIterA;
+  double* B = g->body_tmp + kWsIterB;
+  FVIB_HIP(hipMemcpyAsync(A, in->body, 6 * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
+  const Geo<T>& G = geo_of<T>(g);
+  for (int k = 1;; ++k) {
+    rc = timed(g, FVIB_K_IB, [&] {
+      return launch_ib_classify<T>(g->ib, A, (T*)g->us[0], (T*)g->us[1], g->sc, g->stream);
+    });
+    if (rc) return rc;
+    const IbView<T> ib = ib_view<T>(g, A);
+    if ((rc = timed(g, FVIB_K_PREDICTOR, [&] {
+           return launch_predictor<T>(G, u, fb, (T**)us, ib, 0, g->stream);
+         })))
+      return rc;
+    rc = timed(g, FVIB_K_IB, [&] {
+      return launch_loads_body<T>(g->ib, ib, A, in->body, B, in->kc, nullptr, 1, g->sc,
+                                  g->stream);
+    });
+    if (rc) return rc;
+    *iters = k;
+    if (k >= so->max_iters) break;
+    FVIB_HIP(hipMemcpyAsync(&g->sch->xi, &g->sc->xi, sizeof(double), hipMemcpyDeviceToHost,
+                            g->stream));
+    FVIB_HIP(hipStreamSynchronize(g->stream));
+    const double xi = g->sch->xi;
+    if (!(xi >= so->tol)) break;       // converged (or not finite: stop iterating)
+    std::swap(A, B);
+  }
+  *om = A;
+  *wn = B;
+  return FVIB_OK;
+}
+
+template <typename T>
+static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step_info* info,
+                     const StrongOpt* so = nullptr) {
   int rc;
   if ((rc = reset_scalars(g))) return rc;
   const T* u[3] = {(const T*)in->u[0], (const T*)in->u[1], g->dim == 3 ? (const T*)in->u[2] : nullptr};
@@ -789,16 +880,22 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
   T* us[3] = {(T*)g->ustar[0], (T*)g->ustar[1], (T*)g->ustar[2]};
   T* uo[3] = {(T*)out->u[0], (T*)out->u[1], g->dim == 3 ? (T*)out->u[2] : nullptr};
   const Geo<T>& G = geo_of<T>(g);
-  if (g->has_body) {
+  const bool strong = so && g->has_body;
+  const double* body_f = in->body;    // body state the fluid sees
+  double* wnew = nullptr;
+  int cpl = 0;
+  if (strong) {
+    if ((rc = strong_iterate<T>(g, in, so, u, fb, us, &body_f, &wnew, &cpl))) return rc;
+  } else if (g->has_body) {
     rc = timed(g, FVIB_K_IB, [&] {
       return launch_ib_classify<T>(g->ib, in->body, (T*)g->us[0], (T*)g->us[1], g->sc,
                                    g->stream);
     });
     if (rc) return rc;
   }
-  const IbView<T> ib = ib_view<T>(g, in->body);
-  if ((rc = timed(g, FVIB_K_PREDICTOR,
-                  [&] { return launch_predictor<T>(G, u, fb, us, ib, 0, g->stream); })))
+  const IbView<T> ib = ib_view<T>(g, body_f);
+  if (!strong && (rc = timed(g, FVIB_K_PREDICTOR,
+                             [&] { return launch_predictor<T>(G, u, fb, us, ib, 0, g->stream); })))
     return rc;
   if (g->planes.np &&
       (rc = timed(g, FVIB_K_BOUNDARY, [&] {
@@ -828,7 +925,8 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
   const std::function<int()> project = [&]() {
     return timed(g, FVIB_K_PROJECT, [&] {
       return launch_project<T>(G, g->P64, (const T* const*)us, piter, uo, g->red(), g->sc,
-                               g->stream, fold ? out->p : nullptr, rec ? dst : nullptr);
+                               g->stream, fold ? out->p : nullptr, rec ? dst : nullptr,
+                               g->sticky_d);
     });
   };
   if ((rc = poisson_solve(g, g->b, piter, g->d.poisson_tol, &last, &cg, &ir, !fold, false,
@@ -836,18 +934,26 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
     return rc;
   g->last_iters = last;
   if (g->defer && g->sch->status == FVIB_ENOCONV)
-    return fail(g, FVIB_ENOCONV,
-                "Poisson solve did not reach poisson_tol" + describe_solve(g, g->d.poisson_tol));
+    return device_fail(g, FVIB_ENOCONV,
+                       "Poisson solve did not reach poisson_tol" + describe_solve(g, g->d.poisson_tol));
   if (!fdm && (rc = project())) return rc;
-  if (g->has_body) {
+  if (strong) {
+    // the body state after the step is the last structural update
+    FVIB_HIP(hipMemcpyAsync(out->body, wnew, 6 * sizeof(double), hipMemcpyDeviceToDevice,
+                            g->stream));
+    if (so->omega_out)
+      FVIB_HIP(hipMemcpyAsync(so->omega_out, body_f, 6 * sizeof(double),
+                              hipMemcpyDeviceToDevice, g->stream));
+  } else if (g->has_body) {
     rc = timed(g, FVIB_K_IB, [&] {
-      return launch_loads_body<T>(g->ib, ib, in->body, out->body, in->kc, g->sc, g->stream);
+      return launch_loads_body<T>(g->ib, ib, in->body, in->body, out->body, in->kc, nullptr, 0,
+                                  g->sc, g->stream);
     });
     if (rc) return rc;
   }
   // (a status the host set after the last projection still needs the copy)
   if ((!rec || g->sch->status == FVIB_ENOCONV) &&
-      (rc = launch_copy_info(g->sc, dst, cg, ir, g->stream)))
+      (rc = launch_copy_info(g->sc, dst, cg, ir, g->stream, nullptr, nullptr, g->sticky_d, cpl)))
     return rc;
   if (g->defer) {                // status only in the info record
     g->err.clear();
@@ -857,11 +963,12 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
   if (g->timer.on) g->timer.resolve();
   int st = g->sch->status;
   if (st == FVIB_OK && g->sch->clamp) {
-    return fail(g, FVIB_EINVAL, "immersed body left the region allowed by its window");
+    return device_fail(g, FVIB_EINVAL, "immersed body left the region allowed by its window");
   }
   if (st == FVIB_ENOCONV)
-    return fail(g, st, "Poisson solve did not reach poisson_tol" + describe_solve(g, g->d.poisson_tol));
-  if (st == FVIB_ENONFINITE) return fail(g, st, "non-finite value in a global reduction");
+    return device_fail(g, st, "Poisson solve did not reach poisson_tol" +
+                                  describe_solve(g, g->d.poisson_tol));
+  if (st == FVIB_ENONFINITE) return device_fail(g, st, "non-finite value in a global reduction");
   g->err.clear();
   return st;
 }
@@ -892,10 +999,11 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
                     [&] { return launch_predictor<T>(G, u, fb, usb, ib, 0, g->stream); })))
       return rc;
     rc = timed(g, FVIB_K_IB, [&] {
-      int r = launch_loads_body<T>(g->ib, ib, in->body, g->body_tmp, in->kc, g->sc, g->stream);
+      int r = launch_loads_body<T>(g->ib, ib, in->body, in->body, nullptr, in->kc, nullptr, 0,
+                                   g->sc, g->stream);
       if (r) return r;
-      return launch_adj_body_loads<T>(g->ib, ib, in->body, bo->body, dF, in->kc, bi->body,
-                                      bi->kc, g->sc, g->stream);
+      return launch_adj_body_loads<T>(g->ib, ib, in->body, in->body, bo->body, dF, in->kc,
+                                      bi->body, bi->body, bi->kc, g->sc, 3, g->stream);
     });
     if (rc) return rc;
   }
@@ -908,7 +1016,7 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
   // tolerances and above the double rounding floor of the residual.  A zero
   // right-hand side gives a zero target and a zero residual at once.
   const double rtol = (g->prec == FVIB_PREC_FP64) ? 1e-10 : 1e-7;
-  if ((rc = timed(g, FVIB_K_ADJOINT, [&] {
+  if ((rc = timed(g, FVIB_K_ADJ_RHS, [&] {
          return launch_adj_rhs<T>(G, g->P64, ub1, g->b, g->red(), g->sc, rtol, g->stream);
        })))
     return rc;
@@ -924,7 +1032,7 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
   if (!warm) FVIB_HIP(hipMemsetAsync(mu, 0, g->ncell * sizeof(double), g->stream));
   // ustar_bar (a pure function of mu) is queued behind each convergence check
   const std::function<int()> ustar = [&]() {
-    return timed(g, FVIB_K_ADJOINT,
+    return timed(g, FVIB_K_ADJ_USTAR,
                  [&] { return launch_adj_ustar<T>(G, g->P64, ub1, mu, ib, usb, g->sc, g->stream); });
   };
   const bool fdm = g->d.solver == FVIB_SOLVER_FDM;
@@ -932,8 +1040,8 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
                           fdm ? &ustar : nullptr)))
     return rc;
   if (g->defer && g->sch->status == FVIB_ENOCONV)
-    return fail(g, FVIB_ENOCONV, "adjoint Poisson solve did not converge" +
-                                     describe_solve(g, g->sch->tol_dev));
+    return device_fail(g, FVIB_ENOCONV, "adjoint Poisson solve did not converge" +
+                                            describe_solve(g, g->sch->tol_dev));
   if (!fdm && (rc = ustar())) return rc;
   if (g->has_body && bi->body) {
     rc = timed(g, FVIB_K_IB, [&] {
@@ -954,7 +1062,8 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
        })))
     return rc;
   fvib_step_info* dst = info ? info : g->info_dev;
-  if ((rc = launch_copy_info(g->sc, dst, cg, ir, g->stream, bo->body, body_pass))) return rc;
+  if ((rc = launch_copy_info(g->sc, dst, cg, ir, g->stream, bo->body, body_pass, g->sticky_d)))
+    return rc;
   if (g->defer) {                // status only in the info record
     g->err.clear();
     return FVIB_OK;
@@ -965,10 +1074,125 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
   if (st == FVIB_ENOCONV) {
     char buf[64];
     snprintf(buf, sizeof(buf), "; rhs max |y/V| %.3e", g->sch->ymax);
-    return fail(g, st, "adjoint Poisson solve did not converge" +
-                           describe_solve(g, g->sch->tol_dev) + buf);
+    return device_fail(g, st, "adjoint Poisson solve did not converge" +
+                                  describe_solve(g, g->sch->tol_dev) + buf);
   }
-  if (st == FVIB_ENONFINITE) return fail(g, st, "non-finite value in the adjoint");
+  if (st == FVIB_ENONFINITE) return device_fail(g, st, "non-finite value in the adjoint");
+  g->err.clear();
+  return FVIB_OK;
+}
+
+// Adjoint of the strongly coupled step at its converged iterate om (the
+// iterate the fluid saw in the last sub-iteration; masks frozen at om):
+// implicit differentiation of the coupling fixed point (Eq. 24).  With
+// Phi(w) = RK4(w^n, F(u^n, w)) and J = dPhi/dw at om, the fixed-point
+// adjoint lam solves (I - J^T) lam = wbar + dL/d(om), where dL/d(om)
+// collects the fluid's body-velocity adjoint (through the target and solid
+// velocities) and the force adjoint dF through the loads; the inputs then
+// receive the partial derivatives of L + lam . Phi at fixed om: the fluid
+// adjoint with the force adjoint dF + (dRK4/dF)^T lam, and RK4^T(lam) for
+// w^n, k and c.
+template <typename T>
+static int strong_adjoint_impl(Grid* g, const fvib_fields* in, const double* om,
+                               const fvib_adjoint* bo, const double* dF, fvib_adjoint* bi,
+                               fvib_step_info* info) {
+  int rc;
+  if ((rc = reset_scalars(g))) return rc;
+  const Geo<T>& G = geo_of<T>(g);
+  const int d = g->dim;
+  const T* u[3] = {(const T*)in->u[0], (const T*)in->u[1], nullptr};
+  const T* fb[3] = {(const T*)in->fb[0], (const T*)in->fb[1], nullptr};
+  T* usb[3] = {(T*)g->ustar[0], (T*)g->ustar[1], nullptr};
+  const T* ub1[3] = {(const T*)bo->u[0], (const T*)bo->u[1], nullptr};
+  T* ub0[3] = {(T*)bi->u[0], (T*)bi->u[1], nullptr};
+  T* fbb[3] = {(T*)bi->fb[0], (T*)bi->fb[1], nullptr};
+  (void)d;
+  double* ws = g->body_tmp;
+  const IbView<T> ib = ib_view<T>(g, om);
+  // forward at the iterate: classes, forcing, force (the RK4 linearisation
+  // point), then the sub-iteration Jacobians from the forcing
+  rc = timed(g, FVIB_K_IB, [&] {
+    return launch_ib_classify<T>(g->ib, om, (T*)g->us[0], (T*)g->us[1], g->sc, g->stream);
+  });
+  if (rc) return rc;
+  if ((rc = timed(g, FVIB_K_PREDICTOR,
+                  [&] { return launch_predictor<T>(G, u, fb, usb, ib, 0, g->stream); })))
+    return rc;
+  rc = timed(g, FVIB_K_IB, [&] {
+    int r = launch_loads_body<T>(g->ib, ib, om, in->body, nullptr, in->kc, nullptr, 0, g->sc,
+                                 g->stream);
+    if (r) return r;
+    return launch_strong_jac<T>(g->ib, ib, om, in->kc, ws + kWsDF, ws + kWsRF, g->stream);
+  });
+  if (rc) return rc;
+  // projection^T: A mu = G^T ubar^{n+1}, then ustar_bar (as in the weak step)
+  const double rtol = (g->prec == FVIB_PREC_FP64) ? 1e-10 : 1e-7;
+  if ((rc = timed(g, FVIB_K_ADJ_RHS, [&] {
+         return launch_adj_rhs<T>(G, g->P64, ub1, g->b, g->red(), g->sc, rtol, g->stream);
+       })))
+    return rc;
+  int cg = 0, ir = 0;
+  const bool warm = bi->mu != nullptr && g->d.solver == FVIB_SOLVER_FDM;
+  double* mu = bi->mu ? bi->mu : g->mu;
+  if (!warm) FVIB_HIP(hipMemsetAsync(mu, 0, g->ncell * sizeof(double), g->stream));
+  const std::function<int()> ustar = [&]() {
+    return timed(g, FVIB_K_ADJ_USTAR,
+                 [&] { return launch_adj_ustar<T>(G, g->P64, ub1, mu, ib, usb, g->sc, g->stream); });
+  };
+  const bool fdm = g->d.solver == FVIB_SOLVER_FDM;
+  if ((rc = poisson_solve(g, g->b, mu, -1.0, &g->last_iters_adj, &cg, &ir, false, warm, nullptr,
+                          fdm ? &ustar : nullptr)))
+    return rc;
+  if (g->defer && g->sch->status == FVIB_ENOCONV)
+    return device_fail(g, FVIB_ENOCONV, "adjoint Poisson solve did not converge" +
+                                            describe_solve(g, g->sch->tol_dev));
+  if (!fdm && (rc = ustar())) return rc;
+  // the fluid's body-velocity adjoint without the forcing part (that one is
+  // carried by DF): zero forcing adjoint in the window
+  for (int c = 0; c < 2; ++c)
+    FVIB_HIP(hipMemsetAsync(g->fw[c], 0, (size_t)g->ib.W[c][0] * g->ib.W[c][1] * g->esize(),
+                            g->stream));
+  FVIB_HIP(hipMemsetAsync(ws + kWsUbody, 0, 6 * sizeof(double), g->stream));
+  rc = timed(g, FVIB_K_IB, [&] {
+    int r = launch_adj_ubody<T>(G, g->P64, g->ib, ub1, mu, ib, ws + kWsUbody, g->sc, g->stream);
+    if (r) return r;
+    r = launch_strong_lambda(ws + kWsDF, ws + kWsRF, bo->body, ws + kWsUbody, dF, ws + kWsLam,
+                             g->sc, g->stream);
+    if (r) return r;
+    // RK4^T from w^n with the fixed-point adjoint as the state adjoint: the
+    // state and (k, c) adjoints and the force adjoint dF + RF^T lam, then the
+    // forcing adjoint on the window (markers at om)
+    return launch_adj_body_loads<T>(g->ib, ib, in->body, om, ws + kWsLam, dF, in->kc, bi->body,
+                                    nullptr, bi->kc, g->sc, 1, g->stream);
+  });
+  if (rc) return rc;
+  if ((rc = timed(g, FVIB_K_ADJOINT, [&] {
+         return launch_adj_outflow<T>(G, g->planes, 0, usb, ub0, g->red(), g->sc, g->stream);
+       })))
+    return rc;
+  if ((rc = timed(g, FVIB_K_ADJ_MOMENTUM, [&] {
+         return launch_adj_momentum<T>(G, u, (const T* const*)usb, ib, ub0, fbb, g->stream);
+       })))
+    return rc;
+  if ((rc = timed(g, FVIB_K_ADJOINT, [&] {
+         return launch_adj_outflow<T>(G, g->planes, 1, usb, ub0, g->red(), g->sc, g->stream);
+       })))
+    return rc;
+  fvib_step_info* dst = info ? info : g->info_dev;
+  if ((rc = launch_copy_info(g->sc, dst, cg, ir, g->stream, nullptr, nullptr, g->sticky_d)))
+    return rc;
+  if (g->defer) {
+    g->err.clear();
+    return FVIB_OK;
+  }
+  if ((rc = read_scalars(g))) return rc;
+  if (g->timer.on) g->timer.resolve();
+  const int st = g->sch->status;
+  if (st == FVIB_ENOCONV)
+    return device_fail(g, st, "adjoint Poisson solve did not converge" +
+                                  describe_solve(g, g->sch->tol_dev));
+  if (st == FVIB_ENONFINITE)
+    return device_fail(g, st, "non-finite value in the adjoint of the strongly coupled step");
   g->err.clear();
   return FVIB_OK;
 }
@@ -1070,7 +1294,7 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
   ok &= dmalloc(&g->sc, sizeof(SolverScalars)) == FVIB_OK;
   ok &= dmalloc(&g->info_dev, sizeof(fvib_step_info)) == FVIB_OK;
   ok &= dmalloc(&g->mu, g->ncell * sizeof(double)) == FVIB_OK;
-  ok &= dmalloc(&g->body_tmp, 8 * sizeof(double)) == FVIB_OK;
+  ok &= dmalloc(&g->body_tmp, kWsDoubles * sizeof(double)) == FVIB_OK;
   if (!ok) return bail(FVIB_ENOMEM, "device allocation of the workspace failed");
   if (g->d.solver == FVIB_SOLVER_FDM) {
     if (g->prec == FVIB_PREC_FP64 && dmalloc(&g->d64, g->ncell * sizeof(double)))
@@ -1203,6 +1427,11 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
     return bail(FVIB_ENOMEM, "pinned host allocation failed");
   if (hipHostGetDevicePointer((void**)&g->sch_dev, g->sch, 0) != hipSuccess)
     return bail(FVIB_EHIP, "no device address for the pinned solver scalars");
+  if (hipHostMalloc((void**)&g->sticky_h, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return bail(FVIB_ENOMEM, "pinned host allocation failed");
+  g->sticky_h[0] = g->sticky_h[1] = 0;
+  if (hipHostGetDevicePointer((void**)&g->sticky_d, g->sticky_h, 0) != hipSuccess)
+    return bail(FVIB_EHIP, "no device address for the pinned status word");
   if (hipMemset(g->mu, 0, g->ncell * sizeof(double)) != hipSuccess ||
       hipMemset(g->sc, 0, sizeof(SolverScalars)) != hipSuccess)
     return bail(FVIB_EHIP, "workspace initialisation failed");
@@ -1358,6 +1587,7 @@ int fvib_step(fvib_grid* h, const fvib_fields* in, fvib_fields* out, fvib_step_i
   Grid* g = &h->g;
   int rc;
   if ((rc = check_fields(g, in, g->has_body)) || (rc = check_fields(g, out, g->has_body))) return rc;
+  if ((rc = sticky_check(g))) return rc;
   if (g->prec == FVIB_PREC_FP64) return step_impl<double>(g, in, out, info);
   return step_impl<float>(g, in, out, info);
 }
@@ -1374,8 +1604,62 @@ int fvib_step_adjoint(fvib_grid* h, const fvib_fields* fwd_in, const fvib_adjoin
   }
   if (g->has_body && (!fwd_in->body || !bar_in->body))
     return fail(g, FVIB_EINVAL, "body state and its adjoint are required with a body");
+  int rc;
+  if ((rc = sticky_check(g))) return rc;
   if (g->prec == FVIB_PREC_FP64) return step_adjoint_impl<double>(g, fwd_in, bar_out, dF, bar_in, info);
   return step_adjoint_impl<float>(g, fwd_in, bar_out, dF, bar_in, info);
+}
+
+int fvib_step_strong(fvib_grid* h, const fvib_fields* in, fvib_fields* out, int32_t max_iters,
+                     double tol, double* omega, fvib_step_info* info) {
+  if (!h) return FVIB_EINVAL;
+  Grid* g = &h->g;
+  int rc;
+  if (!g->has_body) return fail(g, FVIB_ESTATE, "the strongly coupled step needs a body");
+  if (max_iters < 1 || max_iters > 0xFFFF)
+    return fail(g, FVIB_EINVAL, "max_iters must be in [1, 65535]");
+  if (!(tol >= 0.0)) return fail(g, FVIB_EINVAL, "tol must be >= 0");
+  if ((rc = check_fields(g, in, true)) || (rc = check_fields(g, out, true))) return rc;
+  if (omega && (omega == in->body || omega == out->body))
+    return fail(g, FVIB_EINVAL, "omega may not alias the body state");
+  if ((rc = sticky_check(g))) return rc;
+  const StrongOpt so{max_iters, tol, omega};
+  if (g->prec == FVIB_PREC_FP64) return step_impl<double>(g, in, out, info, &so);
+  return step_impl<float>(g, in, out, info, &so);
+}
+
+int fvib_step_strong_adjoint(fvib_grid* h, const fvib_fields* fwd_in, const double* omega,
+                             const fvib_adjoint* bar_out, const double* dF, fvib_adjoint* bar_in,
+                             fvib_step_info* info) {
+  if (!h) return FVIB_EINVAL;
+  Grid* g = &h->g;
+  if (!g->has_body) return fail(g, FVIB_ESTATE, "the strongly coupled step needs a body");
+  if (!fwd_in || !omega || !bar_out || !bar_in) return fail(g, FVIB_EINVAL, "NULL argument");
+  for (int c = 0; c < g->dim; ++c) {
+    if (!fwd_in->u[c] || !bar_out->u[c] || !bar_in->u[c])
+      return fail(g, FVIB_EINVAL, "velocity or adjoint pointer is NULL");
+    if (bar_in->u[c] == bar_out->u[c]) return fail(g, FVIB_EINVAL, "bar_in may not alias bar_out");
+  }
+  if (!fwd_in->body || !bar_in->body)
+    return fail(g, FVIB_EINVAL, "body state and its adjoint are required");
+  if (bar_out->body && bar_out->body == bar_in->body)
+    return fail(g, FVIB_EINVAL, "bar_in->body may not alias bar_out->body");
+  int rc;
+  if ((rc = sticky_check(g))) return rc;
+  if (g->prec == FVIB_PREC_FP64)
+    return strong_adjoint_impl<double>(g, fwd_in, omega, bar_out, dF, bar_in, info);
+  return strong_adjoint_impl<float>(g, fwd_in, omega, bar_out, dF, bar_in, info);
+}
+
+int fvib_clear_error(fvib_grid* h) {
+  if (!h) return FVIB_EINVAL;
+  Grid* g = &h->g;
+  FVIB_HIP(hipStreamSynchronize(g->stream));
+  if (g->sticky_h) __atomic_store_n(g->sticky_h, 0, __ATOMIC_RELEASE);
+  g->sticky = 0;
+  g->sticky_msg.clear();
+  g->err.clear();
+  return FVIB_OK;
 }
 
 const char* fvib_last_error(const fvib_grid* h) {
@@ -1491,6 +1775,268 @@ int fvib_test_ib_classify(fvib_grid* h, const double* body, uint8_t* cls[3]) {
     FVIB_HIP(hipMemcpy(cls[c], full.data(), full.size(), hipMemcpyHostToDevice));
   }
   return FVIB_OK;
+}
+
+}  // extern "C"
+
+namespace fvib {
+
+// ---- window <-> full face arrays (test entry points; through the host)
+static int window_origin_host(Grid* g, int org[4]) {
+  FVIB_HIP(hipMemcpyAsync(org, g->origin, 4 * sizeof(int), hipMemcpyDeviceToHost, g->stream));
+  FVIB_HIP(hipStreamSynchronize(g->stream));
+  return FVIB_OK;
+}
+
+// full[c] = window values on forced faces (class != 0), 0 elsewhere
+static int window_to_full(Grid* g, int c, const int org[4], const void* win, void* full) {
+  const size_t es = g->esize();
+  const int Wx = g->ib.W[c][0], Wy = g->ib.W[c][1];
+  std::vector<uint8_t> cls((size_t)Wx * Wy);
+  std::vector<char> w((size_t)Wx * Wy * es), f((size_t)g->nface[c] * es, 0);
+  FVIB_HIP(hipMemcpy(cls.data(), g->cls[c], cls.size(), hipMemcpyDeviceToHost));
+  FVIB_HIP(hipMemcpy(w.data(), win, w.size(), hipMemcpyDeviceToHost));
+  for (int lj = 0; lj < Wy; ++lj)
+    for (int li = 0; li < Wx; ++li) {
+      const size_t l = (size_t)lj * Wx + li;
+      if (!cls[l]) continue;
+      const size_t o = (size_t)(org[2 * c + 1] + lj) * g->ext[c][0] + org[2 * c] + li;
+      memcpy(&f[o * es], &w[l * es], es);
+    }
+  FVIB_HIP(hipMemcpy(full, f.data(), f.size(), hipMemcpyHostToDevice));
+  return FVIB_OK;
+}
+
+// window = the window's part of the full face array (every class)
+static int full_to_window(Grid* g, int c, const int org[4], const void* full, void* win) {
+  const size_t es = g->esize();
+  const int Wx = g->ib.W[c][0], Wy = g->ib.W[c][1];
+  std::vector<char> w((size_t)Wx * Wy * es), f((size_t)g->nface[c] * es);
+  FVIB_HIP(hipMemcpy(f.data(), full, f.size(), hipMemcpyDeviceToHost));
+  for (int lj = 0; lj < Wy; ++lj)
+    for (int li = 0; li < Wx; ++li) {
+      const size_t o = (size_t)(org[2 * c + 1] + lj) * g->ext[c][0] + org[2 * c] + li;
+      memcpy(&w[((size_t)lj * Wx + li) * es], &f[o * es], es);
+    }
+  FVIB_HIP(hipMemcpy(win, w.data(), w.size(), hipMemcpyHostToDevice));
+  return FVIB_OK;
+}
+
+template <typename T>
+static int classify_at(Grid* g, const double* body, int org[4]) {
+  int rc;
+  if ((rc = reset_scalars(g))) return rc;
+  if ((rc = launch_ib_classify<T>(g->ib, body, (T*)g->us[0], (T*)g->us[1], g->sc, g->stream)))
+    return rc;
+  return window_origin_host(g, org);
+}
+
+template <typename T>
+static int test_project_impl(Grid* g, const void* const ustar[3], const double* p, void* u[3],
+                             double* div_max) {
+  int rc;
+  if ((rc = reset_scalars(g))) return rc;
+  const T* us[3] = {(const T*)ustar[0], (const T*)ustar[1], g->dim == 3 ? (const T*)ustar[2] : nullptr};
+  T* uo[3] = {(T*)u[0], (T*)u[1], g->dim == 3 ? (T*)u[2] : nullptr};
+  if ((rc = launch_project<T>(geo_of<T>(g), g->P64, us, p, uo, g->red(), g->sc, g->stream)))
+    return rc;
+  if (div_max)
+    FVIB_HIP(hipMemcpyAsync(div_max, &g->sc->div_max, sizeof(double), hipMemcpyDeviceToDevice,
+                            g->stream));
+  FVIB_HIP(hipStreamSynchronize(g->stream));
+  return FVIB_OK;
+}
+
+template <typename T>
+static int test_project_adjoint_impl(Grid* g, const void* const ubar[3], double* pbar) {
+  int rc;
+  if ((rc = reset_scalars(g))) return rc;
+  const T* ub[3] = {(const T*)ubar[0], (const T*)ubar[1], g->dim == 3 ? (const T*)ubar[2] : nullptr};
+  if ((rc = launch_adj_rhs<T>(geo_of<T>(g), g->P64, ub, pbar, g->red(), g->sc, 1e-10, g->stream)))
+    return rc;
+  if ((rc = launch_scale(g->ncell, -g->P64.dt_over_rho, pbar, pbar, g->stream))) return rc;
+  FVIB_HIP(hipStreamSynchronize(g->stream));
+  return FVIB_OK;
+}
+
+template <typename T>
+static int test_ib_target_impl(Grid* g, const double* body, void* us[3]) {
+  int org[4], rc;
+  if ((rc = classify_at<T>(g, body, org))) return rc;
+  for (int c = 0; c < 2; ++c)
+    if ((rc = window_to_full(g, c, org, g->us[c], us[c]))) return rc;
+  return FVIB_OK;
+}
+
+template <typename T>
+static int test_ib_target_adjoint_impl(Grid* g, const double* body, const void* const usbar[3],
+                                       double* bodybar) {
+  int org[4], rc;
+  if ((rc = classify_at<T>(g, body, org))) return rc;
+  // the body-velocity adjoint kernel of the step with a zero adjoint
+  // pressure and a zero forcing adjoint: the sum of usbar over forced faces
+  FVIB_HIP(hipMemsetAsync(g->mu, 0, g->ncell * sizeof(double), g->stream));
+  for (int c = 0; c < 2; ++c)
+    FVIB_HIP(hipMemsetAsync(g->fw[c], 0, (size_t)g->ib.W[c][0] * g->ib.W[c][1] * g->esize(),
+                            g->stream));
+  const T* ub[3] = {(const T*)usbar[0], (const T*)usbar[1], nullptr};
+  if ((rc = launch_adj_ubody<T>(geo_of<T>(g), g->P64, g->ib, ub, g->mu, ib_view<T>(g, body),
+                                bodybar, g->sc, g->stream)))
+    return rc;
+  FVIB_HIP(hipStreamSynchronize(g->stream));
+  return FVIB_OK;
+}
+
+template <typename T>
+static int test_ib_loads_impl(Grid* g, const double* body, const void* const f[3], double* F) {
+  int org[4], rc;
+  if ((rc = classify_at<T>(g, body, org))) return rc;
+  for (int c = 0; c < 2; ++c)
+    if ((rc = full_to_window(g, c, org, f[c], g->fw[c]))) return rc;
+  if ((rc = launch_loads_body<T>(g->ib, ib_view<T>(g, body), body, body, nullptr, nullptr,
+                                 nullptr, 0, g->sc, g->stream)))
+    return rc;
+  FVIB_HIP(hipMemcpyAsync(F, g->sc->force, 3 * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
+  FVIB_HIP(hipStreamSynchronize(g->stream));
+  return FVIB_OK;
+}
+
+template <typename T>
+static int test_ib_loads_adjoint_impl(Grid* g, const double* body, const void* const f[3],
+                                      const double* Fbar, void* fbar[3], double* bodybar) {
+  int org[4], rc;
+  if ((rc = classify_at<T>(g, body, org))) return rc;
+  for (int c = 0; c < 2; ++c)
+    if ((rc = full_to_window(g, c, org, f[c], g->fw[c]))) return rc;
+  // loads^T alone (no RK4 part): the force adjoint is Fbar itself
+  if ((rc = launch_adj_body_loads<T>(g->ib, ib_view<T>(g, body), body, body, nullptr, Fbar,
+                                     nullptr, nullptr, bodybar, nullptr, g->sc, 2, g->stream)))
+    return rc;
+  for (int c = 0; c < 2; ++c)
+    if ((rc = window_to_full(g, c, org, g->fw[c], fbar[c]))) return rc;
+  return FVIB_OK;
+}
+
+template <typename T>
+static int test_body_rk4_impl(Grid* g, const double* body, const double* F, const double* kc,
+                              double* body_out) {
+  int rc;
+  if ((rc = reset_scalars(g))) return rc;
+  if ((rc = launch_loads_body<T>(g->ib, ib_view<T>(g, body), body, body, body_out, kc, F, 0,
+                                 g->sc, g->stream)))
+    return rc;
+  FVIB_HIP(hipStreamSynchronize(g->stream));
+  return FVIB_OK;
+}
+
+template <typename T>
+static int test_body_rk4_adjoint_impl(Grid* g, const double* body, const double* F,
+                                      const double* kc, const double* bodybar_out,
+                                      double* bodybar_in, double* Fbar, double* kcbar) {
+  int rc;
+  if ((rc = reset_scalars(g))) return rc;
+  // the linearisation point: the force of the step in sc->force
+  FVIB_HIP(hipMemcpyAsync(g->sc->force, F, 3 * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
+  IbView<T> none;
+  memset(&none, 0, sizeof(none));
+  if ((rc = launch_adj_body_loads<T>(g->ib, ib_view<T>(g, body), body, body, bodybar_out,
+                                     nullptr, kc, bodybar_in, nullptr, kcbar, g->sc, 1,
+                                     g->stream)))
+    return rc;
+  FVIB_HIP(hipMemcpyAsync(Fbar, g->sc->force, 3 * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
+  FVIB_HIP(hipStreamSynchronize(g->stream));
+  return FVIB_OK;
+}
+
+}  // namespace fvib
+
+extern "C" {
+
+static int need_body(Grid* g) {
+  return g->has_body ? FVIB_OK : fail(g, FVIB_ESTATE, "no body attached");
+}
+
+int fvib_test_project(fvib_grid* h, const void* const ustar[3], const double* p, void* u[3],
+                      double* div_max) {
+  if (!h || !ustar || !p || !u) return FVIB_EINVAL;
+  Grid* g = &h->g;
+  for (int c = 0; c < g->dim; ++c) {
+    if (!ustar[c] || !u[c]) return fail(g, FVIB_EINVAL, "NULL velocity component");
+    if (ustar[c] == u[c]) return fail(g, FVIB_EINVAL, "u may not alias ustar");
+  }
+  if (g->prec == FVIB_PREC_FP64) return test_project_impl<double>(g, ustar, p, u, div_max);
+  return test_project_impl<float>(g, ustar, p, u, div_max);
+}
+
+int fvib_test_project_adjoint(fvib_grid* h, const void* const ubar[3], double* pbar) {
+  if (!h || !ubar || !pbar) return FVIB_EINVAL;
+  Grid* g = &h->g;
+  for (int c = 0; c < g->dim; ++c)
+    if (!ubar[c]) return fail(g, FVIB_EINVAL, "NULL adjoint component");
+  if (g->prec == FVIB_PREC_FP64) return test_project_adjoint_impl<double>(g, ubar, pbar);
+  return test_project_adjoint_impl<float>(g, ubar, pbar);
+}
+
+int fvib_test_ib_target(fvib_grid* h, const double* body, void* us[3]) {
+  if (!h || !body || !us || !us[0] || !us[1]) return FVIB_EINVAL;
+  Grid* g = &h->g;
+  int rc;
+  if ((rc = need_body(g))) return rc;
+  if (g->prec == FVIB_PREC_FP64) return test_ib_target_impl<double>(g, body, us);
+  return test_ib_target_impl<float>(g, body, us);
+}
+
+int fvib_test_ib_target_adjoint(fvib_grid* h, const double* body, const void* const usbar[3],
+                                double* bodybar) {
+  if (!h || !body || !usbar || !usbar[0] || !usbar[1] || !bodybar) return FVIB_EINVAL;
+  Grid* g = &h->g;
+  int rc;
+  if ((rc = need_body(g))) return rc;
+  if (g->prec == FVIB_PREC_FP64) return test_ib_target_adjoint_impl<double>(g, body, usbar, bodybar);
+  return test_ib_target_adjoint_impl<float>(g, body, usbar, bodybar);
+}
+
+int fvib_test_ib_loads(fvib_grid* h, const double* body, const void* const f[3], double* F) {
+  if (!h || !body || !f || !f[0] || !f[1] || !F) return FVIB_EINVAL;
+  Grid* g = &h->g;
+  int rc;
+  if ((rc = need_body(g))) return rc;
+  if (g->prec == FVIB_PREC_FP64) return test_ib_loads_impl<double>(g, body, f, F);
+  return test_ib_loads_impl<float>(g, body, f, F);
+}
+
+int fvib_test_ib_loads_adjoint(fvib_grid* h, const double* body, const void* const f[3],
+                               const double* Fbar, void* fbar[3], double* bodybar) {
+  if (!h || !body || !f || !f[0] || !f[1] || !Fbar || !fbar || !fbar[0] || !fbar[1] || !bodybar)
+    return FVIB_EINVAL;
+  Grid* g = &h->g;
+  int rc;
+  if ((rc = need_body(g))) return rc;
+  if (g->prec == FVIB_PREC_FP64)
+    return test_ib_loads_adjoint_impl<double>(g, body, f, Fbar, fbar, bodybar);
+  return test_ib_loads_adjoint_impl<float>(g, body, f, Fbar, fbar, bodybar);
+}
+
+int fvib_test_body_rk4(fvib_grid* h, const double* body, const double* F, const double* kc,
+                       double* body_out) {
+  if (!h || !body || !F || !body_out) return FVIB_EINVAL;
+  Grid* g = &h->g;
+  int rc;
+  if ((rc = need_body(g))) return rc;
+  if (g->prec == FVIB_PREC_FP64) return test_body_rk4_impl<double>(g, body, F, kc, body_out);
+  return test_body_rk4_impl<float>(g, body, F, kc, body_out);
+}
+
+int fvib_test_body_rk4_adjoint(fvib_grid* h, const double* body, const double* F, const double* kc,
+                               const double* bodybar_out, double* bodybar_in, double* Fbar,
+                               double* kcbar) {
+  if (!h || !body || !F || !bodybar_out || !bodybar_in || !Fbar) return FVIB_EINVAL;
+  Grid* g = &h->g;
+  int rc;
+  if ((rc = need_body(g))) return rc;
+  if (g->prec == FVIB_PREC_FP64)
+    return test_body_rk4_adjoint_impl<double>(g, body, F, kc, bodybar_out, bodybar_in, Fbar, kcbar);
+  return test_body_rk4_adjoint_impl<float>(g, body, F, kc, bodybar_out, bodybar_in, Fbar, kcbar);
 }
 
 static int wall_shear_run(Grid* g, const void* u0, double* J, void* ubar0, double* partial) {

@@ -118,24 +118,42 @@ int launch_ir_correct(int64_t n, double* p, const float* d, const SolverScalars*
 template <typename T>
 int launch_project(const Geo<T>& G, const PGeo<double>& P, const T* const us[3], const double* p,
                    T* out[3], RedBuf red, SolverScalars* sc, hipStream_t s, double* pg = nullptr,
-                   fvib_step_info* info = nullptr);
+                   fvib_step_info* info = nullptr, int* sticky = nullptr);
 int launch_apply_A(const PGeo<double>& P, const double* x, double* y, hipStream_t s);
+// y = a x over n doubles (y may alias x)
+int launch_scale(int64_t n, double a, const double* x, double* y, hipStream_t s);
 
 // k_ib.hip
 template <typename T>
 int launch_ib_classify(const IbGeo& B, const double* body, T* us0, T* us1, SolverScalars* sc,
                        hipStream_t s);
+// Loads of the forcing in the body window with the markers at body_pos
+// (force into sc->force; Fin, nullable, replaces it) and, when body_out is
+// given, RK4 from body_rk; xi != 0 also stores the coupling error in sc->xi.
 template <typename T>
-int launch_loads_body(const IbGeo& B, const IbView<T>& ib, const double* body_in,
-                      double* body_out, const double* kc, SolverScalars* sc, hipStream_t s);
+int launch_loads_body(const IbGeo& B, const IbView<T>& ib, const double* body_pos,
+                      const double* body_rk, double* body_out, const double* kc,
+                      const double* Fin, int xi, SolverScalars* sc, hipStream_t s);
+// Step record from the solver scalars; a failed status is also stored in
+// *sticky (nullable).
 int launch_copy_info(const SolverScalars* sc, fvib_step_info* info, int cg_iters, int ir_iters,
-                     hipStream_t s, const double* body_src = nullptr, double* body_dst = nullptr);
+                     hipStream_t s, const double* body_src = nullptr, double* body_dst = nullptr,
+                     int* sticky = nullptr, int cpl_iters = 0);
 
 // k_adjoint.hip
 template <typename T>
-int launch_adj_body_loads(const IbGeo& B, const IbView<T>& ib, const double* st,
-                          const double* stbar_out, const double* dF, const double* kc,
-                          double* stbar_in, double* kcbar, SolverScalars* sc, hipStream_t s);
+int launch_adj_body_loads(const IbGeo& B, const IbView<T>& ib, const double* st_rk,
+                          const double* st_pos, const double* stbar_out, const double* dF,
+                          const double* kc, double* stbar_rk, double* stbar_pos, double* kcbar,
+                          SolverScalars* sc, int parts, hipStream_t s);
+template <typename T>
+// Strong coupling: Jacobians of a coupling sub-iteration at the iterate om
+// (DF 3 x 6, RF 6 x 3, device) and the fixed-point adjoint lam (6).
+int launch_strong_jac(const IbGeo& B, const IbView<T>& ib, const double* om, const double* kc,
+                      double* DF, double* RF, hipStream_t s);
+int launch_strong_lambda(const double* DF, const double* RF, const double* wbar,
+                         const double* ubody, const double* dF, double* lam, SolverScalars* sc,
+                         hipStream_t s);
 template <typename T>
 // rtol: relative target of the adjoint solve, set on the device as
 // rtol * max |y / V| * dt / rho (used by a solve called with tol < 0).

@@ -49,26 +49,30 @@ __device__ __forceinline__ double ddh(double r, double h) {
 }
 
 // ---------------------------------------------- RK4^T and loads^T (1 block)
-// body state st = [d(3), v(3)]; stbar_out = adjoint of the state after the
-// step; dF direct force adjoint (may be NULL).  Writes stbar_in (partial:
-// the body-velocity part from the fluid is added later), accumulates
-// kcbar, stores the total force adjoint in sc->force.
+// The RK4 of the step starts from st_rk; the markers sit at st_pos (the
+// same state in a weakly coupled step; the converged structural iterate in
+// a strongly coupled one).  stbar_out = adjoint of the state after the
+// step; dF direct force adjoint (may be NULL).  parts & 1: RK4^T, written
+// into stbar_rk (the body-velocity part from the fluid is added later),
+// kcbar accumulated, force adjoint = dF + RK4^T part; parts & 2: the
+// marker-position part of loads^T for that force adjoint, added into
+// stbar_pos[0..1].  The total force adjoint is left in sc->force.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_adj_body_loads(IbGeo B, IbView<T> ib, const double* __restrict__ st,
-                 const double* __restrict__ stbar_out, const double* __restrict__ dF,
-                 const double* __restrict__ kc, double* __restrict__ stbar_in,
-                 double* __restrict__ kcbar, SolverScalars* sc) {
+k_adj_body_loads(IbGeo B, IbView<T> ib, const double* st_rk, const double* st_pos,
+                 const double* stbar_out, const double* __restrict__ dF,
+                 const double* __restrict__ kc, double* stbar_rk, double* stbar_pos,
+                 double* __restrict__ kcbar, SolverScalars* sc, int parts) {
   __shared__ double Fbar_s[3];
-  __shared__ double F_s[3];
   if (threadIdx.x == 0) {
+    const double* st = st_rk;
     double sb[6];
     for (int a = 0; a < 6; ++a) sb[a] = stbar_out ? stbar_out[a] : 0.0;
     double Fb[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < 3; ++a) Fb[a] = dF ? dF[a] : 0.0;
     double out[6];
     for (int a = 0; a < 6; ++a) out[a] = sb[a];
-    if (B.kind == FVIB_BODY_RIGID_SPRING) {
+    if ((parts & 1) && B.kind == FVIB_BODY_RIGID_SPRING) {
       const double m = B.m, h = B.dt;
       for (int a = 0; a < 3; ++a) {
         if (!B.free_dof[a]) continue;
@@ -132,15 +136,18 @@ k_adj_body_loads(IbGeo B, IbView<T> ib, const double* __restrict__ st,
         }
       }
     }
-    for (int a = 0; a < 6; ++a) stbar_in[a] = out[a];
-    for (int a = 0; a < 3; ++a) {
-      Fbar_s[a] = Fb[a];
-      F_s[a] = sc->force[a];
-    }
+    if (parts & 1)
+      for (int a = 0; a < 6; ++a) stbar_rk[a] = out[a];
+    for (int a = 0; a < 3; ++a) Fbar_s[a] = Fb[a];
   }
   __syncthreads();
+  if (!(parts & 2)) {
+    if (threadIdx.x == 0)
+      for (int a = 0; a < 3; ++a) sc->force[a] = Fbar_s[a];   // total force adjoint
+    return;
+  }
   // marker-position part: dF_c/dX_k,a = rho h^2 dV_k sum_f f_f d(delta)/dr_a
-  const double dxb = st[0], dyb = st[1];
+  const double dxb = st_pos[0], dyb = st_pos[1];
   const double h = B.h;
   double g[2] = {0.0, 0.0};
   for (int k = threadIdx.x; k < B.M; k += kBlock) {
@@ -174,10 +181,9 @@ k_adj_body_loads(IbGeo B, IbView<T> ib, const double* __restrict__ st,
   }
   block_sum<2>(g);
   if (threadIdx.x == 0) {
-    stbar_in[0] += g[0];
-    stbar_in[1] += g[1];
+    stbar_pos[0] += g[0];
+    stbar_pos[1] += g[1];
     for (int a = 0; a < 3; ++a) sc->force[a] = Fbar_s[a];   // total force adjoint
-    (void)F_s;
   }
 }
 
@@ -206,6 +212,134 @@ k_adj_fbar(IbGeo B, const double* __restrict__ st, const SolverScalars* sc, T* _
       s += B.ds[k] * h * dh(px - Xx, h) * dh(py - Xy, h);
     }
     fbar[c][l] = (T)(-B.rho * h * h * sc->force[c] * s);
+  }
+}
+
+// ------------------------------------------ strong coupling (Eq. 24)
+// One classic RK4 step of (d, v) with d' = v, v' = (F - c v - k d) / m.
+__device__ __forceinline__ void rk4_dv(double m, double k, double c, double dt, double d,
+                                       double v, double F, double* d1, double* v1) {
+  const double k1d = v, k1v = (F - c * v - k * d) / m;
+  const double d2 = d + 0.5 * dt * k1d, v2 = v + 0.5 * dt * k1v;
+  const double k2d = v2, k2v = (F - c * v2 - k * d2) / m;
+  const double d3 = d + 0.5 * dt * k2d, v3 = v + 0.5 * dt * k2v;
+  const double k3d = v3, k3v = (F - c * v3 - k * d3) / m;
+  const double d4 = d + dt * k3d, v4 = v + dt * k3v;
+  const double k4d = v4, k4v = (F - c * v4 - k * d4) / m;
+  *d1 = d + (dt / 6.0) * (k1d + 2.0 * k2d + 2.0 * k3d + k4d);
+  *v1 = v + (dt / 6.0) * (k1v + 2.0 * k2v + 2.0 * k3v + k4v);
+}
+
+// Jacobians of one coupling sub-iteration at the iterate om the fluid saw
+// (its point classes and forcing in the window, frozen):
+//   DF = dF/d(om), 3 x 6 row-major: positions through the kernel weights of
+//        the loads, velocities through the forcing, whose target on forced
+//        faces is the rigid velocity (df/dU_c = 1/dt there);
+//   RF = d body^{n+1} / dF, 6 x 3 row-major: the RK4 of Eq. 12 is linear in
+//        the state and the force, so its force column is RK4 of a unit force
+//        from rest (free degrees of freedom only).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_strong_jac(IbGeo B, IbView<T> ib, const double* __restrict__ om,
+             const double* __restrict__ kc, double* __restrict__ DF, double* __restrict__ RF) {
+  const double h = B.h;
+  double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // per component: dF/dd_x, dF/dd_y, dF/dv_c
+  for (int k = threadIdx.x; k < B.M; k += kBlock) {
+    const double Xx = B.X0[2 * k] + om[0], Xy = B.X0[2 * k + 1] + om[1];
+    const double wgt = B.rho * h * h * (B.ds[k] * h);
+    for (int c = 0; c < 2; ++c) {
+      const int i0 = (int)floor((Xx - B.fx[c][0]) / h) - 1;
+      const int j0 = (int)floor((Xy - B.fy[c][0]) / h) - 1;
+      const int ox = ib.origin[2 * c], oy = ib.origin[2 * c + 1];
+      double ax = 0.0, ay = 0.0, s0 = 0.0;
+      for (int dj = 0; dj < 4; ++dj) {
+        const int lj = j0 + dj - oy;
+        if (lj < 0 || lj >= B.W[c][1]) continue;
+        const double ry = B.fy[c][j0 + dj] - Xy;
+        for (int di = 0; di < 4; ++di) {
+          const int li = i0 + di - ox;
+          if (li < 0 || li >= B.W[c][0]) continue;
+          const int l = lj * B.W[c][0] + li;
+          if (!ib.cls[c][l]) continue;
+          const double rx = B.fx[c][i0 + di] - Xx;
+          const double f = (double)ib.f[c][l];
+          ax += f * ddh(rx, h) * dh(ry, h);
+          ay += f * dh(rx, h) * ddh(ry, h);
+          s0 += dh(rx, h) * dh(ry, h);
+        }
+      }
+      s[3 * c + 0] += wgt * ax;
+      s[3 * c + 1] += wgt * ay;
+      s[3 * c + 2] -= wgt * s0 / B.dt;
+    }
+  }
+  block_sum<6>(s);
+  if (threadIdx.x != 0) return;
+  for (int i = 0; i < 18; ++i) DF[i] = 0.0;
+  for (int c = 0; c < 2; ++c) {
+    DF[c * 6 + 0] = s[3 * c + 0];
+    DF[c * 6 + 1] = s[3 * c + 1];
+    DF[c * 6 + 3 + c] = s[3 * c + 2];
+  }
+  for (int i = 0; i < 18; ++i) RF[i] = 0.0;
+  if (B.kind != FVIB_BODY_RIGID_SPRING) return;
+  for (int a = 0; a < 3; ++a) {
+    if (!B.free_dof[a]) continue;
+    double d1, v1;
+    rk4_dv(B.m, kc ? kc[a] : 0.0, kc ? kc[3 + a] : 0.0, B.dt, 0.0, 0.0, 1.0, &d1, &v1);
+    RF[a * 3 + a] = d1;
+    RF[(3 + a) * 3 + a] = v1;
+  }
+}
+
+// Adjoint of the coupling fixed point w* = Phi(w*), Phi(w) = RK4(w^n, F(w))
+// (Eq. 24 with the residual w - Phi(w)): lam solves (I - J^T) lam = a with
+// J = RF DF and a = wbar + ubody + DF^T dF, the direct derivative of the
+// loss with respect to the iterate (wbar: adjoint of the body state after
+// the step; ubody: the fluid's body-velocity adjoint; dF: the direct force
+// adjoint, nullable).  Dense 6 x 6 Gaussian elimination with partial
+// pivoting, one thread.
+__global__ void k_strong_lambda(const double* __restrict__ DF, const double* __restrict__ RF,
+                                const double* __restrict__ wbar, const double* __restrict__ ubody,
+                                const double* __restrict__ dF, double* __restrict__ lam,
+                                SolverScalars* sc) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double M[6][7];
+  for (int i = 0; i < 6; ++i) {
+    double r = (wbar ? wbar[i] : 0.0) + ubody[i];
+    for (int a = 0; a < 3; ++a) r += DF[a * 6 + i] * (dF ? dF[a] : 0.0);
+    M[i][6] = r;
+    for (int j = 0; j < 6; ++j) {
+      double Jji = 0.0;                     // J[j][i] = sum_a RF[j][a] DF[a][i]
+      for (int a = 0; a < 3; ++a) Jji += RF[j * 3 + a] * DF[a * 6 + i];
+      M[i][j] = (i == j ? 1.0 : 0.0) - Jji;
+    }
+  }
+  for (int col = 0; col < 6; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < 6; ++r)
+      if (fabs(M[r][col]) > fabs(M[piv][col])) piv = r;
+    if (piv != col)
+      for (int j = 0; j < 7; ++j) {
+        const double t = M[col][j];
+        M[col][j] = M[piv][j];
+        M[piv][j] = t;
+      }
+    const double d = M[col][col];
+    if (!(fabs(d) > 0.0)) {              // singular: the sub-iterations cannot converge
+      sc->status = FVIB_ENONFINITE;
+      for (int i = 0; i < 6; ++i) lam[i] = 0.0;
+      return;
+    }
+    for (int r = col + 1; r < 6; ++r) {
+      const double f = M[r][col] / d;
+      for (int j = col; j < 7; ++j) M[r][j] -= f * M[col][j];
+    }
+  }
+  for (int i = 5; i >= 0; --i) {
+    double x = M[i][6];
+    for (int j = i + 1; j < 6; ++j) x -= M[i][j] * lam[j];
+    lam[i] = x / M[i][i];
   }
 }
 
@@ -1000,15 +1134,32 @@ k_adj_momentum_lds(AdjCtx<T> X, int ntx, int nty, int nzc, T* __restrict__ ub0,
 
 // ============================================================== launchers
 template <typename T>
-int launch_adj_body_loads(const IbGeo& B, const IbView<T>& ib, const double* st,
-                          const double* stbar_out, const double* dF, const double* kc,
-                          double* stbar_in, double* kcbar, SolverScalars* sc, hipStream_t s) {
-  launch_kernel((k_adj_body_loads<T>), dim3(1), dim3(kBlock), 0, s, B, ib, st, stbar_out, dF,
-                     kc, stbar_in, kcbar, sc);
+int launch_adj_body_loads(const IbGeo& B, const IbView<T>& ib, const double* st_rk,
+                          const double* st_pos, const double* stbar_out, const double* dF,
+                          const double* kc, double* stbar_rk, double* stbar_pos, double* kcbar,
+                          SolverScalars* sc, int parts, hipStream_t s) {
+  launch_kernel((k_adj_body_loads<T>), dim3(1), dim3(kBlock), 0, s, B, ib, st_rk, st_pos,
+                stbar_out, dF, kc, stbar_rk, stbar_pos, kcbar, sc, parts);
   FVIB_HIP(hipGetLastError());
   const int n = B.W[0][0] * B.W[0][1] + B.W[1][0] * B.W[1][1];
-  launch_kernel((k_adj_fbar<T>), dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, B, st,
+  launch_kernel((k_adj_fbar<T>), dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, B, st_pos,
                      (const SolverScalars*)sc, (T*)ib.f[0], (T*)ib.f[1]);
+  FVIB_HIP(hipGetLastError());
+  return FVIB_OK;
+}
+
+template <typename T>
+int launch_strong_jac(const IbGeo& B, const IbView<T>& ib, const double* om, const double* kc,
+                      double* DF, double* RF, hipStream_t s) {
+  launch_kernel((k_strong_jac<T>), dim3(1), dim3(kBlock), 0, s, B, ib, om, kc, DF, RF);
+  FVIB_HIP(hipGetLastError());
+  return FVIB_OK;
+}
+
+int launch_strong_lambda(const double* DF, const double* RF, const double* wbar,
+                         const double* ubody, const double* dF, double* lam, SolverScalars* sc,
+                         hipStream_t s) {
+  launch_kernel(k_strong_lambda, dim3(1), dim3(64), 0, s, DF, RF, wbar, ubody, dF, lam, sc);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
@@ -1123,8 +1274,11 @@ static int launch_adj_momentum_t(const AdjCtx<T>& X, T* ubar[3], T* fbbar[3], hi
 
 #define FVIB_INST(T)                                                                            \
   template int launch_adj_body_loads<T>(const IbGeo&, const IbView<T>&, const double*,          \
-                                        const double*, const double*, const double*, double*,   \
-                                        double*, SolverScalars*, hipStream_t);                  \
+                                        const double*, const double*, const double*,            \
+                                        const double*, double*, double*, double*,               \
+                                        SolverScalars*, int, hipStream_t);                      \
+  template int launch_strong_jac<T>(const IbGeo&, const IbView<T>&, const double*,              \
+                                    const double*, double*, double*, hipStream_t);              \
   template int launch_adj_rhs<T>(const Geo<T>&, const PGeo<double>&, const T* const[3],         \
                                  double*, RedBuf, SolverScalars*, double, hipStream_t);         \
   template int launch_adj_ustar<T>(const Geo<T>&, const PGeo<double>&, const T* const[3],       \

@@ -123,60 +123,86 @@ k_ib_targets(IbGeo B, const double* __restrict__ body, T* __restrict__ us0,
   }
 }
 
-// Loads on the body and RK4 update; one block.
+// Classic RK4 of m w'' + c w' + k w = F per free degree of freedom, F held
+// over the step; fixed degrees of freedom keep their values.
+__device__ void body_rk4(const IbGeo& B, const double* st_in, const double* F,
+                         const double* __restrict__ kc, double* st) {
+  for (int a = 0; a < 6; ++a) st[a] = st_in[a];
+  if (B.kind != FVIB_BODY_RIGID_SPRING) return;
+  const double m = B.m, dt = B.dt;
+  for (int a = 0; a < 3; ++a) {
+    if (!B.free_dof[a]) continue;
+    const double kk = kc ? kc[a] : 0.0, cc = kc ? kc[3 + a] : 0.0;
+    const double d = st[a], v = st[3 + a], Fa = F[a];
+    const double k1d = v, k1v = (Fa - cc * v - kk * d) / m;
+    const double d2 = d + 0.5 * dt * k1d, v2 = v + 0.5 * dt * k1v;
+    const double k2d = v2, k2v = (Fa - cc * v2 - kk * d2) / m;
+    const double d3 = d + 0.5 * dt * k2d, v3 = v + 0.5 * dt * k2v;
+    const double k3d = v3, k3v = (Fa - cc * v3 - kk * d3) / m;
+    const double d4 = d + dt * k3d, v4 = v + dt * k3v;
+    const double k4d = v4, k4v = (Fa - cc * v4 - kk * d4) / m;
+    st[a] = d + (dt / 6.0) * (k1d + 2.0 * k2d + 2.0 * k3d + k4d);
+    st[3 + a] = v + (dt / 6.0) * (k1v + 2.0 * k2v + 2.0 * k3v + k4v);
+  }
+}
+
+// Loads on the body (markers placed by body_pos) and, when body_out is
+// given, the RK4 update from body_rk; one block.  Fin (nullable) replaces
+// the computed force.  With body_out and the coupling error requested
+// (xi != 0), sc->xi = |body_out - body_pos|^2 / max(|body_pos|^2, 1e-30):
+// the change of the structural iterate of a coupling sub-iteration.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_loads_body(IbGeo B, IbView<T> ib, const double* __restrict__ body_in,
-             double* __restrict__ body_out, const double* __restrict__ kc, SolverScalars* sc) {
-  const double dxb = body_in[0], dyb = body_in[1];
-  const double h = B.h;
+k_loads_body(IbGeo B, IbView<T> ib, const double* body_pos, const double* body_rk,
+             double* body_out,
+             const double* __restrict__ kc, const double* __restrict__ Fin, int xi,
+             SolverScalars* sc) {
   double q[2] = {0.0, 0.0};
-  for (int k = threadIdx.x; k < B.M; k += kBlock) {
-    const double Xx = B.X0[2 * k] + dxb, Xy = B.X0[2 * k + 1] + dyb;
-    const double dV = B.ds[k] * h;
+  if (!Fin) {
+    const double dxb = body_pos[0], dyb = body_pos[1];
+    const double h = B.h;
+    for (int k = threadIdx.x; k < B.M; k += kBlock) {
+      const double Xx = B.X0[2 * k] + dxb, Xy = B.X0[2 * k + 1] + dyb;
+      const double dV = B.ds[k] * h;
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int i0 = (int)floor((Xx - B.fx[c][0]) / h) - 1;
-      const int j0 = (int)floor((Xy - B.fy[c][0]) / h) - 1;
-      const int ox = ib.origin[2 * c], oy = ib.origin[2 * c + 1];
-      double acc = 0.0;
-      for (int dj = 0; dj < 4; ++dj) {
-        const int lj = j0 + dj - oy;
-        if (lj < 0 || lj >= B.W[c][1]) continue;
-        const double wy = d_h(B.fy[c][j0 + dj] - Xy, h);
-        for (int di = 0; di < 4; ++di) {
-          const int li = i0 + di - ox;
-          if (li < 0 || li >= B.W[c][0]) continue;
-          const int l = lj * B.W[c][0] + li;
-          if (!ib.cls[c][l]) continue;
-          acc += (double)ib.f[c][l] * d_h(B.fx[c][i0 + di] - Xx, h) * wy;
+      for (int c = 0; c < 2; ++c) {
+        const int i0 = (int)floor((Xx - B.fx[c][0]) / h) - 1;
+        const int j0 = (int)floor((Xy - B.fy[c][0]) / h) - 1;
+        const int ox = ib.origin[2 * c], oy = ib.origin[2 * c + 1];
+        double acc = 0.0;
+        for (int dj = 0; dj < 4; ++dj) {
+          const int lj = j0 + dj - oy;
+          if (lj < 0 || lj >= B.W[c][1]) continue;
+          const double wy = d_h(B.fy[c][j0 + dj] - Xy, h);
+          for (int di = 0; di < 4; ++di) {
+            const int li = i0 + di - ox;
+            if (li < 0 || li >= B.W[c][0]) continue;
+            const int l = lj * B.W[c][0] + li;
+            if (!ib.cls[c][l]) continue;
+            acc += (double)ib.f[c][l] * d_h(B.fx[c][i0 + di] - Xx, h) * wy;
+          }
         }
+        q[c] += acc * (h * h) * dV;
       }
-      q[c] += acc * (h * h) * dV;
     }
+    block_sum<2>(q);
   }
-  block_sum<2>(q);
   if (threadIdx.x != 0) return;
   double F[3] = {-B.rho * q[0], -B.rho * q[1], 0.0};
+  if (Fin)
+    for (int a = 0; a < 3; ++a) F[a] = Fin[a];
   for (int a = 0; a < 3; ++a) sc->force[a] = F[a];
+  if (!body_out) return;
   double st[6];
-  for (int a = 0; a < 6; ++a) st[a] = body_in[a];
-  if (B.kind == FVIB_BODY_RIGID_SPRING) {
-    const double m = B.m, dt = B.dt;
-    for (int a = 0; a < 3; ++a) {
-      if (!B.free_dof[a]) continue;
-      const double kk = kc ? kc[a] : 0.0, cc = kc ? kc[3 + a] : 0.0;
-      const double d = st[a], v = st[3 + a], Fa = F[a];
-      const double k1d = v, k1v = (Fa - cc * v - kk * d) / m;
-      const double d2 = d + 0.5 * dt * k1d, v2 = v + 0.5 * dt * k1v;
-      const double k2d = v2, k2v = (Fa - cc * v2 - kk * d2) / m;
-      const double d3 = d + 0.5 * dt * k2d, v3 = v + 0.5 * dt * k2v;
-      const double k3d = v3, k3v = (Fa - cc * v3 - kk * d3) / m;
-      const double d4 = d + dt * k3d, v4 = v + dt * k3v;
-      const double k4d = v4, k4v = (Fa - cc * v4 - kk * d4) / m;
-      st[a] = d + (dt / 6.0) * (k1d + 2.0 * k2d + 2.0 * k3d + k4d);
-      st[3 + a] = v + (dt / 6.0) * (k1v + 2.0 * k2v + 2.0 * k3v + k4v);
+  body_rk4(B, body_rk, F, kc, st);
+  if (xi) {
+    double num = 0.0, den = 0.0;
+    for (int a = 0; a < 6; ++a) {
+      const double e = st[a] - body_pos[a];
+      num += e * e;
+      den += body_pos[a] * body_pos[a];
     }
+    sc->xi = num / fmax(den, 1e-30);
   }
   for (int a = 0; a < 6; ++a) body_out[a] = st[a];
 }
@@ -184,19 +210,21 @@ k_loads_body(IbGeo B, IbView<T> ib, const double* __restrict__ body_in,
 // Also copies (or zeroes, src == nullptr) a 6-double body state when dst
 // is given (the adjoint body state of a step without a body).
 __global__ void k_copy_info(const SolverScalars* sc, fvib_step_info* info, int cg_iters,
-                            int ir_iters, const double* body_src, double* body_dst) {
+                            int ir_iters, const double* body_src, double* body_dst, int* sticky,
+                            int cpl_iters) {
   if (body_dst && threadIdx.x < 6) body_dst[threadIdx.x] = body_src ? body_src[threadIdx.x] : 0.0;
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int st = sc->status;
   if (st == FVIB_OK && sc->clamp) st = FVIB_EINVAL;
+  if (sticky && st != FVIB_OK) *sticky = st;
   info->status = st;
   info->cg_iters = cg_iters;
   info->ir_iters = ir_iters;
-  info->flags = sc->clamp;
+  info->flags = (sc->clamp ? 1 : 0) | (cpl_iters << 8);
   info->res = sc->crit;
   info->div_max = sc->div_max;
   for (int a = 0; a < 3; ++a) info->force[a] = sc->force[a];
-  info->reserved = 0.0;
+  info->xi = cpl_iters ? sc->xi : 0.0;
 }
 
 // ------------------------------------------------------------ launchers
@@ -213,18 +241,20 @@ int launch_ib_classify(const IbGeo& B, const double* body, T* us0, T* us1, Solve
 }
 
 template <typename T>
-int launch_loads_body(const IbGeo& B, const IbView<T>& ib, const double* body_in,
-                      double* body_out, const double* kc, SolverScalars* sc, hipStream_t s) {
-  launch_kernel((k_loads_body<T>), dim3(1), dim3(kBlock), 0, s, B, ib, body_in, body_out,
-                     kc, sc);
+int launch_loads_body(const IbGeo& B, const IbView<T>& ib, const double* body_pos,
+                      const double* body_rk, double* body_out, const double* kc,
+                      const double* Fin, int xi, SolverScalars* sc, hipStream_t s) {
+  launch_kernel((k_loads_body<T>), dim3(1), dim3(kBlock), 0, s, B, ib, body_pos, body_rk,
+                body_out, kc, Fin, xi, sc);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
 
 int launch_copy_info(const SolverScalars* sc, fvib_step_info* info, int cg_iters, int ir_iters,
-                     hipStream_t s, const double* body_src, double* body_dst) {
+                     hipStream_t s, const double* body_src, double* body_dst, int* sticky,
+                     int cpl_iters) {
   launch_kernel(k_copy_info, dim3(1), dim3(64), 0, s, sc, info, cg_iters, ir_iters, body_src,
-                body_dst);
+                body_dst, sticky, cpl_iters);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
@@ -233,9 +263,11 @@ template int launch_ib_classify<float>(const IbGeo&, const double*, float*, floa
                                        SolverScalars*, hipStream_t);
 template int launch_ib_classify<double>(const IbGeo&, const double*, double*, double*,
                                         SolverScalars*, hipStream_t);
-template int launch_loads_body<float>(const IbGeo&, const IbView<float>&, const double*, double*,
-                                      const double*, SolverScalars*, hipStream_t);
+template int launch_loads_body<float>(const IbGeo&, const IbView<float>&, const double*,
+                                      const double*, double*, const double*, const double*, int,
+                                      SolverScalars*, hipStream_t);
 template int launch_loads_body<double>(const IbGeo&, const IbView<double>&, const double*,
-                                       double*, const double*, SolverScalars*, hipStream_t);
+                                       const double*, double*, const double*, const double*, int,
+                                       SolverScalars*, hipStream_t);
 
 }  // namespace fvib

@@ -15,6 +15,8 @@
 // residual r = b - A p the divergence of the corrected field is
 // -(dt / rho) r_c / V_c, and the solve stops when its maximum over the
 // cells falls below the requested tolerance.
+#include <algorithm>
+
 #include "fvib_internal.h"
 #include "fvib_kernels.h"
 
@@ -165,12 +167,14 @@ struct FinDivMax {
   // fast diagonalisation without a body, whose scalars are final once the
   // projection has run)
   fvib_step_info* info;
+  int* sticky;   // nullable: a failed status is also stored here
   __device__ bool skip(const SolverScalars*) const { return false; }
   __device__ void apply(const double* t, SolverScalars* sc) const {
     sc->div_max = t[0];
     if (!info) return;
     int st = sc->status;
     if (st == FVIB_OK && sc->clamp) st = FVIB_EINVAL;
+    if (sticky && st != FVIB_OK) *sticky = st;
     info->status = st;
     info->cg_iters = 0;
     info->ir_iters = sc->sweeps;
@@ -178,7 +182,7 @@ struct FinDivMax {
     info->res = sc->crit;
     info->div_max = t[0];
     for (int a = 0; a < 3; ++a) info->force[a] = sc->force[a];
-    info->reserved = 0.0;
+    info->xi = 0.0;
   }
 };
 
@@ -665,7 +669,7 @@ int launch_ir_correct(int64_t n, double* p, const float* d, const SolverScalars*
 template <typename T>
 int launch_project(const Geo<T>& G, const PGeo<double>& P, const T* const us[3], const double* p,
                    T* out[3], RedBuf red, SolverScalars* sc, hipStream_t s, double* pg,
-                   fvib_step_info* info) {
+                   fvib_step_info* info, int* sticky) {
   const Tiling tl = red_tiling(G.n);
   if (pg && (G.dim != 3 || pg == p)) return FVIB_EINVAL;
   if (G.dim == 2)
@@ -676,11 +680,25 @@ int launch_project(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
     launch_kernel((k_project_col<T>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct, us[0],
                   us[1], us[2], p, out[0], out[1], out[2], red, pg, sc);
     FVIB_HIP(hipGetLastError());
-    FVIB_HIP((launch_finish<1, 0>(red.partial, ct.nblocks, sc, FinDivMax{info}, s)));
+    FVIB_HIP((launch_finish<1, 0>(red.partial, ct.nblocks, sc, FinDivMax{info, sticky}, s)));
     return FVIB_OK;
   }
   FVIB_HIP(hipGetLastError());
-  FVIB_HIP((launch_finish<1, 0>(red.partial, tl.nblocks, sc, FinDivMax{info}, s)));
+  FVIB_HIP((launch_finish<1, 0>(red.partial, tl.nblocks, sc, FinDivMax{info, sticky}, s)));
+  return FVIB_OK;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_scale(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * kBlock)
+    y[t] = a * x[t];
+}
+
+int launch_scale(int64_t n, double a, const double* x, double* y, hipStream_t s) {
+  const int64_t nb = std::min<int64_t>((n + kBlock - 1) / kBlock, 8 * kMaxRedBlocks);
+  launch_kernel(k_scale, dim3((int)nb), dim3(kBlock), 0, s, n, a, x, y);
+  FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
 
@@ -705,9 +723,10 @@ template int launch_cg_iter<double>(const PGeo<double>&, int, const double*, con
                                     int, hipStream_t, hipEvent_t*);
 template int launch_project<float>(const Geo<float>&, const PGeo<double>&, const float* const[3],
                                    const double*, float* [3], RedBuf, SolverScalars*,
-                                   hipStream_t, double*, fvib_step_info*);
+                                   hipStream_t, double*, fvib_step_info*, int*);
 template int launch_project<double>(const Geo<double>&, const PGeo<double>&,
                                     const double* const[3], const double*, double* [3], RedBuf,
-                                    SolverScalars*, hipStream_t, double*, fvib_step_info*);
+                                    SolverScalars*, hipStream_t, double*, fvib_step_info*,
+                                    int*);
 
 }  // namespace fvib

@@ -2,7 +2,8 @@
 adjoint of each step).
 
 The forward pass repeats ``fvib_step`` (the paper's main loop, Alg. 2, with
-one weakly coupled step per iteration) and keeps a checkpoint every
+one weakly coupled step per iteration, or one strongly coupled step of
+``fvib_step_strong`` when a coupling is given) and keeps a checkpoint every
 ``ckpt_every`` steps.  The backward pass walks the segments in reverse:
 it restores the segment's checkpoint, recomputes the states inside the
 segment with the same (deterministic) forward step, then applies
@@ -31,7 +32,8 @@ def _slots_like(x, n):
     return [flat[s, :x.numel()].view(x.shape) for s in range(n)]
 
 
-def _forward_steps(grid, nsteps, ckpt_every, u, p, body, fbd, kcd, info, ckpts):
+def _forward_steps(grid, nsteps, ckpt_every, u, p, body, fbd, kcd, info, ckpts, coupling=None,
+                   omegas=None):
     # The state entering a segment is kept as is; the segment's first step
     # writes its result into a fresh slot and the segment continues there in
     # place.  The slots of all segments but the last come from one
@@ -50,16 +52,18 @@ def _forward_steps(grid, nsteps, ckpt_every, u, p, body, fbd, kcd, info, ckpts):
             else:
                 u2 = [torch.empty_like(x) for x in u]
                 p2, b2 = torch.empty_like(p), torch.empty_like(body)
-            grid.step(u, p, fbd, body, kcd, u_out=u2, p_out=p2, body_out=b2, info=info[n])
+            grid.step(u, p, fbd, body, kcd, u_out=u2, p_out=p2, body_out=b2, info=info[n],
+                      coupling=coupling, omega=None if omegas is None else omegas[n])
             u, p, body = u2, p2, b2
         else:
-            grid.step(u, p, fbd, body, kcd, info=info[n])
+            grid.step(u, p, fbd, body, kcd, info=info[n], coupling=coupling,
+                      omega=None if omegas is None else omegas[n])
     ckpts["final"] = (u, p, body)
 
 
 class _Rollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, grid: Grid, nsteps: int, ckpt_every: int, nd: int, *tensors):
+    def forward(ctx, grid: Grid, nsteps: int, ckpt_every: int, coupling, nd: int, *tensors):
         u0 = list(tensors[:nd])
         fb = list(tensors[nd:2 * nd])
         kc, body0 = tensors[2 * nd], tensors[2 * nd + 1]
@@ -71,10 +75,16 @@ class _Rollout(torch.autograd.Function):
         kcd = kc.detach()
         info = torch.zeros((nsteps, INFO_DOUBLES), dtype=torch.float64, device=dev)
         ckpts = {}
+        # strongly coupled steps keep the iterate each step's fluid saw last
+        # (the linearisation point of their adjoint)
+        omegas = None
+        if coupling is not None:
+            omegas = torch.zeros((nsteps, 6), dtype=torch.float64, device=dev)
         # steps are enqueued back to back; their statuses are checked once
         grid.defer_status(True)
         try:
-            _forward_steps(grid, nsteps, ckpt_every, u, p, body, fbd, kcd, info, ckpts)
+            _forward_steps(grid, nsteps, ckpt_every, u, p, body, fbd, kcd, info, ckpts, coupling,
+                           omegas)
         finally:
             grid.defer_status(False)
         u, p, body = ckpts.pop("final")
@@ -84,6 +94,8 @@ class _Rollout(torch.autograd.Function):
         ctx.k = ckpt_every
         ctx.nd = nd
         ctx.ckpts = ckpts
+        ctx.coupling = coupling
+        ctx.omegas = omegas
         ctx.save_for_backward(*fbd, kcd)
         Fh = info[:, 4:7].clone()
         ctx.mark_non_differentiable(p)
@@ -135,14 +147,15 @@ class _Rollout(torch.autograd.Function):
                         u2 = [X[q] for X in RU]
                         b2 = RB[q]
                         grid.step(u, p, fb, body, kc, u_out=u2, p_out=p, body_out=b2,
-                                  info=infos_f[n])
+                                  info=infos_f[n], coupling=ctx.coupling)
                         u, body = u2, b2
                         states.append((u, body))
                 for n in reversed(range(s0, s1)):
                     un, bn = states[n - s0]
                     dF = gF[n].contiguous()
                     grid.step_adjoint(un, fb, bn, kc, ubar, bbar, dF, ubar_tmp, bbar_tmp,
-                                      fbbar=fbbar, kcbar=kcbar, info=infos_a[n], mu=mu)
+                                      fbbar=fbbar, kcbar=kcbar, info=infos_a[n], mu=mu,
+                                      omega=None if ctx.omegas is None else ctx.omegas[n])
                     ubar, ubar_tmp = ubar_tmp, ubar
                     bbar, bbar_tmp = bbar_tmp, bbar
         finally:
@@ -150,16 +163,21 @@ class _Rollout(torch.autograd.Function):
         host = infos.cpu()             # one read of both sets of records
         grid.check_infos(host[0], "recomputed step")
         grid.check_infos(host[1], "adjoint step")
-        return (None, None, None, None, *ubar, *fbbar, kcbar, bbar)
+        return (None, None, None, None, None, *ubar, *fbbar, kcbar, bbar)
 
 
 def rollout(grid: Grid, u0: List[torch.Tensor], fb: Optional[List[torch.Tensor]], kc: torch.Tensor,
-            body0: torch.Tensor, nsteps: int, ckpt_every: int = 1):
-    """Differentiable rollout; returns (u_final list, body_final, F history (S, 3), p_final)."""
+            body0: torch.Tensor, nsteps: int, ckpt_every: int = 1, coupling=None):
+    """Differentiable rollout; returns (u_final list, body_final, F history (S, 3), p_final).
+    coupling = (max_iters, tol) runs strongly coupled steps (Alg. 1 with
+    N = max_iters), differentiated through their coupling fixed points."""
     if fb is None:
         fb = grid.zeros_u()
     nd = grid.dim
-    outs = _Rollout.apply(grid, int(nsteps), int(max(1, ckpt_every)), nd, *u0, *fb, kc, body0)
+    if coupling is not None:
+        coupling = (int(coupling[0]), float(coupling[1]))
+    outs = _Rollout.apply(grid, int(nsteps), int(max(1, ckpt_every)), coupling, nd, *u0, *fb, kc,
+                          body0)
     return list(outs[:nd]), outs[nd], outs[nd + 1], outs[nd + 2]
 
 
