@@ -41,6 +41,7 @@ def kernel_cost(d: int, s: int, mixed: bool, n: tuple, solver: str = "fdm"):
     return {
         "predictor": ("bytes", 3 * d * s),                 # read u, f_b; write u*
         "ppe_rhs": ("bytes", d * s + 8),                   # read u*; write b
+        "rhs_res": ("bytes", d * s + 8 + 8 + v),           # read u*, p; write b, r
         "residual": ("bytes", 8 + 8 + v),                  # read b, p; write r
         "cg_dir": ("bytes", 3 * v),                        # read r, p_old; write p_new
         "cg_update": ("bytes", 5 * v),                     # read p, x, r; write x, r
@@ -48,6 +49,7 @@ def kernel_cost(d: int, s: int, mixed: bool, n: tuple, solver: str = "fdm"):
         "project": ("bytes", 2 * d * s + 8 + pg),          # read u*, p; write u (and p)
         "adj_momentum": ("bytes", 5 * d * s),              # read u, ustar_bar; write ubar; rw fbbar
         "adj_rhs": ("bytes", d * s + 8),                   # read ubar; write G^T ubar
+        "adj_rhs_res": ("bytes", d * s + 8 + 8 + v),       # read ubar, mu; write y, r
         "adj_ustar": ("bytes", 2 * d * s + 8),             # read ubar, mu; write ustar_bar
         "fdm_x": ("flops", 2 * n[0]),                      # dense contraction along x
         "fdm_y": ("flops", 2 * n[1]),

@@ -392,7 +392,9 @@ enum {
   FVIB_K_FFT_ACC = 16,    /* last inverse FFT of a sweep, adding into p      */
   FVIB_K_ADJ_RHS = 17,    /* adjoint Poisson right-hand side G^T ubar        */
   FVIB_K_ADJ_USTAR = 18,  /* adjoint predicted velocity from the solution    */
-  FVIB_K_NCLASSES = 19
+  FVIB_K_RHS_RES = 19,    /* Eq. 9 right-hand side with the first residual   */
+  FVIB_K_ADJ_RHS_RES = 20, /* adjoint right-hand side with the first residual */
+  FVIB_K_NCLASSES = 21
 };
 
 /* Start (enable != 0, totals cleared) or stop recording.  A recorded

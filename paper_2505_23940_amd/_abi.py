@@ -39,7 +39,8 @@ EXPORTS = (
 K_CLASSES = {"predictor": 0, "boundary": 1, "ppe_rhs": 2, "residual": 3, "cg_dir": 4,
              "cg_update": 5, "ir_correct": 6, "project": 7, "ib": 8, "adjoint": 9,
              "fdm_x": 10, "fdm_y": 11, "fdm_z": 12, "adj_momentum": 13, "fdm_last": 14,
-             "fft": 15, "fft_acc": 16, "adj_rhs": 17, "adj_ustar": 18}
+             "fft": 15, "fft_acc": 16, "adj_rhs": 17, "adj_ustar": 18,
+             "rhs_res": 19, "adj_rhs_res": 20}
 
 
 class GridDesc(C.Structure):

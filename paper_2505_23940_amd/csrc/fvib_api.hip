@@ -150,6 +150,7 @@ struct Grid {
   FdmPlan<double> F64;
   FdmPlan<float> F32;
   double* body_tmp = nullptr;     // strong-coupling iterates, Jacobians and adjoints
+  double max_iv = 0.0;            // max over cells of 1 / V
   int last_iters = 0;
   int last_iters_adj = 0;
   bool defer = false;        // steps return once enqueued (fvib_defer_status)
@@ -549,7 +550,7 @@ static int read_scalars(Grid* g) {
 static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* last,
                          int* cg_total, int* ir_total, bool gauge = true, bool warm = false,
                          const double* p_in = nullptr,
-                         const std::function<int()>* tail = nullptr) {
+                         const std::function<int()>* tail = nullptr, bool first_done = false) {
   if (!p_in) p_in = p;
   int rc;
   *cg_total = 0;
@@ -636,7 +637,8 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
       return residual(0);
     };
     g->timer.begin_solve();
-    if ((rc = residual(1))) return rc;
+    // the first residual may come with the right-hand side (first_done)
+    if (!first_done && (rc = residual(1))) return rc;
     launched = 0;
     int batch = std::max(1, std::min(g->last_iters, g->d.ir_maxit));
     double prev_crit = HUGE_VAL;
@@ -902,14 +904,26 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
          return launch_boundary<T>(G, g->planes, u, us, g->red(), g->sc, g->stream);
        })))
     return rc;
-  if ((rc = timed(g, FVIB_K_PPE_RHS, [&] {
-         return launch_ppe_rhs<T>(G, g->P64, (const T* const*)us, ib, g->b, g->red(), g->sc,
-                                  g->stream);
-       })))
+  const bool fdm = g->d.solver == FVIB_SOLVER_FDM;
+  // 3D without a body: the right-hand side and the first residual of the
+  // refinement in one pass
+  const bool fuse_rhs = fdm && g->dim == 3 && !g->has_body;
+  if (fuse_rhs) {
+    const bool d64 = g->prec == FVIB_PREC_FP64;
+    if ((rc = timed(g, FVIB_K_RHS_RES, [&] {
+           return launch_rhs_residual<T>(G, g->P64, (const T* const*)us, in->p, g->b,
+                                         d64 ? g->r64 : nullptr, d64 ? nullptr : g->r32,
+                                         g->red(), g->sc, g->d.poisson_tol, g->max_iv, g->stream,
+                                         g->sch_dev);
+         })))
+      return rc;
+  } else if ((rc = timed(g, FVIB_K_PPE_RHS, [&] {
+                return launch_ppe_rhs<T>(G, g->P64, (const T* const*)us, ib, g->b, g->red(),
+                                         g->sc, g->stream);
+              })))
     return rc;
   int cg = 0, ir = 0;
   int last = g->last_iters;
-  const bool fdm = g->d.solver == FVIB_SOLVER_FDM;
   // In 3D with fast diagonalisation the refinement iterates in a workspace
   // (the adjoint's, which keeps nothing between calls) and the projection,
   // reading the iterate anyway, stores it minus its mean in out->p: no
@@ -930,7 +944,7 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
     });
   };
   if ((rc = poisson_solve(g, g->b, piter, g->d.poisson_tol, &last, &cg, &ir, !fold, false,
-                          in->p, fdm ? &project : nullptr)))
+                          in->p, fdm ? &project : nullptr, fuse_rhs)))
     return rc;
   g->last_iters = last;
   if (g->defer && g->sch->status == FVIB_ENOCONV)
@@ -1016,10 +1030,6 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
   // tolerances and above the double rounding floor of the residual.  A zero
   // right-hand side gives a zero target and a zero residual at once.
   const double rtol = (g->prec == FVIB_PREC_FP64) ? 1e-10 : 1e-7;
-  if ((rc = timed(g, FVIB_K_ADJ_RHS, [&] {
-         return launch_adj_rhs<T>(G, g->P64, ub1, g->b, g->red(), g->sc, rtol, g->stream);
-       })))
-    return rc;
   int cg = 0, ir = 0;
   // A caller's guess (the previous adjoint step's solution) usually leaves
   // one sweep to do.  The target is relative to this right-hand side, so a
@@ -1030,6 +1040,21 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
   const bool warm = bi->mu != nullptr && g->d.solver == FVIB_SOLVER_FDM;
   double* mu = bi->mu ? bi->mu : g->mu;
   if (!warm) FVIB_HIP(hipMemsetAsync(mu, 0, g->ncell * sizeof(double), g->stream));
+  // 3D without a body: the right-hand side and the first residual of the
+  // solve in one pass
+  const bool fuse_rhs = g->d.solver == FVIB_SOLVER_FDM && d == 3 && !g->has_body;
+  if (fuse_rhs) {
+    const bool d64 = g->prec == FVIB_PREC_FP64;
+    if ((rc = timed(g, FVIB_K_ADJ_RHS_RES, [&] {
+           return launch_adj_rhs_residual<T>(G, g->P64, ub1, mu, g->b, d64 ? g->r64 : nullptr,
+                                             d64 ? nullptr : g->r32, g->red(), g->sc, rtol,
+                                             g->max_iv, g->stream, g->sch_dev);
+         })))
+      return rc;
+  } else if ((rc = timed(g, FVIB_K_ADJ_RHS, [&] {
+                return launch_adj_rhs<T>(G, g->P64, ub1, g->b, g->red(), g->sc, rtol, g->stream);
+              })))
+    return rc;
   // ustar_bar (a pure function of mu) is queued behind each convergence check
   const std::function<int()> ustar = [&]() {
     return timed(g, FVIB_K_ADJ_USTAR,
@@ -1037,7 +1062,7 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
   };
   const bool fdm = g->d.solver == FVIB_SOLVER_FDM;
   if ((rc = poisson_solve(g, g->b, mu, -1.0, &g->last_iters_adj, &cg, &ir, false, warm, nullptr,
-                          fdm ? &ustar : nullptr)))
+                          fdm ? &ustar : nullptr, fuse_rhs)))
     return rc;
   if (g->defer && g->sch->status == FVIB_ENOCONV)
     return device_fail(g, FVIB_ENOCONV, "adjoint Poisson solve did not converge" +
@@ -1261,6 +1286,12 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
     delete h;
     return fail(nullptr, code, what);
   };
+  g->max_iv = 1.0;
+  for (int a = 0; a < g->dim; ++a) {
+    double mx = 0.0;
+    for (int i = 0; i < g->n[a]; ++i) mx = std::max(mx, 1.0 / (g->faces[a][i + 1] - g->faces[a][i]));
+    g->max_iv *= mx;
+  }
   // the allocation-free loss finds its static scratch on this device
   if (hipGetDevice(&g->device) != hipSuccess) return bail(FVIB_EHIP, "hipGetDevice failed");
   if (noalloc_scratch_init(g->device) != FVIB_OK)
@@ -1290,7 +1321,7 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
     ok &= dmalloc(&g->pA32, g->ncell * sizeof(float)) == FVIB_OK;
     ok &= dmalloc(&g->pB32, g->ncell * sizeof(float)) == FVIB_OK;
   }
-  ok &= dmalloc(&g->partial, 4 * kMaxRedBlocks * sizeof(double)) == FVIB_OK;
+  ok &= dmalloc(&g->partial, 5 * kMaxRedBlocks * sizeof(double)) == FVIB_OK;
   ok &= dmalloc(&g->sc, sizeof(SolverScalars)) == FVIB_OK;
   ok &= dmalloc(&g->info_dev, sizeof(fvib_step_info)) == FVIB_OK;
   ok &= dmalloc(&g->mu, g->ncell * sizeof(double)) == FVIB_OK;

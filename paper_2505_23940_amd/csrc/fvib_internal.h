@@ -463,7 +463,7 @@ struct SolverScalars {
 };
 
 struct RedBuf {
-  double* partial;          // 4 * kMaxRedBlocks doubles
+  double* partial;          // 5 * kMaxRedBlocks doubles
 };
 
 // ------------------------------------------------------------ host glue

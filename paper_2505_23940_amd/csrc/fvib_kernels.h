@@ -120,6 +120,14 @@ int launch_project(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
                    T* out[3], RedBuf red, SolverScalars* sc, hipStream_t s, double* pg = nullptr,
                    fvib_step_info* info = nullptr, int* sticky = nullptr);
 int launch_apply_A(const PGeo<double>& P, const double* x, double* y, hipStream_t s);
+// 3D without a body, fast diagonalisation: the PPE right-hand side b and the
+// first refinement residual r = b - A x (r64 for the double inner solve, else
+// r32) in one pass; criterion max |r| / V + |mean b| max_iv.
+template <typename T>
+int launch_rhs_residual(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
+                        const double* x, double* b, double* r64, float* r32, RedBuf red,
+                        SolverScalars* sc, double tol, double max_iv, hipStream_t s,
+                        SolverScalars* mirror);
 // y = a x over n doubles (y may alias x)
 int launch_scale(int64_t n, double a, const double* x, double* y, hipStream_t s);
 
@@ -154,6 +162,13 @@ int launch_strong_jac(const IbGeo& B, const IbView<T>& ib, const double* om, con
 int launch_strong_lambda(const double* DF, const double* RF, const double* wbar,
                          const double* ubody, const double* dF, double* lam, SolverScalars* sc,
                          hipStream_t s);
+// 3D without a body, fast diagonalisation: y = G^T ubar and the first
+// residual y - A x of the adjoint solve in one pass (target as launch_adj_rhs).
+template <typename T>
+int launch_adj_rhs_residual(const Geo<T>& G, const PGeo<double>& P, const T* const ub[3],
+                            const double* x, double* y, double* r64, float* r32, RedBuf red,
+                            SolverScalars* sc, double rtol, double max_iv, hipStream_t s,
+                            SolverScalars* mirror);
 template <typename T>
 // rtol: relative target of the adjoint solve, set on the device as
 // rtol * max |y / V| * dt / rho (used by a solve called with tol < 0).

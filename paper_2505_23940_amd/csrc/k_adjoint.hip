@@ -461,6 +461,154 @@ k_adj_rhs_col(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__ b0,
   block_partials<2, 1>(v, red.partial);
 }
 
+// 3D column march of k_adj_rhs_col fused with the first residual of the
+// adjoint solve: y = G^T ubar is stored for the later residuals and
+// r = y - A mu_in is handed to the fast-diagonalisation sweep without the mean
+// of y (the sweep drops the constant mode); the criterion is
+// max |r| / V + |mean y| max (1 / V), an upper bound of the mean-free one.
+// Same terms in the same order as k_adj_rhs_col (y) and k_residual (A mu).
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kBlock)
+k_adj_rhs_res_col(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__ b0,
+                  const T* __restrict__ b1, const T* __restrict__ b2,
+                  const double* __restrict__ x, double* __restrict__ y,
+                  double* __restrict__ r64, float* __restrict__ r32, RedBuf red) {
+  const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
+  const int64_t sxy = (int64_t)nx * ny;
+  double rr = 0.0, sx = 0.0, sy = 0.0, mr = 0.0, my = 0.0;
+  const int lx = threadIdx.x & (kTileX - 1), ly = threadIdx.x / kTileX;
+  for (int u = xcd_block(blockIdx.x, gridDim.x); u < ct.nunits; u += gridDim.x) {
+    const int tx = u % ct.ntx, ty = (u / ct.ntx) % ct.nty, zc = u / (ct.ntx * ct.nty);
+    const int i = tx * kTileX + lx, j = ty * kTileY + ly;
+    if (i >= nx || j >= ny) continue;
+    const int k0 = zc * ct.zchunk, k1 = min(k0 + ct.zchunk, nz);
+    const int ex0 = G.ext[0][0], ex1 = G.ext[0][1];
+    const int ey0 = G.ext[1][0], ey1 = G.ext[1][1];
+    const int ez0 = G.ext[2][0], ez1 = G.ext[2][1];
+    const int iH = (G.per[0] && i + 1 == nx) ? 0 : i + 1;
+    const int jH = (G.per[1] && j + 1 == ny) ? 0 : j + 1;
+    const int64_t uL = (int64_t)j * ex0 + i, uH = (int64_t)j * ex0 + iH;
+    const int64_t vL = (int64_t)j * ey0 + i, vH = (int64_t)jH * ey0 + i;
+    const int64_t wL = (int64_t)j * ez0 + i;
+    const int64_t su = (int64_t)ex0 * ex1, sv = (int64_t)ey0 * ey1, sw = (int64_t)ez0 * ez1;
+    const bool xl = G.per[0] || i > 0, xh = G.per[0] || i + 1 < nx;
+    const bool yl = G.per[1] || j > 0, yh = G.per[1] || j + 1 < ny;
+    const double cxl = P.idc[0][i], cxh = P.idc[0][i + 1];
+    const double cyl = P.idc[1][j], cyh = P.idc[1][j + 1];
+    const double ivxy = (double)P.iv[0][i] * (double)P.iv[1][j];
+    auto kup = [&](int k) { return (G.per[2] && k + 1 == nz) ? 0 : k + 1; };
+    // adjoint pressure column: x-y neighbours and coefficients
+    const int64_t cC = (int64_t)j * nx + i;
+    const int64_t cW = (int64_t)j * nx + (i > 0 ? i - 1 : (P.per[0] ? nx - 1 : 0));
+    const int64_t cE = (int64_t)j * nx + (i < nx - 1 ? i + 1 : (P.per[0] ? 0 : nx - 1));
+    const int64_t cS = (int64_t)(j > 0 ? j - 1 : (P.per[1] ? ny - 1 : 0)) * nx + i;
+    const int64_t cN = (int64_t)(j < ny - 1 ? j + 1 : (P.per[1] ? 0 : ny - 1)) * nx + i;
+    const double dxi = P.dx[0][i], dyj = P.dx[1][j];
+    const double kxl = P.kf[0][i], kxh = P.kf[0][i + 1];
+    const double kyl = P.kf[1][j], kyh = P.kf[1][j + 1];
+    const int pz = P.per[2];
+    auto klo = [&](int k) { return k > 0 ? k - 1 : (pz ? nz - 1 : 0); };
+    auto khi = [&](int k) { return k < nz - 1 ? k + 1 : (pz ? 0 : nz - 1); };
+    auto at = [&](int64_t off, int k) { return x[(int64_t)k * sxy + off]; };
+    double xm = at(cC, klo(k0)), xc = at(cC, k0), xp = at(cC, khi(k0));
+    double xw = at(cW, k0), xe = at(cE, k0), xs = at(cS, k0), xn = at(cN, k0);
+    double ulo = (double)b0[(int64_t)k0 * su + uL], uhi = (double)b0[(int64_t)k0 * su + uH];
+    double vlo = (double)b1[(int64_t)k0 * sv + vL], vhi = (double)b1[(int64_t)k0 * sv + vH];
+    double wlo = (double)b2[(int64_t)k0 * sw + wL], whi = (double)b2[(int64_t)kup(k0) * sw + wL];
+    for (int k = k0; k < k1; ++k) {
+      double ulo2 = 0.0, uhi2 = 0.0, vlo2 = 0.0, vhi2 = 0.0, whi2 = 0.0;
+      double xp2 = 0.0, xw2 = 0.0, xe2 = 0.0, xs2 = 0.0, xn2 = 0.0;
+      if (k + 1 < k1) {
+        const int64_t kn = k + 1;
+        ulo2 = (double)b0[kn * su + uL];
+        uhi2 = (double)b0[kn * su + uH];
+        vlo2 = (double)b1[kn * sv + vL];
+        vhi2 = (double)b1[kn * sv + vH];
+        whi2 = (double)b2[(int64_t)kup(k + 1) * sw + wL];
+        xp2 = at(cC, khi(k + 1));
+        xw2 = at(cW, k + 1);
+        xe2 = at(cE, k + 1);
+        xs2 = at(cS, k + 1);
+        xn2 = at(cN, k + 1);
+      }
+      const bool zl = G.per[2] || k > 0, zh = G.per[2] || k + 1 < nz;
+      double acc = 0.0;
+      acc += xl ? ulo * cxl : 0.0;
+      acc -= xh ? uhi * cxh : 0.0;
+      acc += yl ? vlo * cyl : 0.0;
+      acc -= yh ? vhi * cyh : 0.0;
+      acc += zl ? wlo * P.idc[2][k] : 0.0;
+      acc -= zh ? whi * P.idc[2][k + 1] : 0.0;
+      const double dzk = P.dx[2][k], kzl = P.kf[2][k], kzh = P.kf[2][k + 1];
+      double ax_ = 0.0;
+      const double ax = dyj * dzk, ay = dxi * dzk, az = dxi * dyj;
+      ax_ += ax * kxl * (xc - xw);
+      ax_ += ax * kxh * (xc - xe);
+      ax_ += ay * kyl * (xc - xs);
+      ax_ += ay * kyh * (xc - xn);
+      ax_ += az * kzl * (xc - xm);
+      ax_ += az * kzh * (xc - xp);
+      const double r = acc - ax_;
+      const double iv = ivxy * (double)P.iv[2][k];
+      const int64_t c = (int64_t)k * sxy + (int64_t)j * nx + i;
+      y[c] = acc;
+      if (MODE == 3)
+        r64[c] = r;
+      else
+        r32[c] = (float)r;
+      rr += r * r;
+      sx += xc;
+      sy += acc;
+      mr = fmax(mr, fabs(r) * iv);
+      my = fmax(my, fabs(acc) * iv);
+      ulo = ulo2;
+      uhi = uhi2;
+      vlo = vlo2;
+      vhi = vhi2;
+      wlo = whi;
+      whi = whi2;
+      xm = xc;
+      xc = xp;
+      xp = xp2;
+      xw = xw2;
+      xe = xe2;
+      xs = xs2;
+      xn = xn2;
+    }
+  }
+  double v[5] = {rr, sx, sy, mr, my};
+  block_partials<5, 3>(v, red.partial);
+}
+
+// Epilogue of k_adj_rhs_res_col: mean of y, the relative target of the
+// adjoint solve, then what FinResidual does for the first residual.
+struct FinAdjRhsResidual {
+  double inv_ncell, rtol, dt_over_rho, inner_rtol, max_iv;
+  SolverScalars* mirror;
+  __device__ bool skip(const SolverScalars*) const { return false; }
+  __device__ void apply(const double* t, SolverScalars* sc) const {
+    const double mb = t[2] * inv_ncell;
+    sc->meanb = mb;
+    sc->ymax = t[4];
+    sc->tol_dev = rtol * t[4] * dt_over_rho;
+    sc->sweeps = 0;
+    const double crit = (t[3] + fabs(mb) * max_iv) * dt_over_rho;
+    sc->rr = t[0];
+    sc->rr0 = t[0];
+    sc->beta = 0.0;
+    sc->iters = 0;
+    sc->crit = crit;
+    sc->sumx = t[1];
+    sc->tol_rr = inner_rtol * inner_rtol * t[0];
+    const bool bad = !(t[0] == t[0]) || !(crit == crit);
+    if (bad) sc->status = FVIB_ENONFINITE;
+    const bool conv = bad || crit <= sc->tol_dev || t[0] == 0.0;
+    sc->done = conv ? 1 : 0;
+    sc->outer_done = conv ? 1 : 0;
+    if (mirror) *mirror = *sc;
+  }
+};
+
 struct FinAdjRhs {          // mean of G^T ubar, max |y / V| and the solve target
   double inv_ncell, rtol, dt_over_rho;
   __device__ bool skip(const SolverScalars*) const { return false; }
@@ -1165,6 +1313,27 @@ int launch_strong_lambda(const double* DF, const double* RF, const double* wbar,
 }
 
 template <typename T>
+int launch_adj_rhs_residual(const Geo<T>& G, const PGeo<double>& P, const T* const ub[3],
+                            const double* x, double* y, double* r64, float* r32, RedBuf red,
+                            SolverScalars* sc, double rtol, double max_iv, hipStream_t s,
+                            SolverScalars* mirror) {
+  if (G.dim != 3) return FVIB_EINVAL;
+  const ColTiling ct = make_col_tiling(G.n[0], G.n[1], G.n[2]);
+  if (r64)
+    launch_kernel((k_adj_rhs_res_col<T, 3>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct,
+                  ub[0], ub[1], ub[2], x, y, r64, r32, red);
+  else
+    launch_kernel((k_adj_rhs_res_col<T, 2>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct,
+                  ub[0], ub[1], ub[2], x, y, r64, r32, red);
+  FVIB_HIP(hipGetLastError());
+  FVIB_HIP((launch_finish<5, 3>(red.partial, ct.nblocks, sc,
+                                FinAdjRhsResidual{P.inv_ncell, rtol, P.dt_over_rho, 0.5, max_iv,
+                                                  mirror},
+                                s)));
+  return FVIB_OK;
+}
+
+template <typename T>
 int launch_adj_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const ub[3], double* y,
                    RedBuf red, SolverScalars* sc, double rtol, hipStream_t s) {
   if (G.dim == 3) {
@@ -1279,6 +1448,10 @@ static int launch_adj_momentum_t(const AdjCtx<T>& X, T* ubar[3], T* fbbar[3], hi
                                         SolverScalars*, int, hipStream_t);                      \
   template int launch_strong_jac<T>(const IbGeo&, const IbView<T>&, const double*,              \
                                     const double*, double*, double*, hipStream_t);              \
+  template int launch_adj_rhs_residual<T>(const Geo<T>&, const PGeo<double>&,                  \
+                                          const T* const[3], const double*, double*, double*,   \
+                                          float*, RedBuf, SolverScalars*, double, double,       \
+                                          hipStream_t, SolverScalars*);                         \
   template int launch_adj_rhs<T>(const Geo<T>&, const PGeo<double>&, const T* const[3],         \
                                  double*, RedBuf, SolverScalars*, double, hipStream_t);         \
   template int launch_adj_ustar<T>(const Geo<T>&, const PGeo<double>&, const T* const[3],       \

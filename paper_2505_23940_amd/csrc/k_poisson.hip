@@ -339,6 +339,151 @@ k_residual(PGeo<double> P, ColTiling ct, const double* __restrict__ b,
   block_partials<3, 2>(v, red.partial);
 }
 
+// ------------------------------------- RHS and first residual (3D, FDM)
+// The right-hand side of Eq. 9 (no immersed body) and the first residual of
+// the refinement in one column march: b = -(rho/dt) S u* is stored for the
+// later residuals, and r = b - A x_in is handed to the fast-diagonalisation
+// sweep without the mean of b, which is not known until the reduction ends
+// (the sweep drops the constant mode, so the correction is the same).  The
+// stopping criterion is taken as max |r| / V + |mean b| max (1 / V), an
+// upper bound of the criterion of the mean-free residual.  Same terms in the
+// same order as k_ppe_rhs (b) and k_residual (A x).
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kBlock)
+k_rhs_residual_col(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__ s0,
+                   const T* __restrict__ s1, const T* __restrict__ s2,
+                   const double* __restrict__ x, double* __restrict__ b,
+                   double* __restrict__ r64, float* __restrict__ r32, RedBuf red) {
+  const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+  const int64_t sxy = (int64_t)nx * ny;
+  const double scale = -1.0 / P.dt_over_rho;
+  double rr = 0.0, sx = 0.0, sb = 0.0, mx = 0.0;
+  const int lx = threadIdx.x & (kTileX - 1), ly = threadIdx.x / kTileX;
+  for (int u = xcd_block(blockIdx.x, gridDim.x); u < ct.nunits; u += gridDim.x) {
+    const int tx = u % ct.ntx, ty = (u / ct.ntx) % ct.nty, zc = u / (ct.ntx * ct.nty);
+    const int i = tx * kTileX + lx, j = ty * kTileY + ly;
+    if (i >= nx || j >= ny) continue;
+    const int k0 = zc * ct.zchunk, k1 = min(k0 + ct.zchunk, nz);
+    // velocity faces of the column: u at i and its high face, v at j and its
+    // high face, w at k and k + 1 (wrapped on periodic axes)
+    const int iH = (G.per[0] && i + 1 == nx) ? 0 : i + 1;
+    const int jH = (G.per[1] && j + 1 == ny) ? 0 : j + 1;
+    const int ex0 = G.ext[0][0], ex1 = G.ext[0][1];
+    const int ey0 = G.ext[1][0], ey1 = G.ext[1][1];
+    const int ez0 = G.ext[2][0], ez1 = G.ext[2][1];
+    const int64_t su = (int64_t)ex0 * ex1, sv = (int64_t)ey0 * ey1, sw = (int64_t)ez0 * ez1;
+    const int64_t uL = (int64_t)j * ex0 + i, uH = (int64_t)j * ex0 + iH;
+    const int64_t vL = (int64_t)j * ey0 + i, vH = (int64_t)jH * ey0 + i;
+    const int64_t wL = (int64_t)j * ez0 + i;
+    auto kup = [&](int k) { return (G.per[2] && k + 1 == nz) ? 0 : k + 1; };
+    // pressure column: x-y neighbours (wrapped / clamped; kf = 0 on the
+    // boundary faces) and coefficients
+    const int64_t cC = (int64_t)j * nx + i;
+    const int64_t cW = (int64_t)j * nx + nb_lo(i, nx, P.per[0]);
+    const int64_t cE = (int64_t)j * nx + nb_hi(i, nx, P.per[0]);
+    const int64_t cS = (int64_t)nb_lo(j, ny, P.per[1]) * nx + i;
+    const int64_t cN = (int64_t)nb_hi(j, ny, P.per[1]) * nx + i;
+    const double dxi = P.dx[0][i], dyj = P.dx[1][j];
+    const double kxl = P.kf[0][i], kxh = P.kf[0][i + 1];
+    const double kyl = P.kf[1][j], kyh = P.kf[1][j + 1];
+    const double ivxy = (double)P.iv[0][i] * (double)P.iv[1][j];
+    const int pz = P.per[2];
+    auto at = [&](int64_t off, int k) { return x[(int64_t)k * sxy + off]; };
+    double xm = at(cC, nb_lo(k0, nz, pz)), xc = at(cC, k0), xp = at(cC, nb_hi(k0, nz, pz));
+    double xw = at(cW, k0), xe = at(cE, k0), xs = at(cS, k0), xn = at(cN, k0);
+    double ul = (double)s0[(int64_t)k0 * su + uL], uh = (double)s0[(int64_t)k0 * su + uH];
+    double vl = (double)s1[(int64_t)k0 * sv + vL], vh = (double)s1[(int64_t)k0 * sv + vH];
+    double wl = (double)s2[(int64_t)k0 * sw + wL], wh = (double)s2[(int64_t)kup(k0) * sw + wL];
+    for (int k = k0; k < k1; ++k) {
+      // plane k + 1 is fetched while plane k is evaluated
+      double xp2 = 0.0, xw2 = 0.0, xe2 = 0.0, xs2 = 0.0, xn2 = 0.0;
+      double ul2 = 0.0, uh2 = 0.0, vl2 = 0.0, vh2 = 0.0, wh2 = 0.0;
+      if (k + 1 < k1) {
+        const int64_t kn = k + 1;
+        xp2 = at(cC, nb_hi(k + 1, nz, pz));
+        xw2 = at(cW, k + 1);
+        xe2 = at(cE, k + 1);
+        xs2 = at(cS, k + 1);
+        xn2 = at(cN, k + 1);
+        ul2 = (double)s0[kn * su + uL];
+        uh2 = (double)s0[kn * su + uH];
+        vl2 = (double)s1[kn * sv + vL];
+        vh2 = (double)s1[kn * sv + vH];
+        wh2 = (double)s2[(int64_t)kup(k + 1) * sw + wL];
+      }
+      const double dzk = P.dx[2][k], kzl = P.kf[2][k], kzh = P.kf[2][k + 1];
+      // b of this cell (the terms of k_ppe_rhs in its order)
+      double fl = 0.0;
+      fl += uh * (dyj * dzk) - ul * (dyj * dzk);
+      fl += vh * (dxi * dzk) - vl * (dxi * dzk);
+      fl += wh * (dxi * dyj) - wl * (dxi * dyj);
+      const double bc = scale * fl;
+      // A x (the terms of k_residual in its order)
+      double acc = 0.0;
+      const double ax = dyj * dzk, ay = dxi * dzk, az = dxi * dyj;
+      acc += ax * kxl * (xc - xw);
+      acc += ax * kxh * (xc - xe);
+      acc += ay * kyl * (xc - xs);
+      acc += ay * kyh * (xc - xn);
+      acc += az * kzl * (xc - xm);
+      acc += az * kzh * (xc - xp);
+      const double r = bc - acc;
+      const int64_t c = (int64_t)k * sxy + cC;
+      b[c] = bc;
+      if (MODE == 3)
+        r64[c] = r;
+      else
+        r32[c] = (float)r;
+      rr += r * r;
+      sx += xc;
+      sb += bc;
+      mx = fmax(mx, fabs(r) * (ivxy * (double)P.iv[2][k]));
+      xm = xc;
+      xc = xp;
+      xp = xp2;
+      xw = xw2;
+      xe = xe2;
+      xs = xs2;
+      xn = xn2;
+      ul = ul2;
+      uh = uh2;
+      vl = vl2;
+      vh = vh2;
+      wl = wh;
+      wh = wh2;
+    }
+  }
+  double v[4] = {rr, sx, sb, mx};
+  block_partials<4, 3>(v, red.partial);
+}
+
+// Epilogue of k_rhs_residual_col: the mean of b, then what FinResidual does
+// for the first residual of a solve, on the upper-bound criterion.
+struct FinRhsResidual {
+  double tol, inner_rtol, dt_over_rho, inv_ncell, max_iv;
+  SolverScalars* mirror;
+  __device__ bool skip(const SolverScalars*) const { return false; }
+  __device__ void apply(const double* t, SolverScalars* sc) const {
+    const double mb = t[2] * inv_ncell;
+    sc->meanb = mb;
+    sc->sweeps = 0;
+    const double crit = (t[3] + fabs(mb) * max_iv) * dt_over_rho;
+    sc->rr = t[0];
+    sc->rr0 = t[0];
+    sc->beta = 0.0;
+    sc->iters = 0;
+    sc->crit = crit;
+    sc->sumx = t[1];
+    sc->tol_rr = inner_rtol * inner_rtol * t[0];
+    const bool bad = !(t[0] == t[0]) || !(crit == crit);
+    if (bad) sc->status = FVIB_ENONFINITE;
+    const bool conv = bad || crit <= tol || t[0] == 0.0;
+    sc->done = conv ? 1 : 0;
+    sc->outer_done = conv ? 1 : 0;
+    if (mirror) *mirror = *sc;
+  }
+};
+
 // ------------------------------------------------------ CG direction
 // p_new = r + beta p_old (beta = 0 on the first iteration), then p.Ap and
 // sum(p).  p_new is formed on the fly at the stencil neighbours, so p_old
@@ -621,6 +766,27 @@ int launch_residual(const PGeo<double>& P, int mode, const double* b, const doub
   return FVIB_OK;
 }
 
+template <typename T>
+int launch_rhs_residual(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
+                        const double* x, double* b, double* r64, float* r32, RedBuf red,
+                        SolverScalars* sc, double tol, double max_iv, hipStream_t s,
+                        SolverScalars* mirror) {
+  if (G.dim != 3) return FVIB_EINVAL;
+  const ColTiling ct = make_col_tiling(P.n[0], P.n[1], P.n[2]);
+  if (r64)
+    launch_kernel((k_rhs_residual_col<T, 3>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct,
+                  us[0], us[1], us[2], x, b, r64, r32, red);
+  else
+    launch_kernel((k_rhs_residual_col<T, 2>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct,
+                  us[0], us[1], us[2], x, b, r64, r32, red);
+  FVIB_HIP(hipGetLastError());
+  FVIB_HIP((launch_finish<4, 3>(red.partial, ct.nblocks, sc,
+                                FinRhsResidual{tol, 0.5, P.dt_over_rho, P.inv_ncell, max_iv,
+                                               mirror},
+                                s)));
+  return FVIB_OK;
+}
+
 template <typename V>
 int launch_cg_iter(const PGeo<V>& P, int mode, const V* r, const V* pold, V* pnew, V* x, V* rw,
                    RedBuf red, SolverScalars* sc, double tol, int maxit, hipStream_t s,
@@ -715,6 +881,14 @@ template int launch_ppe_rhs<float>(const Geo<float>&, const PGeo<double>&, const
 template int launch_ppe_rhs<double>(const Geo<double>&, const PGeo<double>&,
                                     const double* const[3], const IbView<double>&, double*,
                                     RedBuf, SolverScalars*, hipStream_t);
+template int launch_rhs_residual<float>(const Geo<float>&, const PGeo<double>&,
+                                        const float* const[3], const double*, double*, double*,
+                                        float*, RedBuf, SolverScalars*, double, double,
+                                        hipStream_t, SolverScalars*);
+template int launch_rhs_residual<double>(const Geo<double>&, const PGeo<double>&,
+                                         const double* const[3], const double*, double*,
+                                         double*, float*, RedBuf, SolverScalars*, double, double,
+                                         hipStream_t, SolverScalars*);
 template int launch_cg_iter<float>(const PGeo<float>&, int, const float*, const float*, float*,
                                    float*, float*, RedBuf, SolverScalars*, double, int,
                                    hipStream_t, hipEvent_t*);
