@@ -94,6 +94,12 @@ enum { FVIB_BODY_STATIC = 0, FVIB_BODY_RIGID_SPRING = 1 };
  * refinement; both stop on the same double-precision divergence test. */
 enum { FVIB_SOLVER_CG = 0, FVIB_SOLVER_FDM = 1 };
 enum { FVIB_DTYPE_F32 = 0, FVIB_DTYPE_F64 = 1 };
+/* Time schemes of fvib_step_rk (Sec. 2.3.1, Table 1: forward Euler or an
+ * explicit Runge-Kutta scheme), in Shu-Osher form over the forward-Euler
+ * step S(v) = P(v + dt R(v)): v_0 = u^n, v_s = a_s u^n + b_s S(v_{s-1}),
+ * u^{n+1} = v_S.  FE: (0, 1).  RK2 (Heun): (0, 1), (1/2, 1/2).  RK3 (third
+ * order, strong-stability preserving): (0, 1), (3/4, 1/4), (1/3, 2/3). */
+enum { FVIB_TIME_FE = 0, FVIB_TIME_RK2 = 1, FVIB_TIME_RK3 = 2 };
 
 /* Grid and solver description (Sec. 2.5 of the paper). */
 typedef struct {
@@ -249,6 +255,38 @@ int fvib_step_strong(fvib_grid *g, const fvib_fields *in, fvib_fields *out, int3
 int fvib_step_strong_adjoint(fvib_grid *g, const fvib_fields *fwd_in, const double *omega,
                              const fvib_adjoint *bar_out, const double *dF,
                              fvib_adjoint *bar_in, fvib_step_info *info);
+
+/* One explicit Runge-Kutta step of the fluid (Sec. 2.3.1 and Table 1; the
+ * schemes are listed at FVIB_TIME_*), each stage a forward-Euler step with
+ * its own modified PPE solve and correction, the correction writing the
+ * stage combination a_s u^n + b_s S(v_{s-1}) itself.  Every stage is
+ * divergence free.  Grids without a body (FVIB_ESTATE otherwise: a stage
+ * combination would not hold the forced faces at the body velocity).  out
+ * may alias in; out->p receives the last stage's pressure (each stage's
+ * solve starts from the previous one's).  info: the last stage's record.
+ * The first call allocates the Runge-Kutta workspace (six velocity sets and
+ * one cell array). */
+int fvib_step_rk(fvib_grid *g, const fvib_fields *in, fvib_fields *out, int scheme,
+                 fvib_step_info *info);
+
+/* Discrete adjoint of fvib_step_rk at fwd_in (Sec. 2.4.1): the stage inputs
+ * are recomputed from fwd_in->u (fwd_in->p, may be NULL, is the solves'
+ * initial guess), then each stage's forward-Euler adjoint is applied in
+ * reverse order.  Writes bar_in->u, adds into bar_in->fb; bar_in->mu as in
+ * fvib_step_adjoint.  bar_in may not alias bar_out. */
+int fvib_step_rk_adjoint(fvib_grid *g, const fvib_fields *fwd_in, const fvib_adjoint *bar_out,
+                         fvib_adjoint *bar_in, int scheme, fvib_step_info *info);
+
+/* Change the time step of the handle (every later step and adjoint step
+ * uses it; Sec. 2.5: fixed or CFL-adaptive time steps). */
+int fvib_set_dt(fvib_grid *g, double dt);
+
+/* CFL-adaptive time step from the instantaneous maximum velocity (Sec. 2.5):
+ * *dt (host) = min(dt_max, cfl h_min / max |u|), the maximum over every face
+ * value of every component (a device reduction) and h_min the smallest cell
+ * width; dt_max when u is zero.  Synchronises the stream.  Does not change
+ * the handle's time step (fvib_set_dt does). */
+int fvib_cfl_dt(fvib_grid *g, const void *const u[3], double cfl, double dt_max, double *dt);
 
 /* Mean wall shear J = (nu/2) [ <u>_lo / (yc_0 - y_0) + <u>_hi / (y_N - yc_{N-1}) ]
  * of the streamwise velocity at the two wall-adjacent rows (walls normal

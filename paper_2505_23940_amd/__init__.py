@@ -21,7 +21,8 @@ from ._abi import BC, BODY, CONV, PREC, SOLVER, STATUS_NAMES
 
 __all__ = ["Grid", "FvibError", "fvib_create_grid", "fvib_destroy_grid", "fvib_field_layout",
            "fvib_ib_set_body", "fvib_step", "fvib_step_adjoint", "fvib_step_strong",
-           "fvib_step_strong_adjoint", "fvib_loss_wall_shear",
+           "fvib_step_strong_adjoint", "fvib_step_rk", "fvib_step_rk_adjoint", "fvib_set_dt",
+           "fvib_cfl_dt", "fvib_loss_wall_shear",
            "fvib_loss_wall_shear_noalloc", "fvib_loss_rms_lift", "fvib_last_error", "fvib_version", "lib"]
 
 
@@ -87,6 +88,28 @@ def fvib_step_strong_adjoint(h, fin: _abi.Fields, omega_ptr: int, bar_out: _abi.
     return lib().fvib_step_strong_adjoint(h, C.byref(fin), C.c_void_p(omega_ptr),
                                           C.byref(bar_out), C.c_void_p(dF_ptr), C.byref(bar_in),
                                           C.c_void_p(info_ptr))
+
+
+def fvib_step_rk(h, fin: _abi.Fields, fout: _abi.Fields, scheme: int, info_ptr: int = 0) -> int:
+    return lib().fvib_step_rk(h, C.byref(fin), C.byref(fout), int(scheme), C.c_void_p(info_ptr))
+
+
+def fvib_step_rk_adjoint(h, fin: _abi.Fields, bar_out: _abi.Adjoint, bar_in: _abi.Adjoint,
+                         scheme: int, info_ptr: int = 0) -> int:
+    return lib().fvib_step_rk_adjoint(h, C.byref(fin), C.byref(bar_out), C.byref(bar_in),
+                                      int(scheme), C.c_void_p(info_ptr))
+
+
+def fvib_set_dt(h, dt: float) -> int:
+    return lib().fvib_set_dt(h, float(dt))
+
+
+def fvib_cfl_dt(h, u_ptrs, cfl: float, dt_max: float):
+    vp = C.c_void_p * 3
+    out = C.c_double()
+    rc = lib().fvib_cfl_dt(h, vp(*(list(u_ptrs) + [0] * (3 - len(u_ptrs)))), float(cfl),
+                           float(dt_max), C.byref(out))
+    return rc, out.value
 
 
 def fvib_step_adjoint(h, fin: _abi.Fields, bar_out: _abi.Adjoint, dF_ptr: int,
@@ -296,11 +319,12 @@ class Grid:
 
     def step(self, u, p, fb=None, body=None, kc=None, u_out=None, p_out=None, body_out=None,
              info: Optional[torch.Tensor] = None, check: bool = True, coupling=None,
-             omega: Optional[torch.Tensor] = None) -> int:
+             omega: Optional[torch.Tensor] = None, scheme: Optional[str] = None) -> int:
         """One time step; in place unless *_out are given.  Returns the status.
         coupling = (max_iters, tol) makes it the strongly coupled step
         (fvib_step_strong); omega (6 doubles) then receives the iterate the
-        fluid saw last, which its adjoint needs."""
+        fluid saw last, which its adjoint needs.  scheme ("fe", "rk2", "rk3")
+        makes it an explicit Runge-Kutta step (fvib_step_rk)."""
         self._check_u(u)
         if fb is not None:
             self._check_u(fb, "fb")
@@ -318,7 +342,11 @@ class Grid:
         fin = self._fields(u, p, fb, body, kc)
         fout = self._fields(u_out, p_out, fb, body_out, kc)
         ip = _ptr(info if info is not None else self._info)
-        if coupling is None:
+        if scheme is not None:
+            if coupling is not None:
+                raise ValueError("a Runge-Kutta step has no coupling iterations")
+            rc = fvib_step_rk(self.h, fin, fout, _abi.TIME[scheme], ip)
+        elif coupling is None:
             rc = fvib_step(self.h, fin, fout, ip)
         else:
             nmax, tol = coupling
@@ -335,7 +363,8 @@ class Grid:
                      fbbar=None, kcbar=None, check: bool = True,
                      info: Optional[torch.Tensor] = None,
                      mu: Optional[torch.Tensor] = None,
-                     omega: Optional[torch.Tensor] = None) -> int:
+                     omega: Optional[torch.Tensor] = None, scheme: Optional[str] = None,
+                     p: Optional[torch.Tensor] = None) -> int:
         """Adjoint of one step (fvib_step_adjoint).  mu (optional, float64,
         pressure layout) warm-starts the adjoint Poisson solve and receives
         its solution.  With omega (the iterate a strongly coupled step
@@ -368,7 +397,11 @@ class Grid:
         bi.kc = _ptr(kcbar)
         bi.mu = _ptr(mu)
         ip = _ptr(info if info is not None else self._info)
-        if omega is None:
+        if scheme is not None:
+            self._check_t(p, "p", shape=self.pshape, required=False)
+            fin.p = _ptr(p)
+            rc = fvib_step_rk_adjoint(self.h, fin, bo, bi, _abi.TIME[scheme], ip)
+        elif omega is None:
             rc = fvib_step_adjoint(self.h, fin, bo, _ptr(dF), bi, ip)
         else:
             self._check_t(omega, "omega", min_numel=6)
@@ -546,6 +579,18 @@ class Grid:
                                                 _ptr(bodybar_out), _ptr(bin_), _ptr(Fbar),
                                                 _ptr(kcbar)), self.h)
         return bin_, Fbar
+
+    def set_dt(self, dt: float) -> None:
+        """Time step of every later step (fvib_set_dt)."""
+        _check(fvib_set_dt(self.h, dt), self.h)
+        self.dt = float(dt)
+
+    def cfl_dt(self, u, cfl: float, dt_max: float) -> float:
+        """min(dt_max, cfl h_min / max |u|) from a device reduction (fvib_cfl_dt)."""
+        self._check_u(u)
+        rc, dt = fvib_cfl_dt(self.h, [_ptr(x) for x in u], cfl, dt_max)
+        _check(rc, self.h)
+        return dt
 
     def clear_error(self) -> None:
         """Reset the handle after a device-side failure (fvib_clear_error)."""

@@ -151,6 +151,16 @@ struct Grid {
   FdmPlan<float> F32;
   double* body_tmp = nullptr;     // strong-coupling iterates, Jacobians and adjoints
   double max_iv = 0.0;            // max over cells of 1 / V
+  double h_min = 0.0;             // smallest cell width
+  // Runge-Kutta workspace (allocated at the first Runge-Kutta call): two
+  // stage velocities, the step's input copy (in-place steps), three adjoint
+  // velocity sets and a pressure for recomputed stages
+  void* rkv[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+  void* rku0[3] = {nullptr, nullptr, nullptr};
+  void* rkW[3] = {nullptr, nullptr, nullptr};
+  void* rkZ[3] = {nullptr, nullptr, nullptr};
+  void* rkA[3] = {nullptr, nullptr, nullptr};
+  double* rkp = nullptr;
   int last_iters = 0;
   int last_iters_adj = 0;
   bool defer = false;        // steps return once enqueued (fvib_defer_status)
@@ -219,6 +229,15 @@ static void release(Grid* g) {
   if (g->sticky_h) (void)hipHostFree(g->sticky_h);
   f(g->ib_mem);
   f(g->origin);
+  for (int c = 0; c < 3; ++c) {
+    f(g->rkv[0][c]);
+    f(g->rkv[1][c]);
+    f(g->rku0[c]);
+    f(g->rkW[c]);
+    f(g->rkZ[c]);
+    f(g->rkA[c]);
+  }
+  f(g->rkp);
   for (int c = 0; c < 2; ++c) {
     f(g->cls[c]);
     f(g->us[c]);
@@ -874,7 +893,7 @@ static int strong_iterate(Grid* g, const fvib_fields* in, const StrongOpt* so, c
 
 template <typename T>
 static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step_info* info,
-                     const StrongOpt* so = nullptr) {
+                     const StrongOpt* so = nullptr, const StageMix* mix = nullptr) {
   int rc;
   if ((rc = reset_scalars(g))) return rc;
   const T* u[3] = {(const T*)in->u[0], (const T*)in->u[1], g->dim == 3 ? (const T*)in->u[2] : nullptr};
@@ -940,7 +959,7 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
     return timed(g, FVIB_K_PROJECT, [&] {
       return launch_project<T>(G, g->P64, (const T* const*)us, piter, uo, g->red(), g->sc,
                                g->stream, fold ? out->p : nullptr, rec ? dst : nullptr,
-                               g->sticky_d);
+                               g->sticky_d, mix);
     });
   };
   if ((rc = poisson_solve(g, g->b, piter, g->d.poisson_tol, &last, &cg, &ir, !fold, false,
@@ -1104,6 +1123,155 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
   }
   if (st == FVIB_ENONFINITE) return device_fail(g, st, "non-finite value in the adjoint");
   g->err.clear();
+  return FVIB_OK;
+}
+
+// ---------------------------------------------------------- Runge-Kutta
+// Explicit Runge-Kutta steps in Shu-Osher form over the forward-Euler step
+// S(v) = P(v + dt R(v)) (Sec. 2.3.1: explicit Runge-Kutta schemes besides
+// forward Euler): v_0 = u^n, v_s = a_s u^n + b_s S(v_{s-1}), u^{n+1} = v_S.
+// The velocity correction of each stage writes a_s u^n + b_s S(v_{s-1})
+// itself (no separate combination pass).  Grids without a body.
+struct RkScheme {
+  int stages;
+  double a[3], b[3];
+};
+
+static const RkScheme* rk_scheme(int scheme) {
+  static const RkScheme fe{1, {0.0, 0.0, 0.0}, {1.0, 0.0, 0.0}};
+  static const RkScheme rk2{2, {0.0, 0.5, 0.0}, {1.0, 0.5, 0.0}};
+  static const RkScheme rk3{3, {0.0, 0.75, 1.0 / 3.0}, {1.0, 0.25, 2.0 / 3.0}};
+  switch (scheme) {
+    case FVIB_TIME_FE: return &fe;
+    case FVIB_TIME_RK2: return &rk2;
+    case FVIB_TIME_RK3: return &rk3;
+    default: return nullptr;
+  }
+}
+
+static int ensure_rk_buffers(Grid* g) {
+  if (g->rkp) return FVIB_OK;
+  const size_t es = g->esize();
+  bool ok = true;
+  for (int c = 0; c < g->dim; ++c) {
+    const size_t nb = (size_t)g->nface[c] * es;
+    ok &= dmalloc(&g->rkv[0][c], nb) == FVIB_OK;
+    ok &= dmalloc(&g->rkv[1][c], nb) == FVIB_OK;
+    ok &= dmalloc(&g->rku0[c], nb) == FVIB_OK;
+    ok &= dmalloc(&g->rkW[c], nb) == FVIB_OK;
+    ok &= dmalloc(&g->rkZ[c], nb) == FVIB_OK;
+    ok &= dmalloc(&g->rkA[c], nb) == FVIB_OK;
+  }
+  ok &= dmalloc(&g->rkp, g->ncell * sizeof(double)) == FVIB_OK;
+  if (!ok) return fail(g, FVIB_ENOMEM, "device allocation of the Runge-Kutta workspace failed");
+  return FVIB_OK;
+}
+
+static fvib_fields with_u(const fvib_fields* f, void* const u[3], double* p) {
+  fvib_fields r = *f;
+  for (int c = 0; c < 3; ++c) r.u[c] = u[c];
+  r.p = p;
+  return r;
+}
+
+template <typename T>
+static int rk_impl(Grid* g, const fvib_fields* in, fvib_fields* out, const RkScheme* S,
+                   fvib_step_info* info) {
+  int rc;
+  const int d = g->dim;
+  const void* u0[3] = {in->u[0], in->u[1], d == 3 ? in->u[2] : nullptr};
+  bool alias = false;
+  for (int c = 0; c < d; ++c) alias = alias || out->u[c] == in->u[c];
+  if (alias && S->stages > 1) {
+    // the corrections of later stages read u^n while the last one writes
+    // out, and a correction may be repeated: keep a copy of u^n
+    for (int c = 0; c < d; ++c) {
+      FVIB_HIP(hipMemcpyAsync(g->rku0[c], in->u[c], g->nface[c] * g->esize(),
+                              hipMemcpyDeviceToDevice, g->stream));
+      u0[c] = g->rku0[c];
+    }
+  }
+  void* vin[3] = {in->u[0], in->u[1], in->u[2]};
+  for (int s = 0; s < S->stages; ++s) {
+    const bool last = s == S->stages - 1;
+    void* vout[3];
+    for (int c = 0; c < 3; ++c) vout[c] = last ? out->u[c] : g->rkv[s & 1][c];
+    const fvib_fields fi = with_u(in, vin, s == 0 ? in->p : out->p);
+    fvib_fields fo = with_u(out, vout, out->p);
+    const StageMix m{{u0[0], u0[1], u0[2]}, S->a[s], S->b[s]};
+    const bool plain = S->a[s] == 0.0 && S->b[s] == 1.0;
+    if ((rc = step_impl<T>(g, &fi, &fo, last ? info : nullptr, nullptr, plain ? nullptr : &m)))
+      return rc;
+    for (int c = 0; c < 3; ++c) vin[c] = vout[c];
+  }
+  return FVIB_OK;
+}
+
+// Adjoint of rk_impl: the stage inputs v_1 .. v_{S-1} are recomputed from
+// u^n, then, with W the adjoint of v_s (from v_S = u^{n+1}) and A the
+// accumulated adjoint of u^n:  A += a_s W;  W = S^T(v_{s-1}; b_s W) (the
+// adjoint of one forward-Euler step, f_b adjoint accumulated);  and finally
+// the adjoint of u^n is W + A.
+template <typename T>
+static int rk_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint* bo,
+                           fvib_adjoint* bi, const RkScheme* S, fvib_step_info* info) {
+  int rc;
+  const int d = g->dim;
+  const T* u0[3] = {(const T*)in->u[0], (const T*)in->u[1], d == 3 ? (const T*)in->u[2] : nullptr};
+  // recompute the stage inputs (pressure guess: the step's input pressure)
+  if (in->p)
+    FVIB_HIP(hipMemcpyAsync(g->rkp, in->p, g->ncell * sizeof(double), hipMemcpyDeviceToDevice,
+                            g->stream));
+  else
+    FVIB_HIP(hipMemsetAsync(g->rkp, 0, g->ncell * sizeof(double), g->stream));
+  void* vin[3] = {in->u[0], in->u[1], in->u[2]};
+  for (int s = 0; s + 1 < S->stages; ++s) {
+    void* vout[3] = {g->rkv[s & 1][0], g->rkv[s & 1][1], g->rkv[s & 1][2]};
+    const fvib_fields fi = with_u(in, vin, g->rkp);
+    fvib_fields fo = with_u(in, vout, g->rkp);
+    const StageMix m{{u0[0], u0[1], u0[2]}, S->a[s], S->b[s]};
+    const bool plain = S->a[s] == 0.0 && S->b[s] == 1.0;
+    if ((rc = step_impl<T>(g, &fi, &fo, nullptr, nullptr, plain ? nullptr : &m))) return rc;
+    for (int c = 0; c < 3; ++c) vin[c] = vout[c];
+  }
+  // reverse sweep over the stages
+  for (int c = 0; c < d; ++c) {
+    FVIB_HIP(hipMemcpyAsync(g->rkW[c], bo->u[c], g->nface[c] * g->esize(),
+                            hipMemcpyDeviceToDevice, g->stream));
+    FVIB_HIP(hipMemsetAsync(g->rkA[c], 0, g->nface[c] * g->esize(), g->stream));
+  }
+  for (int s = S->stages - 1; s >= 0; --s) {
+    for (int c = 0; c < d; ++c) {
+      if (S->a[s] != 0.0 &&
+          (rc = launch_axpby<T>(g->nface[c], S->a[s], (const T*)g->rkW[c], 1.0, (T*)g->rkA[c],
+                                g->stream)))
+        return rc;
+      if ((rc = launch_axpby<T>(g->nface[c], S->b[s], (const T*)g->rkW[c], 0.0, (T*)g->rkZ[c],
+                                g->stream)))
+        return rc;
+    }
+    void* vs[3];
+    for (int c = 0; c < 3; ++c) vs[c] = s == 0 ? in->u[c] : g->rkv[(s - 1) & 1][c];
+    const fvib_fields fi = with_u(in, vs, nullptr);
+    fvib_adjoint bo_s{};
+    fvib_adjoint bi_s{};
+    for (int c = 0; c < 3; ++c) {
+      bo_s.u[c] = g->rkZ[c];
+      bi_s.u[c] = g->rkW[c];
+      bi_s.fb[c] = bi->fb[c];
+    }
+    bi_s.mu = bi->mu;
+    if ((rc = step_adjoint_impl<T>(g, &fi, &bo_s, nullptr, &bi_s, s == 0 ? info : nullptr)))
+      return rc;
+  }
+  for (int c = 0; c < d; ++c) {
+    FVIB_HIP(hipMemcpyAsync(bi->u[c], g->rkW[c], g->nface[c] * g->esize(),
+                            hipMemcpyDeviceToDevice, g->stream));
+    if ((rc = launch_axpby<T>(g->nface[c], 1.0, (const T*)g->rkA[c], 1.0, (T*)bi->u[c],
+                              g->stream)))
+      return rc;
+  }
+  if (!g->defer) FVIB_HIP(hipStreamSynchronize(g->stream));
   return FVIB_OK;
 }
 
@@ -1287,9 +1455,14 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
     return fail(nullptr, code, what);
   };
   g->max_iv = 1.0;
+  g->h_min = HUGE_VAL;
   for (int a = 0; a < g->dim; ++a) {
     double mx = 0.0;
-    for (int i = 0; i < g->n[a]; ++i) mx = std::max(mx, 1.0 / (g->faces[a][i + 1] - g->faces[a][i]));
+    for (int i = 0; i < g->n[a]; ++i) {
+      const double w = g->faces[a][i + 1] - g->faces[a][i];
+      mx = std::max(mx, 1.0 / w);
+      g->h_min = std::min(g->h_min, w);
+    }
     g->max_iv *= mx;
   }
   // the allocation-free loss finds its static scratch on this device
@@ -1509,6 +1682,15 @@ int fvib_ib_set_body(fvib_grid* h, const fvib_body_desc* body) {
   };
   f(g->ib_mem);
   f(g->origin);
+  for (int c = 0; c < 3; ++c) {
+    f(g->rkv[0][c]);
+    f(g->rkv[1][c]);
+    f(g->rku0[c]);
+    f(g->rkW[c]);
+    f(g->rkZ[c]);
+    f(g->rkA[c]);
+  }
+  f(g->rkp);
   g->ib_mem = nullptr;
   g->origin = nullptr;
   for (int c = 0; c < 2; ++c) {
@@ -1680,6 +1862,78 @@ int fvib_step_strong_adjoint(fvib_grid* h, const fvib_fields* fwd_in, const doub
   if (g->prec == FVIB_PREC_FP64)
     return strong_adjoint_impl<double>(g, fwd_in, omega, bar_out, dF, bar_in, info);
   return strong_adjoint_impl<float>(g, fwd_in, omega, bar_out, dF, bar_in, info);
+}
+
+int fvib_step_rk(fvib_grid* h, const fvib_fields* in, fvib_fields* out, int scheme,
+                 fvib_step_info* info) {
+  if (!h) return FVIB_EINVAL;
+  Grid* g = &h->g;
+  int rc;
+  const RkScheme* S = rk_scheme(scheme);
+  if (!S) return fail(g, FVIB_EINVAL, "unknown time scheme");
+  if (g->has_body) return fail(g, FVIB_ESTATE, "Runge-Kutta steps need a grid without a body");
+  if ((rc = check_fields(g, in, false)) || (rc = check_fields(g, out, false))) return rc;
+  if (!in->p || !out->p) return fail(g, FVIB_EINVAL, "pressure pointer is NULL");
+  if ((rc = sticky_check(g))) return rc;
+  if (S->stages > 1 && (rc = ensure_rk_buffers(g))) return rc;
+  if (g->prec == FVIB_PREC_FP64) return rk_impl<double>(g, in, out, S, info);
+  return rk_impl<float>(g, in, out, S, info);
+}
+
+int fvib_step_rk_adjoint(fvib_grid* h, const fvib_fields* fwd_in, const fvib_adjoint* bar_out,
+                         fvib_adjoint* bar_in, int scheme, fvib_step_info* info) {
+  if (!h) return FVIB_EINVAL;
+  Grid* g = &h->g;
+  const RkScheme* S = rk_scheme(scheme);
+  if (!S) return fail(g, FVIB_EINVAL, "unknown time scheme");
+  if (g->has_body) return fail(g, FVIB_ESTATE, "Runge-Kutta steps need a grid without a body");
+  if (!fwd_in || !bar_out || !bar_in) return fail(g, FVIB_EINVAL, "NULL argument");
+  for (int c = 0; c < g->dim; ++c) {
+    if (!fwd_in->u[c] || !bar_out->u[c] || !bar_in->u[c])
+      return fail(g, FVIB_EINVAL, "velocity or adjoint pointer is NULL");
+    if (bar_in->u[c] == bar_out->u[c]) return fail(g, FVIB_EINVAL, "bar_in may not alias bar_out");
+  }
+  int rc;
+  if ((rc = sticky_check(g))) return rc;
+  if ((rc = ensure_rk_buffers(g))) return rc;
+  if (g->prec == FVIB_PREC_FP64) return rk_adjoint_impl<double>(g, fwd_in, bar_out, bar_in, S, info);
+  return rk_adjoint_impl<float>(g, fwd_in, bar_out, bar_in, S, info);
+}
+
+int fvib_set_dt(fvib_grid* h, double dt) {
+  if (!h) return FVIB_EINVAL;
+  Grid* g = &h->g;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(g, FVIB_EINVAL, "dt must be positive and finite");
+  g->d.dt = dt;
+  g->G64.dt = dt;
+  g->G32.dt = (float)dt;
+  g->P64.dt_over_rho = dt / g->d.rho;
+  g->P32.dt_over_rho = dt / g->d.rho;
+  g->ib.dt = dt;
+  return FVIB_OK;
+}
+
+int fvib_cfl_dt(fvib_grid* h, const void* const u[3], double cfl, double dt_max, double* dt) {
+  if (!h || !u || !dt) return FVIB_EINVAL;
+  Grid* g = &h->g;
+  for (int c = 0; c < g->dim; ++c)
+    if (!u[c]) return fail(g, FVIB_EINVAL, "NULL velocity component");
+  if (!(cfl > 0.0) || !(dt_max > 0.0)) return fail(g, FVIB_EINVAL, "cfl and dt_max must be positive");
+  int rc;
+  if ((rc = reset_scalars(g))) return rc;
+  const int64_t n[3] = {g->nface[0], g->nface[1], g->dim == 3 ? g->nface[2] : 0};
+  if (g->prec == FVIB_PREC_FP64) {
+    const double* uu[3] = {(const double*)u[0], (const double*)u[1], g->dim == 3 ? (const double*)u[2] : nullptr};
+    rc = launch_cfl_dt<double>(n, uu, cfl, g->h_min, dt_max, g->red(), g->sc, g->stream);
+  } else {
+    const float* uu[3] = {(const float*)u[0], (const float*)u[1], g->dim == 3 ? (const float*)u[2] : nullptr};
+    rc = launch_cfl_dt<float>(n, uu, cfl, g->h_min, dt_max, g->red(), g->sc, g->stream);
+  }
+  if (rc) return rc;
+  if ((rc = read_scalars(g))) return rc;
+  if (g->sch->status == FVIB_ENONFINITE) return fail(g, FVIB_ENONFINITE, "non-finite velocity");
+  *dt = g->sch->cfl_dt;
+  return FVIB_OK;
 }
 
 int fvib_clear_error(fvib_grid* h) {

@@ -453,6 +453,7 @@ struct SolverScalars {
   double ymax;      // adjoint right-hand side: max |y / V|
   double tol_dev;   // stopping target set on the device (tol < 0 on the host)
   double xi;        // coupling error of the last structural sub-iteration
+  double cfl_dt;    // CFL-limited time step of the last launch_cfl_dt
   int done;         // current CG solve finished
   int outer_done;   // refinement finished
   int iters;        // iterations of the current CG solve

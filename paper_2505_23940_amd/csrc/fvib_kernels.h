@@ -26,6 +26,13 @@ struct IbGeo {
   double m, rho, dt;
 };
 
+// Runge-Kutta stage combination written by the velocity correction:
+// out = a u0 + b (corrected field) when u0[0] is not NULL.
+struct StageMix {
+  const void* u0[3];
+  double a, b;
+};
+
 // Fast-diagonalisation plan: per-axis eigenbases on the device.
 struct FdmDiv {
   int dim, axis;               // axis = last forward axis (dim - 1)
@@ -118,7 +125,8 @@ int launch_ir_correct(int64_t n, double* p, const float* d, const SolverScalars*
 template <typename T>
 int launch_project(const Geo<T>& G, const PGeo<double>& P, const T* const us[3], const double* p,
                    T* out[3], RedBuf red, SolverScalars* sc, hipStream_t s, double* pg = nullptr,
-                   fvib_step_info* info = nullptr, int* sticky = nullptr);
+                   fvib_step_info* info = nullptr, int* sticky = nullptr,
+                   const StageMix* mix = nullptr);
 int launch_apply_A(const PGeo<double>& P, const double* x, double* y, hipStream_t s);
 // 3D without a body, fast diagonalisation: the PPE right-hand side b and the
 // first refinement residual r = b - A x (r64 for the double inner solve, else
@@ -130,6 +138,13 @@ int launch_rhs_residual(const Geo<T>& G, const PGeo<double>& P, const T* const u
                         SolverScalars* mirror);
 // y = a x over n doubles (y may alias x)
 int launch_scale(int64_t n, double a, const double* x, double* y, hipStream_t s);
+// y = a x + b y over n values (x NULL: y = b y)
+template <typename T>
+int launch_axpby(int64_t n, double a, const T* x, double b, T* y, hipStream_t s);
+// CFL step min(dt_max, cfl h_min / max |u|) into sc->cfl_dt (n: face counts)
+template <typename T>
+int launch_cfl_dt(const int64_t n[3], const T* const u[3], double cfl, double h_min,
+                  double dt_max, RedBuf red, SolverScalars* sc, hipStream_t s);
 
 // k_ib.hip
 template <typename T>

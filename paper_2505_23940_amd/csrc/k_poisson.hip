@@ -559,15 +559,19 @@ k_ir_correct(int64_t n, double* __restrict__ p, const float* __restrict__ d,
 // low faces of its cell and, on the last cell of a bounded axis, the high
 // boundary face.  The divergence of the corrected field is evaluated in
 // double before rounding to the storage type and its maximum recorded.
-template <typename T, int DIM>
+template <typename T, int DIM, bool MIX>
 __global__ void __launch_bounds__(kBlock)
 k_project(Geo<T> G, PGeo<double> P, Tiling tl, const T* __restrict__ s0,
           const T* __restrict__ s1, const T* __restrict__ s2, const double* __restrict__ p,
-          T* __restrict__ o0, T* __restrict__ o1, T* __restrict__ o2, RedBuf red,
-          SolverScalars* sc) {
+          T* o0, T* o1, T* o2, RedBuf red, SolverScalars* sc, StageMix mix) {
   const int nx_ = G.n[0], ny_ = G.n[1];
   const T* us[3] = {s0, s1, s2};
   T* out[3] = {o0, o1, o2};
+  const T* u0[3] = {(const T*)mix.u0[0], (const T*)mix.u0[1], (const T*)mix.u0[2]};
+  // stage output: a u0 + b (corrected field), or the corrected field
+  auto put = [&](int c, int64_t id, double v) {
+    out[c][id] = MIX ? (T)(mix.a * (double)u0[c][id] + mix.b * v) : (T)v;
+  };
   const double f = P.dt_over_rho;
   double mx = 0.0;
   FVIB_TILE_LOOP(tl)
@@ -605,8 +609,8 @@ k_project(Geo<T> G, PGeo<double> P, Tiling tl, const T* __restrict__ s0,
       // faces of a bounded boundary have kf = 0 and keep u*
       const double lo = ulo[c] - f * (pc - plo[c]) * klo[c];
       const double hi = uhi[c] - f * (phi[c] - pc) * khi[c];
-      out[c][lo_id[c]] = (T)lo;
-      if (!G.per[c] && ic + 1 == nc) out[c][hi_id[c]] = (T)hi;
+      put(c, lo_id[c], lo);
+      if (!G.per[c] && ic + 1 == nc) put(c, hi_id[c], hi);
       div += (hi - lo) * A;
     }
     mx = fmax(mx, fabs(div) * ivol);
@@ -622,13 +626,21 @@ k_project(Geo<T> G, PGeo<double> P, Tiling tl, const T* __restrict__ s0,
 // are shared with the adjacent columns through the caches.  Same arithmetic
 // and term order as k_project.  pg (nullable, not p): receives p minus its
 // mean (the gradient does not see that constant).
-template <typename T>
+template <typename T, bool MIX>
 __global__ void __launch_bounds__(kBlock)
 k_project_col(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__ s0,
               const T* __restrict__ s1, const T* __restrict__ s2, const double* __restrict__ p,
-              T* __restrict__ o0, T* __restrict__ o1, T* __restrict__ o2, RedBuf red,
-              double* __restrict__ pg, const SolverScalars* sc) {
+              T* o0, T* o1, T* o2, RedBuf red, double* __restrict__ pg, const SolverScalars* sc,
+              StageMix mix) {
   const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
+  const T* m0 = (const T*)mix.u0[0];
+  const T* m1 = (const T*)mix.u0[1];
+  const T* m2 = (const T*)mix.u0[2];
+  // stage output: a u0 + b (corrected field), or the corrected field (each
+  // element of u0 is read by the thread that writes it, before the write)
+  auto put = [&](T* o, const T* m, int64_t id, double v) {
+    __builtin_nontemporal_store(MIX ? (T)(mix.a * (double)m[id] + mix.b * v) : (T)v, &o[id]);
+  };
   const int64_t sxy = (int64_t)nx * ny;
   const double f = P.dt_over_rho;
   // gauge constant of the pressure copy (the mean of p, from the sum the
@@ -682,12 +694,12 @@ k_project_col(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__ s0,
       const double lz = wlo - f * (pc - pm) * kzl, hz = whi - f * (pp - pc) * kzh;
       // streaming stores: the next reader is the following step
       if (pg) __builtin_nontemporal_store(pc - mean, &pg[pk + cC]);
-      __builtin_nontemporal_store((T)lx_, &o0[(int64_t)k * su + uL]);
-      if (xlast) __builtin_nontemporal_store((T)hx, &o0[(int64_t)k * su + uH]);
-      __builtin_nontemporal_store((T)ly_, &o1[(int64_t)k * sv + vL]);
-      if (ylast) __builtin_nontemporal_store((T)hy, &o1[(int64_t)k * sv + vH]);
-      __builtin_nontemporal_store((T)lz, &o2[(int64_t)k * sw + wL]);
-      if (!G.per[2] && k + 1 == nz) __builtin_nontemporal_store((T)hz, &o2[(int64_t)kH * sw + wL]);
+      put(o0, m0, (int64_t)k * su + uL, lx_);
+      if (xlast) put(o0, m0, (int64_t)k * su + uH, hx);
+      put(o1, m1, (int64_t)k * sv + vL, ly_);
+      if (ylast) put(o1, m1, (int64_t)k * sv + vH, hy);
+      put(o2, m2, (int64_t)k * sw + wL, lz);
+      if (!G.per[2] && k + 1 == nz) put(o2, m2, (int64_t)kH * sw + wL, hz);
       double div = 0.0;
       div += (hx - lx_) * (dy * dz);
       div += (hy - ly_) * (dx * dz);
@@ -835,16 +847,27 @@ int launch_ir_correct(int64_t n, double* p, const float* d, const SolverScalars*
 template <typename T>
 int launch_project(const Geo<T>& G, const PGeo<double>& P, const T* const us[3], const double* p,
                    T* out[3], RedBuf red, SolverScalars* sc, hipStream_t s, double* pg,
-                   fvib_step_info* info, int* sticky) {
+                   fvib_step_info* info, int* sticky, const StageMix* mix) {
   const Tiling tl = red_tiling(G.n);
   if (pg && (G.dim != 3 || pg == p)) return FVIB_EINVAL;
-  if (G.dim == 2)
-    launch_kernel((k_project<T, 2>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl, us[0],
-                       us[1], us[2], p, out[0], out[1], out[2], red, sc);
-  else {
+  StageMix m{};
+  const bool mx = mix && mix->u0[0];
+  if (mx) m = *mix;
+  if (G.dim == 2) {
+    if (mx)
+      launch_kernel((k_project<T, 2, true>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl,
+                    us[0], us[1], us[2], p, out[0], out[1], out[2], red, sc, m);
+    else
+      launch_kernel((k_project<T, 2, false>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl,
+                    us[0], us[1], us[2], p, out[0], out[1], out[2], red, sc, m);
+  } else {
     const ColTiling ct = make_col_tiling(G.n[0], G.n[1], G.n[2]);
-    launch_kernel((k_project_col<T>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct, us[0],
-                  us[1], us[2], p, out[0], out[1], out[2], red, pg, sc);
+    if (mx)
+      launch_kernel((k_project_col<T, true>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct,
+                    us[0], us[1], us[2], p, out[0], out[1], out[2], red, pg, sc, m);
+    else
+      launch_kernel((k_project_col<T, false>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct,
+                    us[0], us[1], us[2], p, out[0], out[1], out[2], red, pg, sc, m);
     FVIB_HIP(hipGetLastError());
     FVIB_HIP((launch_finish<1, 0>(red.partial, ct.nblocks, sc, FinDivMax{info, sticky}, s)));
     return FVIB_OK;
@@ -860,6 +883,69 @@ k_scale(int64_t n, double a, const double* __restrict__ x, double* __restrict__ 
        t += (int64_t)gridDim.x * kBlock)
     y[t] = a * x[t];
 }
+
+// y = a x + b y over n values of type T (x may be NULL: y = b y; b = 0 does
+// not read y)
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_axpby(int64_t n, double a, const T* __restrict__ x, double b, T* __restrict__ y) {
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * kBlock)
+    y[t] = (T)((x ? a * (double)x[t] : 0.0) + (b != 0.0 ? b * (double)y[t] : 0.0));
+}
+
+template <typename T>
+int launch_axpby(int64_t n, double a, const T* x, double b, T* y, hipStream_t s) {
+  const int64_t nb = std::min<int64_t>((n + kBlock - 1) / kBlock, 8 * kMaxRedBlocks);
+  launch_kernel((k_axpby<T>), dim3((int)nb), dim3(kBlock), 0, s, n, a, x, b, y);
+  FVIB_HIP(hipGetLastError());
+  return FVIB_OK;
+}
+
+// max over every face value of every component of |u|, then the CFL step
+// dt = min(dt_max, cfl h_min / max |u|) into sc->cfl_dt
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_max_speed(int64_t n0, const T* __restrict__ u0, int64_t n1, const T* __restrict__ u1,
+            int64_t n2, const T* __restrict__ u2, RedBuf red) {
+  double m = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  const int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  for (int64_t t = t0; t < n0; t += stride) m = fmax(m, fabs((double)u0[t]));
+  for (int64_t t = t0; t < n1; t += stride) m = fmax(m, fabs((double)u1[t]));
+  if (u2)
+    for (int64_t t = t0; t < n2; t += stride) m = fmax(m, fabs((double)u2[t]));
+  double v[1] = {m};
+  block_partials<1, 0>(v, red.partial);
+}
+
+struct FinCflDt {
+  double cfl, h_min, dt_max;
+  __device__ bool skip(const SolverScalars*) const { return false; }
+  __device__ void apply(const double* t, SolverScalars* sc) const {
+    const double um = t[0];
+    sc->cfl_dt = (um > 0.0) ? fmin(dt_max, cfl * h_min / um) : dt_max;
+    if (!(um == um)) sc->status = FVIB_ENONFINITE;
+  }
+};
+
+template <typename T>
+int launch_cfl_dt(const int64_t n[3], const T* const u[3], double cfl, double h_min,
+                  double dt_max, RedBuf red, SolverScalars* sc, hipStream_t s) {
+  const int nb = (int)std::min<int64_t>((n[0] + kBlock - 1) / kBlock, kMaxRedBlocks);
+  launch_kernel((k_max_speed<T>), dim3(nb), dim3(kBlock), 0, s, n[0], u[0], n[1], u[1], n[2],
+                u[2], red);
+  FVIB_HIP(hipGetLastError());
+  FVIB_HIP((launch_finish<1, 0>(red.partial, nb, sc, FinCflDt{cfl, h_min, dt_max}, s)));
+  return FVIB_OK;
+}
+
+template int launch_axpby<float>(int64_t, double, const float*, double, float*, hipStream_t);
+template int launch_axpby<double>(int64_t, double, const double*, double, double*, hipStream_t);
+template int launch_cfl_dt<float>(const int64_t[3], const float* const[3], double, double, double,
+                                  RedBuf, SolverScalars*, hipStream_t);
+template int launch_cfl_dt<double>(const int64_t[3], const double* const[3], double, double,
+                                   double, RedBuf, SolverScalars*, hipStream_t);
 
 int launch_scale(int64_t n, double a, const double* x, double* y, hipStream_t s) {
   const int64_t nb = std::min<int64_t>((n + kBlock - 1) / kBlock, 8 * kMaxRedBlocks);
@@ -897,10 +983,11 @@ template int launch_cg_iter<double>(const PGeo<double>&, int, const double*, con
                                     int, hipStream_t, hipEvent_t*);
 template int launch_project<float>(const Geo<float>&, const PGeo<double>&, const float* const[3],
                                    const double*, float* [3], RedBuf, SolverScalars*,
-                                   hipStream_t, double*, fvib_step_info*, int*);
+                                   hipStream_t, double*, fvib_step_info*, int*,
+                                   const StageMix*);
 template int launch_project<double>(const Geo<double>&, const PGeo<double>&,
                                     const double* const[3], const double*, double* [3], RedBuf,
                                     SolverScalars*, hipStream_t, double*, fvib_step_info*,
-                                    int*);
+                                    int*, const StageMix*);
 
 }  // namespace fvib

@@ -33,7 +33,7 @@ def _slots_like(x, n):
 
 
 def _forward_steps(grid, nsteps, ckpt_every, u, p, body, fbd, kcd, info, ckpts, coupling=None,
-                   omegas=None):
+                   omegas=None, scheme=None, cfl=None, dts=None):
     # The state entering a segment is kept as is; the segment's first step
     # writes its result into a fresh slot and the segment continues there in
     # place.  The slots of all segments but the last come from one
@@ -44,6 +44,10 @@ def _forward_steps(grid, nsteps, ckpt_every, u, p, body, fbd, kcd, info, ckpts, 
         Us = [_slots_like(x, nseg - 1) for x in u]
         Ps, Bs = _slots_like(p, nseg - 1), _slots_like(body, nseg - 1)
     for n in range(nsteps):
+        if cfl is not None:
+            # CFL-adaptive step from the state entering step n
+            dts[n] = grid.cfl_dt(u, cfl[0], cfl[1])
+            grid.set_dt(dts[n])
         if n % ckpt_every == 0:
             ckpts[n] = (u, p, body)
             s = n // ckpt_every
@@ -53,17 +57,19 @@ def _forward_steps(grid, nsteps, ckpt_every, u, p, body, fbd, kcd, info, ckpts, 
                 u2 = [torch.empty_like(x) for x in u]
                 p2, b2 = torch.empty_like(p), torch.empty_like(body)
             grid.step(u, p, fbd, body, kcd, u_out=u2, p_out=p2, body_out=b2, info=info[n],
-                      coupling=coupling, omega=None if omegas is None else omegas[n])
+                      coupling=coupling, omega=None if omegas is None else omegas[n],
+                      scheme=scheme)
             u, p, body = u2, p2, b2
         else:
             grid.step(u, p, fbd, body, kcd, info=info[n], coupling=coupling,
-                      omega=None if omegas is None else omegas[n])
+                      omega=None if omegas is None else omegas[n], scheme=scheme)
     ckpts["final"] = (u, p, body)
 
 
 class _Rollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, grid: Grid, nsteps: int, ckpt_every: int, coupling, nd: int, *tensors):
+    def forward(ctx, grid: Grid, nsteps: int, ckpt_every: int, coupling, scheme, cfl, nd: int,
+                *tensors):
         u0 = list(tensors[:nd])
         fb = list(tensors[nd:2 * nd])
         kc, body0 = tensors[2 * nd], tensors[2 * nd + 1]
@@ -80,13 +86,18 @@ class _Rollout(torch.autograd.Function):
         omegas = None
         if coupling is not None:
             omegas = torch.zeros((nsteps, 6), dtype=torch.float64, device=dev)
+        # CFL-adaptive steps keep the step size of every step (not differentiated)
+        dt0 = grid.dt
+        dts = [dt0] * nsteps
         # steps are enqueued back to back; their statuses are checked once
         grid.defer_status(True)
         try:
             _forward_steps(grid, nsteps, ckpt_every, u, p, body, fbd, kcd, info, ckpts, coupling,
-                           omegas)
+                           omegas, scheme, cfl, dts)
         finally:
             grid.defer_status(False)
+            if cfl is not None:
+                grid.set_dt(dt0)
         u, p, body = ckpts.pop("final")
         grid.check_infos(info, "forward step")
         ctx.grid = grid
@@ -96,6 +107,9 @@ class _Rollout(torch.autograd.Function):
         ctx.ckpts = ckpts
         ctx.coupling = coupling
         ctx.omegas = omegas
+        ctx.scheme = scheme
+        ctx.dts = dts if cfl is not None else None
+        ctx.dt0 = dt0
         ctx.save_for_backward(*fbd, kcd)
         Fh = info[:, 4:7].clone()
         ctx.mark_non_differentiable(p)
@@ -130,6 +144,12 @@ class _Rollout(torch.autograd.Function):
         # statuses are checked once at the end
         infos = torch.zeros((2, S, INFO_DOUBLES), dtype=torch.float64, device=grid.device)
         infos_f, infos_a = infos[0], infos[1]
+        dts = ctx.dts
+
+        def use_dt(n):
+            if dts is not None:
+                grid.set_dt(dts[n])
+
         grid.defer_status(True)
         try:
             for s0 in reversed(starts):
@@ -146,38 +166,51 @@ class _Rollout(torch.autograd.Function):
                         q = n - s0
                         u2 = [X[q] for X in RU]
                         b2 = RB[q]
+                        use_dt(n)
                         grid.step(u, p, fb, body, kc, u_out=u2, p_out=p, body_out=b2,
-                                  info=infos_f[n], coupling=ctx.coupling)
+                                  info=infos_f[n], coupling=ctx.coupling, scheme=ctx.scheme)
                         u, body = u2, b2
                         states.append((u, body))
                 for n in reversed(range(s0, s1)):
                     un, bn = states[n - s0]
                     dF = gF[n].contiguous()
+                    use_dt(n)
                     grid.step_adjoint(un, fb, bn, kc, ubar, bbar, dF, ubar_tmp, bbar_tmp,
                                       fbbar=fbbar, kcbar=kcbar, info=infos_a[n], mu=mu,
-                                      omega=None if ctx.omegas is None else ctx.omegas[n])
+                                      omega=None if ctx.omegas is None else ctx.omegas[n],
+                                      scheme=ctx.scheme,
+                                      p=(cp if n == s0 else RP) if ctx.scheme else None)
                     ubar, ubar_tmp = ubar_tmp, ubar
                     bbar, bbar_tmp = bbar_tmp, bbar
         finally:
             grid.defer_status(False)
+            if dts is not None:
+                grid.set_dt(ctx.dt0)
         host = infos.cpu()             # one read of both sets of records
         grid.check_infos(host[0], "recomputed step")
         grid.check_infos(host[1], "adjoint step")
-        return (None, None, None, None, None, *ubar, *fbbar, kcbar, bbar)
+        return (None, None, None, None, None, None, None, *ubar, *fbbar, kcbar, bbar)
 
 
 def rollout(grid: Grid, u0: List[torch.Tensor], fb: Optional[List[torch.Tensor]], kc: torch.Tensor,
-            body0: torch.Tensor, nsteps: int, ckpt_every: int = 1, coupling=None):
+            body0: torch.Tensor, nsteps: int, ckpt_every: int = 1, coupling=None,
+            scheme: Optional[str] = None, cfl=None):
     """Differentiable rollout; returns (u_final list, body_final, F history (S, 3), p_final).
     coupling = (max_iters, tol) runs strongly coupled steps (Alg. 1 with
-    N = max_iters), differentiated through their coupling fixed points."""
+    N = max_iters), differentiated through their coupling fixed points.
+    scheme ("fe", "rk2", "rk3") runs explicit Runge-Kutta steps; cfl =
+    (cfl, dt_max) takes each step's size from the CFL rule at the state
+    entering it (the sizes are recorded and replayed by the backward pass;
+    they are not differentiated)."""
     if fb is None:
         fb = grid.zeros_u()
     nd = grid.dim
     if coupling is not None:
         coupling = (int(coupling[0]), float(coupling[1]))
-    outs = _Rollout.apply(grid, int(nsteps), int(max(1, ckpt_every)), coupling, nd, *u0, *fb, kc,
-                          body0)
+    if cfl is not None:
+        cfl = (float(cfl[0]), float(cfl[1]))
+    outs = _Rollout.apply(grid, int(nsteps), int(max(1, ckpt_every)), coupling, scheme, cfl, nd,
+                          *u0, *fb, kc, body0)
     return list(outs[:nd]), outs[nd], outs[nd + 1], outs[nd + 2]
 
 
