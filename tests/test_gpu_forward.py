@@ -154,9 +154,21 @@ def test_tgv2d_fp64_100_steps(solver):
     w = W.tgv2d()
     gr = gpu_rollout(w, w.steps, "fp64", tol=1e-13, solver=solver)
     orc = oracle_rollout(w, w.steps)
-    assert rel_l2(gr["u"], orc["u"]) <= 1e-10
-    assert rel_l2([gauge(gr["p"])], [orc["p"]]) <= 1e-10
-    assert max(i["div_max"] for i in gr["infos"]) <= 1e-12
+    eu = rel_l2(gr["u"], orc["u"])
+    ep = rel_l2([gauge(gr["p"])], [orc["p"]])
+    dm = max(i["div_max"] for i in gr["infos"])
+    # error against the analytic decay at t = 0.1 (the discretisation error,
+    # which the GPU shares with the oracle)
+    t = w.steps * w.dt
+    x, y = W.face_points(w, 0)[:2]
+    ua = np.sin(x) * np.cos(y) * np.exp(-2 * w.nu * t)
+    ea = float(np.abs(gr["u"][0] - ua).max())
+    print(f"TGV 64^2 {solver}, 100 steps float64: u rel L2 vs oracle {eu:.2e}, p {ep:.2e}, "
+          f"max div {dm:.2e}; max |u - analytic| {ea:.2e}")
+    assert eu <= 1e-10
+    assert ep <= 1e-10
+    assert dm <= 1e-12
+    assert ea <= 5e-3
 
 
 @pytest.mark.parametrize("name", ["tgv3d", "channel", "cylinder", "viv"])
