@@ -73,6 +73,8 @@ class Workload:
     conv: str = "central"          # "central" or "upwind"
     precision: str = "fp64"        # "fp64" or "fp32"
     body: Optional[Body] = None
+    # static immersed box (3D grids): ((x0, y0, z0), (x1, y1, z1)), or None
+    box: Optional[tuple] = None
     meta: dict = field(default_factory=dict)
 
     @property

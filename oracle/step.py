@@ -26,7 +26,7 @@ import numpy as np
 import torch
 
 from . import body as bodymod
-from . import fluid, ibm
+from . import fluid, ibm, ibm3d
 from .grid import Grid, F64
 from .poisson import solver
 
@@ -70,7 +70,15 @@ def step(g: Grid, state: dict, params: dict, masks=None):
     """Advance (u, p, body) by one step; returns (new_state, aux)."""
     u, bs = state["u"], state["body"]
     bd = g.w.body
-    if bd is not None:
+    bx = getattr(g.w, "box", None)
+    if bd is None and bx is not None:
+        # static box on a 3D grid (ibm3d): targets and solid velocity zero
+        if masks is None:
+            masks = ibm3d.classify_box(g, bx[0], bx[1])
+        eps = masks[2]
+        us = [torch.zeros(g.face_shape(c), dtype=F64) for c in range(g.dim)]
+        uc = us
+    elif bd is not None:
         Xk, U, dV = body_geometry(g, bs)
         if masks is None:
             masks = ibm.classify(g, Xk.detach().numpy())
@@ -91,6 +99,9 @@ def step(g: Grid, state: dict, params: dict, masks=None):
                                      params["c"], g.dt)
         else:
             bs_new = bs
+    elif bx is not None:
+        F = ibm3d.box_force(g, eps, f)
+        bs_new = bs
     else:
         F = torch.zeros(3, dtype=F64)
         bs_new = bs
