@@ -39,7 +39,7 @@ SCHEMES = {
 
 def step_rk(g: Grid, state: dict, params: dict, scheme: str = "rk3"):
     """One Runge-Kutta step; returns (new_state, aux of the last stage)."""
-    if g.w.body is not None:
+    if g.w.body is not None or getattr(g.w, "box", None) is not None:
         raise ValueError("Runge-Kutta steps are defined for grids without an immersed body")
     u0 = state["u"]
     v, p = u0, state["p"]

@@ -213,6 +213,7 @@ class Grid:
         self.layouts = [fvib_field_layout(self.h, c) for c in range(self.dim)]
         self.pshape = fvib_field_layout(self.h, 3)[0]
         self.has_body = False
+        self.has_box = False
         self._info = torch.zeros(INFO_DOUBLES, dtype=torch.float64, device=self.device)
 
     @classmethod
@@ -226,6 +227,8 @@ class Grid:
         if w.body is not None:
             b = w.body
             g.set_body(b.kind, b.X0, b.ds, b.free_dof, b.m)
+        if getattr(w, "box", None) is not None:
+            g.set_box(w.box[0], w.box[1])
         return g
 
     def close(self):
@@ -292,6 +295,18 @@ class Grid:
                              f"{self.device}")
 
     # ------------------------------------------------------------ body
+    def set_box(self, lo, hi) -> None:
+        """Static immersed box (3D grids): half-open [lo, hi) per axis
+        (fvib_ib_set_box); lo = None removes it."""
+        if lo is None:
+            _check(lib().fvib_ib_set_box(self.h, None, None), self.h)
+            self.has_box = False
+            return
+        lo_a = (C.c_double * 3)(*[float(x) for x in lo])
+        hi_a = (C.c_double * 3)(*[float(x) for x in hi])
+        _check(lib().fvib_ib_set_box(self.h, lo_a, hi_a), self.h)
+        self.has_box = True
+
     def set_body(self, kind: str, X0, ds, free_dof=(0, 0, 0), m: float = 1.0):
         X0 = np.ascontiguousarray(np.asarray(X0, dtype=np.float64))
         ds = np.ascontiguousarray(np.asarray(ds, dtype=np.float64))

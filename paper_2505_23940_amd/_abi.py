@@ -24,7 +24,7 @@ DTYPE_F32, DTYPE_F64 = 0, 1
 EXPORTS = (
     "fvib_create_grid", "fvib_destroy_grid", "fvib_field_layout", "fvib_ib_set_body",
     "fvib_step", "fvib_step_adjoint", "fvib_step_strong", "fvib_step_strong_adjoint",
-    "fvib_step_rk", "fvib_step_rk_adjoint", "fvib_set_dt", "fvib_cfl_dt",
+    "fvib_step_rk", "fvib_step_rk_adjoint", "fvib_set_dt", "fvib_cfl_dt", "fvib_ib_set_box",
     "fvib_loss_wall_shear", "fvib_loss_wall_shear_noalloc",
     "fvib_loss_rms_lift",
     "fvib_last_error", "fvib_test_momentum", "fvib_test_ppe_rhs", "fvib_test_poisson",
@@ -117,6 +117,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.fvib_step_rk_adjoint.argtypes = [vp, C.POINTER(Fields), C.POINTER(Adjoint),
                                          C.POINTER(Adjoint), C.c_int, vp]
     lib.fvib_set_dt.argtypes = [vp, C.c_double]
+    lib.fvib_ib_set_box.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.fvib_cfl_dt.argtypes = [vp, vp * 3, C.c_double, C.c_double, C.POINTER(C.c_double)]
     lib.fvib_step_strong.argtypes = [vp, C.POINTER(Fields), C.POINTER(Fields), C.c_int32,
                                      C.c_double, vp, vp]

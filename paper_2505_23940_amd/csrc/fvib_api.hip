@@ -164,6 +164,10 @@ struct Grid {
   int last_iters = 0;
   int last_iters_adj = 0;
   bool defer = false;        // steps return once enqueued (fvib_defer_status)
+  // static box (3D)
+  bool has_box = false;
+  BoxGeo box;
+  void* bf[3] = {nullptr, nullptr, nullptr};
   // immersed body
   bool has_body = false;
   IbGeo ib;
@@ -238,6 +242,10 @@ static void release(Grid* g) {
     f(g->rkA[c]);
   }
   f(g->rkp);
+  for (int c = 0; c < 3; ++c) {
+    f(g->box.cls[c]);
+    f(g->bf[c]);
+  }
   for (int c = 0; c < 2; ++c) {
     f(g->cls[c]);
     f(g->us[c]);
@@ -787,6 +795,19 @@ template <typename T>
 static IbView<T> ib_view(Grid* g, const double* body) {
   IbView<T> v;
   memset(&v, 0, sizeof(v));
+  if (g->has_box) {
+    v.active = 1;
+    v.box = 1;
+    for (int c = 0; c < 3; ++c) {
+      for (int a = 0; a < 3; ++a) {
+        v.bo[c][a] = g->box.bo[c][a];
+        v.bw[c][a] = g->box.bw[c][a];
+      }
+      v.bcls[c] = g->box.cls[c];
+      v.bf[c] = (T*)g->bf[c];
+    }
+    return v;
+  }
   v.active = g->has_body ? 1 : 0;
   if (!g->has_body) return v;
   for (int c = 0; c < 2; ++c) {
@@ -953,7 +974,7 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
   // Without a body the scalars are final once the projection has run, so
   // with fast diagonalisation its epilogue also writes the step record
   // (sweeps as counted on the device).
-  const bool rec = fdm && !g->has_body;
+  const bool rec = fdm && !g->has_body && !g->has_box;
   // the projection is queued behind each convergence check of the solve
   const std::function<int()> project = [&]() {
     return timed(g, FVIB_K_PROJECT, [&] {
@@ -982,6 +1003,9 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
       return launch_loads_body<T>(g->ib, ib, in->body, in->body, out->body, in->kc, nullptr, 0,
                                   g->sc, g->stream);
     });
+    if (rc) return rc;
+  } else if (g->has_box) {
+    rc = timed(g, FVIB_K_IB, [&] { return launch_box_force<T>(g->G64, ib, g->d.rho, g->sc, g->stream); });
     if (rc) return rc;
   }
   // (a status the host set after the last projection still needs the copy)
@@ -1091,6 +1115,11 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
     rc = timed(g, FVIB_K_IB, [&] {
       return launch_adj_ubody<T>(G, g->P64, g->ib, ub1, mu, ib, bi->body, g->sc, g->stream);
     });
+    if (rc) return rc;
+  }
+  if (g->has_box) {
+    // forcing adjoint of the box's loads for the force adjoint dF
+    rc = timed(g, FVIB_K_IB, [&] { return launch_box_fbar<T>(g->G64, ib, g->d.rho, dF, g->stream); });
     if (rc) return rc;
   }
   if ((rc = timed(g, FVIB_K_ADJOINT, [&] {
@@ -1682,15 +1711,6 @@ int fvib_ib_set_body(fvib_grid* h, const fvib_body_desc* body) {
   };
   f(g->ib_mem);
   f(g->origin);
-  for (int c = 0; c < 3; ++c) {
-    f(g->rkv[0][c]);
-    f(g->rkv[1][c]);
-    f(g->rku0[c]);
-    f(g->rkW[c]);
-    f(g->rkZ[c]);
-    f(g->rkA[c]);
-  }
-  f(g->rkp);
   g->ib_mem = nullptr;
   g->origin = nullptr;
   for (int c = 0; c < 2; ++c) {
@@ -1703,6 +1723,7 @@ int fvib_ib_set_body(fvib_grid* h, const fvib_body_desc* body) {
   }
   g->has_body = false;
   if (!body) return FVIB_OK;
+  if (g->has_box) return fail(g, FVIB_ESTATE, "the grid already has a static box");
   if (g->dim != 2) return fail(g, FVIB_EINVAL, "immersed bodies are supported on 2D grids");
   if (body->n_markers < 3 || !body->X0 || !body->ds)
     return fail(g, FVIB_EINVAL, "body needs at least 3 markers with positions and ds");
@@ -1864,6 +1885,65 @@ int fvib_step_strong_adjoint(fvib_grid* h, const fvib_fields* fwd_in, const doub
   return strong_adjoint_impl<float>(g, fwd_in, omega, bar_out, dF, bar_in, info);
 }
 
+int fvib_ib_set_box(fvib_grid* h, const double* lo, const double* hi) {
+  if (!h) return FVIB_EINVAL;
+  Grid* g = &h->g;
+  (void)hipStreamSynchronize(g->stream);
+  for (int c = 0; c < 3; ++c) {
+    if (g->box.cls[c]) (void)hipFree(g->box.cls[c]);
+    if (g->bf[c]) (void)hipFree(g->bf[c]);
+    g->box.cls[c] = nullptr;
+    g->bf[c] = nullptr;
+  }
+  g->has_box = false;
+  if (!lo) return FVIB_OK;
+  if (!hi) return fail(g, FVIB_EINVAL, "hi is NULL");
+  if (g->dim != 3) return fail(g, FVIB_EINVAL, "static boxes are defined on 3D grids");
+  if (g->has_body) return fail(g, FVIB_ESTATE, "the grid already has an immersed body");
+  for (int a = 0; a < 3; ++a)
+    if (!(lo[a] < hi[a])) return fail(g, FVIB_EINVAL, "the box needs lo < hi on every axis");
+  BoxGeo& B = g->box;
+  bool any = true;
+  for (int c = 0; c < 3; ++c) {
+    for (int a = 0; a < 3; ++a) {
+      // point coordinates of component c along axis a: faces along its own
+      // axis, cell centres across
+      const std::vector<double>& f = g->faces[a];
+      const int ext = g->ext[c][a];
+      auto coord = [&](int i) { return a == c ? f[i] : 0.5 * (f[i] + f[i + 1]); };
+      int s0 = ext, s1 = 0;
+      for (int i = 0; i < ext; ++i)
+        if (coord(i) >= lo[a] && coord(i) < hi[a]) {
+          s0 = std::min(s0, i);
+          s1 = std::max(s1, i + 1);
+        }
+      if (s0 >= s1) any = false;
+      B.bs[c][a][0] = s0;
+      B.bs[c][a][1] = s1;
+      if (!g->per[a] && (s0 < 2 || s1 > ext - 2))
+        return fail(g, FVIB_EINVAL, "the box must stay two faces away from a bounded boundary");
+      if (g->per[a] && s0 < s1 && (s0 == 0) != (s1 == ext))
+        return fail(g, FVIB_EINVAL, "a box on the periodic seam must span the periodic axis");
+      const int o = std::max(0, s0 - 1), e = std::min(ext, s1 + 1);
+      B.bo[c][a] = o;
+      B.bw[c][a] = std::max(0, e - o);
+    }
+  }
+  if (!any) return fail(g, FVIB_EINVAL, "the box contains no face point of some component");
+  const size_t es = g->esize();
+  for (int c = 0; c < 3; ++c) {
+    const size_t n = (size_t)B.bw[c][0] * B.bw[c][1] * B.bw[c][2];
+    if (dmalloc(&B.cls[c], n) || dmalloc(&g->bf[c], n * es))
+      return fail(g, FVIB_ENOMEM, "device allocation for the box failed");
+    FVIB_HIP(hipMemsetAsync(g->bf[c], 0, n * es, g->stream));
+  }
+  int rc;
+  if ((rc = launch_box_classify(B, g->stream))) return rc;
+  FVIB_HIP(hipStreamSynchronize(g->stream));
+  g->has_box = true;
+  return FVIB_OK;
+}
+
 int fvib_step_rk(fvib_grid* h, const fvib_fields* in, fvib_fields* out, int scheme,
                  fvib_step_info* info) {
   if (!h) return FVIB_EINVAL;
@@ -1871,7 +1951,8 @@ int fvib_step_rk(fvib_grid* h, const fvib_fields* in, fvib_fields* out, int sche
   int rc;
   const RkScheme* S = rk_scheme(scheme);
   if (!S) return fail(g, FVIB_EINVAL, "unknown time scheme");
-  if (g->has_body) return fail(g, FVIB_ESTATE, "Runge-Kutta steps need a grid without a body");
+  if (g->has_body || g->has_box)
+    return fail(g, FVIB_ESTATE, "Runge-Kutta steps need a grid without an immersed body");
   if ((rc = check_fields(g, in, false)) || (rc = check_fields(g, out, false))) return rc;
   if (!in->p || !out->p) return fail(g, FVIB_EINVAL, "pressure pointer is NULL");
   if ((rc = sticky_check(g))) return rc;
@@ -1886,7 +1967,8 @@ int fvib_step_rk_adjoint(fvib_grid* h, const fvib_fields* fwd_in, const fvib_adj
   Grid* g = &h->g;
   const RkScheme* S = rk_scheme(scheme);
   if (!S) return fail(g, FVIB_EINVAL, "unknown time scheme");
-  if (g->has_body) return fail(g, FVIB_ESTATE, "Runge-Kutta steps need a grid without a body");
+  if (g->has_body || g->has_box)
+    return fail(g, FVIB_ESTATE, "Runge-Kutta steps need a grid without an immersed body");
   if (!fwd_in || !bar_out || !bar_in) return fail(g, FVIB_EINVAL, "NULL argument");
   for (int c = 0; c < g->dim; ++c) {
     if (!fwd_in->u[c] || !bar_out->u[c] || !bar_in->u[c])

@@ -87,7 +87,26 @@ struct IbView {
   const T *us[2];               // target velocity on forced faces
   T *f[2];                      // direct forcing written by the predictor
   const double *body;           // body state [d(3), v(3)]
+  // static box on a 3D grid (box != 0): per component a fixed window of
+  // faces around the box with a forced flag per face; the predictor writes
+  // the forcing there, the adjoint reads the forcing adjoint from it
+  int box;
+  int bo[3][3];                 // bo[c][a]: first face index of the window
+  int bw[3][3];                 // bw[c][a]: window extent
+  const uint8_t *bcls[3];       // 1 on forced faces
+  T *bf[3];                     // forcing (forward) / its adjoint (adjoint)
 };
+
+// Forced face (i, j, k) of component C of a static box: window index in
+// *lidx.
+template <int C, typename T>
+__device__ __forceinline__ int forced_box(const IbView<T>& ib, int i, int j, int k, int* lidx) {
+  const int li = i - ib.bo[C][0], lj = j - ib.bo[C][1], lk = k - ib.bo[C][2];
+  if (li < 0 || lj < 0 || lk < 0 || li >= ib.bw[C][0] || lj >= ib.bw[C][1] || lk >= ib.bw[C][2])
+    return 0;
+  *lidx = (lk * ib.bw[C][1] + lj) * ib.bw[C][0] + li;
+  return ib.bcls[C][*lidx];
+}
 
 __host__ __device__ inline int64_t fidx(const int ext[3], int i, int j, int k) {
   return ((int64_t)k * ext[1] + j) * ext[0] + i;

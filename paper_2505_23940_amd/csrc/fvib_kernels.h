@@ -33,6 +33,15 @@ struct StageMix {
   double a, b;
 };
 
+// Static box on a 3D grid: windows and face-index ranges per component.
+struct BoxGeo {
+  int bo[3][3];        // window origin, component c, axis a
+  int bw[3][3];        // window extent
+  int bs[3][3][2];     // solid face-index range [bs0, bs1) per axis
+  uint8_t* cls[3];     // forced flags of the window faces
+};
+int launch_box_classify(const BoxGeo& B, hipStream_t s);
+
 // Fast-diagonalisation plan: per-axis eigenbases on the device.
 struct FdmDiv {
   int dim, axis;               // axis = last forward axis (dim - 1)
@@ -169,6 +178,14 @@ int launch_adj_body_loads(const IbGeo& B, const IbView<T>& ib, const double* st_
                           const double* st_pos, const double* stbar_out, const double* dF,
                           const double* kc, double* stbar_rk, double* stbar_pos, double* kcbar,
                           SolverScalars* sc, int parts, hipStream_t s);
+// Static box (3D): force F = -rho sum f dv over the forced faces into
+// sc->force, and the forcing adjoint -rho dv dF_c on them (dF nullable).
+template <typename T>
+int launch_box_force(const Geo<double>& G, const IbView<T>& ib, double rho, SolverScalars* sc,
+                     hipStream_t s);
+template <typename T>
+int launch_box_fbar(const Geo<double>& G, const IbView<T>& ib, double rho, const double* dF,
+                    hipStream_t s);
 template <typename T>
 // Strong coupling: Jacobians of a coupling sub-iteration at the iterate om
 // (DF 3 x 6, RF 6 x 3, device) and the fixed-point adjoint lam (6).

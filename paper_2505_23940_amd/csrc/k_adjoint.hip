@@ -343,6 +343,78 @@ __global__ void k_strong_lambda(const double* __restrict__ DF, const double* __r
   }
 }
 
+// ------------------------------------------------- static box (3D)
+// Control volume of face (i, j, k) of component C: centre spacing along C
+// times the transverse cell widths.
+template <typename T>
+__device__ __forceinline__ double box_face_volume(const Geo<double>& G, int c, int i, int j,
+                                                  int k) {
+  const int I[3] = {i, j, k};
+  double v = 1.0;
+  for (int a = 0; a < 3; ++a) v *= (a == c) ? G.dc[a][I[a]] : G.dx[a][I[a]];
+  return v;
+}
+
+// Force on the box: F = -rho sum over forced faces of f dv (one block).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_box_force(Geo<double> G, IbView<T> ib, double rho, SolverScalars* sc) {
+  double F[3] = {0.0, 0.0, 0.0};
+  for (int c = 0; c < 3; ++c) {
+    const int W0 = ib.bw[c][0], W1 = ib.bw[c][1], n = W0 * W1 * ib.bw[c][2];
+    for (int l = threadIdx.x; l < n; l += kBlock) {
+      if (!ib.bcls[c][l]) continue;
+      const int i = ib.bo[c][0] + l % W0, j = ib.bo[c][1] + (l / W0) % W1,
+                k = ib.bo[c][2] + l / (W0 * W1);
+      F[c] -= rho * (double)ib.bf[c][l] * box_face_volume<T>(G, c, i, j, k);
+    }
+  }
+  block_sum<3>(F);
+  if (threadIdx.x == 0)
+    for (int a = 0; a < 3; ++a) sc->force[a] = F[a];
+}
+
+// Forcing adjoint on the box's forced faces for a force adjoint dF
+// (nullable: zero): fbar = -rho dv dF_c.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_box_fbar(Geo<double> G, IbView<T> ib, double rho, const double* __restrict__ dF) {
+  for (int c = 0; c < 3; ++c) {
+    const int W0 = ib.bw[c][0], W1 = ib.bw[c][1], n = W0 * W1 * ib.bw[c][2];
+    const double g = dF ? -rho * dF[c] : 0.0;
+    for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+      const int i = ib.bo[c][0] + l % W0, j = ib.bo[c][1] + (l / W0) % W1,
+                k = ib.bo[c][2] + l / (W0 * W1);
+      ib.bf[c][l] = (T)(ib.bcls[c][l] ? g * box_face_volume<T>(G, c, i, j, k) : 0.0);
+    }
+  }
+}
+
+template <typename T>
+int launch_box_force(const Geo<double>& G, const IbView<T>& ib, double rho, SolverScalars* sc,
+                     hipStream_t s) {
+  launch_kernel((k_box_force<T>), dim3(1), dim3(kBlock), 0, s, G, ib, rho, sc);
+  FVIB_HIP(hipGetLastError());
+  return FVIB_OK;
+}
+
+template <typename T>
+int launch_box_fbar(const Geo<double>& G, const IbView<T>& ib, double rho, const double* dF,
+                    hipStream_t s) {
+  launch_kernel((k_box_fbar<T>), dim3(64), dim3(kBlock), 0, s, G, ib, rho, dF);
+  FVIB_HIP(hipGetLastError());
+  return FVIB_OK;
+}
+
+template int launch_box_force<float>(const Geo<double>&, const IbView<float>&, double,
+                                     SolverScalars*, hipStream_t);
+template int launch_box_force<double>(const Geo<double>&, const IbView<double>&, double,
+                                      SolverScalars*, hipStream_t);
+template int launch_box_fbar<float>(const Geo<double>&, const IbView<float>&, double,
+                                    const double*, hipStream_t);
+template int launch_box_fbar<double>(const Geo<double>&, const IbView<double>&, double,
+                                     const double*, hipStream_t);
+
 // --------------------------------------------------------- projection^T
 // y_c = (G^T ubar)_c = sum over interior faces of c of (+-) ubar_f / dc_f,
 // + for the low face, - for the high face.  Records sum(y) and max |y / V|.
@@ -622,7 +694,7 @@ struct FinAdjRhs {          // mean of G^T ubar, max |y / V| and the solve targe
 
 template <int C, typename T>
 __device__ __forceinline__ int forced_cls(const IbView<T>& ib, int i, int j, int* lidx) {
-  if (!ib.active || C > 1) return 0;
+  if (!ib.active || ib.box || C > 1) return 0;
   const int li = i - ib.origin[2 * C + 0];
   const int lj = j - ib.origin[2 * C + 1];
   if (li < 0 || lj < 0 || li >= ib.W[C][0] || lj >= ib.W[C][1]) return 0;
@@ -706,6 +778,11 @@ k_adj_ustar(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__ b0,
         bool forced = false;
         if (C == 0) forced = forced_cls<0>(ib, i, j, &li);
         else if (C == 1) forced = forced_cls<1>(ib, i, j, &li);
+        if (DIM == 3 && ib.box) {
+          if (C == 0) forced = forced_box<0>(ib, i, j, k, &li);
+          else if (C == 1) forced = forced_box<1>(ib, i, j, k, &li);
+          else forced = forced_box<2>(ib, i, j, k, &li);
+        }
         if (!forced) v += area[C] * (lo[C] - mc);
         us[C][id] = (T)v;
         // high face of the last cell of a bounded axis
@@ -717,6 +794,11 @@ k_adj_ustar(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__ b0,
           bool fh = false;
           if (C == 0) fh = forced_cls<0>(ib, H[0], H[1], &li);
           else if (C == 1) fh = forced_cls<1>(ib, H[0], H[1], &li);
+          if (DIM == 3 && ib.box) {
+            if (C == 0) fh = forced_box<0>(ib, H[0], H[1], H[2], &li);
+            else if (C == 1) fh = forced_box<1>(ib, H[0], H[1], H[2], &li);
+            else fh = forced_box<2>(ib, H[0], H[1], H[2], &li);
+          }
           if (!fh) vh += area[C] * mc;
           us[C][ih] = (T)vh;
         }
@@ -1048,9 +1130,10 @@ struct AdjHalo {
   uint32_t neg;                  // bit 3 h + c: u negated by an x-y ghost
   uint32_t zr;                   // bit 3 h + c: Rbar zero by the x-y rules
   int li[2][2];                  // forced index of components 0, 1 or -1
+  int bxy[2][3];                 // static box: x-y index in the component's window or -1
 };
 
-template <int DIM, typename T>
+template <int DIM, bool BOX, typename T>
 __device__ __forceinline__ void adj_halo_init(const AdjCtx<T>& X, AdjHalo<T, DIM>& Hh, int i0,
                                               int j0) {
   const Geo<T>& G = X.G;
@@ -1087,6 +1170,11 @@ __device__ __forceinline__ void adj_halo_init(const AdjCtx<T>& X, AdjHalo<T, DIM
       const bool notev = c < 2 && !G.per[c] && (I[c] < 1 || I[c] > G.n[c] - 1);
       Hh.neg |= (neg ? 1u : 0u) << (3 * h + c);
       Hh.zr |= ((out || notev) ? 1u : 0u) << (3 * h + c);
+      if (BOX) {
+        const int li = I[0] - X.ib.bo[c][0], lj = I[1] - X.ib.bo[c][1];
+        const bool in = li >= 0 && lj >= 0 && li < X.ib.bw[c][0] && lj < X.ib.bw[c][1];
+        Hh.bxy[h][c] = in ? lj * X.ib.bw[c][0] + li : -1;
+      }
       if (c < 2) {
         int li = -1;
         if (X.ib.active) {
@@ -1100,13 +1188,14 @@ __device__ __forceinline__ void adj_halo_init(const AdjCtx<T>& X, AdjHalo<T, DIM
   }
 }
 
-template <int DIM, typename T>
+template <int DIM, bool BOX, typename T>
 __device__ __forceinline__ void adj_load(const AdjCtx<T>& X, const AdjHalo<T, DIM>& Hh,
                                          AdjRegs<T, DIM>& P, int kk) {
   const Geo<T>& G = X.G;
   // z part of the rules for this plane (uniform across the block)
   // (per component: w has one more face than cells along a bounded z)
   int64_t pbase[DIM];
+  int bz[DIM];                   // static box: z part of the window index or -1
   bool gz[DIM], dz[DIM], zoff[DIM];
   T g2z[DIM];
 #pragma unroll
@@ -1125,6 +1214,10 @@ __device__ __forceinline__ void adj_load(const AdjCtx<T>& X, const AdjHalo<T, DI
       zoff[c] = gz[c] || (c == 2 && !G.per[2] && (kz < 1 || kz > G.n[2] - 1));
     }
     pbase[c] = (int64_t)kz * G.ext[c][0] * G.ext[c][1];
+    if (BOX) {
+      const int lk = kz - X.ib.bo[c][2];
+      bz[c] = (lk >= 0 && lk < X.ib.bw[c][2]) ? lk * X.ib.bw[c][0] * X.ib.bw[c][1] : -1;
+    }
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -1142,6 +1235,13 @@ __device__ __forceinline__ void adj_load(const AdjCtx<T>& X, const AdjHalo<T, DI
       if (c < 2) {
         const int li = Hh.li[h][c];
         if (li >= 0) rv = -X.ib.f[c][li] / G.dt;
+      }
+      if (BOX) {
+        // forced face of the static box: the forcing adjoint, not ustar_bar
+        if (bz[c] >= 0 && Hh.bxy[h][c] >= 0) {
+          const int l = bz[c] + Hh.bxy[h][c];
+          if (X.ib.bcls[c][l]) rv = -X.ib.bf[c][l] / G.dt;
+        }
       }
       const bool zero = ((Hh.zr >> (3 * h + c)) & 1u) || zoff[c];
       P.r[h][c] = zero ? T(0) : rv;
@@ -1164,17 +1264,17 @@ __device__ __forceinline__ void adj_store(AdjRings<T, DIM>& S, int slot, const A
   }
 }
 
-template <int DIM, typename T>
+template <int DIM, bool BOX, typename T>
 __device__ __forceinline__ void adj_fill(const AdjCtx<T>& X, const AdjHalo<T, DIM>& Hh,
                                          AdjRings<T, DIM>& S, int slot, int kk) {
   AdjRegs<T, DIM> P;
-  adj_load<DIM>(X, Hh, P, kk);
+  adj_load<DIM, BOX>(X, Hh, P, kk);
   adj_store<DIM>(S, slot, P);
 }
 
 // At most 128 registers (four waves per SIMD): a channel-sized grid then
 // runs in one round of blocks.
-template <typename T, int DIM, bool UPW>
+template <typename T, int DIM, bool UPW, bool BOX>
 __global__ void __launch_bounds__(kBlock, 4)
 k_adj_momentum_lds(AdjCtx<T> X, int ntx, int nty, int nzc, T* __restrict__ ub0,
                    T* __restrict__ ub1, T* __restrict__ ub2, T* __restrict__ fb0,
@@ -1197,15 +1297,15 @@ k_adj_momentum_lds(AdjCtx<T> X, int ntx, int nty, int nzc, T* __restrict__ ub0,
   const bool inside = i < G.n[0] && j < G.n[1];
   load_tile_met<DIM>(G, TM, i0, j0, k0);
   AdjHalo<T, DIM> Hh;
-  adj_halo_init<DIM>(X, Hh, i0, j0);
+  adj_halo_init<DIM, BOX>(X, Hh, i0, j0);
   AdjRegs<T, DIM> nxt;
   if (DIM == 3) {
-    adj_fill<DIM>(X, Hh, S, ring_slot(k0 - 1), k0 - 1);
-    adj_fill<DIM>(X, Hh, S, ring_slot(k0), k0);
-    adj_fill<DIM>(X, Hh, S, ring_slot(k0 + 1), k0 + 1);
-    if (k0 + 1 < k1) adj_load<DIM>(X, Hh, nxt, k0 + 2);
+    adj_fill<DIM, BOX>(X, Hh, S, ring_slot(k0 - 1), k0 - 1);
+    adj_fill<DIM, BOX>(X, Hh, S, ring_slot(k0), k0);
+    adj_fill<DIM, BOX>(X, Hh, S, ring_slot(k0 + 1), k0 + 1);
+    if (k0 + 1 < k1) adj_load<DIM, BOX>(X, Hh, nxt, k0 + 2);
   } else {
-    adj_fill<DIM>(X, Hh, S, 0, 0);
+    adj_fill<DIM, BOX>(X, Hh, S, 0, 0);
   }
   for (int k = k0; k < k1; ++k) {
     __syncthreads();
@@ -1274,7 +1374,7 @@ k_adj_momentum_lds(AdjCtx<T> X, int ntx, int nty, int nzc, T* __restrict__ ub0,
     if (DIM == 3 && k + 1 < k1) {
       __syncthreads();
       adj_store<DIM>(S, sm, nxt);                     // slot of plane k-1 takes k+2
-      if (k + 2 < k1) adj_load<DIM>(X, Hh, nxt, k + 3);
+      if (k + 2 < k1) adj_load<DIM, BOX>(X, Hh, nxt, k + 3);
     }
   }
 }
@@ -1432,11 +1532,14 @@ static int launch_adj_momentum_t(const AdjCtx<T>& X, T* ubar[3], T* fbbar[3], hi
   int nb = ntx * nty * nzc;
   nb = (nb + kXcds - 1) / kXcds * kXcds;
   if (G.dim == 2)
-    launch_kernel((k_adj_momentum_lds<T, 2, UPW>), dim3(nb), dim3(kBlock), 0, s, X, ntx, nty,
-                       nzc, ubar[0], ubar[1], ubar[2], fbbar[0], fbbar[1], fbbar[2]);
+    launch_kernel((k_adj_momentum_lds<T, 2, UPW, false>), dim3(nb), dim3(kBlock), 0, s, X, ntx,
+                  nty, nzc, ubar[0], ubar[1], ubar[2], fbbar[0], fbbar[1], fbbar[2]);
+  else if (X.ib.box)
+    launch_kernel((k_adj_momentum_lds<T, 3, UPW, true>), dim3(nb), dim3(kBlock), 0, s, X, ntx,
+                  nty, nzc, ubar[0], ubar[1], ubar[2], fbbar[0], fbbar[1], fbbar[2]);
   else
-    launch_kernel((k_adj_momentum_lds<T, 3, UPW>), dim3(nb), dim3(kBlock), 0, s, X, ntx, nty,
-                       nzc, ubar[0], ubar[1], ubar[2], fbbar[0], fbbar[1], fbbar[2]);
+    launch_kernel((k_adj_momentum_lds<T, 3, UPW, false>), dim3(nb), dim3(kBlock), 0, s, X, ntx,
+                  nty, nzc, ubar[0], ubar[1], ubar[2], fbbar[0], fbbar[1], fbbar[2]);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }

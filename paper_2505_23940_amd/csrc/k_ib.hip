@@ -227,6 +227,35 @@ __global__ void k_copy_info(const SolverScalars* sc, fvib_step_info* info, int c
   info->xi = cpl_iters ? sc->xi : 0.0;
 }
 
+// Static box on a 3D grid: forced flags on the window faces of each
+// component from the box's face-index ranges [bs0, bs1) per axis (the faces
+// whose points lie in the half-open box): solid inside the ranges, immersed
+// boundary one step outside along exactly one axis (a solid axis neighbour).
+__global__ void __launch_bounds__(kBlock) k_box_classify(BoxGeo B) {
+  for (int c = 0; c < 3; ++c) {
+    const int W0 = B.bw[c][0], W1 = B.bw[c][1], n = W0 * W1 * B.bw[c][2];
+    for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+      const int I[3] = {B.bo[c][0] + l % W0, B.bo[c][1] + (l / W0) % W1,
+                        B.bo[c][2] + l / (W0 * W1)};
+      bool in[3], near[3];
+      for (int a = 0; a < 3; ++a) {
+        in[a] = I[a] >= B.bs[c][a][0] && I[a] < B.bs[c][a][1];
+        near[a] = I[a] == B.bs[c][a][0] - 1 || I[a] == B.bs[c][a][1];
+      }
+      const bool solid = in[0] && in[1] && in[2];
+      const bool ibp = !solid && ((near[0] && in[1] && in[2]) || (in[0] && near[1] && in[2]) ||
+                                  (in[0] && in[1] && near[2]));
+      B.cls[c][l] = (solid || ibp) ? 1 : 0;
+    }
+  }
+}
+
+int launch_box_classify(const BoxGeo& B, hipStream_t s) {
+  launch_kernel(k_box_classify, dim3(64), dim3(kBlock), 0, s, B);
+  FVIB_HIP(hipGetLastError());
+  return FVIB_OK;
+}
+
 // ------------------------------------------------------------ launchers
 template <typename T>
 int launch_ib_classify(const IbGeo& B, const double* body, T* us0, T* us1, SolverScalars* sc,

@@ -112,7 +112,16 @@ __device__ __forceinline__ void predict_face(const Geo<T>& G, const Load& L, con
     return;
   }
   const T un = L(C, 0, 0, 0);
-  if constexpr (C < 2 && IBA) {
+  if constexpr (DIM == 3 && IBA) {
+    // static box: target zero on the forced faces
+    int li = 0;
+    if (forced_box<C>(ib, i, j, k, &li)) {
+      ib.bf[C][li] = -R - un / G.dt;
+      out[id] = T(0);
+      return;
+    }
+  }
+  if constexpr (DIM == 2 && C < 2 && IBA) {
     int li = 0;
     if (forced<C>(ib, i, j, &li)) {
       // Eq. 5 substituted into Eq. 4: the forced face takes the target

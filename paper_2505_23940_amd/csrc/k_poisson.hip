@@ -208,8 +208,8 @@ k_ppe_rhs(Geo<T> G, PGeo<double> P, Tiling tl, const T* __restrict__ s0,
       hi[c] = (double)us[c][fidx(G.ext[c], H[0], H[1], H[2])];
       d[c] = P.dx[c][I[c]];
     }
-    if (ib.active) {
-      // u~ = u_c on the forced faces
+    if (ib.active && !ib.box) {
+      // u~ = u_c on the forced faces (a static box has u* = u_c = 0 there)
 #pragma unroll
       for (int c = 0; c < (DIM < 2 ? DIM : 2); ++c) {
         const double Uc = ib.body[3 + c];

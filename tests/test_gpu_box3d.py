@@ -1,0 +1,150 @@
+"""Static immersed boxes on 3D grids (the wall-mounted cube of Sec. 3.4.2
+with the direct forcing of Eq. 5) through the C ABI, against the oracle
+(oracle/ibm3d.py): forward steps (velocity, pressure, momentum-form force),
+one-step vector-Jacobian products with a force adjoint, and a rollout
+gradient; plus the set-up's argument checks."""
+import numpy as np
+import pytest
+import torch
+
+import fvib_workloads as W
+from gpu_util import gauge, make_grid, need_gpu, rel_l2
+from test_gpu_adjoint import _close
+
+pytestmark = pytest.mark.gpu
+F64 = torch.float64
+
+
+def _cases():
+    ch = W.channel(nx=24, ny=16, nz=20, steps=8, dt=1e-5)
+    ch.box = ((2.0, -0.72, 1.0), (3.3, -0.05, 2.1))           # wall-mounted cube region
+    n = 16
+    f = np.linspace(0, 2.0, n + 1)
+    pb = W.generic(3, (n, n, n), [f, f, f], [["periodic", "periodic"]] * 3, nu=0.05, dt=2e-3,
+                   steps=6)
+    pb.box = ((0.61, 0.73, 0.52), (1.22, 1.31, 1.09))
+    return {"channel_box": ch, "periodic_box": pb}
+
+
+def _fields(w, seed):
+    u0, fb = W.initial_fields(w)
+    if w.bc[1][0] == "periodic":
+        u0 = W.random_fields(w, seed, 0.5)
+        fb = [np.full(x.shape, v) for x, v in zip(u0, (0.3, -0.2, 0.1))]
+    return u0, fb
+
+
+@pytest.mark.parametrize("case", list(_cases().keys()))
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_box_steps_match_oracle(case, precision):
+    need_gpu()
+    from oracle import Grid as OGrid
+    from oracle import init_state, make_params, rollout
+    w = _cases()[case]
+    u0, fb = _fields(w, 3)
+    og = OGrid(w)
+    with torch.no_grad():
+        st, Fo, _ = rollout(og, init_state(og, u0), make_params(og, fb), w.steps)
+    g = make_grid(w, precision=precision, poisson_tol=1e-12 if precision == "fp64" else 1e-9)
+    u, fbt, p = g.to_u(u0), g.to_u(fb), g.zeros_p()
+    forces = []
+    for _ in range(w.steps):
+        g.step(u, p, fbt)
+        forces.append(g.last_info()["force"])
+    torch.cuda.synchronize()
+    gu = [x.double().cpu().numpy() for x in u]
+    eu = rel_l2(gu, [x.numpy() for x in st["u"]])
+    ep = rel_l2([gauge(p.cpu().numpy())], [st["p"].numpy()])
+    fo = Fo.numpy()
+    ef = float(max(np.abs(np.asarray(forces[n]) - fo[n]).max() / np.abs(fo[n]).max()
+                   for n in range(w.steps)))
+    print(f"{case} {precision}: u {eu:.2e} p {ep:.2e} force {ef:.2e}")
+    if precision == "fp64":
+        assert eu <= 1e-10 and ep <= 1e-8 and ef <= 1e-9, (eu, ep, ef)
+    else:
+        assert eu <= 1e-5 and ef <= 2e-5, (eu, ef)
+    assert np.abs(fo).max() > 0.0
+
+
+@pytest.mark.parametrize("case", list(_cases().keys()))
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_box_step_vjp(case, precision):
+    need_gpu()
+    from oracle import Grid as OGrid
+    from oracle import init_state, make_params, step
+    w = _cases()[case]
+    u0, fb = _fields(w, 5)
+    rng = np.random.default_rng(6)
+    u = [a + 0.1 * b for a, b in zip(u0, W.random_fields(w, 7))]
+    ubar = W.random_fields(w, 8)
+    dF = rng.standard_normal(3)
+    r32 = precision == "fp32"
+    cast = (lambda a: torch.tensor(a).float().double()) if r32 else (lambda a: torch.tensor(a))
+    if r32:
+        ubar = [np.asarray(x, dtype=np.float32).astype(np.float64) for x in ubar]
+    og = OGrid(w)
+    ut = [cast(x).requires_grad_(True) for x in u]
+    fbt = [cast(x).requires_grad_(True) for x in fb]
+    st, aux = step(og, init_state(og, ut), make_params(og, fbt))
+    L = sum((st["u"][i] * torch.tensor(ubar[i])).sum() for i in range(3))
+    L = L + (aux["F"] * torch.tensor(dF)).sum()
+    L.backward()
+    g = make_grid(w, precision=precision, poisson_tol=1e-12 if not r32 else 1e-9)
+    dev = g.device
+    ub0, fbb = g.zeros_u(), g.zeros_u()
+    g.step_adjoint(g.to_u(u), g.to_u(fb), None, None, g.to_u(ubar), None,
+                   torch.tensor(dF, dtype=F64, device=dev), ub0, None, fbbar=fbb)
+    torch.cuda.synchronize()
+    tol = 1e-9 if not r32 else 2e-4
+    for i in range(3):
+        _close(ub0[i].double().cpu().numpy(), ut[i].grad.numpy(), tol, f"ubar[{i}]")
+        _close(fbb[i].double().cpu().numpy(), fbt[i].grad.numpy(), tol, f"fbbar[{i}]")
+
+
+def test_box_rollout_gradient():
+    need_gpu()
+    from oracle import Grid as OGrid
+    from oracle import init_state, make_params, rollout
+    from oracle.step import wall_shear
+    from paper_2505_23940_amd.rollout import rollout as g_rollout
+    from paper_2505_23940_amd.rollout import wall_shear as g_wall_shear
+    w = _cases()["channel_box"]
+    w.steps = 5
+    og = OGrid(w)
+    u0, fb = W.initial_fields(w)
+    fbt = [torch.tensor(x, requires_grad=True) for x in fb]
+    st, _, _ = rollout(og, init_state(og, u0), make_params(og, fbt), w.steps)
+    Jo = wall_shear(og, st["u"])
+    Jo.backward()
+    g = make_grid(w, precision="fp64", poisson_tol=1e-12)
+    fg = [x.requires_grad_(True) for x in g.to_u(fb)]
+    kc = torch.zeros(6, dtype=F64, device=g.device)
+    b0 = torch.zeros(6, dtype=F64, device=g.device)
+    uS, _, _, _ = g_rollout(g, g.to_u(u0), fg, kc, b0, w.steps, ckpt_every=2)
+    J = g_wall_shear(g, uS[0])
+    J.backward()
+    torch.cuda.synchronize()
+    assert abs(float(J.detach()) - float(Jo.detach())) <= 1e-10 * abs(float(Jo.detach()))
+    e = rel_l2([x.grad.double().cpu().numpy() for x in fg], [x.grad.numpy() for x in fbt])
+    print(f"channel with box, 5 steps: dJ/dfb rel L2 {e:.2e}")
+    assert e <= 1e-8, e
+
+
+def test_box_setup_checks():
+    need_gpu()
+    from paper_2505_23940_amd import FvibError
+    w = W.channel(nx=16, ny=12, nz=10, steps=1)
+    g = make_grid(w, precision="fp64")
+    with pytest.raises(FvibError):
+        g.set_box((1.0, -1.2, 1.0), (2.0, 0.0, 2.0))     # touches the wall
+    with pytest.raises(FvibError):
+        g.set_box((1.0, 0.5, 1.0), (1.0, 0.6, 2.0))      # empty
+    with pytest.raises(FvibError):
+        g.set_box((0.0, -0.5, 1.0), (1.0, 0.1, 2.0))     # on the periodic seam of x
+    g.set_box((1.0, -0.5, 1.0), (2.0, 0.1, 2.0))
+    u0, fb = W.initial_fields(w)
+    u, p = g.to_u(u0), g.zeros_p()
+    with pytest.raises(FvibError):
+        g.step(u, p, g.to_u(fb), scheme="rk3")          # no Runge-Kutta with a body
+    g.set_box(None, None)
+    g.step(u, p, g.to_u(fb), scheme="rk3")
