@@ -16,6 +16,9 @@ Workloads (all nondimensional, rho = 1, see the paper's validation cases):
 * ``channel``  -- 3D plane channel at Re_tau = 180 on a tanh-stretched
                   wall-normal grid, driven by a uniform body force
                   (Sec. 3.4.1 of the paper, Table 4).
+* ``wmles``    -- wall-modelled LES of a plane channel, uniform 64^3 grid on
+                  2pi x 2 x pi, Re_tau = 2000, constant Smagorinsky model and
+                  equilibrium wall model (Sec. 3.4.5, Table 5).
 * ``viv``      -- 2D elastically mounted cylinder, 1-DOF transverse spring
                   (or 2-DOF, equal springs in-line and cross-flow), m* = 2,
                   U_r = 5, zeta = 0, Re = 150 (Sec. 3.2, Table 2); weak or
@@ -75,6 +78,9 @@ class Workload:
     body: Optional[Body] = None
     # static immersed box (3D grids): ((x0, y0, z0), (x1, y1, z1)), or None
     box: Optional[tuple] = None
+    # large-eddy simulation: {"cs": Smagorinsky constant, "wall_model": bool,
+    # "kappa", "B": Spalding-law constants, "eps": Eq. 28 regulariser}, or None
+    les: Optional[dict] = None
     meta: dict = field(default_factory=dict)
 
     @property
@@ -150,6 +156,22 @@ def channel(nx: int = 192, ny: int = 128, nz: int = 160, steps: int = 200,
                  rho=1.0, dt=dt, steps=steps, precision=precision,
                  meta={"seed": seed, "u_bulk": math.sqrt(2.0 / cf),
                        "fb": (1.0, 0.0, 0.0), "perturb": 0.1})
+    return w
+
+
+def wmles(n: int = 64, re_tau: float = 2000.0, cs: float = 0.1, steps: int = 100,
+          dt: float = 1e-3, wall_model: bool = True, precision: str = "fp32",
+          seed: int = 20250531, kappa: float = 0.4, B: float = 5.0,
+          eps: float = 1e-6) -> Workload:
+    """Wall-modelled LES of a plane channel (Sec. 3.4.5, Table 5): uniform
+    n^3 grid on 2pi x 2 x pi, nu = 1 / Re_tau (u_tau = 1, half height 1),
+    driven by the uniform body force 1 that balances the mean wall stress."""
+    faces = [_uniform(n, 0.0, 2.0 * np.pi), _uniform(n, -1.0, 1.0), _uniform(n, 0.0, np.pi)]
+    bc = [["periodic", "periodic"], ["noslip", "noslip"], ["periodic", "periodic"]]
+    w = Workload("wmles", 3, (n, n, n), faces, bc, _bcv(), nu=1.0 / re_tau, rho=1.0,
+                 dt=dt, steps=steps, precision=precision,
+                 les={"cs": cs, "wall_model": wall_model, "kappa": kappa, "B": B, "eps": eps},
+                 meta={"seed": seed, "re_tau": re_tau, "fb": (1.0, 0.0, 0.0), "perturb": 0.1})
     return w
 
 
@@ -261,6 +283,24 @@ def initial_fields(w: Workload):
             u[c] = u[c] + pert
         for c in range(3):
             fb[c][...] = w.meta["fb"][c]
+    elif w.name == "wmles":
+        # Reichardt's mean profile in wall units (u_tau = 1) plus seeded noise
+        re = w.meta["re_tau"]
+        _, y, _ = face_points(w, 0)
+        yp = (1.0 - np.abs(y)) * re
+        k = 0.41
+        up = np.log1p(k * yp) / k + 7.8 * (1.0 - np.exp(-yp / 11.0) - yp / 11.0 * np.exp(-yp / 3.0))
+        u[0] = np.broadcast_to(up, u[0].shape).copy()
+        rng = np.random.default_rng(w.meta["seed"])
+        amp = w.meta["perturb"] * float(up.mean())
+        for c in range(3):
+            pert = amp * (2.0 * rng.random(u[c].shape) - 1.0)
+            if c == 1:
+                pert[:, 0, :] = 0.0
+                pert[:, -1, :] = 0.0
+            u[c] = u[c] + pert
+        for c in range(3):
+            fb[c][...] = w.meta["fb"][c]
     elif w.name in ("cylinder", "viv"):
         u[0][...] = w.bc_vel[0, 0, 0]
     return u, fb
@@ -294,6 +334,8 @@ def by_name(name: str, size: str = "full") -> Workload:
         return tgv3d() if size == "full" else tgv3d(n=24, steps=10)
     if name == "channel":
         return channel() if size == "full" else channel(nx=24, ny=16, nz=20, steps=10)
+    if name == "wmles":
+        return wmles() if size == "full" else wmles(n=16, steps=5)
     if name == "cylinder":
         if size == "full":
             return cylinder()

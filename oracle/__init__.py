@@ -19,6 +19,9 @@ It is a plain, slow, float64 implementation written from the paper
   fluid-to-solid spreading (Eq. 20) with the 4-point kernel (Eqs. 21-22);
 * body  (``body.py``)   -- rigid spring-damper oscillator with classic RK4
   (Eq. 12);
+* LES   (``les.py``)    -- constant Smagorinsky subgrid stress and the
+  equilibrium wall-stress model with the Spalding law (Sec. 3.4.5,
+  Eqs. 27-29), added to the momentum right-hand side;
 * step  (``step.py``)   -- one weakly coupled step (Alg. 1 with N = 1),
   rollouts and the two loss functionals.
 

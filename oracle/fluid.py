@@ -181,7 +181,9 @@ def diffusion(g: Grid, u) -> list:
 
 
 def momentum_rhs(g: Grid, u, fb) -> list:
-    """R = -div(u (x) u) + nu lap(u) + f_b on the evolved faces (zero elsewhere)."""
+    """R = -div(u (x) u) + nu lap(u) + f_b on the evolved faces (zero elsewhere),
+    plus the divergence of the subgrid stress when the workload enables LES
+    (``les.py``)."""
     C = convection(g, u)
     L = diffusion(g, u)
     out = []
@@ -190,6 +192,9 @@ def momentum_rhs(g: Grid, u, fb) -> list:
         Rin = -C[c] + g.nu * L[c] + _sl(fb[c], {c: (e0, e1)})
         R = _place(torch.zeros(g.face_shape(c), dtype=F64), Rin, c, e0, e1)
         out.append(R)
+    if getattr(g.w, "les", None) is not None:
+        from . import les          # subgrid stress divergence (zero off the evolved faces)
+        out = [R + S for R, S in zip(out, les.sgs_force(g, u))]
     return out
 
 
