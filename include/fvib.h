@@ -214,6 +214,30 @@ int fvib_ib_set_body(fvib_grid *g, const fvib_body_desc *body);
  * fvib_ib_set_body fails while a box is). */
 int fvib_ib_set_box(fvib_grid *g, const double *lo, const double *hi);
 
+/* Large-eddy simulation model (Sec. 2.5, Table 1; Sec. 3.4.5, Eqs. 27-29). */
+typedef struct {
+  double cs;                /* Smagorinsky constant C_s >= 0                    */
+  int32_t wall_model;       /* 1: equilibrium wall-stress model on the y walls  */
+  int32_t reserved;         /* 0                                                */
+  double kappa, B;          /* Spalding-law constants (the paper: 0.4, 5)       */
+  double eps;               /* Eq. 28 regulariser (the paper: 1e-6)             */
+} fvib_les_desc;
+
+/* Enable the subgrid model on a 3D grid whose axes are all periodic or
+ * no-slip wall pairs; d = NULL disables it.  Every later step (fvib_step,
+ * fvib_step_rk) adds the divergence of the subgrid stress 2 nu_t S to the
+ * momentum right-hand side on the evolved faces, nu_t = (C_s Delta)^2 |S|
+ * at cell centres (Delta = (dx dy dz)^(1/3), |S| = sqrt(2 S_ij S_ij)),
+ * shear stresses on cell edges with the four-cell mean of nu_t and zero
+ * viscosity on wall edges; fvib_step_adjoint differentiates it.  With
+ * wall_model = 1 (walls normal to y, x and z periodic, n[1] >= 2) the wall
+ * edges of u and w get the viscosity of Eq. 28 from the Spalding law
+ * (Eq. 27) at the half height of the wall cell, tau_w = u_tau^2 split by
+ * Eq. 29 (kinematic stress), the other tangential component averaged from
+ * its four nearest faces.  FVIB_EINVAL for a grid or a descriptor outside
+ * these rules; allocates its workspace (about 20 cell-sized arrays). */
+int fvib_les_set(fvib_grid *g, const fvib_les_desc *d);
+
 /* One weakly coupled time step (Alg. 1 with N = 1): classification and
  * target velocities, predictor with direct forcing (Eqs. 4-5), boundary
  * faces, modified PPE (Eq. 9) solved by conjugate gradients (double, or
@@ -447,7 +471,9 @@ enum {
   FVIB_K_ADJ_USTAR = 18,  /* adjoint predicted velocity from the solution    */
   FVIB_K_RHS_RES = 19,    /* Eq. 9 right-hand side with the first residual   */
   FVIB_K_ADJ_RHS_RES = 20, /* adjoint right-hand side with the first residual */
-  FVIB_K_NCLASSES = 21
+  FVIB_K_LES = 21,        /* subgrid viscosity, wall model, stress divergence */
+  FVIB_K_ADJ_LES = 22,    /* their adjoint                                   */
+  FVIB_K_NCLASSES = 23
 };
 
 /* Start (enable != 0, totals cleared) or stop recording.  A recorded

@@ -214,6 +214,7 @@ class Grid:
         self.pshape = fvib_field_layout(self.h, 3)[0]
         self.has_body = False
         self.has_box = False
+        self.has_les = False
         self._info = torch.zeros(INFO_DOUBLES, dtype=torch.float64, device=self.device)
 
     @classmethod
@@ -229,6 +230,8 @@ class Grid:
             g.set_body(b.kind, b.X0, b.ds, b.free_dof, b.m)
         if getattr(w, "box", None) is not None:
             g.set_box(w.box[0], w.box[1])
+        if getattr(w, "les", None) is not None:
+            g.set_les(**w.les)
         return g
 
     def close(self):
@@ -306,6 +309,23 @@ class Grid:
         hi_a = (C.c_double * 3)(*[float(x) for x in hi])
         _check(lib().fvib_ib_set_box(self.h, lo_a, hi_a), self.h)
         self.has_box = True
+
+    def set_les(self, cs: Optional[float], wall_model: bool = False, kappa: float = 0.4,
+                B: float = 5.0, eps: float = 1e-6) -> None:
+        """Constant Smagorinsky subgrid model, with the equilibrium wall
+        model on the y walls if wall_model (fvib_les_set); cs = None turns
+        the model off."""
+        if cs is None:
+            _check(lib().fvib_les_set(self.h, None), self.h)
+            self.has_les = False
+            return
+        d = _abi.LesDesc()
+        d.cs = float(cs)
+        d.wall_model = 1 if wall_model else 0
+        d.reserved = 0
+        d.kappa, d.B, d.eps = float(kappa), float(B), float(eps)
+        _check(lib().fvib_les_set(self.h, C.byref(d)), self.h)
+        self.has_les = True
 
     def set_body(self, kind: str, X0, ds, free_dof=(0, 0, 0), m: float = 1.0):
         X0 = np.ascontiguousarray(np.asarray(X0, dtype=np.float64))

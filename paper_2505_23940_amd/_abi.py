@@ -25,6 +25,7 @@ EXPORTS = (
     "fvib_create_grid", "fvib_destroy_grid", "fvib_field_layout", "fvib_ib_set_body",
     "fvib_step", "fvib_step_adjoint", "fvib_step_strong", "fvib_step_strong_adjoint",
     "fvib_step_rk", "fvib_step_rk_adjoint", "fvib_set_dt", "fvib_cfl_dt", "fvib_ib_set_box",
+    "fvib_les_set",
     "fvib_loss_wall_shear", "fvib_loss_wall_shear_noalloc",
     "fvib_loss_rms_lift",
     "fvib_last_error", "fvib_test_momentum", "fvib_test_ppe_rhs", "fvib_test_poisson",
@@ -42,7 +43,7 @@ K_CLASSES = {"predictor": 0, "boundary": 1, "ppe_rhs": 2, "residual": 3, "cg_dir
              "cg_update": 5, "ir_correct": 6, "project": 7, "ib": 8, "adjoint": 9,
              "fdm_x": 10, "fdm_y": 11, "fdm_z": 12, "adj_momentum": 13, "fdm_last": 14,
              "fft": 15, "fft_acc": 16, "adj_rhs": 17, "adj_ustar": 18,
-             "rhs_res": 19, "adj_rhs_res": 20}
+             "rhs_res": 19, "adj_rhs_res": 20, "les": 21, "adj_les": 22}
 
 
 class GridDesc(C.Structure):
@@ -66,6 +67,13 @@ class BodyDesc(C.Structure):
         ("kind", C.c_int32), ("n_markers", C.c_int32),
         ("X0", C.c_void_p), ("ds", C.c_void_p),
         ("free_dof", C.c_int32 * 3), ("m", C.c_double),
+    ]
+
+
+class LesDesc(C.Structure):
+    _fields_ = [
+        ("cs", C.c_double), ("wall_model", C.c_int32), ("reserved", C.c_int32),
+        ("kappa", C.c_double), ("B", C.c_double), ("eps", C.c_double),
     ]
 
 
@@ -118,6 +126,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                          C.POINTER(Adjoint), C.c_int, vp]
     lib.fvib_set_dt.argtypes = [vp, C.c_double]
     lib.fvib_ib_set_box.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.fvib_les_set.argtypes = [vp, C.POINTER(LesDesc)]
     lib.fvib_cfl_dt.argtypes = [vp, vp * 3, C.c_double, C.c_double, C.POINTER(C.c_double)]
     lib.fvib_step_strong.argtypes = [vp, C.POINTER(Fields), C.POINTER(Fields), C.c_int32,
                                      C.c_double, vp, vp]

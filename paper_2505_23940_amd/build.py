@@ -18,7 +18,7 @@ OBJ_DIR = os.path.join(OUT_DIR, "obj")
 LIB = os.path.join(OUT_DIR, "libfvib.so")
 
 SOURCES = ["fvib_api.hip", "k_momentum.hip", "k_poisson.hip", "k_ib.hip", "k_adjoint.hip",
-           "k_loss.hip", "k_fdm.hip", "k_fft.hip"]
+           "k_loss.hip", "k_fdm.hip", "k_fft.hip", "k_les.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <functional>
 #include <string>
 #include <vector>
@@ -168,6 +169,16 @@ struct Grid {
   bool has_box = false;
   BoxGeo box;
   void* bf[3] = {nullptr, nullptr, nullptr};
+  // large-eddy simulation: g = fb + subgrid term handed to the predictor,
+  // its adjoint, and the model's work arrays (see k_les.hip)
+  bool has_les = false;
+  fvib_les_desc les{};
+  void* les_nut = nullptr;
+  void* les_g[3] = {nullptr, nullptr, nullptr};
+  void* les_gb[3] = {nullptr, nullptr, nullptr};
+  void* les_cell[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  void* les_edge[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  double* les_wall = nullptr;     // 12 slabs of nz x nx: nuw, wown, woth per [comp][side]
   // immersed body
   bool has_body = false;
   IbGeo ib;
@@ -246,6 +257,14 @@ static void release(Grid* g) {
     f(g->box.cls[c]);
     f(g->bf[c]);
   }
+  f(g->les_nut);
+  for (int c = 0; c < 3; ++c) {
+    f(g->les_g[c]);
+    f(g->les_gb[c]);
+  }
+  for (void* q : g->les_cell) f(q);
+  for (void* q : g->les_edge) f(q);
+  f(g->les_wall);
   for (int c = 0; c < 2; ++c) {
     f(g->cls[c]);
     f(g->us[c]);
@@ -822,6 +841,39 @@ static IbView<T> ib_view(Grid* g, const double* body) {
   return v;
 }
 
+template <typename T>
+static LesView<T> les_view(Grid* g) {
+  LesView<T> v;
+  memset(&v, 0, sizeof(v));
+  v.wall = g->les.wall_model ? 1 : 0;
+  v.cs2 = (T)(g->les.cs * g->les.cs);
+  v.nu = g->d.nu;
+  v.kappa = g->les.kappa;
+  v.B = g->les.B;
+  v.eps = g->les.eps;
+  for (int s = 0; s < 2; ++s) {
+    const std::vector<double>& f = g->faces[1];
+    v.yw[s] = 0.5 * (s == 0 ? f[1] - f[0] : f[g->n[1]] - f[g->n[1] - 1]);
+    for (int c = 0; c < 3; ++c) v.uw[s][c] = g->d.bc_vel[1][s][c];
+  }
+  v.nut = (T*)g->les_nut;
+  const int64_t slab = (int64_t)g->n[0] * g->n[2];
+  for (int c = 0; c < 2; ++c)
+    for (int s = 0; s < 2; ++s) {
+      v.nuw[c][s] = g->les_wall + (0 + 2 * c + s) * slab;
+      v.wown[c][s] = g->les_wall + (4 + 2 * c + s) * slab;
+      v.woth[c][s] = g->les_wall + (8 + 2 * c + s) * slab;
+    }
+  for (int c = 0; c < 3; ++c) {
+    v.wcc[c] = (T*)g->les_cell[c];
+    v.soff[c] = (T*)g->les_cell[3 + c];
+    v.pe[c] = (T*)g->les_edge[c];
+    v.qe[c] = (T*)g->les_edge[3 + c];
+  }
+  v.nbar = (T*)g->les_cell[6];
+  return v;
+}
+
 static int reset_scalars(Grid* g) {
   FVIB_HIP(hipMemsetAsync(g->sc, 0, sizeof(SolverScalars), g->stream));
   return FVIB_OK;
@@ -922,6 +974,15 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
   T* us[3] = {(T*)g->ustar[0], (T*)g->ustar[1], (T*)g->ustar[2]};
   T* uo[3] = {(T*)out->u[0], (T*)out->u[1], g->dim == 3 ? (T*)out->u[2] : nullptr};
   const Geo<T>& G = geo_of<T>(g);
+  if (g->has_les) {
+    // the subgrid term rides in the body force: g = fb + div(2 nu_t S)
+    T* gl[3] = {(T*)g->les_g[0], (T*)g->les_g[1], (T*)g->les_g[2]};
+    if ((rc = timed(g, FVIB_K_LES, [&] {
+           return launch_les_forward<T>(G, les_view<T>(g), u, fb, gl, g->stream);
+         })))
+      return rc;
+    for (int c = 0; c < 3; ++c) fb[c] = gl[c];
+  }
   const bool strong = so && g->has_body;
   const double* body_f = in->body;    // body state the fluid sees
   double* wnew = nullptr;
@@ -1044,6 +1105,16 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
   const T* ub1[3] = {(const T*)bo->u[0], (const T*)bo->u[1], d == 3 ? (const T*)bo->u[2] : nullptr};
   T* ub0[3] = {(T*)bi->u[0], (T*)bi->u[1], d == 3 ? (T*)bi->u[2] : nullptr};
   T* fbb[3] = {(T*)bi->fb[0], (T*)bi->fb[1], d == 3 ? (T*)bi->fb[2] : nullptr};
+  T* fbb_user[3] = {fbb[0], fbb[1], fbb[2]};
+  if (g->has_les) {
+    // The momentum adjoint adds the adjoint of g = fb + subgrid term into
+    // its body-force output; collect this step's share alone in the
+    // workspace (the subgrid adjoint needs it), then add it to the caller's
+    for (int c = 0; c < 3; ++c) {
+      FVIB_HIP(hipMemsetAsync(g->les_gb[c], 0, (size_t)g->nface[c] * g->esize(), g->stream));
+      fbb[c] = (T*)g->les_gb[c];
+    }
+  }
   const IbView<T> ib = ib_view<T>(g, in->body);
   if (g->has_body) {
     // recompute the forward forcing and force of this step (frozen classes)
@@ -1132,6 +1203,12 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
     return rc;
   if ((rc = timed(g, FVIB_K_ADJOINT, [&] {
          return launch_adj_outflow<T>(G, g->planes, 1, usb, ub0, g->red(), g->sc, g->stream);
+       })))
+    return rc;
+  if (g->has_les &&
+      (rc = timed(g, FVIB_K_ADJ_LES, [&] {
+         return launch_les_adjoint<T>(G, les_view<T>(g), u, (const T* const*)fbb, ub0, fbb_user,
+                                      g->stream);
        })))
     return rc;
   fvib_step_info* dst = info ? info : g->info_dev;
@@ -1941,6 +2018,66 @@ int fvib_ib_set_box(fvib_grid* h, const double* lo, const double* hi) {
   if ((rc = launch_box_classify(B, g->stream))) return rc;
   FVIB_HIP(hipStreamSynchronize(g->stream));
   g->has_box = true;
+  return FVIB_OK;
+}
+
+int fvib_les_set(fvib_grid* h, const fvib_les_desc* d) {
+  if (!h) return FVIB_EINVAL;
+  Grid* g = &h->g;
+  (void)hipStreamSynchronize(g->stream);
+  auto f = [](void*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+  };
+  f(g->les_nut);
+  for (int c = 0; c < 3; ++c) {
+    f(g->les_g[c]);
+    f(g->les_gb[c]);
+  }
+  for (void*& q : g->les_cell) f(q);
+  for (void*& q : g->les_edge) f(q);
+  if (g->les_wall) (void)hipFree(g->les_wall);
+  g->les_wall = nullptr;
+  g->has_les = false;
+  if (!d) return FVIB_OK;
+  if (g->dim != 3) return fail(g, FVIB_EINVAL, "the subgrid model is defined on 3D grids");
+  for (int a = 0; a < 3; ++a)
+    if (!g->per[a] && (g->d.bc[a][0] != FVIB_BC_NOSLIP || g->d.bc[a][1] != FVIB_BC_NOSLIP))
+      return fail(g, FVIB_EINVAL, "LES grids need periodic axes or no-slip wall pairs");
+  if (!(d->cs >= 0.0) || !std::isfinite(d->cs))
+    return fail(g, FVIB_EINVAL, "the Smagorinsky constant must be finite and >= 0");
+  if (d->reserved != 0) return fail(g, FVIB_EINVAL, "fvib_les_desc.reserved must be 0");
+  if (d->wall_model) {
+    if (!g->per[0] || g->per[1] || !g->per[2] || g->n[1] < 2)
+      return fail(g, FVIB_EINVAL, "the wall model needs walls normal to y (n[1] >= 2), x and z periodic");
+    if (!(d->kappa > 0.0) || !std::isfinite(d->kappa) || !std::isfinite(d->B) ||
+        !(d->eps >= 0.0) || !std::isfinite(d->eps))
+      return fail(g, FVIB_EINVAL, "wall model: kappa > 0, finite B and eps >= 0 required");
+  }
+  const size_t es = g->esize();
+  const size_t nc = (size_t)g->ncell * es;
+  const size_t ne = (size_t)(g->n[0] + 1) * (g->n[1] + 1) * (g->n[2] + 1) * es;
+  bool ok = dmalloc(&g->les_nut, nc) == FVIB_OK;
+  for (int c = 0; c < 3; ++c) {
+    ok &= dmalloc(&g->les_g[c], (size_t)g->nface[c] * es) == FVIB_OK;
+    ok &= dmalloc(&g->les_gb[c], (size_t)g->nface[c] * es) == FVIB_OK;
+  }
+  for (void*& q : g->les_cell) ok &= dmalloc(&q, nc) == FVIB_OK;
+  for (void*& q : g->les_edge) ok &= dmalloc(&q, ne) == FVIB_OK;
+  ok &= dmalloc(&g->les_wall, 12 * (size_t)g->n[0] * g->n[2] * sizeof(double)) == FVIB_OK;
+  if (!ok) {
+    fvib_les_set(h, nullptr);
+    return fail(g, FVIB_ENOMEM, "device allocation of the LES workspace failed");
+  }
+  // edges never written by the adjoint passes (positions past a cell
+  // extent) are never read either; clear them once so the arrays hold no
+  // uninitialised values
+  for (void* q : g->les_edge) FVIB_HIP(hipMemsetAsync(q, 0, ne, g->stream));
+  FVIB_HIP(hipMemsetAsync(g->les_wall, 0, 12 * (size_t)g->n[0] * g->n[2] * sizeof(double),
+                          g->stream));
+  FVIB_HIP(hipStreamSynchronize(g->stream));
+  g->les = *d;
+  g->has_les = true;
   return FVIB_OK;
 }
 

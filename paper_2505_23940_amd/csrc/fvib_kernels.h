@@ -33,6 +33,43 @@ struct StageMix {
   double a, b;
 };
 
+// Large-eddy simulation terms on a 3D grid (k_les.hip): Smagorinsky
+// viscosity at cell centres, wall-model viscosity on the wall edges of the
+// y walls, and the adjoint work arrays.  Edge arrays use the lattice
+// (n0 + 1) x (n1 + 1) x (n2 + 1); edge type t = C + A - 1 for the plane of
+// axes C < A (0: x-y, 1: x-z, 2: y-z).
+template <typename T>
+struct LesView {
+  int wall;                  // wall model on (walls normal to y, x and z periodic)
+  T cs2;                     // C_s^2
+  double nu, kappa, B, eps;
+  double yw[2];              // matching distance: half height of the wall cells
+  double uw[2][3];           // wall velocity per side
+  T* nut;                    // cell nu_t
+  double* nuw[2][2];         // [0 u / 1 w][side], nz x nx: wall-edge viscosity
+  // adjoint
+  T* wcc[3];                 // cell: coefficient of d_c u_c
+  T* nbar;                   // cell: nu_t adjoint (normal-stress part)
+  T* soff[3];                // cell: strain adjoint of the off-diagonal entries
+  T* pe[3];                  // edge: coefficient of the symmetric gradient
+  T* qe[3];                  // edge: viscosity adjoint
+  double* wown[2][2];        // wall face: adjoint of its own velocity
+  double* woth[2][2];        // wall face: adjoint of the averaged other velocity
+};
+
+// Forward: nu_t, the wall viscosity and g_c = fb_c + div(2 nu_t S)_c on the
+// evolved faces (g_c = fb_c elsewhere; fb may be NULL).
+template <typename T>
+int launch_les_forward(const Geo<T>& G, const LesView<T>& L, const T* const u[3],
+                       const T* const fb[3], T* const g[3], hipStream_t s);
+// Adjoint: given gbar (this step's adjoint of g alone), add the subgrid
+// term's vector-Jacobian product to ubar and gbar to fbar (entries may be
+// NULL); recomputes nu_t and the wall viscosity.
+template <typename T>
+int launch_les_adjoint(const Geo<T>& G, const LesView<T>& L, const T* const u[3],
+                       const T* const gbar[3], T* const ubar[3], T* const fbar[3],
+                       hipStream_t s);
+
 // Static box on a 3D grid: windows and face-index ranges per component.
 struct BoxGeo {
   int bo[3][3];        // window origin, component c, axis a

@@ -1,0 +1,190 @@
+"""Large-eddy simulation through the C ABI (fvib_les_set): the constant
+Smagorinsky subgrid stress and the equilibrium wall model (Sec. 3.4.5,
+Eqs. 27-29) against the oracle (oracle/les.py): forward steps, one-step
+vector-Jacobian products, a rollout gradient, Runge-Kutta steps, and the
+set-up's argument checks."""
+import numpy as np
+import pytest
+import torch
+
+import fvib_workloads as W
+from gpu_util import gauge, make_grid, need_gpu, rel_l2
+from test_gpu_adjoint import _close
+
+pytestmark = pytest.mark.gpu
+F64 = torch.float64
+
+
+def _cases():
+    wm = W.wmles(n=16, steps=4, dt=1e-3)
+    # stretched walls, non-cubic cells, both models
+    ch = W.channel(nx=12, ny=14, nz=10, steps=4, dt=2e-4)
+    ch.nu = 1e-3
+    ch.les = {"cs": 0.17, "wall_model": True, "kappa": 0.4, "B": 5.0, "eps": 1e-6}
+    # periodic box, Smagorinsky only
+    n = 12
+    f = np.linspace(0, 2 * np.pi, n + 1)
+    pb = W.generic(3, (n, n, n), [f, f, np.linspace(0, 3.0, n + 1)],
+                   [["periodic", "periodic"]] * 3, nu=1e-3, dt=2e-3, steps=4)
+    pb.les = {"cs": 0.2, "wall_model": False, "kappa": 0.4, "B": 5.0, "eps": 1e-6}
+    return {"wmles": wm, "channel_les": ch, "periodic_les": pb}
+
+
+def _fields(w, seed):
+    u0, fb = W.initial_fields(w)
+    if w.bc[1][0] == "periodic":
+        u0 = W.random_fields(w, seed, 1.0)
+        fb = [np.full(x.shape, v) for x, v in zip(u0, (0.3, -0.2, 0.1))]
+    return u0, fb
+
+
+@pytest.mark.parametrize("case", list(_cases().keys()))
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_les_steps_match_oracle(case, precision):
+    need_gpu()
+    from oracle import Grid as OGrid
+    from oracle import init_state, make_params, rollout
+    w = _cases()[case]
+    u0, fb = _fields(w, 3)
+    og = OGrid(w)
+    with torch.no_grad():
+        st, _, _ = rollout(og, init_state(og, u0), make_params(og, fb), w.steps)
+    print(f"[les] {case} {precision}: oracle done", flush=True)
+    g = make_grid(w, precision=precision, poisson_tol=1e-12 if precision == "fp64" else 1e-9)
+    u, fbt, p = g.to_u(u0), g.to_u(fb), g.zeros_p()
+    for _ in range(w.steps):
+        g.step(u, p, fbt)
+    torch.cuda.synchronize()
+    gu = [x.double().cpu().numpy() for x in u]
+    eu = rel_l2(gu, [x.numpy() for x in st["u"]])
+    ep = rel_l2([gauge(p.cpu().numpy())], [st["p"].numpy()])
+    # the subgrid term must matter at this size: compare with a step without it
+    g0 = make_grid(w, precision=precision, poisson_tol=1e-12 if precision == "fp64" else 1e-9)
+    g0.set_les(None)
+    v, q = g0.to_u(u0), g0.zeros_p()
+    for _ in range(w.steps):
+        g0.step(v, q, g0.to_u(fb))
+    torch.cuda.synchronize()
+    dles = rel_l2([x.double().cpu().numpy() for x in v], gu)
+    print(f"{case} {precision}: u {eu:.2e} p {ep:.2e}; LES changes u by {dles:.2e}")
+    if precision == "fp64":
+        assert eu <= 1e-10 and ep <= 1e-8, (eu, ep)
+    else:
+        assert eu <= 1e-5, eu
+    assert dles > 100 * eu
+
+
+@pytest.mark.parametrize("case", list(_cases().keys()))
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_les_step_vjp(case, precision):
+    need_gpu()
+    from oracle import Grid as OGrid
+    from oracle import init_state, make_params, step
+    w = _cases()[case]
+    u0, fb = _fields(w, 5)
+    scale = max(float(np.abs(x).max()) for x in u0)
+    u = [a + 0.05 * scale * b for a, b in zip(u0, W.random_fields(w, 7))]
+    if w.bc[1][0] != "periodic":
+        for side in (0, -1):
+            u[1][:, side, :] = 0.0
+    ubar = W.random_fields(w, 8)
+    r32 = precision == "fp32"
+    cast = (lambda a: torch.tensor(a).float().double()) if r32 else (lambda a: torch.tensor(a))
+    if r32:
+        ubar = [np.asarray(x, dtype=np.float32).astype(np.float64) for x in ubar]
+    og = OGrid(w)
+    ut = [cast(x).requires_grad_(True) for x in u]
+    fbt = [cast(x).requires_grad_(True) for x in fb]
+    st, _ = step(og, init_state(og, ut), make_params(og, fbt))
+    L = sum((st["u"][i] * torch.tensor(ubar[i])).sum() for i in range(3))
+    L.backward()
+    print(f"[les] {case} {precision}: oracle VJP done", flush=True)
+    g = make_grid(w, precision=precision, poisson_tol=1e-12 if not r32 else 1e-9)
+    ub0, fbb = g.zeros_u(), g.zeros_u()
+    g.step_adjoint(g.to_u(u), g.to_u(fb), None, None, g.to_u(ubar), None, None, ub0, None,
+                   fbbar=fbb)
+    torch.cuda.synchronize()
+    tol = 1e-9 if not r32 else 2e-4
+    for i in range(3):
+        _close(ub0[i].double().cpu().numpy(), ut[i].grad.numpy(), tol, f"ubar[{i}]")
+        _close(fbb[i].double().cpu().numpy(), fbt[i].grad.numpy(), tol, f"fbbar[{i}]")
+    # without fbbar requested the velocity adjoint is the same
+    ub1 = g.zeros_u()
+    g.step_adjoint(g.to_u(u), g.to_u(fb), None, None, g.to_u(ubar), None, None, ub1, None)
+    torch.cuda.synchronize()
+    for i in range(3):
+        assert torch.equal(ub0[i], ub1[i])
+
+
+def test_les_rollout_gradient():
+    need_gpu()
+    from oracle import Grid as OGrid
+    from oracle import init_state, make_params, rollout
+    from oracle.step import wall_shear
+    from paper_2505_23940_amd.rollout import rollout as g_rollout
+    from paper_2505_23940_amd.rollout import wall_shear as g_wall_shear
+    w = _cases()["wmles"]
+    w.steps = 4
+    og = OGrid(w)
+    u0, fb = W.initial_fields(w)
+    fbt = [torch.tensor(x, requires_grad=True) for x in fb]
+    st, _, _ = rollout(og, init_state(og, u0), make_params(og, fbt), w.steps)
+    Jo = wall_shear(og, st["u"])
+    Jo.backward()
+    g = make_grid(w, precision="fp64", poisson_tol=1e-12)
+    fg = [x.requires_grad_(True) for x in g.to_u(fb)]
+    kc = torch.zeros(6, dtype=F64, device=g.device)
+    b0 = torch.zeros(6, dtype=F64, device=g.device)
+    uS, _, _, _ = g_rollout(g, g.to_u(u0), fg, kc, b0, w.steps, ckpt_every=2)
+    J = g_wall_shear(g, uS[0])
+    J.backward()
+    torch.cuda.synchronize()
+    assert abs(float(J.detach()) - float(Jo.detach())) <= 1e-10 * abs(float(Jo.detach()))
+    e = rel_l2([x.grad.double().cpu().numpy() for x in fg], [x.grad.numpy() for x in fbt])
+    print(f"wmles 16^3, 4 steps: dJ/dfb rel L2 {e:.2e}")
+    assert e <= 1e-8, e
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_les_rk3_matches_oracle(precision):
+    need_gpu()
+    from oracle import Grid as OGrid
+    from oracle import init_state, make_params
+    from oracle.rk import rollout_rk
+    w = _cases()["wmles"]
+    w.steps = 2
+    og = OGrid(w)
+    u0, fb = W.initial_fields(w)
+    with torch.no_grad():
+        st, _ = rollout_rk(og, init_state(og, u0), make_params(og, fb), w.steps, "rk3")
+    g = make_grid(w, precision=precision, poisson_tol=1e-12 if precision == "fp64" else 1e-9)
+    u, fbt, p = g.to_u(u0), g.to_u(fb), g.zeros_p()
+    for _ in range(w.steps):
+        g.step(u, p, fbt, scheme="rk3")
+    torch.cuda.synchronize()
+    e = rel_l2([x.double().cpu().numpy() for x in u], [x.numpy() for x in st["u"]])
+    print(f"wmles rk3 {precision}: u rel L2 {e:.2e}")
+    assert e <= (1e-10 if precision == "fp64" else 1e-5), e
+
+
+def test_les_setup_checks():
+    need_gpu()
+    from paper_2505_23940_amd import FvibError
+    f = np.linspace(0, 1, 9)
+    w2 = W.generic(2, (8, 8, 1), [f, f, f], [["periodic", "periodic"]] * 2)
+    g2 = make_grid(w2, precision="fp64")
+    with pytest.raises(FvibError):
+        g2.set_les(0.1)                                  # 2D
+    wi = W.generic(3, (8, 8, 8), [f, f, f], [["inflow", "outflow_conv"], ["noslip", "noslip"],
+                                             ["periodic", "periodic"]])
+    gi = make_grid(wi, precision="fp64")
+    with pytest.raises(FvibError):
+        gi.set_les(0.1)                                  # inflow axis
+    wp = W.generic(3, (8, 8, 8), [f, f, f], [["periodic", "periodic"]] * 3)
+    gp = make_grid(wp, precision="fp64")
+    with pytest.raises(FvibError):
+        gp.set_les(0.1, wall_model=True)                 # no y walls
+    with pytest.raises(FvibError):
+        gp.set_les(-0.1)
+    gp.set_les(0.1)
+    gp.set_les(None)
