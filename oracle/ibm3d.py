@@ -1,6 +1,6 @@
-"""Static immersed bodies on 3D grids: axis-aligned boxes (the paper's
-wall-mounted cube, Sec. 3.4.2) forced by the direct-forcing IBM of
-Sec. 2.2 and Eq. 5.
+"""Static immersed bodies on 3D grids: axis-aligned boxes (the cubic
+roughness elements on the channel wall of Sec. 3.4.2) forced by the
+direct-forcing IBM (Sec. 2.3.1, Eq. 5; point classes of Sec. 2.2, Fig. 2).
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -11,7 +11,10 @@ Readings taken here:
   y0 <= y < y1, z0 <= z < z1 (the rule the 2D crossing-number test gives a
   rectangle); it is an immersed-boundary point if it is not solid and one of
   its six axis neighbours on the same component grid is solid (neighbours
-  outside the array are not solid); forced = solid or IB;
+  outside the array are not solid); forced = (solid or IB) and advanced by
+  the momentum equation: a boundary-normal face of a bounded axis keeps its
+  boundary condition (Eq. 4 is not solved there, so Eq. 5 cannot force it),
+  which matters for a body standing on a wall (the cubes of Sec. 3.4.2);
 * the body is at rest: target and solid velocities are zero on every
   forced face;
 * there are no Lagrangian markers on a 3D body, so the force on it is the
@@ -46,7 +49,7 @@ def classify_box(g: Grid, lo, hi):
         b = (~s) & nb
         solid.append(torch.tensor(s))
         ib.append(torch.tensor(b))
-        eps.append(torch.tensor(s | b))
+        eps.append(torch.tensor(s | b) & g.evolved(c))
     return solid, ib, eps
 
 

@@ -88,6 +88,33 @@ def test_force_from_rest_closed_form():
         assert int(aux["eps"][c].sum()) == count
 
 
+def test_force_from_rest_box_on_wall():
+    """A box standing on the lower wall (the roughness cubes of Sec. 3.4.2):
+    the six-neighbour shell has no layer below the wall, and the wall-normal
+    faces on the wall keep their boundary condition, so they are not forced."""
+    n, L = 16, 2.0
+    h = L / n
+    f = np.linspace(0, L, n + 1)
+    bc = [["periodic", "periodic"], ["noslip", "noslip"], ["periodic", "periodic"]]
+    w = W.generic(3, (n, n, n), [f, f, f], bc, nu=0.05, dt=1e-3)
+    i0, i1, j1, k0, k1 = 5, 9, 4, 3, 7
+    w.box = (((i0 - 0.25) * h, -0.5, (k0 - 0.25) * h), ((i1 - 0.25) * h, (j1 - 0.25) * h,
+                                                       (k1 - 0.25) * h))
+    g = Grid(w)
+    fb_c = (0.7, -0.4, 1.3)
+    fb = [np.full(g.face_shape(c), fb_c[c]) for c in range(3)]
+    u0 = [np.zeros(g.face_shape(c)) for c in range(3)]
+    with torch.no_grad():
+        _, aux = step(g, init_state(g, u0), make_params(g, fb))
+    nx_, ny_, nz_ = i1 - i0, j1, k1 - k0
+    total = nx_ * ny_ * nz_ + 2 * ny_ * nz_ + 2 * nx_ * ny_ + nx_ * nz_
+    count = [total, total - (nx_ * nz_ + 2 * nz_ + 2 * nx_), total]
+    for c in range(3):
+        exact = w.rho * fb_c[c] * h ** 3 * count[c]
+        assert int(aux["eps"][c].sum()) == count[c], (c, int(aux["eps"][c].sum()), count[c])
+        assert abs(float(aux["F"][c]) - exact) <= 1e-12 * abs(exact), (c, float(aux["F"][c]), exact)
+
+
 def test_divergence_free_with_box():
     w = W.channel(nx=16, ny=12, nz=10, steps=1, dt=1e-5)
     w.box = ((2.0, -0.5, 1.0), (3.2, 0.3, 2.2))
