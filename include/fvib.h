@@ -199,17 +199,19 @@ int fvib_field_layout(const fvib_grid *g, int comp, int64_t shape[3],
  * rebuilt inside fvib_step from the displacement in the body state. */
 int fvib_ib_set_body(fvib_grid *g, const fvib_body_desc *body);
 
-/* Attach a static immersed box to a 3D grid (the paper's wall-mounted cube,
- * Sec. 3.4.2, with the direct-forcing IBM of Sec. 2.2 and Eq. 5); lo = NULL
- * removes it.  lo, hi (host, 3 doubles): the box [lo, hi) per axis.  Point
- * classes per velocity component on its own face points: solid in the
- * half-open box, immersed-boundary point when a six-neighbour is solid;
- * both forced to zero velocity (the body is at rest).  The force reported
- * in fvib_step_info.force is the momentum the forcing removes from the
- * fluid, -rho sum f dv over the forced faces (a 3D body has no Lagrangian
- * markers); fvib_step_adjoint's dF is its adjoint.  The box must stay two
- * faces away from bounded boundaries, and on a periodic axis either span
- * it or stay off its seam (face points 0 and n-1).  No body state: fields.body may be
+/* Attach a static immersed box to a 3D grid (the cubic roughness elements
+ * standing on the channel wall of Sec. 3.4.2, with the direct forcing of
+ * Sec. 2.3.1, Eq. 5, and the point classes of Sec. 2.2, Fig. 2); lo = NULL
+ * removes it.  lo, hi (host, 3 doubles): the box [lo, hi) per axis; it may
+ * reach through a wall.  Point classes per velocity component on its own
+ * face points: solid in the half-open box, immersed-boundary point when a
+ * six-neighbour is solid; both forced to zero velocity (the body is at
+ * rest), except boundary-normal faces of bounded axes, which keep their
+ * boundary condition.  The force reported in fvib_step_info.force is the
+ * momentum the forcing removes from the fluid, -rho sum f dv over the
+ * forced faces (a 3D body has no Lagrangian markers); fvib_step_adjoint's
+ * dF is its adjoint.  On a periodic axis the box either spans the axis or
+ * stays off its seam (face points 0 and n-1).  No body state: fields.body may be
  * NULL.  FVIB_ESTATE if a marker body is attached (and
  * fvib_ib_set_body fails while a box is). */
 int fvib_ib_set_box(fvib_grid *g, const double *lo, const double *hi);

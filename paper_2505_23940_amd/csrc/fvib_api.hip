@@ -1997,8 +1997,6 @@ int fvib_ib_set_box(fvib_grid* h, const double* lo, const double* hi) {
       if (s0 >= s1) any = false;
       B.bs[c][a][0] = s0;
       B.bs[c][a][1] = s1;
-      if (!g->per[a] && (s0 < 2 || s1 > ext - 2))
-        return fail(g, FVIB_EINVAL, "the box must stay two faces away from a bounded boundary");
       if (g->per[a] && s0 < s1 && (s0 == 0) != (s1 == ext))
         return fail(g, FVIB_EINVAL, "a box on the periodic seam must span the periodic axis");
       const int o = std::max(0, s0 - 1), e = std::min(ext, s1 + 1);
@@ -2007,6 +2005,10 @@ int fvib_ib_set_box(fvib_grid* h, const double* lo, const double* hi) {
     }
   }
   if (!any) return fail(g, FVIB_EINVAL, "the box contains no face point of some component");
+  for (int a = 0; a < 3; ++a) {
+    B.per[a] = g->per[a];
+    B.nc[a] = g->n[a];
+  }
   const size_t es = g->esize();
   for (int c = 0; c < 3; ++c) {
     const size_t n = (size_t)B.bw[c][0] * B.bw[c][1] * B.bw[c][2];

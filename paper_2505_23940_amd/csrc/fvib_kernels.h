@@ -75,6 +75,8 @@ struct BoxGeo {
   int bo[3][3];        // window origin, component c, axis a
   int bw[3][3];        // window extent
   int bs[3][3][2];     // solid face-index range [bs0, bs1) per axis
+  int per[3];          // periodic axes
+  int nc[3];           // cells per axis (the last face index of a bounded own axis)
   uint8_t* cls[3];     // forced flags of the window faces
 };
 int launch_box_classify(const BoxGeo& B, hipStream_t s);

@@ -245,7 +245,9 @@ __global__ void __launch_bounds__(kBlock) k_box_classify(BoxGeo B) {
       const bool solid = in[0] && in[1] && in[2];
       const bool ibp = !solid && ((near[0] && in[1] && in[2]) || (in[0] && near[1] && in[2]) ||
                                   (in[0] && in[1] && near[2]));
-      B.cls[c][l] = (solid || ibp) ? 1 : 0;
+      // a boundary-normal face keeps its boundary condition: never forced
+      const bool bnd = !B.per[c] && (I[c] == 0 || I[c] == B.nc[c]);
+      B.cls[c][l] = ((solid || ibp) && !bnd) ? 1 : 0;
     }
   }
 }
