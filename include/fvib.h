@@ -237,7 +237,7 @@ typedef struct {
  * (Eq. 27) at the half height of the wall cell, tau_w = u_tau^2 split by
  * Eq. 29 (kinematic stress), the other tangential component averaged from
  * its four nearest faces.  FVIB_EINVAL for a grid or a descriptor outside
- * these rules; allocates its workspace (about 20 cell-sized arrays). */
+ * these rules; allocates its workspace (about 25 cell-sized arrays). */
 int fvib_les_set(fvib_grid *g, const fvib_les_desc *d);
 
 /* One weakly coupled time step (Alg. 1 with N = 1): classification and

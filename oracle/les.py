@@ -141,9 +141,11 @@ def spalding_uplus(re: torch.Tensor, kappa: float = 0.4, B: float = 5.0) -> torc
     in the log layer (h ~ kappa e^t), so the iteration needs few steps.  It
     starts from the upper end of the bracket t in [t_hi - 80, t_hi],
     t_hi = min(ln sqrt(Re), ln 200) (u+ <= sqrt(Re) because y+ >= u+); a
-    step leaving the current bracket is replaced by bisection.  The root is
-    found without gradients; one Newton step from it with gradients then
-    carries the implicit-function derivative dt/dRe = -h_Re / h_t."""
+    step leaving the current bracket is replaced by bisection, and the
+    iteration stops once a step is below 1e-13.  The root is found without
+    gradients; one more Newton step from it, with gradients, brings it to
+    rounding level (quadratic convergence) and carries the implicit-function
+    derivative dt/dRe = -h_Re / h_t."""
     with torch.no_grad():
         lre = torch.log(re.detach())
         hi = torch.clamp(0.5 * lre, max=math.log(200.0))
@@ -156,7 +158,7 @@ def spalding_uplus(re: torch.Tensor, kappa: float = 0.4, B: float = 5.0) -> torc
             tn = t - h / dh
             bad = (tn <= lo) | (tn >= hi)
             tn = torch.where(bad, 0.5 * (lo + hi), tn)
-            done = bool(((tn - t).abs() <= 1e-15).all())
+            done = bool(((tn - t).abs() <= 1e-13).all())
             t = tn
             if done:
                 break

@@ -177,8 +177,9 @@ struct Grid {
   void* les_g[3] = {nullptr, nullptr, nullptr};
   void* les_gb[3] = {nullptr, nullptr, nullptr};
   void* les_cell[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  void* les_edge[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  double* les_wall = nullptr;     // 12 slabs of nz x nx: nuw, wown, woth per [comp][side]
+  void* les_edge[9] = {nullptr, nullptr, nullptr, nullptr, nullptr,
+                       nullptr, nullptr, nullptr, nullptr};
+  double* les_wall = nullptr;     // 20 slabs of nz x nx: nuw, wown, woth, u+, du+/dRe per [comp][side]
   // immersed body
   bool has_body = false;
   IbGeo ib;
@@ -863,12 +864,15 @@ static LesView<T> les_view(Grid* g) {
       v.nuw[c][s] = g->les_wall + (0 + 2 * c + s) * slab;
       v.wown[c][s] = g->les_wall + (4 + 2 * c + s) * slab;
       v.woth[c][s] = g->les_wall + (8 + 2 * c + s) * slab;
+      v.upl[c][s] = g->les_wall + (12 + 2 * c + s) * slab;
+      v.dupl[c][s] = g->les_wall + (16 + 2 * c + s) * slab;
     }
   for (int c = 0; c < 3; ++c) {
     v.wcc[c] = (T*)g->les_cell[c];
     v.soff[c] = (T*)g->les_cell[3 + c];
     v.pe[c] = (T*)g->les_edge[c];
     v.qe[c] = (T*)g->les_edge[3 + c];
+    v.ge[c] = (T*)g->les_edge[6 + c];
   }
   v.nbar = (T*)g->les_cell[6];
   return v;
@@ -2066,7 +2070,7 @@ int fvib_les_set(fvib_grid* h, const fvib_les_desc* d) {
   }
   for (void*& q : g->les_cell) ok &= dmalloc(&q, nc) == FVIB_OK;
   for (void*& q : g->les_edge) ok &= dmalloc(&q, ne) == FVIB_OK;
-  ok &= dmalloc(&g->les_wall, 12 * (size_t)g->n[0] * g->n[2] * sizeof(double)) == FVIB_OK;
+  ok &= dmalloc(&g->les_wall, 20 * (size_t)g->n[0] * g->n[2] * sizeof(double)) == FVIB_OK;
   if (!ok) {
     fvib_les_set(h, nullptr);
     return fail(g, FVIB_ENOMEM, "device allocation of the LES workspace failed");
@@ -2075,7 +2079,7 @@ int fvib_les_set(fvib_grid* h, const fvib_les_desc* d) {
   // extent) are never read either; clear them once so the arrays hold no
   // uninitialised values
   for (void* q : g->les_edge) FVIB_HIP(hipMemsetAsync(q, 0, ne, g->stream));
-  FVIB_HIP(hipMemsetAsync(g->les_wall, 0, 12 * (size_t)g->n[0] * g->n[2] * sizeof(double),
+  FVIB_HIP(hipMemsetAsync(g->les_wall, 0, 20 * (size_t)g->n[0] * g->n[2] * sizeof(double),
                           g->stream));
   FVIB_HIP(hipStreamSynchronize(g->stream));
   g->les = *d;

@@ -47,6 +47,9 @@ struct LesView {
   double uw[2][3];           // wall velocity per side
   T* nut;                    // cell nu_t
   double* nuw[2][2];         // [0 u / 1 w][side], nz x nx: wall-edge viscosity
+  double* upl[2][2];         // u+ of the wall faces (kept for the adjoint)
+  double* dupl[2][2];        // du+/dRe there
+  T* ge[3];                  // edge: symmetric velocity gradient d_a u_c + d_c u_a
   // adjoint
   T* wcc[3];                 // cell: coefficient of d_c u_c
   T* nbar;                   // cell: nu_t adjoint (normal-stress part)

@@ -132,10 +132,11 @@ __device__ __forceinline__ T edge_nu(const Geo<T>& G, const LesView<T>& L, const
   return T(0.25) * s;
 }
 
-// Cell strain: diagonal and the three off-diagonal entries (x-y, x-z, y-z).
+// Cell strain: diagonal and the three off-diagonal entries (x-y, x-z, y-z),
+// the latter from the edge gradients stored by k_les_grad.
 template <typename T>
-__device__ __forceinline__ void cell_strain(const Geo<T>& G, const U3<T>& u, int i, int j, int k,
-                                            T sd[3], T so[3]) {
+__device__ __forceinline__ void cell_strain(const Geo<T>& G, const LesView<T>& L, const U3<T>& u,
+                                            int i, int j, int k, T sd[3], T so[3]) {
   const int P0[3] = {i, j, k};
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -155,9 +156,9 @@ __device__ __forceinline__ void cell_strain(const Geo<T>& G, const U3<T>& u, int
       const int E01[3] = {i + p, j + q, k};
       const int E02[3] = {i + p, j, k + q};
       const int E12[3] = {i, j + p, k + q};
-      s01 += edge_grad<0, 1>(G, u, E01);
-      s02 += edge_grad<0, 2>(G, u, E02);
-      s12 += edge_grad<1, 2>(G, u, E12);
+      s01 += L.ge[0][eidx(G, E01)];
+      s02 += L.ge[1][eidx(G, E02)];
+      s12 += L.ge[2][eidx(G, E12)];
     }
   so[0] = T(0.125) * s01;
   so[1] = T(0.125) * s02;
@@ -177,7 +178,8 @@ __device__ __forceinline__ T delta2(const Geo<T>& G, int i, int j, int k) {
 // Re), from the upper end of the bracket [t_hi - 80, t_hi], t_hi =
 // min(ln sqrt(Re), ln 200) (y+ >= u+ puts the root below sqrt(Re)); a step
 // leaving the bracket is replaced by bisection; one last Newton step once
-// the step falls under 1e-15.  du+/dRe = 1 / (y+ + u+ dy+/du+), from
+// the step falls under 1e-13 (Newton's quadratic convergence then leaves
+// the root at rounding level).  du+/dRe = 1 / (y+ + u+ dy+/du+), from
 // differentiating Re = u+ y+(u+).
 __device__ double spalding_uplus(double re, double kappa, double B, double* dup_dre) {
   const double lre = log(re);
@@ -197,7 +199,7 @@ __device__ double spalding_uplus(double re, double kappa, double B, double* dup_
     if (h > 0.0) hi = t;
     double tn = t - h / dh;
     if (tn <= lo || tn >= hi) tn = 0.5 * (lo + hi);
-    const bool done = fabs(tn - t) <= 1e-15;
+    const bool done = fabs(tn - t) <= 1e-13;
     t = tn;
     if (done) break;
   }
@@ -234,17 +236,22 @@ __device__ __forceinline__ void wall_pair(const Geo<T>& G, const LesView<T>& L, 
   }
 }
 
+// u+ (Eq. 27) at tangential speed U > 0 and du+/dRe.
+template <typename T>
+__device__ __forceinline__ double wall_uplus(const LesView<T>& L, int side, double U, double* dup) {
+  return spalding_uplus(U * L.yw[side] / L.nu, L.kappa, L.B, dup);
+}
+
 // Wall-edge viscosity (Eq. 28) and its partial derivatives in the own and
-// the other velocity.
+// the other velocity, given u+ and du+/dRe at U = |(own, oth)| (unused
+// when U = 0: no stress).
 template <typename T>
 __device__ __forceinline__ double wall_nu(const LesView<T>& L, int side, double own, double oth,
-                                          double* d_own, double* d_oth) {
+                                          double up, double dup, double* d_own, double* d_oth) {
   const double y = L.yw[side];
   const double U = sqrt(own * own + oth * oth);
   double taui = 0.0, dti_own = 0.0, dti_oth = 0.0;
   if (U > 0.0) {
-    double dup;
-    const double up = spalding_uplus(U * y / L.nu, L.kappa, L.B, &dup);
     const double tau = (U / up) * (U / up);
     // d tau / dU with u+ = u+(U y / nu)
     const double dtau = 2.0 * U / (up * up) - 2.0 * U * U / (up * up * up) * dup * (y / L.nu);
@@ -260,6 +267,28 @@ __device__ __forceinline__ double wall_nu(const LesView<T>& L, int side, double 
 }
 
 // ----------------------------------------------------------------- forward
+template <int C, int A, typename T>
+__device__ __forceinline__ void store_grad(const Geo<T>& G, const LesView<T>& L, const U3<T>& u,
+                                           const int E[3]) {
+  constexpr int B = 3 - C - A;
+  if (E[B] >= G.n[B]) return;
+  L.ge[C + A - 1][eidx(G, E)] = edge_grad<C, A>(G, u, E);
+}
+
+// Edge gradients of the three planes on the whole edge lattice.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_les_grad(Geo<T> G, LesView<T> L, U3<T> u) {
+  const int l0 = G.n[0] + 1, l1 = G.n[1] + 1;
+  const int64_t n = (int64_t)l0 * l1 * (G.n[2] + 1);
+  for (int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x; id < n;
+       id += (int64_t)gridDim.x * kBlock) {
+    const int E[3] = {(int)(id % l0), (int)((id / l0) % l1), (int)(id / ((int64_t)l0 * l1))};
+    store_grad<0, 1>(G, L, u, E);
+    store_grad<0, 2>(G, L, u, E);
+    store_grad<1, 2>(G, L, u, E);
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_les_nut(Geo<T> G, LesView<T> L, U3<T> u) {
   const int64_t n = (int64_t)G.n[0] * G.n[1] * G.n[2];
@@ -269,7 +298,7 @@ __global__ void __launch_bounds__(kBlock) k_les_nut(Geo<T> G, LesView<T> L, U3<T
     const int j = (int)((id / G.n[0]) % G.n[1]);
     const int k = (int)(id / ((int64_t)G.n[0] * G.n[1]));
     T sd[3], so[3];
-    cell_strain(G, u, i, j, k, sd, so);
+    cell_strain(G, L, u, i, j, k, sd, so);
     const T ss = sd[0] * sd[0] + sd[1] * sd[1] + sd[2] * sd[2] +
                  T(2) * (so[0] * so[0] + so[1] * so[1] + so[2] * so[2]);
     L.nut[id] = L.cs2 * delta2(G, i, j, k) * sqrt(T(2) * ss);
@@ -286,17 +315,21 @@ __global__ void __launch_bounds__(kBlock) k_les_wall(Geo<T> G, LesView<T> L, U3<
     const int k = (int)((id / nx) % nz);
     const int side = (int)((id / ((int64_t)nx * nz)) % 2);
     const int comp = (int)(id / (2 * (int64_t)nx * nz));
-    double own, oth, d1, d2;
+    double own, oth, d1, d2, dup = 0.0, up = 1.0;
     wall_pair(G, L, u, comp, side, i, k, &own, &oth);
-    L.nuw[comp][side][(int64_t)k * nx + i] = wall_nu(L, side, own, oth, &d1, &d2);
+    const double U = sqrt(own * own + oth * oth);
+    if (U > 0.0) up = wall_uplus(L, side, U, &dup);
+    const int64_t w = (int64_t)k * nx + i;
+    L.upl[comp][side][w] = up;       // kept for the adjoint of this state
+    L.dupl[comp][side][w] = dup;
+    L.nuw[comp][side][w] = wall_nu(L, side, own, oth, up, dup, &d1, &d2);
   }
 }
 
 template <int C, int A, typename T>
-__device__ __forceinline__ T shear(const Geo<T>& G, const LesView<T>& L, const U3<T>& u,
-                                   const int E[3]) {
+__device__ __forceinline__ T shear(const Geo<T>& G, const LesView<T>& L, const int E[3]) {
   constexpr int lo = C < A ? C : A, hi = C < A ? A : C;
-  return edge_nu<lo, hi>(G, L, E) * edge_grad<lo, hi>(G, u, E);
+  return edge_nu<lo, hi>(G, L, E) * L.ge[lo + hi - 1][eidx(G, E)];
 }
 
 template <int C, typename T>
@@ -331,12 +364,12 @@ k_les_force(Geo<T> G, LesView<T> L, U3<T> u, const T* __restrict__ fb, T* __rest
     {
       int Eh[3] = {F[0], F[1], F[2]};
       Eh[A1] += 1;
-      D += (shear<C, A1>(G, L, u, Eh) - shear<C, A1>(G, L, u, F)) * idx(G, A1, F[A1]);
+      D += (shear<C, A1>(G, L, Eh) - shear<C, A1>(G, L, F)) * idx(G, A1, F[A1]);
     }
     {
       int Eh[3] = {F[0], F[1], F[2]};
       Eh[A2] += 1;
-      D += (shear<C, A2>(G, L, u, Eh) - shear<C, A2>(G, L, u, F)) * idx(G, A2, F[A2]);
+      D += (shear<C, A2>(G, L, Eh) - shear<C, A2>(G, L, F)) * idx(G, A2, F[A2]);
     }
     g[id] = base + D;
   }
@@ -382,7 +415,7 @@ __device__ __forceinline__ void site_edge(const Geo<T>& G, const LesView<T>& L, 
   const T tb = edge_tbar<C, A>(G, gb, E);
   const int64_t e = eidx(G, E);
   L.pe[C + A - 1][e] = tb * edge_nu<C, A>(G, L, E);
-  L.qe[C + A - 1][e] = tb * edge_grad<C, A>(G, u, E);
+  L.qe[C + A - 1][e] = tb * L.ge[C + A - 1][e];
 }
 
 // Pass 1 over the lattice: cells (normal stresses) and edges.
@@ -453,7 +486,7 @@ __global__ void __launch_bounds__(kBlock) k_les_adj_cells(Geo<T> G, LesView<T> L
                                          cell_edge_qsum<0, 2>(G, L, i, j, k) +
                                          cell_edge_qsum<1, 2>(G, L, i, j, k));
     T sd[3], so[3];
-    cell_strain(G, u, i, j, k, sd, so);
+    cell_strain(G, L, u, i, j, k, sd, so);
     const T ss = sd[0] * sd[0] + sd[1] * sd[1] + sd[2] * sd[2] +
                  T(2) * (so[0] * so[0] + so[1] * so[1] + so[2] * so[2]);
     const T mag = sqrt(T(2) * ss);
@@ -481,8 +514,8 @@ __global__ void __launch_bounds__(kBlock) k_les_adj_wall(Geo<T> G, LesView<T> L,
     const double nub = (double)L.qe[comp == 0 ? 0 : 2][eidx(G, E)];
     double own, oth, dn_own, dn_oth;
     wall_pair(G, L, u, comp, side, i, k, &own, &oth);
-    (void)wall_nu(L, side, own, oth, &dn_own, &dn_oth);
     const int64_t w = (int64_t)k * nx + i;
+    (void)wall_nu(L, side, own, oth, L.upl[comp][side][w], L.dupl[comp][side][w], &dn_own, &dn_oth);
     L.wown[comp][side][w] = nub * dn_own;
     L.woth[comp][side][w] = nub * dn_oth;
   }
@@ -604,6 +637,9 @@ int launch_les_forward(const Geo<T>& G, const LesView<T>& L, const T* const u[3]
                        const T* const fb[3], T* const g[3], hipStream_t s) {
   const U3<T> U{{u[0], u[1], u[2]}};
   const int64_t nc = (int64_t)G.n[0] * G.n[1] * G.n[2];
+  const int64_t nl = (int64_t)(G.n[0] + 1) * (G.n[1] + 1) * (G.n[2] + 1);
+  launch_kernel(k_les_grad<T>, dim3(grid_for(nl)), dim3(kBlock), 0, s, G, L, U);
+  FVIB_HIP(hipGetLastError());
   launch_kernel(k_les_nut<T>, dim3(grid_for(nc)), dim3(kBlock), 0, s, G, L, U);
   FVIB_HIP(hipGetLastError());
   if (L.wall) {
@@ -632,6 +668,8 @@ int launch_les_adjoint(const Geo<T>& G, const LesView<T>& L, const T* const u[3]
   const int64_t nc = (int64_t)G.n[0] * G.n[1] * G.n[2];
   const int64_t nl = (int64_t)(G.n[0] + 1) * (G.n[1] + 1) * (G.n[2] + 1);
   const int64_t nw = 4 * (int64_t)G.n[0] * G.n[2];
+  launch_kernel(k_les_grad<T>, dim3(grid_for(nl)), dim3(kBlock), 0, s, G, L, U);
+  FVIB_HIP(hipGetLastError());
   launch_kernel(k_les_nut<T>, dim3(grid_for(nc)), dim3(kBlock), 0, s, G, L, U);
   FVIB_HIP(hipGetLastError());
   if (L.wall) {
