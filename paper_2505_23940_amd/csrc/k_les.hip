@@ -175,16 +175,34 @@ __device__ __forceinline__ T delta2(const Geo<T>& G, int i, int j, int k) {
 // ------------------------------------------------------------ Spalding law
 // u+ of Eq. 27 for Re = U y / nu > 0 (u+ below 200), and du+/dRe.
 // Newton-Raphson on h(t) = t + ln y+(e^t) - ln Re with t = ln u+ (u+ y+ =
-// Re), from the upper end of the bracket [t_hi - 80, t_hi], t_hi =
-// min(ln sqrt(Re), ln 200) (y+ >= u+ puts the root below sqrt(Re)); a step
-// leaving the bracket is replaced by bisection; one last Newton step once
-// the step falls under 1e-13 (Newton's quadratic convergence then leaves
-// the root at rounding level).  du+/dRe = 1 / (y+ + u+ dy+/du+), from
-// differentiating Re = u+ y+(u+).
+// Re): first in float from the upper end of the bracket [t_hi - 80, t_hi],
+// t_hi = min(ln sqrt(Re), ln 200) (y+ >= u+ puts the root below sqrt(Re)),
+// a step leaving the bracket replaced by bisection, until |h| or a step is
+// below about 2e-5 (h' >= 1, so t is then that close to the root); then
+// three Newton steps in double.  du+/dRe = 1 / (y+ + u+ dy+/du+),
+// from differentiating Re = u+ y+(u+).
 __device__ double spalding_uplus(double re, double kappa, double B, double* dup_dre) {
   const double lre = log(re);
   const double e = exp(-kappa * B);
-  double hi = fmin(0.5 * lre, log(200.0)), lo = hi - 80.0, t = hi;
+  // bracketed phase in float (hardware exp / log): the root to ~1e-6 in t
+  const float lref = (float)lre, kf = (float)kappa, ef = (float)e;
+  float hi = fminf(0.5f * lref, 5.298317f), lo = hi - 80.0f, tf = hi;    // ln 200
+  for (int it = 0; it < 100; ++it) {
+    const float up = __expf(tf), k = kf * up, ek = __expf(k);
+    const float yp = up + ef * (ek - 1.0f - k - 0.5f * k * k - k * k * k * (1.0f / 6.0f));
+    const float dyp = 1.0f + ef * kf * (ek - 1.0f - k - 0.5f * k * k);
+    const float h = tf + __logf(yp) - lref, dh = 1.0f + up * dyp / yp;
+    if (fabsf(h) <= 3e-5f) break;      // dh >= 1: within 3e-5 of the root
+    if (h < 0.0f) lo = tf;
+    if (h > 0.0f) hi = tf;
+    float tn = tf - h / dh;
+    if (!(tn > lo && tn < hi)) tn = 0.5f * (lo + hi);
+    const bool done = fabsf(tn - tf) <= 2e-5f;
+    tf = tn;
+    if (done) break;
+  }
+  // Newton in double from there: quadratic convergence takes the 1e-6
+  // start to rounding level in two steps; a third confirms it
   auto eval = [&](double tt, double* h, double* dh) {
     const double up = exp(tt), k = kappa * up, ek = exp(k);
     const double yp = up + e * (ek - 1.0 - k - 0.5 * k * k - k * k * k / 6.0);
@@ -192,20 +210,12 @@ __device__ double spalding_uplus(double re, double kappa, double B, double* dup_
     *h = tt + log(yp) - lre;
     *dh = 1.0 + up * dyp / yp;
   };
-  for (int it = 0; it < 200; ++it) {
+  double t = tf;
+  for (int it = 0; it < 3; ++it) {
     double h, dh;
     eval(t, &h, &dh);
-    if (h < 0.0) lo = t;
-    if (h > 0.0) hi = t;
-    double tn = t - h / dh;
-    if (tn <= lo || tn >= hi) tn = 0.5 * (lo + hi);
-    const bool done = fabs(tn - t) <= 1e-13;
-    t = tn;
-    if (done) break;
+    t -= h / dh;
   }
-  double h, dh;
-  eval(t, &h, &dh);
-  t -= h / dh;
   const double up = exp(t), k = kappa * up, ek = exp(k);
   const double yp = up + e * (ek - 1.0 - k - 0.5 * k * k - k * k * k / 6.0);
   const double dyp = 1.0 + e * kappa * (ek - 1.0 - k - 0.5 * k * k);
