@@ -58,25 +58,46 @@ def kernel_cost(d: int, s: int, mixed: bool, n: tuple, solver: str = "fdm"):
         "fdm_last": ("flops", 4 * n[2 if d == 3 else 1]),
         "fft": ("bytes", 2 * v),                           # read and write one vector
         "fft_acc": ("bytes", v + 16),                      # read d; read and write p
+        # subgrid model (all passes of one step): nu_t (read u, write nu_t),
+        # stress divergence (read u, nu_t, f_b; write g)
+        "les": ("bytes", (d + 1) * s + (2 * d + 1 + d) * s),
+        # its adjoint: nu_t again; sites (read u, gbar, nu_t; write 3 + 1 + 6);
+        # cells (read nbar, 3 q, u; rw 3 w; write 3 s); edges (rw 3 p; read
+        # 3 s); faces (read 3 w, 3 p, gbar; rw ubar, fbbar)
+        "adj_les": ("bytes", (d + 1) * s + (2 * d + 1 + 10) * s + (1 + 3 + d + 6 + 3) * s
+                    + 9 * s + (3 + 3 + 1 + 4) * s),
     }
 
 
 def other_workloads(precision, tol, solver, steps=20):
-    """Mcell-updates/s of the other four workloads at their full sizes, same
+    """Mcell-updates/s of the other workloads at their full sizes, same
     precision and solver: forward + adjoint (K = 1) and forward only, over
-    `steps` steps after a warm-up of the same length."""
+    `steps` steps after a warm-up of the same length.  Besides the five
+    workloads: the channel with third-order Runge-Kutta steps, the channel
+    with a roughness cube on its floor, and the 2-DOF VIV case strongly
+    coupled (sub-iterations to a coupling error of 1e-5, at most 100)."""
     import fvib_workloads as W
     res = {}
-    for name in ("tgv2d", "tgv3d", "cylinder", "viv"):
-        w = W.by_name(name, "full")
+    cases = [(n, W.by_name(n, "full"), None, None)
+             for n in ("tgv2d", "tgv3d", "cylinder", "viv", "wmles")]
+    cases.append(("channel_rk3", W.channel(), "rk3", None))
+    cases.append(("channel_cube", channel_cube(), None, None))
+    wv = W.viv(dof=2, coupling_iters=100, coupling_tol=1e-5)
+    cases.append(("viv_2dof_strong", wv, None, (100, 1e-5)))
+    for name, w, scheme, coupling in cases:
         g, ut, fbt, body, kc = setup(w, precision, tol, solver)
-        fwd_adj_pass(g, w, ut, fbt, body, kc, steps, 1)
-        el, _ = timed(lambda: fwd_adj_pass(g, w, ut, fbt, body, kc, steps, 1))
-        elf, info = timed(lambda: fwd_pass(g, ut, fbt, body, kc, steps))
+        fwd_adj_pass(g, w, ut, fbt, body, kc, steps, 1, scheme, coupling)
+        el, _ = timed(lambda: fwd_adj_pass(g, w, ut, fbt, body, kc, steps, 1, scheme, coupling))
+        elf, info = timed(lambda: fwd_pass(g, ut, fbt, body, kc, steps, scheme, coupling))
         g.check_infos(info, "forward step")
         res[name] = {"cells": w.ncells, "steps": steps,
                      "fwd_adj_value": round(w.ncells * steps / el / 1e6, 3),
                      "fwd_value": round(w.ncells * steps / elf / 1e6, 3)}
+        if coupling is not None:
+            from paper_2505_23940_amd import parse_info
+            recs = parse_info(info)
+            res[name]["coupling_iters_per_step"] = round(
+                sum(r["coupling_iters"] for r in recs) / len(recs), 2)
         print(f"[bench] {name}: fwd+adj {res[name]['fwd_adj_value']} Mcell/s, "
               f"fwd {res[name]['fwd_value']} Mcell/s", file=sys.stderr, flush=True)
         del g
@@ -105,7 +126,17 @@ def make_workload(name):
     import fvib_workloads as W
     if name == "channel":
         return W.channel()
+    if name == "channel_cube":
+        return channel_cube()
     return W.by_name(name, "full")
+
+
+def channel_cube():
+    """The channel with a roughness cube standing on its floor (0.4 high)."""
+    import fvib_workloads as W
+    w = W.channel()
+    w.box = ((2.0, -1.5, 1.2), (2.4, -0.6, 1.6))
+    return w
 
 
 def setup(w, precision, tol, solver):
@@ -123,13 +154,13 @@ def setup(w, precision, tol, solver):
     return g, ut, fbt, body, kc
 
 
-def fwd_adj_pass(g, w, ut, fbt, body, kc, steps, ckpt):
+def fwd_adj_pass(g, w, ut, fbt, body, kc, steps, ckpt, scheme=None, coupling=None):
     """Differentiable rollout of `steps` steps, loss, backward."""
     from paper_2505_23940_amd.rollout import rms_lift, rollout, wall_shear
     fb = [x.detach().clone().requires_grad_(True) for x in fbt]
     kcr = kc.detach().clone().requires_grad_(True)
     uS, bS, Fh, _ = rollout(g, [x.clone() for x in ut], fb, kcr, body.clone(), steps,
-                            ckpt_every=ckpt)
+                            ckpt_every=ckpt, scheme=scheme, coupling=coupling)
     if w.body is not None:
         J = rms_lift(g, Fh)
     elif w.bc[1] == ["noslip", "noslip"]:
@@ -144,7 +175,7 @@ def fwd_adj_pass(g, w, ut, fbt, body, kc, steps, ckpt):
     return J
 
 
-def fwd_pass(g, ut, fbt, body, kc, steps):
+def fwd_pass(g, ut, fbt, body, kc, steps, scheme=None, coupling=None):
     """Forward steps in place, enqueued back to back (one step record per
     step, statuses checked after the last)."""
     import torch
@@ -156,7 +187,11 @@ def fwd_pass(g, ut, fbt, body, kc, steps):
     g.defer_status(True)
     try:
         for n in range(steps):
-            g.step(u, p, fbt, b, kc, info=info[n])
+            if coupling is not None:
+                omega = torch.zeros(6, dtype=torch.float64, device=g.device)
+                g.step(u, p, fbt, b, kc, info=info[n], coupling=coupling, omega=omega)
+            else:
+                g.step(u, p, fbt, b, kc, info=info[n], scheme=scheme)
     finally:
         g.defer_status(False)
     return info

@@ -1004,6 +1004,10 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
   if (!strong && (rc = timed(g, FVIB_K_PREDICTOR,
                              [&] { return launch_predictor<T>(G, u, fb, us, ib, 0, g->stream); })))
     return rc;
+  // static box: its forced faces take the target (zero) and keep the forcing
+  if (g->has_box &&
+      (rc = timed(g, FVIB_K_IB, [&] { return launch_box_fix<T>(G, ib, us, g->stream); })))
+    return rc;
   if (g->planes.np &&
       (rc = timed(g, FVIB_K_BOUNDARY, [&] {
          return launch_boundary<T>(G, g->planes, u, us, g->red(), g->sc, g->stream);
@@ -1070,7 +1074,9 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
     });
     if (rc) return rc;
   } else if (g->has_box) {
-    rc = timed(g, FVIB_K_IB, [&] { return launch_box_force<T>(g->G64, ib, g->d.rho, g->sc, g->stream); });
+    rc = timed(g, FVIB_K_IB, [&] {
+      return launch_box_force<T>(g->G64, ib, g->d.rho, g->red(), g->sc, g->stream);
+    });
     if (rc) return rc;
   }
   // (a status the host set after the last projection still needs the copy)
@@ -1200,6 +1206,9 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
   if ((rc = timed(g, FVIB_K_ADJOINT, [&] {
          return launch_adj_outflow<T>(G, g->planes, 0, usb, ub0, g->red(), g->sc, g->stream);
        })))
+    return rc;
+  if (g->has_box &&
+      (rc = timed(g, FVIB_K_IB, [&] { return launch_box_rbar<T>(G, ib, usb, g->stream); })))
     return rc;
   if ((rc = timed(g, FVIB_K_ADJ_MOMENTUM, [&] {
          return launch_adj_momentum<T>(G, u, (const T* const*)usb, ib, ub0, fbb, g->stream);

@@ -223,8 +223,14 @@ int launch_adj_body_loads(const IbGeo& B, const IbView<T>& ib, const double* st_
 // Static box (3D): force F = -rho sum f dv over the forced faces into
 // sc->force, and the forcing adjoint -rho dv dF_c on them (dF nullable).
 template <typename T>
-int launch_box_force(const Geo<double>& G, const IbView<T>& ib, double rho, SolverScalars* sc,
-                     hipStream_t s);
+int launch_box_force(const Geo<double>& G, const IbView<T>& ib, double rho, RedBuf red,
+                     SolverScalars* sc, hipStream_t s);
+// Forced faces of the box after the predictor: forcing -u*/dt stored, u* = 0.
+template <typename T>
+int launch_box_fix(const Geo<T>& G, const IbView<T>& ib, T* us[3], hipStream_t s);
+// Before the momentum adjoint: ustar_bar = -fbar/dt on the forced faces.
+template <typename T>
+int launch_box_rbar(const Geo<T>& G, const IbView<T>& ib, T* usb[3], hipStream_t s);
 template <typename T>
 int launch_box_fbar(const Geo<double>& G, const IbView<T>& ib, double rho, const double* dF,
                     hipStream_t s);

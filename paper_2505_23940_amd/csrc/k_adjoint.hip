@@ -355,23 +355,30 @@ __device__ __forceinline__ double box_face_volume(const Geo<double>& G, int c, i
   return v;
 }
 
-// Force on the box: F = -rho sum over forced faces of f dv (one block).
+// Force on the box: F = -rho sum over forced faces of f dv (block partial
+// sums, combined in block order by a one-block epilogue).
+struct FinBoxForce {
+  double rho;
+  __device__ bool skip(const SolverScalars*) const { return false; }
+  __device__ void apply(const double* t, SolverScalars* sc) const {
+    for (int a = 0; a < 3; ++a) sc->force[a] = -rho * t[a];
+  }
+};
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_box_force(Geo<double> G, IbView<T> ib, double rho, SolverScalars* sc) {
+k_box_force(Geo<double> G, IbView<T> ib, double* __restrict__ partial) {
   double F[3] = {0.0, 0.0, 0.0};
   for (int c = 0; c < 3; ++c) {
     const int W0 = ib.bw[c][0], W1 = ib.bw[c][1], n = W0 * W1 * ib.bw[c][2];
-    for (int l = threadIdx.x; l < n; l += kBlock) {
+    for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
       if (!ib.bcls[c][l]) continue;
       const int i = ib.bo[c][0] + l % W0, j = ib.bo[c][1] + (l / W0) % W1,
                 k = ib.bo[c][2] + l / (W0 * W1);
-      F[c] -= rho * (double)ib.bf[c][l] * box_face_volume<T>(G, c, i, j, k);
+      F[c] += (double)ib.bf[c][l] * box_face_volume<T>(G, c, i, j, k);
     }
   }
-  block_sum<3>(F);
-  if (threadIdx.x == 0)
-    for (int a = 0; a < 3; ++a) sc->force[a] = F[a];
+  block_partials<3, 3>(F, partial);
 }
 
 // Forcing adjoint on the box's forced faces for a force adjoint dF
@@ -390,10 +397,78 @@ k_box_fbar(Geo<double> G, IbView<T> ib, double rho, const double* __restrict__ d
   }
 }
 
+// Forward: on the forced faces the predictor's u* = u + dt R becomes the
+// target 0, and the forcing of Eq. 5 is f = -R - u / dt = -u* / dt.
 template <typename T>
-int launch_box_force(const Geo<double>& G, const IbView<T>& ib, double rho, SolverScalars* sc,
-                     hipStream_t s) {
-  launch_kernel((k_box_force<T>), dim3(1), dim3(kBlock), 0, s, G, ib, rho, sc);
+__global__ void __launch_bounds__(kBlock)
+k_box_fix(Geo<T> G, IbView<T> ib, T* __restrict__ s0, T* __restrict__ s1, T* __restrict__ s2) {
+  T* us[3] = {s0, s1, s2};
+  for (int c = 0; c < 3; ++c) {
+    const int W0 = ib.bw[c][0], W1 = ib.bw[c][1], n = W0 * W1 * ib.bw[c][2];
+    for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+      if (!ib.bcls[c][l]) continue;
+      const int i = ib.bo[c][0] + l % W0, j = ib.bo[c][1] + (l / W0) % W1,
+                k = ib.bo[c][2] + l / (W0 * W1);
+      const int64_t id = fidx(G.ext[c], i, j, k);
+      ib.bf[c][l] = -us[c][id] / G.dt;
+      us[c][id] = T(0);
+    }
+  }
+}
+
+// Adjoint: on the forced faces the momentum adjoint reads the forcing
+// adjoint -fbar / dt in place of ustar_bar (u* there is the constant
+// target; R reaches the loss only through f).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_box_rbar(Geo<T> G, IbView<T> ib, T* __restrict__ s0, T* __restrict__ s1, T* __restrict__ s2) {
+  T* usb[3] = {s0, s1, s2};
+  for (int c = 0; c < 3; ++c) {
+    const int W0 = ib.bw[c][0], W1 = ib.bw[c][1], n = W0 * W1 * ib.bw[c][2];
+    for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+      if (!ib.bcls[c][l]) continue;
+      const int i = ib.bo[c][0] + l % W0, j = ib.bo[c][1] + (l / W0) % W1,
+                k = ib.bo[c][2] + l / (W0 * W1);
+      usb[c][fidx(G.ext[c], i, j, k)] = -ib.bf[c][l] / G.dt;
+    }
+  }
+}
+
+static int box_blocks(const IbView<float>& ib) {
+  int64_t n = 0;
+  for (int c = 0; c < 3; ++c) n = std::max<int64_t>(n, (int64_t)ib.bw[c][0] * ib.bw[c][1] * ib.bw[c][2]);
+  int64_t b = (n + kBlock - 1) / kBlock;
+  return (int)std::min<int64_t>(std::max<int64_t>(b, 1), kMaxRedBlocks);
+}
+static int box_blocks(const IbView<double>& ib) {
+  int64_t n = 0;
+  for (int c = 0; c < 3; ++c) n = std::max<int64_t>(n, (int64_t)ib.bw[c][0] * ib.bw[c][1] * ib.bw[c][2]);
+  int64_t b = (n + kBlock - 1) / kBlock;
+  return (int)std::min<int64_t>(std::max<int64_t>(b, 1), kMaxRedBlocks);
+}
+
+template <typename T>
+int launch_box_force(const Geo<double>& G, const IbView<T>& ib, double rho, RedBuf red,
+                     SolverScalars* sc, hipStream_t s) {
+  const int nb = box_blocks(ib);
+  launch_kernel((k_box_force<T>), dim3(nb), dim3(kBlock), 0, s, G, ib, red.partial);
+  FVIB_HIP(hipGetLastError());
+  FVIB_HIP((launch_finish<3, 3>(red.partial, nb, sc, FinBoxForce{rho}, s)));
+  return FVIB_OK;
+}
+
+template <typename T>
+int launch_box_fix(const Geo<T>& G, const IbView<T>& ib, T* us[3], hipStream_t s) {
+  launch_kernel((k_box_fix<T>), dim3(box_blocks(ib)), dim3(kBlock), 0, s, G, ib, us[0], us[1],
+                us[2]);
+  FVIB_HIP(hipGetLastError());
+  return FVIB_OK;
+}
+
+template <typename T>
+int launch_box_rbar(const Geo<T>& G, const IbView<T>& ib, T* usb[3], hipStream_t s) {
+  launch_kernel((k_box_rbar<T>), dim3(box_blocks(ib)), dim3(kBlock), 0, s, G, ib, usb[0], usb[1],
+                usb[2]);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
@@ -406,10 +481,18 @@ int launch_box_fbar(const Geo<double>& G, const IbView<T>& ib, double rho, const
   return FVIB_OK;
 }
 
-template int launch_box_force<float>(const Geo<double>&, const IbView<float>&, double,
+template int launch_box_force<float>(const Geo<double>&, const IbView<float>&, double, RedBuf,
                                      SolverScalars*, hipStream_t);
-template int launch_box_force<double>(const Geo<double>&, const IbView<double>&, double,
+template int launch_box_force<double>(const Geo<double>&, const IbView<double>&, double, RedBuf,
                                       SolverScalars*, hipStream_t);
+template int launch_box_fix<float>(const Geo<float>&, const IbView<float>&, float* [3],
+                                   hipStream_t);
+template int launch_box_fix<double>(const Geo<double>&, const IbView<double>&, double* [3],
+                                    hipStream_t);
+template int launch_box_rbar<float>(const Geo<float>&, const IbView<float>&, float* [3],
+                                    hipStream_t);
+template int launch_box_rbar<double>(const Geo<double>&, const IbView<double>&, double* [3],
+                                     hipStream_t);
 template int launch_box_fbar<float>(const Geo<double>&, const IbView<float>&, double,
                                     const double*, hipStream_t);
 template int launch_box_fbar<double>(const Geo<double>&, const IbView<double>&, double,
@@ -1130,10 +1213,9 @@ struct AdjHalo {
   uint32_t neg;                  // bit 3 h + c: u negated by an x-y ghost
   uint32_t zr;                   // bit 3 h + c: Rbar zero by the x-y rules
   int li[2][2];                  // forced index of components 0, 1 or -1
-  int bxy[2][3];                 // static box: x-y index in the component's window or -1
 };
 
-template <int DIM, bool BOX, typename T>
+template <int DIM, typename T>
 __device__ __forceinline__ void adj_halo_init(const AdjCtx<T>& X, AdjHalo<T, DIM>& Hh, int i0,
                                               int j0) {
   const Geo<T>& G = X.G;
@@ -1170,11 +1252,6 @@ __device__ __forceinline__ void adj_halo_init(const AdjCtx<T>& X, AdjHalo<T, DIM
       const bool notev = c < 2 && !G.per[c] && (I[c] < 1 || I[c] > G.n[c] - 1);
       Hh.neg |= (neg ? 1u : 0u) << (3 * h + c);
       Hh.zr |= ((out || notev) ? 1u : 0u) << (3 * h + c);
-      if (BOX) {
-        const int li = I[0] - X.ib.bo[c][0], lj = I[1] - X.ib.bo[c][1];
-        const bool in = li >= 0 && lj >= 0 && li < X.ib.bw[c][0] && lj < X.ib.bw[c][1];
-        Hh.bxy[h][c] = in ? lj * X.ib.bw[c][0] + li : -1;
-      }
       if (c < 2) {
         int li = -1;
         if (X.ib.active) {
@@ -1188,14 +1265,13 @@ __device__ __forceinline__ void adj_halo_init(const AdjCtx<T>& X, AdjHalo<T, DIM
   }
 }
 
-template <int DIM, bool BOX, typename T>
+template <int DIM, typename T>
 __device__ __forceinline__ void adj_load(const AdjCtx<T>& X, const AdjHalo<T, DIM>& Hh,
                                          AdjRegs<T, DIM>& P, int kk) {
   const Geo<T>& G = X.G;
   // z part of the rules for this plane (uniform across the block)
   // (per component: w has one more face than cells along a bounded z)
   int64_t pbase[DIM];
-  int bz[DIM];                   // static box: z part of the window index or -1
   bool gz[DIM], dz[DIM], zoff[DIM];
   T g2z[DIM];
 #pragma unroll
@@ -1214,10 +1290,6 @@ __device__ __forceinline__ void adj_load(const AdjCtx<T>& X, const AdjHalo<T, DI
       zoff[c] = gz[c] || (c == 2 && !G.per[2] && (kz < 1 || kz > G.n[2] - 1));
     }
     pbase[c] = (int64_t)kz * G.ext[c][0] * G.ext[c][1];
-    if (BOX) {
-      const int lk = kz - X.ib.bo[c][2];
-      bz[c] = (lk >= 0 && lk < X.ib.bw[c][2]) ? lk * X.ib.bw[c][0] * X.ib.bw[c][1] : -1;
-    }
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -1235,13 +1307,6 @@ __device__ __forceinline__ void adj_load(const AdjCtx<T>& X, const AdjHalo<T, DI
       if (c < 2) {
         const int li = Hh.li[h][c];
         if (li >= 0) rv = -X.ib.f[c][li] / G.dt;
-      }
-      if (BOX) {
-        // forced face of the static box: the forcing adjoint, not ustar_bar
-        if (bz[c] >= 0 && Hh.bxy[h][c] >= 0) {
-          const int l = bz[c] + Hh.bxy[h][c];
-          if (X.ib.bcls[c][l]) rv = -X.ib.bf[c][l] / G.dt;
-        }
       }
       const bool zero = ((Hh.zr >> (3 * h + c)) & 1u) || zoff[c];
       P.r[h][c] = zero ? T(0) : rv;
@@ -1264,17 +1329,17 @@ __device__ __forceinline__ void adj_store(AdjRings<T, DIM>& S, int slot, const A
   }
 }
 
-template <int DIM, bool BOX, typename T>
+template <int DIM, typename T>
 __device__ __forceinline__ void adj_fill(const AdjCtx<T>& X, const AdjHalo<T, DIM>& Hh,
                                          AdjRings<T, DIM>& S, int slot, int kk) {
   AdjRegs<T, DIM> P;
-  adj_load<DIM, BOX>(X, Hh, P, kk);
+  adj_load<DIM>(X, Hh, P, kk);
   adj_store<DIM>(S, slot, P);
 }
 
 // At most 128 registers (four waves per SIMD): a channel-sized grid then
 // runs in one round of blocks.
-template <typename T, int DIM, bool UPW, bool BOX>
+template <typename T, int DIM, bool UPW>
 __global__ void __launch_bounds__(kBlock, 4)
 k_adj_momentum_lds(AdjCtx<T> X, int ntx, int nty, int nzc, T* __restrict__ ub0,
                    T* __restrict__ ub1, T* __restrict__ ub2, T* __restrict__ fb0,
@@ -1297,15 +1362,15 @@ k_adj_momentum_lds(AdjCtx<T> X, int ntx, int nty, int nzc, T* __restrict__ ub0,
   const bool inside = i < G.n[0] && j < G.n[1];
   load_tile_met<DIM>(G, TM, i0, j0, k0);
   AdjHalo<T, DIM> Hh;
-  adj_halo_init<DIM, BOX>(X, Hh, i0, j0);
+  adj_halo_init<DIM>(X, Hh, i0, j0);
   AdjRegs<T, DIM> nxt;
   if (DIM == 3) {
-    adj_fill<DIM, BOX>(X, Hh, S, ring_slot(k0 - 1), k0 - 1);
-    adj_fill<DIM, BOX>(X, Hh, S, ring_slot(k0), k0);
-    adj_fill<DIM, BOX>(X, Hh, S, ring_slot(k0 + 1), k0 + 1);
-    if (k0 + 1 < k1) adj_load<DIM, BOX>(X, Hh, nxt, k0 + 2);
+    adj_fill<DIM>(X, Hh, S, ring_slot(k0 - 1), k0 - 1);
+    adj_fill<DIM>(X, Hh, S, ring_slot(k0), k0);
+    adj_fill<DIM>(X, Hh, S, ring_slot(k0 + 1), k0 + 1);
+    if (k0 + 1 < k1) adj_load<DIM>(X, Hh, nxt, k0 + 2);
   } else {
-    adj_fill<DIM, BOX>(X, Hh, S, 0, 0);
+    adj_fill<DIM>(X, Hh, S, 0, 0);
   }
   for (int k = k0; k < k1; ++k) {
     __syncthreads();
@@ -1374,7 +1439,7 @@ k_adj_momentum_lds(AdjCtx<T> X, int ntx, int nty, int nzc, T* __restrict__ ub0,
     if (DIM == 3 && k + 1 < k1) {
       __syncthreads();
       adj_store<DIM>(S, sm, nxt);                     // slot of plane k-1 takes k+2
-      if (k + 2 < k1) adj_load<DIM, BOX>(X, Hh, nxt, k + 3);
+      if (k + 2 < k1) adj_load<DIM>(X, Hh, nxt, k + 3);
     }
   }
 }
@@ -1532,13 +1597,10 @@ static int launch_adj_momentum_t(const AdjCtx<T>& X, T* ubar[3], T* fbbar[3], hi
   int nb = ntx * nty * nzc;
   nb = (nb + kXcds - 1) / kXcds * kXcds;
   if (G.dim == 2)
-    launch_kernel((k_adj_momentum_lds<T, 2, UPW, false>), dim3(nb), dim3(kBlock), 0, s, X, ntx,
-                  nty, nzc, ubar[0], ubar[1], ubar[2], fbbar[0], fbbar[1], fbbar[2]);
-  else if (X.ib.box)
-    launch_kernel((k_adj_momentum_lds<T, 3, UPW, true>), dim3(nb), dim3(kBlock), 0, s, X, ntx,
+    launch_kernel((k_adj_momentum_lds<T, 2, UPW>), dim3(nb), dim3(kBlock), 0, s, X, ntx,
                   nty, nzc, ubar[0], ubar[1], ubar[2], fbbar[0], fbbar[1], fbbar[2]);
   else
-    launch_kernel((k_adj_momentum_lds<T, 3, UPW, false>), dim3(nb), dim3(kBlock), 0, s, X, ntx,
+    launch_kernel((k_adj_momentum_lds<T, 3, UPW>), dim3(nb), dim3(kBlock), 0, s, X, ntx,
                   nty, nzc, ubar[0], ubar[1], ubar[2], fbbar[0], fbbar[1], fbbar[2]);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;

@@ -112,15 +112,6 @@ __device__ __forceinline__ void predict_face(const Geo<T>& G, const Load& L, con
     return;
   }
   const T un = L(C, 0, 0, 0);
-  if constexpr (DIM == 3 && IBA) {
-    // static box: target zero on the forced faces
-    int li = 0;
-    if (forced_box<C>(ib, i, j, k, &li)) {
-      ib.bf[C][li] = -R - un / G.dt;
-      out[id] = T(0);
-      return;
-    }
-  }
   if constexpr (DIM == 2 && C < 2 && IBA) {
     int li = 0;
     if (forced<C>(ib, i, j, &li)) {
@@ -444,19 +435,27 @@ int launch_predictor(const Geo<T>& G, const T* const u[3], const T* const fb[3],
 #define FVIB_PRED4(D, M, U, I)                                                                 \
   launch_kernel((k_predictor<T, D, M, U, I>), grid, block, 0, s, G, ntx, nty, nzc, u[0], u[1],  \
                 u[2], fb[0], fb[1], fb[2], out[0], out[1], out[2], ib)
+  // marker bodies (2D) force faces inside the predictor; a static box's
+  // faces are fixed by a pass of their own afterwards
+  const bool iba = ib.active && !ib.box;
 #define FVIB_PRED(D, M)                                                                        \
   do {                                                                                         \
     if (G.upwind) {                                                                            \
-      if (ib.active) FVIB_PRED4(D, M, true, true); else FVIB_PRED4(D, M, true, false);        \
+      if (iba) FVIB_PRED4(D, M, true, true); else FVIB_PRED4(D, M, true, false);              \
     } else {                                                                                   \
-      if (ib.active) FVIB_PRED4(D, M, false, true); else FVIB_PRED4(D, M, false, false);      \
+      if (iba) FVIB_PRED4(D, M, false, true); else FVIB_PRED4(D, M, false, false);            \
     }                                                                                          \
+  } while (0)
+#define FVIB_PRED3(M)                                                                          \
+  do {                                                                                         \
+    if (G.upwind) FVIB_PRED4(3, M, true, false); else FVIB_PRED4(3, M, false, false);          \
   } while (0)
   if (G.dim == 2) {
     if (mode == 0) FVIB_PRED(2, 0); else FVIB_PRED(2, 1);
   } else {
-    if (mode == 0) FVIB_PRED(3, 0); else FVIB_PRED(3, 1);
+    if (mode == 0) FVIB_PRED3(0); else FVIB_PRED3(1);
   }
+#undef FVIB_PRED3
 #undef FVIB_PRED
 #undef FVIB_PRED4
   FVIB_HIP(hipGetLastError());
