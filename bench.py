@@ -81,7 +81,7 @@ def other_workloads(precision, tol, solver, steps=20):
     cases = [(n, W.by_name(n, "full"), None, None)
              for n in ("tgv2d", "tgv3d", "cylinder", "viv", "wmles")]
     cases.append(("channel_rk3", W.channel(), "rk3", None))
-    cases.append(("channel_cube", channel_cube(), None, None))
+    cases.append(("channel_cube", W.channel_cube(), None, None))
     wv = W.viv(dof=2, coupling_iters=100, coupling_tol=1e-5)
     cases.append(("viv_2dof_strong", wv, None, (100, 1e-5)))
     for name, w, scheme, coupling in cases:
@@ -126,17 +126,7 @@ def make_workload(name):
     import fvib_workloads as W
     if name == "channel":
         return W.channel()
-    if name == "channel_cube":
-        return channel_cube()
     return W.by_name(name, "full")
-
-
-def channel_cube():
-    """The channel with a roughness cube standing on its floor (0.4 high)."""
-    import fvib_workloads as W
-    w = W.channel()
-    w.box = ((2.0, -1.5, 1.2), (2.4, -0.6, 1.6))
-    return w
 
 
 def setup(w, precision, tol, solver):

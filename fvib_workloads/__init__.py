@@ -175,6 +175,18 @@ def wmles(n: int = 64, re_tau: float = 2000.0, cs: float = 0.1, steps: int = 100
     return w
 
 
+def channel_cube(nx: int = 192, ny: int = 128, nz: int = 160, steps: int = 200,
+                 dt: float = 1e-5, precision: str = "fp32") -> Workload:
+    """The channel with one cube-like roughness element standing on its
+    floor (Sec. 3.4.2 places a layer of cubes on the wall): a box 0.4 wide
+    in x and z reaching from the lower wall to y = -0.6."""
+    w = channel(nx=nx, ny=ny, nz=nz, steps=steps, dt=dt, precision=precision)
+    w.name = "channel"              # same initial fields
+    w.box = ((2.0, -1.5, 1.2), (2.4, -0.6, 1.6))
+    w.meta["variant"] = "cube"
+    return w
+
+
 def cylinder(nx: int = 512, ny: int = 256, steps: int = 5000, dt: float = 5e-3,
              markers: int = 160, re: float = 100.0, precision: str = "fp32",
              lx: float = 32.0, ly: float = 16.0, center=(8.0, 8.0)) -> Workload:
@@ -334,6 +346,8 @@ def by_name(name: str, size: str = "full") -> Workload:
         return tgv3d() if size == "full" else tgv3d(n=24, steps=10)
     if name == "channel":
         return channel() if size == "full" else channel(nx=24, ny=16, nz=20, steps=10)
+    if name == "channel_cube":
+        return channel_cube() if size == "full" else channel_cube(nx=24, ny=16, nz=20, steps=10)
     if name == "wmles":
         return wmles() if size == "full" else wmles(n=16, steps=5)
     if name == "cylinder":

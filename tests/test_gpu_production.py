@@ -5,10 +5,12 @@
   last one and the column marches several chunks, one-step VJPs and a
   rollout gradient against the oracle's autograd.
 * Full workload grids: the 3D Taylor-Green vortex 128^3, the cylinder
-  512 x 256, the channel 192 x 128 x 160 and the VIV case 1024 x 512,
+  512 x 256, the channel 192 x 128 x 160, the VIV case 1024 x 512, the
+  wall-modelled LES channel 64^3 and the channel with a cube on its floor,
   float64 path within 1e-10 relative L2 of the oracle and float32-mixed path
   within 1e-5 after 100 steps (10 for the VIV case, whose oracle step is the
-  slowest per cell), with forces and body state.
+  slowest per cell, 20 for the LES channel, 12 for the cube), with forces
+  and body state.
 * Bounded axes longer than 256 cells (the 2D workloads' streamwise axis):
   the Poisson solve against the oracle's exact solve.
 * One full-size channel VJP against the oracle's autograd.
@@ -74,9 +76,11 @@ def test_rollout_gradient_multi_chunk(precision):
 
 
 # ------------------------------------------------------------ full grids
-FULL = {"tgv3d": 100, "cylinder": 100, "channel": 100, "viv": 10}
+FULL = {"tgv3d": 100, "cylinder": 100, "channel": 100, "viv": 10, "wmles": 20,
+        "channel_cube": 12}
 SNAP = 10
-FP64_TOL = {"tgv3d": 1e-12, "cylinder": 1e-12, "channel": 1e-10, "viv": 1e-12}
+FP64_TOL = {"tgv3d": 1e-12, "cylinder": 1e-12, "channel": 1e-10, "viv": 1e-12, "wmles": 1e-10,
+            "channel_cube": 1e-10}
 
 
 def _oracle_full(w, steps, snap):
@@ -139,13 +143,15 @@ def test_full_workload_parity(name):
         assert p64 <= 1e-9, (name, n, p64)
         if n == steps:
             assert e32 <= 1e-5, (name, n, e32)
-        if w.body is not None:
+        if w.body is not None or getattr(w, "box", None) is not None:
             fo = orc[n]["forces"]
             scale = max(1.0, np.abs(fo).max())
             f64 = np.abs(g64[n]["forces"] - fo).max() / scale
             f32 = np.abs(g32[n]["forces"] - fo).max() / scale
-            b64 = np.abs(g64[n]["body"] - orc[n]["body"]).max()
-            b32 = np.abs(g32[n]["body"] - orc[n]["body"]).max()
+            b64 = b32 = 0.0
+            if w.body is not None:
+                b64 = np.abs(g64[n]["body"] - orc[n]["body"]).max()
+                b32 = np.abs(g32[n]["body"] - orc[n]["body"]).max()
             report.append(f"  forces fp64 {f64:.2e} fp32 {f32:.2e}; body fp64 {b64:.2e} fp32 {b32:.2e}")
             assert f64 <= 1e-9 and b64 <= 1e-12, (f64, b64)
     assert max(i["div_max"] for i in g64[steps]["infos"]) <= FP64_TOL[name]
