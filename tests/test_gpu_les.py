@@ -1,8 +1,9 @@
 """Large-eddy simulation through the C ABI (fvib_les_set): the constant
 Smagorinsky subgrid stress and the equilibrium wall model (Sec. 3.4.5,
-Eqs. 27-29) against the oracle (oracle/les.py): forward steps, one-step
-vector-Jacobian products, a rollout gradient, Runge-Kutta steps, and the
-set-up's argument checks."""
+Eqs. 27-29) against the oracle (oracle/les.py): forward steps (also with a
+cube on the channel floor, whose forcing then sees the subgrid term),
+one-step vector-Jacobian products, a rollout gradient, Runge-Kutta steps,
+and the set-up's argument checks."""
 import numpy as np
 import pytest
 import torch
@@ -27,7 +28,12 @@ def _cases():
     pb = W.generic(3, (n, n, n), [f, f, np.linspace(0, 3.0, n + 1)],
                    [["periodic", "periodic"]] * 3, nu=1e-3, dt=2e-3, steps=4)
     pb.les = {"cs": 0.2, "wall_model": False, "kappa": 0.4, "B": 5.0, "eps": 1e-6}
-    return {"wmles": wm, "channel_les": ch, "periodic_les": pb}
+    # both models and a cube on the floor: the forcing sees the subgrid term in R
+    cb = W.channel(nx=12, ny=14, nz=10, steps=4, dt=2e-4)
+    cb.nu = 1e-3
+    cb.les = dict(ch.les)
+    cb.box = ((2.0, -1.5, 1.0), (3.3, -0.6, 2.1))
+    return {"wmles": wm, "channel_les": ch, "periodic_les": pb, "channel_les_cube": cb}
 
 
 def _fields(w, seed):
@@ -48,13 +54,21 @@ def test_les_steps_match_oracle(case, precision):
     u0, fb = _fields(w, 3)
     og = OGrid(w)
     with torch.no_grad():
-        st, _, _ = rollout(og, init_state(og, u0), make_params(og, fb), w.steps)
+        st, Fo, _ = rollout(og, init_state(og, u0), make_params(og, fb), w.steps)
     print(f"[les] {case} {precision}: oracle done", flush=True)
     g = make_grid(w, precision=precision, poisson_tol=1e-12 if precision == "fp64" else 1e-9)
     u, fbt, p = g.to_u(u0), g.to_u(fb), g.zeros_p()
+    forces = []
     for _ in range(w.steps):
         g.step(u, p, fbt)
+        forces.append(g.last_info()["force"])
     torch.cuda.synchronize()
+    if w.box is not None:
+        fo = Fo.numpy()
+        ef = max(float(np.abs(np.asarray(forces[n]) - fo[n]).max() / np.abs(fo[n]).max())
+                 for n in range(w.steps))
+        print(f"{case} {precision}: force {ef:.2e}")
+        assert ef <= (1e-9 if precision == "fp64" else 2e-5), ef
     gu = [x.double().cpu().numpy() for x in u]
     eu = rel_l2(gu, [x.numpy() for x in st["u"]])
     ep = rel_l2([gauge(p.cpu().numpy())], [st["p"].numpy()])
