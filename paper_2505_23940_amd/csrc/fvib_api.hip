@@ -1628,7 +1628,7 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
         return bail(FVIB_ENOMEM, "device allocation of the workspace failed");
     }
     std::vector<double> hd;   // per axis: phi, phiT, lam, FFT twiddles, symmetric halves
-    size_t off[3][4];
+    size_t off[3][5];
     size_t soff[3][5];
     bool symok[3] = {false, false, false};
     FftAxis fax[3];
@@ -1649,15 +1649,33 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
       off[a][2] = hd.size();
       hd.insert(hd.end(), lam.begin(), lam.end());
       hd.resize((hd.size() + 3) / 4 * 4, 0.0);
-      // uniform periodic axis: real FFT in place of the contraction with its
-      // Fourier basis; twiddles exp(-2 pi i k / N) as (re, im)
+      // uniform axis: an FFT in place of the contraction with its basis
+      // (real Fourier basis when periodic, cosine basis when bounded);
+      // twiddles exp(-2 pi i k / N) as (re, im), and for the cosine
+      // transform (cos, sin)(pi m / (2N)) for m <= N/2
       const std::vector<double>& fa = g->faces[a];
-      fax[a] = fft_plan(N, (fa[N] - fa[0]) / N);
-      if (!g->per[a]) fax[a].on = 0;
+      const double ha = (fa[N] - fa[0]) / N;
+      bool uni = true;
+      for (int i = 0; i < N; ++i)
+        if (fabs((fa[i + 1] - fa[i]) - ha) > 1e-12 * ha) uni = false;
+      fax[a] = fft_plan(N, ha);
+      if (!g->per[a]) {
+        fax[a].on = (uni && fft_size_ok(N) && N % 2 == 0) ? 1 : 0;
+        fax[a].dct = fax[a].on;
+      }
       off[a][3] = hd.size();
       if (fax[a].on) {
         for (int k = 0; k < N; ++k) {
           const double th = -2.0 * 3.14159265358979323846 * k / N;
+          hd.push_back(cos(th));
+          hd.push_back(sin(th));
+        }
+        hd.resize((hd.size() + 3) / 4 * 4, 0.0);
+      }
+      off[a][4] = hd.size();
+      if (fax[a].dct) {
+        for (int m = 0; m <= N / 2; ++m) {
+          const double th = 3.14159265358979323846 * m / (2.0 * N);
           hd.push_back(cos(th));
           hd.push_back(sin(th));
         }
@@ -1672,7 +1690,7 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
       // the mode order differs from the dense basis)
       int inner_a = 1;
       for (int b2 = 0; b2 < a; ++b2) inner_a *= g->n[b2];
-      if (!g->per[a] && a > 0 && a != g->dim - 1 && inner_a % 32 == 0 &&
+      if (!g->per[a] && !fax[a].dct && a > 0 && a != g->dim - 1 && inner_a % 32 == 0 &&
           fdm_sym_size_supported(N)) {
         const int H = N / 2;
         const double L = fa[N] - fa[0];
@@ -1731,6 +1749,10 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
         if (fax[a].on) {
           g->F64.tw[a] = g->fdm_d + off[a][3];
           g->F32.tw[a] = g->fdm_f + off[a][3];
+        }
+        if (fax[a].dct) {
+          g->F64.dtw[a] = g->fdm_d + off[a][4];
+          g->F32.dtw[a] = g->fdm_f + off[a][4];
         }
       }
     }

@@ -91,14 +91,17 @@ struct FdmDiv {
   const double* lam[3];        // per-axis eigenvalues (ascending, lam[0] = 0)
 };
 
-// Uniform periodic axes whose length factors into 2, 3, 5 use a real FFT
-// in place of the dense contraction with their (real Fourier) basis.
-constexpr int kFftMaxN = 256;
-
+// Uniform axes whose length factors into 2, 3, 5 use an FFT in place of
+// the dense contraction with their basis: a real FFT on a periodic axis
+// (real Fourier basis), a cosine transform through one FFT on a bounded
+// one (cosine basis of the Neumann operator).
 struct FftAxis {
   int on;                      // axis transformed by FFT
+  int dct;                     // bounded axis: cosine transform
   double a, b;                 // basis scales sqrt(2/N)/sqrt(h), 1/sqrt(N h)
 };
+// Whether an FFT kernel exists for axis length n.
+bool fft_size_ok(int n);
 
 // Mirror-symmetric bounded axis split into even and odd halves (float
 // path): half-size operators, row-major H x H, and the mode order
@@ -121,6 +124,7 @@ struct FdmPlan {
   FdmDiv div;
   FftAxis fft[3];
   const V* tw[3];              // exp(-2 pi i k / N), k < N, as (re, im) pairs
+  const V* dtw[3];             // cosine transform: (cos, sin)(pi m / (2N)), m <= N/2
   FdmSym<V> sym[3];
 };
 

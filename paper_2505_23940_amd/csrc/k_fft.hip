@@ -23,13 +23,28 @@
 namespace fvib {
 
 // Lines per block: 16 on the contiguous axis (two buffers of 8 complex
-// lines, about 25 KB of LDS, so six blocks fit a CU); the strided axis keeps
-// 32 float lines, whose interleaved rows then span 128 bytes.
-template <typename V, bool XFAST>
+// lines, about 25 KB of LDS for 192 floats, so six blocks fit a CU); the
+// strided axis keeps 32 float lines, whose interleaved rows then span 128
+// bytes.  Long axes halve the lines until the block's LDS (two line
+// buffers, twiddles, eigenvalues) fits 72 KB.
+constexpr int fft_lds_bytes(int lpb, int n, int vs) {
+  return 2 * (lpb / 2) * n * 2 * vs + n * 2 * vs + n * 8;
+}
+constexpr int fft_lines_fit(int lpb, int n, int vs) {
+  return (lpb > 2 && fft_lds_bytes(lpb, n, vs) > 72 * 1024) ? fft_lines_fit(lpb / 2, n, vs) : lpb;
+}
+template <typename V, bool XFAST, int N>
 struct FftCfg {
-  static constexpr int LPB = (sizeof(V) == 4 && !XFAST) ? 32 : 16;
+  static constexpr int LPB = fft_lines_fit((sizeof(V) == 4 && !XFAST) ? 32 : 16, N, (int)sizeof(V));
   static constexpr int P = LPB / 2;                      // complex lines
 };
+
+// Position of entry j of a line in the even-odd reordered sequence of the
+// cosine transform: v_m = x_{2m}, v_{N-1-m} = x_{2m+1}.
+template <int N>
+__device__ __forceinline__ int dct_pos(int j) {
+  return (j & 1) ? N - 1 - (j >> 1) : (j >> 1);
+}
 
 // sin and cos of 2 pi j / R (compile time): reduction to the nearest
 // quarter turn, then Taylor series on |r| <= pi / 4.
@@ -263,6 +278,20 @@ __device__ __forceinline__ Cx<V>* fft_lines(Cx<V>* src, Cx<V>* dst, const Cx<V>*
 // for 0 < m < N / 2, Y_{N-m} = conj Y_m; x = IDFT(Y1 + i Y2) =
 // conj FFT(conj(Y1 + i Y2)) splits into the two real lines.
 
+// Uniform bounded axis (ax.dct): the basis is the cosine basis of the
+// Neumann operator, phi_m(j) = s_m cos(pi m (j + 1/2) / N) with s_0 = b,
+// s_m = a.  A line's coefficients come from one FFT of its even-odd
+// reordered sequence v (Makhoul's cosine transform): with Z = FFT(v1 + i v2)
+// of a line pair, V1_m = (Z_m + conj Z_{N-m}) / 2, V2_m = (Z_m - conj
+// Z_{N-m}) / (2 i) and t_m = pi m / (2N),
+//   X_m = cos t_m Re V_m + sin t_m Im V_m,  X_{N-m} = sin t_m Re V_m - cos t_m Im V_m,
+// and coefficient m = s_m X_m.  Back: with Y_m = s_m y_m, the sequence
+// v_n = sum_m Y_m cos(pi m (2n + 1/2) / N) (read back in the even-odd order)
+// is the inverse FFT of the Hermitian H_0 = Y_0, H_m = (1/2) e^{i t_m}
+// (Y_m - i Y_{N-m}), H_{N/2} = Y_{N/2} / sqrt 2, H_{N-m} = conj H_m; two
+// lines pack into D = H1 + i H2.  The twiddles (cos t_m, sin t_m) for
+// m <= N/2 come from the plan.
+
 // MODE 0: forward (lines -> basis coefficients), 1: inverse, 2: forward,
 // division by the eigenvalue sum, inverse.  N is the axis length.  ACC
 // (contiguous axis, MODE 1): pacc = pin + result, in double, instead of
@@ -271,13 +300,13 @@ __device__ __forceinline__ Cx<V>* fft_lines(Cx<V>* src, Cx<V>* dst, const Cx<V>*
 template <typename V, int N, bool XFAST, int MODE, bool ACC>
 __global__ void __launch_bounds__(kBlock)
 k_fft_axis(const V* __restrict__ X, V* __restrict__ Y, int inner, int64_t ncols, FftAxis ax,
-           const V* __restrict__ twg, FdmDiv dv, const int* stop, double* pacc,
-           const double* pin) {
+           const V* __restrict__ twg, const V* __restrict__ dtw, FdmDiv dv, const int* stop,
+           double* pacc, const double* pin) {
   static_assert(!ACC || (XFAST && MODE == 1), "accumulation is for the contiguous inverse");
   if (stop && *stop) {
     if constexpr (ACC) {
       if (pin != pacc) {
-        constexpr int L = FftCfg<V, XFAST>::LPB;
+        constexpr int L = FftCfg<V, XFAST, N>::LPB;
         const int64_t b0 = (int64_t)blockIdx.x * L * N;
         const int64_t left = ncols - (int64_t)blockIdx.x * L;
         const int64_t ne = (left < L ? left : L) * N;
@@ -287,7 +316,7 @@ k_fft_axis(const V* __restrict__ X, V* __restrict__ Y, int inner, int64_t ncols,
     return;
   }
   constexpr bool IL = !XFAST;
-  typedef FftCfg<V, XFAST> C;
+  typedef FftCfg<V, XFAST, N> C;
   constexpr int LPB = C::LPB, P = C::P;
   constexpr int VW = 16 / (int)sizeof(V);            // 16-byte global vectors
   typedef __attribute__((ext_vector_type(VW))) V vec_t;
@@ -368,15 +397,29 @@ k_fft_axis(const V* __restrict__ X, V* __restrict__ Y, int inner, int64_t ncols,
   // real row entry (l, c) in LDS, same layout rule as zidx
   auto ridx = [&](int l, int c) -> int { return IL ? c * LPB + l : l * N + c; };
   // LDS image of the block: real rows in bufB (MODE 1) or packed pairs in bufA
+  // (for the cosine transform the pairs in the even-odd order)
+  const bool dct = ax.dct != 0;
 #pragma unroll
   for (int u = 0; u < PT; ++u) {
     const int e = t + u * kBlock;
     if (NV % kBlock == 0 || e < NV) {
       if (IL) {
-        *reinterpret_cast<vec_t*>((MODE == 1 ? fB : fA) + e * VW) = rv[u][0];
+        if (MODE != 1 && dct) {
+          const int k = e / (LPB / VW), c = e - k * (LPB / VW);
+          *reinterpret_cast<vec_t*>(fA + (dct_pos<N>(k) * (LPB / VW) + c) * VW) = rv[u][0];
+        } else {
+          *reinterpret_cast<vec_t*>((MODE == 1 ? fB : fA) + e * VW) = rv[u][0];
+        }
       } else {
         const int p = e / KV, kv = e - p * KV;
-        if (MODE == 1) {
+        if (MODE != 1 && dct) {
+#pragma unroll
+          for (int j = 0; j < VW; ++j) {
+            V* d = fA + 2 * (p * N + dct_pos<N>(kv * VW + j));
+            d[0] = rv[u][0][j];
+            d[1] = rv[u][1][j];
+          }
+        } else if (MODE == 1) {
 #pragma unroll
           for (int h = 0; h < 2; ++h)
             *reinterpret_cast<vec_t*>(fB + (2 * p + h) * N + kv * VW) = rv[u][h];
@@ -407,6 +450,55 @@ k_fft_axis(const V* __restrict__ X, V* __restrict__ Y, int inner, int64_t ncols,
     if (IL) { p = e % P; m = e / P; } else { p = e / (H + 1); m = e - p * (H + 1); }
   };
   Cx<V>* spec = bufA;              // conj packed spectrum for the inverse
+  // cosine transform: coefficients m and N - m of the pair from Z_m, Z_{N-m}
+  // (times 2: the halves are in ha), in the order (line 2p: m, N-m; line
+  // 2p + 1: m, N-m)
+  auto dct_coef = [&](const Cx<V>* Z, int p, int m, V* q) {
+    const Cx<V> zm = Z[zidx<N, P, IL>(p, m)], zn = Z[zidx<N, P, IL>(p, N - m)];
+    const V c = dtw[2 * m], sn = dtw[2 * m + 1];
+    const V rv1 = zm.r + zn.r, iv1 = zm.i - zn.i, rv2 = zm.i + zn.i, iv2 = zn.r - zm.r;
+    q[0] = ha * (c * rv1 + sn * iv1);
+    q[1] = ha * (sn * rv1 - c * iv1);
+    q[2] = ha * (c * rv2 + sn * iv2);
+    q[3] = ha * (sn * rv2 - c * iv2);
+  };
+  const V hq = (V)(ax.a * 0.70710678118654752440);      // a cos(pi / 4)
+  if (MODE == 0 && dct) {
+    const Cx<V>* Z = fft_lines<V, N, P, IL>(bufA, bufB, tw);
+    V* rows = reinterpret_cast<V*>(Z == bufA ? bufB : bufA);
+    for (int e = t; e < NI; e += kBlock) {
+      int p, m;
+      item(e, p, m);
+      if (m == 0 || m == H) {
+        const Cx<V> z = Z[zidx<N, P, IL>(p, m)];
+        const V sc = m == 0 ? hb : hq;
+        rows[ridx(2 * p, m)] = sc * z.r;
+        rows[ridx(2 * p + 1, m)] = sc * z.i;
+      } else {
+        V q[4];
+        dct_coef(Z, p, m, q);
+        rows[ridx(2 * p, m)] = q[0];
+        rows[ridx(2 * p, N - m)] = q[1];
+        rows[ridx(2 * p + 1, m)] = q[2];
+        rows[ridx(2 * p + 1, N - m)] = q[3];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+      const int e = t + u * kBlock;
+      if (NV % kBlock == 0 || e < NV) {
+#pragma unroll
+        for (int h = 0; h < LV; ++h) {
+          const int off = IL ? e * VW : (2 * (e / KV) + h) * N + (e % KV) * VW;
+          if (gvalid(e, h))
+            __builtin_nontemporal_store(*reinterpret_cast<const vec_t*>(rows + off),
+                                        reinterpret_cast<vec_t*>(Y + gaddr(e, h)));
+        }
+      }
+    }
+    return;
+  }
   if (MODE == 0) {
     const Cx<V>* Z = fft_lines<V, N, P, IL>(bufA, bufB, tw);
     V* rows = reinterpret_cast<V*>(Z == bufA ? bufB : bufA);
@@ -450,15 +542,55 @@ k_fft_axis(const V* __restrict__ X, V* __restrict__ Y, int inner, int64_t ncols,
     spec[zidx<N, P, IL>(p, m)] = Cx<V>{y1r + y2s, y1s - y2r};
     spec[zidx<N, P, IL>(p, N - m)] = Cx<V>{y1r - y2s, -(y1s + y2r)};
   };
-  if (MODE == 2) {
+  // cosine transform: packed conj spectrum entries m and N - m of pair p
+  // from the coefficients (y1m, y1n) of line 2p and (y2m, y2n) of line
+  // 2p + 1 at m and N - m (0 < m < N/2)
+  auto dct_put = [&](int p, int m, V y1m, V y1n, V y2m, V y2n) {
+    const V c = dtw[2 * m], sn = dtw[2 * m + 1];
+    const V h1r = ha * (y1m * c + y1n * sn), h1i = ha * (y1m * sn - y1n * c);
+    const V h2r = ha * (y2m * c + y2n * sn), h2i = ha * (y2m * sn - y2n * c);
+    spec[zidx<N, P, IL>(p, m)] = Cx<V>{h1r - h2i, -(h1i + h2r)};
+    spec[zidx<N, P, IL>(p, N - m)] = Cx<V>{h1r + h2i, h1i - h2r};
+  };
+  auto divd = [&](V v, int l, int c) -> V {
+    const double lr = lrest_s[l];
+    if (lr < 0.0 && c == 0) return V(0);
+    return v / (V)((lr < 0.0 ? 0.0 : lr) + lam_s[c]);
+  };
+  if (MODE == 2 && dct) {
+    const Cx<V>* Z = fft_lines<V, N, P, IL>(bufA, bufB, tw);
+    spec = Z == bufA ? bufB : bufA;
+    for (int e = t; e < NI; e += kBlock) {
+      int p, m;
+      item(e, p, m);
+      if (m == 0 || m == H) {
+        const Cx<V> z = Z[zidx<N, P, IL>(p, m)];
+        const V sc = m == 0 ? hb : hq;
+        const V y1 = divd(sc * z.r, 2 * p, m), y2 = divd(sc * z.i, 2 * p + 1, m);
+        spec[zidx<N, P, IL>(p, m)] = Cx<V>{sc * y1, -(sc * y2)};
+      } else {
+        V q[4];
+        dct_coef(Z, p, m, q);
+        dct_put(p, m, divd(q[0], 2 * p, m), divd(q[1], 2 * p, N - m), divd(q[2], 2 * p + 1, m),
+                divd(q[3], 2 * p + 1, N - m));
+      }
+    }
+  } else if (MODE == 1 && dct) {
+    for (int e = t; e < NI; e += kBlock) {
+      int p, m;
+      item(e, p, m);
+      if (m == 0 || m == H) {
+        const V sc = m == 0 ? hb : hq;
+        spec[zidx<N, P, IL>(p, m)] = Cx<V>{sc * fB[ridx(2 * p, m)], -(sc * fB[ridx(2 * p + 1, m)])};
+      } else {
+        dct_put(p, m, fB[ridx(2 * p, m)], fB[ridx(2 * p, N - m)], fB[ridx(2 * p + 1, m)],
+                fB[ridx(2 * p + 1, N - m)]);
+      }
+    }
+  } else if (MODE == 2) {
     const Cx<V>* Z = fft_lines<V, N, P, IL>(bufA, bufB, tw);
     spec = Z == bufA ? bufB : bufA;
     // spectrum -> basis coefficients -> division -> packed conj spectrum
-    auto divd = [&](V v, int l, int c) -> V {
-      const double lr = lrest_s[l];
-      if (lr < 0.0 && c == 0) return V(0);
-      return v / (V)((lr < 0.0 ? 0.0 : lr) + lam_s[c]);
-    };
     for (int e = t; e < NI; e += kBlock) {
       int p, m;
       item(e, p, m);
@@ -498,22 +630,36 @@ k_fft_axis(const V* __restrict__ X, V* __restrict__ Y, int inner, int64_t ncols,
     const int e = t + u * kBlock;
     if (NV % kBlock == 0 || e < NV) {
       if (IL) {
-        vec_t v = *reinterpret_cast<const vec_t*>(fr + e * VW);
+        int off = e * VW;
+        if (dct) {
+          const int k = e / (LPB / VW), c = e - k * (LPB / VW);
+          off = (dct_pos<N>(k) * (LPB / VW) + c) * VW;
+        }
+        vec_t v = *reinterpret_cast<const vec_t*>(fr + off);
 #pragma unroll
         for (int j = 1; j < VW; j += 2) v[j] = -v[j];
         __builtin_nontemporal_store(v, reinterpret_cast<vec_t*>(Y + gaddr(e, 0)));
       } else {
         const int p = e / KV, kv = e - p * KV;
-        const V* s = fr + 2 * (p * N + kv * VW);
-        const vec_t lo = *reinterpret_cast<const vec_t*>(s);
-        const vec_t hi = *reinterpret_cast<const vec_t*>(s + VW);
         vec_t x1, x2;
+        if (dct) {
 #pragma unroll
-        for (int j = 0; j < VW / 2; ++j) {
-          x1[j] = lo[2 * j];
-          x2[j] = -lo[2 * j + 1];
-          x1[j + VW / 2] = hi[2 * j];
-          x2[j + VW / 2] = -hi[2 * j + 1];
+          for (int j = 0; j < VW; ++j) {
+            const V* q = fr + 2 * (p * N + dct_pos<N>(kv * VW + j));
+            x1[j] = q[0];
+            x2[j] = -q[1];
+          }
+        } else {
+          const V* s = fr + 2 * (p * N + kv * VW);
+          const vec_t lo = *reinterpret_cast<const vec_t*>(s);
+          const vec_t hi = *reinterpret_cast<const vec_t*>(s + VW);
+#pragma unroll
+          for (int j = 0; j < VW / 2; ++j) {
+            x1[j] = lo[2 * j];
+            x2[j] = -lo[2 * j + 1];
+            x1[j + VW / 2] = hi[2 * j];
+            x2[j + VW / 2] = -hi[2 * j + 1];
+          }
         }
         if constexpr (ACC) {
           dvec_t q1 = pv[u][0], q2 = pv[u][LV - 1];
@@ -534,7 +680,8 @@ k_fft_axis(const V* __restrict__ X, V* __restrict__ Y, int inner, int64_t ncols,
 }
 
 // Axis lengths with an FFT kernel (every one factors into 2, 3, 5).
-#define FVIB_FFT_SIZES(X) X(24) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(256)
+#define FVIB_FFT_SIZES(X) X(24) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(256) X(384) X(512) \
+  X(768) X(1024)
 
 static bool fft_size_supported(int n) {
 #define FVIB_FFT_IS(NN) if (n == NN) return true;
@@ -548,6 +695,7 @@ FftAxis fft_plan(int n, double h) {
   ax.a = sqrt(2.0 / n) / sqrt(h);
   ax.b = 1.0 / sqrt(n * h);
   ax.on = fft_size_supported(n) ? 1 : 0;
+  ax.dct = 0;
   return ax;
 }
 
@@ -566,12 +714,12 @@ int launch_fft_axis(const FdmPlan<V>& F, int a, int mode, const V* in, V* out, c
   const int64_t ncols = outer * inner;
   if (acc && !(inner == 1 && mode == 1)) return FVIB_EINVAL;
   if (inner == 1 && mode == 2) return FVIB_EINVAL;
-  constexpr int LPBc = FftCfg<V, true>::LPB, LPBs = FftCfg<V, false>::LPB;
-  const dim3 gc((unsigned)((ncols + LPBc - 1) / LPBc)), gs((unsigned)((ncols + LPBs - 1) / LPBs));
   bool done = false;
 #define FVIB_FFT(NN, XF, M, AC)                                                                 \
-  launch_kernel((k_fft_axis<V, NN, XF, M, AC>), XF ? gc : gs, dim3(kBlock), 0, s, in, out,      \
-                inner, ncols, F.fft[a], F.tw[a], F.div, stop, acc, accin)
+  launch_kernel((k_fft_axis<V, NN, XF, M, AC>),                                                 \
+                dim3((unsigned)((ncols + FftCfg<V, XF, NN>::LPB - 1) / FftCfg<V, XF, NN>::LPB)),  \
+                dim3(kBlock), 0, s, in, out, inner, ncols, F.fft[a], F.tw[a], F.dtw[a], F.div,  \
+                stop, acc, accin)
 #define FVIB_FFT_N(NN)                                                                          \
   if (!done && N == NN) {                                                                       \
     done = true;                                                                                \
@@ -599,8 +747,14 @@ bool fft_usable(const FdmPlan<V>& F, int a) {
   if (!F.fft[a].on || !fft_size_supported(F.n[a])) return false;
   int inner = 1;
   for (int q = 0; q < a; ++q) inner *= F.n[q];
-  return inner == 1 || inner % FftCfg<V, false>::LPB == 0;
+  int lpb = 0;
+#define FVIB_FFT_LPB(NN) if (F.n[a] == NN) lpb = FftCfg<V, false, NN>::LPB;
+  FVIB_FFT_SIZES(FVIB_FFT_LPB)
+#undef FVIB_FFT_LPB
+  return inner == 1 || (lpb > 0 && inner % lpb == 0);
 }
+
+bool fft_size_ok(int n) { return fft_size_supported(n); }
 
 template int launch_fft_axis<float>(const FdmPlan<float>&, int, int, const float*, float*,
                                     const int*, hipStream_t, double*, const double*);
