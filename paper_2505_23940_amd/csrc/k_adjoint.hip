@@ -196,22 +196,26 @@ k_adj_fbar(IbGeo B, const double* __restrict__ st, const SolverScalars* sc, T* _
   const int n0 = B.W[0][0] * B.W[0][1];
   const int n1 = B.W[1][0] * B.W[1][1];
   const double h = B.h;
-  for (int t = blockIdx.x * kBlock + threadIdx.x; t < n0 + n1; t += gridDim.x * kBlock) {
+  // one wavefront per window face, its lanes over the markers
+  const int lane = threadIdx.x & 63;
+  const int wpb = kBlock / 64;
+  for (int t = blockIdx.x * wpb + (threadIdx.x >> 6); t < n0 + n1; t += gridDim.x * wpb) {
     const int c = (t < n0) ? 0 : 1;
     const int l = (c == 0) ? t : t - n0;
     if (!B.cls[c][l]) {
-      fbar[c][l] = T(0);
+      if (lane == 0) fbar[c][l] = T(0);
       continue;
     }
     const int li = l % B.W[c][0], lj = l / B.W[c][0];
     const int i = B.origin[2 * c] + li, j = B.origin[2 * c + 1] + lj;
     const double px = B.fx[c][i], py = B.fy[c][j];
     double s = 0.0;
-    for (int k = 0; k < B.M; ++k) {
+    for (int k = lane; k < B.M; k += 64) {
       const double Xx = B.X0[2 * k] + st[0], Xy = B.X0[2 * k + 1] + st[1];
       s += B.ds[k] * h * dh(px - Xx, h) * dh(py - Xy, h);
     }
-    fbar[c][l] = (T)(-B.rho * h * h * sc->force[c] * s);
+    s = wave_sum(s);
+    if (lane == 0) fbar[c][l] = (T)(-B.rho * h * h * sc->force[c] * s);
   }
 }
 
@@ -1455,7 +1459,7 @@ int launch_adj_body_loads(const IbGeo& B, const IbView<T>& ib, const double* st_
                 stbar_out, dF, kc, stbar_rk, stbar_pos, kcbar, sc, parts);
   FVIB_HIP(hipGetLastError());
   const int n = B.W[0][0] * B.W[0][1] + B.W[1][0] * B.W[1][1];
-  launch_kernel((k_adj_fbar<T>), dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, B, st_pos,
+  launch_kernel((k_adj_fbar<T>), dim3((n + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, s, B, st_pos,
                      (const SolverScalars*)sc, (T*)ib.f[0], (T*)ib.f[1]);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;

@@ -10,7 +10,9 @@
 //
 // Target velocity on IB points: the marker velocity interpolated with the
 // normalised 4-point-kernel weights w_k = delta_h(x - X_k) dV_k
-// (Eqs. 18-19, Shepard form); on solid points the body velocity (Eq. 23).
+// (Eqs. 18-19, Shepard form), which for a rigid body (every marker moving
+// with the body velocity) is the body velocity itself, written directly;
+// on solid points the body velocity (Eq. 23).
 //
 // Loads (Eq. 20): q_k = -sum_x f(x) delta_h(x - X_k) h^2 over forced faces,
 // F = rho sum_k q_k dV_k with dV_k = ds_k h; then classic RK4 of
@@ -45,11 +47,14 @@ __device__ __forceinline__ void window_origin(const IbGeo& B, const double* body
   *clamped = *clamped || cl;
 }
 
-__device__ bool inside_polygon(const IbGeo& B, double dxb, double dyb, double px, double py) {
+// Crossing parity of the polygon edges k0, k0 + dk, ... with the ray from
+// (px, py) towards +x (the parity over all edges decides inside).
+__device__ bool crossings_odd(const IbGeo& B, double dxb, double dyb, double px, double py,
+                              int k0, int dk) {
 #pragma clang fp contract(off)
   bool inside = false;
   const int M = B.M;
-  for (int k = 0; k < M; ++k) {
+  for (int k = k0; k < M; k += dk) {
     const int kn = (k + 1 == M) ? 0 : k + 1;
     const double ax = B.X0[2 * k] + dxb, ay = B.X0[2 * k + 1] + dyb;
     const double bx = B.X0[2 * kn] + dxb, by = B.X0[2 * kn + 1] + dyb;
@@ -63,7 +68,9 @@ __device__ bool inside_polygon(const IbGeo& B, double dxb, double dyb, double px
   return inside;
 }
 
-// pass 1: solid flags inside the window, and the window origins
+// pass 1: solid flags inside the window, and the window origins.  One
+// wavefront per window face; its lanes take every 64th polygon edge and the
+// crossing parities combine through a ballot.
 __global__ void __launch_bounds__(kBlock)
 k_ib_solid(IbGeo B, const double* __restrict__ body, SolverScalars* sc) {
   int org[4];
@@ -76,17 +83,23 @@ k_ib_solid(IbGeo B, const double* __restrict__ body, SolverScalars* sc) {
   }
   const int n0 = B.W[0][0] * B.W[0][1];
   const int n1 = B.W[1][0] * B.W[1][1];
-  for (int t = blockIdx.x * kBlock + threadIdx.x; t < n0 + n1; t += gridDim.x * kBlock) {
+  const int lane = threadIdx.x & 63;
+  const int wpb = kBlock / 64;
+  for (int t = blockIdx.x * wpb + (threadIdx.x >> 6); t < n0 + n1; t += gridDim.x * wpb) {
     const int c = (t < n0) ? 0 : 1;
     const int l = (c == 0) ? t : t - n0;
     const int li = l % B.W[c][0], lj = l / B.W[c][0];
     const int i = org[2 * c] + li, j = org[2 * c + 1] + lj;
-    const bool in = inside_polygon(B, body[0], body[1], B.fx[c][i], B.fy[c][j]);
-    B.cls[c][l] = in ? 1 : 0;
+    const bool odd = crossings_odd(B, body[0], body[1], B.fx[c][i], B.fy[c][j], lane, 64);
+    const unsigned long long bal = __ballot(odd ? 1 : 0);
+    if (lane == 0) B.cls[c][l] = (__popcll(bal) & 1) ? 1 : 0;
   }
 }
 
-// pass 2: immersed-boundary points and target velocities
+// pass 2: immersed-boundary points and target velocities.  Every marker of
+// a rigid body moves with the body velocity, so the normalised
+// interpolation of Eqs. 18-19 returns that velocity exactly: the target of
+// an IB point is the body velocity, as on solid points (Eq. 23).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_ib_targets(IbGeo B, const double* __restrict__ body, T* __restrict__ us0,
@@ -94,7 +107,6 @@ k_ib_targets(IbGeo B, const double* __restrict__ body, T* __restrict__ us0,
   T* us[2] = {us0, us1};
   const int n0 = B.W[0][0] * B.W[0][1];
   const int n1 = B.W[1][0] * B.W[1][1];
-  const double dxb = body[0], dyb = body[1];
   for (int t = blockIdx.x * kBlock + threadIdx.x; t < n0 + n1; t += gridDim.x * kBlock) {
     const int c = (t < n0) ? 0 : 1;
     const int l = (c == 0) ? t : t - n0;
@@ -110,16 +122,7 @@ k_ib_targets(IbGeo B, const double* __restrict__ body, T* __restrict__ us0,
                     (lj > 0 && cl[l - Wx] == 1) || (lj + 1 < Wy && cl[l + Wx] == 1);
     if (!nb) continue;
     B.cls[c][l] = 2;
-    const int i = B.origin[2 * c] + li, j = B.origin[2 * c + 1] + lj;
-    const double px = B.fx[c][i], py = B.fy[c][j];
-    double num = 0.0, den = 0.0;
-    for (int k = 0; k < B.M; ++k) {
-      const double Xx = B.X0[2 * k] + dxb, Xy = B.X0[2 * k + 1] + dyb;
-      const double w = d_h(px - Xx, B.h) * d_h(py - Xy, B.h) * (B.ds[k] * B.h);
-      num += w * Uc;
-      den += w;
-    }
-    us[c][l] = (T)((den > 0.0) ? num / den : Uc);
+    us[c][l] = (T)Uc;
   }
 }
 
@@ -264,7 +267,9 @@ int launch_ib_classify(const IbGeo& B, const double* body, T* us0, T* us1, Solve
                        hipStream_t s) {
   const int n = B.W[0][0] * B.W[0][1] + B.W[1][0] * B.W[1][1];
   const int nb = (n + kBlock - 1) / kBlock;
-  launch_kernel(k_ib_solid, dim3(nb), dim3(kBlock), 0, s, B, body, sc);
+  // the polygon test takes one wavefront per window face
+  launch_kernel(k_ib_solid, dim3((n + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, s, B,
+                body, sc);
   FVIB_HIP(hipGetLastError());
   launch_kernel((k_ib_targets<T>), dim3(nb), dim3(kBlock), 0, s, B, body, us0, us1);
   FVIB_HIP(hipGetLastError());
