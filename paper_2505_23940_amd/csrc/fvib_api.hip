@@ -5,7 +5,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstring>
 #include <functional>
 #include <string>
 #include <vector>
@@ -139,6 +141,12 @@ struct Grid {
   SolverScalars* sc = nullptr;
   SolverScalars* sch = nullptr;   // pinned host mirror
   SolverScalars* sch_dev = nullptr;  // its device address
+  // coherent pinned word the refinement checks post their outcome to (see
+  // wait_refinement); nullptr: checks wait on an event and read sch
+  unsigned long long* tick_h = nullptr;
+  unsigned long long* tick_d = nullptr;   // its device address
+  unsigned int tick_seq = 0;              // last ticket handed out
+  bool solve_enoconv = false;   // the last Poisson solve ran out of refinement sweeps
   int* sticky_h = nullptr;        // pinned: a step record's failed status lands here
   int* sticky_d = nullptr;        // its device address
   int sticky = 0;                 // failed status returned by later calls
@@ -242,6 +250,7 @@ static void release(Grid* g) {
   f(g->fdm_d);
   f(g->fdm_f);
   if (g->sch) (void)hipHostFree(g->sch);
+  if (g->tick_h) (void)hipHostFree(g->tick_h);
   if (g->sticky_h) (void)hipHostFree(g->sticky_h);
   f(g->ib_mem);
   f(g->origin);
@@ -579,6 +588,40 @@ static int read_scalars(Grid* g) {
   return rc ? rc : wait_check(g);
 }
 
+// Outcome of the refinement check of the residual launched with ticket t.
+// With the coherent word, the host polls it: the residual's epilogue posts
+// the ticket and the outcome in one store, and no event is recorded (an
+// event's completion fence idles the device before the work queued behind
+// the check).  A post that has not arrived within two seconds falls back to
+// a stream synchronisation and the mirror, as does a handle without the
+// word (after the event).
+static int wait_refinement(Grid* g, unsigned int t, bool* done, int* sweeps, double* crit) {
+  if (g->tick_h) {
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned int n = 1;; ++n) {
+      const unsigned long long w = __atomic_load_n(g->tick_h, __ATOMIC_ACQUIRE);
+      if ((unsigned int)(w >> 40) == (t & 0xFFFFFFu)) {
+        const unsigned int cb = (unsigned int)(w & 0xFFFFFFFFull);
+        float cf;
+        std::memcpy(&cf, &cb, sizeof(cf));
+        *crit = cf;
+        *sweeps = (int)((w >> 32) & 127u);
+        *done = ((w >> 39) & 1u) != 0;
+        return FVIB_OK;
+      }
+      if ((n & 4095u) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2))
+        break;
+    }
+    FVIB_HIP(hipStreamSynchronize(g->stream));
+  } else if (int rc = wait_check(g)) {
+    return rc;
+  }
+  *crit = g->sch->crit;
+  *sweeps = g->sch->sweeps;
+  *done = g->sch->outer_done != 0;
+  return FVIB_OK;
+}
+
 // Solve A p = b - mean(b) in place on p (initial guess on input); meanb
 // must already be in the device scalars.
 // gauge: remove the mean of the fast-diagonalisation result (the pressure
@@ -614,6 +657,7 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
     }
   } restore{g, last, saved};
   g->crit_log.clear();
+  g->solve_enoconv = false;
   if (g->d.solver == FVIB_SOLVER_FDM) {
     // Refinement sweeps are launched ahead of the host's convergence check
     // (as many as the previous solve of this kind needed); once the
@@ -624,11 +668,14 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
     int launched = 0;              // sweeps launched since the last restart
     // the first residual and the first correction read the guess in p_in;
     // the correction writes p (carrying p_in over if the sweep is skipped)
+    unsigned int expect = 0;       // ticket of the last sweep residual launched
     auto residual = [&](int first) {
+      const unsigned int tk = first ? 0u : ++g->tick_seq;
+      if (!first) expect = tk;
       return timed(g, FVIB_K_RESIDUAL, [&] {
         return launch_residual(g->P64, d64 ? 3 : 2, b, first ? p_in : p, g->r64, g->r32,
                                nullptr, g->red(), g->sc, tol, 0.5, g->stream, first,
-                               g->sch_dev);
+                               g->sch_dev, first ? nullptr : g->tick_d, tk);
       });
     };
     auto sweep = [&]() -> int {
@@ -689,23 +736,26 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
     launched = 0;
     int batch = std::max(1, std::min(g->last_iters, g->d.ir_maxit));
     double prev_crit = HUGE_VAL;
+    bool done = false;
+    int dsweeps = 0;
     for (;;) {
       for (int q = 0; q < batch && launched < g->d.ir_maxit; ++q, ++launched)
         if ((rc = sweep())) return rc;
       g->timer.tag = 0;
       // every sweep ends with a residual, whose epilogue (unless skipped
       // after the refinement finished, leaving the scalars unchanged)
-      // copies the scalars into the host mirror: the check only records
-      // an event
-      if ((rc = enqueue_check(g, true))) return rc;
+      // copies the scalars into the host mirror and posts the check's
+      // outcome: without the posted word the check records an event
+      if (!g->tick_h && (rc = enqueue_check(g, true))) return rc;
       if (gauge &&
           (rc = timed(g, FVIB_K_IR_CORRECT, [&] { return launch_gauge(g->ncell, p, g->sc, g->stream); })))
         return rc;
       if (tail && (rc = (*tail)())) return rc;
-      if ((rc = wait_check(g))) return rc;
-      g->crit_log.push_back(g->sch->crit);
-      if (g->sch->outer_done) break;
-      if (warm && !(g->sch->crit < 0.1 * prev_crit)) {
+      double crit = 0.0;
+      if ((rc = wait_refinement(g, expect, &done, &dsweeps, &crit))) return rc;
+      g->crit_log.push_back(crit);
+      if (done) break;
+      if (warm && !(crit < 0.1 * prev_crit)) {
         // the guess has stalled the refinement: restart from zero with the
         // full budget
         warm = false;
@@ -717,18 +767,20 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
         batch = 2;
         continue;
       }
-      prev_crit = g->sch->crit;
+      prev_crit = crit;
       if (launched >= g->d.ir_maxit) {
         // refinement budget exhausted: report it on the device scalars
         int stc = FVIB_ENOCONV;
         FVIB_HIP(hipMemcpyAsync(&g->sc->status, &stc, sizeof(int), hipMemcpyHostToDevice, g->stream));
         FVIB_HIP(hipStreamSynchronize(g->stream));
         g->sch->status = FVIB_ENOCONV;
+        g->solve_enoconv = true;
         break;
       }
       batch = 1;
     }
-    const int sweeps = g->sch->outer_done ? g->sch->sweeps : launched;
+    // (the posted count saturates at 127)
+    const int sweeps = done ? (dsweeps < 127 ? dsweeps : launched) : launched;
     g->timer.end_solve(sweeps);
     g->last_iters = sweeps;
     *cg_total = 0;
@@ -749,6 +801,7 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
     if (rc) return rc;
     *cg_total = it;
     g->last_iters = it;
+    g->solve_enoconv = g->sch->status == FVIB_ENOCONV;
     return FVIB_OK;
   }
   int total = 0;
@@ -783,6 +836,7 @@ static int poisson_solve(Grid* g, const double* b, double* p, double tol, int* l
   }
   *cg_total = total;
   *ir_total = sweeps;
+  g->solve_enoconv = g->sch->status == FVIB_ENOCONV;
   return FVIB_OK;
 }
 
@@ -878,10 +932,7 @@ static LesView<T> les_view(Grid* g) {
   return v;
 }
 
-static int reset_scalars(Grid* g) {
-  FVIB_HIP(hipMemsetAsync(g->sc, 0, sizeof(SolverScalars), g->stream));
-  return FVIB_OK;
-}
+static int reset_scalars(Grid* g) { return launch_zero_scalars(g->sc, g->stream); }
 
 // A device-side failure (no convergence, non-finite reduction, body window
 // left) is sticky: the call that meets it returns it, and so does every
@@ -1056,7 +1107,7 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
                           in->p, fdm ? &project : nullptr, fuse_rhs)))
     return rc;
   g->last_iters = last;
-  if (g->defer && g->sch->status == FVIB_ENOCONV)
+  if (g->defer && g->solve_enoconv)
     return device_fail(g, FVIB_ENOCONV,
                        "Poisson solve did not reach poisson_tol" + describe_solve(g, g->d.poisson_tol));
   if (!fdm && (rc = project())) return rc;
@@ -1080,7 +1131,7 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
     if (rc) return rc;
   }
   // (a status the host set after the last projection still needs the copy)
-  if ((!rec || g->sch->status == FVIB_ENOCONV) &&
+  if ((!rec || g->solve_enoconv) &&
       (rc = launch_copy_info(g->sc, dst, cg, ir, g->stream, nullptr, nullptr, g->sticky_d, cpl)))
     return rc;
   if (g->defer) {                // status only in the info record
@@ -1188,7 +1239,7 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
   if ((rc = poisson_solve(g, g->b, mu, -1.0, &g->last_iters_adj, &cg, &ir, false, warm, nullptr,
                           fdm ? &ustar : nullptr, fuse_rhs)))
     return rc;
-  if (g->defer && g->sch->status == FVIB_ENOCONV)
+  if (g->defer && g->solve_enoconv)
     return device_fail(g, FVIB_ENOCONV, "adjoint Poisson solve did not converge" +
                                             describe_solve(g, g->sch->tol_dev));
   if (!fdm && (rc = ustar())) return rc;
@@ -1455,7 +1506,7 @@ static int strong_adjoint_impl(Grid* g, const fvib_fields* in, const double* om,
   if ((rc = poisson_solve(g, g->b, mu, -1.0, &g->last_iters_adj, &cg, &ir, false, warm, nullptr,
                           fdm ? &ustar : nullptr)))
     return rc;
-  if (g->defer && g->sch->status == FVIB_ENOCONV)
+  if (g->defer && g->solve_enoconv)
     return device_fail(g, FVIB_ENOCONV, "adjoint Poisson solve did not converge" +
                                             describe_solve(g, g->sch->tol_dev));
   if (!fdm && (rc = ustar())) return rc;
@@ -1772,6 +1823,18 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
     return bail(FVIB_ENOMEM, "pinned host allocation failed");
   if (hipHostGetDevicePointer((void**)&g->sch_dev, g->sch, 0) != hipSuccess)
     return bail(FVIB_EHIP, "no device address for the pinned solver scalars");
+  // without a coherent word the checks fall back to events
+  if (hipHostMalloc((void**)&g->tick_h, sizeof(unsigned long long), hipHostMallocCoherent) ==
+      hipSuccess) {
+    *g->tick_h = 0ull;
+    if (hipHostGetDevicePointer((void**)&g->tick_d, g->tick_h, 0) != hipSuccess) {
+      (void)hipHostFree(g->tick_h);
+      g->tick_h = nullptr;
+      g->tick_d = nullptr;
+    }
+  } else {
+    g->tick_h = nullptr;
+  }
   if (hipHostMalloc((void**)&g->sticky_h, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess)
     return bail(FVIB_ENOMEM, "pinned host allocation failed");
   g->sticky_h[0] = g->sticky_h[1] = 0;

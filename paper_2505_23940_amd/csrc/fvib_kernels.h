@@ -162,10 +162,14 @@ int launch_ppe_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
 // does nothing once the device scalars say the refinement is finished.
 // mirror (nullable): device address of a pinned host SolverScalars that
 // receives a copy of the scalars whenever the launch is not skipped.
+// tick (nullable): device address of a coherent pinned 64-bit word that
+// receives, skipped or not, ticket (low 24 bits) << 40 | converged << 39 |
+// min(sweeps, 127) << 32 | the criterion as float bits, in one store.
 int launch_residual(const PGeo<double>& P, int mode, const double* b, const double* x,
                     double* r64, float* r32, float* d32, RedBuf red, SolverScalars* sc,
                     double tol, double inner_rtol, hipStream_t s, int first = 1,
-                    SolverScalars* mirror = nullptr);
+                    SolverScalars* mirror = nullptr, unsigned long long* tick = nullptr,
+                    unsigned int ticket = 0);
 // ev (nullable): three events recorded before the direction kernel, between
 // the two kernels and after the update kernel.
 template <typename V>
@@ -214,6 +218,7 @@ int launch_loads_body(const IbGeo& B, const IbView<T>& ib, const double* body_po
                       const double* Fin, int xi, SolverScalars* sc, hipStream_t s);
 // Step record from the solver scalars; a failed status is also stored in
 // *sticky (nullable).
+int launch_zero_scalars(SolverScalars* sc, hipStream_t s);
 int launch_copy_info(const SolverScalars* sc, fvib_step_info* info, int cg_iters, int ir_iters,
                      hipStream_t s, const double* body_src = nullptr, double* body_dst = nullptr,
                      int* sticky = nullptr, int cpl_iters = 0);

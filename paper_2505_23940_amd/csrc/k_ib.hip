@@ -286,6 +286,20 @@ int launch_loads_body(const IbGeo& B, const IbView<T>& ib, const double* body_po
   return FVIB_OK;
 }
 
+// The solver scalars cleared at the start of a step: one small launch in
+// place of a runtime fill (which issues two fill kernels for this size).
+__global__ void k_zero_scalars(SolverScalars* sc) {
+  constexpr int kWords = (int)(sizeof(SolverScalars) / sizeof(uint32_t));
+  static_assert(sizeof(SolverScalars) % sizeof(uint32_t) == 0 && kWords <= 64, "one wavefront");
+  if (threadIdx.x < kWords) reinterpret_cast<uint32_t*>(sc)[threadIdx.x] = 0u;
+}
+
+int launch_zero_scalars(SolverScalars* sc, hipStream_t s) {
+  launch_kernel(k_zero_scalars, dim3(1), dim3(64), 0, s, sc);
+  FVIB_HIP(hipGetLastError());
+  return FVIB_OK;
+}
+
 int launch_copy_info(const SolverScalars* sc, fvib_step_info* info, int cg_iters, int ir_iters,
                      hipStream_t s, const double* body_src, double* body_dst, int* sticky,
                      int cpl_iters) {

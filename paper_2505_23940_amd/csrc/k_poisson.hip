@@ -93,7 +93,24 @@ struct FinResidual {        // start of a solve / refinement sweep
   double tol, inner_rtol, dt_over_rho;
   int first;                // first residual of the solve (never skipped)
   SolverScalars* mirror;    // nullable: device view of the host's pinned copy
-  __device__ bool skip(const SolverScalars* sc) const { return !first && sc->outer_done; }
+  // nullable: a coherent pinned word the host polls for this check: one
+  // 64-bit store (no fence) of the ticket with the check's outcome
+  unsigned long long* tick;
+  unsigned int ticket;
+  __device__ void post(const SolverScalars* sc) const {
+    unsigned long long w = (unsigned long long)__float_as_uint((float)sc->crit);
+    w |= (unsigned long long)(sc->sweeps < 127 ? sc->sweeps : 127) << 32;
+    w |= (unsigned long long)(sc->outer_done ? 1 : 0) << 39;
+    w |= (unsigned long long)(ticket & 0xFFFFFFu) << 40;
+    __hip_atomic_store(tick, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  // a sweep queued after the refinement finished is skipped, but still
+  // answers its ticket (with the finished solve's outcome)
+  __device__ bool skip(const SolverScalars* sc) const {
+    const bool s = !first && sc->outer_done;
+    if (s && tick && threadIdx.x == 0) post(sc);
+    return s;
+  }
   __device__ void apply(const double* t, SolverScalars* sc) const {
     sc->sweeps = first ? 0 : sc->sweeps + 1;
     const double crit = t[2] * dt_over_rho;
@@ -113,6 +130,7 @@ struct FinResidual {        // start of a solve / refinement sweep
     // the host's check reads the scalars once the stream has passed this
     // kernel (completion makes the stores visible to it)
     if (mirror) *mirror = *sc;
+    if (tick) post(sc);
   }
 };
 
@@ -749,7 +767,7 @@ int launch_ppe_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
 int launch_residual(const PGeo<double>& P, int mode, const double* b, const double* x,
                     double* r64, float* r32, float* d32, RedBuf red, SolverScalars* sc,
                     double tol, double inner_rtol, hipStream_t s, int first,
-                    SolverScalars* mirror) {
+                    SolverScalars* mirror, unsigned long long* tick, unsigned int ticket) {
   const ColTiling ct = make_col_tiling(P.n[0], P.n[1], P.n[2]);
   dim3 g(ct.nblocks), bl(kBlock);
 #define FVIB_RES(D, M)                                                                        \
@@ -757,7 +775,8 @@ int launch_residual(const PGeo<double>& P, int mode, const double* b, const doub
                      first);                                                                    \
   FVIB_HIP(hipGetLastError());                                                                  \
   FVIB_HIP((launch_finish<3, 2>(red.partial, ct.nblocks, sc,                                    \
-                                FinResidual<M>{tol, inner_rtol, P.dt_over_rho, first, mirror}, s)))
+                                FinResidual<M>{tol, inner_rtol, P.dt_over_rho, first, mirror,  \
+                                               tick, ticket}, s)))
   if (P.dim == 2) {
     switch (mode) {
       case 0: FVIB_RES(2, 0); break;
