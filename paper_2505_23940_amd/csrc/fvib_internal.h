@@ -330,6 +330,27 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
   __syncthreads();
 }
 
+// As block_sum for a block of NT threads (a multiple of 64).
+template <int NV, int NT>
+__device__ __forceinline__ void block_sum_n(double (&v)[NV]) {
+  __shared__ double sh[NV][NT / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double s = wave_sum(v[q]);
+    if (lane == 0) sh[q][w] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) s += sh[q][k];
+    v[q] = s;
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ double block_max(double v) {
   __shared__ double sh[kBlock / 64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;

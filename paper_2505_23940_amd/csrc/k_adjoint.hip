@@ -48,6 +48,10 @@ __device__ __forceinline__ double ddh(double r, double h) {
   return r < 0.0 ? -g : g;
 }
 
+// Threads of the body-load adjoint: its marker-position gather takes one
+// item per (marker, component, stencil row).
+constexpr int kAdjLoadsBlock = 1024;
+
 // ---------------------------------------------- RK4^T and loads^T (1 block)
 // The RK4 of the step starts from st_rk; the markers sit at st_pos (the
 // same state in a weakly coupled step; the converged structural iterate in
@@ -58,7 +62,7 @@ __device__ __forceinline__ double ddh(double r, double h) {
 // marker-position part of loads^T for that force adjoint, added into
 // stbar_pos[0..1].  The total force adjoint is left in sc->force.
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kAdjLoadsBlock)
 k_adj_body_loads(IbGeo B, IbView<T> ib, const double* st_rk, const double* st_pos,
                  const double* stbar_out, const double* __restrict__ dF,
                  const double* __restrict__ kc, double* stbar_rk, double* stbar_pos,
@@ -149,37 +153,36 @@ k_adj_body_loads(IbGeo B, IbView<T> ib, const double* st_rk, const double* st_po
   // marker-position part: dF_c/dX_k,a = rho h^2 dV_k sum_f f_f d(delta)/dr_a
   const double dxb = st_pos[0], dyb = st_pos[1];
   const double h = B.h;
+  // one item per (marker, component, stencil row), as the loads gather
   double g[2] = {0.0, 0.0};
-  for (int k = threadIdx.x; k < B.M; k += kBlock) {
+  for (int it = threadIdx.x; it < 8 * B.M; it += kAdjLoadsBlock) {
+    const int k = it >> 3, c = (it >> 2) & 1, dj = it & 3;
+    const double Fb = Fbar_s[c];
+    if (Fb == 0.0) continue;
     const double Xx = B.X0[2 * k] + dxb, Xy = B.X0[2 * k + 1] + dyb;
     const double dV = B.ds[k] * h;
-    for (int c = 0; c < 2; ++c) {
-      const double Fb = Fbar_s[c];
-      if (Fb == 0.0) continue;
-      const int i0 = (int)floor((Xx - B.fx[c][0]) / h) - 1;
-      const int j0 = (int)floor((Xy - B.fy[c][0]) / h) - 1;
-      const int ox = ib.origin[2 * c], oy = ib.origin[2 * c + 1];
-      double ax = 0.0, ay = 0.0;
-      for (int dj = 0; dj < 4; ++dj) {
-        const int lj = j0 + dj - oy;
-        if (lj < 0 || lj >= B.W[c][1]) continue;
-        const double ry = B.fy[c][j0 + dj] - Xy;
-        for (int di = 0; di < 4; ++di) {
-          const int li = i0 + di - ox;
-          if (li < 0 || li >= B.W[c][0]) continue;
-          const int l = lj * B.W[c][0] + li;
-          if (!ib.cls[c][l]) continue;
-          const double rx = B.fx[c][i0 + di] - Xx;
-          const double f = (double)ib.f[c][l];
-          ax += f * ddh(rx, h) * dh(ry, h);
-          ay += f * dh(rx, h) * ddh(ry, h);
-        }
-      }
-      g[0] += Fb * B.rho * h * h * dV * ax;
-      g[1] += Fb * B.rho * h * h * dV * ay;
+    const int i0 = (int)floor((Xx - B.fx[c][0]) / h) - 1;
+    const int j0 = (int)floor((Xy - B.fy[c][0]) / h) - 1;
+    const int ox = ib.origin[2 * c], oy = ib.origin[2 * c + 1];
+    const int lj = j0 + dj - oy;
+    if (lj < 0 || lj >= B.W[c][1]) continue;
+    const double ry = B.fy[c][j0 + dj] - Xy;
+    const double wy = dh(ry, h), gy = ddh(ry, h);
+    double ax = 0.0, ay = 0.0;
+    for (int di = 0; di < 4; ++di) {
+      const int li = i0 + di - ox;
+      if (li < 0 || li >= B.W[c][0]) continue;
+      const int l = lj * B.W[c][0] + li;
+      if (!ib.cls[c][l]) continue;
+      const double rx = B.fx[c][i0 + di] - Xx;
+      const double f = (double)ib.f[c][l];
+      ax += f * ddh(rx, h) * wy;
+      ay += f * dh(rx, h) * gy;
     }
+    g[0] += Fb * B.rho * h * h * dV * ax;
+    g[1] += Fb * B.rho * h * h * dV * ay;
   }
-  block_sum<2>(g);
+  block_sum_n<2, kAdjLoadsBlock>(g);
   if (threadIdx.x == 0) {
     stbar_pos[0] += g[0];
     stbar_pos[1] += g[1];
@@ -1455,7 +1458,7 @@ int launch_adj_body_loads(const IbGeo& B, const IbView<T>& ib, const double* st_
                           const double* st_pos, const double* stbar_out, const double* dF,
                           const double* kc, double* stbar_rk, double* stbar_pos, double* kcbar,
                           SolverScalars* sc, int parts, hipStream_t s) {
-  launch_kernel((k_adj_body_loads<T>), dim3(1), dim3(kBlock), 0, s, B, ib, st_rk, st_pos,
+  launch_kernel((k_adj_body_loads<T>), dim3(1), dim3(kAdjLoadsBlock), 0, s, B, ib, st_rk, st_pos,
                 stbar_out, dF, kc, stbar_rk, stbar_pos, kcbar, sc, parts);
   FVIB_HIP(hipGetLastError());
   const int n = B.W[0][0] * B.W[0][1] + B.W[1][0] * B.W[1][1];

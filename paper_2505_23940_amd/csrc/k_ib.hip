@@ -154,8 +154,13 @@ __device__ void body_rk4(const IbGeo& B, const double* st_in, const double* F,
 // the computed force.  With body_out and the coupling error requested
 // (xi != 0), sc->xi = |body_out - body_pos|^2 / max(|body_pos|^2, 1e-30):
 // the change of the structural iterate of a coupling sub-iteration.
+// The loads gather takes one item per (marker, component, stencil row):
+// kLoadsBlock threads, each summing its items' four faces, then one
+// block-wide sum (fixed order).
+constexpr int kLoadsBlock = 1024;
+
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kLoadsBlock)
 k_loads_body(IbGeo B, IbView<T> ib, const double* body_pos, const double* body_rk,
              double* body_out,
              const double* __restrict__ kc, const double* __restrict__ Fin, int xi,
@@ -164,31 +169,27 @@ k_loads_body(IbGeo B, IbView<T> ib, const double* body_pos, const double* body_r
   if (!Fin) {
     const double dxb = body_pos[0], dyb = body_pos[1];
     const double h = B.h;
-    for (int k = threadIdx.x; k < B.M; k += kBlock) {
+    for (int it = threadIdx.x; it < 8 * B.M; it += kLoadsBlock) {
+      const int k = it >> 3, c = (it >> 2) & 1, dj = it & 3;
       const double Xx = B.X0[2 * k] + dxb, Xy = B.X0[2 * k + 1] + dyb;
       const double dV = B.ds[k] * h;
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const int i0 = (int)floor((Xx - B.fx[c][0]) / h) - 1;
-        const int j0 = (int)floor((Xy - B.fy[c][0]) / h) - 1;
-        const int ox = ib.origin[2 * c], oy = ib.origin[2 * c + 1];
-        double acc = 0.0;
-        for (int dj = 0; dj < 4; ++dj) {
-          const int lj = j0 + dj - oy;
-          if (lj < 0 || lj >= B.W[c][1]) continue;
-          const double wy = d_h(B.fy[c][j0 + dj] - Xy, h);
-          for (int di = 0; di < 4; ++di) {
-            const int li = i0 + di - ox;
-            if (li < 0 || li >= B.W[c][0]) continue;
-            const int l = lj * B.W[c][0] + li;
-            if (!ib.cls[c][l]) continue;
-            acc += (double)ib.f[c][l] * d_h(B.fx[c][i0 + di] - Xx, h) * wy;
-          }
-        }
-        q[c] += acc * (h * h) * dV;
+      const int i0 = (int)floor((Xx - B.fx[c][0]) / h) - 1;
+      const int j0 = (int)floor((Xy - B.fy[c][0]) / h) - 1;
+      const int ox = ib.origin[2 * c], oy = ib.origin[2 * c + 1];
+      const int lj = j0 + dj - oy;
+      if (lj < 0 || lj >= B.W[c][1]) continue;
+      const double wy = d_h(B.fy[c][j0 + dj] - Xy, h);
+      double acc = 0.0;
+      for (int di = 0; di < 4; ++di) {
+        const int li = i0 + di - ox;
+        if (li < 0 || li >= B.W[c][0]) continue;
+        const int l = lj * B.W[c][0] + li;
+        if (!ib.cls[c][l]) continue;
+        acc += (double)ib.f[c][l] * d_h(B.fx[c][i0 + di] - Xx, h) * wy;
       }
+      q[c] += acc * (h * h) * dV;
     }
-    block_sum<2>(q);
+    block_sum_n<2, kLoadsBlock>(q);
   }
   if (threadIdx.x != 0) return;
   double F[3] = {-B.rho * q[0], -B.rho * q[1], 0.0};
@@ -280,7 +281,7 @@ template <typename T>
 int launch_loads_body(const IbGeo& B, const IbView<T>& ib, const double* body_pos,
                       const double* body_rk, double* body_out, const double* kc,
                       const double* Fin, int xi, SolverScalars* sc, hipStream_t s) {
-  launch_kernel((k_loads_body<T>), dim3(1), dim3(kBlock), 0, s, B, ib, body_pos, body_rk,
+  launch_kernel((k_loads_body<T>), dim3(1), dim3(kLoadsBlock), 0, s, B, ib, body_pos, body_rk,
                 body_out, kc, Fin, xi, sc);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
