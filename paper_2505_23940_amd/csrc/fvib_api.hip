@@ -1065,16 +1065,16 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
        })))
     return rc;
   const bool fdm = g->d.solver == FVIB_SOLVER_FDM;
-  // 3D without a body: the right-hand side and the first residual of the
-  // refinement in one pass
-  const bool fuse_rhs = fdm && g->dim == 3 && !g->has_body;
+  // the right-hand side and the first residual of the refinement in one
+  // pass (fast diagonalisation; a 3D grid without a rigid body, or 2D)
+  const bool fuse_rhs = fdm && (g->dim == 2 || !g->has_body);
   if (fuse_rhs) {
     const bool d64 = g->prec == FVIB_PREC_FP64;
     if ((rc = timed(g, FVIB_K_RHS_RES, [&] {
            return launch_rhs_residual<T>(G, g->P64, (const T* const*)us, in->p, g->b,
                                          d64 ? g->r64 : nullptr, d64 ? nullptr : g->r32,
                                          g->red(), g->sc, g->d.poisson_tol, g->max_iv, g->stream,
-                                         g->sch_dev);
+                                         g->sch_dev, ib);
          })))
       return rc;
   } else if ((rc = timed(g, FVIB_K_PPE_RHS, [&] {
@@ -1119,9 +1119,10 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
       FVIB_HIP(hipMemcpyAsync(so->omega_out, body_f, 6 * sizeof(double),
                               hipMemcpyDeviceToDevice, g->stream));
   } else if (g->has_body) {
+    // the loads are the step's last launch: they also write its record
     rc = timed(g, FVIB_K_IB, [&] {
       return launch_loads_body<T>(g->ib, ib, in->body, in->body, out->body, in->kc, nullptr, 0,
-                                  g->sc, g->stream);
+                                  g->sc, g->stream, dst, cg, ir, g->sticky_d);
     });
     if (rc) return rc;
   } else if (g->has_box) {
@@ -1131,7 +1132,8 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
     if (rc) return rc;
   }
   // (a status the host set after the last projection still needs the copy)
-  if ((!rec || g->solve_enoconv) &&
+  const bool loads_rec = g->has_body && !strong;
+  if (!loads_rec && (!rec || g->solve_enoconv) &&
       (rc = launch_copy_info(g->sc, dst, cg, ir, g->stream, nullptr, nullptr, g->sticky_d, cpl)))
     return rc;
   if (g->defer) {                // status only in the info record

@@ -187,14 +187,16 @@ int launch_project(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
                    fvib_step_info* info = nullptr, int* sticky = nullptr,
                    const StageMix* mix = nullptr);
 int launch_apply_A(const PGeo<double>& P, const double* x, double* y, hipStream_t s);
-// 3D without a body, fast diagonalisation: the PPE right-hand side b and the
-// first refinement residual r = b - A x (r64 for the double inner solve, else
-// r32) in one pass; criterion max |r| / V + |mean b| max_iv.
+// Fast diagonalisation: the PPE right-hand side b and the first refinement
+// residual r = b - A x (r64 for the double inner solve, else r32) in one
+// pass; criterion max |r| / V + |mean b| max_iv.  2D grids take the immersed
+// body's forced faces from ib (as launch_ppe_rhs); a 3D grid accepts no
+// rigid body (a static box needs no change of the right-hand side).
 template <typename T>
 int launch_rhs_residual(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
                         const double* x, double* b, double* r64, float* r32, RedBuf red,
                         SolverScalars* sc, double tol, double max_iv, hipStream_t s,
-                        SolverScalars* mirror);
+                        SolverScalars* mirror, const IbView<T>& ib);
 // y = a x over n doubles (y may alias x)
 int launch_scale(int64_t n, double a, const double* x, double* y, hipStream_t s);
 // y = a x + b y over n values (x NULL: y = b y)
@@ -212,10 +214,14 @@ int launch_ib_classify(const IbGeo& B, const double* body, T* us0, T* us1, Solve
 // Loads of the forcing in the body window with the markers at body_pos
 // (force into sc->force; Fin, nullable, replaces it) and, when body_out is
 // given, RK4 from body_rk; xi != 0 also stores the coupling error in sc->xi.
+// info (nullable): the step record, written by the same launch (in place of
+// launch_copy_info when the loads are a step's last launch).
 template <typename T>
 int launch_loads_body(const IbGeo& B, const IbView<T>& ib, const double* body_pos,
                       const double* body_rk, double* body_out, const double* kc,
-                      const double* Fin, int xi, SolverScalars* sc, hipStream_t s);
+                      const double* Fin, int xi, SolverScalars* sc, hipStream_t s,
+                      fvib_step_info* info = nullptr, int cg_iters = 0, int ir_iters = 0,
+                      int* sticky = nullptr);
 // Step record from the solver scalars; a failed status is also stored in
 // *sticky (nullable).
 int launch_zero_scalars(SolverScalars* sc, hipStream_t s);

@@ -149,11 +149,30 @@ __device__ void body_rk4(const IbGeo& B, const double* st_in, const double* F,
   }
 }
 
+// The step record from the solver scalars (one thread); a failed status is
+// also stored in *sticky (nullable).
+__device__ void put_record(const SolverScalars* sc, fvib_step_info* info, int cg_iters,
+                           int ir_iters, int* sticky, int cpl_iters) {
+  int st = sc->status;
+  if (st == FVIB_OK && sc->clamp) st = FVIB_EINVAL;
+  if (sticky && st != FVIB_OK) *sticky = st;
+  info->status = st;
+  info->cg_iters = cg_iters;
+  info->ir_iters = ir_iters;
+  info->flags = (sc->clamp ? 1 : 0) | (cpl_iters << 8);
+  info->res = sc->crit;
+  info->div_max = sc->div_max;
+  for (int a = 0; a < 3; ++a) info->force[a] = sc->force[a];
+  info->xi = cpl_iters ? sc->xi : 0.0;
+}
+
 // Loads on the body (markers placed by body_pos) and, when body_out is
 // given, the RK4 update from body_rk; one block.  Fin (nullable) replaces
 // the computed force.  With body_out and the coupling error requested
 // (xi != 0), sc->xi = |body_out - body_pos|^2 / max(|body_pos|^2, 1e-30):
 // the change of the structural iterate of a coupling sub-iteration.
+// info (nullable): the step's record, written last (the step's final
+// launch), with the host's iteration counts and sticky word.
 // The loads gather takes one item per (marker, component, stencil row):
 // kLoadsBlock threads, each summing its items' four faces, then one
 // block-wide sum (fixed order).
@@ -164,7 +183,7 @@ __global__ void __launch_bounds__(kLoadsBlock)
 k_loads_body(IbGeo B, IbView<T> ib, const double* body_pos, const double* body_rk,
              double* body_out,
              const double* __restrict__ kc, const double* __restrict__ Fin, int xi,
-             SolverScalars* sc) {
+             SolverScalars* sc, fvib_step_info* info, int cg_iters, int ir_iters, int* sticky) {
   double q[2] = {0.0, 0.0};
   if (!Fin) {
     const double dxb = body_pos[0], dyb = body_pos[1];
@@ -196,19 +215,21 @@ k_loads_body(IbGeo B, IbView<T> ib, const double* body_pos, const double* body_r
   if (Fin)
     for (int a = 0; a < 3; ++a) F[a] = Fin[a];
   for (int a = 0; a < 3; ++a) sc->force[a] = F[a];
-  if (!body_out) return;
-  double st[6];
-  body_rk4(B, body_rk, F, kc, st);
-  if (xi) {
-    double num = 0.0, den = 0.0;
-    for (int a = 0; a < 6; ++a) {
-      const double e = st[a] - body_pos[a];
-      num += e * e;
-      den += body_pos[a] * body_pos[a];
+  if (body_out) {
+    double st[6];
+    body_rk4(B, body_rk, F, kc, st);
+    if (xi) {
+      double num = 0.0, den = 0.0;
+      for (int a = 0; a < 6; ++a) {
+        const double e = st[a] - body_pos[a];
+        num += e * e;
+        den += body_pos[a] * body_pos[a];
+      }
+      sc->xi = num / fmax(den, 1e-30);
     }
-    sc->xi = num / fmax(den, 1e-30);
+    for (int a = 0; a < 6; ++a) body_out[a] = st[a];
   }
-  for (int a = 0; a < 6; ++a) body_out[a] = st[a];
+  if (info) put_record(sc, info, cg_iters, ir_iters, sticky, 0);
 }
 
 // Also copies (or zeroes, src == nullptr) a 6-double body state when dst
@@ -218,17 +239,7 @@ __global__ void k_copy_info(const SolverScalars* sc, fvib_step_info* info, int c
                             int cpl_iters) {
   if (body_dst && threadIdx.x < 6) body_dst[threadIdx.x] = body_src ? body_src[threadIdx.x] : 0.0;
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int st = sc->status;
-  if (st == FVIB_OK && sc->clamp) st = FVIB_EINVAL;
-  if (sticky && st != FVIB_OK) *sticky = st;
-  info->status = st;
-  info->cg_iters = cg_iters;
-  info->ir_iters = ir_iters;
-  info->flags = (sc->clamp ? 1 : 0) | (cpl_iters << 8);
-  info->res = sc->crit;
-  info->div_max = sc->div_max;
-  for (int a = 0; a < 3; ++a) info->force[a] = sc->force[a];
-  info->xi = cpl_iters ? sc->xi : 0.0;
+  put_record(sc, info, cg_iters, ir_iters, sticky, cpl_iters);
 }
 
 // Static box on a 3D grid: forced flags on the window faces of each
@@ -280,9 +291,10 @@ int launch_ib_classify(const IbGeo& B, const double* body, T* us0, T* us1, Solve
 template <typename T>
 int launch_loads_body(const IbGeo& B, const IbView<T>& ib, const double* body_pos,
                       const double* body_rk, double* body_out, const double* kc,
-                      const double* Fin, int xi, SolverScalars* sc, hipStream_t s) {
+                      const double* Fin, int xi, SolverScalars* sc, hipStream_t s,
+                      fvib_step_info* info, int cg_iters, int ir_iters, int* sticky) {
   launch_kernel((k_loads_body<T>), dim3(1), dim3(kLoadsBlock), 0, s, B, ib, body_pos, body_rk,
-                body_out, kc, Fin, xi, sc);
+                body_out, kc, Fin, xi, sc, info, cg_iters, ir_iters, sticky);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
@@ -316,9 +328,11 @@ template int launch_ib_classify<double>(const IbGeo&, const double*, double*, do
                                         SolverScalars*, hipStream_t);
 template int launch_loads_body<float>(const IbGeo&, const IbView<float>&, const double*,
                                       const double*, double*, const double*, const double*, int,
-                                      SolverScalars*, hipStream_t);
+                                      SolverScalars*, hipStream_t, fvib_step_info*, int, int,
+                                      int*);
 template int launch_loads_body<double>(const IbGeo&, const IbView<double>&, const double*,
                                        const double*, double*, const double*, const double*, int,
-                                       SolverScalars*, hipStream_t);
+                                       SolverScalars*, hipStream_t, fvib_step_info*, int, int,
+                                       int*);
 
 }  // namespace fvib

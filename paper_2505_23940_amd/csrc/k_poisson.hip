@@ -475,6 +475,78 @@ k_rhs_residual_col(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__
   block_partials<4, 3>(v, red.partial);
 }
 
+// ------------------------------------- RHS and first residual (2D, FDM)
+// As k_rhs_residual_col on a 2D grid (one cell per thread), with the
+// immersed body's forced faces taking the body velocity in the divergence
+// (Eq. 9's u~ = u_c there, the terms of k_ppe_rhs): one pass in place of
+// the right-hand side, its epilogue, the first residual and its epilogue.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kBlock)
+k_rhs_residual_2d(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__ s0,
+                  const T* __restrict__ s1, IbView<T> ib, const double* __restrict__ x,
+                  double* __restrict__ b, double* __restrict__ r64, float* __restrict__ r32,
+                  RedBuf red) {
+  const int nx = P.n[0], ny = P.n[1];
+  const double scale = -1.0 / P.dt_over_rho;
+  double rr = 0.0, sx = 0.0, sb = 0.0, mx = 0.0;
+  const int lx = threadIdx.x & (kTileX - 1), ly = threadIdx.x / kTileX;
+  for (int u = xcd_block(blockIdx.x, gridDim.x); u < ct.nunits; u += gridDim.x) {
+    const int tx = u % ct.ntx, ty = (u / ct.ntx) % ct.nty;
+    const int i = tx * kTileX + lx, j = ty * kTileY + ly;
+    if (i >= nx || j >= ny) continue;
+    const int iH = (G.per[0] && i + 1 == nx) ? 0 : i + 1;
+    const int jH = (G.per[1] && j + 1 == ny) ? 0 : j + 1;
+    double lo[2], hi[2];
+    lo[0] = (double)s0[(int64_t)j * G.ext[0][0] + i];
+    hi[0] = (double)s0[(int64_t)j * G.ext[0][0] + iH];
+    lo[1] = (double)s1[(int64_t)j * G.ext[1][0] + i];
+    hi[1] = (double)s1[(int64_t)jH * G.ext[1][0] + i];
+    if (ib.active && !ib.box) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const double Uc = ib.body[3 + c];
+        const int* o = ib.origin;
+        const int W0 = ib.W[c][0], W1 = ib.W[c][1];
+        int li = i - o[2 * c], lj = j - o[2 * c + 1];
+        if (li >= 0 && lj >= 0 && li < W0 && lj < W1 && ib.cls[c][lj * W0 + li]) lo[c] = Uc;
+        li = (c == 0 ? iH : i) - o[2 * c];
+        lj = (c == 1 ? jH : j) - o[2 * c + 1];
+        if (li >= 0 && lj >= 0 && li < W0 && lj < W1 && ib.cls[c][lj * W0 + li]) hi[c] = Uc;
+      }
+    }
+    const double dxi = P.dx[0][i], dyj = P.dx[1][j];
+    // b of this cell (the terms of k_ppe_rhs in its order)
+    double fl = 0.0;
+    fl += hi[0] * dyj - lo[0] * dyj;
+    fl += hi[1] * dxi - lo[1] * dxi;
+    const double bc = scale * fl;
+    // A x (the terms of k_residual in its order)
+    const int64_t cC = (int64_t)j * nx + i;
+    const double xc = x[cC];
+    const double xw = x[(int64_t)j * nx + nb_lo(i, nx, P.per[0])];
+    const double xe = x[(int64_t)j * nx + nb_hi(i, nx, P.per[0])];
+    const double xs = x[(int64_t)nb_lo(j, ny, P.per[1]) * nx + i];
+    const double xn = x[(int64_t)nb_hi(j, ny, P.per[1]) * nx + i];
+    double acc = 0.0;
+    acc += dyj * P.kf[0][i] * (xc - xw);
+    acc += dyj * P.kf[0][i + 1] * (xc - xe);
+    acc += dxi * P.kf[1][j] * (xc - xs);
+    acc += dxi * P.kf[1][j + 1] * (xc - xn);
+    const double r = bc - acc;
+    b[cC] = bc;
+    if (MODE == 3)
+      r64[cC] = r;
+    else
+      r32[cC] = (float)r;
+    rr += r * r;
+    sx += xc;
+    sb += bc;
+    mx = fmax(mx, fabs(r) * ((double)P.iv[0][i] * (double)P.iv[1][j]));
+  }
+  double v[4] = {rr, sx, sb, mx};
+  block_partials<4, 3>(v, red.partial);
+}
+
 // Epilogue of k_rhs_residual_col: the mean of b, then what FinResidual does
 // for the first residual of a solve, on the upper-bound criterion.
 struct FinRhsResidual {
@@ -801,10 +873,18 @@ template <typename T>
 int launch_rhs_residual(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
                         const double* x, double* b, double* r64, float* r32, RedBuf red,
                         SolverScalars* sc, double tol, double max_iv, hipStream_t s,
-                        SolverScalars* mirror) {
-  if (G.dim != 3) return FVIB_EINVAL;
+                        SolverScalars* mirror, const IbView<T>& ib) {
   const ColTiling ct = make_col_tiling(P.n[0], P.n[1], P.n[2]);
-  if (r64)
+  if (G.dim == 2) {
+    if (r64)
+      launch_kernel((k_rhs_residual_2d<T, 3>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct,
+                    us[0], us[1], ib, x, b, r64, r32, red);
+    else
+      launch_kernel((k_rhs_residual_2d<T, 2>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct,
+                    us[0], us[1], ib, x, b, r64, r32, red);
+  } else if (ib.active && !ib.box) {
+    return FVIB_EINVAL;           // a 3D grid has no immersed rigid body
+  } else if (r64)
     launch_kernel((k_rhs_residual_col<T, 3>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct,
                   us[0], us[1], us[2], x, b, r64, r32, red);
   else
@@ -989,11 +1069,11 @@ template int launch_ppe_rhs<double>(const Geo<double>&, const PGeo<double>&,
 template int launch_rhs_residual<float>(const Geo<float>&, const PGeo<double>&,
                                         const float* const[3], const double*, double*, double*,
                                         float*, RedBuf, SolverScalars*, double, double,
-                                        hipStream_t, SolverScalars*);
+                                        hipStream_t, SolverScalars*, const IbView<float>&);
 template int launch_rhs_residual<double>(const Geo<double>&, const PGeo<double>&,
                                          const double* const[3], const double*, double*,
                                          double*, float*, RedBuf, SolverScalars*, double, double,
-                                         hipStream_t, SolverScalars*);
+                                         hipStream_t, SolverScalars*, const IbView<double>&);
 template int launch_cg_iter<float>(const PGeo<float>&, int, const float*, const float*, float*,
                                    float*, float*, RedBuf, SolverScalars*, double, int,
                                    hipStream_t, hipEvent_t*);
