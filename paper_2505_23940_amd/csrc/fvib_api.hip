@@ -1217,9 +1217,9 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
   const bool warm = bi->mu != nullptr && g->d.solver == FVIB_SOLVER_FDM;
   double* mu = bi->mu ? bi->mu : g->mu;
   if (!warm) FVIB_HIP(hipMemsetAsync(mu, 0, g->ncell * sizeof(double), g->stream));
-  // 3D without a body: the right-hand side and the first residual of the
-  // solve in one pass
-  const bool fuse_rhs = g->d.solver == FVIB_SOLVER_FDM && d == 3 && !g->has_body;
+  // the right-hand side and the first residual of the solve in one pass
+  // (fast diagonalisation; 2D, or 3D without a rigid body)
+  const bool fuse_rhs = g->d.solver == FVIB_SOLVER_FDM && (d == 2 || !g->has_body);
   if (fuse_rhs) {
     const bool d64 = g->prec == FVIB_PREC_FP64;
     if ((rc = timed(g, FVIB_K_ADJ_RHS_RES, [&] {
@@ -1492,21 +1492,31 @@ static int strong_adjoint_impl(Grid* g, const fvib_fields* in, const double* om,
   if (rc) return rc;
   // projection^T: A mu = G^T ubar^{n+1}, then ustar_bar (as in the weak step)
   const double rtol = (g->prec == FVIB_PREC_FP64) ? 1e-10 : 1e-7;
-  if ((rc = timed(g, FVIB_K_ADJ_RHS, [&] {
-         return launch_adj_rhs<T>(G, g->P64, ub1, g->b, g->red(), g->sc, rtol, g->stream);
-       })))
-    return rc;
   int cg = 0, ir = 0;
   const bool warm = bi->mu != nullptr && g->d.solver == FVIB_SOLVER_FDM;
   double* mu = bi->mu ? bi->mu : g->mu;
   if (!warm) FVIB_HIP(hipMemsetAsync(mu, 0, g->ncell * sizeof(double), g->stream));
+  const bool fdm = g->d.solver == FVIB_SOLVER_FDM;
+  if (fdm) {
+    // with its first residual, as in the weak step
+    const bool d64 = g->prec == FVIB_PREC_FP64;
+    if ((rc = timed(g, FVIB_K_ADJ_RHS_RES, [&] {
+           return launch_adj_rhs_residual<T>(G, g->P64, ub1, mu, g->b, d64 ? g->r64 : nullptr,
+                                             d64 ? nullptr : g->r32, g->red(), g->sc, rtol,
+                                             g->max_iv, g->stream, g->sch_dev);
+         })))
+      return rc;
+  } else if ((rc = timed(g, FVIB_K_ADJ_RHS, [&] {
+                return launch_adj_rhs<T>(G, g->P64, ub1, g->b, g->red(), g->sc, rtol, g->stream);
+              }))) {
+    return rc;
+  }
   const std::function<int()> ustar = [&]() {
     return timed(g, FVIB_K_ADJ_USTAR,
                  [&] { return launch_adj_ustar<T>(G, g->P64, ub1, mu, ib, usb, g->sc, g->stream); });
   };
-  const bool fdm = g->d.solver == FVIB_SOLVER_FDM;
   if ((rc = poisson_solve(g, g->b, mu, -1.0, &g->last_iters_adj, &cg, &ir, false, warm, nullptr,
-                          fdm ? &ustar : nullptr)))
+                          fdm ? &ustar : nullptr, fdm)))
     return rc;
   if (g->defer && g->solve_enoconv)
     return device_fail(g, FVIB_ENOCONV, "adjoint Poisson solve did not converge" +

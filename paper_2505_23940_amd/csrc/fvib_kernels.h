@@ -257,8 +257,9 @@ int launch_strong_jac(const IbGeo& B, const IbView<T>& ib, const double* om, con
 int launch_strong_lambda(const double* DF, const double* RF, const double* wbar,
                          const double* ubody, const double* dF, double* lam, SolverScalars* sc,
                          hipStream_t s);
-// 3D without a body, fast diagonalisation: y = G^T ubar and the first
-// residual y - A x of the adjoint solve in one pass (target as launch_adj_rhs).
+// Fast diagonalisation (2D, or 3D without a rigid body): y = G^T ubar and the
+// first residual y - A x of the adjoint solve in one pass (target as
+// launch_adj_rhs).
 template <typename T>
 int launch_adj_rhs_residual(const Geo<T>& G, const PGeo<double>& P, const T* const ub[3],
                             const double* x, double* y, double* r64, float* r32, RedBuf red,

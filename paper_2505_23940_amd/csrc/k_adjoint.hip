@@ -742,6 +742,64 @@ k_adj_rhs_res_col(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__ 
   block_partials<5, 3>(v, red.partial);
 }
 
+// k_adj_rhs_res_col on a 2D grid (one cell per thread): y = G^T ubar (the
+// terms of k_adj_rhs) and the first residual r = y - A mu_in (the terms of
+// k_residual) in one pass.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kBlock)
+k_adj_rhs_res_2d(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__ b0,
+                 const T* __restrict__ b1, const double* __restrict__ x,
+                 double* __restrict__ y, double* __restrict__ r64, float* __restrict__ r32,
+                 RedBuf red) {
+  const int nx = G.n[0], ny = G.n[1];
+  double rr = 0.0, sx = 0.0, sy = 0.0, mr = 0.0, my = 0.0;
+  const int lx = threadIdx.x & (kTileX - 1), ly = threadIdx.x / kTileX;
+  for (int u = xcd_block(blockIdx.x, gridDim.x); u < ct.nunits; u += gridDim.x) {
+    const int tx = u % ct.ntx, ty = (u / ct.ntx) % ct.nty;
+    const int i = tx * kTileX + lx, j = ty * kTileY + ly;
+    if (i >= nx || j >= ny) continue;
+    const int iH = (G.per[0] && i + 1 == nx) ? 0 : i + 1;
+    const int jH = (G.per[1] && j + 1 == ny) ? 0 : j + 1;
+    const double ulo = (double)b0[(int64_t)j * G.ext[0][0] + i];
+    const double uhi = (double)b0[(int64_t)j * G.ext[0][0] + iH];
+    const double vlo = (double)b1[(int64_t)j * G.ext[1][0] + i];
+    const double vhi = (double)b1[(int64_t)jH * G.ext[1][0] + i];
+    const bool xl = G.per[0] || i > 0, xh = G.per[0] || i + 1 < nx;
+    const bool yl = G.per[1] || j > 0, yh = G.per[1] || j + 1 < ny;
+    double acc = 0.0;
+    acc += xl ? ulo * P.idc[0][i] : 0.0;
+    acc -= xh ? uhi * P.idc[0][i + 1] : 0.0;
+    acc += yl ? vlo * P.idc[1][j] : 0.0;
+    acc -= yh ? vhi * P.idc[1][j + 1] : 0.0;
+    const int64_t cC = (int64_t)j * nx + i;
+    const double xc = x[cC];
+    const double xw = x[(int64_t)j * nx + (i > 0 ? i - 1 : (P.per[0] ? nx - 1 : 0))];
+    const double xe = x[(int64_t)j * nx + (i < nx - 1 ? i + 1 : (P.per[0] ? 0 : nx - 1))];
+    const double xs = x[(int64_t)(j > 0 ? j - 1 : (P.per[1] ? ny - 1 : 0)) * nx + i];
+    const double xn = x[(int64_t)(j < ny - 1 ? j + 1 : (P.per[1] ? 0 : ny - 1)) * nx + i];
+    const double dxi = P.dx[0][i], dyj = P.dx[1][j];
+    double ax_ = 0.0;
+    ax_ += dyj * P.kf[0][i] * (xc - xw);
+    ax_ += dyj * P.kf[0][i + 1] * (xc - xe);
+    ax_ += dxi * P.kf[1][j] * (xc - xs);
+    ax_ += dxi * P.kf[1][j + 1] * (xc - xn);
+    const double r = acc - ax_;
+    const double iv = (double)P.iv[0][i] * (double)P.iv[1][j];
+    y[cC] = acc;
+    if (MODE == 3)
+      r64[cC] = r;
+    else
+      r32[cC] = (float)r;
+    rr += r * r;
+    sx += xc;
+    sy += acc;
+    mr = fmax(mr, fabs(r) * iv);
+    my = fmax(my, fabs(acc) * iv);
+  }
+  double v[5] = {rr, sx, sy, mr, my};
+  block_partials<5, 3>(v, red.partial);
+}
+
 // Epilogue of k_adj_rhs_res_col: mean of y, the relative target of the
 // adjoint solve, then what FinResidual does for the first residual.
 struct FinAdjRhsResidual {
@@ -1489,14 +1547,21 @@ int launch_adj_rhs_residual(const Geo<T>& G, const PGeo<double>& P, const T* con
                             const double* x, double* y, double* r64, float* r32, RedBuf red,
                             SolverScalars* sc, double rtol, double max_iv, hipStream_t s,
                             SolverScalars* mirror) {
-  if (G.dim != 3) return FVIB_EINVAL;
   const ColTiling ct = make_col_tiling(G.n[0], G.n[1], G.n[2]);
-  if (r64)
+  if (G.dim == 2) {
+    if (r64)
+      launch_kernel((k_adj_rhs_res_2d<T, 3>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct,
+                    ub[0], ub[1], x, y, r64, r32, red);
+    else
+      launch_kernel((k_adj_rhs_res_2d<T, 2>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct,
+                    ub[0], ub[1], x, y, r64, r32, red);
+  } else if (r64) {
     launch_kernel((k_adj_rhs_res_col<T, 3>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct,
                   ub[0], ub[1], ub[2], x, y, r64, r32, red);
-  else
+  } else {
     launch_kernel((k_adj_rhs_res_col<T, 2>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct,
                   ub[0], ub[1], ub[2], x, y, r64, r32, red);
+  }
   FVIB_HIP(hipGetLastError());
   FVIB_HIP((launch_finish<5, 3>(red.partial, ct.nblocks, sc,
                                 FinAdjRhsResidual{P.inv_ncell, rtol, P.dt_over_rho, 0.5, max_iv,
