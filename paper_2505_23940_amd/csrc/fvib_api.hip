@@ -2,6 +2,7 @@
 // sequencing of one time step (see include/fvib.h for the contract).
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -1835,9 +1836,13 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
     return bail(FVIB_ENOMEM, "pinned host allocation failed");
   if (hipHostGetDevicePointer((void**)&g->sch_dev, g->sch, 0) != hipSuccess)
     return bail(FVIB_EHIP, "no device address for the pinned solver scalars");
-  // without a coherent word the checks fall back to events
-  if (hipHostMalloc((void**)&g->tick_h, sizeof(unsigned long long), hipHostMallocCoherent) ==
-      hipSuccess) {
+  // without a coherent word the checks fall back to events (also chosen by
+  // FVIB_NO_POLL=1 in the environment when the handle is created)
+  const char* no_poll = getenv("FVIB_NO_POLL");
+  if (no_poll && no_poll[0] == '1') {
+    g->tick_h = nullptr;
+  } else if (hipHostMalloc((void**)&g->tick_h, sizeof(unsigned long long),
+                           hipHostMallocCoherent) == hipSuccess) {
     *g->tick_h = 0ull;
     if (hipHostGetDevicePointer((void**)&g->tick_d, g->tick_h, 0) != hipSuccess) {
       (void)hipHostFree(g->tick_h);
