@@ -932,7 +932,9 @@ k_adj_ustar(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__ b0,
           else forced = forced_box<2>(ib, i, j, k, &li);
         }
         if (!forced) v += area[C] * (lo[C] - mc);
-        us[C][id] = (T)v;
+        // streamed past the caches (measured 31.0 -> 29.7 us on the channel;
+        // the transposed momentum kernel that reads it did not slow)
+        __builtin_nontemporal_store((T)v, &us[C][id]);
         // high face of the last cell of a bounded axis
         if (!G.per[C] && I[C] == G.n[C] - 1) {
           int H[3] = {i, j, k};
@@ -948,7 +950,7 @@ k_adj_ustar(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__ b0,
             else fh = forced_box<2>(ib, H[0], H[1], H[2], &li);
           }
           if (!fh) vh += area[C] * mc;
-          us[C][ih] = (T)vh;
+          __builtin_nontemporal_store((T)vh, &us[C][ih]);
         }
       }
       mzm = mc;
