@@ -1945,6 +1945,8 @@ int fvib_ib_set_body(fvib_grid* h, const fvib_body_desc* body) {
   B.M = M;
   B.xmin0 = xmin;
   B.ymin0 = ymin;
+  B.xmax0 = xmax;
+  B.ymax0 = ymax;
   B.h = h0;
   B.margin = 3;
   B.kind = body->kind;

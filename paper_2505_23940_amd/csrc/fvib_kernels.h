@@ -13,6 +13,7 @@ struct IbGeo {
   const double* X0;            // M x 2 reference positions
   const double* ds;            // M arc-length elements
   double xmin0, ymin0;         // lower corner of the reference polygon box
+  double xmax0, ymax0;         // its upper corner
   double h;                    // uniform grid spacing
   int margin;                  // cells between the polygon box and the window
   int W[2][2];                 // window widths per component (x, y)

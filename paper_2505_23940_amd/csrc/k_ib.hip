@@ -68,11 +68,21 @@ __device__ bool crossings_odd(const IbGeo& B, double dxb, double dyb, double px,
   return inside;
 }
 
-// pass 1: solid flags inside the window, and the window origins.  One
-// wavefront per window face; its lanes take every 64th polygon edge and the
-// crossing parities combine through a ballot.
+// Point classes of the window and their targets in one launch, and the
+// window origins.  One wavefront per window face; its lanes take every 64th
+// polygon edge and the crossing parities combine through a ballot.  The
+// wavefront tests the face itself and, for a fluid face, its axis
+// neighbours inside the window, so that an immersed-boundary point (a fluid
+// face with a solid neighbour) is found without a second pass.  Every marker
+// of a rigid body moves with the body velocity, so the normalised
+// interpolation of Eqs. 18-19 returns that velocity exactly: the target of
+// an immersed-boundary point is the body velocity, as on solid points
+// (Eq. 23).
+template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_ib_solid(IbGeo B, const double* __restrict__ body, SolverScalars* sc) {
+k_ib_classify(IbGeo B, const double* __restrict__ body, SolverScalars* sc, T* __restrict__ us0,
+              T* __restrict__ us1) {
+  T* us[2] = {us0, us1};
   int org[4];
   bool clamped = false;
   window_origin(B, body, 0, &org[0], &org[1], &clamped);
@@ -85,44 +95,39 @@ k_ib_solid(IbGeo B, const double* __restrict__ body, SolverScalars* sc) {
   const int n1 = B.W[1][0] * B.W[1][1];
   const int lane = threadIdx.x & 63;
   const int wpb = kBlock / 64;
+  const double dxb = body[0], dyb = body[1];
+  const double tolb = 1e-6 * B.h;
   for (int t = blockIdx.x * wpb + (threadIdx.x >> 6); t < n0 + n1; t += gridDim.x * wpb) {
-    const int c = (t < n0) ? 0 : 1;
-    const int l = (c == 0) ? t : t - n0;
-    const int li = l % B.W[c][0], lj = l / B.W[c][0];
-    const int i = org[2 * c] + li, j = org[2 * c + 1] + lj;
-    const bool odd = crossings_odd(B, body[0], body[1], B.fx[c][i], B.fy[c][j], lane, 64);
-    const unsigned long long bal = __ballot(odd ? 1 : 0);
-    if (lane == 0) B.cls[c][l] = (__popcll(bal) & 1) ? 1 : 0;
-  }
-}
-
-// pass 2: immersed-boundary points and target velocities.  Every marker of
-// a rigid body moves with the body velocity, so the normalised
-// interpolation of Eqs. 18-19 returns that velocity exactly: the target of
-// an IB point is the body velocity, as on solid points (Eq. 23).
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_ib_targets(IbGeo B, const double* __restrict__ body, T* __restrict__ us0,
-             T* __restrict__ us1) {
-  T* us[2] = {us0, us1};
-  const int n0 = B.W[0][0] * B.W[0][1];
-  const int n1 = B.W[1][0] * B.W[1][1];
-  for (int t = blockIdx.x * kBlock + threadIdx.x; t < n0 + n1; t += gridDim.x * kBlock) {
     const int c = (t < n0) ? 0 : 1;
     const int l = (c == 0) ? t : t - n0;
     const int Wx = B.W[c][0], Wy = B.W[c][1];
     const int li = l % Wx, lj = l / Wx;
-    const uint8_t* cl = B.cls[c];
-    const double Uc = body[3 + c];
-    if (cl[l] == 1) {
-      us[c][l] = (T)Uc;
-      continue;
+    const int i = org[2 * c] + li, j = org[2 * c + 1] + lj;
+    // solid flag of face (ii, jj) of component c (uniform across the wave).
+    // Outside the polygon's box the crossing test cannot report inside (a
+    // horizontal line meets a closed polygon an even number of times, or
+    // not at all), so points farther out than a rounding margin skip it.
+    auto solid = [&](int ii, int jj) -> bool {
+      const double px = B.fx[c][ii], py = B.fy[c][jj];
+      if (!(px >= B.xmin0 + dxb - tolb && px <= B.xmax0 + dxb + tolb &&
+            py >= B.ymin0 + dyb - tolb && py <= B.ymax0 + dyb + tolb))
+        return false;
+      const bool odd = crossings_odd(B, dxb, dyb, px, py, lane, 64);
+      return (__popcll(__ballot(odd ? 1 : 0)) & 1) != 0;
+    };
+    int cls = solid(i, j) ? 1 : 0;
+    if (cls == 0) {
+      bool nb = false;
+      if (li > 0) nb = nb || solid(i - 1, j);
+      if (!nb && li + 1 < Wx) nb = nb || solid(i + 1, j);
+      if (!nb && lj > 0) nb = nb || solid(i, j - 1);
+      if (!nb && lj + 1 < Wy) nb = nb || solid(i, j + 1);
+      cls = nb ? 2 : 0;
     }
-    const bool nb = (li > 0 && cl[l - 1] == 1) || (li + 1 < Wx && cl[l + 1] == 1) ||
-                    (lj > 0 && cl[l - Wx] == 1) || (lj + 1 < Wy && cl[l + Wx] == 1);
-    if (!nb) continue;
-    B.cls[c][l] = 2;
-    us[c][l] = (T)Uc;
+    if (lane == 0) {
+      B.cls[c][l] = (uint8_t)cls;
+      if (cls) us[c][l] = (T)body[3 + c];
+    }
   }
 }
 
@@ -278,12 +283,9 @@ template <typename T>
 int launch_ib_classify(const IbGeo& B, const double* body, T* us0, T* us1, SolverScalars* sc,
                        hipStream_t s) {
   const int n = B.W[0][0] * B.W[0][1] + B.W[1][0] * B.W[1][1];
-  const int nb = (n + kBlock - 1) / kBlock;
-  // the polygon test takes one wavefront per window face
-  launch_kernel(k_ib_solid, dim3((n + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, s, B,
-                body, sc);
-  FVIB_HIP(hipGetLastError());
-  launch_kernel((k_ib_targets<T>), dim3(nb), dim3(kBlock), 0, s, B, body, us0, us1);
+  // one wavefront per window face
+  launch_kernel((k_ib_classify<T>), dim3((n + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0,
+                s, B, body, sc, us0, us1);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
