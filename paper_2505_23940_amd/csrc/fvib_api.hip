@@ -1190,12 +1190,10 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
     if ((rc = timed(g, FVIB_K_PREDICTOR,
                     [&] { return launch_predictor<T>(G, u, fb, usb, ib, 0, g->stream); })))
       return rc;
+    // the step's force is gathered again inside the loads adjoint (parts 4)
     rc = timed(g, FVIB_K_IB, [&] {
-      int r = launch_loads_body<T>(g->ib, ib, in->body, in->body, nullptr, in->kc, nullptr, 0,
-                                   g->sc, g->stream);
-      if (r) return r;
       return launch_adj_body_loads<T>(g->ib, ib, in->body, in->body, bo->body, dF, in->kc,
-                                      bi->body, bi->body, bi->kc, g->sc, 3, g->stream);
+                                      bi->body, bi->body, bi->kc, g->sc, 7, g->stream);
     });
     if (rc) return rc;
   }

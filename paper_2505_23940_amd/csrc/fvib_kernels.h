@@ -27,6 +27,59 @@ struct IbGeo {
   double m, rho, dt;
 };
 
+// The 4-point regularised delta of the immersed boundary (Eq. 22): phi of
+// the distance in grid spacings, its derivative (s >= 0; the kernel is
+// even), the 1D kernel d_h(r) = phi(|r| / h) / h and its derivative in r.
+__device__ __forceinline__ double ib_phi4(double s) {
+  s = fabs(s);
+  if (s <= 1.0) return (3.0 - 2.0 * s + sqrt(1.0 + 4.0 * s - 4.0 * s * s)) / 8.0;
+  if (s <= 2.0) return (5.0 - 2.0 * s - sqrt(-7.0 + 12.0 * s - 4.0 * s * s)) / 8.0;
+  return 0.0;
+}
+__device__ __forceinline__ double ib_dphi4(double s) {
+  if (s <= 1.0) return (-2.0 + (4.0 - 8.0 * s) / (2.0 * sqrt(1.0 + 4.0 * s - 4.0 * s * s))) / 8.0;
+  if (s <= 2.0) return (-2.0 - (12.0 - 8.0 * s) / (2.0 * sqrt(-7.0 + 12.0 * s - 4.0 * s * s))) / 8.0;
+  return 0.0;
+}
+__device__ __forceinline__ double ib_dh(double r, double h) { return ib_phi4(r / h) / h; }
+__device__ __forceinline__ double ib_ddh(double r, double h) {
+  const double s = fabs(r) / h;
+  const double g = ib_dphi4(s) / (h * h);
+  return r < 0.0 ? -g : g;
+}
+
+// This thread's share of the loads gather of Eq. 20 over the window's
+// forcing with the markers at body_pos: q_c += dV_k h^2 sum_faces f d_h d_h
+// for the items t, t + nt, ... of the (marker, component, stencil row)
+// list (8 M items).
+template <typename T>
+__device__ __forceinline__ void ib_loads_share(const IbGeo& B, const IbView<T>& ib,
+                                               const double* body_pos, int t, int nt,
+                                               double q[2]) {
+  const double dxb = body_pos[0], dyb = body_pos[1];
+  const double h = B.h;
+  for (int it = t; it < 8 * B.M; it += nt) {
+    const int k = it >> 3, c = (it >> 2) & 1, dj = it & 3;
+    const double Xx = B.X0[2 * k] + dxb, Xy = B.X0[2 * k + 1] + dyb;
+    const double dV = B.ds[k] * h;
+    const int i0 = (int)floor((Xx - B.fx[c][0]) / h) - 1;
+    const int j0 = (int)floor((Xy - B.fy[c][0]) / h) - 1;
+    const int ox = ib.origin[2 * c], oy = ib.origin[2 * c + 1];
+    const int lj = j0 + dj - oy;
+    if (lj < 0 || lj >= B.W[c][1]) continue;
+    const double wy = ib_dh(B.fy[c][j0 + dj] - Xy, h);
+    double acc = 0.0;
+    for (int di = 0; di < 4; ++di) {
+      const int li = i0 + di - ox;
+      if (li < 0 || li >= B.W[c][0]) continue;
+      const int l = lj * B.W[c][0] + li;
+      if (!ib.cls[c][l]) continue;
+      acc += (double)ib.f[c][l] * ib_dh(B.fx[c][i0 + di] - Xx, h) * wy;
+    }
+    q[c] += acc * (h * h) * dV;
+  }
+}
+
 // Runge-Kutta stage combination written by the velocity correction:
 // out = a u0 + b (corrected field) when u0[0] is not NULL.
 struct StageMix {
@@ -231,6 +284,9 @@ int launch_copy_info(const SolverScalars* sc, fvib_step_info* info, int cg_iters
                      int* sticky = nullptr, int cpl_iters = 0);
 
 // k_adjoint.hip
+// RK4^T (parts & 1) and the marker-position part of loads^T (parts & 2) in
+// one block; parts & 4 first gathers the step's force from the recomputed
+// forcing (else it is read from sc->force).
 template <typename T>
 int launch_adj_body_loads(const IbGeo& B, const IbView<T>& ib, const double* st_rk,
                           const double* st_pos, const double* stbar_out, const double* dF,

@@ -24,30 +24,6 @@
 
 namespace fvib {
 
-// ------------------------------------------------------------------ kernel
-__device__ __forceinline__ double phi4a(double s) {
-  s = fabs(s);
-  if (s <= 1.0) return (3.0 - 2.0 * s + sqrt(1.0 + 4.0 * s - 4.0 * s * s)) / 8.0;
-  if (s <= 2.0) return (5.0 - 2.0 * s - sqrt(-7.0 + 12.0 * s - 4.0 * s * s)) / 8.0;
-  return 0.0;
-}
-
-// d phi / d s for s >= 0 (the kernel is even; phi'(0) = 0)
-__device__ __forceinline__ double dphi4(double s) {
-  if (s <= 1.0) return (-2.0 + (4.0 - 8.0 * s) / (2.0 * sqrt(1.0 + 4.0 * s - 4.0 * s * s))) / 8.0;
-  if (s <= 2.0) return (-2.0 - (12.0 - 8.0 * s) / (2.0 * sqrt(-7.0 + 12.0 * s - 4.0 * s * s))) / 8.0;
-  return 0.0;
-}
-
-__device__ __forceinline__ double dh(double r, double h) { return phi4a(r / h) / h; }
-
-// d/dr of d_h(r) = phi(|r|/h)/h
-__device__ __forceinline__ double ddh(double r, double h) {
-  const double s = fabs(r) / h;
-  const double g = dphi4(s) / (h * h);
-  return r < 0.0 ? -g : g;
-}
-
 // Threads of the body-load adjoint: its marker-position gather takes one
 // item per (marker, component, stencil row).
 constexpr int kAdjLoadsBlock = 1024;
@@ -60,7 +36,10 @@ constexpr int kAdjLoadsBlock = 1024;
 // into stbar_rk (the body-velocity part from the fluid is added later),
 // kcbar accumulated, force adjoint = dF + RK4^T part; parts & 2: the
 // marker-position part of loads^T for that force adjoint, added into
-// stbar_pos[0..1].  The total force adjoint is left in sc->force.
+// stbar_pos[0..1]; parts & 4: the step's force (which RK4^T linearises
+// about) gathered here from the recomputed forcing with the markers at
+// st_pos, else read from sc->force.  The total force adjoint is left in
+// sc->force.
 template <typename T>
 __global__ void __launch_bounds__(kAdjLoadsBlock)
 k_adj_body_loads(IbGeo B, IbView<T> ib, const double* st_rk, const double* st_pos,
@@ -68,6 +47,17 @@ k_adj_body_loads(IbGeo B, IbView<T> ib, const double* st_rk, const double* st_po
                  const double* __restrict__ kc, double* stbar_rk, double* stbar_pos,
                  double* __restrict__ kcbar, SolverScalars* sc, int parts) {
   __shared__ double Fbar_s[3];
+  if (parts & 4) {
+    double q[2] = {0.0, 0.0};
+    ib_loads_share<T>(B, ib, st_pos, threadIdx.x, kAdjLoadsBlock, q);
+    block_sum_n<2, kAdjLoadsBlock>(q);
+    if (threadIdx.x == 0) {
+      sc->force[0] = -B.rho * q[0];
+      sc->force[1] = -B.rho * q[1];
+      sc->force[2] = 0.0;
+    }
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
     const double* st = st_rk;
     double sb[6];
@@ -167,7 +157,7 @@ k_adj_body_loads(IbGeo B, IbView<T> ib, const double* st_rk, const double* st_po
     const int lj = j0 + dj - oy;
     if (lj < 0 || lj >= B.W[c][1]) continue;
     const double ry = B.fy[c][j0 + dj] - Xy;
-    const double wy = dh(ry, h), gy = ddh(ry, h);
+    const double wy = ib_dh(ry, h), gy = ib_ddh(ry, h);
     double ax = 0.0, ay = 0.0;
     for (int di = 0; di < 4; ++di) {
       const int li = i0 + di - ox;
@@ -176,8 +166,8 @@ k_adj_body_loads(IbGeo B, IbView<T> ib, const double* st_rk, const double* st_po
       if (!ib.cls[c][l]) continue;
       const double rx = B.fx[c][i0 + di] - Xx;
       const double f = (double)ib.f[c][l];
-      ax += f * ddh(rx, h) * wy;
-      ay += f * dh(rx, h) * gy;
+      ax += f * ib_ddh(rx, h) * wy;
+      ay += f * ib_dh(rx, h) * gy;
     }
     g[0] += Fb * B.rho * h * h * dV * ax;
     g[1] += Fb * B.rho * h * h * dV * ay;
@@ -215,7 +205,7 @@ k_adj_fbar(IbGeo B, const double* __restrict__ st, const SolverScalars* sc, T* _
     double s = 0.0;
     for (int k = lane; k < B.M; k += 64) {
       const double Xx = B.X0[2 * k] + st[0], Xy = B.X0[2 * k + 1] + st[1];
-      s += B.ds[k] * h * dh(px - Xx, h) * dh(py - Xy, h);
+      s += B.ds[k] * h * ib_dh(px - Xx, h) * ib_dh(py - Xy, h);
     }
     s = wave_sum(s);
     if (lane == 0) fbar[c][l] = (T)(-B.rho * h * h * sc->force[c] * s);
@@ -270,9 +260,9 @@ k_strong_jac(IbGeo B, IbView<T> ib, const double* __restrict__ om,
           if (!ib.cls[c][l]) continue;
           const double rx = B.fx[c][i0 + di] - Xx;
           const double f = (double)ib.f[c][l];
-          ax += f * ddh(rx, h) * dh(ry, h);
-          ay += f * dh(rx, h) * ddh(ry, h);
-          s0 += dh(rx, h) * dh(ry, h);
+          ax += f * ib_ddh(rx, h) * ib_dh(ry, h);
+          ay += f * ib_dh(rx, h) * ib_ddh(ry, h);
+          s0 += ib_dh(rx, h) * ib_dh(ry, h);
         }
       }
       s[3 * c + 0] += wgt * ax;

@@ -21,14 +21,6 @@
 
 namespace fvib {
 
-__device__ __forceinline__ double phi4(double s) {
-  s = fabs(s);
-  if (s <= 1.0) return (3.0 - 2.0 * s + sqrt(1.0 + 4.0 * s - 4.0 * s * s)) / 8.0;
-  if (s <= 2.0) return (5.0 - 2.0 * s - sqrt(-7.0 + 12.0 * s - 4.0 * s * s)) / 8.0;
-  return 0.0;
-}
-
-__device__ __forceinline__ double d_h(double r, double h) { return phi4(r / h) / h; }
 
 __device__ __forceinline__ void window_origin(const IbGeo& B, const double* body, int c,
                                               int* ox, int* oy, bool* clamped) {
@@ -191,28 +183,7 @@ k_loads_body(IbGeo B, IbView<T> ib, const double* body_pos, const double* body_r
              SolverScalars* sc, fvib_step_info* info, int cg_iters, int ir_iters, int* sticky) {
   double q[2] = {0.0, 0.0};
   if (!Fin) {
-    const double dxb = body_pos[0], dyb = body_pos[1];
-    const double h = B.h;
-    for (int it = threadIdx.x; it < 8 * B.M; it += kLoadsBlock) {
-      const int k = it >> 3, c = (it >> 2) & 1, dj = it & 3;
-      const double Xx = B.X0[2 * k] + dxb, Xy = B.X0[2 * k + 1] + dyb;
-      const double dV = B.ds[k] * h;
-      const int i0 = (int)floor((Xx - B.fx[c][0]) / h) - 1;
-      const int j0 = (int)floor((Xy - B.fy[c][0]) / h) - 1;
-      const int ox = ib.origin[2 * c], oy = ib.origin[2 * c + 1];
-      const int lj = j0 + dj - oy;
-      if (lj < 0 || lj >= B.W[c][1]) continue;
-      const double wy = d_h(B.fy[c][j0 + dj] - Xy, h);
-      double acc = 0.0;
-      for (int di = 0; di < 4; ++di) {
-        const int li = i0 + di - ox;
-        if (li < 0 || li >= B.W[c][0]) continue;
-        const int l = lj * B.W[c][0] + li;
-        if (!ib.cls[c][l]) continue;
-        acc += (double)ib.f[c][l] * d_h(B.fx[c][i0 + di] - Xx, h) * wy;
-      }
-      q[c] += acc * (h * h) * dV;
-    }
+    ib_loads_share<T>(B, ib, body_pos, threadIdx.x, kLoadsBlock, q);
     block_sum_n<2, kLoadsBlock>(q);
   }
   if (threadIdx.x != 0) return;
