@@ -210,6 +210,28 @@ def host_cpu():
     return model, os.cpu_count() or 1
 
 
+def copy_bandwidth(device, nbytes=1 << 30, reps=5):
+    """Achievable HBM bandwidth: the best of `reps` device-to-device copies of
+    nbytes (read + write counted), timed with events on the copy's stream."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=device)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        t = e0.elapsed_time(e1) / 1e3
+        best = t if best is None else min(best, t)
+    del src, dst
+    return 2 * nbytes / best / 1e9
+
+
 def cpu_baseline(w, budget_s):
     """The oracle as it stands, forward + adjoint like `value`: a rollout
     with autograd through every step (float64, exact Poisson solves), the
@@ -415,6 +437,14 @@ def main():
                             "frac": round(ach / HBM_PEAK_GBS, 4),
                             "launch_counts": f"kernel table pass ({a.steps} steps)",
                             "classes_without_model": unmod}
+    if a.solver == "fdm" and "residual" in table:
+        # refinement sweeps per Poisson solve (forward and adjoint, two per
+        # step) from the table pass: residual launches that ran; the inner
+        # solve is direct (no CG iterations)
+        res = table["residual"]
+        out["ir_sweeps_per_solve"] = round((res["launches"] - res.get("skipped", 0))
+                                           / (2 * a.steps), 3)
+        out["inner_iters_per_sweep"] = 0
     if not a.no_extra:
         if a.ckpt != 20 and a.steps >= 20:
             el20, _ = timed(lambda: fwd_adj_pass(g, w, ut, fbt, body, kc, a.steps, 20))
@@ -441,6 +471,13 @@ def main():
             print(f"[bench] fp64 fwd+adj {n64} steps in {el64:.3f} s", file=sys.stderr, flush=True)
     if not a.no_extra and a.workload == "channel":
         out["other_workloads"] = other_workloads(a.precision, a.tol, a.solver)
+    # the fractions against a measured copy as well as against the peak
+    cb = copy_bandwidth(g.device)
+    for key in ("roofline", "roofline_step"):
+        r = out.get(key)
+        if r and r.get("unit") == "GB/s":
+            r["copy_GB_s"] = round(cb, 1)
+            r["frac_of_copy"] = round(r["achieved"] / cb, 4)
     if a.copy_probe:
         import torch
         src = torch.ones(64 << 20, dtype=torch.float32, device=g.device)
