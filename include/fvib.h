@@ -182,7 +182,12 @@ typedef struct {
  * uniform periodic axes, increasing faces, positive nu / rho / dt), uploads
  * the per-axis metrics and allocates the workspace.  hip_stream is a
  * hipStream_t (NULL = default stream).  On success *out receives the
- * handle; on failure *out is NULL. */
+ * handle; on failure *out is NULL.  The handle also takes one word of
+ * coherent pinned host memory, through which the device reports each
+ * convergence check of the refinement (Sec. 2.5's Poisson solve) and the
+ * host polls it; with FVIB_NO_POLL=1 in the environment at creation (or if
+ * that allocation fails) the checks wait on a HIP event instead.  Both
+ * take the same decisions and give the same results. */
 int fvib_create_grid(const fvib_grid_desc *desc, void *hip_stream, fvib_grid **out);
 
 /* Destroy a handle and release its workspace (synchronises its stream). */
