@@ -342,14 +342,15 @@ __device__ __forceinline__ T shear(const Geo<T>& G, const LesView<T>& L, const i
   return edge_nu<lo, hi>(G, L, E) * L.ge[lo + hi - 1][eidx(G, E)];
 }
 
+// The faces of component C taken by blocks blk = 0 .. nblk - 1 of a range.
 template <int C, typename T>
-__global__ void __launch_bounds__(kBlock)
-k_les_force(Geo<T> G, LesView<T> L, U3<T> u, const T* __restrict__ fb, T* __restrict__ g) {
+__device__ __forceinline__ void les_force_faces(const Geo<T>& G, const LesView<T>& L,
+                                                const U3<T>& u, const T* __restrict__ fb,
+                                                T* __restrict__ g, int blk, int nblk) {
   constexpr int A1 = (C + 1) % 3, A2 = (C + 2) % 3;
   const int e0 = G.ext[C][0], e1 = G.ext[C][1], e2 = G.ext[C][2];
   const int64_t n = (int64_t)e0 * e1 * e2;
-  for (int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x; id < n;
-       id += (int64_t)gridDim.x * kBlock) {
+  for (int64_t id = (int64_t)blk * kBlock + threadIdx.x; id < n; id += (int64_t)nblk * kBlock) {
     const int F[3] = {(int)(id % e0), (int)((id / e0) % e1), (int)(id / ((int64_t)e0 * e1))};
     const T base = fb ? fb[id] : T(0);
     const bool ev = G.per[C] || (F[C] >= 1 && F[C] <= G.n[C] - 1);
@@ -383,6 +384,21 @@ k_les_force(Geo<T> G, LesView<T> L, U3<T> u, const T* __restrict__ fb, T* __rest
     }
     g[id] = base + D;
   }
+}
+
+// All three components in one launch: blocks [0, b0) take u, [b0, b0 + b1)
+// take v and the rest w (the component is uniform across a block).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_les_force(Geo<T> G, LesView<T> L, U3<T> u, U3<T> fb, T* __restrict__ g0, T* __restrict__ g1,
+            T* __restrict__ g2, int b0, int b1) {
+  const int b = blockIdx.x;
+  if (b < b0)
+    les_force_faces<0>(G, L, u, fb.c[0], g0, b, b0);
+  else if (b < b0 + b1)
+    les_force_faces<1>(G, L, u, fb.c[1], g1, b - b0, b1);
+  else
+    les_force_faces<2>(G, L, u, fb.c[2], g2, b - b0 - b1, (int)gridDim.x - b0 - b1);
 }
 
 // ----------------------------------------------------------------- adjoint
@@ -586,16 +602,16 @@ __device__ __forceinline__ T face_from_edges(const Geo<T>& G, const LesView<T>& 
          L.pe[lo + hi - 1][eidx(G, Eh)] * idc(G, A, F[A] + 1) * wh;
 }
 
-// Pass 4 over the faces of component C: ubar += the subgrid VJP.
+// Pass 4 over the faces of component C (blocks blk = 0 .. nblk - 1 of a
+// range): ubar += the subgrid VJP.
 template <int C, typename T>
-__global__ void __launch_bounds__(kBlock)
-k_les_adj_face(Geo<T> G, LesView<T> L, T* __restrict__ ub, const T* __restrict__ gb,
-               T* __restrict__ fbar) {
+__device__ __forceinline__ void les_adj_faces(const Geo<T>& G, const LesView<T>& L,
+                                              T* __restrict__ ub, const T* __restrict__ gb,
+                                              T* __restrict__ fbar, int blk, int nblk) {
   constexpr int A1 = (C + 1) % 3, A2 = (C + 2) % 3;
   const int e0 = G.ext[C][0], e1 = G.ext[C][1], e2 = G.ext[C][2];
   const int64_t n = (int64_t)e0 * e1 * e2;
-  for (int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x; id < n;
-       id += (int64_t)gridDim.x * kBlock) {
+  for (int64_t id = (int64_t)blk * kBlock + threadIdx.x; id < n; id += (int64_t)nblk * kBlock) {
     const int F[3] = {(int)(id % e0), (int)((id / e0) % e1), (int)(id / ((int64_t)e0 * e1))};
     T acc = T(0);
     if (G.per[C] || F[C] - 1 >= 0) {
@@ -634,6 +650,21 @@ k_les_adj_face(Geo<T> G, LesView<T> L, T* __restrict__ ub, const T* __restrict__
   }
 }
 
+// All three components in one launch (block ranges as k_les_force).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_les_adj_face(Geo<T> G, LesView<T> L, T* __restrict__ ub0, T* __restrict__ ub1,
+               T* __restrict__ ub2, U3<T> gb, T* __restrict__ fb0, T* __restrict__ fb1,
+               T* __restrict__ fb2, int b0, int b1) {
+  const int b = blockIdx.x;
+  if (b < b0)
+    les_adj_faces<0>(G, L, ub0, gb.c[0], fb0, b, b0);
+  else if (b < b0 + b1)
+    les_adj_faces<1>(G, L, ub1, gb.c[1], fb1, b - b0, b1);
+  else
+    les_adj_faces<2>(G, L, ub2, gb.c[2], fb2, b - b0 - b1, (int)gridDim.x - b0 - b1);
+}
+
 inline int grid_for(int64_t n) {
   int64_t b = (n + kBlock - 1) / kBlock;
   if (b > 8192) b = 8192;
@@ -660,11 +691,10 @@ int launch_les_forward(const Geo<T>& G, const LesView<T>& L, const T* const u[3]
   const int64_t nf[3] = {(int64_t)G.ext[0][0] * G.ext[0][1] * G.ext[0][2],
                          (int64_t)G.ext[1][0] * G.ext[1][1] * G.ext[1][2],
                          (int64_t)G.ext[2][0] * G.ext[2][1] * G.ext[2][2]};
-  launch_kernel(k_les_force<0, T>, dim3(grid_for(nf[0])), dim3(kBlock), 0, s, G, L, U, fb[0], g[0]);
-  FVIB_HIP(hipGetLastError());
-  launch_kernel(k_les_force<1, T>, dim3(grid_for(nf[1])), dim3(kBlock), 0, s, G, L, U, fb[1], g[1]);
-  FVIB_HIP(hipGetLastError());
-  launch_kernel(k_les_force<2, T>, dim3(grid_for(nf[2])), dim3(kBlock), 0, s, G, L, U, fb[2], g[2]);
+  const int b0 = grid_for(nf[0]), b1 = grid_for(nf[1]), b2 = grid_for(nf[2]);
+  const U3<T> FB{{fb[0], fb[1], fb[2]}};
+  launch_kernel(k_les_force<T>, dim3(b0 + b1 + b2), dim3(kBlock), 0, s, G, L, U, FB, g[0], g[1],
+                g[2], b0, b1);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
@@ -699,14 +729,9 @@ int launch_les_adjoint(const Geo<T>& G, const LesView<T>& L, const T* const u[3]
   const int64_t nf[3] = {(int64_t)G.ext[0][0] * G.ext[0][1] * G.ext[0][2],
                          (int64_t)G.ext[1][0] * G.ext[1][1] * G.ext[1][2],
                          (int64_t)G.ext[2][0] * G.ext[2][1] * G.ext[2][2]};
-  launch_kernel(k_les_adj_face<0, T>, dim3(grid_for(nf[0])), dim3(kBlock), 0, s, G, L, ubar[0],
-                gbar[0], fbar[0]);
-  FVIB_HIP(hipGetLastError());
-  launch_kernel(k_les_adj_face<1, T>, dim3(grid_for(nf[1])), dim3(kBlock), 0, s, G, L, ubar[1],
-                gbar[1], fbar[1]);
-  FVIB_HIP(hipGetLastError());
-  launch_kernel(k_les_adj_face<2, T>, dim3(grid_for(nf[2])), dim3(kBlock), 0, s, G, L, ubar[2],
-                gbar[2], fbar[2]);
+  const int b0 = grid_for(nf[0]), b1 = grid_for(nf[1]), b2 = grid_for(nf[2]);
+  launch_kernel(k_les_adj_face<T>, dim3(b0 + b1 + b2), dim3(kBlock), 0, s, G, L, ubar[0], ubar[1],
+                ubar[2], GB, fbar[0], fbar[1], fbar[2], b0, b1);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
