@@ -368,7 +368,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {a.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md and not built.", file=sys.stderr)
+              "sharding the step across GPUs is not built.", file=sys.stderr)
         sys.exit(2)
     w = make_workload(a.workload)
     mixed = a.precision == "fp32"
