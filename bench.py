@@ -367,7 +367,7 @@ def roofline(timing, w, precision, mixed, solver, dom=None):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {a.gpus}); "
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}); "
               "sharding the step across GPUs is not built.", file=sys.stderr)
         sys.exit(2)
     w = make_workload(a.workload)
