@@ -1231,10 +1231,18 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
                 return launch_adj_rhs<T>(G, g->P64, ub1, g->b, g->red(), g->sc, rtol, g->stream);
               })))
     return rc;
-  // ustar_bar (a pure function of mu) is queued behind each convergence check
+  // ustar_bar (a pure function of mu) is queued behind each convergence check.
+  // With fast diagonalisation and no body the scalars are final once the
+  // solve has converged, so it also writes the step record (and passes the
+  // adjoint body state through): no record-copy launch ends the step.
+  fvib_step_info* dst = info ? info : g->info_dev;
+  const bool rec = g->d.solver == FVIB_SOLVER_FDM && !g->has_body;
   const std::function<int()> ustar = [&]() {
-    return timed(g, FVIB_K_ADJ_USTAR,
-                 [&] { return launch_adj_ustar<T>(G, g->P64, ub1, mu, ib, usb, g->sc, g->stream); });
+    return timed(g, FVIB_K_ADJ_USTAR, [&] {
+      return launch_adj_ustar<T>(G, g->P64, ub1, mu, ib, usb, g->sc, g->stream,
+                                 rec ? dst : nullptr, rec ? bo->body : nullptr,
+                                 rec ? body_pass : nullptr, g->sticky_d);
+    });
   };
   const bool fdm = g->d.solver == FVIB_SOLVER_FDM;
   if ((rc = poisson_solve(g, g->b, mu, -1.0, &g->last_iters_adj, &cg, &ir, false, warm, nullptr,
@@ -1276,8 +1284,9 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
                                       g->stream);
        })))
     return rc;
-  fvib_step_info* dst = info ? info : g->info_dev;
-  if ((rc = launch_copy_info(g->sc, dst, cg, ir, g->stream, bo->body, body_pass, g->sticky_d)))
+  // (a status the host set after the last ustar_bar still needs the copy)
+  if ((!rec || g->solve_enoconv) &&
+      (rc = launch_copy_info(g->sc, dst, cg, ir, g->stream, bo->body, body_pass, g->sticky_d)))
     return rc;
   if (g->defer) {                // status only in the info record
     g->err.clear();

@@ -27,6 +27,24 @@ struct IbGeo {
   double m, rho, dt;
 };
 
+// The step record from the solver scalars (one thread); a failed status is
+// also stored in *sticky (nullable).
+__device__ __forceinline__ void put_record(const SolverScalars* sc, fvib_step_info* info,
+                                           int cg_iters, int ir_iters, int* sticky,
+                                           int cpl_iters) {
+  int st = sc->status;
+  if (st == FVIB_OK && sc->clamp) st = FVIB_EINVAL;
+  if (sticky && st != FVIB_OK) *sticky = st;
+  info->status = st;
+  info->cg_iters = cg_iters;
+  info->ir_iters = ir_iters;
+  info->flags = (sc->clamp ? 1 : 0) | (cpl_iters << 8);
+  info->res = sc->crit;
+  info->div_max = sc->div_max;
+  for (int a = 0; a < 3; ++a) info->force[a] = sc->force[a];
+  info->xi = cpl_iters ? sc->xi : 0.0;
+}
+
 // The 4-point regularised delta of the immersed boundary (Eq. 22): phi of
 // the distance in grid spacings, its derivative (s >= 0; the kernel is
 // even), the 1D kernel d_h(r) = phi(|r| / h) / h and its derivative in r.
@@ -330,9 +348,14 @@ int launch_adj_rhs(const Geo<T>& G, const PGeo<double>& P, const T* const ub[3],
 template <typename T>
 // mu is used at zero mean: sc->sumx is its sum (measured by the solve's
 // last residual sweep)
+// info (nullable): the adjoint step's record, written by block 0 with the
+// device's sweep count (and the 6-double body state body_src copied to
+// body_dst, zero when body_src is NULL, when body_dst is given).
 int launch_adj_ustar(const Geo<T>& G, const PGeo<double>& P, const T* const ub1[3],
                      const double* mu, const IbView<T>& ib, T* usb[3], const SolverScalars* sc,
-                     hipStream_t s);
+                     hipStream_t s, fvib_step_info* info = nullptr,
+                     const double* body_src = nullptr, double* body_dst = nullptr,
+                     int* sticky = nullptr);
 template <typename T>
 int launch_adj_ubody(const Geo<T>& G, const PGeo<double>& P, const IbGeo& B, const T* const ub1[3],
                      const double* mu, const IbView<T>& ib, double* stbar,

@@ -875,9 +875,17 @@ __global__ void __launch_bounds__(kBlock)
 k_adj_ustar(Geo<T> G, PGeo<double> P, ColTiling ct, const T* __restrict__ b0,
             const T* __restrict__ b1, const T* __restrict__ b2, const double* __restrict__ mu,
             IbView<T> ib, T* __restrict__ s0, T* __restrict__ s1, T* __restrict__ s2,
-            const SolverScalars* sc) {
+            const SolverScalars* sc, fvib_step_info* info, const double* body_src,
+            double* body_dst, int* sticky) {
   const T* ub[3] = {b0, b1, b2};
   T* us[3] = {s0, s1, s2};
+  if (info && blockIdx.x == 0) {
+    // the step record (the scalars are final once the solve has converged;
+    // a repeated launch writes the same record again) and the adjoint body
+    // state of a step without a body, passed through
+    if (body_dst && threadIdx.x < 6) body_dst[threadIdx.x] = body_src ? body_src[threadIdx.x] : 0.0;
+    if (threadIdx.x == 0) put_record(sc, info, 0, sc->sweeps, sticky, 0);
+  }
   const double shift = sc->sumx * P.inv_ncell;
   const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
   const int64_t sxy = (int64_t)nx * ny;
@@ -1592,14 +1600,17 @@ static inline int nblk(int64_t n) {
 template <typename T>
 int launch_adj_ustar(const Geo<T>& G, const PGeo<double>& P, const T* const ub1[3],
                      const double* mu, const IbView<T>& ib, T* usb[3], const SolverScalars* sc,
-                     hipStream_t s) {
+                     hipStream_t s, fvib_step_info* info, const double* body_src,
+                     double* body_dst, int* sticky) {
   const ColTiling ct = make_col_tiling(G.n[0], G.n[1], G.n[2]);
   if (G.dim == 2)
     launch_kernel((k_adj_ustar<T, 2>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct, ub1[0],
-                       ub1[1], ub1[2], mu, ib, usb[0], usb[1], usb[2], sc);
+                  ub1[1], ub1[2], mu, ib, usb[0], usb[1], usb[2], sc, info, body_src, body_dst,
+                  sticky);
   else
     launch_kernel((k_adj_ustar<T, 3>), dim3(ct.nblocks), dim3(kBlock), 0, s, G, P, ct, ub1[0],
-                       ub1[1], ub1[2], mu, ib, usb[0], usb[1], usb[2], sc);
+                  ub1[1], ub1[2], mu, ib, usb[0], usb[1], usb[2], sc, info, body_src, body_dst,
+                  sticky);
   FVIB_HIP(hipGetLastError());
   return FVIB_OK;
 }
@@ -1685,7 +1696,8 @@ static int launch_adj_momentum_t(const AdjCtx<T>& X, T* ubar[3], T* fbbar[3], hi
                                  double*, RedBuf, SolverScalars*, double, hipStream_t);         \
   template int launch_adj_ustar<T>(const Geo<T>&, const PGeo<double>&, const T* const[3],       \
                                    const double*, const IbView<T>&, T* [3],                     \
-                                   const SolverScalars*, hipStream_t);                          \
+                                   const SolverScalars*, hipStream_t, fvib_step_info*,        \
+                                   const double*, double*, int*);                               \
   template int launch_adj_ubody<T>(const Geo<T>&, const PGeo<double>&, const IbGeo&,            \
                                    const T* const[3], const double*, const IbView<T>&,          \
                                    double*, const SolverScalars*, hipStream_t);                 \

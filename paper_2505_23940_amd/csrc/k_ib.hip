@@ -146,23 +146,6 @@ __device__ void body_rk4(const IbGeo& B, const double* st_in, const double* F,
   }
 }
 
-// The step record from the solver scalars (one thread); a failed status is
-// also stored in *sticky (nullable).
-__device__ void put_record(const SolverScalars* sc, fvib_step_info* info, int cg_iters,
-                           int ir_iters, int* sticky, int cpl_iters) {
-  int st = sc->status;
-  if (st == FVIB_OK && sc->clamp) st = FVIB_EINVAL;
-  if (sticky && st != FVIB_OK) *sticky = st;
-  info->status = st;
-  info->cg_iters = cg_iters;
-  info->ir_iters = ir_iters;
-  info->flags = (sc->clamp ? 1 : 0) | (cpl_iters << 8);
-  info->res = sc->crit;
-  info->div_max = sc->div_max;
-  for (int a = 0; a < 3; ++a) info->force[a] = sc->force[a];
-  info->xi = cpl_iters ? sc->xi : 0.0;
-}
-
 // Loads on the body (markers placed by body_pos) and, when body_out is
 // given, the RK4 update from body_rk; one block.  Fin (nullable) replaces
 // the computed force.  With body_out and the coupling error requested
