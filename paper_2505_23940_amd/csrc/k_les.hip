@@ -287,11 +287,11 @@ __device__ __forceinline__ void store_grad(const Geo<T>& G, const LesView<T>& L,
 
 // Edge gradients of the three planes on the whole edge lattice.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_les_grad(Geo<T> G, LesView<T> L, U3<T> u) {
+__device__ __forceinline__ void les_grad_sites(const Geo<T>& G, const LesView<T>& L,
+                                               const U3<T>& u, int blk, int nblk) {
   const int l0 = G.n[0] + 1, l1 = G.n[1] + 1;
   const int64_t n = (int64_t)l0 * l1 * (G.n[2] + 1);
-  for (int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x; id < n;
-       id += (int64_t)gridDim.x * kBlock) {
+  for (int64_t id = (int64_t)blk * kBlock + threadIdx.x; id < n; id += (int64_t)nblk * kBlock) {
     const int E[3] = {(int)(id % l0), (int)((id / l0) % l1), (int)(id / ((int64_t)l0 * l1))};
     store_grad<0, 1>(G, L, u, E);
     store_grad<0, 2>(G, L, u, E);
@@ -316,11 +316,11 @@ __global__ void __launch_bounds__(kBlock) k_les_nut(Geo<T> G, LesView<T> L, U3<T
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_les_wall(Geo<T> G, LesView<T> L, U3<T> u) {
+__device__ __forceinline__ void les_wall_faces(const Geo<T>& G, const LesView<T>& L,
+                                               const U3<T>& u, int blk, int nblk) {
   const int nx = G.n[0], nz = G.n[2];
   const int64_t n = 4 * (int64_t)nx * nz;
-  for (int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x; id < n;
-       id += (int64_t)gridDim.x * kBlock) {
+  for (int64_t id = (int64_t)blk * kBlock + threadIdx.x; id < n; id += (int64_t)nblk * kBlock) {
     const int i = (int)(id % nx);
     const int k = (int)((id / nx) % nz);
     const int side = (int)((id / ((int64_t)nx * nz)) % 2);
@@ -334,6 +334,18 @@ __global__ void __launch_bounds__(kBlock) k_les_wall(Geo<T> G, LesView<T> L, U3<
     L.dupl[comp][side][w] = dup;
     L.nuw[comp][side][w] = wall_nu(L, side, own, oth, up, dup, &d1, &d2);
   }
+}
+
+// The edge gradients and, with the wall model, the wall faces' Eq. 27 solve
+// in one launch: both read u only.  Blocks [0, bg) take the edge lattice,
+// the rest the wall faces.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_les_grad(Geo<T> G, LesView<T> L, U3<T> u, int bg) {
+  const int b = blockIdx.x;
+  if (b < bg)
+    les_grad_sites(G, L, u, b, bg);
+  else
+    les_wall_faces(G, L, u, b - bg, (int)gridDim.x - bg);
 }
 
 template <int C, int A, typename T>
@@ -679,15 +691,12 @@ int launch_les_forward(const Geo<T>& G, const LesView<T>& L, const T* const u[3]
   const U3<T> U{{u[0], u[1], u[2]}};
   const int64_t nc = (int64_t)G.n[0] * G.n[1] * G.n[2];
   const int64_t nl = (int64_t)(G.n[0] + 1) * (G.n[1] + 1) * (G.n[2] + 1);
-  launch_kernel(k_les_grad<T>, dim3(grid_for(nl)), dim3(kBlock), 0, s, G, L, U);
+  const int bg = grid_for(nl);
+  const int bw = L.wall ? grid_for(4 * (int64_t)G.n[0] * G.n[2]) : 0;
+  launch_kernel(k_les_grad<T>, dim3(bg + bw), dim3(kBlock), 0, s, G, L, U, bg);
   FVIB_HIP(hipGetLastError());
   launch_kernel(k_les_nut<T>, dim3(grid_for(nc)), dim3(kBlock), 0, s, G, L, U);
   FVIB_HIP(hipGetLastError());
-  if (L.wall) {
-    launch_kernel(k_les_wall<T>, dim3(grid_for(4 * (int64_t)G.n[0] * G.n[2])), dim3(kBlock), 0,
-                  s, G, L, U);
-    FVIB_HIP(hipGetLastError());
-  }
   const int64_t nf[3] = {(int64_t)G.ext[0][0] * G.ext[0][1] * G.ext[0][2],
                          (int64_t)G.ext[1][0] * G.ext[1][1] * G.ext[1][2],
                          (int64_t)G.ext[2][0] * G.ext[2][1] * G.ext[2][2]};
@@ -708,14 +717,11 @@ int launch_les_adjoint(const Geo<T>& G, const LesView<T>& L, const T* const u[3]
   const int64_t nc = (int64_t)G.n[0] * G.n[1] * G.n[2];
   const int64_t nl = (int64_t)(G.n[0] + 1) * (G.n[1] + 1) * (G.n[2] + 1);
   const int64_t nw = 4 * (int64_t)G.n[0] * G.n[2];
-  launch_kernel(k_les_grad<T>, dim3(grid_for(nl)), dim3(kBlock), 0, s, G, L, U);
+  const int bg = grid_for(nl), bw = L.wall ? grid_for(nw) : 0;
+  launch_kernel(k_les_grad<T>, dim3(bg + bw), dim3(kBlock), 0, s, G, L, U, bg);
   FVIB_HIP(hipGetLastError());
   launch_kernel(k_les_nut<T>, dim3(grid_for(nc)), dim3(kBlock), 0, s, G, L, U);
   FVIB_HIP(hipGetLastError());
-  if (L.wall) {
-    launch_kernel(k_les_wall<T>, dim3(grid_for(nw)), dim3(kBlock), 0, s, G, L, U);
-    FVIB_HIP(hipGetLastError());
-  }
   launch_kernel(k_les_adj_sites<T>, dim3(grid_for(nl)), dim3(kBlock), 0, s, G, L, U, GB);
   FVIB_HIP(hipGetLastError());
   launch_kernel(k_les_adj_cells<T>, dim3(grid_for(nc)), dim3(kBlock), 0, s, G, L, U);
