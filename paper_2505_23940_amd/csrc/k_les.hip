@@ -513,10 +513,10 @@ __device__ __forceinline__ T cell_edge_qsum(const Geo<T>& G, const LesView<T>& L
 
 // Pass 2 over the cells: viscosity adjoint through |S|.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_les_adj_cells(Geo<T> G, LesView<T> L, U3<T> u) {
+__device__ __forceinline__ void les_adj_cells(const Geo<T>& G, const LesView<T>& L,
+                                              const U3<T>& u, int blk, int nblk) {
   const int64_t n = (int64_t)G.n[0] * G.n[1] * G.n[2];
-  for (int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x; id < n;
-       id += (int64_t)gridDim.x * kBlock) {
+  for (int64_t id = (int64_t)blk * kBlock + threadIdx.x; id < n; id += (int64_t)nblk * kBlock) {
     const int i = (int)(id % G.n[0]);
     const int j = (int)((id / G.n[0]) % G.n[1]);
     const int k = (int)(id / ((int64_t)G.n[0] * G.n[1]));
@@ -539,11 +539,11 @@ __global__ void __launch_bounds__(kBlock) k_les_adj_cells(Geo<T> G, LesView<T> L
 
 // Pass 2b over the wall faces: Eqs. 27-29 adjoint.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_les_adj_wall(Geo<T> G, LesView<T> L, U3<T> u) {
+__device__ __forceinline__ void les_adj_wall(const Geo<T>& G, const LesView<T>& L,
+                                             const U3<T>& u, int blk, int nblk) {
   const int nx = G.n[0], nz = G.n[2];
   const int64_t n = 4 * (int64_t)nx * nz;
-  for (int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x; id < n;
-       id += (int64_t)gridDim.x * kBlock) {
+  for (int64_t id = (int64_t)blk * kBlock + threadIdx.x; id < n; id += (int64_t)nblk * kBlock) {
     const int i = (int)(id % nx);
     const int k = (int)((id / nx) % nz);
     const int side = (int)((id / ((int64_t)nx * nz)) % 2);
@@ -557,6 +557,18 @@ __global__ void __launch_bounds__(kBlock) k_les_adj_wall(Geo<T> G, LesView<T> L,
     L.wown[comp][side][w] = nub * dn_own;
     L.woth[comp][side][w] = nub * dn_oth;
   }
+}
+
+// Passes 2 and 2b in one launch (they read the stress sites' output only):
+// blocks [0, bc) take the cells, the rest the wall faces.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_les_adj_cells(Geo<T> G, LesView<T> L, U3<T> u,
+                                                          int bc) {
+  const int b = blockIdx.x;
+  if (b < bc)
+    les_adj_cells(G, L, u, b, bc);
+  else
+    les_adj_wall(G, L, u, b - bc, (int)gridDim.x - bc);
 }
 
 template <int C, int A, typename T>
@@ -724,12 +736,9 @@ int launch_les_adjoint(const Geo<T>& G, const LesView<T>& L, const T* const u[3]
   FVIB_HIP(hipGetLastError());
   launch_kernel(k_les_adj_sites<T>, dim3(grid_for(nl)), dim3(kBlock), 0, s, G, L, U, GB);
   FVIB_HIP(hipGetLastError());
-  launch_kernel(k_les_adj_cells<T>, dim3(grid_for(nc)), dim3(kBlock), 0, s, G, L, U);
+  const int bc = grid_for(nc);
+  launch_kernel(k_les_adj_cells<T>, dim3(bc + bw), dim3(kBlock), 0, s, G, L, U, bc);
   FVIB_HIP(hipGetLastError());
-  if (L.wall) {
-    launch_kernel(k_les_adj_wall<T>, dim3(grid_for(nw)), dim3(kBlock), 0, s, G, L, U);
-    FVIB_HIP(hipGetLastError());
-  }
   launch_kernel(k_les_adj_edges<T>, dim3(grid_for(nl)), dim3(kBlock), 0, s, G, L);
   FVIB_HIP(hipGetLastError());
   const int64_t nf[3] = {(int64_t)G.ext[0][0] * G.ext[0][1] * G.ext[0][2],
