@@ -130,6 +130,12 @@ struct Grid {
   Planes planes;
   // workspace
   void* ustar[3] = {nullptr, nullptr, nullptr};
+  // the adjoint's ustar_bar (its own arrays, so the boundary-normal faces
+  // of u* keep the values the boundary pass set)
+  void* ustar_bar[3] = {nullptr, nullptr, nullptr};
+  // u*'s boundary-normal faces hold their constant boundary values (set by a
+  // boundary pass; only walls and inflow, whose values never change)
+  bool ustar_bc_set = false;
   double* b = nullptr;
   double* r64 = nullptr;
   double* pA64 = nullptr;
@@ -234,6 +240,7 @@ static void release(Grid* g) {
   f(g->md);
   f(g->mf);
   for (int c = 0; c < 3; ++c) f(g->ustar[c]);
+  for (int c = 0; c < 3; ++c) f(g->ustar_bar[c]);
   f(g->b);
   f(g->r64);
   f(g->pA64);
@@ -1060,11 +1067,15 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
   if (g->has_box &&
       (rc = timed(g, FVIB_K_IB, [&] { return launch_box_fix<T>(G, ib, us, g->stream); })))
     return rc;
-  if (g->planes.np &&
-      (rc = timed(g, FVIB_K_BOUNDARY, [&] {
-         return launch_boundary<T>(G, g->planes, u, us, g->red(), g->sc, g->stream);
-       })))
-    return rc;
+  // boundary faces of u*: an outflow every step; walls and inflow hold
+  // constant values, set once (nothing else writes those faces of u*)
+  if (g->planes.np && (g->planes.any_outflow || !g->ustar_bc_set)) {
+    if ((rc = timed(g, FVIB_K_BOUNDARY, [&] {
+           return launch_boundary<T>(G, g->planes, u, us, g->red(), g->sc, g->stream);
+         })))
+      return rc;
+    g->ustar_bc_set = true;
+  }
   const bool fdm = g->d.solver == FVIB_SOLVER_FDM;
   // the right-hand side and the first residual of the refinement in one
   // pass (fast diagonalisation; a 3D grid without a rigid body, or 2D)
@@ -1165,7 +1176,7 @@ static int step_adjoint_impl(Grid* g, const fvib_fields* in, const fvib_adjoint*
   const int d = g->dim;
   const T* u[3] = {(const T*)in->u[0], (const T*)in->u[1], d == 3 ? (const T*)in->u[2] : nullptr};
   const T* fb[3] = {(const T*)in->fb[0], (const T*)in->fb[1], d == 3 ? (const T*)in->fb[2] : nullptr};
-  T* usb[3] = {(T*)g->ustar[0], (T*)g->ustar[1], (T*)g->ustar[2]};
+  T* usb[3] = {(T*)g->ustar_bar[0], (T*)g->ustar_bar[1], (T*)g->ustar_bar[2]};
   const T* ub1[3] = {(const T*)bo->u[0], (const T*)bo->u[1], d == 3 ? (const T*)bo->u[2] : nullptr};
   T* ub0[3] = {(T*)bi->u[0], (T*)bi->u[1], d == 3 ? (T*)bi->u[2] : nullptr};
   T* fbb[3] = {(T*)bi->fb[0], (T*)bi->fb[1], d == 3 ? (T*)bi->fb[2] : nullptr};
@@ -1475,7 +1486,7 @@ static int strong_adjoint_impl(Grid* g, const fvib_fields* in, const double* om,
   const int d = g->dim;
   const T* u[3] = {(const T*)in->u[0], (const T*)in->u[1], nullptr};
   const T* fb[3] = {(const T*)in->fb[0], (const T*)in->fb[1], nullptr};
-  T* usb[3] = {(T*)g->ustar[0], (T*)g->ustar[1], nullptr};
+  T* usb[3] = {(T*)g->ustar_bar[0], (T*)g->ustar_bar[1], nullptr};
   const T* ub1[3] = {(const T*)bo->u[0], (const T*)bo->u[1], nullptr};
   T* ub0[3] = {(T*)bi->u[0], (T*)bi->u[1], nullptr};
   T* fbb[3] = {(T*)bi->fb[0], (T*)bi->fb[1], nullptr};
@@ -1673,6 +1684,7 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
   const size_t es = g->esize();
   bool ok = true;
   for (int c = 0; c < g->dim; ++c) ok &= dmalloc(&g->ustar[c], g->nface[c] * es) == FVIB_OK;
+  for (int c = 0; c < g->dim; ++c) ok &= dmalloc(&g->ustar_bar[c], g->nface[c] * es) == FVIB_OK;
   ok &= dmalloc(&g->b, g->ncell * sizeof(double)) == FVIB_OK;
   if (g->prec == FVIB_PREC_FP64) {
     ok &= dmalloc(&g->r64, g->ncell * sizeof(double)) == FVIB_OK;
@@ -1868,7 +1880,8 @@ int fvib_create_grid(const fvib_grid_desc* desc, void* hip_stream, fvib_grid** o
       hipMemset(g->sc, 0, sizeof(SolverScalars)) != hipSuccess)
     return bail(FVIB_EHIP, "workspace initialisation failed");
   for (int c = 0; c < g->dim; ++c)
-    if (hipMemset(g->ustar[c], 0, g->nface[c] * es) != hipSuccess)
+    if (hipMemset(g->ustar[c], 0, g->nface[c] * es) != hipSuccess ||
+        hipMemset(g->ustar_bar[c], 0, g->nface[c] * es) != hipSuccess)
       return bail(FVIB_EHIP, "workspace initialisation failed");
   if (hipDeviceSynchronize() != hipSuccess) return bail(FVIB_EHIP, "device synchronisation failed");
   *out = h;
