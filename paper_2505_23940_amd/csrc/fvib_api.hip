@@ -1096,11 +1096,11 @@ static int step_impl(Grid* g, const fvib_fields* in, fvib_fields* out, fvib_step
     return rc;
   int cg = 0, ir = 0;
   int last = g->last_iters;
-  // In 3D with fast diagonalisation the refinement iterates in a workspace
-  // (the adjoint's, which keeps nothing between calls) and the projection,
+  // With fast diagonalisation the refinement iterates in a workspace (the
+  // adjoint's, which keeps nothing between calls) and the projection,
   // reading the iterate anyway, stores it minus its mean in out->p: no
   // separate gauge pass.
-  const bool fold = fdm && g->dim == 3;
+  const bool fold = fdm;
   double* piter = fold ? g->mu : out->p;
   fvib_step_info* dst = info ? info : g->info_dev;
   // Without a body the scalars are final once the projection has run, so

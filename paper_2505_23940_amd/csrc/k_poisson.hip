@@ -653,10 +653,13 @@ template <typename T, int DIM, bool MIX>
 __global__ void __launch_bounds__(kBlock)
 k_project(Geo<T> G, PGeo<double> P, Tiling tl, const T* __restrict__ s0,
           const T* __restrict__ s1, const T* __restrict__ s2, const double* __restrict__ p,
-          T* o0, T* o1, T* o2, RedBuf red, SolverScalars* sc, StageMix mix) {
+          T* o0, T* o1, T* o2, RedBuf red, SolverScalars* sc, StageMix mix,
+          double* __restrict__ pg) {
   const int nx_ = G.n[0], ny_ = G.n[1];
   const T* us[3] = {s0, s1, s2};
   T* out[3] = {o0, o1, o2};
+  // pg (nullable): the pressure minus its mean (the gradient does not see it)
+  const double mean = pg ? sc->sumx * P.inv_ncell : 0.0;
   const T* u0[3] = {(const T*)mix.u0[0], (const T*)mix.u0[1], (const T*)mix.u0[2]};
   // stage output: a u0 + b (corrected field), or the corrected field
   auto put = [&](int c, int64_t id, double v) {
@@ -667,6 +670,7 @@ k_project(Geo<T> G, PGeo<double> P, Tiling tl, const T* __restrict__ s0,
   FVIB_TILE_LOOP(tl)
     const int I[3] = {i, j, k};
     const double pc = p[c_];
+    if (pg) pg[c_] = pc - mean;
     const double ivol = inv_volume(P, i, j, k);
     int64_t lo_id[DIM], hi_id[DIM];
     double ulo[DIM], uhi[DIM], plo[DIM], phi[DIM], d[DIM], klo[DIM], khi[DIM];
@@ -948,17 +952,17 @@ int launch_project(const Geo<T>& G, const PGeo<double>& P, const T* const us[3],
                    T* out[3], RedBuf red, SolverScalars* sc, hipStream_t s, double* pg,
                    fvib_step_info* info, int* sticky, const StageMix* mix) {
   const Tiling tl = red_tiling(G.n);
-  if (pg && (G.dim != 3 || pg == p)) return FVIB_EINVAL;
+  if (pg && pg == p) return FVIB_EINVAL;
   StageMix m{};
   const bool mx = mix && mix->u0[0];
   if (mx) m = *mix;
   if (G.dim == 2) {
     if (mx)
       launch_kernel((k_project<T, 2, true>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl,
-                    us[0], us[1], us[2], p, out[0], out[1], out[2], red, sc, m);
+                    us[0], us[1], us[2], p, out[0], out[1], out[2], red, sc, m, pg);
     else
       launch_kernel((k_project<T, 2, false>), dim3(tl.nblocks), dim3(kBlock), 0, s, G, P, tl,
-                    us[0], us[1], us[2], p, out[0], out[1], out[2], red, sc, m);
+                    us[0], us[1], us[2], p, out[0], out[1], out[2], red, sc, m, pg);
   } else {
     const ColTiling ct = make_col_tiling(G.n[0], G.n[1], G.n[2]);
     if (mx)
